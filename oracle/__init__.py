@@ -1,0 +1,271 @@
+"""FP64 CPU oracle for the pressure-correction Poisson solve -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does, and shares
+no source with it.
+
+* ``cps_oracle.c`` -- map, face metrics (Sec. 3.2), the nine-term flux-form
+  operator of eq. (PC_8)/(PC_term1-3), Gauss-Seidel colour passes, grid
+  transfers, dense coarse LU and the multigrid solve of eq. (PC_6).
+* ``direct.py`` -- exact solves (dense, DCT/FFT on the identity box, rFFT in
+  phi with sparse LU per mode on axisymmetric maps) that pin the multigrid.
+
+The C library is compiled with gcc on first use (or by ``build()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cps_oracle.c")
+_LIB = os.path.join(_HERE, "libcps_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+MAP_IDENTITY, MAP_SPHERE, MAP_OBLATE, MAP_TRIAXIAL = 0, 1, 2, 3
+METRICS_CENTRAL, METRICS_VERTEX = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [
+        ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+        ("map", ctypes.c_int32),
+        ("r_inner", ctypes.c_double), ("r_outer", ctypes.c_double),
+        ("theta0", ctypes.c_double), ("theta1", ctypes.c_double),
+        ("radial_stretch", ctypes.c_double), ("flattening", ctypes.c_double),
+        ("skew", ctypes.c_double),
+    ]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            I = ctypes.c_int
+            D = ctypes.c_double
+            lib.orc_map.argtypes = [P, D, D, D, P]
+            lib.orc_metric_from_chords.argtypes = [P, P]
+            lib.orc_metric_from_chords.restype = D
+            lib.orc_face_metrics.argtypes = [P, I, I, I, I, P]
+            lib.orc_face_metrics.restype = I
+            lib.orc_apply.argtypes = [I, I, I, P, P, P]
+            lib.orc_residual.argtypes = [I, I, I, P, P, P, P]
+            lib.orc_colour.argtypes = [I, I, I, I]
+            lib.orc_colour.restype = I
+            lib.orc_gs_pass.argtypes = [I, I, I, I, I, P, P, P]
+            lib.orc_prolong_add.argtypes = [I, I, I, P, P]
+            lib.orc_restrict.argtypes = [I, I, I, P, P]
+            lib.orc_dense_matrix.argtypes = [I, I, I, P, P]
+            lib.orc_level_plan.argtypes = [I, I, I, I, P]
+            lib.orc_level_plan.restype = I
+            lib.orc_mg_create.argtypes = [P, I, I, I]
+            lib.orc_mg_create.restype = P
+            lib.orc_mg_destroy.argtypes = [P]
+            lib.orc_mg_levels.argtypes = [P, P, P]
+            lib.orc_mg_levels.restype = I
+            lib.orc_mg_metrics.argtypes = [P, I]
+            lib.orc_mg_metrics.restype = P
+            lib.orc_mg_vcycle.argtypes = [P, P, P]
+            lib.orc_mg_coarse_solve.argtypes = [P, P, P]
+            lib.orc_mg_solve.argtypes = [P, P, P, D, I, I, P, P, P, P]
+            lib.orc_mg_solve.restype = I
+            _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Grid:
+    """Shell (or box) grid: cells n_r x n_theta x n_phi, phi periodic."""
+    n_r: int
+    n_theta: int
+    n_phi: int
+    map: int = MAP_SPHERE
+    r_inner: float = 1.5
+    r_outer: float = 2.5
+    theta0: float = 0.05
+    theta1: float = np.pi - 0.05
+    radial_stretch: float = 0.0
+    flattening: float = 0.0
+    skew: float = 0.0
+
+    def c_struct(self) -> _Grid:
+        return _Grid(self.n_r, self.n_theta, self.n_phi, self.map, self.r_inner, self.r_outer,
+                     self.theta0, self.theta1, self.radial_stretch, self.flattening, self.skew)
+
+    @property
+    def shape(self):
+        return (self.n_r, self.n_theta, self.n_phi)
+
+
+def as_grid(g) -> Grid:
+    """Accept an oracle Grid or any object with the same attribute names."""
+    if isinstance(g, Grid):
+        return g
+    return Grid(**{k: getattr(g, k) for k in Grid.__dataclass_fields__})
+
+
+def map_point(grid, sr: float, st: float, sp: float) -> np.ndarray:
+    g = as_grid(grid).c_struct()
+    X = np.zeros(3)
+    _load().orc_map(ctypes.byref(g), sr, st, sp, _p(X))
+    return X
+
+
+def metric_from_chords(t: np.ndarray):
+    """t[q] = chord along q; returns (G[3][3], det)."""
+    t = _f64(t).reshape(9)
+    G = np.zeros(9)
+    det = _load().orc_metric_from_chords(_p(t), _p(G))
+    return G.reshape(3, 3), det
+
+
+def face_metrics(grid, shape=None, method: int = METRICS_CENTRAL) -> np.ndarray:
+    """G[9, n_r, n_theta, n_phi] of the level with the given dims."""
+    g = as_grid(grid)
+    nr, nt, np_ = shape or g.shape
+    G = np.zeros((9, nr, nt, np_))
+    rc = _load().orc_face_metrics(ctypes.byref(g.c_struct()), nr, nt, np_, method, _p(G))
+    if rc != 0:
+        raise ValueError("non-positive det on an interior face")
+    return G
+
+
+def apply(G: np.ndarray, x: np.ndarray) -> np.ndarray:
+    G = _f64(G); x = _f64(x)
+    y = np.empty_like(x)
+    _load().orc_apply(*x.shape, _p(G), _p(x), _p(y))
+    return y
+
+
+def residual(G, b, x) -> np.ndarray:
+    G = _f64(G); b = _f64(b); x = _f64(x)
+    r = np.empty_like(x)
+    _load().orc_residual(*x.shape, _p(G), _p(b), _p(x), _p(r))
+    return r
+
+
+def colour(ncol: int, a: int, b: int, c: int) -> int:
+    return _load().orc_colour(ncol, a, b, c)
+
+
+def gs_pass(G, b, x, ncol: int, col: int) -> np.ndarray:
+    """Returns a new array: x after one Gauss-Seidel pass over colour col."""
+    G = _f64(G); b = _f64(b)
+    y = _f64(x).copy()
+    _load().orc_gs_pass(*y.shape, ncol, col, _p(G), _p(b), _p(y))
+    return y
+
+
+def prolong_add(e, x) -> np.ndarray:
+    """x + P e for fine x (new array)."""
+    e = _f64(e)
+    y = _f64(x).copy()
+    _load().orc_prolong_add(*y.shape, _p(e), _p(y))
+    return y
+
+
+def restrict(r) -> np.ndarray:
+    r = _f64(r)
+    nr, nt, np_ = r.shape
+    bc = np.zeros((nr // 2, nt // 2, np_ // 2))
+    _load().orc_restrict(nr, nt, np_, _p(r), _p(bc))
+    return bc
+
+
+def dense_matrix(G) -> np.ndarray:
+    G = _f64(G)
+    nr, nt, np_ = G.shape[1:]
+    n = nr * nt * np_
+    A = np.zeros((n, n))
+    _load().orc_dense_matrix(nr, nt, np_, _p(G), _p(A))
+    return A
+
+
+def level_plan(nr: int, nt: int, np_: int, n_levels: int = 0):
+    dims = np.zeros(48, dtype=np.int32)
+    L = _load().orc_level_plan(nr, nt, np_, n_levels, _p(dims))
+    if L < 1:
+        raise ValueError("no level plan")
+    return [tuple(int(v) for v in dims[3 * l:3 * l + 3]) for l in range(L)]
+
+
+class Multigrid:
+    """Oracle multigrid hierarchy for one grid (metrics from the map)."""
+
+    def __init__(self, grid, method: int = METRICS_CENTRAL, n_levels: int = 0, ncol: int = 0):
+        self._lib = _load()
+        self.grid = as_grid(grid)
+        self._g = self.grid.c_struct()
+        self._h = self._lib.orc_mg_create(ctypes.byref(self._g), method, n_levels, ncol)
+        if not self._h:
+            raise ValueError("oracle multigrid setup failed")
+        dims = np.zeros(48, dtype=np.int32)
+        nc = ctypes.c_int(0)
+        L = self._lib.orc_mg_levels(self._h, _p(dims), ctypes.byref(nc))
+        self.levels = [tuple(int(v) for v in dims[3 * l:3 * l + 3]) for l in range(L)]
+        self.ncol = nc.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_mg_destroy(h)
+            self._h = None
+
+    def metrics(self, level: int = 0) -> np.ndarray:
+        nr, nt, np_ = self.levels[level]
+        ptr = self._lib.orc_mg_metrics(self._h, level)
+        buf = (ctypes.c_double * (9 * nr * nt * np_)).from_address(ptr)
+        return np.frombuffer(buf, dtype=np.float64).reshape(9, nr, nt, np_).copy()
+
+    def vcycle(self, b, x) -> np.ndarray:
+        b = _f64(b)
+        y = _f64(x).copy()
+        self._lib.orc_mg_vcycle(self._h, _p(b), _p(y))
+        return y
+
+    def coarse_solve(self, b) -> np.ndarray:
+        b = _f64(b)
+        e = np.zeros_like(b)
+        self._lib.orc_mg_coarse_solve(self._h, _p(b), _p(e))
+        return e
+
+    def solve(self, b, tol: float = 1e-10, max_iters: int = 200, accel: int = 0):
+        """Returns (x, status, iterations, rel_residual, history, mean_removed)."""
+        b = _f64(b)
+        x = np.zeros_like(b)
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        mean = ctypes.c_double(0.0)
+        hist = np.zeros(max(max_iters, 1))
+        st = self._lib.orc_mg_solve(self._h, _p(b), _p(x), tol, max_iters, accel,
+                                    ctypes.byref(it), ctypes.byref(rel), _p(hist),
+                                    ctypes.byref(mean))
+        return x, st, it.value, rel.value, hist[:it.value].copy(), mean.value
