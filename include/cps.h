@@ -1,0 +1,184 @@
+/*
+ * cps.h -- C ABI of the curvilinear pressure-Poisson multigrid for MI355X.
+ *
+ * Solves the pressure-correction equation of Naskar et al. (arXiv
+ * 2305.17875), eq. (PC_6): d/ds_i ( G_ij d phi / ds_j ) = rhs, written in the
+ * transformed Cartesian coordinates of Sec. 3.1 with unit cell sides, the
+ * face metrics G of Sec. 3.2 and the nine-term second-order flux form of
+ * eq. (PC_8) / (PC_term1-3).  phi is hdP of eq. (PC_6); the caller divides by
+ * the substep h.
+ *
+ * Geometry and boundary conventions (the paper leaves the pressure boundary
+ * condition unstated; these are the library's):
+ *   - cells n_r x n_theta x n_phi, arrays [r][theta][phi] in C order with phi
+ *     contiguous; phi is periodic;
+ *   - the r-walls and the theta-walls (cones at theta0, theta1) carry zero
+ *     flux; stencil reads that leave the domain in r or theta mirror to the
+ *     nearest cell;
+ *   - A is singular with the constants as null space and 1^T A = 0, so the
+ *     mean of rhs is removed (and reported) and the returned p has mean 0.
+ *
+ * Pointers: unless stated otherwise, array arguments are DEVICE pointers on
+ * the current HIP device, owned by the caller and not retained after the call
+ * returns.  Every call is ordered on opts.stream (0 = the null stream).
+ *
+ * Errors: functions return cps_status.  On a non-OK status, cps_last_error()
+ * gives a thread-local text.  A handle is not thread-safe; distinct handles
+ * are independent.
+ */
+#ifndef CPS_H
+#define CPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CPS_OK = 0,
+    CPS_E_INVALID = -1,       /* bad argument, dims, or a face with det <= 0 */
+    CPS_E_OOM = -2,           /* device allocation failed */
+    CPS_E_HIP = -3,           /* a HIP runtime call failed */
+    CPS_E_NOT_CONVERGED = -4, /* iteration cap reached; p holds the last iterate */
+    CPS_E_DIVERGED = -5       /* residual norm became NaN or Inf */
+} cps_status;
+
+/* Maps from computational (s_r, s_theta, s_phi) in [0,1]^3 to physical X;
+ * the polar axis is x1 (Sec. 2).  r(s) is linear, or the tanh clustering of
+ * eq. (stretching) shifted to the mid-radius and scaled by the gap;
+ * theta = theta0 + s_theta (theta1 - theta0); phi = 2 pi s_phi. */
+typedef enum {
+    CPS_MAP_IDENTITY = 0, /* X = (r, theta, phi): a box, for tests */
+    CPS_MAP_SPHERE = 1,   /* X = (r cos t, r sin t cos p, r sin t sin p) */
+    CPS_MAP_OBLATE = 2,   /* x1 scaled by (1 - flattening) */
+    CPS_MAP_TRIAXIAL = 3  /* x1 by (1 - flattening), x2 by (1 + skew) */
+} cps_map;
+
+typedef struct {
+    int32_t n_r, n_theta, n_phi; /* cells; every level but the coarsest needs even dims */
+    int32_t map;                 /* cps_map */
+    double r_inner, r_outer;     /* the paper's shell: 1.5, 2.5 (gap 1, ratio 0.6) */
+    double theta0, theta1;       /* cone walls, e.g. 0.05 and pi - 0.05 */
+    double radial_stretch;       /* rx2 of eq. (stretching); 0 = uniform */
+    double flattening, skew;     /* oblate / triaxial shape parameters */
+    int32_t n_levels;            /* 0 = halve while > 1024 cells and dims even, >= 4 */
+} cps_grid;
+
+/* How the face metrics G_dq = |J^-1| (ds_d/dx_k)(ds_q/dx_k) (eq. (skewness))
+ * are formed at each face (Sec. 3.2 items 1-5):
+ *   MAP_CENTRAL   the inverse Jacobian's columns are chords of the map
+ *                 across the face centre (second-order central differences);
+ *   PAPER_VERTEX  the paper's item 1: the normal derivative averaged over the
+ *                 face's four vertices, tangential ones over its two edges. */
+typedef enum { CPS_METRICS_MAP_CENTRAL = 0, CPS_METRICS_PAPER_VERTEX = 1 } cps_metrics_method;
+
+typedef struct {
+    int32_t method; /* cps_metrics_method */
+} cps_metrics;
+
+typedef struct {
+    int32_t precision; /* 0: FP64 throughout; 1: FP32 V-cycles inside an FP64
+                          refinement loop (FP64 residual, update, coarse solve) */
+    int32_t max_iters; /* outer iterations; <= 0 means 200 */
+    int32_t accel;     /* 0: stationary iteration of V-cycles; 1: Krylov
+                          acceleration with the V-cycle as preconditioner
+                          (conjugate gradients for symmetric operators,
+                          BiCGStab when cross metrics make A non-symmetric) */
+    void* stream;      /* hipStream_t the calls are ordered on; NULL = null stream */
+} cps_opts;
+
+typedef struct {
+    int32_t iterations;      /* outer iterations done */
+    double rel_residual;     /* ||b - A p|| / ||b|| with b = rhs - mean(rhs) */
+    double rhs_mean_removed; /* mean(rhs) */
+    double seconds;          /* wall time of the call */
+} cps_info;
+
+typedef struct cps_handle cps_handle;
+
+/* Fill *g with the paper's shell defaults (n_* = 32, sphere, r 1.5..2.5,
+ * theta 0.05..pi-0.05, uniform radius, rule-based levels). */
+void cps_grid_default(cps_grid* g);
+
+/* Build the hierarchy on the current device: level plan, face metrics of
+ * every level (computed on the GPU from the map), classification of the
+ * operator (7-point when every cross metric vanishes, else 19-point), and
+ * the dense inverse of the coarsest operator plus alpha 1 1^T.
+ * grid, metrics, opts: host pointers, read during the call only.
+ * *out receives a handle owning all device memory of the hierarchy.
+ * Errors: CPS_E_INVALID (dims, non-positive det), CPS_E_OOM, CPS_E_HIP. */
+cps_status cps_setup(const cps_grid* grid, const cps_metrics* metrics, const cps_opts* opts,
+                     cps_handle** out);
+
+/* Solve A p = rhs - mean(rhs) to ||b - A p||_2 <= tol ||b||_2 from p = 0,
+ * then return p with zero mean.  rhs, p: device FP64 arrays of
+ * n_r*n_theta*n_phi elements (may not alias).  info: host, nullable.
+ * Synchronises the stream once per outer iteration (an 8-byte read).
+ * CPS_E_NOT_CONVERGED leaves the last iterate in p; a zero rhs returns
+ * p = 0 after 0 iterations. */
+cps_status cps_solve(cps_handle* h, const double* rhs, double* p, double tol, cps_info* info);
+
+/* Release every device allocation of the handle (NULL is allowed). */
+void cps_destroy(cps_handle* h);
+
+/* Thread-local description of the last error on this thread. */
+const char* cps_last_error(void);
+
+/* Levels and colouring of a handle: dims_out[3*l + {0,1,2}] for l < levels
+ * (host array of 48 ints), *ncolours = 2 (7-point) or 4 (19-point),
+ * *phi_invariant = 1 when the metrics are stored once per (r, theta). */
+cps_status cps_levels(const cps_handle* h, int32_t* n_levels, int32_t* dims_out,
+                      int32_t* ncolours, int32_t* phi_invariant);
+
+/* ---- Kernel-level entry points (FP64 hierarchy of the handle) ----------
+ * For parity tests of each step against an independent implementation.
+ * level l indexes the hierarchy (0 = finest); all arrays are device FP64
+ * in the [r][theta][phi] layout of that level. */
+
+/* G_out: [9][n_r][n_theta][n_phi] face metrics of level l as used by the
+ * kernels (entry 3d+q of a cell: G_dq on its low face in direction d). */
+cps_status cps_debug_metrics(cps_handle* h, int32_t level, double* G_out);
+/* y = A x on level l (eq. (PC_8) flux form). */
+cps_status cps_debug_apply(cps_handle* h, int32_t level, const double* x, double* y);
+/* r = b - A x on level l; *norm2 (host) receives sum of r^2. */
+cps_status cps_debug_residual(cps_handle* h, int32_t level, const double* b, const double* x,
+                              double* r, double* norm2);
+/* one Gauss-Seidel pass over the cells of colour `colour`, x in place. */
+cps_status cps_debug_gs_pass(cps_handle* h, int32_t level, int32_t colour, const double* b,
+                             double* x);
+/* bc (level l+1) = P^T r (level l): full weighting, 64-point. */
+cps_status cps_debug_restrict(cps_handle* h, int32_t level, const double* r, double* bc);
+/* x (level l) += P e (level l+1): cell-centred trilinear. */
+cps_status cps_debug_prolong(cps_handle* h, int32_t level, const double* e, double* x);
+/* e = (A_c + alpha 1 1^T)^-1 (b - mean b) on the coarsest level. */
+cps_status cps_debug_coarse_solve(cps_handle* h, const double* b, double* e);
+/* one V(2,2) cycle on level 0 with right-hand side b, x in place. */
+cps_status cps_debug_vcycle(cps_handle* h, const double* b, double* x);
+
+/* ---- Measurement -------------------------------------------------------
+ * Kernel classes timed on the finest level with HIP events recorded on the
+ * handle's stream around each launch. */
+enum {
+    CPS_KERNEL_GS = 0,       /* one Gauss-Seidel colour pass */
+    CPS_KERNEL_RESIDUAL = 1, /* r = b - A x (+ norm partials) */
+    CPS_KERNEL_APPLY = 2,    /* y = A x (Krylov products) */
+    CPS_KERNEL_RESTRICT = 3, /* full weighting to level 1 */
+    CPS_KERNEL_PROLONG = 4,  /* trilinear correction from level 1 */
+    CPS_KERNEL_CLASSES = 5
+};
+/* enable != 0 starts recording (and clears earlier records). */
+cps_status cps_profile_enable(cps_handle* h, int32_t enable);
+/* Synchronises the stream; *total_ms (host) = summed duration of the
+ * recorded launches of the class, *launches = their count; then clears. */
+cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_ms,
+                            int64_t* launches);
+/* dst[i] = src[i] for i < n (device FP64, ordered on `stream`, synchronous):
+ * a plain copy of known size, the yardstick for the HBM byte counters. */
+cps_status cps_debug_copy(const double* src, double* dst, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPS_H */

@@ -63,6 +63,7 @@ def _load():
             P = ctypes.c_void_p
             I = ctypes.c_int
             D = ctypes.c_double
+            lib.orc_max_threads.restype = I
             lib.orc_map.argtypes = [P, D, D, D, P]
             lib.orc_metric_from_chords.argtypes = [P, P]
             lib.orc_metric_from_chords.restype = D
@@ -130,6 +131,10 @@ def as_grid(g) -> Grid:
     if isinstance(g, Grid):
         return g
     return Grid(**{k: getattr(g, k) for k in Grid.__dataclass_fields__})
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
 
 
 def map_point(grid, sr: float, st: float, sp: float) -> np.ndarray:

@@ -26,6 +26,9 @@
  * parity unpinned (the paper reports none).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -33,6 +36,16 @@
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
+
+/* threads the oracle's parallel loops use */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Grid and map (Sec. 2, 3.1; the tanh clustering is eq. (stretching))      */

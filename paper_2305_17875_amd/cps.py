@@ -1,0 +1,295 @@
+"""ctypes binding of libcps.so -- argument marshalling only.
+
+Every function here forwards to the C ABI of ``include/cps.h`` with the same
+name; all computation runs in the HIP library.  Arrays are torch tensors on
+the current HIP device (float64, contiguous, [r][theta][phi]); torch is used
+only to own device memory and to provide the stream.  Loading fails loudly if
+the library has not been built (``python -m paper_2305_17875_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcps.so")
+
+CPS_OK, CPS_E_INVALID, CPS_E_OOM, CPS_E_HIP, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "CPS_OK", -1: "CPS_E_INVALID", -2: "CPS_E_OOM", -3: "CPS_E_HIP",
+                -4: "CPS_E_NOT_CONVERGED", -5: "CPS_E_DIVERGED"}
+MAP_IDENTITY, MAP_SPHERE, MAP_OBLATE, MAP_TRIAXIAL = 0, 1, 2, 3
+METRICS_MAP_CENTRAL, METRICS_PAPER_VERTEX = 0, 1
+
+
+class cps_grid(ctypes.Structure):
+    _fields_ = [
+        ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+        ("map", ctypes.c_int32),
+        ("r_inner", ctypes.c_double), ("r_outer", ctypes.c_double),
+        ("theta0", ctypes.c_double), ("theta1", ctypes.c_double),
+        ("radial_stretch", ctypes.c_double), ("flattening", ctypes.c_double),
+        ("skew", ctypes.c_double), ("n_levels", ctypes.c_int32),
+    ]
+
+
+class cps_metrics(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32)]
+
+
+class cps_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("accel", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class cps_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("rhs_mean_removed", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+class CpsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded library (raises if libcps.so is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2305_17875_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.cps_grid_default.argtypes = [P]
+        L.cps_grid_default.restype = None
+        L.cps_last_error.restype = ctypes.c_char_p
+        L.cps_setup.argtypes = [P, P, P, ctypes.POINTER(P)]
+        L.cps_setup.restype = I
+        L.cps_solve.argtypes = [P, P, P, D, P]
+        L.cps_solve.restype = I
+        L.cps_destroy.argtypes = [P]
+        L.cps_destroy.restype = None
+        L.cps_levels.argtypes = [P, P, P, P, P]
+        L.cps_levels.restype = I
+        L.cps_debug_metrics.argtypes = [P, I, P]
+        L.cps_debug_apply.argtypes = [P, I, P, P]
+        L.cps_debug_residual.argtypes = [P, I, P, P, P, P]
+        L.cps_debug_gs_pass.argtypes = [P, I, I, P, P]
+        L.cps_debug_restrict.argtypes = [P, I, P, P]
+        L.cps_debug_prolong.argtypes = [P, I, P, P]
+        L.cps_debug_coarse_solve.argtypes = [P, P, P]
+        L.cps_debug_vcycle.argtypes = [P, P, P]
+        L.cps_profile_enable.argtypes = [P, I]
+        L.cps_profile_read.argtypes = [P, I, P, P]
+        L.cps_debug_copy.argtypes = [P, P, ctypes.c_int64, P]
+        for f in ("cps_profile_enable", "cps_profile_read", "cps_debug_copy",
+                  "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
+                  "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
+                  "cps_debug_coarse_solve", "cps_debug_vcycle"):
+            getattr(L, f).restype = I
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().cps_last_error().decode()
+
+
+def _check(st: int):
+    if st != CPS_OK:
+        raise CpsError(st, last_error())
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def make_grid(g, n_levels: int = 0) -> cps_grid:
+    """A cps_grid from any object with the shell attributes (inputs.Shell)."""
+    c = cps_grid()
+    lib().cps_grid_default(ctypes.byref(c))
+    c.n_r, c.n_theta, c.n_phi = g.n_r, g.n_theta, g.n_phi
+    c.map = g.map
+    c.r_inner, c.r_outer = g.r_inner, g.r_outer
+    c.theta0, c.theta1 = g.theta0, g.theta1
+    c.radial_stretch = g.radial_stretch
+    c.flattening, c.skew = g.flattening, g.skew
+    c.n_levels = n_levels
+    return c
+
+
+def cps_setup(grid: cps_grid, metrics: cps_metrics, opts: cps_opts) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().cps_setup(ctypes.byref(grid), ctypes.byref(metrics), ctypes.byref(opts),
+                           ctypes.byref(h)))
+    return h
+
+
+def cps_solve(h, rhs, p, tol: float):
+    """Returns (status, cps_info); status CPS_E_NOT_CONVERGED is returned,
+    every other error raises."""
+    _, n = _dims(h, 0)
+    _expect(rhs, n, "rhs"); _expect(p, n, "p")
+    info = cps_info()
+    st = lib().cps_solve(h, _ptr(rhs), _ptr(p), tol, ctypes.byref(info))
+    if st not in (CPS_OK, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED):
+        _check(st)
+    return st, info
+
+
+def cps_destroy(h):
+    if h:
+        lib().cps_destroy(h)
+
+
+def cps_levels(h):
+    nl = ctypes.c_int32()
+    dims = (ctypes.c_int32 * 48)()
+    nc = ctypes.c_int32()
+    axi = ctypes.c_int32()
+    _check(lib().cps_levels(h, ctypes.byref(nl), dims, ctypes.byref(nc), ctypes.byref(axi)))
+    return [tuple(dims[3 * l:3 * l + 3]) for l in range(nl.value)], nc.value, bool(axi.value)
+
+
+def _dims(h, level):
+    levels, _, _ = cps_levels(h)
+    if not 0 <= level < len(levels):
+        raise ValueError(f"level {level} out of range")
+    return levels, levels[level][0] * levels[level][1] * levels[level][2]
+
+
+def _expect(t, n, what):
+    import torch
+    if t.dtype != torch.float64 or t.numel() != n:
+        raise ValueError(f"{what}: expected {n} float64 values, got {t.numel()} {t.dtype}")
+
+
+def cps_debug_metrics(h, level, G_out):
+    _, n = _dims(h, level)
+    _expect(G_out, 9 * n, "G_out")
+    _check(lib().cps_debug_metrics(h, level, _ptr(G_out)))
+
+
+def cps_debug_apply(h, level, x, y):
+    _, n = _dims(h, level)
+    _expect(x, n, "x"); _expect(y, n, "y")
+    _check(lib().cps_debug_apply(h, level, _ptr(x), _ptr(y)))
+
+
+def cps_debug_residual(h, level, b, x, r) -> float:
+    _, n = _dims(h, level)
+    for t, w in ((b, "b"), (x, "x"), (r, "r")):
+        _expect(t, n, w)
+    n2 = ctypes.c_double()
+    _check(lib().cps_debug_residual(h, level, _ptr(b), _ptr(x), _ptr(r), ctypes.byref(n2)))
+    return n2.value
+
+
+def cps_debug_gs_pass(h, level, colour, b, x):
+    _, n = _dims(h, level)
+    _expect(b, n, "b"); _expect(x, n, "x")
+    _check(lib().cps_debug_gs_pass(h, level, colour, _ptr(b), _ptr(x)))
+
+
+def cps_debug_restrict(h, level, r, bc):
+    levels, n = _dims(h, level)
+    if level + 1 >= len(levels):
+        raise ValueError("no coarser level")
+    _expect(r, n, "r"); _expect(bc, n // 8, "bc")
+    _check(lib().cps_debug_restrict(h, level, _ptr(r), _ptr(bc)))
+
+
+def cps_debug_prolong(h, level, e, x):
+    levels, n = _dims(h, level)
+    if level + 1 >= len(levels):
+        raise ValueError("no coarser level")
+    _expect(e, n // 8, "e"); _expect(x, n, "x")
+    _check(lib().cps_debug_prolong(h, level, _ptr(e), _ptr(x)))
+
+
+def cps_debug_coarse_solve(h, b, e):
+    levels, _ = _dims(h, 0)
+    nc = levels[-1][0] * levels[-1][1] * levels[-1][2]
+    _expect(b, nc, "b"); _expect(e, nc, "e")
+    _check(lib().cps_debug_coarse_solve(h, _ptr(b), _ptr(e)))
+
+
+def cps_debug_vcycle(h, b, x):
+    _, n = _dims(h, 0)
+    _expect(b, n, "b"); _expect(x, n, "x")
+    _check(lib().cps_debug_vcycle(h, _ptr(b), _ptr(x)))
+
+
+KERNEL_GS, KERNEL_RESIDUAL, KERNEL_APPLY, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
+
+
+def cps_profile_enable(h, enable: bool):
+    _check(lib().cps_profile_enable(h, 1 if enable else 0))
+
+
+def cps_profile_read(h, kernel_class: int):
+    """(total_ms, launches) recorded for the class since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().cps_profile_read(h, kernel_class, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def cps_debug_copy(src, dst, stream=None):
+    if src.numel() != dst.numel():
+        raise ValueError("size mismatch")
+    _expect(src, src.numel(), "src")
+    _expect(dst, src.numel(), "dst")
+    st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib().cps_debug_copy(_ptr(src), _ptr(dst), src.numel(), st))
+
+
+@dataclass
+class Result:
+    p: object
+    status: int
+    iterations: int
+    rel_residual: float
+    rhs_mean_removed: float
+    seconds: float
+
+
+class Solver:
+    """One hierarchy on the current device (owns a cps_handle)."""
+
+    def __init__(self, grid, precision: int = 0, accel: int = 1, max_iters: int = 200,
+                 metrics: int = METRICS_MAP_CENTRAL, n_levels: int = 0, stream=None):
+        import torch
+        self.shape = (grid.n_r, grid.n_theta, grid.n_phi)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        opts = cps_opts(precision, max_iters, accel, ctypes.c_void_p(s.cuda_stream))
+        self.h = cps_setup(make_grid(grid, n_levels), cps_metrics(metrics), opts)
+        self.levels, self.ncolours, self.phi_invariant = cps_levels(self.h)
+
+    def solve(self, rhs, tol: float = 1e-10, out=None) -> Result:
+        import torch
+        p = out if out is not None else torch.empty_like(rhs)
+        st, info = cps_solve(self.h, rhs, p, tol)
+        return Result(p, st, info.iterations, info.rel_residual, info.rhs_mean_removed,
+                      info.seconds)
+
+    def close(self):
+        if getattr(self, "h", None):
+            cps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

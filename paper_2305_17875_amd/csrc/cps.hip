@@ -1,0 +1,942 @@
+// cps.hip -- hierarchy, V-cycle, outer iterations and the C ABI.
+//
+// The library solves eq. (PC_6) of the shell solver (pressure correction)
+// by geometric multigrid on the transformed grid: face metrics computed on
+// the device for every level (Sec. 3.2), the flux-form operator of eq.
+// (PC_8), colour Gauss-Seidel smoothing, full-weighting restriction,
+// trilinear prolongation, a dense exact coarsest solve, V(2,2) cycles, and an
+// outer stationary or Krylov iteration, in FP64 or with FP32 V-cycles inside
+// FP64 refinement.
+#include "cps.h"
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+using namespace cps;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+    cps_status st;
+};
+
+[[noreturn]] void fail(cps_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+[[noreturn]] void fail(cps_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    throw Fail{st};
+}
+
+#define HIPC(call)                                                                         \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            fail(e_ == hipErrorOutOfMemory ? CPS_E_OOM : CPS_E_HIP, "%s: %s (%s:%d)", #call, \
+                 hipGetErrorString(e_), __FILE__, __LINE__);                               \
+    } while (0)
+
+#define LAUNCH_CHECK() HIPC(hipGetLastError())
+
+constexpr int kMaxLevels = 16;
+constexpr long long kMaxCoarse = 4096;
+
+inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <int M>
+using IM = std::integral_constant<int, M>;
+template <bool B>
+using BA = std::integral_constant<bool, B>;
+
+template <typename F>
+void dispatch(int mode, bool axi, F&& f)
+{
+    if (axi) {
+        if (mode == MODE_ORTHO) f(IM<MODE_ORTHO>{}, BA<true>{});
+        else if (mode == MODE_RT) f(IM<MODE_RT>{}, BA<true>{});
+        else f(IM<MODE_FULL>{}, BA<true>{});
+    } else {
+        if (mode == MODE_ORTHO) f(IM<MODE_ORTHO>{}, BA<false>{});
+        else if (mode == MODE_RT) f(IM<MODE_RT>{}, BA<false>{});
+        else f(IM<MODE_FULL>{}, BA<false>{});
+    }
+}
+
+template <typename T>
+struct Buf {
+    T* p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count)
+    {
+        if (p) HIPC(hipFree(p));
+        p = nullptr;
+        n = count;
+        if (count) HIPC(hipMalloc(&p, count * sizeof(T)));
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct LevelMem {
+    int nr = 0, nt = 0, np = 0, nc = 0;
+    long long n = 0, gk = 0;
+    Buf<double> G64;
+    Buf<float> G32;
+    Buf<double> x64, b64, r64;
+    Buf<float> x32, b32, r32;
+};
+
+} // namespace
+
+struct cps_handle {
+    cps_grid grid{};
+    cps_metrics met{};
+    cps_opts opts{};
+    hipStream_t stream = nullptr;
+    int L = 0;
+    LevelMem lv[kMaxLevels];
+    int mode = MODE_ORTHO;
+    bool axi = true;
+    int ncol = 2;
+    int nc = 0;
+    Buf<double> Ainv;
+    Buf<double> partial;
+    Buf<double> sc; // device scalars (S_* slots)
+    double* hsc = nullptr; // pinned host mirror
+    // level-0 FP64 work vectors
+    Buf<double> b0, r, z, pd, q, r0, v, s, t, ph, sh;
+    // optional HIP-event timing of the finest-level kernels, per class
+    bool prof = false;
+    std::vector<hipEvent_t> ev[CPS_KERNEL_CLASSES];
+    size_t ev_used[CPS_KERNEL_CLASSES] = {};
+};
+
+namespace {
+
+template <typename T>
+Level<T> view(const cps_handle* h, int l);
+
+template <>
+Level<double> view<double>(const cps_handle* h, int l)
+{
+    const LevelMem& m = h->lv[l];
+    return Level<double>{m.nr, m.nt, m.np, m.G64.p, m.gk};
+}
+
+template <>
+Level<float> view<float>(const cps_handle* h, int l)
+{
+    const LevelMem& m = h->lv[l];
+    return Level<float>{m.nr, m.nt, m.np, m.G32.p, m.gk};
+}
+
+template <typename T>
+T* xl(cps_handle* h, int l);
+template <>
+double* xl<double>(cps_handle* h, int l) { return h->lv[l].x64.p; }
+template <>
+float* xl<float>(cps_handle* h, int l) { return h->lv[l].x32.p; }
+template <typename T>
+T* bl(cps_handle* h, int l);
+template <>
+double* bl<double>(cps_handle* h, int l) { return h->lv[l].b64.p; }
+template <>
+float* bl<float>(cps_handle* h, int l) { return h->lv[l].b32.p; }
+template <typename T>
+T* rl(cps_handle* h, int l);
+template <>
+double* rl<double>(cps_handle* h, int l) { return h->lv[l].r64.p; }
+template <>
+float* rl<float>(cps_handle* h, int l) { return h->lv[l].r32.p; }
+
+// Brackets one finest-level launch of kernel class k with two events on the
+// handle's stream (no-op unless profiling is enabled).
+struct ProfScope {
+    cps_handle* h;
+    int k;
+    hipEvent_t stop = nullptr;
+    ProfScope(cps_handle* hh, int kk, int level) : h(hh), k(kk)
+    {
+        if (!h->prof || level != 0) return;
+        auto& v = h->ev[k];
+        size_t& u = h->ev_used[k];
+        while (v.size() < u + 2) {
+            hipEvent_t e;
+            HIPC(hipEventCreate(&e));
+            v.push_back(e);
+        }
+        HIPC(hipEventRecord(v[u], h->stream));
+        stop = v[u + 1];
+        u += 2;
+    }
+    ~ProfScope() noexcept(false)
+    {
+        if (stop) HIPC(hipEventRecord(stop, h->stream));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void fill(cps_handle* h, T* x, long long n, T v)
+{
+    k_fill<T><<<nblk(n), kBlock, 0, h->stream>>>(n, x, v);
+    LAUNCH_CHECK();
+}
+
+template <typename T>
+void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x)
+{
+    const Level<T> L = view<T>(h, l);
+    const long long nthreads = h->lv[l].n / (h->ncol == 2 ? 2 : 4);
+    ProfScope ps(h, CPS_KERNEL_GS, l);
+    dispatch(h->mode, h->axi, [&](auto M, auto A) {
+        k_gs<T, decltype(M)::value, decltype(A)::value>
+            <<<nblk(nthreads), kBlock, 0, h->stream>>>(L, b, x, colour, h->ncol);
+    });
+    LAUNCH_CHECK();
+}
+
+template <typename T>
+void smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse)
+{
+    for (int s = 0; s < sweeps; ++s)
+        for (int k = 0; k < h->ncol; ++k) gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x);
+}
+
+// r = b - A x; partial sums of r^2 into h->partial when want_norm
+template <typename T>
+void residual(cps_handle* h, int l, const T* b, const T* x, T* r, bool want_norm)
+{
+    const Level<T> L = view<T>(h, l);
+    const long long n = h->lv[l].n;
+    double* part = want_norm ? h->partial.p : nullptr;
+    ProfScope ps(h, CPS_KERNEL_RESIDUAL, l);
+    dispatch(h->mode, h->axi, [&](auto M, auto A) {
+        k_residual<T, decltype(M)::value, decltype(A)::value>
+            <<<nblk(n), kBlock, 0, h->stream>>>(L, b, x, r, part);
+    });
+    LAUNCH_CHECK();
+}
+
+// y = A x (level l); with dotv, partial sums of y . dotv
+template <typename T>
+void apply(cps_handle* h, int l, const T* x, T* y, const T* dotv)
+{
+    const Level<T> L = view<T>(h, l);
+    const long long n = h->lv[l].n;
+    double* part = dotv ? h->partial.p : nullptr;
+    ProfScope ps(h, CPS_KERNEL_APPLY, l);
+    dispatch(h->mode, h->axi, [&](auto M, auto A) {
+        k_apply<T, decltype(M)::value, decltype(A)::value>
+            <<<nblk(n), kBlock, 0, h->stream>>>(L, x, y, part, dotv);
+    });
+    LAUNCH_CHECK();
+}
+
+void reduce(cps_handle* h, long long nparts, int slot)
+{
+    k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p, nparts, h->sc.p + slot);
+    LAUNCH_CHECK();
+}
+
+template <typename T, typename U>
+void dot(cps_handle* h, long long n, const T* u, const U* v, int slot)
+{
+    k_dot<T, U><<<nblk(n), kBlock, 0, h->stream>>>(n, u, v, h->partial.p);
+    LAUNCH_CHECK();
+    reduce(h, nblk(n), slot);
+}
+
+template <typename T>
+void restrict_to(cps_handle* h, int l, const T* r, T* bc)
+{
+    const LevelMem& m = h->lv[l];
+    ProfScope ps(h, CPS_KERNEL_RESTRICT, l);
+    k_restrict<T><<<nblk(m.n / 8), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, r, bc);
+    LAUNCH_CHECK();
+}
+
+template <typename T>
+void prolong_add(cps_handle* h, int l, const T* e, T* x)
+{
+    const LevelMem& m = h->lv[l];
+    ProfScope ps(h, CPS_KERNEL_PROLONG, l);
+    k_prolong<T><<<nblk(m.n), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, e, x);
+    LAUNCH_CHECK();
+}
+
+template <typename T>
+void coarse_solve(cps_handle* h, const T* b, T* e)
+{
+    const int n = h->nc;
+    k_coarse_gemv<T><<<(n + 3) / 4, kBlock, 0, h->stream>>>(n, h->Ainv.p, b, e);
+    LAUNCH_CHECK();
+}
+
+// One V(2,2) cycle with level-0 right-hand side b0 and iterate x0 (in place).
+template <typename T>
+void vcycle(cps_handle* h, const T* b0, T* x0)
+{
+    const int L = h->L;
+    if (L == 1) {
+        coarse_solve<T>(h, b0, x0);
+        return;
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        const T* b = l == 0 ? b0 : bl<T>(h, l);
+        T* x = l == 0 ? x0 : xl<T>(h, l);
+        if (l > 0) fill<T>(h, x, h->lv[l].n, T(0));
+        smooth<T>(h, l, b, x, 2, false);
+        residual<T>(h, l, b, x, rl<T>(h, l), false);
+        restrict_to<T>(h, l, rl<T>(h, l), bl<T>(h, l + 1));
+    }
+    coarse_solve<T>(h, bl<T>(h, L - 1), xl<T>(h, L - 1));
+    for (int l = L - 2; l >= 0; --l) {
+        const T* b = l == 0 ? b0 : bl<T>(h, l);
+        T* x = l == 0 ? x0 : xl<T>(h, l);
+        prolong_add<T>(h, l, xl<T>(h, l + 1), x);
+        smooth<T>(h, l, b, x, 2, true);
+    }
+}
+
+// out = M^-1 in : one V-cycle from zero, FP64 or FP32 inside (scaled by
+// sc[S_SCALE] so that FP32 sees O(1) values).
+void precondition(cps_handle* h, const double* in, double* out)
+{
+    const long long n = h->lv[0].n;
+    if (h->opts.precision == 0) {
+        fill<double>(h, out, n, 0.0);
+        vcycle<double>(h, in, out);
+    } else {
+        float* b = h->lv[0].b32.p;
+        float* x = h->lv[0].x32.p;
+        k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, in, b, h->sc.p, S_SCALE, 1);
+        LAUNCH_CHECK();
+        fill<float>(h, x, n, 0.0f);
+        vcycle<float>(h, b, x);
+        k_cast<float, double><<<nblk(n), kBlock, 0, h->stream>>>(n, x, out, h->sc.p, S_SCALE, 0);
+        LAUNCH_CHECK();
+    }
+}
+
+double read_scalar(cps_handle* h, int slot)
+{
+    HIPC(hipMemcpyAsync(h->hsc + slot, h->sc.p + slot, sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    return h->hsc[slot];
+}
+
+#define SCALAR_KERNEL(h, k)                                 \
+    do {                                                    \
+        k<<<1, 1, 0, (h)->stream>>>((h)->sc.p);             \
+        LAUNCH_CHECK();                                     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+int level_plan(const cps_grid* g, int dims[kMaxLevels][3])
+{
+    int L = 1;
+    dims[0][0] = g->n_r;
+    dims[0][1] = g->n_theta;
+    dims[0][2] = g->n_phi;
+    for (;;) {
+        const int* p = dims[L - 1];
+        const bool can = p[0] % 2 == 0 && p[1] % 2 == 0 && p[2] % 2 == 0 && p[0] >= 4 &&
+                         p[1] >= 4 && p[2] >= 4;
+        const long long cells = (long long)p[0] * p[1] * p[2];
+        const bool want = g->n_levels > 0 ? L < g->n_levels : cells > 1024;
+        if (!want) break;
+        if (!can || L == kMaxLevels) {
+            if (g->n_levels > 0) fail(CPS_E_INVALID, "cannot build %d levels", g->n_levels);
+            break;
+        }
+        dims[L][0] = p[0] / 2;
+        dims[L][1] = p[1] / 2;
+        dims[L][2] = p[2] / 2;
+        ++L;
+    }
+    return L;
+}
+
+void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
+{
+    if (!g) fail(CPS_E_INVALID, "grid is NULL");
+    if (g->n_r < 1 || g->n_theta < 1 || g->n_phi < 1)
+        fail(CPS_E_INVALID, "dims must be positive (%d %d %d)", g->n_r, g->n_theta, g->n_phi);
+    if ((long long)g->n_r * g->n_theta * g->n_phi > (1LL << 31))
+        fail(CPS_E_INVALID, "grid too large");
+    if (g->map < CPS_MAP_IDENTITY || g->map > CPS_MAP_TRIAXIAL) fail(CPS_E_INVALID, "bad map");
+    if (!(g->r_outer > g->r_inner)) fail(CPS_E_INVALID, "r_outer must exceed r_inner");
+    if (g->map != CPS_MAP_IDENTITY && !(g->r_inner > 0)) fail(CPS_E_INVALID, "r_inner must be > 0");
+    if (!(g->theta1 > g->theta0)) fail(CPS_E_INVALID, "theta1 must exceed theta0");
+    if (g->map != CPS_MAP_IDENTITY && !(g->theta0 > 0 && g->theta1 < M_PI))
+        fail(CPS_E_INVALID, "cone walls must lie inside (0, pi)");
+    if (g->radial_stretch < 0) fail(CPS_E_INVALID, "radial_stretch must be >= 0");
+    if (g->n_levels < 0 || g->n_levels > kMaxLevels) fail(CPS_E_INVALID, "bad n_levels");
+    if (m && m->method != CPS_METRICS_MAP_CENTRAL && m->method != CPS_METRICS_PAPER_VERTEX)
+        fail(CPS_E_INVALID, "bad metrics method");
+    if (o && (o->precision < 0 || o->precision > 1)) fail(CPS_E_INVALID, "bad precision");
+    if (o && (o->accel < 0 || o->accel > 1)) fail(CPS_E_INVALID, "bad accel");
+}
+
+void build(cps_handle* h)
+{
+    int dims[kMaxLevels][3];
+    h->L = level_plan(&h->grid, dims);
+    const cps_grid& g = h->grid;
+    const bool axi = g.map != CPS_MAP_TRIAXIAL;
+    h->axi = axi;
+    MapParams mp{g.map, g.r_inner, g.r_outer, g.theta0, g.theta1, g.radial_stretch, g.flattening,
+                 g.skew};
+    int flags_all = 0;
+    std::vector<int> hflags;
+    Buf<int> dflags;
+    long long maxn = 0;
+    for (int l = 0; l < h->L; ++l) maxn = std::max(maxn, (long long)dims[l][0] * dims[l][1] * dims[l][2]);
+    dflags.alloc(nblk(maxn) + 1);
+    for (int l = 0; l < h->L; ++l) {
+        LevelMem& m = h->lv[l];
+        m.nr = dims[l][0];
+        m.nt = dims[l][1];
+        m.np = dims[l][2];
+        m.nc = axi ? 1 : m.np;
+        m.n = (long long)m.nr * m.nt * m.np;
+        m.gk = (long long)m.nr * m.nt * m.nc;
+        m.G64.alloc(9 * m.gk);
+        k_metrics<<<nblk(m.gk), kBlock, 0, h->stream>>>(mp, m.nr, m.nt, m.np, m.nc,
+                                                         h->met.method, m.G64.p, dflags.p);
+        LAUNCH_CHECK();
+        hflags.resize(nblk(m.gk));
+        HIPC(hipMemcpyAsync(hflags.data(), dflags.p, hflags.size() * sizeof(int),
+                            hipMemcpyDeviceToHost, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+        for (int f : hflags) flags_all |= f;
+    }
+    dflags.release();
+    if (flags_all & 1) fail(CPS_E_INVALID, "a face of the map has det <= 0");
+    h->mode = (flags_all & 4) ? MODE_FULL : ((flags_all & 2) ? MODE_RT : MODE_ORTHO);
+    h->ncol = h->mode == MODE_ORTHO ? 2 : 4;
+    if (h->L > 1) {
+        for (int l = 0; l < h->L - 1; ++l) {
+            const LevelMem& m = h->lv[l];
+            if (m.nr % 2 || m.nt % 2 || m.np % 2)
+                fail(CPS_E_INVALID, "level %d dims must be even", l);
+        }
+    }
+    // coarsest dense inverse of A_c + alpha 1 1^T
+    LevelMem& c = h->lv[h->L - 1];
+    if (c.n > kMaxCoarse)
+        fail(CPS_E_INVALID, "coarsest level has %lld cells (max %lld): choose even dims", c.n,
+             kMaxCoarse);
+    const int n = (int)c.n;
+    h->nc = n;
+    {
+        Buf<double> A, M0, M1;
+        Buf<int> used, piv, bad;
+        A.alloc((size_t)n * n);
+        M0.alloc((size_t)n * 2 * n);
+        M1.alloc((size_t)n * 2 * n);
+        used.alloc(n);
+        piv.alloc(n);
+        bad.alloc(1);
+        h->Ainv.alloc((size_t)n * n);
+        HIPC(hipMemsetAsync(A.p, 0, (size_t)n * n * sizeof(double), h->stream));
+        const Level<double> Lc = view<double>(h, h->L - 1);
+        dispatch(h->mode, h->axi, [&](auto M, auto AX) {
+            k_dense_rows<decltype(M)::value, decltype(AX)::value>
+                <<<nblk(27LL * n), kBlock, 0, h->stream>>>(Lc, A.p);
+        });
+        LAUNCH_CHECK();
+        const unsigned gblocks = std::min<long long>(nblk(2LL * n * n), 1024);
+        k_augment<<<gblocks, kBlock, 0, h->stream>>>(n, A.p, M0.p);
+        LAUNCH_CHECK();
+        k_fill<int><<<nblk(n), kBlock, 0, h->stream>>>(n, used.p, INT_MAX);
+        k_fill<int><<<nblk(n), kBlock, 0, h->stream>>>(n, piv.p, 0);
+        k_fill<int><<<1, kBlock, 0, h->stream>>>(1, bad.p, 0);
+        LAUNCH_CHECK();
+        double* src = M0.p;
+        double* dst = M1.p;
+        for (int k = 0; k < n; ++k) {
+            k_gj_step<<<gblocks, kBlock, 0, h->stream>>>(n, k, src, dst, used.p, piv.p, bad.p);
+            std::swap(src, dst);
+        }
+        LAUNCH_CHECK();
+        k_gj_extract<<<nblk((long long)n * n), kBlock, 0, h->stream>>>(n, src, piv.p, h->Ainv.p);
+        LAUNCH_CHECK();
+        int hbad = 0;
+        HIPC(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPC(hipStreamSynchronize(h->stream));
+        if (hbad) fail(CPS_E_INVALID, "coarsest operator is singular");
+        A.release(); M0.release(); M1.release(); used.release(); piv.release(); bad.release();
+    }
+    // per-level vectors
+    const bool mixed = h->opts.precision == 1;
+    for (int l = 0; l < h->L; ++l) {
+        LevelMem& m = h->lv[l];
+        if (l > 0) {
+            if (!mixed) {
+                m.x64.alloc(m.n);
+                m.b64.alloc(m.n);
+            }
+        }
+        if (!mixed && l < h->L - 1) m.r64.alloc(m.n);
+        if (mixed) {
+            m.G32.alloc(9 * m.gk);
+            k_to_f32<<<nblk(9 * m.gk), kBlock, 0, h->stream>>>(9 * m.gk, m.G64.p, m.G32.p);
+            LAUNCH_CHECK();
+            m.x32.alloc(m.n);
+            m.b32.alloc(m.n);
+            if (l < h->L - 1) m.r32.alloc(m.n);
+        }
+    }
+    if (mixed) // FP64 metrics are kept only on the finest level
+        for (int l = 1; l < h->L; ++l) h->lv[l].G64.release();
+    const long long n0 = h->lv[0].n;
+    h->partial.alloc(nblk(n0) + 64);
+    h->sc.alloc(S_COUNT);
+    HIPC(hipHostMalloc(&h->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
+    h->b0.alloc(n0);
+    h->r.alloc(n0);
+    if (h->opts.accel == 1) {
+        h->z.alloc(n0);
+        h->pd.alloc(n0);
+        h->q.alloc(n0);
+        if (h->mode != MODE_ORTHO) {
+            h->r0.alloc(n0); h->v.alloc(n0); h->s.alloc(n0); h->t.alloc(n0);
+            h->ph.alloc(n0); h->sh.alloc(n0);
+        }
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+}
+
+void destroy(cps_handle* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        LevelMem& m = h->lv[l];
+        m.G64.release(); m.G32.release();
+        m.x64.release(); m.b64.release(); m.r64.release();
+        m.x32.release(); m.b32.release(); m.r32.release();
+    }
+    h->Ainv.release(); h->partial.release(); h->sc.release();
+    h->b0.release(); h->r.release(); h->z.release(); h->pd.release(); h->q.release();
+    h->r0.release(); h->v.release(); h->s.release(); h->t.release(); h->ph.release();
+    h->sh.release();
+    if (h->hsc) (void)hipHostFree(h->hsc);
+    for (auto& v : h->ev)
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    delete h;
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+
+cps_status check_norm(double rr, double bb, double tol, double* rel)
+{
+    *rel = std::sqrt(rr / bb);
+    if (!std::isfinite(*rel)) return CPS_E_DIVERGED;
+    return *rel <= tol ? CPS_OK : CPS_E_NOT_CONVERGED;
+}
+
+cps_status solve(cps_handle* h, const double* rhs, double* x, double tol, cps_info* info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const long long n = h->lv[0].n;
+    const int maxit = h->opts.max_iters > 0 ? h->opts.max_iters : 200;
+    const bool mixed = h->opts.precision == 1;
+    // b0 = rhs - mean(rhs); bb = ||b0||^2
+    dot<double, double>(h, n, rhs, nullptr, S_SUM);
+    k_sub_mean<<<nblk(n), kBlock, 0, h->stream>>>(n, rhs, h->sc.p + S_SUM, h->b0.p);
+    LAUNCH_CHECK();
+    dot<double, double>(h, n, h->b0.p, h->b0.p, S_BB);
+    k_sqrt_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_SCALE, S_BB);
+    LAUNCH_CHECK();
+    fill<double>(h, x, n, 0.0);
+    HIPC(hipMemcpyAsync(h->hsc, h->sc.p, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    const double bb = h->hsc[S_BB];
+    const double mean = h->hsc[S_SUM] / (double)n;
+    int it = 0;
+    double rel = 0.0;
+    cps_status st = CPS_OK;
+    if (!std::isfinite(bb)) {
+        st = CPS_E_DIVERGED;
+        rel = NAN;
+    } else if (bb > 0.0) {
+        st = CPS_E_NOT_CONVERGED;
+        if (h->opts.accel == 0) {
+            // stationary: x <- x + V(b - A x)
+            if (!mixed) {
+                for (it = 1; it <= maxit; ++it) {
+                    vcycle<double>(h, h->b0.p, x);
+                    residual<double>(h, 0, h->b0.p, x, h->r.p, true);
+                    reduce(h, nblk(n), S_RR);
+                    st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
+                    if (st != CPS_E_NOT_CONVERGED) break;
+                }
+            } else {
+                k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, h->r.p);
+                LAUNCH_CHECK();
+                k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RR, S_BB);
+                LAUNCH_CHECK();
+                float* b32 = h->lv[0].b32.p;
+                float* x32 = h->lv[0].x32.p;
+                for (it = 1; it <= maxit; ++it) {
+                    // s = ||r||; FP32 cycle on r/s; x += s e; FP64 residual
+                    k_sqrt_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_SCALE, S_RR);
+                    k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, h->r.p, b32, h->sc.p, S_SCALE, 1);
+                    LAUNCH_CHECK();
+                    fill<float>(h, x32, n, 0.0f);
+                    vcycle<float>(h, b32, x32);
+                    k_ir_update<float><<<nblk(n), kBlock, 0, h->stream>>>(n, x, x32, h->sc.p + S_SCALE);
+                    LAUNCH_CHECK();
+                    residual<double>(h, 0, h->b0.p, x, h->r.p, true);
+                    reduce(h, nblk(n), S_RR);
+                    st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
+                    if (st != CPS_E_NOT_CONVERGED) break;
+                }
+            }
+        } else if (h->mode == MODE_ORTHO) {
+            // preconditioned CG; flexible (Polak-Ribiere) when the
+            // preconditioner runs in FP32
+            const int flexible = mixed ? 1 : 0;
+            double* r = h->r.p;
+            double* z = h->z.p;
+            double* p = h->pd.p;
+            double* q = h->q.p;
+            k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, r);
+            LAUNCH_CHECK();
+            precondition(h, r, z);
+            dot<double, double>(h, n, r, z, S_RZ);
+            k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, z, p);
+            LAUNCH_CHECK();
+            for (it = 1; it <= maxit; ++it) {
+                apply<double>(h, 0, p, q, p);
+                reduce(h, nblk(n), S_PQ);
+                SCALAR_KERNEL(h, k_cg_alpha);
+                k_cg_step<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, p, q, h->partial.p);
+                LAUNCH_CHECK();
+                reduce(h, nblk(n), S_RR);
+                st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
+                if (st != CPS_E_NOT_CONVERGED) break;
+                k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
+                LAUNCH_CHECK();
+                precondition(h, r, z);
+                dot<double, double>(h, n, r, z, S_RZ);
+                if (flexible) dot<double, double>(h, n, z, q, S_ZQ);
+                k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
+                k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
+                LAUNCH_CHECK();
+            }
+        } else {
+            // BiCGStab, right-preconditioned by the V-cycle
+            double* r = h->r.p;
+            double* p = h->pd.p;
+            k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, r);
+            k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, h->r0.p);
+            LAUNCH_CHECK();
+            fill<double>(h, p, n, 0.0);
+            fill<double>(h, h->v.p, n, 0.0);
+            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO_OLD, 1.0);
+            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_ALPHA, 1.0);
+            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_OMEGA, 1.0);
+            LAUNCH_CHECK();
+            for (it = 1; it <= maxit; ++it) {
+                dot<double, double>(h, n, h->r0.p, r, S_RHO);
+                SCALAR_KERNEL(h, k_bicg_beta);
+                k_bicg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, p);
+                LAUNCH_CHECK();
+                precondition(h, p, h->ph.p);
+                apply<double>(h, 0, h->ph.p, h->v.p, h->r0.p);
+                reduce(h, nblk(n), S_R0V);
+                SCALAR_KERNEL(h, k_bicg_alpha);
+                k_bicg_s<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, h->s.p);
+                LAUNCH_CHECK();
+                precondition(h, h->s.p, h->sh.p);
+                apply<double>(h, 0, h->sh.p, h->t.p, h->s.p);
+                reduce(h, nblk(n), S_TS);
+                dot<double, double>(h, n, h->t.p, h->t.p, S_TT);
+                SCALAR_KERNEL(h, k_bicg_omega);
+                k_bicg_step<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, h->ph.p, h->sh.p,
+                                                               h->s.p, h->t.p, h->partial.p);
+                LAUNCH_CHECK();
+                reduce(h, nblk(n), S_RR);
+                st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
+                if (st != CPS_E_NOT_CONVERGED) break;
+                k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO_OLD, S_RHO);
+                LAUNCH_CHECK();
+            }
+        }
+        if (it > maxit) it = maxit;
+        // zero-mean result
+        dot<double, double>(h, n, x, nullptr, S_SUM);
+        k_sub_mean<<<nblk(n), kBlock, 0, h->stream>>>(n, x, h->sc.p + S_SUM, x);
+        LAUNCH_CHECK();
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+    if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->rhs_mean_removed = mean;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (st == CPS_E_NOT_CONVERGED)
+        g_err = "iteration cap reached at relative residual " + std::to_string(rel);
+    else if (st == CPS_E_DIVERGED)
+        g_err = "residual norm is not finite";
+    return st;
+}
+
+template <typename F>
+cps_status guarded(F&& f)
+{
+    try {
+        f();
+        return CPS_OK;
+    } catch (const Fail& e) {
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return CPS_E_OOM;
+    }
+}
+
+void need_level(const cps_handle* h, int l, bool fine)
+{
+    if (!h) fail(CPS_E_INVALID, "handle is NULL");
+    if (l < 0 || l >= h->L || (fine && l >= h->L - 1))
+        fail(CPS_E_INVALID, "level %d out of range", l);
+    if (h->opts.precision != 0) fail(CPS_E_INVALID, "debug entry points need an FP64 handle");
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void cps_grid_default(cps_grid* g)
+{
+    if (!g) return;
+    std::memset(g, 0, sizeof *g);
+    g->n_r = g->n_theta = g->n_phi = 32;
+    g->map = CPS_MAP_SPHERE;
+    g->r_inner = 1.5;
+    g->r_outer = 2.5;
+    g->theta0 = 0.05;
+    g->theta1 = M_PI - 0.05;
+}
+
+const char* cps_last_error(void) { return g_err.c_str(); }
+
+cps_status cps_setup(const cps_grid* grid, const cps_metrics* metrics, const cps_opts* opts,
+                     cps_handle** out)
+{
+    if (!out) {
+        g_err = "out is NULL";
+        return CPS_E_INVALID;
+    }
+    *out = nullptr;
+    cps_handle* h = nullptr;
+    cps_status st = guarded([&] {
+        validate(grid, metrics, opts);
+        h = new cps_handle();
+        h->grid = *grid;
+        if (metrics) h->met = *metrics;
+        if (opts) h->opts = *opts;
+        h->stream = (hipStream_t)h->opts.stream;
+        build(h);
+    });
+    if (st != CPS_OK) {
+        destroy(h);
+        return st;
+    }
+    *out = h;
+    return CPS_OK;
+}
+
+cps_status cps_solve(cps_handle* h, const double* rhs, double* p, double tol, cps_info* info)
+{
+    cps_status st = CPS_OK;
+    cps_status g = guarded([&] {
+        if (!h || !rhs || !p) fail(CPS_E_INVALID, "NULL argument");
+        if (rhs == p) fail(CPS_E_INVALID, "rhs and p must not alias");
+        if (!(tol > 0)) fail(CPS_E_INVALID, "tol must be positive");
+        st = solve(h, rhs, p, tol, info);
+    });
+    return g != CPS_OK ? g : st;
+}
+
+void cps_destroy(cps_handle* h) { destroy(h); }
+
+cps_status cps_levels(const cps_handle* h, int32_t* n_levels, int32_t* dims_out,
+                      int32_t* ncolours, int32_t* phi_invariant)
+{
+    return guarded([&] {
+        if (!h) fail(CPS_E_INVALID, "handle is NULL");
+        if (n_levels) *n_levels = h->L;
+        if (dims_out)
+            for (int l = 0; l < h->L; ++l) {
+                dims_out[3 * l] = h->lv[l].nr;
+                dims_out[3 * l + 1] = h->lv[l].nt;
+                dims_out[3 * l + 2] = h->lv[l].np;
+            }
+        if (ncolours) *ncolours = h->ncol;
+        if (phi_invariant) *phi_invariant = h->axi ? 1 : 0;
+    });
+}
+
+cps_status cps_debug_metrics(cps_handle* h, int32_t level, double* G_out)
+{
+    return guarded([&] {
+        need_level(h, level, false);
+        const LevelMem& m = h->lv[level];
+        k_expand_metrics<<<nblk(m.n), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, m.nc, m.G64.p, G_out);
+        LAUNCH_CHECK();
+        HIPC(hipStreamSynchronize(h->stream));
+    });
+}
+
+cps_status cps_debug_apply(cps_handle* h, int32_t level, const double* x, double* y)
+{
+    return guarded([&] {
+        need_level(h, level, false);
+        apply<double>(h, level, x, y, nullptr);
+        HIPC(hipStreamSynchronize(h->stream));
+    });
+}
+
+cps_status cps_debug_residual(cps_handle* h, int32_t level, const double* b, const double* x,
+                              double* r, double* norm2)
+{
+    return guarded([&] {
+        need_level(h, level, false);
+        residual<double>(h, level, b, x, r, true);
+        reduce(h, nblk(h->lv[level].n), S_RR);
+        const double v = read_scalar(h, S_RR);
+        if (norm2) *norm2 = v;
+    });
+}
+
+cps_status cps_debug_gs_pass(cps_handle* h, int32_t level, int32_t colour, const double* b,
+                             double* x)
+{
+    return guarded([&] {
+        need_level(h, level, true);
+        if (colour < 0 || colour >= h->ncol) fail(CPS_E_INVALID, "bad colour");
+        gs_pass<double>(h, level, colour, b, x);
+        HIPC(hipStreamSynchronize(h->stream));
+    });
+}
+
+cps_status cps_debug_restrict(cps_handle* h, int32_t level, const double* r, double* bc)
+{
+    return guarded([&] {
+        need_level(h, level, true);
+        restrict_to<double>(h, level, r, bc);
+        HIPC(hipStreamSynchronize(h->stream));
+    });
+}
+
+cps_status cps_debug_prolong(cps_handle* h, int32_t level, const double* e, double* x)
+{
+    return guarded([&] {
+        need_level(h, level, true);
+        prolong_add<double>(h, level, e, x);
+        HIPC(hipStreamSynchronize(h->stream));
+    });
+}
+
+cps_status cps_debug_coarse_solve(cps_handle* h, const double* b, double* e)
+{
+    return guarded([&] {
+        need_level(h, 0, false);
+        coarse_solve<double>(h, b, e);
+        HIPC(hipStreamSynchronize(h->stream));
+    });
+}
+
+cps_status cps_debug_vcycle(cps_handle* h, const double* b, double* x)
+{
+    return guarded([&] {
+        need_level(h, 0, false);
+        vcycle<double>(h, b, x);
+        HIPC(hipStreamSynchronize(h->stream));
+    });
+}
+
+cps_status cps_profile_enable(cps_handle* h, int32_t enable)
+{
+    return guarded([&] {
+        if (!h) fail(CPS_E_INVALID, "handle is NULL");
+        h->prof = enable != 0;
+        for (auto& u : h->ev_used) u = 0;
+    });
+}
+
+cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_ms,
+                            int64_t* launches)
+{
+    return guarded([&] {
+        if (!h) fail(CPS_E_INVALID, "handle is NULL");
+        if (kernel_class < 0 || kernel_class >= CPS_KERNEL_CLASSES)
+            fail(CPS_E_INVALID, "bad kernel class");
+        HIPC(hipStreamSynchronize(h->stream));
+        double tot = 0.0;
+        const size_t u = h->ev_used[kernel_class];
+        for (size_t i = 0; i + 1 < u; i += 2) {
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, h->ev[kernel_class][i], h->ev[kernel_class][i + 1]));
+            tot += ms;
+        }
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = (int64_t)(u / 2);
+        h->ev_used[kernel_class] = 0;
+    });
+}
+
+cps_status cps_debug_copy(const double* src, double* dst, int64_t n, void* stream)
+{
+    return guarded([&] {
+        if (n < 0 || (n && (!src || !dst))) fail(CPS_E_INVALID, "bad copy arguments");
+        if (n == 0) return;
+        k_copy<double><<<nblk(n), kBlock, 0, (hipStream_t)stream>>>(n, src, dst);
+        LAUNCH_CHECK();
+        HIPC(hipStreamSynchronize((hipStream_t)stream));
+    });
+}
+
+} // extern "C"

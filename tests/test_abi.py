@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every function that include/cps.h declares, and the ctypes structures match
+the C layout (sizes and offsets printed by a gcc-compiled probe)."""
+import os
+import re
+import subprocess
+import ctypes
+
+import pytest
+
+from paper_2305_17875_amd import cps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cps.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cps_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("cps_setup", "cps_solve", "cps_destroy", "cps_last_error", "cps_levels",
+                 "cps_debug_residual", "cps_debug_gs_pass", "cps_debug_vcycle"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(cps.LIB_PATH):
+        pytest.skip("libcps.so not built")
+    out = subprocess.check_output(["nm", "-D", "--defined-only", cps.LIB_PATH], text=True)
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    L = cps.lib()  # loads on a host without a GPU
+    for n in declared_functions():
+        assert hasattr(L, n)
+
+
+def test_ctypes_layout_matches_c(tmp_path):
+    probe = tmp_path / "probe.c"
+    probe.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "cps.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu %zu\\n", sizeof(cps_grid), sizeof(cps_metrics), sizeof(cps_opts), sizeof(cps_info));\n'
+        'printf("%zu %zu %zu\\n", offsetof(cps_grid, r_inner), offsetof(cps_grid, skew), offsetof(cps_grid, n_levels));\n'
+        'printf("%zu %zu\\n", offsetof(cps_opts, stream), offsetof(cps_info, seconds));\n'
+        "return 0;}\n")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe),
+                           "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
+    assert vals[:4] == [ctypes.sizeof(cps.cps_grid), ctypes.sizeof(cps.cps_metrics),
+                        ctypes.sizeof(cps.cps_opts), ctypes.sizeof(cps.cps_info)]
+    assert vals[4:7] == [cps.cps_grid.r_inner.offset, cps.cps_grid.skew.offset,
+                         cps.cps_grid.n_levels.offset]
+    assert vals[7:] == [cps.cps_opts.stream.offset, cps.cps_info.seconds.offset]
+
+
+def test_grid_default_and_invalid_setup_without_gpu():
+    """cps_grid_default is pure host code; cps_setup rejects bad grids before
+    touching the device."""
+    if not os.path.exists(cps.LIB_PATH):
+        pytest.skip("libcps.so not built")
+    g = cps.cps_grid()
+    cps.lib().cps_grid_default(ctypes.byref(g))
+    assert (g.n_r, g.n_theta, g.n_phi, g.map) == (32, 32, 32, cps.MAP_SPHERE)
+    assert abs(g.r_inner - 1.5) < 1e-15 and abs(g.theta1 - (3.141592653589793 - 0.05)) < 1e-15
+    g.n_r = 0
+    h = ctypes.c_void_p()
+    st = cps.lib().cps_setup(ctypes.byref(g), None, None, ctypes.byref(h))
+    assert st == cps.CPS_E_INVALID and not h.value
+    assert "positive" in cps.last_error()
