@@ -63,7 +63,8 @@ typedef struct {
     double theta0, theta1;       /* cone walls, e.g. 0.05 and pi - 0.05 */
     double radial_stretch;       /* rx2 of eq. (stretching); 0 = uniform */
     double flattening, skew;     /* oblate / triaxial shape parameters */
-    int32_t n_levels;            /* 0 = halve while > 1024 cells and dims even, >= 4 */
+    int32_t n_levels;            /* 0 = halve while > 1024 cells, dims even and >= 4, and
+                                    n_phi stays even; n_phi must be even on every level */
 } cps_grid;
 
 /* How the face metrics G_dq = |J^-1| (ds_d/dx_k)(ds_q/dx_k) (eq. (skewness))

@@ -147,7 +147,9 @@ double orc_metric_from_chords(const double t[9], double G[9])
  *   the face's four vertices of the central difference across vertex planes
  *   (weight 1/8), each tangential derivative is the mean of the face's two
  *   edges along that direction (weight 1/2).
- * Cross entries below 1e-13 sqrt(G_dd G_qq) are set to zero; wall faces are
+ * Cross entries below 1e-10 sqrt(G_dd G_qq) are set to zero (chords are
+ * differences of nearby points, so an orthogonal map shows rounding noise of
+ * about 1e-12 relative at 512 cells per direction); wall faces are
  * zero.  Returns 0, or -1 if some interior face has det <= 0. */
 int orc_face_metrics(const og_grid* g, int nr, int nt, int np, int method, double* G)
 {
@@ -211,7 +213,7 @@ int orc_face_metrics(const og_grid* g, int nr, int nt, int np, int method, doubl
                         for (int p = 0; p < 3; ++p)
                             for (int q = 0; q < 3; ++q)
                                 if (p != q &&
-                                    fabs(Gf[3 * p + q]) <= 1e-13 * sqrt(fabs(Gf[4 * p] * Gf[4 * q])))
+                                    fabs(Gf[3 * p + q]) <= 1e-10 * sqrt(fabs(Gf[4 * p] * Gf[4 * q])))
                                     Gf[3 * p + q] = 0.0;
                     }
                     for (int q = 0; q < 3; ++q) G[(size_t)(3 * d + q) * N + id] = Gf[3 * d + q];
@@ -493,15 +495,17 @@ typedef struct {
 static size_t og_n(og_dims d) { return (size_t)d.nr * d.nt * d.np; }
 
 /* Level plan: halve every dimension while the level has more than 1024
- * cells and every dimension is even and at least 4.  n_levels > 0 asks for
- * exactly that many levels (-1 if impossible). */
+ * cells, every dimension is even and at least 4, and n_phi stays even on
+ * the coarser level (red-black colouring wraps around the periodic phi
+ * direction only when n_phi is even).  n_levels > 0 asks for exactly that
+ * many levels (-1 if impossible). */
 int orc_level_plan(int nr, int nt, int np, int n_levels, int* dims_out /* [16][3] */)
 {
     int L = 1;
     dims_out[0] = nr; dims_out[1] = nt; dims_out[2] = np;
     for (;;) {
         int* p = &dims_out[3 * (L - 1)];
-        int can = p[0] % 2 == 0 && p[1] % 2 == 0 && p[2] % 2 == 0 && p[0] >= 4 && p[1] >= 4 &&
+        int can = p[0] % 2 == 0 && p[1] % 2 == 0 && p[2] % 4 == 0 && p[0] >= 4 && p[1] >= 4 &&
                   p[2] >= 4;
         long cells = (long)p[0] * p[1] * p[2];
         int want = n_levels > 0 ? L < n_levels : cells > 1024;

@@ -59,11 +59,41 @@ constexpr int kMaxLevels = 16;
 constexpr long long kMaxCoarse = 4096;
 
 inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+// capped grid of a stencil launch over nr planes of bpa blocks each
+inline unsigned grid_of(int nr, int bpa) { return (unsigned)std::min<long long>((long long)nr * bpa, kMaxGrid); }
+// capped grid of a grid-stride vector launch
+inline unsigned vgrid(long long n) { return std::min<unsigned>(nblk(n), kMaxGrid); }
 
 template <int M>
 using IM = std::integral_constant<int, M>;
 template <bool B>
 using BA = std::integral_constant<bool, B>;
+
+// Calls f(MODE, AXI, UROW, LTAG) as integral constants for a level: the
+// stencil shape, phi-invariant metrics, wave-uniform rows (n_phi / 2 a
+// multiple of 64) and the finest-level tag.
+template <typename F>
+void dispatch4(int mode, bool axi, bool urow, int ltag, F&& f)
+{
+    auto rest = [&](auto M, auto A) {
+        if (urow) {
+            if (ltag == 0) f(M, A, BA<true>{}, IM<0>{});
+            else f(M, A, BA<true>{}, IM<1>{});
+        } else {
+            if (ltag == 0) f(M, A, BA<false>{}, IM<0>{});
+            else f(M, A, BA<false>{}, IM<1>{});
+        }
+    };
+    if (axi) {
+        if (mode == MODE_ORTHO) rest(IM<MODE_ORTHO>{}, BA<true>{});
+        else if (mode == MODE_RT) rest(IM<MODE_RT>{}, BA<true>{});
+        else rest(IM<MODE_FULL>{}, BA<true>{});
+    } else {
+        if (mode == MODE_ORTHO) rest(IM<MODE_ORTHO>{}, BA<false>{});
+        else if (mode == MODE_RT) rest(IM<MODE_RT>{}, BA<false>{});
+        else rest(IM<MODE_FULL>{}, BA<false>{});
+    }
+}
 
 template <typename F>
 void dispatch(int mode, bool axi, F&& f)
@@ -79,10 +109,15 @@ void dispatch(int mode, bool axi, F&& f)
     }
 }
 
+// Owning device buffer (freed on destruction; not copyable).
 template <typename T>
 struct Buf {
     T* p = nullptr;
     size_t n = 0;
+    Buf() = default;
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+    ~Buf() { release(); }
     void alloc(size_t count)
     {
         if (p) HIPC(hipFree(p));
@@ -101,6 +136,7 @@ struct Buf {
 struct LevelMem {
     int nr = 0, nt = 0, np = 0, nc = 0;
     long long n = 0, gk = 0;
+    Geo geo{};
     Buf<double> G64;
     Buf<float> G32;
     Buf<double> x64, b64, r64;
@@ -125,7 +161,7 @@ struct cps_handle {
     Buf<double> sc; // device scalars (S_* slots)
     double* hsc = nullptr; // pinned host mirror
     // level-0 FP64 work vectors
-    Buf<double> b0, r, z, pd, q, r0, v, s, t, ph, sh;
+    Buf<double> x0, b0, r, z, pd, q, r0, v, s, t, ph, sh;
     // optional HIP-event timing of the finest-level kernels, per class
     bool prof = false;
     std::vector<hipEvent_t> ev[CPS_KERNEL_CLASSES];
@@ -141,14 +177,14 @@ template <>
 Level<double> view<double>(const cps_handle* h, int l)
 {
     const LevelMem& m = h->lv[l];
-    return Level<double>{m.nr, m.nt, m.np, m.G64.p, m.gk};
+    return Level<double>{m.geo, m.G64.p, m.gk};
 }
 
 template <>
 Level<float> view<float>(const cps_handle* h, int l)
 {
     const LevelMem& m = h->lv[l];
-    return Level<float>{m.nr, m.nt, m.np, m.G32.p, m.gk};
+    return Level<float>{m.geo, m.G32.p, m.gk};
 }
 
 template <typename T>
@@ -207,15 +243,47 @@ void fill(cps_handle* h, T* x, long long n, T v)
     LAUNCH_CHECK();
 }
 
+// Launch shape of the marching kernels (7-point stencil, phi-invariant
+// metrics): bpa blocks per plane, planes split into chunks of ch so that the
+// grid has about 2048 blocks (one resident wave of 8 blocks per CU).
+struct MarchShape {
+    int bpa, ch, grid;
+};
+
+MarchShape march_shape(const Geo& g)
+{
+    const int bpa = (int)nblk(g.rowlen);
+    int nchunks = std::max(1, std::min(g.nr, (2048 + bpa - 1) / bpa));
+    const int ch = (g.nr + nchunks - 1) / nchunks;
+    nchunks = (g.nr + ch - 1) / ch;
+    return {bpa, ch, bpa * nchunks};
+}
+
+inline bool marching(const cps_handle* h) { return h->mode == MODE_ORTHO && h->axi; }
+
 template <typename T>
 void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x)
 {
     const Level<T> L = view<T>(h, l);
-    const long long nthreads = h->lv[l].n / (h->ncol == 2 ? 2 : 4);
+    const int rowlen = h->ncol == 2 ? L.g.rowlen : L.g.rowlen / 2;
+    const int bpa = (int)nblk(rowlen);
     ProfScope ps(h, CPS_KERNEL_GS, l);
-    dispatch(h->mode, h->axi, [&](auto M, auto A) {
-        k_gs<T, decltype(M)::value, decltype(A)::value>
-            <<<nblk(nthreads), kBlock, 0, h->stream>>>(L, b, x, colour, h->ncol);
+    if (marching(h)) {
+        const MarchShape ms = march_shape(L.g);
+        auto launch = [&](auto U, auto T_) {
+            k_gs_march<T, decltype(U)::value, decltype(T_)::value>
+                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour);
+        };
+        const bool u = L.g.nh % 64 == 0;
+        if (l == 0) u ? launch(BA<true>{}, IM<0>{}) : launch(BA<false>{}, IM<0>{});
+        else u ? launch(BA<true>{}, IM<1>{}) : launch(BA<false>{}, IM<1>{});
+        LAUNCH_CHECK();
+        return;
+    }
+    dispatch4(h->mode, h->axi, L.g.nh % 64 == 0, l == 0 ? 0 : 1, [&](auto M, auto A, auto U, auto T_) {
+        k_gs<T, decltype(M)::value, decltype(A)::value, decltype(U)::value, decltype(T_)::value>
+            <<<grid_of(L.g.nr, bpa), kBlock, 0, h->stream>>>(L.g, L.G, L.gk, bpa, b, x, colour,
+                                                             h->ncol);
     });
     LAUNCH_CHECK();
 }
@@ -227,34 +295,62 @@ void smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse)
         for (int k = 0; k < h->ncol; ++k) gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x);
 }
 
-// r = b - A x; partial sums of r^2 into h->partial when want_norm
+// r = b - A x; partial sums of r^2 into h->partial when want_norm.
+// Returns the number of partial sums written.
 template <typename T>
-void residual(cps_handle* h, int l, const T* b, const T* x, T* r, bool want_norm)
+long long residual(cps_handle* h, int l, const T* b, const T* x, T* r, bool want_norm)
 {
     const Level<T> L = view<T>(h, l);
-    const long long n = h->lv[l].n;
+    const int bpa = (int)nblk(L.g.rowlen);
     double* part = want_norm ? h->partial.p : nullptr;
     ProfScope ps(h, CPS_KERNEL_RESIDUAL, l);
-    dispatch(h->mode, h->axi, [&](auto M, auto A) {
-        k_residual<T, decltype(M)::value, decltype(A)::value>
-            <<<nblk(n), kBlock, 0, h->stream>>>(L, b, x, r, part);
+    if (marching(h)) {
+        const MarchShape ms = march_shape(L.g);
+        auto launch = [&](auto U, auto T_) {
+            k_residual_march<T, decltype(U)::value, decltype(T_)::value>
+                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, r, part);
+        };
+        const bool u = L.g.nh % 64 == 0;
+        if (l == 0) u ? launch(BA<true>{}, IM<0>{}) : launch(BA<false>{}, IM<0>{});
+        else u ? launch(BA<true>{}, IM<1>{}) : launch(BA<false>{}, IM<1>{});
+        LAUNCH_CHECK();
+        return ms.grid;
+    }
+    dispatch4(h->mode, h->axi, L.g.nh % 64 == 0, l == 0 ? 0 : 1, [&](auto M, auto A, auto U, auto T_) {
+        k_residual<T, decltype(M)::value, decltype(A)::value, decltype(U)::value, decltype(T_)::value>
+            <<<grid_of(L.g.nr, bpa), kBlock, 0, h->stream>>>(L.g, L.G, L.gk, bpa, b, x, r, part);
     });
     LAUNCH_CHECK();
+    return grid_of(L.g.nr, bpa);
 }
 
-// y = A x (level l); with dotv, partial sums of y . dotv
+// y = A x (level l); with dotv, partial sums of y . dotv.  Returns the
+// number of partial sums written.
 template <typename T>
-void apply(cps_handle* h, int l, const T* x, T* y, const T* dotv)
+long long apply(cps_handle* h, int l, const T* x, T* y, const T* dotv)
 {
     const Level<T> L = view<T>(h, l);
-    const long long n = h->lv[l].n;
+    const int bpa = (int)nblk(L.g.rowlen);
     double* part = dotv ? h->partial.p : nullptr;
     ProfScope ps(h, CPS_KERNEL_APPLY, l);
-    dispatch(h->mode, h->axi, [&](auto M, auto A) {
-        k_apply<T, decltype(M)::value, decltype(A)::value>
-            <<<nblk(n), kBlock, 0, h->stream>>>(L, x, y, part, dotv);
+    if (marching(h)) {
+        const MarchShape ms = march_shape(L.g);
+        auto launch = [&](auto U, auto T_) {
+            k_apply_march<T, decltype(U)::value, decltype(T_)::value>
+                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, x, y, part, dotv);
+        };
+        const bool u = L.g.nh % 64 == 0;
+        if (l == 0) u ? launch(BA<true>{}, IM<0>{}) : launch(BA<false>{}, IM<0>{});
+        else u ? launch(BA<true>{}, IM<1>{}) : launch(BA<false>{}, IM<1>{});
+        LAUNCH_CHECK();
+        return ms.grid;
+    }
+    dispatch4(h->mode, h->axi, L.g.nh % 64 == 0, l == 0 ? 0 : 1, [&](auto M, auto A, auto U, auto T_) {
+        k_apply<T, decltype(M)::value, decltype(A)::value, decltype(U)::value, decltype(T_)::value>
+            <<<grid_of(L.g.nr, bpa), kBlock, 0, h->stream>>>(L.g, L.G, L.gk, bpa, x, y, part, dotv);
     });
     LAUNCH_CHECK();
+    return grid_of(L.g.nr, bpa);
 }
 
 void reduce(cps_handle* h, long long nparts, int slot)
@@ -266,26 +362,30 @@ void reduce(cps_handle* h, long long nparts, int slot)
 template <typename T, typename U>
 void dot(cps_handle* h, long long n, const T* u, const U* v, int slot)
 {
-    k_dot<T, U><<<nblk(n), kBlock, 0, h->stream>>>(n, u, v, h->partial.p);
+    k_dot<T, U><<<vgrid(n), kBlock, 0, h->stream>>>(n, u, v, h->partial.p);
     LAUNCH_CHECK();
-    reduce(h, nblk(n), slot);
+    reduce(h, vgrid(n), slot);
 }
 
 template <typename T>
 void restrict_to(cps_handle* h, int l, const T* r, T* bc)
 {
-    const LevelMem& m = h->lv[l];
+    const Geo& f = h->lv[l].geo;
+    const Geo& c = h->lv[l + 1].geo;
+    const int bpa = (int)nblk(c.rowlen);
     ProfScope ps(h, CPS_KERNEL_RESTRICT, l);
-    k_restrict<T><<<nblk(m.n / 8), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, r, bc);
+    k_restrict<T><<<c.nr * bpa, kBlock, 0, h->stream>>>(f, c, bpa, r, bc);
     LAUNCH_CHECK();
 }
 
 template <typename T>
 void prolong_add(cps_handle* h, int l, const T* e, T* x)
 {
-    const LevelMem& m = h->lv[l];
+    const Geo& f = h->lv[l].geo;
+    const Geo& c = h->lv[l + 1].geo;
+    const int bpa = (int)nblk(f.rowlen);
     ProfScope ps(h, CPS_KERNEL_PROLONG, l);
-    k_prolong<T><<<nblk(m.n), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, e, x);
+    k_prolong<T><<<f.nr * bpa, kBlock, 0, h->stream>>>(f, c, bpa, e, x);
     LAUNCH_CHECK();
 }
 
@@ -369,7 +469,9 @@ int level_plan(const cps_grid* g, int dims[kMaxLevels][3])
     dims[0][2] = g->n_phi;
     for (;;) {
         const int* p = dims[L - 1];
-        const bool can = p[0] % 2 == 0 && p[1] % 2 == 0 && p[2] % 2 == 0 && p[0] >= 4 &&
+        // halving keeps n_phi even on the coarser level (colourings and the
+        // parity-split layout wrap around phi only for even n_phi)
+        const bool can = p[0] % 2 == 0 && p[1] % 2 == 0 && p[2] % 4 == 0 && p[0] >= 4 &&
                          p[1] >= 4 && p[2] >= 4;
         const long long cells = (long long)p[0] * p[1] * p[2];
         const bool want = g->n_levels > 0 ? L < g->n_levels : cells > 1024;
@@ -430,6 +532,9 @@ void build(cps_handle* h)
         m.nc = axi ? 1 : m.np;
         m.n = (long long)m.nr * m.nt * m.np;
         m.gk = (long long)m.nr * m.nt * m.nc;
+        m.geo = make_geo(m.nr, m.nt, m.np);
+        if (m.np % 2)
+            fail(CPS_E_INVALID, "n_phi must be even on every level (level %d has %d)", l, m.np);
         m.G64.alloc(9 * m.gk);
         k_metrics<<<nblk(m.gk), kBlock, 0, h->stream>>>(mp, m.nr, m.nt, m.np, m.nc,
                                                          h->met.method, m.G64.p, dflags.p);
@@ -523,6 +628,7 @@ void build(cps_handle* h)
     h->partial.alloc(nblk(n0) + 64);
     h->sc.alloc(S_COUNT);
     HIPC(hipHostMalloc(&h->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
+    h->x0.alloc(n0);
     h->b0.alloc(n0);
     h->r.alloc(n0);
     if (h->opts.accel == 1) {
@@ -548,7 +654,7 @@ void destroy(cps_handle* h)
         m.x32.release(); m.b32.release(); m.r32.release();
     }
     h->Ainv.release(); h->partial.release(); h->sc.release();
-    h->b0.release(); h->r.release(); h->z.release(); h->pd.release(); h->q.release();
+    h->x0.release(); h->b0.release(); h->r.release(); h->z.release(); h->pd.release(); h->q.release();
     h->r0.release(); h->v.release(); h->s.release(); h->t.release(); h->ph.release();
     h->sh.release();
     if (h->hsc) (void)hipHostFree(h->hsc);
@@ -568,20 +674,23 @@ cps_status check_norm(double rr, double bb, double tol, double* rel)
     return *rel <= tol ? CPS_OK : CPS_E_NOT_CONVERGED;
 }
 
-cps_status solve(cps_handle* h, const double* rhs, double* x, double tol, cps_info* info)
+cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cps_info* info)
 {
     const auto t0 = std::chrono::steady_clock::now();
     const long long n = h->lv[0].n;
     const int maxit = h->opts.max_iters > 0 ? h->opts.max_iters : 200;
     const bool mixed = h->opts.precision == 1;
-    // b0 = rhs - mean(rhs); bb = ||b0||^2
+    double* x = h->x0.p; // iterate, parity-split order
+    // b0 = rhs - mean(rhs) in split order; bb = ||b0||^2
     dot<double, double>(h, n, rhs, nullptr, S_SUM);
-    k_sub_mean<<<nblk(n), kBlock, 0, h->stream>>>(n, rhs, h->sc.p + S_SUM, h->b0.p);
+    k_to_split<double, double><<<nblk(n), kBlock, 0, h->stream>>>(h->lv[0].geo, rhs, h->b0.p,
+                                                                   h->sc.p + S_SUM);
     LAUNCH_CHECK();
     dot<double, double>(h, n, h->b0.p, h->b0.p, S_BB);
     k_sqrt_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_SCALE, S_BB);
     LAUNCH_CHECK();
     fill<double>(h, x, n, 0.0);
+    fill<double>(h, p_out, n, 0.0);
     HIPC(hipMemcpyAsync(h->hsc, h->sc.p, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                         h->stream));
     HIPC(hipStreamSynchronize(h->stream));
@@ -600,8 +709,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* x, double tol, cps_in
             if (!mixed) {
                 for (it = 1; it <= maxit; ++it) {
                     vcycle<double>(h, h->b0.p, x);
-                    residual<double>(h, 0, h->b0.p, x, h->r.p, true);
-                    reduce(h, nblk(n), S_RR);
+                    reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
                     st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
                     if (st != CPS_E_NOT_CONVERGED) break;
                 }
@@ -621,8 +729,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* x, double tol, cps_in
                     vcycle<float>(h, b32, x32);
                     k_ir_update<float><<<nblk(n), kBlock, 0, h->stream>>>(n, x, x32, h->sc.p + S_SCALE);
                     LAUNCH_CHECK();
-                    residual<double>(h, 0, h->b0.p, x, h->r.p, true);
-                    reduce(h, nblk(n), S_RR);
+                    reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
                     st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
                     if (st != CPS_E_NOT_CONVERGED) break;
                 }
@@ -642,12 +749,11 @@ cps_status solve(cps_handle* h, const double* rhs, double* x, double tol, cps_in
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, z, p);
             LAUNCH_CHECK();
             for (it = 1; it <= maxit; ++it) {
-                apply<double>(h, 0, p, q, p);
-                reduce(h, nblk(n), S_PQ);
+                reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
                 SCALAR_KERNEL(h, k_cg_alpha);
-                k_cg_step<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, p, q, h->partial.p);
+                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, p, q, h->partial.p);
                 LAUNCH_CHECK();
-                reduce(h, nblk(n), S_RR);
+                reduce(h, vgrid(n), S_RR);
                 st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
                 if (st != CPS_E_NOT_CONVERGED) break;
                 k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
@@ -678,20 +784,18 @@ cps_status solve(cps_handle* h, const double* rhs, double* x, double tol, cps_in
                 k_bicg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, p);
                 LAUNCH_CHECK();
                 precondition(h, p, h->ph.p);
-                apply<double>(h, 0, h->ph.p, h->v.p, h->r0.p);
-                reduce(h, nblk(n), S_R0V);
+                reduce(h, apply<double>(h, 0, h->ph.p, h->v.p, h->r0.p), S_R0V);
                 SCALAR_KERNEL(h, k_bicg_alpha);
                 k_bicg_s<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, h->s.p);
                 LAUNCH_CHECK();
                 precondition(h, h->s.p, h->sh.p);
-                apply<double>(h, 0, h->sh.p, h->t.p, h->s.p);
-                reduce(h, nblk(n), S_TS);
+                reduce(h, apply<double>(h, 0, h->sh.p, h->t.p, h->s.p), S_TS);
                 dot<double, double>(h, n, h->t.p, h->t.p, S_TT);
                 SCALAR_KERNEL(h, k_bicg_omega);
-                k_bicg_step<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, h->ph.p, h->sh.p,
+                k_bicg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, h->ph.p, h->sh.p,
                                                                h->s.p, h->t.p, h->partial.p);
                 LAUNCH_CHECK();
-                reduce(h, nblk(n), S_RR);
+                reduce(h, vgrid(n), S_RR);
                 st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
                 if (st != CPS_E_NOT_CONVERGED) break;
                 k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO_OLD, S_RHO);
@@ -699,9 +803,10 @@ cps_status solve(cps_handle* h, const double* rhs, double* x, double tol, cps_in
             }
         }
         if (it > maxit) it = maxit;
-        // zero-mean result
+        // zero-mean result in natural order
         dot<double, double>(h, n, x, nullptr, S_SUM);
-        k_sub_mean<<<nblk(n), kBlock, 0, h->stream>>>(n, x, h->sc.p + S_SUM, x);
+        k_from_split<double, double><<<nblk(n), kBlock, 0, h->stream>>>(h->lv[0].geo, x, p_out,
+                                                                         h->sc.p + S_SUM);
         LAUNCH_CHECK();
     }
     HIPC(hipStreamSynchronize(h->stream));
@@ -730,6 +835,26 @@ cps_status guarded(F&& f)
         g_err = "host allocation failed";
         return CPS_E_OOM;
     }
+}
+
+// Device copy of a natural-order level vector in parity-split order (the
+// buffer is owned by `tmp`), and the copy back.  Used by the per-step entry
+// points, whose arguments are in natural order.
+double* split_copy(cps_handle* h, int l, const double* nat, Buf<double>& tmp)
+{
+    const long long n = h->lv[l].n;
+    tmp.alloc(n);
+    k_to_split<double, double><<<nblk(n), kBlock, 0, h->stream>>>(h->lv[l].geo, nat, tmp.p, nullptr);
+    LAUNCH_CHECK();
+    return tmp.p;
+}
+
+void natural_copy(cps_handle* h, int l, const double* split, double* nat)
+{
+    const long long n = h->lv[l].n;
+    k_from_split<double, double><<<nblk(n), kBlock, 0, h->stream>>>(h->lv[l].geo, split, nat, nullptr);
+    LAUNCH_CHECK();
+    HIPC(hipStreamSynchronize(h->stream));
 }
 
 void need_level(const cps_handle* h, int l, bool fine)
@@ -824,7 +949,7 @@ cps_status cps_debug_metrics(cps_handle* h, int32_t level, double* G_out)
     return guarded([&] {
         need_level(h, level, false);
         const LevelMem& m = h->lv[level];
-        k_expand_metrics<<<nblk(m.n), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, m.nc, m.G64.p, G_out);
+        k_expand_metrics<<<nblk(m.n), kBlock, 0, h->stream>>>(m.geo, h->axi ? 1 : 0, m.G64.p, G_out);
         LAUNCH_CHECK();
         HIPC(hipStreamSynchronize(h->stream));
     });
@@ -834,8 +959,11 @@ cps_status cps_debug_apply(cps_handle* h, int32_t level, const double* x, double
 {
     return guarded([&] {
         need_level(h, level, false);
-        apply<double>(h, level, x, y, nullptr);
-        HIPC(hipStreamSynchronize(h->stream));
+        Buf<double> xs, ys;
+        const double* xp = split_copy(h, level, x, xs);
+        ys.alloc(h->lv[level].n);
+        apply<double>(h, level, xp, ys.p, nullptr);
+        natural_copy(h, level, ys.p, y);
     });
 }
 
@@ -844,8 +972,12 @@ cps_status cps_debug_residual(cps_handle* h, int32_t level, const double* b, con
 {
     return guarded([&] {
         need_level(h, level, false);
-        residual<double>(h, level, b, x, r, true);
-        reduce(h, nblk(h->lv[level].n), S_RR);
+        Buf<double> bs, xs, rs;
+        const double* bp = split_copy(h, level, b, bs);
+        const double* xp = split_copy(h, level, x, xs);
+        rs.alloc(h->lv[level].n);
+        reduce(h, residual<double>(h, level, bp, xp, rs.p, true), S_RR);
+        natural_copy(h, level, rs.p, r);
         const double v = read_scalar(h, S_RR);
         if (norm2) *norm2 = v;
     });
@@ -857,8 +989,11 @@ cps_status cps_debug_gs_pass(cps_handle* h, int32_t level, int32_t colour, const
     return guarded([&] {
         need_level(h, level, true);
         if (colour < 0 || colour >= h->ncol) fail(CPS_E_INVALID, "bad colour");
-        gs_pass<double>(h, level, colour, b, x);
-        HIPC(hipStreamSynchronize(h->stream));
+        Buf<double> bs, xs;
+        const double* bp = split_copy(h, level, b, bs);
+        double* xp = split_copy(h, level, x, xs);
+        gs_pass<double>(h, level, colour, bp, xp);
+        natural_copy(h, level, xp, x);
     });
 }
 
@@ -866,8 +1001,11 @@ cps_status cps_debug_restrict(cps_handle* h, int32_t level, const double* r, dou
 {
     return guarded([&] {
         need_level(h, level, true);
-        restrict_to<double>(h, level, r, bc);
-        HIPC(hipStreamSynchronize(h->stream));
+        Buf<double> rs, cs;
+        const double* rp = split_copy(h, level, r, rs);
+        cs.alloc(h->lv[level + 1].n);
+        restrict_to<double>(h, level, rp, cs.p);
+        natural_copy(h, level + 1, cs.p, bc);
     });
 }
 
@@ -875,8 +1013,11 @@ cps_status cps_debug_prolong(cps_handle* h, int32_t level, const double* e, doub
 {
     return guarded([&] {
         need_level(h, level, true);
-        prolong_add<double>(h, level, e, x);
-        HIPC(hipStreamSynchronize(h->stream));
+        Buf<double> es, xs;
+        const double* ep = split_copy(h, level + 1, e, es);
+        double* xp = split_copy(h, level, x, xs);
+        prolong_add<double>(h, level, ep, xp);
+        natural_copy(h, level, xp, x);
     });
 }
 
@@ -884,8 +1025,12 @@ cps_status cps_debug_coarse_solve(cps_handle* h, const double* b, double* e)
 {
     return guarded([&] {
         need_level(h, 0, false);
-        coarse_solve<double>(h, b, e);
-        HIPC(hipStreamSynchronize(h->stream));
+        const int lc = h->L - 1;
+        Buf<double> bs, es;
+        const double* bp = split_copy(h, lc, b, bs);
+        es.alloc(h->lv[lc].n);
+        coarse_solve<double>(h, bp, es.p);
+        natural_copy(h, lc, es.p, e);
     });
 }
 
@@ -893,8 +1038,11 @@ cps_status cps_debug_vcycle(cps_handle* h, const double* b, double* x)
 {
     return guarded([&] {
         need_level(h, 0, false);
-        vcycle<double>(h, b, x);
-        HIPC(hipStreamSynchronize(h->stream));
+        Buf<double> bs, xs;
+        const double* bp = split_copy(h, 0, b, bs);
+        double* xp = split_copy(h, 0, x, xs);
+        vcycle<double>(h, bp, xp);
+        natural_copy(h, 0, xp, x);
     });
 }
 

@@ -1,20 +1,26 @@
 // kernels.hpp -- gfx950 kernels of the shell pressure-Poisson multigrid.
 //
-// Every kernel is a template over the value type T (double or float), the
-// stencil shape MODE and the metric storage AXI:
-//   MODE_ORTHO   all cross metrics vanish: 7-point stencil, 3 arrays
-//                (G_rr, G_tt, G_pp);
-//   MODE_RT      only G_rt and G_tr cross terms (every map that is invariant
-//                under rotation about the polar axis): 11 points;
+// Every stencil kernel is a template over the value type T (double or
+// float), the stencil shape MODE and the metric storage AXI:
+//   MODE_ORTHO   all cross metrics vanish: 7-point stencil (G_rr, G_tt, G_pp);
+//   MODE_RT      only the G_rt and G_tr cross terms (maps invariant under
+//                rotation about the polar axis): 11-point stencil;
 //   MODE_FULL    all nine metrics: the 19-point stencil of eq. (PC_8).
 //   AXI          metrics independent of phi, stored once per (r, theta).
-// Metrics are [9][n_r][n_theta][nc] with nc = 1 (AXI) or n_phi; entry 3d+q
-// of a cell is G_dq on the cell's low face in direction d (Sec. 3.2), zero on
-// the low r- and theta-walls; the high walls are implicit zeros.
 //
-// Fields are [n_r][n_theta][n_phi], phi contiguous; one thread per cell (or
-// per cell of one colour) with consecutive threads along phi, so every load
-// of a wavefront is one contiguous run.
+// Field layout ("phi-parity split"): a level vector is [2][n_r][n_theta][nh]
+// with nh = n_phi / 2; cell (a, b, c) lives in plane s = c mod 2 at index
+// j = c / 2.  A colour pass then reads only the planes of the other colours
+// and writes only its own, so no cache line carries cells it does not need.
+// Metrics are [9][n_r][n_theta] (AXI) or [9][2][n_r][n_theta][nh]; entry
+// 3d+q of a cell is G_dq on the cell's low face in direction d (Sec. 3.2),
+// zero on the low r- and theta-walls; the high walls are implicit zeros.
+//
+// Launch shape: 1-D grids of 256-thread blocks.  A block's logical index is
+// remapped so that each of the 8 XCDs (which receive blocks round-robin)
+// works on one contiguous range of r-planes and keeps its neighbours in its
+// own L2.  Within a plane, consecutive threads take consecutive (theta, j)
+// positions, so each wavefront touches contiguous runs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,17 +32,59 @@ enum { MODE_ORTHO = 0, MODE_RT = 1, MODE_FULL = 2 };
 
 constexpr int kBlock = 256;
 
+// geometry of one level in the parity-split layout
+struct Geo {
+    int nr, nt, np, nh; // nh = np / 2
+    int rowlen;         // nt * nh: cells of one parity in one r-plane
+    long long P;        // nr * nt * nh: one parity plane
+};
+
+inline Geo make_geo(int nr, int nt, int np)
+{
+    Geo g;
+    g.nr = nr;
+    g.nt = nt;
+    g.np = np;
+    g.nh = np / 2;
+    g.rowlen = nt * g.nh;
+    g.P = (long long)nr * g.rowlen;
+    return g;
+}
+
 template <typename T>
 struct Level {
-    int nr, nt, np;
-    const T* G;   // [9][nr][nt][nc]
-    long long gk; // nr * nt * nc
+    Geo g;
+    const T* G;   // metrics, see above
+    long long gk; // stride between the nine metric arrays
 };
 
 __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
-// Reads field values of the 3x3x3 block around (a, b, c), mirrored in r and
-// theta and wrapped in phi.
+__device__ __forceinline__ long long split_index(const Geo& g, int a, int b, int c)
+{
+    return (long long)(c & 1) * g.P + ((long long)a * g.nt + b) * g.nh + (c >> 1);
+}
+
+// Logical block index with XCD-contiguous ranges: hardware block B runs on
+// XCD B mod 8; XCD x gets the logical range [x q + min(x, r), ...) where
+// q, r = divmod(number of blocks, 8).
+__device__ __forceinline__ unsigned xcd_block()
+{
+    const unsigned B = blockIdx.x, T = gridDim.x;
+    const unsigned x = B & 7u, k = B >> 3, q = T >> 3, r = T & 7u;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Position of this thread in a launch over nr planes of `rowlen` positions
+// each, with `bpa` blocks per plane; m = position inside the plane.
+__device__ __forceinline__ bool plane_pos(int rowlen, int bpa, int& a, int& m)
+{
+    const int L = (int)xcd_block();
+    a = L / bpa;
+    m = (L - a * bpa) * kBlock + (int)threadIdx.x;
+    return m < rowlen;
+}
+
 template <typename T>
 struct Field {
     const T* x;
@@ -50,84 +98,103 @@ struct Delta {
     __device__ __forceinline__ T operator()(long long i) const { return i == j ? T(1) : T(0); }
 };
 
-template <typename T, int MODE, bool AXI>
-__device__ __forceinline__ T coef(const Level<T>& L, int k, int a, int b, int c)
-{
-    long long i = AXI ? (long long)a * L.nt + b : ((long long)a * L.nt + b) * L.np + c;
-    return L.G[k * L.gk + i];
-}
-
-// (A x) at cell (a, b, c) as the sum over directions of (flux through the
-// high face) - (flux through the low face), and D = -(sum of the six G_dd).
-// The flux through a face in direction d is
+// (A x) at cell (a, b, c = 2j + s) as the sum over directions of (flux
+// through the high face) - (flux through the low face), and
+// D = -(sum of the six G_dd).  The flux through a face in direction d is
 //   G_dd (x_hi - x_lo) + sum_{q != d} G_dq/4 (x_hi+q + x_lo+q - x_hi-q - x_lo-q),
-// eq. (PC_term1)-(PC_term3) generalised to all nine terms.
-template <typename T, int MODE, bool AXI, typename Acc>
-__device__ __forceinline__ T apply_cell(const Level<T>& L, const Acc& X, int a, int b, int c,
-                                        T& D)
+// eq. (PC_term1)-(PC_term3) generalised to all nine terms; reads that leave
+// the domain in r or theta mirror onto the wall cell, phi wraps.
+// OFFDIAG: return instead S = (A x)_c - D x_c, the sum over the neighbours
+// (including a wall-mirrored read of the cell itself in a cross term), so a
+// Gauss-Seidel update x_c = (b_c - S) / D never loads the old x_c.  The flux
+// form (differences first) is kept for residuals, whose value is small next
+// to D x_c near convergence.
+template <typename T, int MODE, bool AXI, bool OFFDIAG = false, typename Acc>
+__device__ __forceinline__ T apply_cell(const Geo& g, const T* __restrict__ G, long long gk,
+                                        const Acc& X, int a, int b, int s, int j, T& D)
 {
-    const int nr = L.nr, nt = L.nt, np = L.np;
-    const long long st = np, sr = (long long)nt * np;
-    const int cm = c == 0 ? np - 1 : c - 1;
-    const int cp = c == np - 1 ? 0 : c + 1;
-    const bool rhi = a < nr - 1, thi = b < nt - 1;
-    // diagonal metrics of the six faces
-    const T grl = coef<T, MODE, AXI>(L, 0, a, b, c);
-    const T grh = rhi ? coef<T, MODE, AXI>(L, 0, a + 1, b, c) : T(0);
-    const T gtl = coef<T, MODE, AXI>(L, 4, a, b, c);
-    const T gth = thi ? coef<T, MODE, AXI>(L, 4, a, b + 1, c) : T(0);
-    const T gpl = coef<T, MODE, AXI>(L, 8, a, b, c);
-    const T gph = coef<T, MODE, AXI>(L, 8, a, b, cp);
+    const int nh = g.nh;
+    const long long sr = g.rowlen, st = nh;
+    const long long row = (long long)a * sr + (long long)b * nh;
+    const long long i0 = s * g.P + row + j;
+    // phi neighbours c+1 and c-1 live in the other plane
+    long long ipp, ipm;
+    if (s == 0) {
+        ipp = g.P + row + j;
+        ipm = g.P + row + (j == 0 ? nh - 1 : j - 1);
+    } else {
+        ipp = row + (j == nh - 1 ? 0 : j + 1);
+        ipm = row + j;
+    }
+    const long long pa = ipm - i0, pb = ipp - i0;
+    const bool rhi = a < g.nr - 1, thi = b < g.nt - 1;
+    // metric indices of the low faces and of the three high faces
+    long long ci, cr, ct, cp;
+    if (AXI) {
+        ci = (long long)a * g.nt + b;
+        cr = ci + g.nt;
+        ct = ci + 1;
+        cp = ci;
+    } else {
+        ci = i0;
+        cr = i0 + sr;
+        ct = i0 + st;
+        cp = ipp;
+    }
+    const T grl = G[ci];
+    const T grh = rhi ? G[cr] : T(0);
+    const T gtl = G[4 * gk + ci];
+    const T gth = thi ? G[4 * gk + ct] : T(0);
+    const T gpl = G[8 * gk + ci];
+    const T gph = G[8 * gk + cp];
     D = -(grl + grh + gtl + gth + gpl + gph);
-    // offsets of the neighbour planes, mirrored at the walls
     const long long ra = a > 0 ? -sr : 0, rb = rhi ? sr : 0;
     const long long ta = b > 0 ? -st : 0, tb = thi ? st : 0;
-    const long long base = (long long)a * sr + (long long)b * st;
-    const long long pa = cm - c, pb = cp - c;
-    const long long i0 = base + c;
-    const T x0 = X(i0);
     const T xrm = X(i0 + ra), xrp = X(i0 + rb);
     const T xtm = X(i0 + ta), xtp = X(i0 + tb);
     const T xpm = X(i0 + pa), xpp = X(i0 + pb);
-    T s = grh * (xrp - x0) - grl * (x0 - xrm) + gth * (xtp - x0) - gtl * (x0 - xtm) +
-          gph * (xpp - x0) - gpl * (x0 - xpm);
+    T acc;
+    if constexpr (OFFDIAG) {
+        acc = grh * xrp + grl * xrm + gth * xtp + gtl * xtm + gph * xpp + gpl * xpm;
+    } else {
+        const T x0 = X(i0);
+        acc = grh * (xrp - x0) - grl * (x0 - xrm) + gth * (xtp - x0) - gtl * (x0 - xtm) +
+              gph * (xpp - x0) - gpl * (x0 - xpm);
+    }
     if constexpr (MODE != MODE_ORTHO) {
-        // r-theta edges
+        const T q = T(0.25);
         const T xrmtm = X(i0 + ra + ta), xrmtp = X(i0 + ra + tb);
         const T xrptm = X(i0 + rb + ta), xrptp = X(i0 + rb + tb);
-        const T q = T(0.25);
-        const T grt_l = coef<T, MODE, AXI>(L, 1, a, b, c);
-        const T grt_h = rhi ? coef<T, MODE, AXI>(L, 1, a + 1, b, c) : T(0);
-        const T gtr_l = coef<T, MODE, AXI>(L, 3, a, b, c);
-        const T gtr_h = thi ? coef<T, MODE, AXI>(L, 3, a, b + 1, c) : T(0);
-        // r-flux cross terms (q = theta)
-        s += q * grt_h * (xrptp + xtp - xrptm - xtm) - q * grt_l * (xtp + xrmtp - xtm - xrmtm);
-        // theta-flux cross terms (q = r)
-        s += q * gtr_h * (xrptp + xrp - xrmtp - xrm) - q * gtr_l * (xrp + xrptm - xrm - xrmtm);
+        const T grt_l = G[gk + ci];
+        const T grt_h = rhi ? G[gk + cr] : T(0);
+        const T gtr_l = G[3 * gk + ci];
+        const T gtr_h = thi ? G[3 * gk + ct] : T(0);
+        // r-flux, q = theta
+        acc += q * grt_h * (xrptp + xtp - xrptm - xtm) - q * grt_l * (xtp + xrmtp - xtm - xrmtm);
+        // theta-flux, q = r
+        acc += q * gtr_h * (xrptp + xrp - xrmtp - xrm) - q * gtr_l * (xrp + xrptm - xrm - xrmtm);
         if constexpr (MODE == MODE_FULL) {
             const T xrmpm = X(i0 + ra + pa), xrmpp = X(i0 + ra + pb);
             const T xrppm = X(i0 + rb + pa), xrppp = X(i0 + rb + pb);
             const T xtmpm = X(i0 + ta + pa), xtmpp = X(i0 + ta + pb);
             const T xtppm = X(i0 + tb + pa), xtppp = X(i0 + tb + pb);
-            const T grp_l = coef<T, MODE, AXI>(L, 2, a, b, c);
-            const T grp_h = rhi ? coef<T, MODE, AXI>(L, 2, a + 1, b, c) : T(0);
-            const T gtp_l = coef<T, MODE, AXI>(L, 5, a, b, c);
-            const T gtp_h = thi ? coef<T, MODE, AXI>(L, 5, a, b + 1, c) : T(0);
-            const T gpr_l = coef<T, MODE, AXI>(L, 6, a, b, c);
-            const T gpr_h = coef<T, MODE, AXI>(L, 6, a, b, cp);
-            const T gpt_l = coef<T, MODE, AXI>(L, 7, a, b, c);
-            const T gpt_h = coef<T, MODE, AXI>(L, 7, a, b, cp);
+            const T grp_l = G[2 * gk + ci];
+            const T grp_h = rhi ? G[2 * gk + cr] : T(0);
+            const T gtp_l = G[5 * gk + ci];
+            const T gtp_h = thi ? G[5 * gk + ct] : T(0);
+            const T gpr_l = G[6 * gk + ci], gpr_h = G[6 * gk + cp];
+            const T gpt_l = G[7 * gk + ci], gpt_h = G[7 * gk + cp];
             // r-flux, q = phi
-            s += q * grp_h * (xrppp + xpp - xrppm - xpm) - q * grp_l * (xpp + xrmpp - xpm - xrmpm);
+            acc += q * grp_h * (xrppp + xpp - xrppm - xpm) - q * grp_l * (xpp + xrmpp - xpm - xrmpm);
             // theta-flux, q = phi
-            s += q * gtp_h * (xtppp + xpp - xtppm - xpm) - q * gtp_l * (xpp + xtmpp - xpm - xtmpm);
+            acc += q * gtp_h * (xtppp + xpp - xtppm - xpm) - q * gtp_l * (xpp + xtmpp - xpm - xtmpm);
             // phi-flux, q = r
-            s += q * gpr_h * (xrppp + xrp - xrmpp - xrm) - q * gpr_l * (xrp + xrppm - xrm - xrmpm);
+            acc += q * gpr_h * (xrppp + xrp - xrmpp - xrm) - q * gpr_l * (xrp + xrppm - xrm - xrmpm);
             // phi-flux, q = theta
-            s += q * gpt_h * (xtppp + xtp - xtmpp - xtm) - q * gpt_l * (xtp + xtppm - xtm - xtmpm);
+            acc += q * gpt_h * (xtppp + xtp - xtmpp - xtm) - q * gpt_l * (xtp + xtppm - xtm - xtmpm);
         }
     }
-    return s;
+    return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -155,101 +222,318 @@ __device__ __forceinline__ double block_sum(double v)
     return t;
 }
 
-// out[slot] = sum of partial[0..n) in a fixed order (one block).
+// *out = sum of partial[0..n) in a fixed order (one block; four
+// independent accumulators per thread keep several loads in flight).
 __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partial, long long n,
                                                    double* __restrict__ out)
 {
-    double s = 0.0;
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
-    s = block_sum(s);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    long long i = threadIdx.x;
+    for (; i + 3 * kBlock < n; i += 4 * kBlock) {
+        s0 += partial[i];
+        s1 += partial[i + kBlock];
+        s2 += partial[i + 2 * kBlock];
+        s3 += partial[i + 3 * kBlock];
+    }
+    for (; i < n; i += kBlock) s0 += partial[i];
+    const double s = block_sum((s0 + s1) + (s2 + s3));
     if (threadIdx.x == 0) *out = s;
 }
 
-// ---------------------------------------------------------------------------
-// Operator kernels
-// ---------------------------------------------------------------------------
+// Blocks of the stencil kernels walk a contiguous range of "units" (256
+// consecutive positions of one r-plane): unit u covers plane a = u / bpa,
+// positions m = (u mod bpa) * 256 + thread.  Grids are capped (kMaxGrid), so
+// a block takes several units in order and each kernel leaves at most
+// kMaxGrid partial sums.
+constexpr int kMaxGrid = 4096;
 
-// y = A x over all cells.
-template <typename T, int MODE, bool AXI>
-__global__ void __launch_bounds__(kBlock) k_apply(Level<T> L, const T* __restrict__ x,
-                                                  T* __restrict__ y, double* __restrict__ partial,
-                                                  const T* __restrict__ dotv)
+template <typename F>
+__device__ __forceinline__ void for_units(int rowlen, int bpa, long long nunits, F&& f)
 {
-    const long long n = (long long)L.nr * L.nt * L.np;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double acc = 0.0;
-    if (i < n) {
-        const int c = (int)(i % L.np);
-        const long long row = i / L.np;
-        const int b = (int)(row % L.nt), a = (int)(row / L.nt);
-        T D;
-        const T v = apply_cell<T, MODE, AXI>(L, Field<T>{x}, a, b, c, D);
-        y[i] = v;
-        if (dotv) acc = (double)v * (double)dotv[i];
-    }
-    if (partial) {
-        acc = block_sum(acc);
-        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    const long long L = xcd_block(), G = gridDim.x;
+    const unsigned u0 = (unsigned)(nunits * L / G), u1 = (unsigned)(nunits * (L + 1) / G);
+    for (unsigned u = u0; u < u1; ++u) {
+        const unsigned a = u / (unsigned)bpa;
+        const int m = (int)(u - a * (unsigned)bpa) * kBlock + (int)threadIdx.x;
+        if (m < rowlen) f((int)a, m);
     }
 }
 
-// r = b - A x, and per-block partial sums of r^2.
-template <typename T, int MODE, bool AXI>
-__global__ void __launch_bounds__(kBlock) k_residual(Level<T> L, const T* __restrict__ bv,
+// Row (theta index) of plane position m.  UROW: n_phi / 2 is a multiple of
+// 64, so no wavefront straddles two rows; the row is then made
+// wave-uniform, which turns the per-row metric loads of phi-invariant maps
+// into scalar loads.
+template <bool UROW>
+__device__ __forceinline__ int row_of(int m, int nh)
+{
+    int b = m / nh;
+    if constexpr (UROW) b = __builtin_amdgcn_readfirstlane(b);
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Operator kernels.  One thread per (a, b, j): both parities of the pair.
+// LTAG only tells the finest level (0) from the others (1) so that profiles
+// can separate them; the code is the same.
+// ---------------------------------------------------------------------------
+
+// y = A x; with dotv, per-block partial sums of y . dotv
+template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_apply(Geo g, const T* __restrict__ G, long long gk,
+                                                  int bpa, const T* __restrict__ x,
+                                                  T* __restrict__ y, double* __restrict__ partial,
+                                                  const T* __restrict__ dotv)
+{
+    double acc = 0.0;
+    for_units(g.rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
+        const int b = row_of<UROW>(m, g.nh), j = m - b * g.nh;
+        const long long i0 = (long long)a * g.rowlen + m;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            T D;
+            const T v = apply_cell<T, MODE, AXI>(g, G, gk, Field<T>{x}, a, b, s, j, D);
+            y[i0 + s * g.P] = v;
+            if (dotv) acc += (double)v * (double)dotv[i0 + s * g.P];
+        }
+    });
+    if (partial) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partial[xcd_block()] = acc;
+    }
+}
+
+// r = b - A x; with partial, per-block partial sums of r^2
+template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_residual(Geo g, const T* __restrict__ G, long long gk,
+                                                     int bpa, const T* __restrict__ bv,
                                                      const T* __restrict__ x, T* __restrict__ r,
                                                      double* __restrict__ partial)
 {
-    const long long n = (long long)L.nr * L.nt * L.np;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (i < n) {
-        const int c = (int)(i % L.np);
-        const long long row = i / L.np;
-        const int b = (int)(row % L.nt), a = (int)(row / L.nt);
-        T D;
-        const T v = bv[i] - apply_cell<T, MODE, AXI>(L, Field<T>{x}, a, b, c, D);
-        r[i] = v;
-        acc = (double)v * (double)v;
-    }
+    for_units(g.rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
+        const int b = row_of<UROW>(m, g.nh), j = m - b * g.nh;
+        const long long i0 = (long long)a * g.rowlen + m;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            T D;
+            const long long i = i0 + s * g.P;
+            const T v = bv[i] - apply_cell<T, MODE, AXI>(g, G, gk, Field<T>{x}, a, b, s, j, D);
+            r[i] = v;
+            acc += (double)v * (double)v;
+        }
+    });
     if (partial) {
         acc = block_sum(acc);
-        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+        if (threadIdx.x == 0) partial[xcd_block()] = acc;
     }
 }
 
 // One Gauss-Seidel pass over the cells of one colour, in place:
-// x_c += (b_c - (A x)_c) / D_c.  Two colours: (a+b+c) mod 2.  Four colours:
-// k = 2((a+c) mod 2) + ((b+c) mod 2).  Cells of one colour never read one
-// another, so all threads of the pass update concurrently.  Needs even dims.
-template <typename T, int MODE, bool AXI>
-__global__ void __launch_bounds__(kBlock) k_gs(Level<T> L, const T* __restrict__ bv,
+// x_c = (b_c - S_c) / D_c with S_c the neighbour sum of (A x)_c (the same
+// value as x_c + (b_c - (A x)_c) / D_c).  Two colours: (a+b+c) mod 2; four
+// colours: k = 2((a+c) mod 2) + ((b+c) mod 2).  Cells of one colour never
+// read one another, so all threads of the pass update concurrently.
+// Two colours: one thread per (a, b, j), the cell of the colour is in plane
+// (k + a + b) mod 2.  Four colours: the colour occupies every other theta
+// row (b = (k0 + k1 + a) mod 2 + 2 bh) in plane (k1 + a) mod 2.
+template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_gs(Geo g, const T* __restrict__ G, long long gk,
+                                               int bpa, const T* __restrict__ bv,
                                                T* __restrict__ x, int colour, int ncol)
 {
-    const int np2 = L.np >> 1;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int a, b, c;
-    if (ncol == 2) {
-        if (i >= (long long)L.nr * L.nt * np2) return;
-        const int ch = (int)(i % np2);
-        const long long row = i / np2;
-        b = (int)(row % L.nt);
-        a = (int)(row / L.nt);
-        c = 2 * ch + ((colour + a + b) & 1);
-    } else {
-        const int nt2 = L.nt >> 1;
-        if (i >= (long long)L.nr * nt2 * np2) return;
-        const int ch = (int)(i % np2);
-        const long long row = i / np2;
-        const int bh = (int)(row % nt2);
-        a = (int)(row / nt2);
-        const int k1 = colour >> 1, k0 = colour & 1;
-        b = 2 * bh + ((a + k0 + k1) & 1);
-        c = 2 * ch + ((k1 + a) & 1);
+    const int rowlen = ncol == 2 ? g.rowlen : g.rowlen / 2;
+    for_units(rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
+        const int bb = row_of<UROW>(m, g.nh), j = m - bb * g.nh;
+        int b, s;
+        if (ncol == 2) {
+            b = bb;
+            s = (colour + a + b) & 1;
+        } else {
+            const int k1 = colour >> 1, k0 = colour & 1;
+            b = 2 * bb + ((k0 + k1 + a) & 1);
+            s = (k1 + a) & 1;
+        }
+        T D;
+        const T S = apply_cell<T, MODE, AXI, true>(g, G, gk, Field<T>{x}, a, b, s, j, D);
+        const long long id = s * g.P + ((long long)a * g.nt + b) * g.nh + j;
+        x[id] = (bv[id] - S) / D;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Marching (2.5-D) kernels for the 7-point stencil with phi-invariant
+// metrics.  A block owns 256 consecutive positions (theta row, j) of a plane
+// and walks r over a chunk of planes; each thread keeps the values of its
+// own column at a-1, a, a+1 in registers, so every r-neighbour is read from
+// memory once.  theta and phi neighbours come from the plane being swept by
+// all blocks of the chunk at the same time (L2 hits).  With blocks laid out
+// chunk-major and XCD-contiguous, each XCD sweeps its own chunk.
+// Launch: grid = bpa * nchunks, chunk of `ch` planes.  Neighbour values
+// past a wall are replaced by the cell's own value: they are multiplied by
+// a zero wall metric.
+// ---------------------------------------------------------------------------
+
+struct March {
+    int unit, a0, a1, m, b, j;
+};
+
+template <bool UROW>
+__device__ __forceinline__ bool march_pos(const Geo& g, int bpa, int ch, March& p)
+{
+    const int L = (int)xcd_block();
+    const int chunk = L / bpa;
+    p.unit = L - chunk * bpa;
+    p.m = p.unit * kBlock + (int)threadIdx.x;
+    p.a0 = chunk * ch;
+    p.a1 = min(g.nr, p.a0 + ch);
+    if (p.m >= g.rowlen || p.a0 >= g.nr) return false;
+    p.b = row_of<UROW>(p.m, g.nh);
+    p.j = p.m - p.b * g.nh;
+    return true;
+}
+
+// Red-black Gauss-Seidel pass (colour k): at plane a the cell of column
+// (b, j) with colour k sits in plane p = (k + a + b) mod 2 and its black
+// neighbours are: the column's own cells at a-1, a+1 (plane p) and at a
+// (plane 1-p), the cells at (a, b+-1) in plane p, and one phi neighbour in
+// plane 1-p of the adjacent column.
+template <typename T, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict__ G, long long gk,
+                                                     int bpa, int ch, const T* __restrict__ bv,
+                                                     T* __restrict__ x, int colour)
+{
+    March p;
+    if (!march_pos<UROW>(g, bpa, ch, p)) return;
+    const long long sr = g.rowlen;
+    const int nh = g.nh, b = p.b, j = p.j;
+    // the other-colour cell of this column at plane a
+    auto other = [&](int a) -> T {
+        if (a < 0 || a >= g.nr) return T(0);
+        const int q = (colour + a + b + 1) & 1;
+        return x[q * g.P + (long long)a * sr + p.m];
+    };
+    T om = other(p.a0 - 1), o0 = other(p.a0);
+    const int jn0 = j == 0 ? nh - 1 : j - 1, jn1 = j == nh - 1 ? 0 : j + 1;
+    for (int a = p.a0; a < p.a1; ++a) {
+        const T op = other(a + 1);
+        const int s = (colour + a + b) & 1;
+        const long long ci = (long long)a * g.nt + b;
+        const T grl = G[ci];
+        const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
+        const T gtl = G[4 * gk + ci];
+        const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
+        const T gpp = G[8 * gk + ci];
+        const T D = -(grl + grh + gtl + gth + gpp + gpp);
+        const long long base = (long long)a * sr + p.m; // (a, b, j) within a plane
+        const T* xs = x + s * g.P;
+        const T xtm = b > 0 ? xs[base - nh] : T(0);
+        const T xtp = b < g.nt - 1 ? xs[base + nh] : T(0);
+        // phi: plane 1-s holds c-1 and c+1; o0 is the one at index j
+        const T on = x[(1 - s) * g.P + base - j + (s == 0 ? jn0 : jn1)];
+        const T S = grh * op + grl * om + gth * xtp + gtl * xtm + gpp * (o0 + on);
+        const long long id = s * g.P + base;
+        x[id] = (bv[id] - S) / D;
+        om = o0;
+        o0 = op;
     }
-    T D;
-    const T Ax = apply_cell<T, MODE, AXI>(L, Field<T>{x}, a, b, c, D);
-    const long long id = ((long long)a * L.nt + b) * L.np + c;
-    x[id] += (bv[id] - Ax) / D;
+}
+
+// Flux-form (A x) of the two cells (a, b, 2j) and (a, b, 2j+1) given the
+// column values at a-1, a, a+1 (u = plane 0, v = plane 1).
+template <typename T, typename Ld>
+__device__ __forceinline__ void march_apply2(const Geo& g, const T* __restrict__ G, long long gk,
+                                             const Ld& X, int a, int b, int j, long long base,
+                                             T um, T u0, T up, T vm, T v0, T vp, T& y0, T& y1)
+{
+    const int nh = g.nh;
+    const long long ci = (long long)a * g.nt + b;
+    const T grl = G[ci];
+    const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
+    const T gtl = G[4 * gk + ci];
+    const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
+    const T gpp = G[8 * gk + ci];
+    const bool tlo = b > 0, thi = b < g.nt - 1;
+    // plane 0 cell c = 2j: phi neighbours c-1 = (1, j-1), c+1 = (1, j)
+    const T u_tm = tlo ? X(base - nh) : u0, u_tp = thi ? X(base + nh) : u0;
+    const T v_jm = X(g.P + base - j + (j == 0 ? nh - 1 : j - 1));
+    y0 = grh * (up - u0) - grl * (u0 - um) + gth * (u_tp - u0) - gtl * (u0 - u_tm) +
+         gpp * (v0 - u0) - gpp * (u0 - v_jm);
+    // plane 1 cell c = 2j+1: phi neighbours c-1 = (0, j), c+1 = (0, j+1)
+    const T v_tm = tlo ? X(g.P + base - nh) : v0, v_tp = thi ? X(g.P + base + nh) : v0;
+    const T u_jp = X(base - j + (j == nh - 1 ? 0 : j + 1));
+    y1 = grh * (vp - v0) - grl * (v0 - vm) + gth * (v_tp - v0) - gtl * (v0 - v_tm) +
+         gpp * (u_jp - v0) - gpp * (v0 - u0);
+}
+
+// r = b - A x (and partial sums of r^2), marching.
+template <typename T, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_residual_march(Geo g, const T* __restrict__ G,
+                                                           long long gk, int bpa, int ch,
+                                                           const T* __restrict__ bv,
+                                                           const T* __restrict__ x,
+                                                           T* __restrict__ r,
+                                                           double* __restrict__ partial)
+{
+    March p;
+    double acc = 0.0;
+    if (march_pos<UROW>(g, bpa, ch, p)) {
+        const long long sr = g.rowlen;
+        auto col = [&](int a, int s, T own) -> T {
+            return (a < 0 || a >= g.nr) ? own : x[s * g.P + (long long)a * sr + p.m];
+        };
+        T u0 = col(p.a0, 0, T(0)), v0 = col(p.a0, 1, T(0));
+        T um = col(p.a0 - 1, 0, u0), vm = col(p.a0 - 1, 1, v0);
+        for (int a = p.a0; a < p.a1; ++a) {
+            const T up = col(a + 1, 0, u0), vp = col(a + 1, 1, v0);
+            const long long base = (long long)a * sr + p.m;
+            T y0, y1;
+            march_apply2<T>(g, G, gk, Field<T>{x}, a, p.b, p.j, base, um, u0, up, vm, v0, vp, y0, y1);
+            const T r0 = bv[base] - y0, r1 = bv[g.P + base] - y1;
+            r[base] = r0;
+            r[g.P + base] = r1;
+            acc += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+            um = u0; u0 = up; vm = v0; v0 = vp;
+        }
+    }
+    if (partial) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partial[xcd_block()] = acc;
+    }
+}
+
+// y = A x (and partial sums of y . dotv), marching.
+template <typename T, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restrict__ G,
+                                                        long long gk, int bpa, int ch,
+                                                        const T* __restrict__ x,
+                                                        T* __restrict__ y,
+                                                        double* __restrict__ partial,
+                                                        const T* __restrict__ dotv)
+{
+    March p;
+    double acc = 0.0;
+    if (march_pos<UROW>(g, bpa, ch, p)) {
+        const long long sr = g.rowlen;
+        auto col = [&](int a, int s, T own) -> T {
+            return (a < 0 || a >= g.nr) ? own : x[s * g.P + (long long)a * sr + p.m];
+        };
+        T u0 = col(p.a0, 0, T(0)), v0 = col(p.a0, 1, T(0));
+        T um = col(p.a0 - 1, 0, u0), vm = col(p.a0 - 1, 1, v0);
+        for (int a = p.a0; a < p.a1; ++a) {
+            const T up = col(a + 1, 0, u0), vp = col(a + 1, 1, v0);
+            const long long base = (long long)a * sr + p.m;
+            T y0, y1;
+            march_apply2<T>(g, G, gk, Field<T>{x}, a, p.b, p.j, base, um, u0, up, vm, v0, vp, y0, y1);
+            y[base] = y0;
+            y[g.P + base] = y1;
+            if (dotv) acc += (double)y0 * (double)dotv[base] + (double)y1 * (double)dotv[g.P + base];
+            um = u0; u0 = up; vm = v0; v0 = vp;
+        }
+    }
+    if (partial) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partial[xcd_block()] = acc;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -258,67 +542,110 @@ __global__ void __launch_bounds__(kBlock) k_gs(Level<T> L, const T* __restrict__
 
 // bc = P^T r, gathered: coarse index I takes fine 2I-1, 2I, 2I+1, 2I+2 with
 // weights 1/4, 3/4, 3/4, 1/4 per direction; fine indices past a wall fold
-// onto the wall cell, phi wraps.  (nr, nt, np) are the fine dims.
+// onto the wall cell, phi wraps.  One thread per coarse (I, J, jc): the two
+// coarse cells K = 2 jc and 2 jc + 1.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict(int nr, int nt, int np,
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa,
                                                      const T* __restrict__ r,
                                                      T* __restrict__ bc)
 {
-    const int mr = nr >> 1, mt = nt >> 1, mp = np >> 1;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)mr * mt * mp) return;
-    const int K = (int)(i % mp);
-    const long long row = i / mp;
-    const int J = (int)(row % mt), I = (int)(row / mt);
+    int I, m;
+    if (!plane_pos(c.rowlen, bpa, I, m)) return;
+    const int J = m / c.nh, jc = m - J * c.nh;
     const T w[4] = {T(0.25), T(0.75), T(0.75), T(0.25)};
-    int ia[4], ib[4], ic[4];
-    for (int o = 0; o < 4; ++o) {
-        ia[o] = clampi(2 * I - 1 + o, nr - 1);
-        ib[o] = clampi(2 * J - 1 + o, nt - 1);
-        int cc = 2 * K - 1 + o;
-        ic[o] = cc < 0 ? cc + np : (cc >= np ? cc - np : cc);
-    }
-    T s = T(0);
-    for (int p = 0; p < 4; ++p)
+    long long rowoff[4][4]; // fine (ia, ib) row offsets
+    for (int p = 0; p < 4; ++p) {
+        const int ia = clampi(2 * I - 1 + p, f.nr - 1);
         for (int q = 0; q < 4; ++q) {
-            const T* rowp = r + ((long long)ia[p] * nt + ib[q]) * np;
-            T t = w[0] * rowp[ic[0]] + w[1] * rowp[ic[1]] + w[2] * rowp[ic[2]] + w[3] * rowp[ic[3]];
-            s += w[p] * w[q] * t;
+            const int ib = clampi(2 * J - 1 + q, f.nt - 1);
+            rowoff[p][q] = ((long long)ia * f.nt + ib) * f.nh;
         }
-    bc[i] = s;
+    }
+#pragma unroll
+    for (int sc = 0; sc < 2; ++sc) {
+        const int K = 2 * jc + sc;
+        long long co[4]; // fine phi offsets (plane + index)
+        for (int o = 0; o < 4; ++o) {
+            int cc = 2 * K - 1 + o;
+            cc = cc < 0 ? cc + f.np : (cc >= f.np ? cc - f.np : cc);
+            co[o] = (cc & 1) * f.P + (cc >> 1);
+        }
+        T s = T(0);
+        for (int p = 0; p < 4; ++p)
+            for (int q = 0; q < 4; ++q) {
+                const T* rr = r + rowoff[p][q];
+                const T t = w[0] * rr[co[0]] + w[1] * rr[co[1]] + w[2] * rr[co[2]] + w[3] * rr[co[3]];
+                s += w[p] * w[q] * t;
+            }
+        bc[sc * c.P + (long long)I * c.rowlen + m] = s;
+    }
 }
 
 // x += P e: fine cell i in a direction takes 3/4 of coarse i/2 and 1/4 of
 // coarse i/2 - 1 (even i) or i/2 + 1 (odd i), mirrored at walls, wrapped in
-// phi; trilinear = the product of the three.  (nr, nt, np) are fine dims.
+// phi; trilinear = the product of the three.  One thread per fine (a, b, j):
+// the fine cells c = 2j and 2j + 1 (coarse phi index j for both).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong(int nr, int nt, int np,
+__global__ void __launch_bounds__(kBlock) k_prolong(Geo f, Geo c, int bpa,
                                                     const T* __restrict__ e,
                                                     T* __restrict__ x)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long long)nr * nt * np) return;
-    const int c = (int)(i % np);
-    const long long row = i / np;
-    const int b = (int)(row % nt), a = (int)(row / nt);
-    const int mr = nr >> 1, mt = nt >> 1, mp = np >> 1;
-    const int A0 = a >> 1, B0 = b >> 1, C0 = c >> 1;
-    const int A1 = clampi((a & 1) ? A0 + 1 : A0 - 1, mr - 1);
-    const int B1 = clampi((b & 1) ? B0 + 1 : B0 - 1, mt - 1);
-    int C1 = (c & 1) ? C0 + 1 : C0 - 1;
-    C1 = C1 < 0 ? C1 + mp : (C1 >= mp ? C1 - mp : C1);
+    int a, m;
+    if (!plane_pos(f.rowlen, bpa, a, m)) return;
+    const int b = m / f.nh, j = m - b * f.nh;
+    const int A0 = a >> 1, B0 = b >> 1;
+    const int A1 = clampi((a & 1) ? A0 + 1 : A0 - 1, c.nr - 1);
+    const int B1 = clampi((b & 1) ? B0 + 1 : B0 - 1, c.nt - 1);
+    const long long r00 = ((long long)A0 * c.nt + B0) * c.nh, r01 = ((long long)A0 * c.nt + B1) * c.nh;
+    const long long r10 = ((long long)A1 * c.nt + B0) * c.nh, r11 = ((long long)A1 * c.nt + B1) * c.nh;
+    auto kofs = [&](int K) {
+        K = K < 0 ? K + c.np : (K >= c.np ? K - c.np : K);
+        return (K & 1) * c.P + (K >> 1);
+    };
+    const long long k0 = kofs(j);
     const T w0 = T(0.75), w1 = T(0.25);
-    auto E = [&](int p, int q, int s) { return e[((long long)p * mt + q) * mp + s]; };
-    const T v0 = w0 * (w0 * E(A0, B0, C0) + w1 * E(A0, B0, C1)) +
-                 w1 * (w0 * E(A0, B1, C0) + w1 * E(A0, B1, C1));
-    const T v1 = w0 * (w0 * E(A1, B0, C0) + w1 * E(A1, B0, C1)) +
-                 w1 * (w0 * E(A1, B1, C0) + w1 * E(A1, B1, C1));
-    x[i] += w0 * v0 + w1 * v1;
+    const long long i0 = (long long)a * f.rowlen + m;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const long long k1 = kofs(s ? j + 1 : j - 1);
+        const T v0 = w0 * (w0 * e[r00 + k0] + w1 * e[r00 + k1]) + w1 * (w0 * e[r01 + k0] + w1 * e[r01 + k1]);
+        const T v1 = w0 * (w0 * e[r10 + k0] + w1 * e[r10 + k1]) + w1 * (w0 * e[r11 + k0] + w1 * e[r11 + k1]);
+        x[i0 + s * f.P] += w0 * v0 + w1 * v1;
+    }
+}
+
+// Natural [r][theta][phi] <-> parity-split order.  y_split = x_nat - *mean
+// (mean may be null), and the inverse.
+template <typename T, typename U>
+__global__ void __launch_bounds__(kBlock) k_to_split(Geo g, const T* __restrict__ x,
+                                                     U* __restrict__ y, const double* __restrict__ sum)
+{
+    const long long n = 2 * g.P;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double sub = sum ? *sum / (double)n : 0.0;
+    const long long row = i / g.np;
+    const int c = (int)(i - row * g.np);
+    y[(c & 1) * g.P + row * g.nh + (c >> 1)] = (U)((double)x[i] - sub);
+}
+
+template <typename T, typename U>
+__global__ void __launch_bounds__(kBlock) k_from_split(Geo g, const T* __restrict__ x,
+                                                       U* __restrict__ y, const double* __restrict__ sum)
+{
+    const long long n = 2 * g.P;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double sub = sum ? *sum / (double)n : 0.0;
+    const long long row = i / g.np;
+    const int c = (int)(i - row * g.np);
+    y[i] = (U)((double)x[(c & 1) * g.P + row * g.nh + (c >> 1)] - sub);
 }
 
 // ---------------------------------------------------------------------------
-// Coarsest level: e = Ainv (b - mean b), Ainv row-major FP64.  One wave per
-// row, lanes striding over the columns; every block recomputes the mean.
+// Coarsest level: e = Ainv (b - mean b), Ainv row-major FP64 (rows and
+// columns in the parity-split order of the level).  One wave per row, lanes
+// striding over the columns; every block recomputes the mean.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_gemv(int n, const double* __restrict__ Ainv,
@@ -331,13 +658,13 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gemv(int n, const double* __r
     s = block_sum(s);
     if (threadIdx.x == 0) smean = s / n;
     __syncthreads();
-    const double m = smean;
+    const double mu = smean;
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (row >= n) return;
     const double* Ar = Ainv + (long long)row * n;
     double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc += Ar[j] * ((double)bv[j] - m);
+    for (int j = lane; j < n; j += 64) acc += Ar[j] * ((double)bv[j] - mu);
     acc = wave_sum(acc);
     if (lane == 0) e[row] = (T)acc;
 }
@@ -346,15 +673,19 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gemv(int n, const double* __r
 // Vector kernels
 // ---------------------------------------------------------------------------
 
+// Reducing vector kernels walk the vector with a grid stride (grids are
+// capped at kMaxGrid blocks), one partial sum per block.
+
 // partial sums of u.v (or of u alone when v == nullptr)
 template <typename T, typename U>
 __global__ void __launch_bounds__(kBlock) k_dot(long long n, const T* __restrict__ u,
                                                 const U* __restrict__ v,
                                                 double* __restrict__ partial)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (i < n) acc = v ? (double)u[i] * (double)v[i] : (double)u[i];
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        acc += v ? (double)u[i] * (double)v[i] : (double)u[i];
     acc = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
@@ -440,14 +771,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* _
                                                     const double* __restrict__ q,
                                                     double* __restrict__ partial)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const double al = sc[S_ALPHA];
     double acc = 0.0;
-    if (i < n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         x[i] += al * p[i];
         const double v = r[i] - al * q[i];
         r[i] = v;
-        acc = v * v;
+        acc += v * v;
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -492,13 +823,13 @@ __global__ void __launch_bounds__(kBlock) k_bicg_step(long long n, const double*
                                                       const double* __restrict__ t,
                                                       double* __restrict__ partial)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    if (i < n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         x[i] += sc[S_ALPHA] * ph[i] + sc[S_OMEGA] * sh[i];
         const double v = s[i] - sc[S_OMEGA] * t[i];
         r[i] = v;
-        acc = v * v;
+        acc += v * v;
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
@@ -623,13 +954,18 @@ __global__ void __launch_bounds__(kBlock) k_metrics(MapParams m, int nr, int nt,
                     nn[q] = nv[q][0] * nv[q][0] + nv[q][1] * nv[q][1] + nv[q][2] * nv[q][2];
                 for (int q = 0; q < 3; ++q) {
                     double v = (nv[d][0] * nv[q][0] + nv[d][1] * nv[q][1] + nv[d][2] * nv[q][2]) / det;
-                    if (q != d && fabs(v) <= 1e-13 * sqrt(fabs(nn[d] * nn[q])) / fabs(det)) v = 0.0;
+                    if (q != d && fabs(v) <= 1e-10 * sqrt(fabs(nn[d] * nn[q])) / fabs(det)) v = 0.0;
                     Gd[q] = v;
                 }
                 for (int q = 0; q < 3; ++q)
                     if (q != d && Gd[q] != 0.0) fl |= (d == 2 || q == 2) ? 4 : 2;
             }
-            for (int q = 0; q < 3; ++q) G[(long long)(3 * d + q) * n + i] = Gd[q];
+            // phi-invariant metrics: one entry per (r, theta); otherwise the
+            // parity-split layout of the level's fields
+            const long long oi = nc == 1 ? i
+                                         : (long long)(c & 1) * (n / 2) +
+                                               ((long long)a * nt + b) * (np / 2) + (c >> 1);
+            for (int q = 0; q < 3; ++q) G[(long long)(3 * d + q) * n + oi] = Gd[q];
         }
     }
     if (fl) atomicOr(&sflag, fl);
@@ -638,6 +974,7 @@ __global__ void __launch_bounds__(kBlock) k_metrics(MapParams m, int nr, int nt,
 }
 
 // Float copy of an FP64 array.
+// Float copy of an FP64 array.
 __global__ void __launch_bounds__(kBlock) k_to_f32(long long n, const double* __restrict__ a,
                                                    float* __restrict__ b)
 {
@@ -645,47 +982,50 @@ __global__ void __launch_bounds__(kBlock) k_to_f32(long long n, const double* __
     if (i < n) b[i] = (float)a[i];
 }
 
-// Expand stored metrics to [9][nr][nt][np] (for inspection).
-__global__ void __launch_bounds__(kBlock) k_expand_metrics(int nr, int nt, int np, int nc,
+// Expand stored metrics to natural [9][nr][nt][np] (for inspection).
+__global__ void __launch_bounds__(kBlock) k_expand_metrics(Geo g, int axi,
                                                            const double* __restrict__ G,
                                                            double* __restrict__ out)
 {
-    const long long n = (long long)nr * nt * np;
+    const long long n = 2 * g.P;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int c = (int)(i % np);
-    const long long row = i / np;
-    const long long src = row * nc + (nc == 1 ? 0 : c);
-    const long long gk = (long long)nr * nt * nc;
+    const long long row = i / g.np;
+    const int c = (int)(i - row * g.np);
+    const long long src = axi ? row : (c & 1) * g.P + row * g.nh + (c >> 1);
+    const long long gk = axi ? (long long)g.nr * g.nt : n;
     for (int k = 0; k < 9; ++k) out[k * n + i] = G[k * gk + src];
 }
 
-// Dense coarsest operator: row i gets A[i][j] = (A delta_j)_i for every
-// cell j of the 3x3x3 block around cell i (mirrored / wrapped; a cell
-// reached twice is evaluated once).  A must be zeroed first.
+// Dense coarsest operator in parity-split order: row i (cell (a, b, c)) gets
+// A[i][j] = (A delta_j)_i for every cell j of the 3x3x3 block around it
+// (mirrored / wrapped; a cell reached twice is evaluated once).  A must be
+// zeroed first.
 template <int MODE, bool AXI>
 __global__ void __launch_bounds__(kBlock) k_dense_rows(Level<double> L, double* __restrict__ A)
 {
-    const long long n = (long long)L.nr * L.nt * L.np;
+    const Geo& g = L.g;
+    const long long n = 2 * g.P;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * 27) return;
-    const long long i = t / 27;
-    const int s = (int)(t % 27);
-    const int c = (int)(i % L.np);
-    const long long row = i / L.np;
-    const int b = (int)(row % L.nt), a = (int)(row / L.nt);
-    auto nb = [&](int k) {
-        const int da = k / 9 - 1, db = (k / 3) % 3 - 1, dc = k % 3 - 1;
-        const int aa = clampi(a + da, L.nr - 1), bb = clampi(b + db, L.nt - 1);
+    const long long nat = t / 27;
+    const int k = (int)(t - nat * 27);
+    const long long rowi = nat / g.np;
+    const int c = (int)(nat - rowi * g.np);
+    const int b = (int)(rowi % g.nt), a = (int)(rowi / g.nt);
+    auto nb = [&](int q) {
+        const int da = q / 9 - 1, db = (q / 3) % 3 - 1, dc = q % 3 - 1;
+        const int aa = clampi(a + da, g.nr - 1), bb = clampi(b + db, g.nt - 1);
         int cc = c + dc;
-        cc = cc < 0 ? cc + L.np : (cc >= L.np ? cc - L.np : cc);
-        return ((long long)aa * L.nt + bb) * L.np + cc;
+        cc = cc < 0 ? cc + g.np : (cc >= g.np ? cc - g.np : cc);
+        return split_index(g, aa, bb, cc);
     };
-    const long long j = nb(s);
-    for (int k = 0; k < s; ++k)
-        if (nb(k) == j) return;
+    const long long j = nb(k);
+    for (int q = 0; q < k; ++q)
+        if (nb(q) == j) return;
     double D;
-    A[i * n + j] = apply_cell<double, MODE, AXI>(L, Delta<double>{j}, a, b, c, D);
+    const long long i = split_index(g, a, b, c);
+    A[i * n + j] = apply_cell<double, MODE, AXI>(g, L.G, L.gk, Delta<double>{j}, a, b, c & 1, c >> 1, D);
 }
 
 // alpha = mean |diag| / n, added to every entry (A + alpha 1 1^T); also
