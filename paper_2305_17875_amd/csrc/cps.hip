@@ -261,18 +261,21 @@ MarchShape march_shape(const Geo& g)
 
 inline bool marching(const cps_handle* h) { return h->mode == MODE_ORTHO && h->axi; }
 
+// One colour pass; zero: the iterate is zero before this pass (two colours
+// only), so the other colour is not read and need not be initialised.
 template <typename T>
-void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x)
+void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero = false)
 {
     const Level<T> L = view<T>(h, l);
     const int rowlen = h->ncol == 2 ? L.g.rowlen : L.g.rowlen / 2;
     const int bpa = (int)nblk(rowlen);
+    const int z = zero ? 1 : 0;
     ProfScope ps(h, CPS_KERNEL_GS, l);
     if (marching(h)) {
         const MarchShape ms = march_shape(L.g);
         auto launch = [&](auto U, auto T_) {
             k_gs_march<T, decltype(U)::value, decltype(T_)::value>
-                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour);
+                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour, z);
         };
         const bool u = L.g.nh % 64 == 0;
         if (l == 0) u ? launch(BA<true>{}, IM<0>{}) : launch(BA<false>{}, IM<0>{});
@@ -283,16 +286,23 @@ void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x)
     dispatch4(h->mode, h->axi, L.g.nh % 64 == 0, l == 0 ? 0 : 1, [&](auto M, auto A, auto U, auto T_) {
         k_gs<T, decltype(M)::value, decltype(A)::value, decltype(U)::value, decltype(T_)::value>
             <<<grid_of(L.g.nr, bpa), kBlock, 0, h->stream>>>(L.g, L.G, L.gk, bpa, b, x, colour,
-                                                             h->ncol);
+                                                             h->ncol, z);
     });
     LAUNCH_CHECK();
 }
 
+// Gauss-Seidel sweeps over all colours (reverse order for post-smoothing).
+// from_zero: x is zero on entry; with two colours it is then not even read
+// (nor initialised) before the first pass writes it, otherwise it is filled.
 template <typename T>
-void smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse)
+void smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse,
+            bool from_zero = false)
 {
+    const bool skip = from_zero && h->ncol == 2;
+    if (from_zero && !skip) fill<T>(h, x, h->lv[l].n, T(0));
     for (int s = 0; s < sweeps; ++s)
-        for (int k = 0; k < h->ncol; ++k) gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x);
+        for (int k = 0; k < h->ncol; ++k)
+            gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x, skip && s == 0 && k == 0);
 }
 
 // r = b - A x; partial sums of r^2 into h->partial when want_norm.
@@ -372,9 +382,9 @@ void restrict_to(cps_handle* h, int l, const T* r, T* bc)
 {
     const Geo& f = h->lv[l].geo;
     const Geo& c = h->lv[l + 1].geo;
-    const int bpa = (int)nblk(c.rowlen);
+    const MarchShape ms = march_shape(c);
     ProfScope ps(h, CPS_KERNEL_RESTRICT, l);
-    k_restrict<T><<<c.nr * bpa, kBlock, 0, h->stream>>>(f, c, bpa, r, bc);
+    k_restrict<T><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, r, bc);
     LAUNCH_CHECK();
 }
 
@@ -383,9 +393,9 @@ void prolong_add(cps_handle* h, int l, const T* e, T* x)
 {
     const Geo& f = h->lv[l].geo;
     const Geo& c = h->lv[l + 1].geo;
-    const int bpa = (int)nblk(f.rowlen);
+    const MarchShape ms = march_shape(c);
     ProfScope ps(h, CPS_KERNEL_PROLONG, l);
-    k_prolong<T><<<f.nr * bpa, kBlock, 0, h->stream>>>(f, c, bpa, e, x);
+    k_prolong<T><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, e, x);
     LAUNCH_CHECK();
 }
 
@@ -399,7 +409,7 @@ void coarse_solve(cps_handle* h, const T* b, T* e)
 
 // One V(2,2) cycle with level-0 right-hand side b0 and iterate x0 (in place).
 template <typename T>
-void vcycle(cps_handle* h, const T* b0, T* x0)
+void vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false)
 {
     const int L = h->L;
     if (L == 1) {
@@ -409,8 +419,8 @@ void vcycle(cps_handle* h, const T* b0, T* x0)
     for (int l = 0; l < L - 1; ++l) {
         const T* b = l == 0 ? b0 : bl<T>(h, l);
         T* x = l == 0 ? x0 : xl<T>(h, l);
-        if (l > 0) fill<T>(h, x, h->lv[l].n, T(0));
-        smooth<T>(h, l, b, x, 2, false);
+        // coarse corrections start from zero
+        smooth<T>(h, l, b, x, 2, false, l > 0 || x0_zero);
         residual<T>(h, l, b, x, rl<T>(h, l), false);
         restrict_to<T>(h, l, rl<T>(h, l), bl<T>(h, l + 1));
     }
@@ -429,15 +439,13 @@ void precondition(cps_handle* h, const double* in, double* out)
 {
     const long long n = h->lv[0].n;
     if (h->opts.precision == 0) {
-        fill<double>(h, out, n, 0.0);
-        vcycle<double>(h, in, out);
+        vcycle<double>(h, in, out, true);
     } else {
         float* b = h->lv[0].b32.p;
         float* x = h->lv[0].x32.p;
         k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, in, b, h->sc.p, S_SCALE, 1);
         LAUNCH_CHECK();
-        fill<float>(h, x, n, 0.0f);
-        vcycle<float>(h, b, x);
+        vcycle<float>(h, b, x, true);
         k_cast<float, double><<<nblk(n), kBlock, 0, h->stream>>>(n, x, out, h->sc.p, S_SCALE, 0);
         LAUNCH_CHECK();
     }
@@ -725,8 +733,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                     k_sqrt_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_SCALE, S_RR);
                     k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, h->r.p, b32, h->sc.p, S_SCALE, 1);
                     LAUNCH_CHECK();
-                    fill<float>(h, x32, n, 0.0f);
-                    vcycle<float>(h, b32, x32);
+                    vcycle<float>(h, b32, x32, true);
                     k_ir_update<float><<<nblk(n), kBlock, 0, h->stream>>>(n, x, x32, h->sc.p + S_SCALE);
                     LAUNCH_CHECK();
                     reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);

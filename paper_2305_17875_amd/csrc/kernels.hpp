@@ -336,10 +336,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(Geo g, const T* __restrict_
 // Two colours: one thread per (a, b, j), the cell of the colour is in plane
 // (k + a + b) mod 2.  Four colours: the colour occupies every other theta
 // row (b = (k0 + k1 + a) mod 2 + 2 bh) in plane (k1 + a) mod 2.
+// zero != 0 (two colours only): first pass from a zero iterate, the other
+// colour is neither read nor needed.
 template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
 __global__ void __launch_bounds__(kBlock) k_gs(Geo g, const T* __restrict__ G, long long gk,
                                                int bpa, const T* __restrict__ bv,
-                                               T* __restrict__ x, int colour, int ncol)
+                                               T* __restrict__ x, int colour, int ncol, int zero)
 {
     const int rowlen = ncol == 2 ? g.rowlen : g.rowlen / 2;
     for_units(rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
@@ -354,7 +356,8 @@ __global__ void __launch_bounds__(kBlock) k_gs(Geo g, const T* __restrict__ G, l
             s = (k1 + a) & 1;
         }
         T D;
-        const T S = apply_cell<T, MODE, AXI, true>(g, G, gk, Field<T>{x}, a, b, s, j, D);
+        const T S = zero ? apply_cell<T, MODE, AXI, true>(g, G, gk, Delta<T>{-1}, a, b, s, j, D)
+                         : apply_cell<T, MODE, AXI, true>(g, G, gk, Field<T>{x}, a, b, s, j, D);
         const long long id = s * g.P + ((long long)a * g.nt + b) * g.nh + j;
         x[id] = (bv[id] - S) / D;
     });
@@ -397,13 +400,27 @@ __device__ __forceinline__ bool march_pos(const Geo& g, int bpa, int ch, March& 
 // neighbours are: the column's own cells at a-1, a+1 (plane p) and at a
 // (plane 1-p), the cells at (a, b+-1) in plane p, and one phi neighbour in
 // plane 1-p of the adjacent column.
+// zero != 0: first pass from a zero iterate (the other colour is taken as 0
+// and not read; it need not be initialised), x = b / D.
 template <typename T, bool UROW, int LTAG>
 __global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict__ G, long long gk,
                                                      int bpa, int ch, const T* __restrict__ bv,
-                                                     T* __restrict__ x, int colour)
+                                                     T* __restrict__ x, int colour, int zero)
 {
     March p;
     if (!march_pos<UROW>(g, bpa, ch, p)) return;
+    if (zero) {
+        for (int a = p.a0; a < p.a1; ++a) {
+            const int s = (colour + a + p.b) & 1;
+            const long long ci = (long long)a * g.nt + p.b;
+            const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
+            const T gth = p.b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
+            const T D = -(G[ci] + grh + G[4 * gk + ci] + gth + T(2) * G[8 * gk + ci]);
+            const long long id = s * g.P + (long long)a * g.rowlen + p.m;
+            x[id] = bv[id] / D;
+        }
+        return;
+    }
     const long long sr = g.rowlen;
     const int nh = g.nh, b = p.b, j = p.j;
     // the other-colour cell of this column at plane a
@@ -540,77 +557,144 @@ __global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restri
 // Grid transfers (cell-centred, coarsening by 2 in every direction)
 // ---------------------------------------------------------------------------
 
-// bc = P^T r, gathered: coarse index I takes fine 2I-1, 2I, 2I+1, 2I+2 with
-// weights 1/4, 3/4, 3/4, 1/4 per direction; fine indices past a wall fold
-// onto the wall cell, phi wraps.  One thread per coarse (I, J, jc): the two
-// coarse cells K = 2 jc and 2 jc + 1.
+// Both transfers are separable products of 1-D cell-centred linear
+// interpolation (P) and its transpose (R = P^T): fine cell i takes 3/4 of
+// coarse i/2 and 1/4 of coarse i/2 - 1 (even i) or i/2 + 1 (odd i), indices
+// mirrored at walls and wrapped in phi; coarse I gathers fine 2I-1, 2I,
+// 2I+1, 2I+2 with weights 1/4, 3/4, 3/4, 1/4 (a fine index past a wall folds
+// onto the wall cell).  One thread per coarse column (J, jc), i.e. the
+// coarse cells K = 2 jc and 2 jc + 1, marching over a chunk of coarse
+// planes: the theta-phi part for one plane is formed once and used by every
+// r position that needs it.  Launch: grid = bpa * nchunks over the coarse
+// plane positions, `ch` coarse planes per chunk.
+
+struct CoarseCol {
+    int I0, I1, m, J, jc;
+};
+
+__device__ __forceinline__ bool coarse_col(const Geo& c, int bpa, int ch, CoarseCol& p)
+{
+    const int L = (int)xcd_block();
+    const int chunk = L / bpa;
+    p.m = (L - chunk * bpa) * kBlock + (int)threadIdx.x;
+    p.I0 = chunk * ch;
+    p.I1 = min(c.nr, p.I0 + ch);
+    if (p.m >= c.rowlen || p.I0 >= c.nr) return false;
+    p.J = p.m / c.nh;
+    p.jc = p.m - p.J * c.nh;
+    return true;
+}
+
+// bc = R r (full weighting; interior rows sum to 8).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa,
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa, int ch,
                                                      const T* __restrict__ r,
                                                      T* __restrict__ bc)
 {
-    int I, m;
-    if (!plane_pos(c.rowlen, bpa, I, m)) return;
-    const int J = m / c.nh, jc = m - J * c.nh;
-    const T w[4] = {T(0.25), T(0.75), T(0.75), T(0.25)};
-    long long rowoff[4][4]; // fine (ia, ib) row offsets
-    for (int p = 0; p < 4; ++p) {
-        const int ia = clampi(2 * I - 1 + p, f.nr - 1);
-        for (int q = 0; q < 4; ++q) {
-            const int ib = clampi(2 * J - 1 + q, f.nt - 1);
-            rowoff[p][q] = ((long long)ia * f.nt + ib) * f.nh;
-        }
+    CoarseCol p;
+    if (!coarse_col(c, bpa, ch, p)) return;
+    const T w0 = T(0.25), w1 = T(0.75);
+    long long rowo[4];
+    for (int q = 0; q < 4; ++q) rowo[q] = (long long)clampi(2 * p.J - 1 + q, f.nt - 1) * f.nh;
+    long long co[6]; // fine phi positions 4jc-1 .. 4jc+4 (plane + index)
+    for (int o = 0; o < 6; ++o) {
+        int cc = 4 * p.jc - 1 + o;
+        cc = cc < 0 ? cc + f.np : (cc >= f.np ? cc - f.np : cc);
+        co[o] = (long long)(cc & 1) * f.P + (cc >> 1);
     }
+    const T wq[4] = {w0, w1, w1, w0};
+    // theta-phi restriction of fine plane a for K = 2jc (s0) and 2jc+1 (s1)
+    auto plane = [&](int a, T& s0, T& s1) {
+        const T* ra = r + (long long)clampi(a, f.nr - 1) * f.rowlen;
+        s0 = T(0);
+        s1 = T(0);
 #pragma unroll
-    for (int sc = 0; sc < 2; ++sc) {
-        const int K = 2 * jc + sc;
-        long long co[4]; // fine phi offsets (plane + index)
-        for (int o = 0; o < 4; ++o) {
-            int cc = 2 * K - 1 + o;
-            cc = cc < 0 ? cc + f.np : (cc >= f.np ? cc - f.np : cc);
-            co[o] = (cc & 1) * f.P + (cc >> 1);
+        for (int q = 0; q < 4; ++q) {
+            const T* rr = ra + rowo[q];
+            const T v0 = rr[co[0]], v1 = rr[co[1]], v2 = rr[co[2]];
+            const T v3 = rr[co[3]], v4 = rr[co[4]], v5 = rr[co[5]];
+            s0 += wq[q] * (w0 * v0 + w1 * v1 + w1 * v2 + w0 * v3);
+            s1 += wq[q] * (w0 * v2 + w1 * v3 + w1 * v4 + w0 * v5);
         }
-        T s = T(0);
-        for (int p = 0; p < 4; ++p)
-            for (int q = 0; q < 4; ++q) {
-                const T* rr = r + rowoff[p][q];
-                const T t = w[0] * rr[co[0]] + w[1] * rr[co[1]] + w[2] * rr[co[2]] + w[3] * rr[co[3]];
-                s += w[p] * w[q] * t;
-            }
-        bc[sc * c.P + (long long)I * c.rowlen + m] = s;
+    };
+    T pa0, pa1, pb0, pb1;
+    plane(2 * p.I0 - 1, pa0, pa1);
+    plane(2 * p.I0, pb0, pb1);
+    for (int I = p.I0; I < p.I1; ++I) {
+        T qa0, qa1, qb0, qb1;
+        plane(2 * I + 1, qa0, qa1);
+        plane(2 * I + 2, qb0, qb1);
+        const long long o = (long long)I * c.rowlen + p.m;
+        bc[o] = w0 * pa0 + w1 * pb0 + w1 * qa0 + w0 * qb0;
+        bc[c.P + o] = w0 * pa1 + w1 * pb1 + w1 * qa1 + w0 * qb1;
+        pa0 = qa0; pa1 = qa1; pb0 = qb0; pb1 = qb1;
     }
 }
 
-// x += P e: fine cell i in a direction takes 3/4 of coarse i/2 and 1/4 of
-// coarse i/2 - 1 (even i) or i/2 + 1 (odd i), mirrored at walls, wrapped in
-// phi; trilinear = the product of the three.  One thread per fine (a, b, j):
-// the fine cells c = 2j and 2j + 1 (coarse phi index j for both).
+// x += P e (trilinear); the thread writes fine rows 2J, 2J+1 and fine phi
+// 4jc .. 4jc+3 on the two fine planes of every coarse plane of its chunk.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong(Geo f, Geo c, int bpa,
+__global__ void __launch_bounds__(kBlock) k_prolong(Geo f, Geo c, int bpa, int ch,
                                                     const T* __restrict__ e,
                                                     T* __restrict__ x)
 {
-    int a, m;
-    if (!plane_pos(f.rowlen, bpa, a, m)) return;
-    const int b = m / f.nh, j = m - b * f.nh;
-    const int A0 = a >> 1, B0 = b >> 1;
-    const int A1 = clampi((a & 1) ? A0 + 1 : A0 - 1, c.nr - 1);
-    const int B1 = clampi((b & 1) ? B0 + 1 : B0 - 1, c.nt - 1);
-    const long long r00 = ((long long)A0 * c.nt + B0) * c.nh, r01 = ((long long)A0 * c.nt + B1) * c.nh;
-    const long long r10 = ((long long)A1 * c.nt + B0) * c.nh, r11 = ((long long)A1 * c.nt + B1) * c.nh;
-    auto kofs = [&](int K) {
-        K = K < 0 ? K + c.np : (K >= c.np ? K - c.np : K);
-        return (K & 1) * c.P + (K >> 1);
-    };
-    const long long k0 = kofs(j);
+    CoarseCol p;
+    if (!coarse_col(c, bpa, ch, p)) return;
     const T w0 = T(0.75), w1 = T(0.25);
-    const long long i0 = (long long)a * f.rowlen + m;
+    long long crow[3]; // coarse rows J-1, J, J+1 (mirrored)
+    for (int q = 0; q < 3; ++q) crow[q] = (long long)clampi(p.J - 1 + q, c.nt - 1) * c.nh;
+    long long ck[4]; // coarse K = 2jc-1 .. 2jc+2 (plane + index)
+    for (int o = 0; o < 4; ++o) {
+        int K = 2 * p.jc - 1 + o;
+        K = K < 0 ? K + c.np : (K >= c.np ? K - c.np : K);
+        ck[o] = (long long)(K & 1) * c.P + (K >> 1);
+    }
+    // theta-phi interpolation of coarse plane I onto the thread's 2 x 4
+    // fine (row, phi) positions: out[row][t], fine phi = 4jc + t
+    auto plane = [&](int I, T out[2][4]) {
+        const T* ea = e + (long long)clampi(I, c.nr - 1) * c.rowlen;
+        T th[2][4];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const long long k1 = kofs(s ? j + 1 : j - 1);
-        const T v0 = w0 * (w0 * e[r00 + k0] + w1 * e[r00 + k1]) + w1 * (w0 * e[r01 + k0] + w1 * e[r01 + k1]);
-        const T v1 = w0 * (w0 * e[r10 + k0] + w1 * e[r10 + k1]) + w1 * (w0 * e[r11 + k0] + w1 * e[r11 + k1]);
-        x[i0 + s * f.P] += w0 * v0 + w1 * v1;
+        for (int o = 0; o < 4; ++o) {
+            const T em = ea[crow[0] + ck[o]], e0 = ea[crow[1] + ck[o]], ep = ea[crow[2] + ck[o]];
+            th[0][o] = w0 * e0 + w1 * em;
+            th[1][o] = w0 * e0 + w1 * ep;
+        }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            // fine 4jc, 4jc+1 come from K = 2jc (o = 1); 4jc+2, 4jc+3 from 2jc+1 (o = 2)
+            out[rr][0] = w0 * th[rr][1] + w1 * th[rr][0];
+            out[rr][1] = w0 * th[rr][1] + w1 * th[rr][2];
+            out[rr][2] = w0 * th[rr][2] + w1 * th[rr][1];
+            out[rr][3] = w0 * th[rr][2] + w1 * th[rr][3];
+        }
+    };
+    T tm[2][4], t0[2][4], tp[2][4];
+    plane(p.I0 - 1, tm);
+    plane(p.I0, t0);
+    // fine offsets inside a fine plane of (row 2J + rr, phi 4jc + t)
+    long long fo[2][4];
+    for (int rr = 0; rr < 2; ++rr)
+        for (int t = 0; t < 4; ++t)
+            fo[rr][t] = (long long)(t & 1) * f.P + (long long)(2 * p.J + rr) * f.nh + 2 * p.jc + (t >> 1);
+    for (int I = p.I0; I < p.I1; ++I) {
+        plane(I + 1, tp);
+        T* x0 = x + (long long)(2 * I) * f.rowlen;
+        T* x1 = x0 + f.rowlen;
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                x0[fo[rr][t]] += w0 * t0[rr][t] + w1 * tm[rr][t];
+                x1[fo[rr][t]] += w0 * t0[rr][t] + w1 * tp[rr][t];
+            }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                tm[rr][t] = t0[rr][t];
+                t0[rr][t] = tp[rr][t];
+            }
     }
 }
 

@@ -1,0 +1,116 @@
+"""Summarise rocprofv3 result databases of bench.py into short text.
+
+    python -m paper_2305_17875_amd.profsum --kt KT.db --fetch F.db --write W.db \\
+        --cmd "<the rocprofv3 commands>" --md out.md --traffic out.json
+
+--kt     database of `rocprofv3 --kernel-trace --stats -- python3 bench.py ...`
+--fetch  database of `rocprofv3 --pmc FETCH_SIZE -- python3 bench.py ...`
+--write  database of `rocprofv3 --pmc WRITE_SIZE -- python3 bench.py ...`
+
+Counter values (KiB per dispatch) are scaled by what the same counter reads
+on bench.py's plain copy kernel of 192*256*512 doubles (201,326,592 bytes
+read and written), which turns them into bytes.  The traffic JSON records
+the finest-level Gauss-Seidel kernel's bytes per launch together with a hash
+of the kernel source, so bench.py can tell whether it is still current.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import hashlib
+import json
+import os
+import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(HERE, "csrc", "kernels.hpp")
+COPY_BYTES = 192 * 256 * 512 * 8
+GS_FINEST = "k_gs_march<double, true, 0>"
+
+
+def short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").replace("cps::", "")
+
+
+def durations(db):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, duration, grid_x from kernels").fetchall()
+    agg = collections.defaultdict(list)
+    for n, d, g in rows:
+        agg[(short(n), g)].append(d)
+    return agg
+
+
+def counters(db):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, grid_size, counter_name, value "
+                     "from counters_collection").fetchall()
+    agg = collections.defaultdict(list)
+    for n, g, cn, v in rows:
+        agg[(short(n), g, cn)].append(v)
+    return agg
+
+
+def mean(v):
+    return sum(v) / len(v)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kt", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--cmd", required=True)
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--traffic", required=True)
+    ap.add_argument("--top", type=int, default=16)
+    a = ap.parse_args()
+    kh = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    dur = durations(a.kt)
+    fe = counters(a.fetch)
+    wr = counters(a.write)
+    copy_f = mean([v for (n, g, cn), v in fe.items() if n.startswith("k_copy<double>")
+                   and g == COPY_BYTES // 8][0])
+    copy_w = mean([v for (n, g, cn), v in wr.items() if n.startswith("k_copy<double>")
+                   and g == COPY_BYTES // 8][0])
+    sf = COPY_BYTES / (copy_f * 1024.0)
+    sw = COPY_BYTES / (copy_w * 1024.0)
+    lines = [f"# rocprofv3 summary: bench.py (spherical shell 192x256x512, FP64 PCG-multigrid)",
+             "", "Commands (run from the repository root on one MI355X):", "", "```",
+             a.cmd, "```", "",
+             f"kernel source sha256[:16] = `{kh}`", "",
+             "## Kernel durations (--kernel-trace --stats)", "",
+             "| kernel | grid (threads) | launches | avg us | total ms |", "|---|---|---|---|---|"]
+    for (n, g), v in sorted(dur.items(), key=lambda kv: -sum(kv[1]))[:a.top]:
+        lines.append(f"| `{n}` | {g} | {len(v)} | {mean(v) / 1e3:.1f} | {sum(v) / 1e6:.2f} |")
+    lines += ["", "## HBM bytes per dispatch (FETCH_SIZE, WRITE_SIZE)", "",
+              f"Scale: the copy kernel of {COPY_BYTES} bytes reads as {copy_f:.1f} KiB fetched "
+              f"and {copy_w:.1f} KiB written, so fetch x{sf:.3f}, write x{sw:.3f}.", "",
+              "| kernel | grid (threads) | fetch MB | write MB |", "|---|---|---|---|"]
+    keys = sorted({(n, g) for (n, g, cn) in fe}, key=lambda k: -mean(fe[(k[0], k[1], 'FETCH_SIZE')]))
+    gs = None
+    for n, g in keys[:a.top]:
+        f = mean(fe[(n, g, "FETCH_SIZE")]) * 1024 * sf
+        w = mean(wr.get((n, g, "WRITE_SIZE"), [0.0])) * 1024 * sw
+        lines.append(f"| `{n}` | {g} | {f / 1e6:.1f} | {w / 1e6:.1f} |")
+        if n.startswith(GS_FINEST):
+            gs = (f, w, g)
+    if gs is None:
+        for (n, g, cn), v in fe.items():
+            if n.startswith(GS_FINEST):
+                gs = (mean(v) * 1024 * sf, mean(wr[(n, g, "WRITE_SIZE")]) * 1024 * sw, g)
+    gsd = [v for (n, g), v in dur.items() if n.startswith(GS_FINEST)]
+    lines += ["", f"Finest-level Gauss-Seidel colour pass `{GS_FINEST}`: average "
+              f"{mean(gsd[0]) / 1e3:.1f} us over {len(gsd[0])} launches; "
+              f"{gs[0] / 1e6:.1f} MB fetched + {gs[1] / 1e6:.1f} MB written per launch.", ""]
+    os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
+    open(a.md, "w").write("\n".join(lines))
+    json.dump({"kernel": GS_FINEST, "kernel_source_sha256_16": kh,
+               "bytes_per_launch": gs[0] + gs[1], "fetch_bytes": gs[0], "write_bytes": gs[1],
+               "fetch_scale": sf, "write_scale": sw, "avg_us_trace": mean(gsd[0]) / 1e3},
+              open(a.traffic, "w"), indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
