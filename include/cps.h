@@ -158,6 +158,29 @@ cps_status cps_debug_coarse_solve(cps_handle* h, const double* b, double* e);
 /* one V(2,2) cycle on level 0 with right-hand side b, x in place. */
 cps_status cps_debug_vcycle(cps_handle* h, const double* b, double* x);
 
+/* ---- Batched form ------------------------------------------------------
+ * Many independent shell problems (uneven sizes, any maps) solved together:
+ * each phase of the iteration is one launch for all problems (a device work
+ * table maps every block to its problem), the iteration bodies are captured
+ * in hipGraphs, converged problems retire.  Every problem runs FP32 V-cycles
+ * inside FP64 refinement with Krylov acceleration, exactly as cps_solve with
+ * precision = 1, accel = 1 on the same stream: results equal the problem
+ * solved alone, bit for bit. */
+typedef struct cps_batch cps_batch;
+
+/* grids: host array of n grids; metrics, opts: host, nullable (opts.precision
+ * must be 1 when given; opts.stream NULL creates a private stream).
+ * Builds every hierarchy on the device.  Errors as cps_setup; a batch may hold
+ * the 7-point class plus one other stencil class. */
+cps_status cps_batch_setup(int32_t n, const cps_grid* grids, const cps_metrics* metrics,
+                           const cps_opts* opts, cps_batch** out);
+/* rhs, p: host arrays of n DEVICE pointers (FP64, natural order, each of its
+ * grid's size); infos: host array of n, nullable.  Returns CPS_OK when every
+ * problem converged, else CPS_E_DIVERGED / CPS_E_NOT_CONVERGED (see infos). */
+cps_status cps_batch_solve(cps_batch* b, const double* const* rhs, double* const* p, double tol,
+                           cps_info* infos);
+void cps_batch_destroy(cps_batch* b);
+
 /* ---- Measurement -------------------------------------------------------
  * Kernel classes timed on the finest level with HIP events recorded on the
  * handle's stream around each launch. */

@@ -85,6 +85,12 @@ def lib():
         L.cps_debug_prolong.argtypes = [P, I, P, P]
         L.cps_debug_coarse_solve.argtypes = [P, P, P]
         L.cps_debug_vcycle.argtypes = [P, P, P]
+        L.cps_batch_setup.argtypes = [I, P, P, P, ctypes.POINTER(P)]
+        L.cps_batch_setup.restype = I
+        L.cps_batch_solve.argtypes = [P, P, P, D, P]
+        L.cps_batch_solve.restype = I
+        L.cps_batch_destroy.argtypes = [P]
+        L.cps_batch_destroy.restype = None
         L.cps_profile_enable.argtypes = [P, I]
         L.cps_profile_read.argtypes = [P, I, P, P]
         L.cps_debug_copy.argtypes = [P, P, ctypes.c_int64, P]
@@ -286,6 +292,69 @@ class Solver:
     def close(self):
         if getattr(self, "h", None):
             cps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cps_batch_setup(grids, metrics: cps_metrics, opts: cps_opts):
+    arr = (cps_grid * len(grids))(*grids)
+    h = ctypes.c_void_p()
+    _check(lib().cps_batch_setup(len(grids), arr, ctypes.byref(metrics), ctypes.byref(opts),
+                                 ctypes.byref(h)))
+    return h
+
+
+def cps_batch_solve(h, rhs_list, p_list, sizes, tol: float):
+    """rhs_list / p_list: device tensors (checked against sizes).  Returns
+    (status, [cps_info])."""
+    n = len(rhs_list)
+    if len(p_list) != n or len(sizes) != n:
+        raise ValueError("one rhs and one p per problem")
+    for r, p, s in zip(rhs_list, p_list, sizes):
+        _expect(r, s, "rhs")
+        _expect(p, s, "p")
+    rp = (ctypes.c_void_p * n)(*[_ptr(t) for t in rhs_list])
+    pp = (ctypes.c_void_p * n)(*[_ptr(t) for t in p_list])
+    infos = (cps_info * n)()
+    st = lib().cps_batch_solve(h, rp, pp, tol, infos)
+    if st not in (CPS_OK, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED):
+        _check(st)
+    return st, list(infos)
+
+
+def cps_batch_destroy(h):
+    if h:
+        lib().cps_batch_destroy(h)
+
+
+class Batch:
+    """Many problems solved together (FP32 V-cycles inside FP64 refinement)."""
+
+    def __init__(self, grids, max_iters: int = 200, metrics: int = METRICS_MAP_CENTRAL,
+                 stream=None):
+        import torch
+        self.grids = list(grids)
+        self.sizes = [g.n_r * g.n_theta * g.n_phi for g in self.grids]
+        s = stream if stream is not None else torch.cuda.current_stream()
+        opts = cps_opts(1, max_iters, 1, ctypes.c_void_p(s.cuda_stream))
+        self.h = cps_batch_setup([make_grid(g) for g in self.grids], cps_metrics(metrics), opts)
+
+    def solve(self, rhs_list, tol: float = 1e-10, out=None):
+        import torch
+        p = out if out is not None else [torch.empty_like(r) for r in rhs_list]
+        # the batch may run on its own stream: inputs must be complete
+        torch.cuda.current_stream().synchronize()
+        st, infos = cps_batch_solve(self.h, rhs_list, p, self.sizes, tol)
+        return st, p, infos
+
+    def close(self):
+        if getattr(self, "h", None):
+            cps_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -55,7 +55,6 @@ struct Fail {
 
 #define LAUNCH_CHECK() HIPC(hipGetLastError())
 
-constexpr int kMaxLevels = 16;
 constexpr long long kMaxCoarse = 4096;
 
 inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -141,6 +140,7 @@ struct LevelMem {
     Buf<float> G32;
     Buf<double> x64, b64, r64;
     Buf<float> x32, b32, r32;
+    int gs_ch = 0; // marching chunk of the colour pass (0 = default; autotuned)
 };
 
 } // namespace
@@ -243,22 +243,7 @@ void fill(cps_handle* h, T* x, long long n, T v)
     LAUNCH_CHECK();
 }
 
-// Launch shape of the marching kernels (7-point stencil, phi-invariant
-// metrics): bpa blocks per plane, planes split into chunks of ch so that the
-// grid has about 2048 blocks (one resident wave of 8 blocks per CU).
-struct MarchShape {
-    int bpa, ch, grid;
-};
-
-MarchShape march_shape(const Geo& g)
-{
-    const int bpa = (int)nblk(g.rowlen);
-    int nchunks = std::max(1, std::min(g.nr, (2048 + bpa - 1) / bpa));
-    const int ch = (g.nr + nchunks - 1) / nchunks;
-    nchunks = (g.nr + ch - 1) / ch;
-    return {bpa, ch, bpa * nchunks};
-}
-
+// marching kernels serve the 7-point stencil with phi-invariant metrics
 inline bool marching(const cps_handle* h) { return h->mode == MODE_ORTHO && h->axi; }
 
 // One colour pass; zero: the iterate is zero before this pass (two colours
@@ -272,7 +257,7 @@ void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero = fal
     const int z = zero ? 1 : 0;
     ProfScope ps(h, CPS_KERNEL_GS, l);
     if (marching(h)) {
-        const MarchShape ms = march_shape(L.g);
+        const MarchShape ms = march_shape(L.g, h->lv[l].gs_ch);
         auto launch = [&](auto U, auto T_) {
             k_gs_march<T, decltype(U)::value, decltype(T_)::value>
                 <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour, z);
@@ -873,6 +858,9 @@ void need_level(const cps_handle* h, int l, bool fine)
 }
 
 } // namespace
+
+// batched form (same translation unit: shares the hierarchy code above)
+#include "batch.hpp"
 
 // ---------------------------------------------------------------------------
 // C ABI

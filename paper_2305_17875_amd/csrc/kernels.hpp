@@ -75,15 +75,14 @@ __device__ __forceinline__ unsigned xcd_block()
     return x * q + (x < r ? x : r) + k;
 }
 
-// Position of this thread in a launch over nr planes of `rowlen` positions
-// each, with `bpa` blocks per plane; m = position inside the plane.
-__device__ __forceinline__ bool plane_pos(int rowlen, int bpa, int& a, int& m)
-{
-    const int L = (int)xcd_block();
-    a = L / bpa;
-    m = (L - a * bpa) * kBlock + (int)threadIdx.x;
-    return m < rowlen;
-}
+// The block a kernel body works as: logical index L of G blocks of one
+// problem's launch.  A single-problem launch takes its XCD-remapped block
+// index; a batched launch takes (problem, L, G) from a work table.
+struct Blk {
+    unsigned L, G;
+};
+
+__device__ __forceinline__ Blk self_blk() { return Blk{xcd_block(), gridDim.x}; }
 
 template <typename T>
 struct Field {
@@ -224,7 +223,7 @@ __device__ __forceinline__ double block_sum(double v)
 
 // *out = sum of partial[0..n) in a fixed order (one block; four
 // independent accumulators per thread keep several loads in flight).
-__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partial, long long n,
+__device__ __forceinline__ void d_reduce(Blk bk, const double* __restrict__ partial, long long n,
                                                    double* __restrict__ out)
 {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -240,6 +239,12 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ pa
     if (threadIdx.x == 0) *out = s;
 }
 
+__global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partial, long long n,
+                                                   double* __restrict__ out)
+{
+    d_reduce(self_blk(), partial, n, out);
+}
+
 // Blocks of the stencil kernels walk a contiguous range of "units" (256
 // consecutive positions of one r-plane): unit u covers plane a = u / bpa,
 // positions m = (u mod bpa) * 256 + thread.  Grids are capped (kMaxGrid), so
@@ -248,9 +253,9 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ pa
 constexpr int kMaxGrid = 4096;
 
 template <typename F>
-__device__ __forceinline__ void for_units(int rowlen, int bpa, long long nunits, F&& f)
+__device__ __forceinline__ void for_units(Blk bk, int rowlen, int bpa, long long nunits, F&& f)
 {
-    const long long L = xcd_block(), G = gridDim.x;
+    const long long L = bk.L, G = bk.G;
     const unsigned u0 = (unsigned)(nunits * L / G), u1 = (unsigned)(nunits * (L + 1) / G);
     for (unsigned u = u0; u < u1; ++u) {
         const unsigned a = u / (unsigned)bpa;
@@ -279,13 +284,13 @@ __device__ __forceinline__ int row_of(int m, int nh)
 
 // y = A x; with dotv, per-block partial sums of y . dotv
 template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
-__global__ void __launch_bounds__(kBlock) k_apply(Geo g, const T* __restrict__ G, long long gk,
+__device__ __forceinline__ void d_apply(Blk bk, Geo g, const T* __restrict__ G, long long gk,
                                                   int bpa, const T* __restrict__ x,
                                                   T* __restrict__ y, double* __restrict__ partial,
                                                   const T* __restrict__ dotv)
 {
     double acc = 0.0;
-    for_units(g.rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
+    for_units(bk, g.rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
         const int b = row_of<UROW>(m, g.nh), j = m - b * g.nh;
         const long long i0 = (long long)a * g.rowlen + m;
 #pragma unroll
@@ -298,19 +303,28 @@ __global__ void __launch_bounds__(kBlock) k_apply(Geo g, const T* __restrict__ G
     });
     if (partial) {
         acc = block_sum(acc);
-        if (threadIdx.x == 0) partial[xcd_block()] = acc;
+        if (threadIdx.x == 0) partial[bk.L] = acc;
     }
+}
+
+template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_apply(Geo g, const T* __restrict__ G, long long gk,
+                                                  int bpa, const T* __restrict__ x,
+                                                  T* __restrict__ y, double* __restrict__ partial,
+                                                  const T* __restrict__ dotv)
+{
+    d_apply<T, MODE, AXI, UROW, LTAG>(self_blk(), g, G, gk, bpa, x, y, partial, dotv);
 }
 
 // r = b - A x; with partial, per-block partial sums of r^2
 template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
-__global__ void __launch_bounds__(kBlock) k_residual(Geo g, const T* __restrict__ G, long long gk,
+__device__ __forceinline__ void d_residual(Blk bk, Geo g, const T* __restrict__ G, long long gk,
                                                      int bpa, const T* __restrict__ bv,
                                                      const T* __restrict__ x, T* __restrict__ r,
                                                      double* __restrict__ partial)
 {
     double acc = 0.0;
-    for_units(g.rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
+    for_units(bk, g.rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
         const int b = row_of<UROW>(m, g.nh), j = m - b * g.nh;
         const long long i0 = (long long)a * g.rowlen + m;
 #pragma unroll
@@ -324,8 +338,17 @@ __global__ void __launch_bounds__(kBlock) k_residual(Geo g, const T* __restrict_
     });
     if (partial) {
         acc = block_sum(acc);
-        if (threadIdx.x == 0) partial[xcd_block()] = acc;
+        if (threadIdx.x == 0) partial[bk.L] = acc;
     }
+}
+
+template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_residual(Geo g, const T* __restrict__ G, long long gk,
+                                                     int bpa, const T* __restrict__ bv,
+                                                     const T* __restrict__ x, T* __restrict__ r,
+                                                     double* __restrict__ partial)
+{
+    d_residual<T, MODE, AXI, UROW, LTAG>(self_blk(), g, G, gk, bpa, bv, x, r, partial);
 }
 
 // One Gauss-Seidel pass over the cells of one colour, in place:
@@ -339,12 +362,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(Geo g, const T* __restrict_
 // zero != 0 (two colours only): first pass from a zero iterate, the other
 // colour is neither read nor needed.
 template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
-__global__ void __launch_bounds__(kBlock) k_gs(Geo g, const T* __restrict__ G, long long gk,
+__device__ __forceinline__ void d_gs(Blk bk, Geo g, const T* __restrict__ G, long long gk,
                                                int bpa, const T* __restrict__ bv,
                                                T* __restrict__ x, int colour, int ncol, int zero)
 {
     const int rowlen = ncol == 2 ? g.rowlen : g.rowlen / 2;
-    for_units(rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
+    for_units(bk, rowlen, bpa, (long long)g.nr * bpa, [&](int a, int m) {
         const int bb = row_of<UROW>(m, g.nh), j = m - bb * g.nh;
         int b, s;
         if (ncol == 2) {
@@ -361,6 +384,14 @@ __global__ void __launch_bounds__(kBlock) k_gs(Geo g, const T* __restrict__ G, l
         const long long id = s * g.P + ((long long)a * g.nt + b) * g.nh + j;
         x[id] = (bv[id] - S) / D;
     });
+}
+
+template <typename T, int MODE, bool AXI, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_gs(Geo g, const T* __restrict__ G, long long gk,
+                                               int bpa, const T* __restrict__ bv,
+                                               T* __restrict__ x, int colour, int ncol, int zero)
+{
+    d_gs<T, MODE, AXI, UROW, LTAG>(self_blk(), g, G, gk, bpa, bv, x, colour, ncol, zero);
 }
 
 // ---------------------------------------------------------------------------
@@ -381,9 +412,9 @@ struct March {
 };
 
 template <bool UROW>
-__device__ __forceinline__ bool march_pos(const Geo& g, int bpa, int ch, March& p)
+__device__ __forceinline__ bool march_pos(Blk bk, const Geo& g, int bpa, int ch, March& p)
 {
-    const int L = (int)xcd_block();
+    const int L = (int)bk.L;
     const int chunk = L / bpa;
     p.unit = L - chunk * bpa;
     p.m = p.unit * kBlock + (int)threadIdx.x;
@@ -403,12 +434,12 @@ __device__ __forceinline__ bool march_pos(const Geo& g, int bpa, int ch, March& 
 // zero != 0: first pass from a zero iterate (the other colour is taken as 0
 // and not read; it need not be initialised), x = b / D.
 template <typename T, bool UROW, int LTAG>
-__global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict__ G, long long gk,
+__device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ G, long long gk,
                                                      int bpa, int ch, const T* __restrict__ bv,
                                                      T* __restrict__ x, int colour, int zero)
 {
     March p;
-    if (!march_pos<UROW>(g, bpa, ch, p)) return;
+    if (!march_pos<UROW>(bk, g, bpa, ch, p)) return;
     if (zero) {
         for (int a = p.a0; a < p.a1; ++a) {
             const int s = (colour + a + p.b) & 1;
@@ -455,6 +486,14 @@ __global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict_
     }
 }
 
+template <typename T, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict__ G, long long gk,
+                                                     int bpa, int ch, const T* __restrict__ bv,
+                                                     T* __restrict__ x, int colour, int zero)
+{
+    d_gs_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero);
+}
+
 // Flux-form (A x) of the two cells (a, b, 2j) and (a, b, 2j+1) given the
 // column values at a-1, a, a+1 (u = plane 0, v = plane 1).
 template <typename T, typename Ld>
@@ -484,7 +523,7 @@ __device__ __forceinline__ void march_apply2(const Geo& g, const T* __restrict__
 
 // r = b - A x (and partial sums of r^2), marching.
 template <typename T, bool UROW, int LTAG>
-__global__ void __launch_bounds__(kBlock) k_residual_march(Geo g, const T* __restrict__ G,
+__device__ __forceinline__ void d_residual_march(Blk bk, Geo g, const T* __restrict__ G,
                                                            long long gk, int bpa, int ch,
                                                            const T* __restrict__ bv,
                                                            const T* __restrict__ x,
@@ -493,7 +532,7 @@ __global__ void __launch_bounds__(kBlock) k_residual_march(Geo g, const T* __res
 {
     March p;
     double acc = 0.0;
-    if (march_pos<UROW>(g, bpa, ch, p)) {
+    if (march_pos<UROW>(bk, g, bpa, ch, p)) {
         const long long sr = g.rowlen;
         auto col = [&](int a, int s, T own) -> T {
             return (a < 0 || a >= g.nr) ? own : x[s * g.P + (long long)a * sr + p.m];
@@ -514,13 +553,24 @@ __global__ void __launch_bounds__(kBlock) k_residual_march(Geo g, const T* __res
     }
     if (partial) {
         acc = block_sum(acc);
-        if (threadIdx.x == 0) partial[xcd_block()] = acc;
+        if (threadIdx.x == 0) partial[bk.L] = acc;
     }
+}
+
+template <typename T, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_residual_march(Geo g, const T* __restrict__ G,
+                                                           long long gk, int bpa, int ch,
+                                                           const T* __restrict__ bv,
+                                                           const T* __restrict__ x,
+                                                           T* __restrict__ r,
+                                                           double* __restrict__ partial)
+{
+    d_residual_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, r, partial);
 }
 
 // y = A x (and partial sums of y . dotv), marching.
 template <typename T, bool UROW, int LTAG>
-__global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restrict__ G,
+__device__ __forceinline__ void d_apply_march(Blk bk, Geo g, const T* __restrict__ G,
                                                         long long gk, int bpa, int ch,
                                                         const T* __restrict__ x,
                                                         T* __restrict__ y,
@@ -529,7 +579,7 @@ __global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restri
 {
     March p;
     double acc = 0.0;
-    if (march_pos<UROW>(g, bpa, ch, p)) {
+    if (march_pos<UROW>(bk, g, bpa, ch, p)) {
         const long long sr = g.rowlen;
         auto col = [&](int a, int s, T own) -> T {
             return (a < 0 || a >= g.nr) ? own : x[s * g.P + (long long)a * sr + p.m];
@@ -549,8 +599,19 @@ __global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restri
     }
     if (partial) {
         acc = block_sum(acc);
-        if (threadIdx.x == 0) partial[xcd_block()] = acc;
+        if (threadIdx.x == 0) partial[bk.L] = acc;
     }
+}
+
+template <typename T, bool UROW, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restrict__ G,
+                                                        long long gk, int bpa, int ch,
+                                                        const T* __restrict__ x,
+                                                        T* __restrict__ y,
+                                                        double* __restrict__ partial,
+                                                        const T* __restrict__ dotv)
+{
+    d_apply_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, x, y, partial, dotv);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,9 +633,9 @@ struct CoarseCol {
     int I0, I1, m, J, jc;
 };
 
-__device__ __forceinline__ bool coarse_col(const Geo& c, int bpa, int ch, CoarseCol& p)
+__device__ __forceinline__ bool coarse_col(Blk bk, const Geo& c, int bpa, int ch, CoarseCol& p)
 {
-    const int L = (int)xcd_block();
+    const int L = (int)bk.L;
     const int chunk = L / bpa;
     p.m = (L - chunk * bpa) * kBlock + (int)threadIdx.x;
     p.I0 = chunk * ch;
@@ -587,12 +648,12 @@ __device__ __forceinline__ bool coarse_col(const Geo& c, int bpa, int ch, Coarse
 
 // bc = R r (full weighting; interior rows sum to 8).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa, int ch,
+__device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch,
                                                      const T* __restrict__ r,
                                                      T* __restrict__ bc)
 {
     CoarseCol p;
-    if (!coarse_col(c, bpa, ch, p)) return;
+    if (!coarse_col(bk, c, bpa, ch, p)) return;
     const T w0 = T(0.25), w1 = T(0.75);
     long long rowo[4];
     for (int q = 0; q < 4; ++q) rowo[q] = (long long)clampi(2 * p.J - 1 + q, f.nt - 1) * f.nh;
@@ -631,15 +692,23 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa, int 
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa, int ch,
+                                                     const T* __restrict__ r,
+                                                     T* __restrict__ bc)
+{
+    d_restrict<T>(self_blk(), f, c, bpa, ch, r, bc);
+}
+
 // x += P e (trilinear); the thread writes fine rows 2J, 2J+1 and fine phi
 // 4jc .. 4jc+3 on the two fine planes of every coarse plane of its chunk.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong(Geo f, Geo c, int bpa, int ch,
+__device__ __forceinline__ void d_prolong(Blk bk, Geo f, Geo c, int bpa, int ch,
                                                     const T* __restrict__ e,
                                                     T* __restrict__ x)
 {
     CoarseCol p;
-    if (!coarse_col(c, bpa, ch, p)) return;
+    if (!coarse_col(bk, c, bpa, ch, p)) return;
     const T w0 = T(0.75), w1 = T(0.25);
     long long crow[3]; // coarse rows J-1, J, J+1 (mirrored)
     for (int q = 0; q < 3; ++q) crow[q] = (long long)clampi(p.J - 1 + q, c.nt - 1) * c.nh;
@@ -698,14 +767,22 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Geo f, Geo c, int bpa, int c
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong(Geo f, Geo c, int bpa, int ch,
+                                                    const T* __restrict__ e,
+                                                    T* __restrict__ x)
+{
+    d_prolong<T>(self_blk(), f, c, bpa, ch, e, x);
+}
+
 // Natural [r][theta][phi] <-> parity-split order.  y_split = x_nat - *mean
 // (mean may be null), and the inverse.
 template <typename T, typename U>
-__global__ void __launch_bounds__(kBlock) k_to_split(Geo g, const T* __restrict__ x,
+__device__ __forceinline__ void d_to_split(Blk bk, Geo g, const T* __restrict__ x,
                                                      U* __restrict__ y, const double* __restrict__ sum)
 {
     const long long n = 2 * g.P;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double sub = sum ? *sum / (double)n : 0.0;
     const long long row = i / g.np;
@@ -714,16 +791,30 @@ __global__ void __launch_bounds__(kBlock) k_to_split(Geo g, const T* __restrict_
 }
 
 template <typename T, typename U>
-__global__ void __launch_bounds__(kBlock) k_from_split(Geo g, const T* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_to_split(Geo g, const T* __restrict__ x,
+                                                     U* __restrict__ y, const double* __restrict__ sum)
+{
+    d_to_split<T, U>(self_blk(), g, x, y, sum);
+}
+
+template <typename T, typename U>
+__device__ __forceinline__ void d_from_split(Blk bk, Geo g, const T* __restrict__ x,
                                                        U* __restrict__ y, const double* __restrict__ sum)
 {
     const long long n = 2 * g.P;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double sub = sum ? *sum / (double)n : 0.0;
     const long long row = i / g.np;
     const int c = (int)(i - row * g.np);
     y[i] = (U)((double)x[(c & 1) * g.P + row * g.nh + (c >> 1)] - sub);
+}
+
+template <typename T, typename U>
+__global__ void __launch_bounds__(kBlock) k_from_split(Geo g, const T* __restrict__ x,
+                                                       U* __restrict__ y, const double* __restrict__ sum)
+{
+    d_from_split<T, U>(self_blk(), g, x, y, sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -732,7 +823,7 @@ __global__ void __launch_bounds__(kBlock) k_from_split(Geo g, const T* __restric
 // striding over the columns; every block recomputes the mean.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_coarse_gemv(int n, const double* __restrict__ Ainv,
+__device__ __forceinline__ void d_coarse_gemv(Blk bk, int n, const double* __restrict__ Ainv,
                                                         const T* __restrict__ bv,
                                                         T* __restrict__ e)
 {
@@ -744,13 +835,21 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gemv(int n, const double* __r
     __syncthreads();
     const double mu = smean;
     const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int row = bk.L * (kBlock / 64) + (threadIdx.x >> 6);
     if (row >= n) return;
     const double* Ar = Ainv + (long long)row * n;
     double acc = 0.0;
     for (int j = lane; j < n; j += 64) acc += Ar[j] * ((double)bv[j] - mu);
     acc = wave_sum(acc);
     if (lane == 0) e[row] = (T)acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coarse_gemv(int n, const double* __restrict__ Ainv,
+                                                        const T* __restrict__ bv,
+                                                        T* __restrict__ e)
+{
+    d_coarse_gemv<T>(self_blk(), n, Ainv, bv, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -762,16 +861,24 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gemv(int n, const double* __r
 
 // partial sums of u.v (or of u alone when v == nullptr)
 template <typename T, typename U>
-__global__ void __launch_bounds__(kBlock) k_dot(long long n, const T* __restrict__ u,
+__device__ __forceinline__ void d_dot(Blk bk, long long n, const T* __restrict__ u,
                                                 const U* __restrict__ v,
                                                 double* __restrict__ partial)
 {
     double acc = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    const long long stride = (long long)bk.G * blockDim.x;
+    for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride)
         acc += v ? (double)u[i] * (double)v[i] : (double)u[i];
     acc = block_sum(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    if (threadIdx.x == 0) partial[bk.L] = acc;
+}
+
+template <typename T, typename U>
+__global__ void __launch_bounds__(kBlock) k_dot(long long n, const T* __restrict__ u,
+                                                const U* __restrict__ v,
+                                                double* __restrict__ partial)
+{
+    d_dot<T, U>(self_blk(), n, u, v, partial);
 }
 
 // y = x - (*sum)/n  (mean removal; *sum is a device scalar)
@@ -785,41 +892,70 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(long long n, const double* 
 
 // y = (U) (x * s) with s = sc[slot] or 1 / sc[slot] (a device scalar)
 template <typename T, typename U>
-__global__ void __launch_bounds__(kBlock) k_cast(long long n, const T* __restrict__ x,
+__device__ __forceinline__ void d_cast(Blk bk, long long n, const T* __restrict__ x,
                                                  U* __restrict__ y, const double* __restrict__ sc,
                                                  int slot, int invert)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
     const double s = invert ? 1.0 / sc[slot] : sc[slot];
     if (i < n) y[i] = (U)((double)x[i] * s);
 }
 
+template <typename T, typename U>
+__global__ void __launch_bounds__(kBlock) k_cast(long long n, const T* __restrict__ x,
+                                                 U* __restrict__ y, const double* __restrict__ sc,
+                                                 int slot, int invert)
+{
+    d_cast<T, U>(self_blk(), n, x, y, sc, slot, invert);
+}
+
 // x[i] = v
+template <typename T>
+__device__ __forceinline__ void d_fill(Blk bk, long long n, T* __restrict__ x, T v)
+{
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fill(long long n, T* __restrict__ x, T v)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = v;
+    d_fill<T>(self_blk(), n, x, v);
 }
 
 // y[i] = x[i]
 template <typename T>
+__device__ __forceinline__ void d_copy(Blk bk, long long n, const T* __restrict__ x,
+                                                 T* __restrict__ y)
+{
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_copy(long long n, const T* __restrict__ x,
                                                  T* __restrict__ y)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = x[i];
+    d_copy<T>(self_blk(), n, x, y);
 }
 
 // x += s * (double) e   (iterative-refinement update, s a device scalar
 // holding the norm the residual was divided by)
 template <typename U>
+__device__ __forceinline__ void d_ir_update(Blk bk, long long n, double* __restrict__ x,
+                                                      const U* __restrict__ e,
+                                                      const double* __restrict__ s)
+{
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += *s * (double)e[i];
+}
+
+template <typename U>
 __global__ void __launch_bounds__(kBlock) k_ir_update(long long n, double* __restrict__ x,
                                                       const U* __restrict__ e,
                                                       const double* __restrict__ s)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] += *s * (double)e[i];
+    d_ir_update<U>(self_blk(), n, x, e, s);
 }
 
 // Scalar recurrences of the Krylov solvers, evaluated by one thread on
@@ -848,7 +984,7 @@ __global__ void k_set_scalar(double* sc, int dst, double v) { sc[dst] = v; }
 __global__ void k_sqrt_scalar(double* sc, int dst, int src) { sc[dst] = sqrt(sc[src]); }
 
 // x += alpha p ; r -= alpha q ; partial sums of r^2   (CG step)
-__global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* __restrict__ sc,
+__device__ __forceinline__ void d_cg_step(Blk bk, long long n, const double* __restrict__ sc,
                                                     double* __restrict__ x,
                                                     double* __restrict__ r,
                                                     const double* __restrict__ p,
@@ -857,48 +993,81 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* _
 {
     const double al = sc[S_ALPHA];
     double acc = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const long long stride = (long long)bk.G * blockDim.x;
+    for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride) {
         x[i] += al * p[i];
         const double v = r[i] - al * q[i];
         r[i] = v;
         acc += v * v;
     }
     acc = block_sum(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    if (threadIdx.x == 0) partial[bk.L] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* __restrict__ sc,
+                                                    double* __restrict__ x,
+                                                    double* __restrict__ r,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ q,
+                                                    double* __restrict__ partial)
+{
+    d_cg_step(self_blk(), n, sc, x, r, p, q, partial);
 }
 
 // p = z + beta p
+__device__ __forceinline__ void d_cg_dir(Blk bk, long long n, const double* __restrict__ sc,
+                                                   const double* __restrict__ z,
+                                                   double* __restrict__ p)
+{
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + sc[S_BETA] * p[i];
+}
+
 __global__ void __launch_bounds__(kBlock) k_cg_dir(long long n, const double* __restrict__ sc,
                                                    const double* __restrict__ z,
                                                    double* __restrict__ p)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = z[i] + sc[S_BETA] * p[i];
+    d_cg_dir(self_blk(), n, sc, z, p);
 }
 
 // BiCGStab: p = r + beta (p - omega v)
+__device__ __forceinline__ void d_bicg_dir(Blk bk, long long n, const double* __restrict__ sc,
+                                                     const double* __restrict__ r,
+                                                     const double* __restrict__ v,
+                                                     double* __restrict__ p)
+{
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = r[i] + sc[S_BETA] * (p[i] - sc[S_OMEGA] * v[i]);
+}
+
 __global__ void __launch_bounds__(kBlock) k_bicg_dir(long long n, const double* __restrict__ sc,
                                                      const double* __restrict__ r,
                                                      const double* __restrict__ v,
                                                      double* __restrict__ p)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = r[i] + sc[S_BETA] * (p[i] - sc[S_OMEGA] * v[i]);
+    d_bicg_dir(self_blk(), n, sc, r, v, p);
 }
 
 // BiCGStab: s = r - alpha v (into s)
+__device__ __forceinline__ void d_bicg_s(Blk bk, long long n, const double* __restrict__ sc,
+                                                   const double* __restrict__ r,
+                                                   const double* __restrict__ v,
+                                                   double* __restrict__ s)
+{
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
+    if (i < n) s[i] = r[i] - sc[S_ALPHA] * v[i];
+}
+
 __global__ void __launch_bounds__(kBlock) k_bicg_s(long long n, const double* __restrict__ sc,
                                                    const double* __restrict__ r,
                                                    const double* __restrict__ v,
                                                    double* __restrict__ s)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) s[i] = r[i] - sc[S_ALPHA] * v[i];
+    d_bicg_s(self_blk(), n, sc, r, v, s);
 }
 
 // BiCGStab: x += alpha ph + omega sh ; r = s - omega t ; partial r^2
-__global__ void __launch_bounds__(kBlock) k_bicg_step(long long n, const double* __restrict__ sc,
+__device__ __forceinline__ void d_bicg_step(Blk bk, long long n, const double* __restrict__ sc,
                                                       double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       const double* __restrict__ ph,
@@ -908,15 +1077,351 @@ __global__ void __launch_bounds__(kBlock) k_bicg_step(long long n, const double*
                                                       double* __restrict__ partial)
 {
     double acc = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const long long stride = (long long)bk.G * blockDim.x;
+    for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride) {
         x[i] += sc[S_ALPHA] * ph[i] + sc[S_OMEGA] * sh[i];
         const double v = s[i] - sc[S_OMEGA] * t[i];
         r[i] = v;
         acc += v * v;
     }
     acc = block_sum(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    if (threadIdx.x == 0) partial[bk.L] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_bicg_step(long long n, const double* __restrict__ sc,
+                                                      double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ ph,
+                                                      const double* __restrict__ sh,
+                                                      const double* __restrict__ s,
+                                                      const double* __restrict__ t,
+                                                      double* __restrict__ partial)
+{
+    d_bicg_step(self_blk(), n, sc, x, r, ph, sh, s, t, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Launch shapes, shared by host and device so that a batched launch gives
+// each problem exactly the blocks (and reduction order) of its own launch.
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxLevels = 16;
+
+__host__ __device__ inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+struct MarchShape {
+    int bpa, ch, grid;
+};
+
+// Marching launch over the planes of g: bpa blocks per plane, chunks of ch
+// planes; ch <= 0 picks chunks that give about 2048 blocks (one resident
+// wave of 8 blocks per CU).
+__host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
+{
+    const int bpa = cdiv(g.rowlen, kBlock);
+    if (ch <= 0) {
+        int nchunks = cdiv(2048, bpa);
+        nchunks = nchunks < 1 ? 1 : (nchunks > g.nr ? g.nr : nchunks);
+        ch = cdiv(g.nr, nchunks);
+    }
+    if (ch > g.nr) ch = g.nr;
+    return MarchShape{bpa, ch, bpa * cdiv(g.nr, ch)};
+}
+
+// blocks per plane of the generic colour pass and of generic stencil kernels
+__host__ __device__ inline int gs_bpa(const Geo& g, int ncol)
+{
+    return cdiv(ncol == 2 ? g.rowlen : g.rowlen / 2, kBlock);
+}
+__host__ __device__ inline int capped_grid(long long blocks)
+{
+    return blocks < kMaxGrid ? (int)blocks : kMaxGrid;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches.  A work table lists, for every block of the launch, the
+// problem it serves and its logical index L among the G blocks that the
+// problem's own launch would have; the block then runs the same kernel body
+// on that problem's data, read from a per-problem descriptor.  Blocks of
+// problems marked inactive (converged) return at once.
+// ---------------------------------------------------------------------------
+
+struct BItem {
+    int prob;
+    unsigned L, G;
+};
+
+// finest-level FP64 vectors of a problem, by id
+enum VecId {
+    V_X = 0, V_B0, V_R, V_Z, V_P, V_Q, V_R0, V_V, V_S, V_T, V_PH, V_SH, V_RHS, V_OUT, V_COUNT
+};
+
+template <typename T>
+struct LDesc {
+    Geo g;
+    const T* G;
+    long long gk;
+    T *x, *b, *r;
+    int gs_ch; // marching chunk of the colour pass (autotuned)
+};
+
+template <typename T>
+struct PDesc {
+    int L, nc, ncol, pad;
+    const double* Ainv;
+    const double* G64; // finest-level FP64 metrics
+    long long gk64;
+    long long parts_apply, parts_vec; // partial sums left by apply / vector reductions
+    double* vec[V_COUNT];
+    double* sc;
+    double* partial;
+    LDesc<T> lv[kMaxLevels];
+};
+
+#define CPS_BATCH_BLOCK                                                                    \
+    const BItem it = items[blockIdx.x];                                                    \
+    if (!active[it.prob]) return;                                                          \
+    const Blk bk{it.L, it.G};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_gs_march(const BItem* __restrict__ items,
+                                                      const int* __restrict__ active,
+                                                      const PDesc<T>* __restrict__ pd, int level,
+                                                      int colour, int zero)
+{
+    CPS_BATCH_BLOCK
+    const LDesc<T>& d = pd[it.prob].lv[level];
+    const MarchShape ms = march_shape(d.g, d.gs_ch);
+    if (d.g.nh % 64 == 0)
+        d_gs_march<T, true, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, colour, zero);
+    else
+        d_gs_march<T, false, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, colour, zero);
+}
+
+template <typename T, int MODE, bool AXI>
+__global__ void __launch_bounds__(kBlock) kb_gs(const BItem* __restrict__ items,
+                                                const int* __restrict__ active,
+                                                const PDesc<T>* __restrict__ pd, int level,
+                                                int colour, int zero)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    const LDesc<T>& d = P.lv[level];
+    const int bpa = gs_bpa(d.g, P.ncol);
+    if (d.g.nh % 64 == 0)
+        d_gs<T, MODE, AXI, true, 1>(bk, d.g, d.G, d.gk, bpa, d.b, d.x, colour, P.ncol, zero);
+    else
+        d_gs<T, MODE, AXI, false, 1>(bk, d.g, d.G, d.gk, bpa, d.b, d.x, colour, P.ncol, zero);
+}
+
+// r = b - A x on a level (no norm), marching (7-point, phi-invariant) or generic
+template <typename T, int MODE, bool AXI>
+__global__ void __launch_bounds__(kBlock) kb_residual(const BItem* __restrict__ items,
+                                                      const int* __restrict__ active,
+                                                      const PDesc<T>* __restrict__ pd, int level)
+{
+    CPS_BATCH_BLOCK
+    const LDesc<T>& d = pd[it.prob].lv[level];
+    const bool u = d.g.nh % 64 == 0;
+    if constexpr (MODE == MODE_ORTHO && AXI) {
+        const MarchShape ms = march_shape(d.g);
+        if (u) d_residual_march<T, true, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
+        else d_residual_march<T, false, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
+    } else {
+        const int bpa = cdiv(d.g.rowlen, kBlock);
+        if (u) d_residual<T, MODE, AXI, true, 1>(bk, d.g, d.G, d.gk, bpa, d.b, d.x, d.r, nullptr);
+        else d_residual<T, MODE, AXI, false, 1>(bk, d.g, d.G, d.gk, bpa, d.b, d.x, d.r, nullptr);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_restrict(const BItem* __restrict__ items,
+                                                      const int* __restrict__ active,
+                                                      const PDesc<T>* __restrict__ pd, int level)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    const MarchShape ms = march_shape(P.lv[level + 1].g);
+    d_restrict<T>(bk, P.lv[level].g, P.lv[level + 1].g, ms.bpa, ms.ch, P.lv[level].r,
+                  P.lv[level + 1].b);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_prolong(const BItem* __restrict__ items,
+                                                     const int* __restrict__ active,
+                                                     const PDesc<T>* __restrict__ pd, int level)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    const MarchShape ms = march_shape(P.lv[level + 1].g);
+    d_prolong<T>(bk, P.lv[level].g, P.lv[level + 1].g, ms.bpa, ms.ch, P.lv[level + 1].x,
+                 P.lv[level].x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_fill_level(const BItem* __restrict__ items,
+                                                        const int* __restrict__ active,
+                                                        const PDesc<T>* __restrict__ pd, int level)
+{
+    CPS_BATCH_BLOCK
+    const LDesc<T>& d = pd[it.prob].lv[level];
+    d_fill<T>(bk, 2 * d.g.P, d.x, T(0));
+}
+
+// coarsest level of each problem (its own level count)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_coarse(const BItem* __restrict__ items,
+                                                    const int* __restrict__ active,
+                                                    const PDesc<T>* __restrict__ pd)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    const LDesc<T>& d = P.lv[P.L - 1];
+    d_coarse_gemv<T>(bk, P.nc, P.Ainv, d.b, d.x);
+}
+
+// finest-level vector in (FP64) -> level-0 b of the V-cycle / level-0 x -> out
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_cast_in(const BItem* __restrict__ items,
+                                                     const int* __restrict__ active,
+                                                     const PDesc<T>* __restrict__ pd, int in)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    d_cast<double, T>(bk, 2 * P.lv[0].g.P, P.vec[in], P.lv[0].b, P.sc, S_SCALE, 1);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_cast_out(const BItem* __restrict__ items,
+                                                      const int* __restrict__ active,
+                                                      const PDesc<T>* __restrict__ pd, int out)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    d_cast<T, double>(bk, 2 * P.lv[0].g.P, P.lv[0].x, P.vec[out], P.sc, S_SCALE, 0);
+}
+
+// y = A x at the finest level in FP64, with partial sums of y . vec[dot]
+template <typename T, int MODE, bool AXI>
+__global__ void __launch_bounds__(kBlock) kb_apply64(const BItem* __restrict__ items,
+                                                     const int* __restrict__ active,
+                                                     const PDesc<T>* __restrict__ pd, int in,
+                                                     int out, int dot)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    const Geo& g = P.lv[0].g;
+    const bool u = g.nh % 64 == 0;
+    const double* dv = dot >= 0 ? P.vec[dot] : nullptr;
+    if constexpr (MODE == MODE_ORTHO && AXI) {
+        const MarchShape ms = march_shape(g);
+        if (u) d_apply_march<double, true, 0>(bk, g, P.G64, P.gk64, ms.bpa, ms.ch, P.vec[in], P.vec[out], P.partial, dv);
+        else d_apply_march<double, false, 0>(bk, g, P.G64, P.gk64, ms.bpa, ms.ch, P.vec[in], P.vec[out], P.partial, dv);
+    } else {
+        const int bpa = cdiv(g.rowlen, kBlock);
+        if (u) d_apply<double, MODE, AXI, true, 0>(bk, g, P.G64, P.gk64, bpa, P.vec[in], P.vec[out], P.partial, dv);
+        else d_apply<double, MODE, AXI, false, 0>(bk, g, P.G64, P.gk64, bpa, P.vec[in], P.vec[out], P.partial, dv);
+    }
+}
+
+// partial sums of vec[u] . vec[v] (v < 0: of vec[u])
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_dot(const BItem* __restrict__ items,
+                                                 const int* __restrict__ active,
+                                                 const PDesc<T>* __restrict__ pd, int u, int v)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    d_dot<double, double>(bk, 2 * P.lv[0].g.P, P.vec[u], v >= 0 ? P.vec[v] : nullptr, P.partial);
+}
+
+// sc[slot] = sum of the problem's partial sums (one block per problem);
+// apply != 0: the partials of kb_apply64, else of a vector reduction
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_reduce(const int* __restrict__ active,
+                                                    const PDesc<T>* __restrict__ pd, int apply,
+                                                    int slot)
+{
+    if (!active[blockIdx.x]) return;
+    const PDesc<T>& P = pd[blockIdx.x];
+    d_reduce(Blk{0, 1}, P.partial, apply ? P.parts_apply : P.parts_vec, P.sc + slot);
+}
+
+enum { SOP_CG_ALPHA = 0, SOP_CG_BETA, SOP_FCG_BETA, SOP_BICG_BETA, SOP_BICG_ALPHA, SOP_BICG_OMEGA,
+       SOP_COPY, SOP_SQRT, SOP_SET };
+
+// scalar recurrences, one thread per problem (same formulas as k_cg_* etc.)
+template <typename T>
+__global__ void kb_scalar(const int* __restrict__ active, const PDesc<T>* __restrict__ pd, int nprob,
+                          int op, int dst, int src, double value)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob || !active[p]) return;
+    double* sc = pd[p].sc;
+    switch (op) {
+    case SOP_CG_ALPHA: sc[S_ALPHA] = sc[S_RZ] / sc[S_PQ]; break;
+    case SOP_CG_BETA: sc[S_BETA] = sc[S_RZ] / sc[S_RZ_OLD]; break;
+    case SOP_FCG_BETA: sc[S_BETA] = -sc[S_ALPHA] * sc[S_ZQ] / sc[S_RZ_OLD]; break;
+    case SOP_BICG_BETA: sc[S_BETA] = (sc[S_RHO] / sc[S_RHO_OLD]) * (sc[S_ALPHA] / sc[S_OMEGA]); break;
+    case SOP_BICG_ALPHA: sc[S_ALPHA] = sc[S_RHO] / sc[S_R0V]; break;
+    case SOP_BICG_OMEGA: sc[S_OMEGA] = sc[S_TS] / sc[S_TT]; break;
+    case SOP_COPY: sc[dst] = sc[src]; break;
+    case SOP_SQRT: sc[dst] = sqrt(sc[src]); break;
+    default: sc[dst] = value; break;
+    }
+}
+
+// out[p] = sc[slot] of problem p (all problems, active or not)
+template <typename T>
+__global__ void kb_gather(const PDesc<T>* __restrict__ pd, int nprob, int slot, double* __restrict__ out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) out[p] = pd[p].sc[slot];
+}
+
+// element-wise finest-level operations
+enum { EOP_FILL = 0, EOP_COPY, EOP_CG_DIR, EOP_BICG_DIR, EOP_BICG_S, EOP_TO_SPLIT, EOP_FROM_SPLIT };
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_elem(const BItem* __restrict__ items,
+                                                  const int* __restrict__ active,
+                                                  const PDesc<T>* __restrict__ pd, int op, int a,
+                                                  int b, int c)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    const Geo& g = P.lv[0].g;
+    const long long n = 2 * g.P;
+    switch (op) {
+    case EOP_FILL: d_fill<double>(bk, n, P.vec[a], 0.0); break;
+    case EOP_COPY: d_copy<double>(bk, n, P.vec[a], P.vec[b]); break;
+    case EOP_CG_DIR: d_cg_dir(bk, n, P.sc, P.vec[a], P.vec[b]); break;
+    case EOP_BICG_DIR: d_bicg_dir(bk, n, P.sc, P.vec[a], P.vec[b], P.vec[c]); break;
+    case EOP_BICG_S: d_bicg_s(bk, n, P.sc, P.vec[a], P.vec[b], P.vec[c]); break;
+    case EOP_TO_SPLIT: d_to_split<double, double>(bk, g, P.vec[a], P.vec[b], c >= 0 ? P.sc + c : nullptr); break;
+    default: d_from_split<double, double>(bk, g, P.vec[a], P.vec[b], c >= 0 ? P.sc + c : nullptr); break;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_cg_step(const BItem* __restrict__ items,
+                                                     const int* __restrict__ active,
+                                                     const PDesc<T>* __restrict__ pd)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    d_cg_step(bk, 2 * P.lv[0].g.P, P.sc, P.vec[V_X], P.vec[V_R], P.vec[V_P], P.vec[V_Q], P.partial);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_bicg_step(const BItem* __restrict__ items,
+                                                       const int* __restrict__ active,
+                                                       const PDesc<T>* __restrict__ pd)
+{
+    CPS_BATCH_BLOCK
+    const PDesc<T>& P = pd[it.prob];
+    d_bicg_step(bk, 2 * P.lv[0].g.P, P.sc, P.vec[V_X], P.vec[V_R], P.vec[V_PH], P.vec[V_SH],
+                P.vec[V_S], P.vec[V_T], P.partial);
 }
 
 // ---------------------------------------------------------------------------

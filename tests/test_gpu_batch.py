@@ -1,0 +1,89 @@
+"""Batched form: uneven-size problems (7-point spherical shells and 11-point
+oblate shells) solved together in one launch per phase.  Each result must
+equal the same problem solved alone by cps_solve (FP32 V-cycles inside FP64
+refinement), bit for bit, and the oracle's exact solution to 1e-9."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import direct
+from paper_2305_17875_amd import cps, inputs
+from paper_2305_17875_amd.inputs import Shell, MAP_OBLATE
+from gpu_util import needs_gpu, log, dev, host, rel, torch
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+GRIDS = [
+    Shell(16, 16, 16),
+    Shell(32, 32, 64, map=MAP_OBLATE, flattening=0.1),
+    Shell(16, 16, 32, radial_stretch=2.0),
+    Shell(24, 20, 28, map=MAP_OBLATE, flattening=0.15),
+    Shell(32, 32, 32),
+    Shell(16, 16, 16, map=MAP_OBLATE, flattening=0.05),
+    Shell(32, 32, 64, radial_stretch=2.0),
+]
+
+
+def rhs_of(i, g):
+    return inputs.smoothed_noise(g.shape, seed=100 + i)
+
+
+def alone(g, b):
+    s = cps.Solver(g, precision=1, accel=1)
+    try:
+        r = s.solve(dev(b).flatten())
+        return host(r.p).reshape(g.shape), r
+    finally:
+        s.close()
+
+
+def test_batch_equals_alone_and_oracle():
+    log("batch", len(GRIDS))
+    rhs = [rhs_of(i, g) for i, g in enumerate(GRIDS)]
+    rhs[5] = np.zeros(GRIDS[5].shape)  # a problem that needs no iteration
+    B = cps.Batch(GRIDS)
+    try:
+        st, p, infos = B.solve([dev(b).flatten() for b in rhs])
+        xs = [host(t).reshape(g.shape) for t, g in zip(p, GRIDS)]
+        # a second solve on the same batch gives the same bits
+        st2, p2, _ = B.solve([dev(b).flatten() for b in rhs])
+        for t1, t2 in zip(p, p2):
+            assert np.array_equal(host(t1), host(t2))
+    finally:
+        B.close()
+    assert st == cps.CPS_OK
+    for i, (g, b, x, info) in enumerate(zip(GRIDS, rhs, xs, infos)):
+        xa, ra = alone(g, b)
+        assert info.iterations == ra.iterations, i
+        assert np.array_equal(x, xa), (i, np.abs(x - xa).max())
+        if i == 5:
+            assert info.iterations == 0 and not x.any()
+            continue
+        G = O.face_metrics(g)
+        want = direct.solve_axisym(G, b)
+        assert rel(x, want) <= 1e-9, (i, rel(x, want))
+
+
+def test_batch_retires_diverged_and_capped_problems():
+    log("batch errors")
+    grids = [Shell(16, 16, 16), Shell(16, 16, 32), Shell(16, 16, 16, map=MAP_OBLATE, flattening=0.1)]
+    rhs = [rhs_of(i, g) for i, g in enumerate(grids)]
+    rhs[1][2, 3, 4] = np.nan
+    B = cps.Batch(grids)
+    try:
+        st, p, infos = B.solve([dev(b).flatten() for b in rhs])
+    finally:
+        B.close()
+    assert st == cps.CPS_E_DIVERGED
+    assert infos[0].iterations > 0 and infos[0].rel_residual <= 1e-10
+    assert infos[2].iterations > 0 and infos[2].rel_residual <= 1e-10
+    x0, _ = alone(grids[0], rhs[0])
+    assert np.array_equal(host(p[0]).reshape(grids[0].shape), x0)
+    B = cps.Batch(grids[:1], max_iters=1)
+    try:
+        st, p, infos = B.solve([dev(rhs[0]).flatten()])
+    finally:
+        B.close()
+    assert st == cps.CPS_E_NOT_CONVERGED and infos[0].iterations == 1
+    with pytest.raises(cps.CpsError):
+        cps.Batch([Shell(34, 34, 34)])
