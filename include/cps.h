@@ -87,6 +87,12 @@ typedef struct {
                           acceleration with the V-cycle as preconditioner
                           (conjugate gradients for symmetric operators,
                           BiCGStab when cross metrics make A non-symmetric) */
+    int32_t tune;      /* smoother tile shapes (marching chunk per level shape):
+                          0 use the cached choice if any; 1 time the shapes not
+                          yet cached at setup; 2 retime all.  Cache: the JSON
+                          file named by the environment variable CPS_TUNE_CACHE
+                          (unset: this process only).  Results do not depend
+                          on the choice. */
     void* stream;      /* hipStream_t the calls are ordered on; NULL = null stream */
 } cps_opts;
 
@@ -180,6 +186,55 @@ cps_status cps_batch_setup(int32_t n, const cps_grid* grids, const cps_metrics* 
 cps_status cps_batch_solve(cps_batch* b, const double* const* rhs, double* const* p, double tol,
                            cps_info* infos);
 void cps_batch_destroy(cps_batch* b);
+
+/* ---- Solve service -----------------------------------------------------
+ * A stream of independent requests (any dims, maps and metrics) served by
+ * `max_slots` worker threads, each with its own HIP stream (default
+ * priority) on the device current at creation.  Requests are admitted first
+ * come, first served, while the device memory of the resident hierarchies
+ * plus the ones being built stays within `hbm_budget_bytes`.  A finished
+ * request leaves its hierarchy resident: a later request with the same dims
+ * and stencil class reuses it (recomputing metrics and coarse inverse when
+ * its map differs), and idle hierarchies are evicted least recently used
+ * first when a new one does not fit.  Every request runs exactly the code of
+ * cps_solve with the service's opts, so its p equals the same problem solved
+ * alone with cps_setup/cps_solve, bit for bit.  All functions are
+ * thread-safe; latency is measured from submission to completion. */
+typedef struct cps_service cps_service;
+
+typedef struct {
+    uint64_t submitted, completed, failed; /* failed: status other than CPS_OK */
+    uint64_t queued;                       /* waiting for admission now */
+    int32_t active, peak_active;           /* requests being solved */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency of completed requests */
+    double unknowns_per_s; /* cells solved / (last completion - first submission) */
+    uint64_t hbm_in_use, hbm_budget; /* bytes: resident plus reserved hierarchies */
+    uint64_t hierarchies_built, hierarchies_reused, map_rebuilds, evictions;
+} cps_service_report;
+
+/* opts: host, nullable; opts.stream must be NULL.  max_slots: 1..64.
+ * Errors: CPS_E_INVALID, CPS_E_HIP. */
+cps_status cps_service_create(size_t hbm_budget_bytes, int32_t max_slots, const cps_opts* opts,
+                              cps_service** out);
+/* Queue one solve of A p = rhs - mean(rhs) to relative residual tol.
+ * grid, metrics (nullable): host, read during the call; rhs_host: host FP64
+ * array of n_r*n_theta*n_phi elements, copied before the call returns.
+ * *ticket receives the request's id.  Grid errors are reported here. */
+cps_status cps_service_submit(cps_service* s, const cps_grid* grid, const cps_metrics* metrics,
+                              const double* rhs_host, double tol, uint64_t* ticket);
+/* Block until the request finishes; p_host (host, nullable) receives p,
+ * info (nullable) its cps_info.  Returns the request's status (CPS_E_OOM if
+ * it can never fit the budget); each ticket can be waited for once. */
+cps_status cps_service_wait(cps_service* s, uint64_t ticket, double* p_host, cps_info* info);
+/* *bytes = the device memory a request of this grid is admitted against
+ * with these opts (nullable): its hierarchy, two staging vectors and the
+ * transient buffers of the coarse inverse.  Host only; checks the grid. */
+cps_status cps_service_footprint(const cps_grid* grid, const cps_opts* opts, uint64_t* bytes);
+/* Snapshot of the counters and latency percentiles (host struct). */
+cps_status cps_service_stats(cps_service* s, cps_service_report* out);
+/* Stops the workers after their current requests, frees every hierarchy
+ * and every request not yet waited for.  No call may be in flight. */
+void cps_service_destroy(cps_service* s);
 
 /* ---- Measurement -------------------------------------------------------
  * Kernel classes timed on the finest level with HIP events recorded on the

@@ -40,12 +40,24 @@ class cps_metrics(ctypes.Structure):
 
 class cps_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32),
-                ("accel", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("accel", ctypes.c_int32), ("tune", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class cps_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("rhs_mean_removed", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class cps_service_report(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("active", ctypes.c_int32), ("peak_active", ctypes.c_int32),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("unknowns_per_s", ctypes.c_double),
+                ("hbm_in_use", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64),
+                ("hierarchies_built", ctypes.c_uint64), ("hierarchies_reused", ctypes.c_uint64),
+                ("map_rebuilds", ctypes.c_uint64), ("evictions", ctypes.c_uint64)]
 
 
 _lib = None
@@ -91,6 +103,18 @@ def lib():
         L.cps_batch_solve.restype = I
         L.cps_batch_destroy.argtypes = [P]
         L.cps_batch_destroy.restype = None
+        L.cps_service_create.argtypes = [ctypes.c_size_t, I, P, ctypes.POINTER(P)]
+        L.cps_service_create.restype = I
+        L.cps_service_submit.argtypes = [P, P, P, P, D, ctypes.POINTER(ctypes.c_uint64)]
+        L.cps_service_submit.restype = I
+        L.cps_service_wait.argtypes = [P, ctypes.c_uint64, P, P]
+        L.cps_service_wait.restype = I
+        L.cps_service_footprint.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint64)]
+        L.cps_service_footprint.restype = I
+        L.cps_service_stats.argtypes = [P, P]
+        L.cps_service_stats.restype = I
+        L.cps_service_destroy.argtypes = [P]
+        L.cps_service_destroy.restype = None
         L.cps_profile_enable.argtypes = [P, I]
         L.cps_profile_read.argtypes = [P, I, P, P]
         L.cps_debug_copy.argtypes = [P, P, ctypes.c_int64, P]
@@ -273,12 +297,13 @@ class Solver:
     """One hierarchy on the current device (owns a cps_handle)."""
 
     def __init__(self, grid, precision: int = 0, accel: int = 1, max_iters: int = 200,
-                 metrics: int = METRICS_MAP_CENTRAL, n_levels: int = 0, stream=None):
+                 metrics: int = METRICS_MAP_CENTRAL, n_levels: int = 0, stream=None,
+                 tune: int = 0):
         import torch
         self.shape = (grid.n_r, grid.n_theta, grid.n_phi)
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
-        opts = cps_opts(precision, max_iters, accel, ctypes.c_void_p(s.cuda_stream))
+        opts = cps_opts(precision, max_iters, accel, tune, ctypes.c_void_p(s.cuda_stream))
         self.h = cps_setup(make_grid(grid, n_levels), cps_metrics(metrics), opts)
         self.levels, self.ncolours, self.phi_invariant = cps_levels(self.h)
 
@@ -336,12 +361,12 @@ class Batch:
     """Many problems solved together (FP32 V-cycles inside FP64 refinement)."""
 
     def __init__(self, grids, max_iters: int = 200, metrics: int = METRICS_MAP_CENTRAL,
-                 stream=None):
+                 stream=None, tune: int = 0):
         import torch
         self.grids = list(grids)
         self.sizes = [g.n_r * g.n_theta * g.n_phi for g in self.grids]
         s = stream if stream is not None else torch.cuda.current_stream()
-        opts = cps_opts(1, max_iters, 1, ctypes.c_void_p(s.cuda_stream))
+        opts = cps_opts(1, max_iters, 1, tune, ctypes.c_void_p(s.cuda_stream))
         self.h = cps_batch_setup([make_grid(g) for g in self.grids], cps_metrics(metrics), opts)
 
     def solve(self, rhs_list, tol: float = 1e-10, out=None):
@@ -355,6 +380,101 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             cps_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- solve service (host arrays in and out) -------------------------------
+
+def cps_service_create(hbm_budget_bytes: int, max_slots: int, opts: cps_opts):
+    h = ctypes.c_void_p()
+    _check(lib().cps_service_create(hbm_budget_bytes, max_slots, ctypes.byref(opts),
+                                    ctypes.byref(h)))
+    return h
+
+
+def _host_f64(a, n, what):
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise ValueError(f"{what}: expected a C-contiguous float64 numpy array")
+    if a.size != n:
+        raise ValueError(f"{what}: {a.size} elements, expected {n}")
+    return a.ctypes.data
+
+
+def cps_service_submit(h, grid: cps_grid, metrics: cps_metrics, rhs, tol: float) -> int:
+    n = grid.n_r * grid.n_theta * grid.n_phi
+    t = ctypes.c_uint64()
+    _check(lib().cps_service_submit(h, ctypes.byref(grid), ctypes.byref(metrics),
+                                    _host_f64(rhs, n, "rhs"), tol, ctypes.byref(t)))
+    return t.value
+
+
+def cps_service_wait(h, ticket: int, p):
+    """Blocks (without the GIL) until the request ends; fills p (host).
+    Returns (status, cps_info); raises for argument and device errors."""
+    info = cps_info()
+    st = lib().cps_service_wait(h, ticket, p.ctypes.data if p is not None else None,
+                                ctypes.byref(info))
+    if st not in (CPS_OK, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED):
+        _check(st)
+    return st, info
+
+
+def cps_service_footprint(grid: cps_grid, opts: cps_opts) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().cps_service_footprint(ctypes.byref(grid), ctypes.byref(opts), ctypes.byref(b)))
+    return b.value
+
+
+def cps_service_stats(h) -> dict:
+    r = cps_service_report()
+    _check(lib().cps_service_stats(h, ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in cps_service_report._fields_}
+
+
+def cps_service_destroy(h):
+    if h:
+        lib().cps_service_destroy(h)
+
+
+class Service:
+    """Continuous solve service on the current device: submit() queues a
+    request and returns its ticket; wait() returns (status, p, info)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, precision: int = 1,
+                 accel: int = 1, max_iters: int = 200, tune: int = 0):
+        self.opts = cps_opts(precision, max_iters, accel, tune, None)
+        self.h = cps_service_create(int(hbm_budget_bytes), max_slots, self.opts)
+        self._shape = {}
+
+    def submit(self, grid, rhs, tol: float = 1e-10, metrics: int = METRICS_MAP_CENTRAL,
+               n_levels: int = 0) -> int:
+        t = cps_service_submit(self.h, make_grid(grid, n_levels), cps_metrics(metrics), rhs, tol)
+        self._shape[t] = rhs.shape
+        return t
+
+    def wait(self, ticket: int):
+        import numpy as np
+        shape = self._shape.pop(ticket)
+        p = np.empty(shape, dtype=np.float64)
+        st, info = cps_service_wait(self.h, ticket, p)
+        return st, p, info
+
+    def stats(self) -> dict:
+        return cps_service_stats(self.h)
+
+    def footprint(self, grid, n_levels: int = 0) -> int:
+        return cps_service_footprint(make_grid(grid, n_levels), self.opts)
+
+    def close(self):
+        if getattr(self, "h", None):
+            cps_service_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -22,6 +22,12 @@
 #include <string>
 #include <type_traits>
 #include <vector>
+#include <map>
+#include <mutex>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <thread>
 
 using namespace cps;
 
@@ -450,6 +456,12 @@ double read_scalar(cps_handle* h, int slot)
         LAUNCH_CHECK();                                     \
     } while (0)
 
+} // namespace
+
+#include "autotune.hpp"
+
+namespace {
+
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
@@ -481,6 +493,13 @@ int level_plan(const cps_grid* g, int dims[kMaxLevels][3])
     return L;
 }
 
+void validate_opts(const cps_opts* o)
+{
+    if (o && (o->precision < 0 || o->precision > 1)) fail(CPS_E_INVALID, "bad precision");
+    if (o && (o->accel < 0 || o->accel > 1)) fail(CPS_E_INVALID, "bad accel");
+    if (o && (o->tune < 0 || o->tune > 2)) fail(CPS_E_INVALID, "bad tune");
+}
+
 void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
 {
     if (!g) fail(CPS_E_INVALID, "grid is NULL");
@@ -498,37 +517,28 @@ void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
     if (g->n_levels < 0 || g->n_levels > kMaxLevels) fail(CPS_E_INVALID, "bad n_levels");
     if (m && m->method != CPS_METRICS_MAP_CENTRAL && m->method != CPS_METRICS_PAPER_VERTEX)
         fail(CPS_E_INVALID, "bad metrics method");
-    if (o && (o->precision < 0 || o->precision > 1)) fail(CPS_E_INVALID, "bad precision");
-    if (o && (o->accel < 0 || o->accel > 1)) fail(CPS_E_INVALID, "bad accel");
+    validate_opts(o);
 }
 
-void build(cps_handle* h)
+// Face metrics of every level from the map (FP64, plus FP32 copies for the
+// mixed form), the stencil class, and the dense inverse of the coarsest
+// operator.  Buffers are allocated on first use and reused when the
+// operator is recomputed for a new map of the same dims (remap); returns
+// the stencil class (MODE_*) found.
+int compute_operator(cps_handle* h)
 {
-    int dims[kMaxLevels][3];
-    h->L = level_plan(&h->grid, dims);
     const cps_grid& g = h->grid;
-    const bool axi = g.map != CPS_MAP_TRIAXIAL;
-    h->axi = axi;
     MapParams mp{g.map, g.r_inner, g.r_outer, g.theta0, g.theta1, g.radial_stretch, g.flattening,
                  g.skew};
     int flags_all = 0;
     std::vector<int> hflags;
     Buf<int> dflags;
     long long maxn = 0;
-    for (int l = 0; l < h->L; ++l) maxn = std::max(maxn, (long long)dims[l][0] * dims[l][1] * dims[l][2]);
+    for (int l = 0; l < h->L; ++l) maxn = std::max(maxn, h->lv[l].gk);
     dflags.alloc(nblk(maxn) + 1);
     for (int l = 0; l < h->L; ++l) {
         LevelMem& m = h->lv[l];
-        m.nr = dims[l][0];
-        m.nt = dims[l][1];
-        m.np = dims[l][2];
-        m.nc = axi ? 1 : m.np;
-        m.n = (long long)m.nr * m.nt * m.np;
-        m.gk = (long long)m.nr * m.nt * m.nc;
-        m.geo = make_geo(m.nr, m.nt, m.np);
-        if (m.np % 2)
-            fail(CPS_E_INVALID, "n_phi must be even on every level (level %d has %d)", l, m.np);
-        m.G64.alloc(9 * m.gk);
+        if (!m.G64.p) m.G64.alloc(9 * m.gk);
         k_metrics<<<nblk(m.gk), kBlock, 0, h->stream>>>(mp, m.nr, m.nt, m.np, m.nc,
                                                          h->met.method, m.G64.p, dflags.p);
         LAUNCH_CHECK();
@@ -540,22 +550,20 @@ void build(cps_handle* h)
     }
     dflags.release();
     if (flags_all & 1) fail(CPS_E_INVALID, "a face of the map has det <= 0");
-    h->mode = (flags_all & 4) ? MODE_FULL : ((flags_all & 2) ? MODE_RT : MODE_ORTHO);
+    const int mode = (flags_all & 4) ? MODE_FULL : ((flags_all & 2) ? MODE_RT : MODE_ORTHO);
+    if (h->Ainv.p && mode != h->mode)
+        fail(CPS_E_INVALID, "the new map changes the stencil class of the hierarchy");
+    h->mode = mode;
     h->ncol = h->mode == MODE_ORTHO ? 2 : 4;
-    if (h->L > 1) {
-        for (int l = 0; l < h->L - 1; ++l) {
-            const LevelMem& m = h->lv[l];
-            if (m.nr % 2 || m.nt % 2 || m.np % 2)
-                fail(CPS_E_INVALID, "level %d dims must be even", l);
+    if (h->opts.precision == 1)
+        for (int l = 0; l < h->L; ++l) {
+            LevelMem& m = h->lv[l];
+            if (!m.G32.p) m.G32.alloc(9 * m.gk);
+            k_to_f32<<<nblk(9 * m.gk), kBlock, 0, h->stream>>>(9 * m.gk, m.G64.p, m.G32.p);
+            LAUNCH_CHECK();
         }
-    }
     // coarsest dense inverse of A_c + alpha 1 1^T
-    LevelMem& c = h->lv[h->L - 1];
-    if (c.n > kMaxCoarse)
-        fail(CPS_E_INVALID, "coarsest level has %lld cells (max %lld): choose even dims", c.n,
-             kMaxCoarse);
-    const int n = (int)c.n;
-    h->nc = n;
+    const int n = h->nc;
     {
         Buf<double> A, M0, M1;
         Buf<int> used, piv, bad;
@@ -565,7 +573,7 @@ void build(cps_handle* h)
         used.alloc(n);
         piv.alloc(n);
         bad.alloc(1);
-        h->Ainv.alloc((size_t)n * n);
+        if (!h->Ainv.p) h->Ainv.alloc((size_t)n * n);
         HIPC(hipMemsetAsync(A.p, 0, (size_t)n * n * sizeof(double), h->stream));
         const Level<double> Lc = view<double>(h, h->L - 1);
         dispatch(h->mode, h->axi, [&](auto M, auto AX) {
@@ -595,6 +603,44 @@ void build(cps_handle* h)
         if (hbad) fail(CPS_E_INVALID, "coarsest operator is singular");
         A.release(); M0.release(); M1.release(); used.release(); piv.release(); bad.release();
     }
+    return mode;
+}
+
+// Level plan of a grid with the checks the kernels rely on; returns L.
+int checked_plan(const cps_grid& g, int dims[kMaxLevels][3])
+{
+    const int L = level_plan(&g, dims);
+    for (int l = 0; l < L; ++l) {
+        if (dims[l][2] % 2)
+            fail(CPS_E_INVALID, "n_phi must be even on every level (level %d has %d)", l,
+                 dims[l][2]);
+        if (l + 1 < L && (dims[l][0] % 2 || dims[l][1] % 2))
+            fail(CPS_E_INVALID, "level %d dims must be even", l);
+    }
+    const long long nc = (long long)dims[L - 1][0] * dims[L - 1][1] * dims[L - 1][2];
+    if (nc > kMaxCoarse)
+        fail(CPS_E_INVALID, "coarsest level has %lld cells (max %lld): choose even dims", nc,
+             kMaxCoarse);
+    return L;
+}
+
+void build(cps_handle* h)
+{
+    int dims[kMaxLevels][3];
+    h->L = checked_plan(h->grid, dims);
+    h->axi = h->grid.map != CPS_MAP_TRIAXIAL;
+    for (int l = 0; l < h->L; ++l) {
+        LevelMem& m = h->lv[l];
+        m.nr = dims[l][0];
+        m.nt = dims[l][1];
+        m.np = dims[l][2];
+        m.nc = h->axi ? 1 : m.np;
+        m.n = (long long)m.nr * m.nt * m.np;
+        m.gk = (long long)m.nr * m.nt * m.nc;
+        m.geo = make_geo(m.nr, m.nt, m.np);
+    }
+    h->nc = (int)h->lv[h->L - 1].n;
+    compute_operator(h);
     // per-level vectors
     const bool mixed = h->opts.precision == 1;
     for (int l = 0; l < h->L; ++l) {
@@ -607,16 +653,11 @@ void build(cps_handle* h)
         }
         if (!mixed && l < h->L - 1) m.r64.alloc(m.n);
         if (mixed) {
-            m.G32.alloc(9 * m.gk);
-            k_to_f32<<<nblk(9 * m.gk), kBlock, 0, h->stream>>>(9 * m.gk, m.G64.p, m.G32.p);
-            LAUNCH_CHECK();
             m.x32.alloc(m.n);
             m.b32.alloc(m.n);
             if (l < h->L - 1) m.r32.alloc(m.n);
         }
     }
-    if (mixed) // FP64 metrics are kept only on the finest level
-        for (int l = 1; l < h->L; ++l) h->lv[l].G64.release();
     const long long n0 = h->lv[0].n;
     h->partial.alloc(nblk(n0) + 64);
     h->sc.alloc(S_COUNT);
@@ -633,6 +674,7 @@ void build(cps_handle* h)
             h->ph.alloc(n0); h->sh.alloc(n0);
         }
     }
+    autotune(h, h->opts.tune);
     HIPC(hipStreamSynchronize(h->stream));
 }
 
@@ -861,6 +903,8 @@ void need_level(const cps_handle* h, int l, bool fine)
 
 // batched form (same translation unit: shares the hierarchy code above)
 #include "batch.hpp"
+// solve service (same translation unit)
+#include "service.hpp"
 
 // ---------------------------------------------------------------------------
 // C ABI

@@ -73,3 +73,38 @@ def test_grid_default_and_invalid_setup_without_gpu():
     st = cps.lib().cps_setup(ctypes.byref(g), None, None, ctypes.byref(h))
     assert st == cps.CPS_E_INVALID and not h.value
     assert "positive" in cps.last_error()
+
+
+def test_service_report_layout_and_footprint(tmp_path):
+    """cps_service_report matches the C layout; cps_service_footprint is host
+    code: it grows with the grid, covers the FP64 metrics and vectors, and
+    rejects grids the level plan cannot take."""
+    probe = tmp_path / "probe2.c"
+    probe.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "cps.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(cps_service_report),'
+        " offsetof(cps_service_report, active), offsetof(cps_service_report, p50_ms),"
+        " offsetof(cps_service_report, hbm_in_use), offsetof(cps_service_report, evictions));\n"
+        "return 0;}\n")
+    exe = tmp_path / "probe2"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe),
+                           "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
+    R = cps.cps_service_report
+    assert vals == [ctypes.sizeof(R), R.active.offset, R.p50_ms.offset, R.hbm_in_use.offset,
+                    R.evictions.offset]
+    if not os.path.exists(cps.LIB_PATH):
+        pytest.skip("libcps.so not built")
+    from paper_2305_17875_amd.inputs import Shell, MAP_OBLATE
+    opts = cps.cps_opts(1, 200, 1, 0, None)
+    f = [cps.cps_service_footprint(cps.make_grid(Shell(*s)), opts)
+         for s in [(16, 16, 16), (32, 32, 32), (64, 64, 128)]]
+    assert f[0] < f[1] < f[2]
+    n = 64 * 64 * 128
+    assert f[2] > 8 * 5 * n  # at least the five FP64 vectors of the finest level
+    fo = cps.cps_service_footprint(cps.make_grid(Shell(64, 64, 128, map=MAP_OBLATE,
+                                                        flattening=0.1)), opts)
+    assert fo > f[2]  # BiCGStab vectors of the 11-point class
+    with pytest.raises(cps.CpsError, match="coarsest"):
+        cps.cps_service_footprint(cps.make_grid(Shell(15, 16, 32)), opts)
