@@ -129,6 +129,160 @@ def cpu_baseline(g, rhs_np, gpu_iters):
                       f"same algorithm takes to reach 1e-10"}
 
 
+def batch_form(cps, torch, inputs, n_problems, steps, warmup):
+    """64 uneven-size problems (half spherical, half oblate with flattening
+    0.1) solved together by the batched form, against the same problems
+    solved one after another by cps_solve with the same options."""
+    probs = inputs.batch_problems(n_problems)
+    grids = [p.grid for p in probs]
+    log(f"batch: generating {n_problems} right-hand sides")
+    rhs = [torch.from_numpy(p.rhs()).cuda().flatten() for p in probs]
+    cells = sum(g.cells for g in grids)
+    t0 = time.perf_counter()
+    B = cps.Batch(grids, tune=1)
+    setup = time.perf_counter() - t0
+    out = [torch.empty_like(r) for r in rhs]
+    for _ in range(warmup):
+        B.solve(rhs, TOL, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, _, infos = B.solve(rhs, TOL, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    B.close()
+    its = [i.iterations for i in infos]
+    worst = max(i.rel_residual for i in infos)
+    log(f"batch: {dt * 1e3:.1f} ms per batch solve, status {st}, iterations {min(its)}..{max(its)}")
+    # the same problems one at a time (hierarchies built beforehand)
+    solvers = [cps.Solver(g, precision=1, accel=1) for g in grids]
+    for s, r, o in zip(solvers, rhs, out):
+        s.solve(r, TOL, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, r, o in zip(solvers, rhs, out):
+        s.solve(r, TOL, out=o)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    log(f"batch: sequential {seq * 1e3:.1f} ms")
+    return {"value": cells / dt, "unit": "unknowns/s", "ms_per_step": dt * 1e3,
+            "problems": n_problems, "cells": cells, "status": st,
+            "iterations_min": min(its), "iterations_max": max(its), "worst_rel_residual": worst,
+            "setup_s": setup, "sequential_ms": seq * 1e3, "speedup_vs_sequential": seq / dt,
+            "dtype": "f32 V-cycles, f64 outer",
+            "workload": f"{n_problems} shells, sizes by seed 4 from 16^3, 32^3, 64x64x128, "
+                        "96x128x256, 128x128x256; even index sphere, odd oblate f=0.1; "
+                        "smoothed N(0,1) rhs seeds 1000+i; rel residual 1e-10"}
+
+
+def rhs_pool(inputs, shapes, per_shape):
+    return {s: [inputs.smoothed_noise(s, seed=10**6 + k) for k in range(per_shape)]
+            for s in shapes}
+
+
+def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator):
+    """Poisson arrivals at `rate`/s for `duration` s submitted in real time
+    to the solve service (FP32 V-cycles in FP64 refinement, hierarchies kept
+    resident); then, if asked, the same stream served one request at a time
+    by a plain FP64 cps_setup + cps_solve per request."""
+    import threading
+    import numpy as np
+    arr = inputs.arrival_stream(rate=rate, duration=duration)
+    pool = rhs_pool(inputs, inputs.SIZE_SET, 4)
+    demand = sum(a.problem.grid.cells for a in arr) / duration
+    svc = cps.Service(budget_gib * (1 << 30), max_slots=slots, precision=1, accel=1)
+    # warm the code paths once per (size, class) so that start-up compiles
+    # and tuning are not in the measured stream
+    for s in inputs.SIZE_SET:
+        for g in (inputs.Shell(*s), inputs.Shell(*s, map=inputs.MAP_OBLATE, flattening=0.1)):
+            svc.wait(svc.submit(g, pool[s][0], TOL))
+    base = svc.stats()
+    tickets = []
+    lock = threading.Lock()
+    results = []
+
+    def waiter():
+        k = 0
+        while True:
+            with lock:
+                t = tickets[k] if k < len(tickets) else None
+            if t is None:
+                if k >= len(arr):
+                    return
+                time.sleep(0.0005)
+                continue
+            st, _, info = svc.wait(t)
+            results.append((st, info.iterations))
+            k += 1
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for a in arr:
+        d = t0 + a.t - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        s = a.problem.grid.shape
+        t = svc.submit(a.problem.grid, pool[s][a.rid % 4], TOL)
+        with lock:
+            tickets.append(t)
+    th.join()
+    wall = time.perf_counter() - t0
+    st = svc.stats()
+    svc.close()
+    fails = sum(1 for r in results if r[0] != cps.CPS_OK)
+    cells = sum(a.problem.grid.cells for a in arr)
+    out = {"rate_per_s": rate, "duration_s": duration, "requests": len(arr),
+           "failed": fails, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+           "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+           "unknowns_per_s": cells / wall, "demand_unknowns_per_s": demand,
+           "drain_s": wall - duration, "slots": slots, "hbm_budget_gib": budget_gib,
+           "peak_active": st["peak_active"],
+           "hierarchies_built": st["hierarchies_built"] - base["hierarchies_built"],
+           "hierarchies_reused": st["hierarchies_reused"] - base["hierarchies_reused"],
+           "map_rebuilds": st["map_rebuilds"] - base["map_rebuilds"],
+           "evictions": st["evictions"] - base["evictions"],
+           "dtype": "f32 V-cycles, f64 outer",
+           "workload": f"Poisson arrivals {rate}/s for {duration} s (seed 5), sizes uniform over "
+                       "16^3, 32^3, 64x64x128, 96x128x256, 128x128x256, sphere or oblate "
+                       "f~U(0,0.15); rhs from 4 smoothed N(0,1) fields per size; tol 1e-10; "
+                       "host rhs in, host p out"}
+    out["p50_p99_note"] = ("latency = submission to completion, p50/p99 over this stream "
+                           "(the latency percentiles include queueing: at this rate the stream "
+                           "asks for more unknowns/s than one GPU serves)"
+                           if demand > out["unknowns_per_s"] else
+                           "latency = submission to completion, p50/p99 over this stream")
+    log(f"serve: {len(arr)} requests, p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, "
+        f"{cells / wall / 1e6:.1f} M unknowns/s (demand {demand / 1e6:.1f} M)")
+    if comparator:
+        import torch
+        lat = []
+        t0 = time.perf_counter()
+        for a in arr:
+            d = t0 + a.t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            g = a.problem.grid
+            s = cps.Solver(g, precision=0, accel=1)
+            r = torch.from_numpy(pool[g.shape][a.rid % 4]).cuda().flatten()
+            res = s.solve(r, TOL)
+            p = res.p.cpu().numpy()
+            s.close()
+            lat.append(time.perf_counter() - (t0 + a.t))
+        wall_c = time.perf_counter() - t0
+        lat = np.array(lat) * 1e3
+        out["comparator_fp64_per_request"] = {
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "unknowns_per_s": cells / wall_c,
+            "what": "same stream, one request at a time: FP64 cps_setup + cps_solve + "
+                    "cps_destroy per request, host rhs in, host p out"}
+        log(f"serve comparator: p50 {np.percentile(lat, 50):.1f} ms p99 "
+            f"{np.percentile(lat, 99):.1f} ms, {cells / wall_c / 1e6:.1f} M unknowns/s")
+    return out
+
+
 def traffic_for(kh):
     """Per-launch HBM bytes of the finest-level colour pass from the counter
     summary, if it was taken on this kernel source."""
@@ -148,6 +302,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-problems", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-serve-comparator", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {a.gpus}): one grid's solve is not "
@@ -210,9 +371,18 @@ def main():
                          "kernels": kernel_table(mx["prof"], a.steps)}
         mx["solver"].close()
     s64.close()
+    gpu_iters = f64["iters"][-1]
+    del x64, f64, rhs
+    torch.cuda.empty_cache()
+    if not a.no_batch:
+        line["batch"] = batch_form(cps, torch, inputs, a.batch_problems, a.steps, a.warmup)
+        torch.cuda.empty_cache()
+    if not a.no_serve:
+        line["serve"] = serve_form(cps, inputs, a.serve_seconds, a.serve_rate, a.serve_slots,
+                                   64, not a.no_serve_comparator)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(g, rhs_np, f64["iters"][-1])
+        line["cpu_baseline"] = cpu_baseline(g, rhs_np, gpu_iters)
     print(json.dumps(line), flush=True)
 
 

@@ -217,15 +217,20 @@ typedef struct {
 cps_status cps_service_create(size_t hbm_budget_bytes, int32_t max_slots, const cps_opts* opts,
                               cps_service** out);
 /* Queue one solve of A p = rhs - mean(rhs) to relative residual tol.
- * grid, metrics (nullable): host, read during the call; rhs_host: host FP64
- * array of n_r*n_theta*n_phi elements, copied before the call returns.
- * *ticket receives the request's id.  Grid errors are reported here. */
+ * grid, metrics (nullable): host, read during the call.  rhs_host, p_host:
+ * host FP64 arrays of n_r*n_theta*n_phi elements, owned by the caller, which
+ * keeps them valid and leaves them alone until cps_service_wait returns for
+ * this ticket (no host copy is made; a worker reads rhs_host and writes
+ * p_host).  *ticket receives the request's id.  Grid errors are reported
+ * here. */
 cps_status cps_service_submit(cps_service* s, const cps_grid* grid, const cps_metrics* metrics,
-                              const double* rhs_host, double tol, uint64_t* ticket);
-/* Block until the request finishes; p_host (host, nullable) receives p,
- * info (nullable) its cps_info.  Returns the request's status (CPS_E_OOM if
- * it can never fit the budget); each ticket can be waited for once. */
-cps_status cps_service_wait(cps_service* s, uint64_t ticket, double* p_host, cps_info* info);
+                              const double* rhs_host, double* p_host, double tol,
+                              uint64_t* ticket);
+/* Block until the request finishes; then p_host holds p (the last iterate
+ * for CPS_E_NOT_CONVERGED) and info (nullable) its cps_info.  Returns the
+ * request's status (CPS_E_OOM if it can never fit the budget); each ticket
+ * can be waited for once. */
+cps_status cps_service_wait(cps_service* s, uint64_t ticket, cps_info* info);
 /* *bytes = the device memory a request of this grid is admitted against
  * with these opts (nullable): its hierarchy, two staging vectors and the
  * transient buffers of the coarse inverse.  Host only; checks the grid. */

@@ -105,9 +105,9 @@ def lib():
         L.cps_batch_destroy.restype = None
         L.cps_service_create.argtypes = [ctypes.c_size_t, I, P, ctypes.POINTER(P)]
         L.cps_service_create.restype = I
-        L.cps_service_submit.argtypes = [P, P, P, P, D, ctypes.POINTER(ctypes.c_uint64)]
+        L.cps_service_submit.argtypes = [P, P, P, P, P, D, ctypes.POINTER(ctypes.c_uint64)]
         L.cps_service_submit.restype = I
-        L.cps_service_wait.argtypes = [P, ctypes.c_uint64, P, P]
+        L.cps_service_wait.argtypes = [P, ctypes.c_uint64, P]
         L.cps_service_wait.restype = I
         L.cps_service_footprint.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint64)]
         L.cps_service_footprint.restype = I
@@ -407,20 +407,22 @@ def _host_f64(a, n, what):
     return a.ctypes.data
 
 
-def cps_service_submit(h, grid: cps_grid, metrics: cps_metrics, rhs, tol: float) -> int:
+def cps_service_submit(h, grid: cps_grid, metrics: cps_metrics, rhs, p, tol: float) -> int:
+    """rhs, p: host float64 arrays the caller keeps alive and untouched until
+    the ticket's wait returns."""
     n = grid.n_r * grid.n_theta * grid.n_phi
     t = ctypes.c_uint64()
     _check(lib().cps_service_submit(h, ctypes.byref(grid), ctypes.byref(metrics),
-                                    _host_f64(rhs, n, "rhs"), tol, ctypes.byref(t)))
+                                    _host_f64(rhs, n, "rhs"), _host_f64(p, n, "p"), tol,
+                                    ctypes.byref(t)))
     return t.value
 
 
-def cps_service_wait(h, ticket: int, p):
-    """Blocks (without the GIL) until the request ends; fills p (host).
-    Returns (status, cps_info); raises for argument and device errors."""
+def cps_service_wait(h, ticket: int):
+    """Blocks (without the GIL) until the request ends.  Returns (status,
+    cps_info); raises for argument and device errors."""
     info = cps_info()
-    st = lib().cps_service_wait(h, ticket, p.ctypes.data if p is not None else None,
-                                ctypes.byref(info))
+    st = lib().cps_service_wait(h, ticket, ctypes.byref(info))
     if st not in (CPS_OK, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED):
         _check(st)
     return st, info
@@ -451,20 +453,24 @@ class Service:
                  accel: int = 1, max_iters: int = 200, tune: int = 0):
         self.opts = cps_opts(precision, max_iters, accel, tune, None)
         self.h = cps_service_create(int(hbm_budget_bytes), max_slots, self.opts)
-        self._shape = {}
+        self._held = {}  # ticket -> (rhs, p): alive until the wait returns
 
     def submit(self, grid, rhs, tol: float = 1e-10, metrics: int = METRICS_MAP_CENTRAL,
-               n_levels: int = 0) -> int:
-        t = cps_service_submit(self.h, make_grid(grid, n_levels), cps_metrics(metrics), rhs, tol)
-        self._shape[t] = rhs.shape
+               n_levels: int = 0, out=None) -> int:
+        import numpy as np
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        p = out if out is not None else np.empty(rhs.shape, dtype=np.float64)
+        t = cps_service_submit(self.h, make_grid(grid, n_levels), cps_metrics(metrics), rhs, p,
+                               tol)
+        self._held[t] = (rhs, p)
         return t
 
     def wait(self, ticket: int):
-        import numpy as np
-        shape = self._shape.pop(ticket)
-        p = np.empty(shape, dtype=np.float64)
-        st, info = cps_service_wait(self.h, ticket, p)
-        return st, p, info
+        try:
+            st, info = cps_service_wait(self.h, ticket)
+        finally:
+            held = self._held.pop(ticket, None)
+        return st, held[1], info
 
     def stats(self) -> dict:
         return cps_service_stats(self.h)

@@ -27,7 +27,7 @@ struct SvcReq {
     cps_metrics met{};
     double tol = 1e-10;
     long long n = 0;
-    double* rhs = nullptr; // pinned host copies
+    const double* rhs = nullptr; // the caller's host arrays, held until the wait
     double* p = nullptr;
     cps_info info{};
     cps_status st = CPS_OK;
@@ -343,11 +343,7 @@ void service_destroy(cps_service* S)
     for (auto& t : S->workers)
         if (t.joinable()) t.join();
     for (auto& e : S->pool) destroy(e->h);
-    for (auto& kv : S->reqs) {
-        if (kv.second->rhs) (void)hipHostFree(kv.second->rhs);
-        if (kv.second->p) (void)hipHostFree(kv.second->p);
-        delete kv.second;
-    }
+    for (auto& kv : S->reqs) delete kv.second;
     delete S;
 }
 
@@ -395,10 +391,11 @@ cps_status cps_service_create(size_t hbm_budget_bytes, int32_t max_slots, const 
 }
 
 cps_status cps_service_submit(cps_service* S, const cps_grid* grid, const cps_metrics* metrics,
-                              const double* rhs_host, double tol, uint64_t* ticket)
+                              const double* rhs_host, double* p_host, double tol,
+                              uint64_t* ticket)
 {
     return guarded([&] {
-        if (!S || !grid || !rhs_host || !ticket) fail(CPS_E_INVALID, "NULL argument");
+        if (!S || !grid || !rhs_host || !p_host || !ticket) fail(CPS_E_INVALID, "NULL argument");
         if (!(tol > 0)) fail(CPS_E_INVALID, "tol must be positive");
         validate(grid, metrics, &S->opts);
         int dims[kMaxLevels][3];
@@ -408,9 +405,8 @@ cps_status cps_service_submit(cps_service* S, const cps_grid* grid, const cps_me
         if (metrics) R->met = *metrics;
         R->tol = tol;
         R->n = (long long)grid->n_r * grid->n_theta * grid->n_phi;
-        HIPC(hipHostMalloc(&R->rhs, R->n * sizeof(double), hipHostMallocDefault));
-        HIPC(hipHostMalloc(&R->p, R->n * sizeof(double), hipHostMallocDefault));
-        std::memcpy(R->rhs, rhs_host, R->n * sizeof(double));
+        R->rhs = rhs_host;
+        R->p = p_host;
         R->t_submit = now_s();
         std::lock_guard<std::mutex> lk(S->mu);
         R->id = S->next_id++;
@@ -424,7 +420,7 @@ cps_status cps_service_submit(cps_service* S, const cps_grid* grid, const cps_me
     });
 }
 
-cps_status cps_service_wait(cps_service* S, uint64_t ticket, double* p_host, cps_info* info)
+cps_status cps_service_wait(cps_service* S, uint64_t ticket, cps_info* info)
 {
     SvcReq* R = nullptr;
     cps_status g = guarded([&] {
@@ -437,13 +433,9 @@ cps_status cps_service_wait(cps_service* S, uint64_t ticket, double* p_host, cps
         S->reqs.erase(it);
     });
     if (g != CPS_OK) return g;
-    if (p_host && R->st != CPS_E_OOM && R->st != CPS_E_INVALID && R->st != CPS_E_HIP)
-        std::memcpy(p_host, R->p, R->n * sizeof(double));
     if (info) *info = R->info;
     const cps_status st = R->st;
     if (st != CPS_OK) g_err = R->err;
-    (void)hipHostFree(R->rhs);
-    (void)hipHostFree(R->p);
     delete R;
     return st;
 }

@@ -146,7 +146,7 @@ def test_service_fp64_and_errors():
         nan[1, 2, 3] = np.nan
         st_nan, _, _ = svc.wait(svc.submit(g, nan))
         with pytest.raises(cps.CpsError, match="ticket"):
-            cps.cps_service_wait(svc.h, 12345, None)
+            cps.cps_service_wait(svc.h, 12345)
     finally:
         svc.close()
     xa, _ = alone(g, b, precision=0)
