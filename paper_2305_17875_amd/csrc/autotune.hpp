@@ -129,7 +129,7 @@ void autotune_levels(cps_handle* h, int mode)
         double tbest = 1e30;
         std::vector<int> seen;
         for (int c : cand) {
-            const MarchShape ms = march_shape(g, c);
+            const MarchShape ms = stencil_shape(g, c);
             if (c > g.nr || std::find(seen.begin(), seen.end(), ms.ch) != seen.end()) continue;
             seen.push_back(ms.ch);
             const double t = time_gs<T>(h, l, b, x, ms.ch, 5);

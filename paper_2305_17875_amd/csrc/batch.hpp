@@ -228,7 +228,7 @@ PDesc<float> make_desc(cps_handle* h)
     d.G64 = h->lv[0].G64.p;
     d.gk64 = h->lv[0].gk;
     const Geo& g0 = h->lv[0].geo;
-    d.parts_apply = marching(h) ? march_shape(g0).grid : grid_of(g0.nr, cdiv(g0.rowlen, kBlock));
+    d.parts_apply = marching(h) ? stencil_shape(g0).grid : grid_of(g0.nr, cdiv(g0.rowlen, kBlock));
     d.parts_vec = vgrid(h->lv[0].n);
     double* v[V_COUNT] = {h->x0.p, h->b0.p, h->r.p, h->z.p, h->pd.p, h->q.p, h->r0.p,
                           h->v.p,  h->s.p,  h->t.p, h->ph.p, h->sh.p, nullptr, nullptr};
@@ -254,8 +254,8 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
             if (l + 1 >= h->L) continue;
             const Geo& g = h->lv[l].geo;
             if (G.march) {
-                gs.push_back({p, march_shape(g, h->lv[l].gs_ch).grid});
-                res.push_back({p, march_shape(g).grid});
+                gs.push_back({p, stencil_shape(g, h->lv[l].gs_ch).grid});
+                res.push_back({p, stencil_shape(g).grid});
             } else {
                 gs.push_back({p, (int)grid_of(g.nr, gs_bpa(g, h->ncol))});
                 res.push_back({p, (int)grid_of(g.nr, cdiv(g.rowlen, kBlock))});

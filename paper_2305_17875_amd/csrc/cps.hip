@@ -263,7 +263,17 @@ void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero = fal
     const int z = zero ? 1 : 0;
     ProfScope ps(h, CPS_KERNEL_GS, l);
     if (marching(h)) {
-        const MarchShape ms = march_shape(L.g, h->lv[l].gs_ch);
+        const MarchShape ms = stencil_shape(L.g, h->lv[l].gs_ch);
+        if (row_pairs(L.g)) {
+            if (l == 0)
+                k_gs_march2<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch,
+                                                                    b, x, colour, z);
+            else
+                k_gs_march2<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch,
+                                                                    b, x, colour, z);
+            LAUNCH_CHECK();
+            return;
+        }
         auto launch = [&](auto U, auto T_) {
             k_gs_march<T, decltype(U)::value, decltype(T_)::value>
                 <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour, z);
@@ -306,7 +316,17 @@ long long residual(cps_handle* h, int l, const T* b, const T* x, T* r, bool want
     double* part = want_norm ? h->partial.p : nullptr;
     ProfScope ps(h, CPS_KERNEL_RESIDUAL, l);
     if (marching(h)) {
-        const MarchShape ms = march_shape(L.g);
+        const MarchShape ms = stencil_shape(L.g);
+        if (row_pairs(L.g)) {
+            if (l == 0)
+                k_residual_march2<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa,
+                                                                          ms.ch, b, x, r, part);
+            else
+                k_residual_march2<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa,
+                                                                          ms.ch, b, x, r, part);
+            LAUNCH_CHECK();
+            return ms.grid;
+        }
         auto launch = [&](auto U, auto T_) {
             k_residual_march<T, decltype(U)::value, decltype(T_)::value>
                 <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, r, part);
@@ -335,7 +355,17 @@ long long apply(cps_handle* h, int l, const T* x, T* y, const T* dotv)
     double* part = dotv ? h->partial.p : nullptr;
     ProfScope ps(h, CPS_KERNEL_APPLY, l);
     if (marching(h)) {
-        const MarchShape ms = march_shape(L.g);
+        const MarchShape ms = stencil_shape(L.g);
+        if (row_pairs(L.g)) {
+            if (l == 0)
+                k_apply_march2<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa,
+                                                                       ms.ch, x, y, part, dotv);
+            else
+                k_apply_march2<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa,
+                                                                       ms.ch, x, y, part, dotv);
+            LAUNCH_CHECK();
+            return ms.grid;
+        }
         auto launch = [&](auto U, auto T_) {
             k_apply_march<T, decltype(U)::value, decltype(T_)::value>
                 <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, x, y, part, dotv);

@@ -426,34 +426,63 @@ __device__ __forceinline__ bool march_pos(Blk bk, const Geo& g, int bpa, int ch,
     return true;
 }
 
+// Planes a marching thread loads ahead: the loads of kAhead planes are
+// issued together before any of them is used, so each wavefront keeps
+// several memory requests in flight (one plane at a time leaves the kernels
+// bound by memory latency, not bandwidth).
+// The colour pass loads 5 values per plane, the two-cell residual and
+// product kernels 10: they go 2 planes ahead to stay at high occupancy.
+constexpr int kAhead = 4;
+constexpr int kAhead2 = 2;
+
 // Red-black Gauss-Seidel pass (colour k): at plane a the cell of column
 // (b, j) with colour k sits in plane p = (k + a + b) mod 2 and its black
 // neighbours are: the column's own cells at a-1, a+1 (plane p) and at a
 // (plane 1-p), the cells at (a, b+-1) in plane p, and one phi neighbour in
-// plane 1-p of the adjacent column.
+// plane 1-p of the adjacent column.  A pass writes only cells of colour k
+// and reads only the other colour, so loads may run ahead of the stores.
 // zero != 0: first pass from a zero iterate (the other colour is taken as 0
 // and not read; it need not be initialised), x = b / D.
-template <typename T, bool UROW, int LTAG>
+template <typename T, bool UROW, int LTAG, int AHEAD = kAhead>
 __device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ G, long long gk,
                                                      int bpa, int ch, const T* __restrict__ bv,
                                                      T* __restrict__ x, int colour, int zero)
 {
     March p;
     if (!march_pos<UROW>(bk, g, bpa, ch, p)) return;
+    const int b = p.b;
+    const bool thi = b < g.nt - 1;
+    // metrics of the column at plane a: D and the five face values
+    auto diag = [&](int a, T& grl, T& grh, T& gtl, T& gth, T& gpp) {
+        const long long ci = (long long)a * g.nt + b;
+        grl = G[ci];
+        grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
+        gtl = G[4 * gk + ci];
+        gth = thi ? G[4 * gk + ci + 1] : T(0);
+        gpp = G[8 * gk + ci];
+    };
     if (zero) {
-        for (int a = p.a0; a < p.a1; ++a) {
-            const int s = (colour + a + p.b) & 1;
-            const long long ci = (long long)a * g.nt + p.b;
-            const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
-            const T gth = p.b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
-            const T D = -(G[ci] + grh + G[4 * gk + ci] + gth + T(2) * G[8 * gk + ci]);
-            const long long id = s * g.P + (long long)a * g.rowlen + p.m;
-            x[id] = bv[id] / D;
+        for (int a = p.a0; a < p.a1; a += AHEAD) {
+            T bb[AHEAD];
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1)
+                    bb[u] = bv[((colour + a + u + b) & 1) * g.P + (long long)(a + u) * g.rowlen + p.m];
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1) {
+                    T grl, grh, gtl, gth, gpp;
+                    diag(a + u, grl, grh, gtl, gth, gpp);
+                    const T D = -(grl + grh + gtl + gth + T(2) * gpp);
+                    x[((colour + a + u + b) & 1) * g.P + (long long)(a + u) * g.rowlen + p.m] =
+                        bb[u] / D;
+                }
         }
         return;
     }
     const long long sr = g.rowlen;
-    const int nh = g.nh, b = p.b, j = p.j;
+    const int nh = g.nh, j = p.j;
+    const bool tlo = b > 0;
     // the other-colour cell of this column at plane a
     auto other = [&](int a) -> T {
         if (a < 0 || a >= g.nr) return T(0);
@@ -462,27 +491,37 @@ __device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ 
     };
     T om = other(p.a0 - 1), o0 = other(p.a0);
     const int jn0 = j == 0 ? nh - 1 : j - 1, jn1 = j == nh - 1 ? 0 : j + 1;
-    for (int a = p.a0; a < p.a1; ++a) {
-        const T op = other(a + 1);
-        const int s = (colour + a + b) & 1;
-        const long long ci = (long long)a * g.nt + b;
-        const T grl = G[ci];
-        const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
-        const T gtl = G[4 * gk + ci];
-        const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
-        const T gpp = G[8 * gk + ci];
-        const T D = -(grl + grh + gtl + gth + gpp + gpp);
-        const long long base = (long long)a * sr + p.m; // (a, b, j) within a plane
-        const T* xs = x + s * g.P;
-        const T xtm = b > 0 ? xs[base - nh] : T(0);
-        const T xtp = b < g.nt - 1 ? xs[base + nh] : T(0);
-        // phi: plane 1-s holds c-1 and c+1; o0 is the one at index j
-        const T on = x[(1 - s) * g.P + base - j + (s == 0 ? jn0 : jn1)];
-        const T S = grh * op + grl * om + gth * xtp + gtl * xtm + gpp * (o0 + on);
-        const long long id = s * g.P + base;
-        x[id] = (bv[id] - S) / D;
-        om = o0;
-        o0 = op;
+    for (int a = p.a0; a < p.a1; a += AHEAD) {
+        T op[AHEAD], tm[AHEAD], tp[AHEAD], on[AHEAD], bb[AHEAD];
+#pragma unroll
+        for (int u = 0; u < AHEAD; ++u) {
+            const int aa = a + u;
+            if (aa < p.a1) {
+                const int s = (colour + aa + b) & 1;
+                const long long base = (long long)aa * sr + p.m; // (a, b, j) within a plane
+                const T* xs = x + s * g.P;
+                op[u] = other(aa + 1);
+                tm[u] = tlo ? xs[base - nh] : T(0);
+                tp[u] = thi ? xs[base + nh] : T(0);
+                // phi: plane 1-s holds c-1 and c+1; o0 is the one at index j
+                on[u] = x[(1 - s) * g.P + base - j + (s == 0 ? jn0 : jn1)];
+                bb[u] = bv[s * g.P + base];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < AHEAD; ++u) {
+            const int aa = a + u;
+            if (aa < p.a1) {
+                T grl, grh, gtl, gth, gpp;
+                diag(aa, grl, grh, gtl, gth, gpp);
+                const T D = -(grl + grh + gtl + gth + gpp + gpp);
+                const T S = grh * op[u] + grl * om + gth * tp[u] + gtl * tm[u] + gpp * (o0 + on[u]);
+                const int s = (colour + aa + b) & 1;
+                x[s * g.P + (long long)aa * sr + p.m] = (bb[u] - S) / D;
+                om = o0;
+                o0 = op[u];
+            }
+        }
     }
 }
 
@@ -494,31 +533,67 @@ __global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict_
     d_gs_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero);
 }
 
-// Flux-form (A x) of the two cells (a, b, 2j) and (a, b, 2j+1) given the
-// column values at a-1, a, a+1 (u = plane 0, v = plane 1).
-template <typename T, typename Ld>
-__device__ __forceinline__ void march_apply2(const Geo& g, const T* __restrict__ G, long long gk,
-                                             const Ld& X, int a, int b, int j, long long base,
-                                             T um, T u0, T up, T vm, T v0, T vp, T& y0, T& y1)
+
+// Values a marching thread needs at plane a for the two cells (a, b, 2j)
+// and (a, b, 2j+1) besides the column at a-1 and a: the column at a+1, the
+// theta neighbours of both cells and their phi neighbours in the other
+// plane.  A read past an r- or theta-wall takes the cell itself (its flux
+// difference is then 0 and the zero wall metric multiplies it).
+template <typename T>
+struct Nb2 {
+    T up, vp, utm, utp, vtm, vtp, vjm, ujp;
+};
+
+template <typename T>
+__device__ __forceinline__ void march_load2(const Geo& g, const T* __restrict__ x, int a, int b,
+                                            int j, long long base, Nb2<T>& n)
 {
     const int nh = g.nh;
+    const long long ab = a < g.nr - 1 ? base + g.rowlen : base;
+    const long long tl = b > 0 ? base - nh : base, th = b < g.nt - 1 ? base + nh : base;
+    n.up = x[ab];
+    n.vp = x[g.P + ab];
+    n.utm = x[tl];
+    n.utp = x[th];
+    n.vtm = x[g.P + tl];
+    n.vtp = x[g.P + th];
+    // plane 0 cell c = 2j: phi neighbours c-1 = (1, j-1), c+1 = (1, j);
+    // plane 1 cell c = 2j+1: c-1 = (0, j), c+1 = (0, j+1)
+    n.vjm = x[g.P + base - j + (j == 0 ? nh - 1 : j - 1)];
+    n.ujp = x[base - j + (j == nh - 1 ? 0 : j + 1)];
+}
+
+// Flux-form (A x) of the two cells given the column values at a-1, a
+// (u = plane 0, v = plane 1) and the neighbours n.
+template <typename T>
+__device__ __forceinline__ void march_apply2(const Geo& g, const T* __restrict__ G, long long gk,
+                                             int a, int b, T um, T u0, T vm, T v0, const Nb2<T>& n,
+                                             T& y0, T& y1)
+{
     const long long ci = (long long)a * g.nt + b;
     const T grl = G[ci];
     const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
     const T gtl = G[4 * gk + ci];
     const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
     const T gpp = G[8 * gk + ci];
-    const bool tlo = b > 0, thi = b < g.nt - 1;
-    // plane 0 cell c = 2j: phi neighbours c-1 = (1, j-1), c+1 = (1, j)
-    const T u_tm = tlo ? X(base - nh) : u0, u_tp = thi ? X(base + nh) : u0;
-    const T v_jm = X(g.P + base - j + (j == 0 ? nh - 1 : j - 1));
-    y0 = grh * (up - u0) - grl * (u0 - um) + gth * (u_tp - u0) - gtl * (u0 - u_tm) +
-         gpp * (v0 - u0) - gpp * (u0 - v_jm);
-    // plane 1 cell c = 2j+1: phi neighbours c-1 = (0, j), c+1 = (0, j+1)
-    const T v_tm = tlo ? X(g.P + base - nh) : v0, v_tp = thi ? X(g.P + base + nh) : v0;
-    const T u_jp = X(base - j + (j == nh - 1 ? 0 : j + 1));
-    y1 = grh * (vp - v0) - grl * (v0 - vm) + gth * (v_tp - v0) - gtl * (v0 - v_tm) +
-         gpp * (u_jp - v0) - gpp * (v0 - u0);
+    y0 = grh * (n.up - u0) - grl * (u0 - um) + gth * (n.utp - u0) - gtl * (u0 - n.utm) +
+         gpp * (v0 - u0) - gpp * (u0 - n.vjm);
+    y1 = grh * (n.vp - v0) - grl * (v0 - vm) + gth * (n.vtp - v0) - gtl * (v0 - n.vtm) +
+         gpp * (n.ujp - v0) - gpp * (v0 - u0);
+}
+
+// First column values of a marching thread: (um, u0, vm, v0) at a0-1, a0,
+// with the cell itself past the low r-wall.
+template <typename T>
+__device__ __forceinline__ void march_start(const Geo& g, const T* __restrict__ x, const March& p,
+                                            T& um, T& u0, T& vm, T& v0)
+{
+    const long long base = (long long)p.a0 * g.rowlen + p.m;
+    const long long bm = p.a0 > 0 ? base - g.rowlen : base;
+    u0 = x[base];
+    v0 = x[g.P + base];
+    um = x[bm];
+    vm = x[g.P + bm];
 }
 
 // r = b - A x (and partial sums of r^2), marching.
@@ -533,22 +608,31 @@ __device__ __forceinline__ void d_residual_march(Blk bk, Geo g, const T* __restr
     March p;
     double acc = 0.0;
     if (march_pos<UROW>(bk, g, bpa, ch, p)) {
-        const long long sr = g.rowlen;
-        auto col = [&](int a, int s, T own) -> T {
-            return (a < 0 || a >= g.nr) ? own : x[s * g.P + (long long)a * sr + p.m];
-        };
-        T u0 = col(p.a0, 0, T(0)), v0 = col(p.a0, 1, T(0));
-        T um = col(p.a0 - 1, 0, u0), vm = col(p.a0 - 1, 1, v0);
-        for (int a = p.a0; a < p.a1; ++a) {
-            const T up = col(a + 1, 0, u0), vp = col(a + 1, 1, v0);
-            const long long base = (long long)a * sr + p.m;
-            T y0, y1;
-            march_apply2<T>(g, G, gk, Field<T>{x}, a, p.b, p.j, base, um, u0, up, vm, v0, vp, y0, y1);
-            const T r0 = bv[base] - y0, r1 = bv[g.P + base] - y1;
-            r[base] = r0;
-            r[g.P + base] = r1;
-            acc += (double)r0 * (double)r0 + (double)r1 * (double)r1;
-            um = u0; u0 = up; vm = v0; v0 = vp;
+        T um, u0, vm, v0;
+        march_start<T>(g, x, p, um, u0, vm, v0);
+        for (int a = p.a0; a < p.a1; a += kAhead2) {
+            Nb2<T> nb[kAhead2];
+            T b0[kAhead2], b1[kAhead2];
+#pragma unroll
+            for (int u = 0; u < kAhead2; ++u)
+                if (a + u < p.a1) {
+                    const long long base = (long long)(a + u) * g.rowlen + p.m;
+                    march_load2<T>(g, x, a + u, p.b, p.j, base, nb[u]);
+                    b0[u] = bv[base];
+                    b1[u] = bv[g.P + base];
+                }
+#pragma unroll
+            for (int u = 0; u < kAhead2; ++u)
+                if (a + u < p.a1) {
+                    const long long base = (long long)(a + u) * g.rowlen + p.m;
+                    T y0, y1;
+                    march_apply2<T>(g, G, gk, a + u, p.b, um, u0, vm, v0, nb[u], y0, y1);
+                    const T r0 = b0[u] - y0, r1 = b1[u] - y1;
+                    r[base] = r0;
+                    r[g.P + base] = r1;
+                    acc += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+                    um = u0; u0 = nb[u].up; vm = v0; v0 = nb[u].vp;
+                }
         }
     }
     if (partial) {
@@ -580,21 +664,32 @@ __device__ __forceinline__ void d_apply_march(Blk bk, Geo g, const T* __restrict
     March p;
     double acc = 0.0;
     if (march_pos<UROW>(bk, g, bpa, ch, p)) {
-        const long long sr = g.rowlen;
-        auto col = [&](int a, int s, T own) -> T {
-            return (a < 0 || a >= g.nr) ? own : x[s * g.P + (long long)a * sr + p.m];
-        };
-        T u0 = col(p.a0, 0, T(0)), v0 = col(p.a0, 1, T(0));
-        T um = col(p.a0 - 1, 0, u0), vm = col(p.a0 - 1, 1, v0);
-        for (int a = p.a0; a < p.a1; ++a) {
-            const T up = col(a + 1, 0, u0), vp = col(a + 1, 1, v0);
-            const long long base = (long long)a * sr + p.m;
-            T y0, y1;
-            march_apply2<T>(g, G, gk, Field<T>{x}, a, p.b, p.j, base, um, u0, up, vm, v0, vp, y0, y1);
-            y[base] = y0;
-            y[g.P + base] = y1;
-            if (dotv) acc += (double)y0 * (double)dotv[base] + (double)y1 * (double)dotv[g.P + base];
-            um = u0; u0 = up; vm = v0; v0 = vp;
+        T um, u0, vm, v0;
+        march_start<T>(g, x, p, um, u0, vm, v0);
+        for (int a = p.a0; a < p.a1; a += kAhead2) {
+            Nb2<T> nb[kAhead2];
+            T d0[kAhead2], d1[kAhead2];
+#pragma unroll
+            for (int u = 0; u < kAhead2; ++u)
+                if (a + u < p.a1) {
+                    const long long base = (long long)(a + u) * g.rowlen + p.m;
+                    march_load2<T>(g, x, a + u, p.b, p.j, base, nb[u]);
+                    if (dotv) {
+                        d0[u] = dotv[base];
+                        d1[u] = dotv[g.P + base];
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < kAhead2; ++u)
+                if (a + u < p.a1) {
+                    const long long base = (long long)(a + u) * g.rowlen + p.m;
+                    T y0, y1;
+                    march_apply2<T>(g, G, gk, a + u, p.b, um, u0, vm, v0, nb[u], y0, y1);
+                    y[base] = y0;
+                    y[g.P + base] = y1;
+                    if (dotv) acc += (double)y0 * (double)d0[u] + (double)y1 * (double)d1[u];
+                    um = u0; u0 = nb[u].up; vm = v0; v0 = nb[u].vp;
+                }
         }
     }
     if (partial) {
@@ -615,6 +710,404 @@ __global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Row-pair marching kernels (7-point, phi-invariant metrics; levels whose
+// n_phi / 2 is a multiple of 64 and whose n_theta is even).  A thread owns
+// the columns (b0 = 2 bp, j) and (b1 = b0 + 1, j) and marches over a chunk
+// of r-planes like the kernels above.  The theta neighbour between its two
+// rows is the other row's value, already in registers, and a wavefront
+// covers 64 consecutive j of one row pair, so phi neighbours are the
+// adjacent lanes' values (lane shuffles; with n_phi / 2 = 64 the wavefront
+// is the whole ring).  Besides the streamed column values only the rows
+// just outside the pair and, for longer rings, the phi neighbours past the
+// wavefront's ends are loaded.  Launch: grid = bpa * nchunks with bpa
+// blocks over the (n_theta / 2) * (n_phi / 2) row-pair positions.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline bool row_pairs(const Geo& g) { return g.nh % 64 == 0 && g.nt % 2 == 0; }
+
+struct March2 {
+    int a0, a1, b0, j, lane;
+    long long r0; // offset of (b0, j) within a plane
+    bool ring;    // the wavefront holds the whole phi ring of its rows
+};
+
+__device__ __forceinline__ bool march2_pos(Blk bk, const Geo& g, int bpa, int ch, March2& p)
+{
+    const int L = (int)bk.L;
+    const int chunk = L / bpa;
+    const int m2 = (L - chunk * bpa) * kBlock + (int)threadIdx.x;
+    p.a0 = chunk * ch;
+    p.a1 = min(g.nr, p.a0 + ch);
+    // (n_theta / 2) * nh is a multiple of 64: whole wavefronts drop out
+    if (m2 >= (g.nt >> 1) * g.nh || p.a0 >= g.nr) return false;
+    const int bp = __builtin_amdgcn_readfirstlane(m2 / g.nh);
+    p.b0 = 2 * bp;
+    p.j = m2 - bp * g.nh;
+    p.lane = (int)threadIdx.x & 63;
+    p.r0 = (long long)p.b0 * g.nh + p.j;
+    p.ring = g.nh == 64;
+    return true;
+}
+
+// Red-black colour pass over row pairs (stencil and colouring of
+// d_gs_march).  At plane a the cells of colour k of row b sit in plane
+// s_b = (k + a + b) mod 2 and the other colour of the column in 1 - s_b; for
+// the two rows s_b1 = 1 - s_b0, so each row's theta neighbour across the
+// pair is the other row's column value.  zero != 0: first pass from a zero
+// iterate, x = b / D.
+template <typename T, int LTAG, int AHEAD = 2>
+__device__ __forceinline__ void d_gs_march2(Blk bk, Geo g, const T* __restrict__ G, long long gk,
+                                                      int bpa, int ch, const T* __restrict__ bv,
+                                                      T* __restrict__ x, int colour, int zero)
+{
+    March2 p;
+    if (!march2_pos(bk, g, bpa, ch, p)) return;
+    const long long sr = g.rowlen, r0 = p.r0, r1 = p.r0 + g.nh;
+    const int b0 = p.b0, b1 = b0 + 1, nh = g.nh, j = p.j, lane = p.lane;
+    const bool tlo = b0 > 0, thi = b1 < g.nt - 1;
+    // metrics of rows b0, b1 at plane a
+    auto metrics = [&](int a, T* m0, T* m1) {
+        const long long ci = (long long)a * g.nt + b0;
+        const bool rh = a < g.nr - 1;
+        m0[0] = G[ci];
+        m0[1] = rh ? G[ci + g.nt] : T(0);
+        m0[2] = G[4 * gk + ci];
+        m0[3] = G[4 * gk + ci + 1];
+        m0[4] = G[8 * gk + ci];
+        m1[0] = G[ci + 1];
+        m1[1] = rh ? G[ci + 1 + g.nt] : T(0);
+        m1[2] = G[4 * gk + ci + 1];
+        m1[3] = thi ? G[4 * gk + ci + 2] : T(0);
+        m1[4] = G[8 * gk + ci + 1];
+    };
+    if (zero) {
+        for (int a = p.a0; a < p.a1; a += AHEAD) {
+            T q0[AHEAD], q1[AHEAD];
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1) {
+                    const int s0 = (colour + a + u + b0) & 1;
+                    const long long base = (long long)(a + u) * sr;
+                    q0[u] = bv[s0 * g.P + base + r0];
+                    q1[u] = bv[(1 - s0) * g.P + base + r1];
+                }
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1) {
+                    const int s0 = (colour + a + u + b0) & 1;
+                    const long long base = (long long)(a + u) * sr;
+                    T m0[5], m1[5];
+                    metrics(a + u, m0, m1);
+                    const T D0 = -(m0[0] + m0[1] + m0[2] + m0[3] + T(2) * m0[4]);
+                    const T D1 = -(m1[0] + m1[1] + m1[2] + m1[3] + T(2) * m1[4]);
+                    x[s0 * g.P + base + r0] = q0[u] / D0;
+                    x[(1 - s0) * g.P + base + r1] = q1[u] / D1;
+                }
+        }
+        return;
+    }
+    const int jlo = j == 0 ? nh - 1 : j - 1, jhi = j == nh - 1 ? 0 : j + 1;
+    // the other-colour cell of row b's column at plane a (0 past the r-walls)
+    auto col = [&](int a, int b, long long r) -> T {
+        if (a < 0 || a >= g.nr) return T(0);
+        return x[((colour + a + b + 1) & 1) * g.P + (long long)a * sr + r];
+    };
+    // a row whose updated cells are in plane s needs the other colour at
+    // j - 1 (s = 0) or j + 1 (s = 1): loaded at the wavefront's ends
+    auto edge = [&](int s) { return !p.ring && (s == 0 ? lane == 0 : lane == 63); };
+    T m0 = col(p.a0 - 1, b0, r0), c0 = col(p.a0, b0, r0);
+    T m1 = col(p.a0 - 1, b1, r1), c1 = col(p.a0, b1, r1);
+    for (int a = p.a0; a < p.a1; a += AHEAD) {
+        T p0[AHEAD], p1[AHEAD], q0[AHEAD], q1[AHEAD], tm0[AHEAD], tp1[AHEAD], e0[AHEAD], e1[AHEAD];
+#pragma unroll
+        for (int u = 0; u < AHEAD; ++u) {
+            const int aa = a + u;
+            if (aa < p.a1) {
+                const int s0 = (colour + aa + b0) & 1, s1 = 1 - s0;
+                const long long base = (long long)aa * sr;
+                p0[u] = col(aa + 1, b0, r0);
+                p1[u] = col(aa + 1, b1, r1);
+                q0[u] = bv[s0 * g.P + base + r0];
+                q1[u] = bv[s1 * g.P + base + r1];
+                tm0[u] = tlo ? x[s0 * g.P + base + r0 - nh] : T(0);
+                tp1[u] = thi ? x[s1 * g.P + base + r1 + nh] : T(0);
+                e0[u] = edge(s0) ? x[s1 * g.P + base + r0 - j + (s0 == 0 ? jlo : jhi)] : T(0);
+                e1[u] = edge(s1) ? x[s0 * g.P + base + r1 - j + (s1 == 0 ? jlo : jhi)] : T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < AHEAD; ++u) {
+            const int aa = a + u;
+            if (aa < p.a1) {
+                const int s0 = (colour + aa + b0) & 1, s1 = 1 - s0;
+                const T n0 = __shfl(c0, s0 == 0 ? lane - 1 : lane + 1);
+                const T n1 = __shfl(c1, s1 == 0 ? lane - 1 : lane + 1);
+                const T on0 = edge(s0) ? e0[u] : n0;
+                const T on1 = edge(s1) ? e1[u] : n1;
+                T g0[5], g1[5];
+                metrics(aa, g0, g1);
+                // g[]: r low, r high, theta low, theta high, phi (both faces)
+                const T D0 = -(g0[0] + g0[1] + g0[2] + g0[3] + g0[4] + g0[4]);
+                const T D1 = -(g1[0] + g1[1] + g1[2] + g1[3] + g1[4] + g1[4]);
+                const T S0 = g0[1] * p0[u] + g0[0] * m0 + g0[3] * c1 + g0[2] * tm0[u] +
+                             g0[4] * (c0 + on0);
+                const T S1 = g1[1] * p1[u] + g1[0] * m1 + g1[3] * tp1[u] + g1[2] * c0 +
+                             g1[4] * (c1 + on1);
+                const long long base = (long long)aa * sr;
+                x[s0 * g.P + base + r0] = (q0[u] - S0) / D0;
+                x[s1 * g.P + base + r1] = (q1[u] - S1) / D1;
+                m0 = c0;
+                c0 = p0[u];
+                m1 = c1;
+                c1 = p1[u];
+            }
+        }
+    }
+}
+
+template <typename T, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_gs_march2(Geo g, const T* __restrict__ G, long long gk,
+                                                      int bpa, int ch, const T* __restrict__ bv,
+                                                      T* __restrict__ x, int colour, int zero)
+{
+    d_gs_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero);
+}
+
+// Column values of a row-pair thread at one plane: u = plane 0, v = plane 1
+// of rows b0 (suffix 0) and b1 (suffix 1).
+template <typename T>
+struct Col4 {
+    T u0, v0, u1, v1;
+};
+
+// Values a row-pair thread loads at plane a for (A x) of its four cells:
+// the columns at a+1 (the cell itself past the high r-wall), the theta
+// neighbours outside the pair (the cell itself past a theta-wall) and the
+// phi neighbours past the wavefront's ends (only lanes 0 and 63 of long
+// rings read them).
+template <typename T>
+struct Nb4 {
+    Col4<T> up;
+    T utm0, vtm0, utp1, vtp1;
+    T vjm0, vjm1, ujp0, ujp1;
+};
+
+template <typename T>
+__device__ __forceinline__ void march2_load(const Geo& g, const T* __restrict__ x, const March2& p,
+                                            int a, Nb4<T>& n)
+{
+    const int nh = g.nh, j = p.j;
+    const long long base = (long long)a * g.rowlen + p.r0;
+    const long long ab = a < g.nr - 1 ? base + g.rowlen : base;
+    n.up.u0 = x[ab];
+    n.up.v0 = x[g.P + ab];
+    n.up.u1 = x[ab + nh];
+    n.up.v1 = x[g.P + ab + nh];
+    const long long tl = p.b0 > 0 ? base - nh : base;
+    const long long th = p.b0 + 1 < g.nt - 1 ? base + 2 * nh : base + nh;
+    n.utm0 = x[tl];
+    n.vtm0 = x[g.P + tl];
+    n.utp1 = x[th];
+    n.vtp1 = x[g.P + th];
+    if (!p.ring && p.lane == 0) {
+        const long long jm = base - j + (j == 0 ? nh - 1 : j - 1);
+        n.vjm0 = x[g.P + jm];
+        n.vjm1 = x[g.P + jm + nh];
+    }
+    if (!p.ring && p.lane == 63) {
+        const long long jp = base - j + (j == nh - 1 ? 0 : j + 1);
+        n.ujp0 = x[jp];
+        n.ujp1 = x[jp + nh];
+    }
+}
+
+// Flux-form (A x) of one row's two cells (plane 0 cell 2j, plane 1 cell
+// 2j+1) from the row's column values at a-1 (um, vm), a (u, v), a+1 (up,
+// vp), its theta neighbours below (utm, vtm) and above (utp, vtp), and the
+// phi neighbours vjm (plane 1, j-1) and ujp (plane 0, j+1); the sums are
+// those of march_apply2.
+template <typename T>
+__device__ __forceinline__ void row_apply(const T* __restrict__ G, long long gk, long long ci,
+                                          bool rh, bool th, long long nt, T um, T u, T up, T vm,
+                                          T v, T vp, T utm, T utp, T vtm, T vtp, T vjm, T ujp,
+                                          T& y0, T& y1)
+{
+    const T grl = G[ci];
+    const T grh = rh ? G[ci + nt] : T(0);
+    const T gtl = G[4 * gk + ci];
+    const T gth = th ? G[4 * gk + ci + 1] : T(0);
+    const T gpp = G[8 * gk + ci];
+    y0 = grh * (up - u) - grl * (u - um) + gth * (utp - u) - gtl * (u - utm) + gpp * (v - u) -
+         gpp * (u - vjm);
+    y1 = grh * (vp - v) - grl * (v - vm) + gth * (vtp - v) - gtl * (v - vtm) + gpp * (ujp - v) -
+         gpp * (v - u);
+}
+
+// (A x) of the four cells of a row-pair thread at plane a.
+template <typename T>
+__device__ __forceinline__ void march2_apply(const Geo& g, const T* __restrict__ G, long long gk,
+                                             const March2& p, int a, const Col4<T>& cm,
+                                             const Col4<T>& c, const Nb4<T>& n, T y[4])
+{
+    const int lane = p.lane;
+    // phi neighbours inside the wavefront come from the adjacent lanes (the
+    // shuffles run on every lane; the ends of a long ring take the loads)
+    const T sv0 = __shfl(c.v0, lane - 1), sv1 = __shfl(c.v1, lane - 1);
+    const T su0 = __shfl(c.u0, lane + 1), su1 = __shfl(c.u1, lane + 1);
+    const T vjm0 = p.ring || lane > 0 ? sv0 : n.vjm0;
+    const T vjm1 = p.ring || lane > 0 ? sv1 : n.vjm1;
+    const T ujp0 = p.ring || lane < 63 ? su0 : n.ujp0;
+    const T ujp1 = p.ring || lane < 63 ? su1 : n.ujp1;
+    const long long ci = (long long)a * g.nt + p.b0;
+    const bool rh = a < g.nr - 1;
+    // row b0: theta below from memory (the cell itself at the wall), above = row b1
+    row_apply<T>(G, gk, ci, rh, true, g.nt, cm.u0, c.u0, n.up.u0, cm.v0, c.v0, n.up.v0,
+                 p.b0 > 0 ? n.utm0 : c.u0, c.u1, p.b0 > 0 ? n.vtm0 : c.v0, c.v1, vjm0, ujp0,
+                 y[0], y[1]);
+    // row b1: theta below = row b0, above from memory
+    const bool thi = p.b0 + 1 < g.nt - 1;
+    row_apply<T>(G, gk, ci + 1, rh, thi, g.nt, cm.u1, c.u1, n.up.u1, cm.v1, c.v1, n.up.v1, c.u0,
+                 thi ? n.utp1 : c.u1, c.v0, thi ? n.vtp1 : c.v1, vjm1, ujp1, y[2], y[3]);
+}
+
+template <typename T>
+__device__ __forceinline__ void march2_start(const Geo& g, const T* __restrict__ x,
+                                             const March2& p, Col4<T>& cm, Col4<T>& c)
+{
+    const long long base = (long long)p.a0 * g.rowlen + p.r0;
+    const long long bm = p.a0 > 0 ? base - g.rowlen : base;
+    c.u0 = x[base];
+    c.v0 = x[g.P + base];
+    c.u1 = x[base + g.nh];
+    c.v1 = x[g.P + base + g.nh];
+    cm.u0 = x[bm];
+    cm.v0 = x[g.P + bm];
+    cm.u1 = x[bm + g.nh];
+    cm.v1 = x[g.P + bm + g.nh];
+}
+
+// r = b - A x (and partial sums of r^2) over row pairs.
+template <typename T, int LTAG, int AHEAD = 1>
+__device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __restrict__ G,
+                                                            long long gk, int bpa, int ch,
+                                                            const T* __restrict__ bv,
+                                                            const T* __restrict__ x,
+                                                            T* __restrict__ r,
+                                                            double* __restrict__ partial)
+{
+    March2 p;
+    double acc = 0.0;
+    if (march2_pos(bk, g, bpa, ch, p)) {
+        Col4<T> cm, c;
+        march2_start<T>(g, x, p, cm, c);
+        const long long o[4] = {0, g.P, g.nh, g.P + g.nh}; // u0, v0, u1, v1
+        for (int a = p.a0; a < p.a1; a += AHEAD) {
+            Nb4<T> nb[AHEAD];
+            T bb[AHEAD][4];
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1) {
+                    march2_load<T>(g, x, p, a + u, nb[u]);
+                    const long long base = (long long)(a + u) * g.rowlen + p.r0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) bb[u][k] = bv[base + o[k]];
+                }
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1) {
+                    T y[4];
+                    march2_apply<T>(g, G, gk, p, a + u, cm, c, nb[u], y);
+                    const long long base = (long long)(a + u) * g.rowlen + p.r0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const T rk = bb[u][k] - y[k];
+                        r[base + o[k]] = rk;
+                        acc += (double)rk * (double)rk;
+                    }
+                    cm = c;
+                    c = nb[u].up;
+                }
+        }
+    }
+    if (partial) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partial[bk.L] = acc;
+    }
+}
+
+template <typename T, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_residual_march2(Geo g, const T* __restrict__ G,
+                                                            long long gk, int bpa, int ch,
+                                                            const T* __restrict__ bv,
+                                                            const T* __restrict__ x,
+                                                            T* __restrict__ r,
+                                                            double* __restrict__ partial)
+{
+    d_residual_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, r, partial);
+}
+
+// y = A x (and partial sums of y . dotv) over row pairs.
+template <typename T, int LTAG, int AHEAD = 1>
+__device__ __forceinline__ void d_apply_march2(Blk bk, Geo g, const T* __restrict__ G,
+                                                         long long gk, int bpa, int ch,
+                                                         const T* __restrict__ x,
+                                                         T* __restrict__ y,
+                                                         double* __restrict__ partial,
+                                                         const T* __restrict__ dotv)
+{
+    March2 p;
+    double acc = 0.0;
+    if (march2_pos(bk, g, bpa, ch, p)) {
+        Col4<T> cm, c;
+        march2_start<T>(g, x, p, cm, c);
+        const long long o[4] = {0, g.P, g.nh, g.P + g.nh};
+        for (int a = p.a0; a < p.a1; a += AHEAD) {
+            Nb4<T> nb[AHEAD];
+            T dv[AHEAD][4];
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1) {
+                    march2_load<T>(g, x, p, a + u, nb[u]);
+                    if (dotv) {
+                        const long long base = (long long)(a + u) * g.rowlen + p.r0;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) dv[u][k] = dotv[base + o[k]];
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u)
+                if (a + u < p.a1) {
+                    T yk[4];
+                    march2_apply<T>(g, G, gk, p, a + u, cm, c, nb[u], yk);
+                    const long long base = (long long)(a + u) * g.rowlen + p.r0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        y[base + o[k]] = yk[k];
+                        if (dotv) acc += (double)yk[k] * (double)dv[u][k];
+                    }
+                    cm = c;
+                    c = nb[u].up;
+                }
+        }
+    }
+    if (partial) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partial[bk.L] = acc;
+    }
+}
+
+template <typename T, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restrict__ G,
+                                                         long long gk, int bpa, int ch,
+                                                         const T* __restrict__ x,
+                                                         T* __restrict__ y,
+                                                         double* __restrict__ partial,
+                                                         const T* __restrict__ dotv)
+{
+    d_apply_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, x, y, partial, dotv);
+}
+
+// ---------------------------------------------------------------------------
 // Grid transfers (cell-centred, coarsening by 2 in every direction)
 // ---------------------------------------------------------------------------
 
@@ -628,6 +1121,13 @@ __global__ void __launch_bounds__(kBlock) k_apply_march(Geo g, const T* __restri
 // planes: the theta-phi part for one plane is formed once and used by every
 // r position that needs it.  Launch: grid = bpa * nchunks over the coarse
 // plane positions, `ch` coarse planes per chunk.
+
+// Two consecutive values of one parity plane (16 B for FP64, 8 B for FP32):
+// fine phi indices 2jc, 2jc+1 of a coarse column's cells.  Level vectors
+// are separate device allocations and every offset used is even, so the
+// accesses are aligned.
+template <typename T>
+using Vec2 = T __attribute__((ext_vector_type(2)));
 
 struct CoarseCol {
     int I0, I1, m, J, jc;
@@ -657,25 +1157,33 @@ __device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch
     const T w0 = T(0.25), w1 = T(0.75);
     long long rowo[4];
     for (int q = 0; q < 4; ++q) rowo[q] = (long long)clampi(2 * p.J - 1 + q, f.nt - 1) * f.nh;
-    long long co[6]; // fine phi positions 4jc-1 .. 4jc+4 (plane + index)
-    for (int o = 0; o < 6; ++o) {
-        int cc = 4 * p.jc - 1 + o;
-        cc = cc < 0 ? cc + f.np : (cc >= f.np ? cc - f.np : cc);
-        co[o] = (long long)(cc & 1) * f.P + (cc >> 1);
-    }
+    // fine phi positions 4jc-1 .. 4jc+4: 4jc .. 4jc+3 are the pairs at index
+    // 2jc, 2jc+1 of both planes (one 2-vector each); 4jc-1 is plane 1 index
+    // 2jc-1 and 4jc+4 plane 0 index 2jc+2 (wrapped in phi)
+    const long long cv = 2 * p.jc;
+    const long long cm = f.P + (p.jc == 0 ? f.nh - 1 : cv - 1);
+    const long long cp = p.jc == c.nh - 1 ? 0 : cv + 2;
     const T wq[4] = {w0, w1, w1, w0};
     // theta-phi restriction of fine plane a for K = 2jc (s0) and 2jc+1 (s1)
     auto plane = [&](int a, T& s0, T& s1) {
         const T* ra = r + (long long)clampi(a, f.nr - 1) * f.rowlen;
+        Vec2<T> e[4], o[4];
+        T v0[4], v5[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T* rr = ra + rowo[q];
+            e[q] = *reinterpret_cast<const Vec2<T>*>(rr + cv);
+            o[q] = *reinterpret_cast<const Vec2<T>*>(rr + f.P + cv);
+            v0[q] = rr[cm];
+            v5[q] = rr[cp];
+        }
         s0 = T(0);
         s1 = T(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const T* rr = ra + rowo[q];
-            const T v0 = rr[co[0]], v1 = rr[co[1]], v2 = rr[co[2]];
-            const T v3 = rr[co[3]], v4 = rr[co[4]], v5 = rr[co[5]];
-            s0 += wq[q] * (w0 * v0 + w1 * v1 + w1 * v2 + w0 * v3);
-            s1 += wq[q] * (w0 * v2 + w1 * v3 + w1 * v4 + w0 * v5);
+            const T v1 = e[q].x, v2 = o[q].x, v3 = e[q].y, v4 = o[q].y;
+            s0 += wq[q] * (w0 * v0[q] + w1 * v1 + w1 * v2 + w0 * v3);
+            s1 += wq[q] * (w0 * v2 + w1 * v3 + w1 * v4 + w0 * v5[q]);
         }
     };
     T pa0, pa1, pb0, pb1;
@@ -741,21 +1249,34 @@ __device__ __forceinline__ void d_prolong(Blk bk, Geo f, Geo c, int bpa, int ch,
     T tm[2][4], t0[2][4], tp[2][4];
     plane(p.I0 - 1, tm);
     plane(p.I0, t0);
-    // fine offsets inside a fine plane of (row 2J + rr, phi 4jc + t)
-    long long fo[2][4];
+    // fine phi 4jc + t sits in plane t & 1 at index 2jc + (t >> 1): per fine
+    // row and plane the thread owns the 2-vector at index 2jc (t = s, s + 2)
+    long long fo[2][2];
     for (int rr = 0; rr < 2; ++rr)
-        for (int t = 0; t < 4; ++t)
-            fo[rr][t] = (long long)(t & 1) * f.P + (long long)(2 * p.J + rr) * f.nh + 2 * p.jc + (t >> 1);
+        for (int sp = 0; sp < 2; ++sp)
+            fo[rr][sp] = (long long)sp * f.P + (long long)(2 * p.J + rr) * f.nh + 2 * p.jc;
     for (int I = p.I0; I < p.I1; ++I) {
         plane(I + 1, tp);
         T* x0 = x + (long long)(2 * I) * f.rowlen;
         T* x1 = x0 + f.rowlen;
+        Vec2<T> y0[2][2], y1[2][2];
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                x0[fo[rr][t]] += w0 * t0[rr][t] + w1 * tm[rr][t];
-                x1[fo[rr][t]] += w0 * t0[rr][t] + w1 * tp[rr][t];
+            for (int sp = 0; sp < 2; ++sp) {
+                y0[rr][sp] = *reinterpret_cast<const Vec2<T>*>(x0 + fo[rr][sp]);
+                y1[rr][sp] = *reinterpret_cast<const Vec2<T>*>(x1 + fo[rr][sp]);
+            }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp) {
+                y0[rr][sp].x += w0 * t0[rr][sp] + w1 * tm[rr][sp];
+                y0[rr][sp].y += w0 * t0[rr][sp + 2] + w1 * tm[rr][sp + 2];
+                y1[rr][sp].x += w0 * t0[rr][sp] + w1 * tp[rr][sp];
+                y1[rr][sp].y += w0 * t0[rr][sp + 2] + w1 * tp[rr][sp + 2];
+                *reinterpret_cast<Vec2<T>*>(x0 + fo[rr][sp]) = y0[rr][sp];
+                *reinterpret_cast<Vec2<T>*>(x1 + fo[rr][sp]) = y1[rr][sp];
             }
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr)
@@ -1116,9 +1637,8 @@ struct MarchShape {
 // Marching launch over the planes of g: bpa blocks per plane, chunks of ch
 // planes; ch <= 0 picks chunks that give about 2048 blocks (one resident
 // wave of 8 blocks per CU).
-__host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
+__host__ __device__ inline MarchShape chunked(const Geo& g, int bpa, int ch)
 {
-    const int bpa = cdiv(g.rowlen, kBlock);
     if (ch <= 0) {
         int nchunks = cdiv(2048, bpa);
         nchunks = nchunks < 1 ? 1 : (nchunks > g.nr ? g.nr : nchunks);
@@ -1126,6 +1646,20 @@ __host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
     }
     if (ch > g.nr) ch = g.nr;
     return MarchShape{bpa, ch, bpa * cdiv(g.nr, ch)};
+}
+__host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
+{
+    return chunked(g, cdiv(g.rowlen, kBlock), ch);
+}
+// Row-pair kernels: bpa blocks over the (n_theta / 2) * (n_phi / 2)
+// positions of a plane.  stencil_shape: the marching launch a level uses.
+__host__ __device__ inline MarchShape march2_shape(const Geo& g, int ch = 0)
+{
+    return chunked(g, cdiv((long long)(g.nt / 2) * g.nh, kBlock), ch);
+}
+__host__ __device__ inline MarchShape stencil_shape(const Geo& g, int ch = 0)
+{
+    return row_pairs(g) ? march2_shape(g, ch) : march_shape(g, ch);
 }
 
 // blocks per plane of the generic colour pass and of generic stencil kernels
@@ -1191,8 +1725,10 @@ __global__ void __launch_bounds__(kBlock) kb_gs_march(const BItem* __restrict__ 
 {
     CPS_BATCH_BLOCK
     const LDesc<T>& d = pd[it.prob].lv[level];
-    const MarchShape ms = march_shape(d.g, d.gs_ch);
-    if (d.g.nh % 64 == 0)
+    const MarchShape ms = stencil_shape(d.g, d.gs_ch);
+    if (row_pairs(d.g))
+        d_gs_march2<T, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, colour, zero);
+    else if (d.g.nh % 64 == 0)
         d_gs_march<T, true, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, colour, zero);
     else
         d_gs_march<T, false, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, colour, zero);
@@ -1224,8 +1760,9 @@ __global__ void __launch_bounds__(kBlock) kb_residual(const BItem* __restrict__ 
     const LDesc<T>& d = pd[it.prob].lv[level];
     const bool u = d.g.nh % 64 == 0;
     if constexpr (MODE == MODE_ORTHO && AXI) {
-        const MarchShape ms = march_shape(d.g);
-        if (u) d_residual_march<T, true, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
+        const MarchShape ms = stencil_shape(d.g);
+        if (row_pairs(d.g)) d_residual_march2<T, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
+        else if (u) d_residual_march<T, true, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
         else d_residual_march<T, false, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
     } else {
         const int bpa = cdiv(d.g.rowlen, kBlock);
@@ -1314,8 +1851,9 @@ __global__ void __launch_bounds__(kBlock) kb_apply64(const BItem* __restrict__ i
     const bool u = g.nh % 64 == 0;
     const double* dv = dot >= 0 ? P.vec[dot] : nullptr;
     if constexpr (MODE == MODE_ORTHO && AXI) {
-        const MarchShape ms = march_shape(g);
-        if (u) d_apply_march<double, true, 0>(bk, g, P.G64, P.gk64, ms.bpa, ms.ch, P.vec[in], P.vec[out], P.partial, dv);
+        const MarchShape ms = stencil_shape(g);
+        if (row_pairs(g)) d_apply_march2<double, 0>(bk, g, P.G64, P.gk64, ms.bpa, ms.ch, P.vec[in], P.vec[out], P.partial, dv);
+        else if (u) d_apply_march<double, true, 0>(bk, g, P.G64, P.gk64, ms.bpa, ms.ch, P.vec[in], P.vec[out], P.partial, dv);
         else d_apply_march<double, false, 0>(bk, g, P.G64, P.gk64, ms.bpa, ms.ch, P.vec[in], P.vec[out], P.partial, dv);
     } else {
         const int bpa = cdiv(g.rowlen, kBlock);

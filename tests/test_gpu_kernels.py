@@ -28,6 +28,11 @@ CASES = [
     ("identity-8x12x16", Shell(8, 12, 16, map=MAP_IDENTITY), 0),
     ("sphere-vertex-16x16x16", Shell(16, 16, 16), 1),
     ("triaxial-vertex-12x12x16", Shell(12, 12, 16, map=MAP_TRIAXIAL, flattening=0.1, skew=0.2), 1),
+    # n_phi / 2 a multiple of 64: LDS-staged tiles of 4 theta rows x 64 phi;
+    # one segment per row (phi wraps inside the wavefront), a tile row
+    # group overhanging n_theta, and rows of 2 segments (phi halo loads)
+    ("sphere-tile-8x6x128", Shell(8, 6, 128, radial_stretch=2.0), 0),
+    ("sphere-tile-6x10x256", Shell(6, 10, 256), 0),
 ]
 
 
