@@ -254,8 +254,11 @@ inline bool marching(const cps_handle* h) { return h->mode == MODE_ORTHO && h->a
 
 // One colour pass; zero: the iterate is zero before this pass (two colours
 // only), so the other colour is not read and need not be initialised.
+// dot (marching levels only): per-block partial sums of b . x over the
+// updated cells, written at dot[0 .. grid); returns the number written.
 template <typename T>
-void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero = false)
+long long gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero = false,
+                  double* dot = nullptr)
 {
     const Level<T> L = view<T>(h, l);
     const int rowlen = h->ncol == 2 ? L.g.rowlen : L.g.rowlen / 2;
@@ -267,43 +270,56 @@ void gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero = fal
         if (row_pairs(L.g)) {
             if (l == 0)
                 k_gs_march2<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch,
-                                                                    b, x, colour, z);
+                                                                    b, x, colour, z, dot);
             else
                 k_gs_march2<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch,
-                                                                    b, x, colour, z);
+                                                                    b, x, colour, z, dot);
             LAUNCH_CHECK();
-            return;
+            return dot ? ms.grid : 0;
         }
         auto launch = [&](auto U, auto T_) {
             k_gs_march<T, decltype(U)::value, decltype(T_)::value>
-                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour, z);
+                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour, z,
+                                                    dot);
         };
         const bool u = L.g.nh % 64 == 0;
         if (l == 0) u ? launch(BA<true>{}, IM<0>{}) : launch(BA<false>{}, IM<0>{});
         else u ? launch(BA<true>{}, IM<1>{}) : launch(BA<false>{}, IM<1>{});
         LAUNCH_CHECK();
-        return;
+        return dot ? ms.grid : 0;
     }
+    if (dot) fail(CPS_E_INVALID, "internal: fused dot on a non-marching level");
     dispatch4(h->mode, h->axi, L.g.nh % 64 == 0, l == 0 ? 0 : 1, [&](auto M, auto A, auto U, auto T_) {
         k_gs<T, decltype(M)::value, decltype(A)::value, decltype(U)::value, decltype(T_)::value>
             <<<grid_of(L.g.nr, bpa), kBlock, 0, h->stream>>>(L.g, L.G, L.gk, bpa, b, x, colour,
                                                              h->ncol, z);
     });
     LAUNCH_CHECK();
+    return 0;
 }
 
 // Gauss-Seidel sweeps over all colours (reverse order for post-smoothing).
 // from_zero: x is zero on entry; with two colours it is then not even read
 // (nor initialised) before the first pass writes it, otherwise it is filled.
+// dot (two colours on marching levels): the last two passes, which leave
+// every cell final, write partial sums of b . x at dot[0 ..) and after
+// them; returns the number of partial sums written (0 without dot).
 template <typename T>
-void smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse,
-            bool from_zero = false)
+long long smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse,
+                 bool from_zero = false, double* dot = nullptr)
 {
     const bool skip = from_zero && h->ncol == 2;
     if (from_zero && !skip) fill<T>(h, x, h->lv[l].n, T(0));
+    long long parts = 0;
+    const int last = sweeps * h->ncol;
     for (int s = 0; s < sweeps; ++s)
-        for (int k = 0; k < h->ncol; ++k)
-            gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x, skip && s == 0 && k == 0);
+        for (int k = 0; k < h->ncol; ++k) {
+            const int pass = s * h->ncol + k;
+            const bool with_dot = dot && h->ncol == 2 && pass >= last - 2;
+            parts += gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x, skip && pass == 0,
+                                with_dot ? dot + parts : nullptr);
+        }
+    return parts;
 }
 
 // r = b - A x; partial sums of r^2 into h->partial when want_norm.
@@ -384,9 +400,9 @@ long long apply(cps_handle* h, int l, const T* x, T* y, const T* dotv)
     return grid_of(L.g.nr, bpa);
 }
 
-void reduce(cps_handle* h, long long nparts, int slot)
+void reduce(cps_handle* h, long long nparts, int slot, long long first = 0)
 {
-    k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p, nparts, h->sc.p + slot);
+    k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p + first, nparts, h->sc.p + slot);
     LAUNCH_CHECK();
 }
 
@@ -429,13 +445,15 @@ void coarse_solve(cps_handle* h, const T* b, T* e)
 }
 
 // One V(2,2) cycle with level-0 right-hand side b0 and iterate x0 (in place).
+// dot: the last level-0 passes leave partial sums of b0 . x0 in h->partial;
+// returns their number (0 when the cycle cannot provide them).
 template <typename T>
-void vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false)
+long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool dot = false)
 {
     const int L = h->L;
     if (L == 1) {
         coarse_solve<T>(h, b0, x0);
-        return;
+        return 0;
     }
     for (int l = 0; l < L - 1; ++l) {
         const T* b = l == 0 ? b0 : bl<T>(h, l);
@@ -446,29 +464,50 @@ void vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false)
         restrict_to<T>(h, l, rl<T>(h, l), bl<T>(h, l + 1));
     }
     coarse_solve<T>(h, bl<T>(h, L - 1), xl<T>(h, L - 1));
+    long long parts = 0;
     for (int l = L - 2; l >= 0; --l) {
         const T* b = l == 0 ? b0 : bl<T>(h, l);
         T* x = l == 0 ? x0 : xl<T>(h, l);
         prolong_add<T>(h, l, xl<T>(h, l + 1), x);
-        smooth<T>(h, l, b, x, 2, true);
+        const bool d = dot && l == 0 && marching(h);
+        parts = smooth<T>(h, l, b, x, 2, true, false, d ? h->partial.p : nullptr);
     }
+    return parts;
 }
 
 // out = M^-1 in : one V-cycle from zero, FP64 or FP32 inside (scaled by
-// sc[S_SCALE] so that FP32 sees O(1) values).
-void precondition(cps_handle* h, const double* in, double* out)
+// sc[S_SCALE] so that FP32 sees O(1) values).  rz_slot >= 0: also
+// sc[rz_slot] = in . out; zq: also sc[S_ZQ] = out . zq.  Both are taken
+// from passes that already touch the vectors where possible (the last
+// level-0 smoothing passes in FP64, the cast back in the mixed form).
+void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1,
+                  const double* zq = nullptr)
 {
     const long long n = h->lv[0].n;
     if (h->opts.precision == 0) {
-        vcycle<double>(h, in, out, true);
+        const long long parts = vcycle<double>(h, in, out, true, rz_slot >= 0);
+        if (rz_slot >= 0) {
+            if (parts) reduce(h, parts, rz_slot);
+            else dot<double, double>(h, n, in, out, rz_slot);
+        }
+        if (zq) dot<double, double>(h, n, out, zq, S_ZQ);
     } else {
         float* b = h->lv[0].b32.p;
         float* x = h->lv[0].x32.p;
         k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, in, b, h->sc.p, S_SCALE, 1);
         LAUNCH_CHECK();
         vcycle<float>(h, b, x, true);
-        k_cast<float, double><<<nblk(n), kBlock, 0, h->stream>>>(n, x, out, h->sc.p, S_SCALE, 0);
+        if (rz_slot < 0 && !zq) {
+            k_cast<float, double><<<nblk(n), kBlock, 0, h->stream>>>(n, x, out, h->sc.p, S_SCALE, 0);
+            LAUNCH_CHECK();
+            return;
+        }
+        const int vg = vgrid(n);
+        k_cast_dots<<<vg, kBlock, 0, h->stream>>>(n, x, out, h->sc.p, S_SCALE, in, zq,
+                                                  h->partial.p, h->partial.p + vg);
         LAUNCH_CHECK();
+        if (rz_slot >= 0) reduce(h, vg, rz_slot);
+        if (zq) reduce(h, vg, S_ZQ, vg);
     }
 }
 
@@ -689,7 +728,8 @@ void build(cps_handle* h)
         }
     }
     const long long n0 = h->lv[0].n;
-    h->partial.alloc(nblk(n0) + 64);
+    // two passes' (or two reductions') partial sums side by side
+    h->partial.alloc(2 * std::max<long long>(nblk(n0), kMaxGrid) + 64);
     h->sc.alloc(S_COUNT);
     HIPC(hipHostMalloc(&h->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
     h->x0.alloc(n0);
@@ -699,9 +739,10 @@ void build(cps_handle* h)
         h->z.alloc(n0);
         h->pd.alloc(n0);
         h->q.alloc(n0);
+        h->ph.alloc(n0); // BiCGStab's M^-1 p, or the second CG direction buffer
         if (h->mode != MODE_ORTHO) {
             h->r0.alloc(n0); h->v.alloc(n0); h->s.alloc(n0); h->t.alloc(n0);
-            h->ph.alloc(n0); h->sh.alloc(n0);
+            h->sh.alloc(n0);
         }
     }
     autotune(h, h->opts.tune);
@@ -800,20 +841,24 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             }
         } else if (h->mode == MODE_ORTHO) {
             // preconditioned CG; flexible (Polak-Ribiere) when the
-            // preconditioner runs in FP32
+            // preconditioner runs in FP32.  The search direction alternates
+            // between two buffers: p = z + beta p_old is formed inside the
+            // product q = A p where the level allows it.
             const int flexible = mixed ? 1 : 0;
             double* r = h->r.p;
             double* z = h->z.p;
             double* p = h->pd.p;
+            double* pn = h->ph.p;
             double* q = h->q.p;
+            const Geo& g0 = h->lv[0].geo;
+            const bool fused = row_pairs(g0);
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, r);
             LAUNCH_CHECK();
-            precondition(h, r, z);
-            dot<double, double>(h, n, r, z, S_RZ);
+            precondition(h, r, z, S_RZ);
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, z, p);
             LAUNCH_CHECK();
+            reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
             for (it = 1; it <= maxit; ++it) {
-                reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
                 SCALAR_KERNEL(h, k_cg_alpha);
                 k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, p, q, h->partial.p);
                 LAUNCH_CHECK();
@@ -822,12 +867,23 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                 if (st != CPS_E_NOT_CONVERGED) break;
                 k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
                 LAUNCH_CHECK();
-                precondition(h, r, z);
-                dot<double, double>(h, n, r, z, S_RZ);
-                if (flexible) dot<double, double>(h, n, z, q, S_ZQ);
+                precondition(h, r, z, S_RZ, flexible ? q : nullptr);
                 k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
-                k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
                 LAUNCH_CHECK();
+                if (fused) {
+                    const MarchShape ms = stencil_shape(g0);
+                    ProfScope ps(h, CPS_KERNEL_APPLY, 0);
+                    k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
+                        g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, p, h->sc.p + S_BETA,
+                        pn, q, h->partial.p);
+                    LAUNCH_CHECK();
+                    reduce(h, ms.grid, S_PQ);
+                    std::swap(p, pn);
+                } else {
+                    k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
+                    LAUNCH_CHECK();
+                    reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
+                }
             }
         } else {
             // BiCGStab, right-preconditioned by the V-cycle

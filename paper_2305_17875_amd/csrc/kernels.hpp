@@ -443,13 +443,12 @@ constexpr int kAhead2 = 2;
 // and reads only the other colour, so loads may run ahead of the stores.
 // zero != 0: first pass from a zero iterate (the other colour is taken as 0
 // and not read; it need not be initialised), x = b / D.
-template <typename T, bool UROW, int LTAG, int AHEAD = kAhead>
-__device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ G, long long gk,
-                                                     int bpa, int ch, const T* __restrict__ bv,
-                                                     T* __restrict__ x, int colour, int zero)
+
+template <typename T, int AHEAD>
+__device__ __forceinline__ void gs_march_body(const Geo& g, const T* __restrict__ G, long long gk,
+                                              const March& p, const T* __restrict__ bv,
+                                              T* __restrict__ x, int colour, int zero, double& acc)
 {
-    March p;
-    if (!march_pos<UROW>(bk, g, bpa, ch, p)) return;
     const int b = p.b;
     const bool thi = b < g.nt - 1;
     // metrics of the column at plane a: D and the five face values
@@ -517,7 +516,9 @@ __device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ 
                 const T D = -(grl + grh + gtl + gth + gpp + gpp);
                 const T S = grh * op[u] + grl * om + gth * tp[u] + gtl * tm[u] + gpp * (o0 + on[u]);
                 const int s = (colour + aa + b) & 1;
-                x[s * g.P + (long long)aa * sr + p.m] = (bb[u] - S) / D;
+                const T xn = (bb[u] - S) / D;
+                x[s * g.P + (long long)aa * sr + p.m] = xn;
+                acc += (double)bb[u] * (double)xn;
                 om = o0;
                 o0 = op[u];
             }
@@ -525,12 +526,32 @@ __device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ 
     }
 }
 
+// dot != nullptr (non-zero passes): per-block partial sums of b_c x_c over
+// the cells the pass updates, with their new values.  The last two passes
+// of a sweep update every cell once more and leave it final, so their sums
+// give b . x for the smoothed iterate without another pass over memory.
+template <typename T, bool UROW, int LTAG, int AHEAD = kAhead>
+__device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ G, long long gk,
+                                                     int bpa, int ch, const T* __restrict__ bv,
+                                                     T* __restrict__ x, int colour, int zero,
+                                                     double* __restrict__ dot = nullptr)
+{
+    March p;
+    double acc = 0.0;
+    if (march_pos<UROW>(bk, g, bpa, ch, p)) gs_march_body<T, AHEAD>(g, G, gk, p, bv, x, colour, zero, acc);
+    if (dot) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) dot[bk.L] = acc;
+    }
+}
+
 template <typename T, bool UROW, int LTAG>
 __global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict__ G, long long gk,
                                                      int bpa, int ch, const T* __restrict__ bv,
-                                                     T* __restrict__ x, int colour, int zero)
+                                                     T* __restrict__ x, int colour, int zero,
+                                                     double* __restrict__ dot)
 {
-    d_gs_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero);
+    d_gs_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero, dot);
 }
 
 
@@ -755,13 +776,12 @@ __device__ __forceinline__ bool march2_pos(Blk bk, const Geo& g, int bpa, int ch
 // the two rows s_b1 = 1 - s_b0, so each row's theta neighbour across the
 // pair is the other row's column value.  zero != 0: first pass from a zero
 // iterate, x = b / D.
-template <typename T, int LTAG, int AHEAD = 2>
-__device__ __forceinline__ void d_gs_march2(Blk bk, Geo g, const T* __restrict__ G, long long gk,
-                                                      int bpa, int ch, const T* __restrict__ bv,
-                                                      T* __restrict__ x, int colour, int zero)
+template <typename T, int AHEAD>
+__device__ __forceinline__ void gs_march2_body(const Geo& g, const T* __restrict__ G, long long gk,
+                                               const March2& p, const T* __restrict__ bv,
+                                               T* __restrict__ x, int colour, int zero,
+                                               double& acc)
 {
-    March2 p;
-    if (!march2_pos(bk, g, bpa, ch, p)) return;
     const long long sr = g.rowlen, r0 = p.r0, r1 = p.r0 + g.nh;
     const int b0 = p.b0, b1 = b0 + 1, nh = g.nh, j = p.j, lane = p.lane;
     const bool tlo = b0 > 0, thi = b1 < g.nt - 1;
@@ -854,8 +874,10 @@ __device__ __forceinline__ void d_gs_march2(Blk bk, Geo g, const T* __restrict__
                 const T S1 = g1[1] * p1[u] + g1[0] * m1 + g1[3] * tp1[u] + g1[2] * c0 +
                              g1[4] * (c1 + on1);
                 const long long base = (long long)aa * sr;
-                x[s0 * g.P + base + r0] = (q0[u] - S0) / D0;
-                x[s1 * g.P + base + r1] = (q1[u] - S1) / D1;
+                const T x0n = (q0[u] - S0) / D0, x1n = (q1[u] - S1) / D1;
+                x[s0 * g.P + base + r0] = x0n;
+                x[s1 * g.P + base + r1] = x1n;
+                acc += (double)q0[u] * (double)x0n + (double)q1[u] * (double)x1n;
                 m0 = c0;
                 c0 = p0[u];
                 m1 = c1;
@@ -865,12 +887,29 @@ __device__ __forceinline__ void d_gs_march2(Blk bk, Geo g, const T* __restrict__
     }
 }
 
+// dot: as for d_gs_march.
+template <typename T, int LTAG, int AHEAD = 2>
+__device__ __forceinline__ void d_gs_march2(Blk bk, Geo g, const T* __restrict__ G, long long gk,
+                                                      int bpa, int ch, const T* __restrict__ bv,
+                                                      T* __restrict__ x, int colour, int zero,
+                                                      double* __restrict__ dot = nullptr)
+{
+    March2 p;
+    double acc = 0.0;
+    if (march2_pos(bk, g, bpa, ch, p)) gs_march2_body<T, AHEAD>(g, G, gk, p, bv, x, colour, zero, acc);
+    if (dot) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) dot[bk.L] = acc;
+    }
+}
+
 template <typename T, int LTAG>
 __global__ void __launch_bounds__(kBlock) k_gs_march2(Geo g, const T* __restrict__ G, long long gk,
                                                       int bpa, int ch, const T* __restrict__ bv,
-                                                      T* __restrict__ x, int colour, int zero)
+                                                      T* __restrict__ x, int colour, int zero,
+                                                      double* __restrict__ dot)
 {
-    d_gs_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero);
+    d_gs_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero, dot);
 }
 
 // Column values of a row-pair thread at one plane: u = plane 0, v = plane 1
@@ -892,32 +931,47 @@ struct Nb4 {
     T vjm0, vjm1, ujp0, ujp1;
 };
 
+// Element access of the field a row-pair stencil kernel reads: a plain
+// array, or the search direction p = z + beta p_old formed where it is read.
 template <typename T>
-__device__ __forceinline__ void march2_load(const Geo& g, const T* __restrict__ x, const March2& p,
-                                            int a, Nb4<T>& n)
+struct Plain {
+    const T* __restrict__ x;
+    __device__ __forceinline__ T operator()(long long i) const { return x[i]; }
+};
+template <typename T>
+struct Dir {
+    const T* __restrict__ z;
+    const T* __restrict__ p;
+    T beta;
+    __device__ __forceinline__ T operator()(long long i) const { return z[i] + beta * p[i]; }
+};
+
+template <typename T, typename X>
+__device__ __forceinline__ void march2_load(const Geo& g, const X& x, const March2& p, int a,
+                                            Nb4<T>& n)
 {
     const int nh = g.nh, j = p.j;
     const long long base = (long long)a * g.rowlen + p.r0;
     const long long ab = a < g.nr - 1 ? base + g.rowlen : base;
-    n.up.u0 = x[ab];
-    n.up.v0 = x[g.P + ab];
-    n.up.u1 = x[ab + nh];
-    n.up.v1 = x[g.P + ab + nh];
+    n.up.u0 = x(ab);
+    n.up.v0 = x(g.P + ab);
+    n.up.u1 = x(ab + nh);
+    n.up.v1 = x(g.P + ab + nh);
     const long long tl = p.b0 > 0 ? base - nh : base;
     const long long th = p.b0 + 1 < g.nt - 1 ? base + 2 * nh : base + nh;
-    n.utm0 = x[tl];
-    n.vtm0 = x[g.P + tl];
-    n.utp1 = x[th];
-    n.vtp1 = x[g.P + th];
+    n.utm0 = x(tl);
+    n.vtm0 = x(g.P + tl);
+    n.utp1 = x(th);
+    n.vtp1 = x(g.P + th);
     if (!p.ring && p.lane == 0) {
         const long long jm = base - j + (j == 0 ? nh - 1 : j - 1);
-        n.vjm0 = x[g.P + jm];
-        n.vjm1 = x[g.P + jm + nh];
+        n.vjm0 = x(g.P + jm);
+        n.vjm1 = x(g.P + jm + nh);
     }
     if (!p.ring && p.lane == 63) {
         const long long jp = base - j + (j == nh - 1 ? 0 : j + 1);
-        n.ujp0 = x[jp];
-        n.ujp1 = x[jp + nh];
+        n.ujp0 = x(jp);
+        n.ujp1 = x(jp + nh);
     }
 }
 
@@ -970,20 +1024,20 @@ __device__ __forceinline__ void march2_apply(const Geo& g, const T* __restrict__
                  thi ? n.utp1 : c.u1, c.v0, thi ? n.vtp1 : c.v1, vjm1, ujp1, y[2], y[3]);
 }
 
-template <typename T>
-__device__ __forceinline__ void march2_start(const Geo& g, const T* __restrict__ x,
-                                             const March2& p, Col4<T>& cm, Col4<T>& c)
+template <typename T, typename X>
+__device__ __forceinline__ void march2_start(const Geo& g, const X& x, const March2& p,
+                                             Col4<T>& cm, Col4<T>& c)
 {
     const long long base = (long long)p.a0 * g.rowlen + p.r0;
     const long long bm = p.a0 > 0 ? base - g.rowlen : base;
-    c.u0 = x[base];
-    c.v0 = x[g.P + base];
-    c.u1 = x[base + g.nh];
-    c.v1 = x[g.P + base + g.nh];
-    cm.u0 = x[bm];
-    cm.v0 = x[g.P + bm];
-    cm.u1 = x[bm + g.nh];
-    cm.v1 = x[g.P + bm + g.nh];
+    c.u0 = x(base);
+    c.v0 = x(g.P + base);
+    c.u1 = x(base + g.nh);
+    c.v1 = x(g.P + base + g.nh);
+    cm.u0 = x(bm);
+    cm.v0 = x(g.P + bm);
+    cm.u1 = x(bm + g.nh);
+    cm.v1 = x(g.P + bm + g.nh);
 }
 
 // r = b - A x (and partial sums of r^2) over row pairs.
@@ -999,7 +1053,7 @@ __device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __rest
     double acc = 0.0;
     if (march2_pos(bk, g, bpa, ch, p)) {
         Col4<T> cm, c;
-        march2_start<T>(g, x, p, cm, c);
+        march2_start<T>(g, Plain<T>{x}, p, cm, c);
         const long long o[4] = {0, g.P, g.nh, g.P + g.nh}; // u0, v0, u1, v1
         for (int a = p.a0; a < p.a1; a += AHEAD) {
             Nb4<T> nb[AHEAD];
@@ -1007,7 +1061,7 @@ __device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __rest
 #pragma unroll
             for (int u = 0; u < AHEAD; ++u)
                 if (a + u < p.a1) {
-                    march2_load<T>(g, x, p, a + u, nb[u]);
+                    march2_load<T>(g, Plain<T>{x}, p, a + u, nb[u]);
                     const long long base = (long long)(a + u) * g.rowlen + p.r0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) bb[u][k] = bv[base + o[k]];
@@ -1059,7 +1113,7 @@ __device__ __forceinline__ void d_apply_march2(Blk bk, Geo g, const T* __restric
     double acc = 0.0;
     if (march2_pos(bk, g, bpa, ch, p)) {
         Col4<T> cm, c;
-        march2_start<T>(g, x, p, cm, c);
+        march2_start<T>(g, Plain<T>{x}, p, cm, c);
         const long long o[4] = {0, g.P, g.nh, g.P + g.nh};
         for (int a = p.a0; a < p.a1; a += AHEAD) {
             Nb4<T> nb[AHEAD];
@@ -1067,7 +1121,7 @@ __device__ __forceinline__ void d_apply_march2(Blk bk, Geo g, const T* __restric
 #pragma unroll
             for (int u = 0; u < AHEAD; ++u)
                 if (a + u < p.a1) {
-                    march2_load<T>(g, x, p, a + u, nb[u]);
+                    march2_load<T>(g, Plain<T>{x}, p, a + u, nb[u]);
                     if (dotv) {
                         const long long base = (long long)(a + u) * g.rowlen + p.r0;
 #pragma unroll
@@ -1105,6 +1159,61 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
                                                          const T* __restrict__ dotv)
 {
     d_apply_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, x, y, partial, dotv);
+}
+
+// Conjugate-gradient direction and product in one pass over row pairs:
+// p = z + beta p_old (beta: a device scalar) is formed wherever it is read,
+// written for the thread's own cells, and q = A p with partial sums of
+// p . q.  p must not alias p_old (other threads still read p_old).
+template <typename T, int LTAG>
+__device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __restrict__ G,
+                                                             long long gk, int bpa, int ch,
+                                                             const T* __restrict__ z,
+                                                             const T* __restrict__ pold,
+                                                             const double* __restrict__ beta,
+                                                             T* __restrict__ pnew,
+                                                             T* __restrict__ q,
+                                                             double* __restrict__ partial)
+{
+    March2 p;
+    double acc = 0.0;
+    if (march2_pos(bk, g, bpa, ch, p)) {
+        const Dir<T> X{z, pold, (T)*beta};
+        Col4<T> cm, c;
+        march2_start<T>(g, X, p, cm, c);
+        const long long o[4] = {0, g.P, g.nh, g.P + g.nh};
+        for (int a = p.a0; a < p.a1; ++a) {
+            Nb4<T> nb;
+            march2_load<T>(g, X, p, a, nb);
+            T yk[4];
+            march2_apply<T>(g, G, gk, p, a, cm, c, nb, yk);
+            const long long base = (long long)a * g.rowlen + p.r0;
+            const T own[4] = {c.u0, c.v0, c.u1, c.v1};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                pnew[base + o[k]] = own[k];
+                q[base + o[k]] = yk[k];
+                acc += (double)yk[k] * (double)own[k];
+            }
+            cm = c;
+            c = nb.up;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[bk.L] = acc;
+}
+
+template <typename T, int LTAG>
+__global__ void __launch_bounds__(kBlock) k_apply_dir_march2(Geo g, const T* __restrict__ G,
+                                                             long long gk, int bpa, int ch,
+                                                             const T* __restrict__ z,
+                                                             const T* __restrict__ pold,
+                                                             const double* __restrict__ beta,
+                                                             T* __restrict__ pnew,
+                                                             T* __restrict__ q,
+                                                             double* __restrict__ partial)
+{
+    d_apply_dir_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, z, pold, beta, pnew, q, partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -1428,6 +1537,34 @@ __global__ void __launch_bounds__(kBlock) k_cast(long long n, const T* __restric
                                                  int slot, int invert)
 {
     d_cast<T, U>(self_blk(), n, x, y, sc, slot, invert);
+}
+
+// z = (double) x * sc[slot] (the cast of k_cast) with per-block partial
+// sums of r . z and, when q is given, of q . z, in one grid-stride pass.
+__global__ void __launch_bounds__(kBlock) k_cast_dots(long long n, const float* __restrict__ x,
+                                                      double* __restrict__ z,
+                                                      const double* __restrict__ sc, int slot,
+                                                      const double* __restrict__ r,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ prz,
+                                                      double* __restrict__ pzq)
+{
+    const Blk bk = self_blk();
+    const double s = sc[slot];
+    double arz = 0.0, azq = 0.0;
+    const long long stride = (long long)bk.G * blockDim.x;
+    for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = (double)x[i] * s;
+        z[i] = v;
+        arz += r[i] * v;
+        if (q) azq += q[i] * v;
+    }
+    arz = block_sum(arz);
+    if (threadIdx.x == 0) prz[bk.L] = arz;
+    if (q) {
+        azq = block_sum(azq);
+        if (threadIdx.x == 0) pzq[bk.L] = azq;
+    }
 }
 
 // x[i] = v
