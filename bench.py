@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 TOL = 1e-10
 KERNEL_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_pass_config2_traffic.json")
-KNAMES = ["gs_pass", "residual", "apply", "restrict", "prolong"]
+KNAMES = ["gs_pass", "residual", "apply", "restrict", "prolong", "vcycle"]
+GS_KERNEL = "k_gs_march2<double, 0, 0>"
 
 
 def log(*a):
@@ -55,6 +56,24 @@ def gs_bytes_per_launch(shape, ncol, word, phi_invariant, nterms):
     field = upd * 2 * word + (n - upd) * word
     coef = nterms * (nr * nt if phi_invariant else n) * word
     return field + coef
+
+
+def vcycle_bytes(levels, word, phi_invariant=True):
+    """Algorithmic HBM bytes of one V(2,2) cycle from a zero iterate on the
+    7-point hierarchy: per smoothed level of n cells, the zero-iterate pass
+    (b and x of one colour: n words), seven full colour passes (b and x of
+    the updated colour, x of the other: 1.5 n words each), the residual (x,
+    b in, r out: 3 n), restriction (n in, n/8 out) and prolongation (n/8 in,
+    x in and out: 2 n + n/8) -- 17.75 n words -- plus the three metric
+    arrays per (r, theta) read by each of the 8 passes and the residual;
+    the coarsest level reads its FP64 dense inverse once."""
+    total = 0
+    for nr, nt, np_ in levels[:-1]:
+        n = nr * nt * np_
+        coef = 3 * nr * nt * (1 if phi_invariant else np_)
+        total += (17.75 * n + 9 * coef) * word
+    nc = levels[-1][0] * levels[-1][1] * levels[-1][2]
+    return total + nc * nc * 8 + 2 * nc * word
 
 
 def run_form(cps, torch, g, rhs, precision, steps, warmup):
@@ -87,6 +106,18 @@ def kernel_table(prof, steps):
         out[name] = {"launches_per_step": cnt / steps,
                      "avg_us": round(ms / cnt * 1e3, 2) if cnt else None}
     return out
+
+
+def vcycle_rate(prof, levels, word):
+    """HBM rate of the preconditioning V-cycle: the byte model of
+    vcycle_bytes over the span of each cycle measured with HIP events."""
+    ms, cnt = prof[KNAMES.index("vcycle")]
+    if not cnt:
+        return None
+    t = ms / cnt * 1e-3
+    b = vcycle_bytes(levels, word)
+    return {"bytes_per_cycle": b, "avg_us": t * 1e6, "achieved_GBs": b / t / 1e9,
+            "frac_of_peak": b / t / 1e9 / HBM_PEAK_GBS, "cycles_per_step": cnt}
 
 
 def yardstick(cps, torch, n):
@@ -356,10 +387,12 @@ def main():
         "rel_residual": f64["res"].rel_residual,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(kh),
-                     "kernel": "k_gs<double,ORTHO,phi-invariant> finest-level colour pass",
+                     "kernel": GS_KERNEL + " (finest-level red-black colour pass, row pairs; "
+                               "the zero-iterate first pass of a cycle is a kernel of its own)",
                      "avg_us": avg_gs_s * 1e6, "algorithmic_bytes": gs_bytes,
                      "kernel_source_sha256_16": kh, "copy_yardstick_GBs": copy_gbs},
         "kernels_fp64": kernel_table(f64["prof"], a.steps),
+        "vcycle_fp64": vcycle_rate(f64["prof"], s64.levels, 8),
     }
     x64 = f64["p"]
     if not a.no_mixed:
@@ -368,7 +401,8 @@ def main():
         line["mixed"] = {"value": n / mx["sec"], "ms_per_step": mx["sec"] * 1e3,
                          "iterations": mx["iters"][-1], "rel_residual": mx["res"].rel_residual,
                          "rel_diff_vs_fp64": err, "dtype": "f32 V-cycles, f64 outer",
-                         "kernels": kernel_table(mx["prof"], a.steps)}
+                         "kernels": kernel_table(mx["prof"], a.steps),
+                         "vcycle": vcycle_rate(mx["prof"], mx["solver"].levels, 4)}
         mx["solver"].close()
     s64.close()
     gpu_iters = f64["iters"][-1]

@@ -243,14 +243,17 @@ void cps_service_destroy(cps_service* s);
 
 /* ---- Measurement -------------------------------------------------------
  * Kernel classes timed on the finest level with HIP events recorded on the
- * handle's stream around each launch. */
+ * handle's stream around each launch (the colour class leaves out the
+ * zero-iterate first pass of a cycle, which moves fewer bytes). */
 enum {
     CPS_KERNEL_GS = 0,       /* one Gauss-Seidel colour pass */
     CPS_KERNEL_RESIDUAL = 1, /* r = b - A x (+ norm partials) */
     CPS_KERNEL_APPLY = 2,    /* y = A x (Krylov products) */
     CPS_KERNEL_RESTRICT = 3, /* full weighting to level 1 */
     CPS_KERNEL_PROLONG = 4,  /* trilinear correction from level 1 */
-    CPS_KERNEL_CLASSES = 5
+    CPS_KERNEL_VCYCLE = 5,   /* one preconditioning V-cycle, all levels (the span
+                                from its first to its last launch) */
+    CPS_KERNEL_CLASSES = 6
 };
 /* enable != 0 starts recording (and clears earlier records). */
 cps_status cps_profile_enable(cps_handle* h, int32_t enable);

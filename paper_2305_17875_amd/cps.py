@@ -259,7 +259,7 @@ def cps_debug_vcycle(h, b, x):
     _check(lib().cps_debug_vcycle(h, _ptr(b), _ptr(x)))
 
 
-KERNEL_GS, KERNEL_RESIDUAL, KERNEL_APPLY, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
+KERNEL_GS, KERNEL_RESIDUAL, KERNEL_APPLY, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE = range(6)
 
 
 def cps_profile_enable(h, enable: bool):

@@ -220,7 +220,7 @@ struct ProfScope {
     hipEvent_t stop = nullptr;
     ProfScope(cps_handle* hh, int kk, int level) : h(hh), k(kk)
     {
-        if (!h->prof || level != 0) return;
+        if (!h->prof || level != 0 || k < 0) return;
         auto& v = h->ev[k];
         size_t& u = h->ev_used[k];
         while (v.size() < u + 2) {
@@ -264,27 +264,32 @@ long long gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero 
     const int rowlen = h->ncol == 2 ? L.g.rowlen : L.g.rowlen / 2;
     const int bpa = (int)nblk(rowlen);
     const int z = zero ? 1 : 0;
-    ProfScope ps(h, CPS_KERNEL_GS, l);
+    // the zero-iterate first pass moves fewer bytes: not in the GS class
+    ProfScope ps(h, zero ? -1 : CPS_KERNEL_GS, l);
     if (marching(h)) {
         const MarchShape ms = stencil_shape(L.g, h->lv[l].gs_ch);
         if (row_pairs(L.g)) {
-            if (l == 0)
-                k_gs_march2<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch,
-                                                                    b, x, colour, z, dot);
-            else
-                k_gs_march2<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch,
-                                                                    b, x, colour, z, dot);
+            auto launch = [&](auto T_, auto Z) {
+                k_gs_march2<T, decltype(T_)::value, decltype(Z)::value>
+                    <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour,
+                                                        dot);
+            };
+            if (l == 0) zero ? launch(IM<0>{}, IM<1>{}) : launch(IM<0>{}, IM<0>{});
+            else zero ? launch(IM<1>{}, IM<1>{}) : launch(IM<1>{}, IM<0>{});
             LAUNCH_CHECK();
             return dot ? ms.grid : 0;
         }
-        auto launch = [&](auto U, auto T_) {
-            k_gs_march<T, decltype(U)::value, decltype(T_)::value>
-                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour, z,
+        auto launch = [&](auto U, auto T_, auto Z) {
+            k_gs_march<T, decltype(U)::value, decltype(T_)::value, decltype(Z)::value>
+                <<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, colour,
                                                     dot);
         };
         const bool u = L.g.nh % 64 == 0;
-        if (l == 0) u ? launch(BA<true>{}, IM<0>{}) : launch(BA<false>{}, IM<0>{});
-        else u ? launch(BA<true>{}, IM<1>{}) : launch(BA<false>{}, IM<1>{});
+        auto by_zero = [&](auto U, auto T_) {
+            zero ? launch(U, T_, IM<1>{}) : launch(U, T_, IM<0>{});
+        };
+        if (l == 0) u ? by_zero(BA<true>{}, IM<0>{}) : by_zero(BA<false>{}, IM<0>{});
+        else u ? by_zero(BA<true>{}, IM<1>{}) : by_zero(BA<false>{}, IM<1>{});
         LAUNCH_CHECK();
         return dot ? ms.grid : 0;
     }
@@ -485,7 +490,11 @@ void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1
 {
     const long long n = h->lv[0].n;
     if (h->opts.precision == 0) {
-        const long long parts = vcycle<double>(h, in, out, true, rz_slot >= 0);
+        long long parts;
+        {
+            ProfScope ps(h, CPS_KERNEL_VCYCLE, 0);
+            parts = vcycle<double>(h, in, out, true, rz_slot >= 0);
+        }
         if (rz_slot >= 0) {
             if (parts) reduce(h, parts, rz_slot);
             else dot<double, double>(h, n, in, out, rz_slot);
@@ -496,7 +505,10 @@ void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1
         float* x = h->lv[0].x32.p;
         k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, in, b, h->sc.p, S_SCALE, 1);
         LAUNCH_CHECK();
-        vcycle<float>(h, b, x, true);
+        {
+            ProfScope ps(h, CPS_KERNEL_VCYCLE, 0);
+            vcycle<float>(h, b, x, true);
+        }
         if (rz_slot < 0 && !zq) {
             k_cast<float, double><<<nblk(n), kBlock, 0, h->stream>>>(n, x, out, h->sc.p, S_SCALE, 0);
             LAUNCH_CHECK();

@@ -60,6 +60,15 @@ struct Level {
 
 __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
+// Streaming accesses: values read once or written once by a pass carry the
+// non-temporal hint, so that the L2 of an XCD keeps the stencil field whose
+// rows neighbouring wavefronts read again.
+template <typename T>
+__device__ __forceinline__ T ld_once(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_once(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
+
 __device__ __forceinline__ long long split_index(const Geo& g, int a, int b, int c)
 {
     return (long long)(c & 1) * g.P + ((long long)a * g.nt + b) * g.nh + (c >> 1);
@@ -545,13 +554,13 @@ __device__ __forceinline__ void d_gs_march(Blk bk, Geo g, const T* __restrict__ 
     }
 }
 
-template <typename T, bool UROW, int LTAG>
+template <typename T, bool UROW, int LTAG, int ZERO>
 __global__ void __launch_bounds__(kBlock) k_gs_march(Geo g, const T* __restrict__ G, long long gk,
                                                      int bpa, int ch, const T* __restrict__ bv,
-                                                     T* __restrict__ x, int colour, int zero,
+                                                     T* __restrict__ x, int colour,
                                                      double* __restrict__ dot)
 {
-    d_gs_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero, dot);
+    d_gs_march<T, UROW, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, ZERO, dot);
 }
 
 
@@ -752,19 +761,28 @@ struct March2 {
     bool ring;    // the wavefront holds the whole phi ring of its rows
 };
 
+// A block is kPairs adjacent row pairs x one 64-wide segment of phi (one
+// wavefront per pair), so the rows just outside a pair are mostly the
+// neighbouring wavefronts' own rows, read on the same CU at about the same
+// time.  Units of a plane: cdiv(n_theta / 2, kPairs) pair groups x
+// (n_phi / 128) segments.
+constexpr int kPairs = kBlock / 64;
+
 __device__ __forceinline__ bool march2_pos(Blk bk, const Geo& g, int bpa, int ch, March2& p)
 {
     const int L = (int)bk.L;
     const int chunk = L / bpa;
-    const int m2 = (L - chunk * bpa) * kBlock + (int)threadIdx.x;
+    const int unit = L - chunk * bpa;
+    const int segs = g.nh >> 6;
+    const int pg = unit / segs, seg = unit - pg * segs;
+    const int bp = pg * kPairs + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     p.a0 = chunk * ch;
     p.a1 = min(g.nr, p.a0 + ch);
-    // (n_theta / 2) * nh is a multiple of 64: whole wavefronts drop out
-    if (m2 >= (g.nt >> 1) * g.nh || p.a0 >= g.nr) return false;
-    const int bp = __builtin_amdgcn_readfirstlane(m2 / g.nh);
+    // pairs past the last one: whole wavefronts drop out
+    if (bp >= (g.nt >> 1) || p.a0 >= g.nr) return false;
     p.b0 = 2 * bp;
-    p.j = m2 - bp * g.nh;
     p.lane = (int)threadIdx.x & 63;
+    p.j = seg * 64 + p.lane;
     p.r0 = (long long)p.b0 * g.nh + p.j;
     p.ring = g.nh == 64;
     return true;
@@ -847,8 +865,8 @@ __device__ __forceinline__ void gs_march2_body(const Geo& g, const T* __restrict
                 const long long base = (long long)aa * sr;
                 p0[u] = col(aa + 1, b0, r0);
                 p1[u] = col(aa + 1, b1, r1);
-                q0[u] = bv[s0 * g.P + base + r0];
-                q1[u] = bv[s1 * g.P + base + r1];
+                q0[u] = ld_once(bv + s0 * g.P + base + r0);
+                q1[u] = ld_once(bv + s1 * g.P + base + r1);
                 tm0[u] = tlo ? x[s0 * g.P + base + r0 - nh] : T(0);
                 tp1[u] = thi ? x[s1 * g.P + base + r1 + nh] : T(0);
                 e0[u] = edge(s0) ? x[s1 * g.P + base + r0 - j + (s0 == 0 ? jlo : jhi)] : T(0);
@@ -875,8 +893,8 @@ __device__ __forceinline__ void gs_march2_body(const Geo& g, const T* __restrict
                              g1[4] * (c1 + on1);
                 const long long base = (long long)aa * sr;
                 const T x0n = (q0[u] - S0) / D0, x1n = (q1[u] - S1) / D1;
-                x[s0 * g.P + base + r0] = x0n;
-                x[s1 * g.P + base + r1] = x1n;
+                st_once(x + s0 * g.P + base + r0, x0n);
+                st_once(x + s1 * g.P + base + r1, x1n);
                 acc += (double)q0[u] * (double)x0n + (double)q1[u] * (double)x1n;
                 m0 = c0;
                 c0 = p0[u];
@@ -903,13 +921,15 @@ __device__ __forceinline__ void d_gs_march2(Blk bk, Geo g, const T* __restrict__
     }
 }
 
-template <typename T, int LTAG>
+// ZERO: the zero-iterate first pass, a kernel of its own so that profiles
+// keep it apart from the full passes.
+template <typename T, int LTAG, int ZERO>
 __global__ void __launch_bounds__(kBlock) k_gs_march2(Geo g, const T* __restrict__ G, long long gk,
                                                       int bpa, int ch, const T* __restrict__ bv,
-                                                      T* __restrict__ x, int colour, int zero,
+                                                      T* __restrict__ x, int colour,
                                                       double* __restrict__ dot)
 {
-    d_gs_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, zero, dot);
+    d_gs_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, colour, ZERO, dot);
 }
 
 // Column values of a row-pair thread at one plane: u = plane 0, v = plane 1
@@ -1064,7 +1084,7 @@ __device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __rest
                     march2_load<T>(g, Plain<T>{x}, p, a + u, nb[u]);
                     const long long base = (long long)(a + u) * g.rowlen + p.r0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) bb[u][k] = bv[base + o[k]];
+                    for (int k = 0; k < 4; ++k) bb[u][k] = ld_once(bv + base + o[k]);
                 }
 #pragma unroll
             for (int u = 0; u < AHEAD; ++u)
@@ -1075,7 +1095,7 @@ __device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __rest
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const T rk = bb[u][k] - y[k];
-                        r[base + o[k]] = rk;
+                        st_once(r + base + o[k], rk);
                         acc += (double)rk * (double)rk;
                     }
                     cm = c;
@@ -1136,7 +1156,7 @@ __device__ __forceinline__ void d_apply_march2(Blk bk, Geo g, const T* __restric
                     const long long base = (long long)(a + u) * g.rowlen + p.r0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        y[base + o[k]] = yk[k];
+                        st_once(y + base + o[k], yk[k]);
                         if (dotv) acc += (double)yk[k] * (double)dv[u][k];
                     }
                     cm = c;
@@ -1191,8 +1211,8 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
             const T own[4] = {c.u0, c.v0, c.u1, c.v1};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                pnew[base + o[k]] = own[k];
-                q[base + o[k]] = yk[k];
+                st_once(pnew + base + o[k], own[k]);
+                st_once(q + base + o[k], yk[k]);
                 acc += (double)yk[k] * (double)own[k];
             }
             cm = c;
@@ -1792,7 +1812,7 @@ __host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
 // positions of a plane.  stencil_shape: the marching launch a level uses.
 __host__ __device__ inline MarchShape march2_shape(const Geo& g, int ch = 0)
 {
-    return chunked(g, cdiv((long long)(g.nt / 2) * g.nh, kBlock), ch);
+    return chunked(g, cdiv(g.nt / 2, kPairs) * (g.nh / 64), ch);
 }
 __host__ __device__ inline MarchShape stencil_shape(const Geo& g, int ch = 0)
 {

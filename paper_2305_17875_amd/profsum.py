@@ -25,7 +25,7 @@ import sqlite3
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "kernels.hpp")
 COPY_BYTES = 192 * 256 * 512 * 8
-GS_FINEST = "k_gs_march<double, true, 0>"
+GS_FINEST = "k_gs_march2<double, 0, 0>"
 
 
 def short(name: str) -> str:
