@@ -21,6 +21,10 @@ GRIDS = [
     Shell(32, 32, 32),
     Shell(16, 16, 16, map=MAP_OBLATE, flattening=0.05),
     Shell(32, 32, 64, radial_stretch=2.0),
+    # rings of 64 / 128 cells per parity: row-pair kernels; the single solve
+    # forms the CG direction inside the product, the batch in its own pass
+    Shell(16, 16, 128, radial_stretch=2.0),
+    Shell(8, 12, 256),
 ]
 
 

@@ -53,6 +53,10 @@ AXI = [
     ("sphere-tanh-32x32x64", Shell(32, 32, 64, radial_stretch=2.0)),
     ("oblate-32x32x64", Shell(32, 32, 64, map=MAP_OBLATE, flattening=0.1)),
     ("oblate-ragged-24x20x28", Shell(24, 20, 28, map=MAP_OBLATE, flattening=0.15)),
+    # phi rings of 64 and 128 cells per parity: the row-pair kernels and the
+    # fused conjugate-gradient direction + product run on level 0
+    ("sphere-ring64-16x16x128", Shell(16, 16, 128, radial_stretch=2.0)),
+    ("sphere-ring128-8x12x256", Shell(8, 12, 256)),
 ]
 
 
