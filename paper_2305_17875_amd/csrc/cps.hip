@@ -646,11 +646,12 @@ int compute_operator(cps_handle* h)
     // coarsest dense inverse of A_c + alpha 1 1^T
     const int n = h->nc;
     {
-        Buf<double> A, M0, M1;
+        Buf<double> A, M0, E, Xp;
         Buf<int> used, piv, bad;
         A.alloc((size_t)n * n);
         M0.alloc((size_t)n * 2 * n);
-        M1.alloc((size_t)n * 2 * n);
+        E.alloc((size_t)n * kGJ);
+        Xp.alloc((size_t)kGJ * 2 * n);
         used.alloc(n);
         piv.alloc(n);
         bad.alloc(1);
@@ -669,20 +670,35 @@ int compute_operator(cps_handle* h)
         k_fill<int><<<nblk(n), kBlock, 0, h->stream>>>(n, piv.p, 0);
         k_fill<int><<<1, kBlock, 0, h->stream>>>(1, bad.p, 0);
         LAUNCH_CHECK();
-        double* src = M0.p;
-        double* dst = M1.p;
-        for (int k = 0; k < n; ++k) {
-            k_gj_step<<<gblocks, kBlock, 0, h->stream>>>(n, k, src, dst, used.p, piv.p, bad.p);
-            std::swap(src, dst);
+        // blocked Gauss-Jordan: a panel of kGJ pivot steps, then the rank-kGJ
+        // update of the columns past the panel
+        const int R = cdiv(n, kGJThreads); // rows per thread: 1, 2 or 4 (n <= 4096)
+        const int KB = R == 1 ? 16 : (R == 2 ? 8 : 4);
+        for (int c0 = 0; c0 < n; c0 += KB) {
+            if (R == 1)
+                k_gj_panel<1, 16><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, Xp.p, used.p,
+                                                                   piv.p, bad.p);
+            else if (R == 2)
+                k_gj_panel<2, 8><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, Xp.p, used.p,
+                                                                  piv.p, bad.p);
+            else
+                k_gj_panel<4, 4><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, Xp.p, used.p,
+                                                                  piv.p, bad.p);
+            const int kb = std::min(KB, n - c0);
+            const long long rest = 2LL * n - c0 - kb;
+            const long long blocks = cdiv(rest, 64) * (long long)cdiv(n, kBlock / 64);
+            k_gj_update<<<(unsigned)blocks, kBlock, 0, h->stream>>>(n, c0, kb, M0.p, E.p, Xp.p,
+                                                                   used.p);
         }
         LAUNCH_CHECK();
-        k_gj_extract<<<nblk((long long)n * n), kBlock, 0, h->stream>>>(n, src, piv.p, h->Ainv.p);
+        k_gj_extract<<<nblk((long long)n * n), kBlock, 0, h->stream>>>(n, M0.p, piv.p, h->Ainv.p);
         LAUNCH_CHECK();
         int hbad = 0;
         HIPC(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIPC(hipStreamSynchronize(h->stream));
         if (hbad) fail(CPS_E_INVALID, "coarsest operator is singular");
-        A.release(); M0.release(); M1.release(); used.release(); piv.release(); bad.release();
+        A.release(); M0.release(); E.release(); Xp.release();
+        used.release(); piv.release(); bad.release();
     }
     return mode;
 }

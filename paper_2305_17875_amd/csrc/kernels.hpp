@@ -2332,58 +2332,155 @@ __global__ void __launch_bounds__(kBlock) k_augment(int n, const double* __restr
     }
 }
 
-// One Gauss-Jordan step on the augmented n x 2n matrix, out of place.
-// Partial pivoting: the pivot of column k is the not-yet-used row with the
-// largest |entry| (lowest index on ties); used_at[i] = step at which row i
-// became a pivot (INT_MAX if not yet).  Every block finds the pivot itself.
-__global__ void __launch_bounds__(kBlock) k_gj_step(int n, int k, const double* __restrict__ src,
-                                                    double* __restrict__ dst,
-                                                    int* __restrict__ used_at,
-                                                    int* __restrict__ piv,
-                                                    int* __restrict__ fail)
+// Blocked Gauss-Jordan inversion of the augmented n x 2n matrix [A | I]
+// with partial pivoting, in place.  Columns are taken in panels of KB.
+// The pivot of column c is the not-yet-used row with the largest |entry|
+// (lowest index on ties); used_at[i] = column at which row i became a pivot
+// (INT_MAX before).  For a panel:
+//  - k_gj_panel (one block of kGJThreads, R rows per thread, the rows' panel
+//    entries in registers) runs the KB pivot steps on the panel's own
+//    columns and, alongside, on KB probe columns E, where probe u is the
+//    unit vector of the pivot row of step u (untouched by the steps before
+//    it, so it is set when that step starts).  Afterwards any column x of the
+//    rest transforms as x' = (x off the panel's pivot rows) + E x[pivots].
+//    The panel's pivot rows are copied aside (Xp) before the update.
+//  - k_gj_update applies that rank-KB update to the columns past the panel.
+// KB = 16 / R keeps a thread's registers to 2 R KB values (n <= 1024 R).
+constexpr int kGJ = 16;          // row stride of E
+constexpr int kGJThreads = 1024;
+
+template <int R, int KB>
+__global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* __restrict__ M,
+                                                         double* __restrict__ E,
+                                                         double* __restrict__ Xp,
+                                                         int* __restrict__ used_at,
+                                                         int* __restrict__ piv,
+                                                         int* __restrict__ fail)
 {
-    __shared__ double sv[kBlock];
-    __shared__ int si[kBlock];
+    // per-wave candidates and the broadcast pivot row, alternating between
+    // steps so that one barrier separates writers from readers
+    __shared__ double sv[2][kGJThreads / 64];
+    __shared__ int si[2][kGJThreads / 64];
+    __shared__ double prow[2][KB], erow[2][KB];
     const long long w = 2LL * n;
-    double best = -1.0;
-    int bi = -1;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        if (used_at[i] < k) continue;
-        const double v = fabs(src[i * w + k]);
-        if (v > best) { best = v; bi = i; }
+    const int kb = min(KB, n - c0);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double pv[R][KB], ev[R][KB];
+    int used[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + r * kGJThreads;
+        used[r] = i < n ? used_at[i] : 0; // rows past n never qualify
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            pv[r][q] = (i < n && q < kb) ? M[i * w + c0 + q] : 0.0;
+            ev[r][q] = 0.0;
+        }
     }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            const double v2 = sv[threadIdx.x + o];
-            const int i2 = si[threadIdx.x + o];
-            if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 >= 0 &&
-                                         (si[threadIdx.x] < 0 || i2 < si[threadIdx.x]))) {
-                sv[threadIdx.x] = v2;
-                si[threadIdx.x] = i2;
+#pragma unroll
+    for (int t = 0; t < KB; ++t) {
+        if (t >= kb) continue; // uniform; keeps the loop unrollable
+        const int c = c0 + t;
+        double best = -1.0;
+        int bi = -1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = threadIdx.x + r * kGJThreads;
+            const double v = fabs(pv[r][t]);
+            if (used[r] >= c && v > best) { best = v; bi = i; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_down(best, o);
+            const int i2 = __shfl_down(bi, o);
+            if (v2 > best || (v2 == best && i2 >= 0 && (bi < 0 || i2 < bi))) { best = v2; bi = i2; }
+        }
+        const int h = t & 1;
+        if (lane == 0) { sv[h][wid] = best; si[h][wid] = bi; }
+        __syncthreads();
+        // every thread combines the wavefronts' candidates itself
+        double bb = sv[h][0];
+        int p = si[h][0];
+        for (int q = 1; q < kGJThreads / 64; ++q) {
+            const double v2 = sv[h][q];
+            const int i2 = si[h][q];
+            if (v2 > bb || (v2 == bb && i2 >= 0 && (p < 0 || i2 < p))) { bb = v2; p = i2; }
+        }
+        if (p < 0 || bb == 0.0) {
+            if (threadIdx.x == 0) *fail = 1;
+            return; // uniform: every thread reached the same decision
+        }
+        // the owner of the pivot row broadcasts it, scaled
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (threadIdx.x + r * kGJThreads == p) {
+                used[r] = c;
+                used_at[p] = c;
+                piv[c] = p;
+                ev[r][t] = 1.0;
+                const double inv = 1.0 / pv[r][t];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) {
+                    prow[h][q] = q >= t ? pv[r][q] * inv : 0.0;
+                    erow[h][q] = ev[r][q] * inv;
+                }
+            }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = threadIdx.x + r * kGJThreads;
+            if (i == p) {
+#pragma unroll
+                for (int q = 0; q < KB; ++q) {
+                    if (q >= t) pv[r][q] = prow[h][q];
+                    ev[r][q] = erow[h][q];
+                }
+            } else {
+                const double m = pv[r][t];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) {
+                    if (q >= t) pv[r][q] -= m * prow[h][q];
+                    ev[r][q] -= m * erow[h][q];
+                }
             }
         }
-        __syncthreads();
     }
-    const int p = si[0];
-    if (p < 0 || sv[0] == 0.0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *fail = 1;
-        return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = threadIdx.x + r * kGJThreads;
+        if (i >= n) continue;
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            if (q < kb) M[i * w + c0 + q] = pv[r][q];
+            E[(long long)i * kGJ + q] = ev[r][q];
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        used_at[p] = k;
-        piv[k] = p;
+    // the panel's pivot rows, before the update of the other columns
+    for (long long q = threadIdx.x; q < (long long)kb * w; q += blockDim.x) {
+        const int u = (int)(q / w);
+        const long long col = q - (long long)u * w;
+        Xp[q] = M[(long long)piv[c0 + u] * w + col];
     }
-    const double inv = 1.0 / src[p * w + k];
-    const long long tot = (long long)n * w;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
-         t += (long long)gridDim.x * blockDim.x) {
-        const long long i = t / w, j = t % w;
-        const double pj = src[p * w + j] * inv;
-        dst[t] = i == p ? pj : src[t] - src[i * w + k] * pj;
-    }
+}
+
+// x' = (x off the pivot rows) + E x[pivots] for the columns past the panel.
+// A wavefront takes one row and 64 columns; the row's E entries are
+// wave-uniform, the pivot rows come from the copy Xp (L2-resident).
+__global__ void __launch_bounds__(kBlock) k_gj_update(int n, int c0, int kb, double* __restrict__ M,
+                                                      const double* __restrict__ E,
+                                                      const double* __restrict__ Xp,
+                                                      const int* __restrict__ used_at)
+{
+    const long long w = 2LL * n;
+    const long long cstart = c0 + kb;
+    const int ctiles = (int)((w - cstart + 63) / 64);
+    const int tile = (int)(blockIdx.x % ctiles), rg = (int)(blockIdx.x / ctiles);
+    const int i = rg * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const long long col = cstart + (long long)tile * 64 + (threadIdx.x & 63);
+    if (i >= n || col >= w) return;
+    const int ua = used_at[i];
+    double acc = (ua >= c0 && ua < c0 + kb) ? 0.0 : M[i * w + col];
+    for (int u = 0; u < kb; ++u) acc += E[(long long)i * kGJ + u] * Xp[(long long)u * w + col];
+    M[i * w + col] = acc;
 }
 
 // Ainv row k = right half of row piv[k].
