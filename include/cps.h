@@ -83,16 +83,23 @@ typedef struct {
     int32_t precision; /* 0: FP64 throughout; 1: FP32 V-cycles inside an FP64
                           refinement loop (FP64 residual, update, coarse solve) */
     int32_t max_iters; /* outer iterations; <= 0 means 200 */
-    int32_t accel;     /* 0: stationary iteration of V-cycles; 1: Krylov
-                          acceleration with the V-cycle as preconditioner
-                          (conjugate gradients for symmetric operators,
-                          BiCGStab when cross metrics make A non-symmetric) */
+    int32_t accel;     /* 0: stationary iteration of V-cycles; 1: conjugate
+                          gradients with the V-cycle as preconditioner
+                          (flexible, Polak-Ribiere form for the FP32 cycles
+                          and for operators with cross terms, which are only
+                          mildly non-symmetric); 2: BiCGStab, two V-cycles
+                          per iteration, for strongly non-symmetric cases */
     int32_t tune;      /* smoother tile shapes (marching chunk per level shape):
                           0 use the cached choice if any; 1 time the shapes not
                           yet cached at setup; 2 retime all.  Cache: the JSON
                           file named by the environment variable CPS_TUNE_CACHE
                           (unset: this process only).  Results do not depend
                           on the choice. */
+    int32_t eager;     /* 0: each outer iteration of cps_solve is captured once
+                          into a hipGraph (per handle) and replayed, one launch
+                          per iteration, when the stream is not the null stream
+                          and profiling is off; 1: every kernel is launched
+                          directly.  Results are the same bits either way. */
     void* stream;      /* hipStream_t the calls are ordered on; NULL = null stream */
 } cps_opts;
 

@@ -40,7 +40,8 @@ class cps_metrics(ctypes.Structure):
 
 class cps_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32),
-                ("accel", ctypes.c_int32), ("tune", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("accel", ctypes.c_int32), ("tune", ctypes.c_int32), ("eager", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class cps_info(ctypes.Structure):
@@ -298,12 +299,13 @@ class Solver:
 
     def __init__(self, grid, precision: int = 0, accel: int = 1, max_iters: int = 200,
                  metrics: int = METRICS_MAP_CENTRAL, n_levels: int = 0, stream=None,
-                 tune: int = 0):
+                 tune: int = 0, eager: bool = False):
         import torch
         self.shape = (grid.n_r, grid.n_theta, grid.n_phi)
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
-        opts = cps_opts(precision, max_iters, accel, tune, ctypes.c_void_p(s.cuda_stream))
+        opts = cps_opts(precision, max_iters, accel, tune, 1 if eager else 0,
+                        ctypes.c_void_p(s.cuda_stream))
         self.h = cps_setup(make_grid(grid, n_levels), cps_metrics(metrics), opts)
         self.levels, self.ncolours, self.phi_invariant = cps_levels(self.h)
 
@@ -366,7 +368,7 @@ class Batch:
         self.grids = list(grids)
         self.sizes = [g.n_r * g.n_theta * g.n_phi for g in self.grids]
         s = stream if stream is not None else torch.cuda.current_stream()
-        opts = cps_opts(1, max_iters, 1, tune, ctypes.c_void_p(s.cuda_stream))
+        opts = cps_opts(1, max_iters, 1, tune, 0, ctypes.c_void_p(s.cuda_stream))
         self.h = cps_batch_setup([make_grid(g) for g in self.grids], cps_metrics(metrics), opts)
 
     def solve(self, rhs_list, tol: float = 1e-10, out=None):
@@ -451,7 +453,7 @@ class Service:
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, precision: int = 1,
                  accel: int = 1, max_iters: int = 200, tune: int = 0):
-        self.opts = cps_opts(precision, max_iters, accel, tune, None)
+        self.opts = cps_opts(precision, max_iters, accel, tune, 0, None)
         self.h = cps_service_create(int(hbm_budget_bytes), max_slots, self.opts)
         self._held = {}  # ticket -> (rhs, p): alive until the wait returns
 

@@ -10,7 +10,7 @@
 // sees exactly the arithmetic and reduction order of its own solve: the
 // result of a problem is the same alone and in the batch, bit for bit.
 // Problems are grouped by stencil: 7-point with phi-invariant metrics
-// (marching kernels, flexible CG) and the rest (BiCGStab).  The iteration
+// (marching kernels) and the rest (generic kernels); both run flexible CG.  The iteration
 // bodies of both groups are captured once in hipGraphs and replayed; the
 // only host round trip per iteration gathers the residual norms, retires
 // converged problems and uploads the active flags.
@@ -354,7 +354,7 @@ void batch_build(cps_batch* B, int n, const cps_grid* grids, const cps_metrics* 
     g1.axi = axi1;
     g1.march = false;
     g1.ncol = mode1 == MODE_ORTHO ? 2 : 4;
-    g1.flexible_cg = mode1 == MODE_ORTHO;
+    g1.flexible_cg = true; // as cps_solve with accel = 1 for every stencil class
     for (auto& G : B->grp)
         if (!G.probs.empty()) build_group_tables(B, G);
     std::vector<std::pair<int, int>> vr, el;

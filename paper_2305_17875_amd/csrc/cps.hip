@@ -168,6 +168,8 @@ struct cps_handle {
     double* hsc = nullptr; // pinned host mirror
     // level-0 FP64 work vectors
     Buf<double> x0, b0, r, z, pd, q, r0, v, s, t, ph, sh;
+    // captured outer-iteration bodies (G_* keys), replayed by run_body
+    hipGraphExec_t gexec[4] = {};
     // optional HIP-event timing of the finest-level kernels, per class
     bool prof = false;
     std::vector<hipEvent_t> ev[CPS_KERNEL_CLASSES];
@@ -523,6 +525,54 @@ void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1
     }
 }
 
+// Outer-iteration bodies: captured once per handle into a hipGraph and
+// replayed (one launch per iteration), or launched kernel by kernel when
+// the handle runs eagerly, is being profiled (per-launch events) or runs on
+// the null stream (which cannot be captured).  A body ends by copying the
+// residual norm to the pinned host mirror; the caller synchronises.
+enum { G_CG0 = 0, G_CG1 = 1, G_BICG = 2, G_RICH = 3 };
+
+template <typename F>
+void run_body(cps_handle* h, int key, F&& body)
+{
+    if (h->opts.eager || h->prof || !h->stream) {
+        body();
+        return;
+    }
+    hipGraphExec_t& ex = h->gexec[key];
+    if (!ex) {
+        hipGraph_t g = nullptr;
+        HIPC(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(h->stream, &g2);
+            if (g2) (void)hipGraphDestroy(g2);
+            throw;
+        }
+        HIPC(hipStreamEndCapture(h->stream, &g));
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) ex = nullptr;
+        HIPC(e);
+    }
+    HIPC(hipGraphLaunch(ex, h->stream));
+}
+
+// the residual norm the last body left in the host mirror
+double body_norm(cps_handle* h, int slot)
+{
+    HIPC(hipStreamSynchronize(h->stream));
+    return h->hsc[slot];
+}
+
+void copy_norm(cps_handle* h, int slot)
+{
+    HIPC(hipMemcpyAsync(h->hsc + slot, h->sc.p + slot, sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+}
+
 double read_scalar(cps_handle* h, int slot)
 {
     HIPC(hipMemcpyAsync(h->hsc + slot, h->sc.p + slot, sizeof(double), hipMemcpyDeviceToHost,
@@ -577,8 +627,9 @@ int level_plan(const cps_grid* g, int dims[kMaxLevels][3])
 void validate_opts(const cps_opts* o)
 {
     if (o && (o->precision < 0 || o->precision > 1)) fail(CPS_E_INVALID, "bad precision");
-    if (o && (o->accel < 0 || o->accel > 1)) fail(CPS_E_INVALID, "bad accel");
+    if (o && (o->accel < 0 || o->accel > 2)) fail(CPS_E_INVALID, "bad accel");
     if (o && (o->tune < 0 || o->tune > 2)) fail(CPS_E_INVALID, "bad tune");
+    if (o && (o->eager < 0 || o->eager > 1)) fail(CPS_E_INVALID, "bad eager");
 }
 
 void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
@@ -763,15 +814,15 @@ void build(cps_handle* h)
     h->x0.alloc(n0);
     h->b0.alloc(n0);
     h->r.alloc(n0);
-    if (h->opts.accel == 1) {
+    if (h->opts.accel >= 1) {
         h->z.alloc(n0);
         h->pd.alloc(n0);
         h->q.alloc(n0);
         h->ph.alloc(n0); // BiCGStab's M^-1 p, or the second CG direction buffer
-        if (h->mode != MODE_ORTHO) {
-            h->r0.alloc(n0); h->v.alloc(n0); h->s.alloc(n0); h->t.alloc(n0);
-            h->sh.alloc(n0);
-        }
+    }
+    if (h->opts.accel == 2) {
+        h->r0.alloc(n0); h->v.alloc(n0); h->s.alloc(n0); h->t.alloc(n0);
+        h->sh.alloc(n0);
     }
     autotune(h, h->opts.tune);
     HIPC(hipStreamSynchronize(h->stream));
@@ -791,6 +842,8 @@ void destroy(cps_handle* h)
     h->x0.release(); h->b0.release(); h->r.release(); h->z.release(); h->pd.release(); h->q.release();
     h->r0.release(); h->v.release(); h->s.release(); h->t.release(); h->ph.release();
     h->sh.release();
+    for (hipGraphExec_t& g : h->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (h->hsc) (void)hipHostFree(h->hsc);
     for (auto& v : h->ev)
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
@@ -842,9 +895,12 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             // stationary: x <- x + V(b - A x)
             if (!mixed) {
                 for (it = 1; it <= maxit; ++it) {
-                    vcycle<double>(h, h->b0.p, x);
-                    reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
-                    st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
+                    run_body(h, G_RICH, [&] {
+                        vcycle<double>(h, h->b0.p, x);
+                        reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
+                        copy_norm(h, S_RR);
+                    });
+                    st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
                     if (st != CPS_E_NOT_CONVERGED) break;
                 }
             } else {
@@ -856,65 +912,87 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                 float* x32 = h->lv[0].x32.p;
                 for (it = 1; it <= maxit; ++it) {
                     // s = ||r||; FP32 cycle on r/s; x += s e; FP64 residual
-                    k_sqrt_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_SCALE, S_RR);
-                    k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, h->r.p, b32, h->sc.p, S_SCALE, 1);
-                    LAUNCH_CHECK();
-                    vcycle<float>(h, b32, x32, true);
-                    k_ir_update<float><<<nblk(n), kBlock, 0, h->stream>>>(n, x, x32, h->sc.p + S_SCALE);
-                    LAUNCH_CHECK();
-                    reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
-                    st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
+                    run_body(h, G_RICH, [&] {
+                        k_sqrt_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_SCALE, S_RR);
+                        k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, h->r.p, b32, h->sc.p, S_SCALE, 1);
+                        LAUNCH_CHECK();
+                        vcycle<float>(h, b32, x32, true);
+                        k_ir_update<float><<<nblk(n), kBlock, 0, h->stream>>>(n, x, x32, h->sc.p + S_SCALE);
+                        LAUNCH_CHECK();
+                        reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
+                        copy_norm(h, S_RR);
+                    });
+                    st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
                     if (st != CPS_E_NOT_CONVERGED) break;
                 }
             }
-        } else if (h->mode == MODE_ORTHO) {
+        } else if (h->opts.accel == 1) {
             // preconditioned CG; flexible (Polak-Ribiere) when the
-            // preconditioner runs in FP32.  The search direction alternates
-            // between two buffers: p = z + beta p_old is formed inside the
-            // product q = A p where the level allows it.
-            const int flexible = mixed ? 1 : 0;
+            // preconditioner runs in FP32 or the operator has cross terms
+            // (mildly non-symmetric: the flexible form converges there in
+            // fewer V-cycles than BiCGStab's two per iteration).  The search
+            // direction alternates between two buffers: p = z + beta p_old
+            // is formed inside the product q = A p where the level allows it.
+            const int flexible = (mixed || h->mode != MODE_ORTHO) ? 1 : 0;
             double* r = h->r.p;
             double* z = h->z.p;
             double* p = h->pd.p;
             double* pn = h->ph.p;
             double* q = h->q.p;
             const Geo& g0 = h->lv[0].geo;
-            const bool fused = row_pairs(g0);
+            const bool fused = marching(h) && row_pairs(g0);
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, r);
             LAUNCH_CHECK();
             precondition(h, r, z, S_RZ);
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, z, p);
             LAUNCH_CHECK();
             reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
-            for (it = 1; it <= maxit; ++it) {
+            // x += alpha p, r -= alpha q and ||r||^2 (the first iteration's
+            // step, and the tail of every later body)
+            auto step = [&](double* pk) {
                 SCALAR_KERNEL(h, k_cg_alpha);
-                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, p, q, h->partial.p);
+                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, pk, q, h->partial.p);
                 LAUNCH_CHECK();
                 reduce(h, vgrid(n), S_RR);
-                st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
-                if (st != CPS_E_NOT_CONVERGED) break;
-                k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
-                LAUNCH_CHECK();
-                precondition(h, r, z, S_RZ, flexible ? q : nullptr);
-                k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
-                LAUNCH_CHECK();
-                if (fused) {
-                    const MarchShape ms = stencil_shape(g0);
-                    ProfScope ps(h, CPS_KERNEL_APPLY, 0);
-                    k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
-                        g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, p, h->sc.p + S_BETA,
-                        pn, q, h->partial.p);
+                copy_norm(h, S_RR);
+            };
+            step(p);
+            it = 1;
+            st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
+            // later iterations: new direction from the preconditioned
+            // residual, then the step; with the fused product the direction
+            // alternates between two buffers, so two bodies by parity
+            while (st == CPS_E_NOT_CONVERGED && it < maxit) {
+                ++it;
+                const int parity = fused ? (it & 1) : 0;
+                double* pc = parity ? pn : p; // direction of the previous iteration
+                double* pnx = parity ? p : pn;
+                run_body(h, G_CG0 + parity, [&] {
+                    k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
                     LAUNCH_CHECK();
-                    reduce(h, ms.grid, S_PQ);
-                    std::swap(p, pn);
-                } else {
-                    k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
+                    precondition(h, r, z, S_RZ, flexible ? q : nullptr);
+                    k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
                     LAUNCH_CHECK();
-                    reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
-                }
+                    if (fused) {
+                        const MarchShape ms = stencil_shape(g0);
+                        ProfScope ps(h, CPS_KERNEL_APPLY, 0);
+                        k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
+                            g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
+                            h->sc.p + S_BETA, pnx, q, h->partial.p);
+                        LAUNCH_CHECK();
+                        reduce(h, ms.grid, S_PQ);
+                        step(pnx);
+                    } else {
+                        k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
+                        LAUNCH_CHECK();
+                        reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
+                        step(p);
+                    }
+                });
+                st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
             }
         } else {
-            // BiCGStab, right-preconditioned by the V-cycle
+            // BiCGStab (accel = 2), right-preconditioned by the V-cycle
             double* r = h->r.p;
             double* p = h->pd.p;
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, r);
@@ -922,32 +1000,36 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             LAUNCH_CHECK();
             fill<double>(h, p, n, 0.0);
             fill<double>(h, h->v.p, n, 0.0);
-            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO_OLD, 1.0);
+            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO, 1.0); // becomes rho_old
             k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_ALPHA, 1.0);
             k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_OMEGA, 1.0);
             LAUNCH_CHECK();
             for (it = 1; it <= maxit; ++it) {
-                dot<double, double>(h, n, h->r0.p, r, S_RHO);
-                SCALAR_KERNEL(h, k_bicg_beta);
-                k_bicg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, p);
-                LAUNCH_CHECK();
-                precondition(h, p, h->ph.p);
-                reduce(h, apply<double>(h, 0, h->ph.p, h->v.p, h->r0.p), S_R0V);
-                SCALAR_KERNEL(h, k_bicg_alpha);
-                k_bicg_s<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, h->s.p);
-                LAUNCH_CHECK();
-                precondition(h, h->s.p, h->sh.p);
-                reduce(h, apply<double>(h, 0, h->sh.p, h->t.p, h->s.p), S_TS);
-                dot<double, double>(h, n, h->t.p, h->t.p, S_TT);
-                SCALAR_KERNEL(h, k_bicg_omega);
-                k_bicg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, h->ph.p, h->sh.p,
-                                                               h->s.p, h->t.p, h->partial.p);
-                LAUNCH_CHECK();
-                reduce(h, vgrid(n), S_RR);
-                st = check_norm(read_scalar(h, S_RR), bb, tol, &rel);
+                run_body(h, G_BICG, [&] {
+                    k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO_OLD, S_RHO);
+                    LAUNCH_CHECK();
+                    dot<double, double>(h, n, h->r0.p, r, S_RHO);
+                    SCALAR_KERNEL(h, k_bicg_beta);
+                    k_bicg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, p);
+                    LAUNCH_CHECK();
+                    precondition(h, p, h->ph.p);
+                    reduce(h, apply<double>(h, 0, h->ph.p, h->v.p, h->r0.p), S_R0V);
+                    SCALAR_KERNEL(h, k_bicg_alpha);
+                    k_bicg_s<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, r, h->v.p, h->s.p);
+                    LAUNCH_CHECK();
+                    precondition(h, h->s.p, h->sh.p);
+                    reduce(h, apply<double>(h, 0, h->sh.p, h->t.p, h->s.p), S_TS);
+                    dot<double, double>(h, n, h->t.p, h->t.p, S_TT);
+                    SCALAR_KERNEL(h, k_bicg_omega);
+                    k_bicg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, h->ph.p,
+                                                                   h->sh.p, h->s.p, h->t.p,
+                                                                   h->partial.p);
+                    LAUNCH_CHECK();
+                    reduce(h, vgrid(n), S_RR);
+                    copy_norm(h, S_RR);
+                });
+                st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
                 if (st != CPS_E_NOT_CONVERGED) break;
-                k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO_OLD, S_RHO);
-                LAUNCH_CHECK();
             }
         }
         if (it > maxit) it = maxit;

@@ -94,7 +94,7 @@ size_t estimate_bytes(const cps_grid& g, const cps_opts& o)
     }
     const size_t n0 = (size_t)g.n_r * g.n_theta * g.n_phi;
     const size_t nc = (size_t)dims[L - 1][0] * dims[L - 1][1] * dims[L - 1][2];
-    s += n0 * 8 * (3 + 2 + (o.accel == 1 ? 4 : 0) + (o.accel == 1 && stencil_class(g) ? 5 : 0));
+    s += n0 * 8 * (3 + 2 + (o.accel >= 1 ? 4 : 0) + (o.accel == 2 ? 5 : 0));
     s += (2 * std::max<size_t>(n0 / kBlock + 1, kMaxGrid) + 64) * 8 + nc * nc * 8 * 4 +
          nc * kGJ * 8 * 3;
     return s;

@@ -72,12 +72,14 @@ def test_axisymmetric_against_fft_lu(name, g, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_triaxial_against_sparse_lu(precision):
+@pytest.mark.parametrize("accel", [1, 2])
+def test_triaxial_against_sparse_lu(precision, accel):
+    """19-point stencil: flexible CG (accel 1) and BiCGStab (accel 2)."""
     g = Shell(16, 16, 32, map=MAP_TRIAXIAL, flattening=0.1, skew=0.2)
-    log("triaxial", precision)
+    log("triaxial", precision, accel)
     b = inputs.smoothed_noise(g.shape, seed=8)
     want = direct.solve_sparse(O.face_metrics(g), b)
-    x, res = solve(g, b, precision, 1)
+    x, res = solve(g, b, precision, accel)
     assert res.status == cps.CPS_OK, res
     assert rel(x, want) <= 1e-9, rel(x, want)
 
@@ -129,3 +131,39 @@ def test_error_paths():
     with pytest.raises(ValueError):
         s.solve(dev(np.zeros(10)))
     s.close()
+
+
+GRAPH_CASES = [
+    ("sphere-ring64-cg", Shell(16, 16, 128, radial_stretch=2.0), 1),
+    ("sphere-32-cg", Shell(32, 32, 32), 1),
+    ("oblate-fcg", Shell(16, 16, 32, map=MAP_OBLATE, flattening=0.1), 1),
+    ("oblate-bicgstab", Shell(16, 16, 32, map=MAP_OBLATE, flattening=0.1), 2),
+    ("sphere-richardson", Shell(16, 16, 32), 0),
+]
+
+
+@pytest.mark.parametrize("name,g,accel", GRAPH_CASES, ids=[c[0] for c in GRAPH_CASES])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_equal_eager_solves(name, g, accel, precision):
+    """On a side stream each outer iteration is captured once into a hipGraph
+    and replayed; every replayed solve (several in a row, with eager solves
+    and synchronisations between them) must give the bits of the same solve
+    launched kernel by kernel."""
+    log("graphs", name, precision)
+    side = torch.cuda.Stream()
+    sg = cps.Solver(g, precision=precision, accel=accel, max_iters=400, stream=side)
+    se = cps.Solver(g, precision=precision, accel=accel, max_iters=400, stream=side, eager=True)
+    try:
+        for k in range(3):
+            b = dev(inputs.smoothed_noise(g.shape, 300 + k)).flatten()
+            torch.cuda.synchronize()
+            rg = sg.solve(b)
+            xg = host(rg.p)
+            re = se.solve(b)
+            xe = host(re.p)
+            assert rg.status == re.status == cps.CPS_OK
+            assert rg.iterations == re.iterations
+            assert np.array_equal(xg, xe), (k, np.abs(xg - xe).max())
+    finally:
+        sg.close()
+        se.close()
