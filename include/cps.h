@@ -100,6 +100,15 @@ typedef struct {
                           per iteration, when the stream is not the null stream
                           and profiling is off; 1: every kernel is launched
                           directly.  Results are the same bits either way. */
+    int32_t smoother;  /* 0: red-black point Gauss-Seidel (any stencil);
+                          1: zebra (r, phi)-plane relaxation -- the theta rows
+                          of one parity at a time, each (r, phi) plane solved
+                          exactly by a Fourier transform along phi and the
+                          Thomas algorithm along r; robust to the shell's
+                          radial and cone-tip anisotropy.  Needs the 7-point
+                          operator with phi-invariant metrics (identity box,
+                          sphere) and n_phi a power of two in [4, 2048] on
+                          every smoothed level. */
     void* stream;      /* hipStream_t the calls are ordered on; NULL = null stream */
 } cps_opts;
 
@@ -168,6 +177,10 @@ cps_status cps_debug_restrict(cps_handle* h, int32_t level, const double* r, dou
 cps_status cps_debug_prolong(cps_handle* h, int32_t level, const double* e, double* x);
 /* e = (A_c + alpha 1 1^T)^-1 (b - mean b) on the coarsest level. */
 cps_status cps_debug_coarse_solve(cps_handle* h, const double* b, double* e);
+/* one zebra half-sweep of the plane smoother on level l (handle set up
+ * with smoother = 1): the theta rows b = parity (mod 2), x in place. */
+cps_status cps_debug_plane_sweep(cps_handle* h, int32_t level, int32_t parity, const double* b,
+                                 double* x);
 /* one V(2,2) cycle on level 0 with right-hand side b, x in place. */
 cps_status cps_debug_vcycle(cps_handle* h, const double* b, double* x);
 

@@ -41,7 +41,7 @@ class cps_metrics(ctypes.Structure):
 class cps_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("accel", ctypes.c_int32), ("tune", ctypes.c_int32), ("eager", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("smoother", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class cps_info(ctypes.Structure):
@@ -98,6 +98,7 @@ def lib():
         L.cps_debug_prolong.argtypes = [P, I, P, P]
         L.cps_debug_coarse_solve.argtypes = [P, P, P]
         L.cps_debug_vcycle.argtypes = [P, P, P]
+        L.cps_debug_plane_sweep.argtypes = [P, I, I, P, P]
         L.cps_batch_setup.argtypes = [I, P, P, P, ctypes.POINTER(P)]
         L.cps_batch_setup.restype = I
         L.cps_batch_solve.argtypes = [P, P, P, D, P]
@@ -122,7 +123,7 @@ def lib():
         for f in ("cps_profile_enable", "cps_profile_read", "cps_debug_copy",
                   "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
                   "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
-                  "cps_debug_coarse_solve", "cps_debug_vcycle"):
+                  "cps_debug_coarse_solve", "cps_debug_vcycle", "cps_debug_plane_sweep"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -254,6 +255,12 @@ def cps_debug_coarse_solve(h, b, e):
     _check(lib().cps_debug_coarse_solve(h, _ptr(b), _ptr(e)))
 
 
+def cps_debug_plane_sweep(h, level, parity, b, x):
+    _, n = _dims(h, level)
+    _expect(b, n, "b"); _expect(x, n, "x")
+    _check(lib().cps_debug_plane_sweep(h, level, parity, _ptr(b), _ptr(x)))
+
+
 def cps_debug_vcycle(h, b, x):
     _, n = _dims(h, 0)
     _expect(b, n, "b"); _expect(x, n, "x")
@@ -299,12 +306,12 @@ class Solver:
 
     def __init__(self, grid, precision: int = 0, accel: int = 1, max_iters: int = 200,
                  metrics: int = METRICS_MAP_CENTRAL, n_levels: int = 0, stream=None,
-                 tune: int = 0, eager: bool = False):
+                 tune: int = 0, eager: bool = False, smoother: int = 0):
         import torch
         self.shape = (grid.n_r, grid.n_theta, grid.n_phi)
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
-        opts = cps_opts(precision, max_iters, accel, tune, 1 if eager else 0,
+        opts = cps_opts(precision, max_iters, accel, tune, 1 if eager else 0, smoother,
                         ctypes.c_void_p(s.cuda_stream))
         self.h = cps_setup(make_grid(grid, n_levels), cps_metrics(metrics), opts)
         self.levels, self.ncolours, self.phi_invariant = cps_levels(self.h)
@@ -368,7 +375,7 @@ class Batch:
         self.grids = list(grids)
         self.sizes = [g.n_r * g.n_theta * g.n_phi for g in self.grids]
         s = stream if stream is not None else torch.cuda.current_stream()
-        opts = cps_opts(1, max_iters, 1, tune, 0, ctypes.c_void_p(s.cuda_stream))
+        opts = cps_opts(1, max_iters, 1, tune, 0, 0, ctypes.c_void_p(s.cuda_stream))
         self.h = cps_batch_setup([make_grid(g) for g in self.grids], cps_metrics(metrics), opts)
 
     def solve(self, rhs_list, tol: float = 1e-10, out=None):
@@ -452,8 +459,8 @@ class Service:
     request and returns its ticket; wait() returns (status, p, info)."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, precision: int = 1,
-                 accel: int = 1, max_iters: int = 200, tune: int = 0):
-        self.opts = cps_opts(precision, max_iters, accel, tune, 0, None)
+                 accel: int = 1, max_iters: int = 200, tune: int = 0, smoother: int = 0):
+        self.opts = cps_opts(precision, max_iters, accel, tune, 0, smoother, None)
         self.h = cps_service_create(int(hbm_budget_bytes), max_slots, self.opts)
         self._held = {}  # ticket -> (rhs, p): alive until the wait returns
 

@@ -512,6 +512,8 @@ cps_status cps_batch_setup(int32_t n, const cps_grid* grids, const cps_metrics* 
         if (opts && opts->precision != 1)
             fail(CPS_E_INVALID, "the batched form runs FP32 V-cycles inside FP64 refinement "
                                 "(precision = 1)");
+        if (opts && opts->smoother != 0)
+            fail(CPS_E_INVALID, "the batched form runs the point smoother (smoother = 0)");
         B = new cps_batch();
         batch_build(B, n, grids, metrics, opts);
     });

@@ -9,6 +9,7 @@
 // FP64 refinement.
 #include "cps.h"
 #include "kernels.hpp"
+#include "plane.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -147,6 +148,10 @@ struct LevelMem {
     Buf<double> x64, b64, r64;
     Buf<float> x32, b32, r32;
     int gs_ch = 0; // marching chunk of the colour pass (0 = default; autotuned)
+    // plane smoother: twiddles exp(-2 pi i q / nh) (q < nh/2), exp(-2 pi i m /
+    // n_phi) (m <= nh) as (re, im) pairs, and the symbols 2 cos(2 pi m/n_phi) - 2
+    Buf<double> tw64, twN64, lam64;
+    Buf<float> tw32, twN32, lam32;
 };
 
 } // namespace
@@ -168,6 +173,9 @@ struct cps_handle {
     double* hsc = nullptr; // pinned host mirror
     // level-0 FP64 work vectors
     Buf<double> x0, b0, r, z, pd, q, r0, v, s, t, ph, sh;
+    // plane smoother scratch: spectra and elimination factors of one parity
+    Buf<double> ps64, pc64;
+    Buf<float> ps32, pc32;
     // captured outer-iteration bodies (G_* keys), replayed by run_body
     hipGraphExec_t gexec[4] = {};
     // optional HIP-event timing of the finest-level kernels, per class
@@ -305,9 +313,54 @@ long long gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero 
     return 0;
 }
 
+// One zebra half-sweep of the plane smoother on level l: the theta rows of
+// the given parity, each (r, phi) plane solved exactly (plane.hpp).
+template <typename T>
+struct PlaneBufs;
+template <>
+struct PlaneBufs<double> {
+    static const double* tw(const LevelMem& m) { return m.tw64.p; }
+    static const double* twN(const LevelMem& m) { return m.twN64.p; }
+    static const double* lam(const LevelMem& m) { return m.lam64.p; }
+    static double* S(cps_handle* h) { return h->ps64.p; }
+    static double* C(cps_handle* h) { return h->pc64.p; }
+};
+template <>
+struct PlaneBufs<float> {
+    static const float* tw(const LevelMem& m) { return m.tw32.p; }
+    static const float* twN(const LevelMem& m) { return m.twN32.p; }
+    static const float* lam(const LevelMem& m) { return m.lam32.p; }
+    static float* S(cps_handle* h) { return h->ps32.p; }
+    static float* C(cps_handle* h) { return h->pc32.p; }
+};
+
+template <typename T>
+void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
+{
+    using PB = PlaneBufs<T>;
+    const Level<T> L = view<T>(h, l);
+    const LevelMem& m = h->lv[l];
+    if (!PB::tw(m) || !PB::S(h)) fail(CPS_E_INVALID, "internal: plane smoother not set up");
+    const PlaneLaunch pl = plane_launch(L.g, parity);
+    const auto* tw = reinterpret_cast<const Vec2<T>*>(PB::tw(m));
+    const auto* twN = reinterpret_cast<const Vec2<T>*>(PB::twN(m));
+    auto* S = reinterpret_cast<Vec2<T>*>(PB::S(h));
+    ProfScope ps(h, CPS_KERNEL_GS, l);
+    k_plane_fwd<T><<<pl.blocks, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, b, x, parity, tw, twN, S);
+    LAUNCH_CHECK();
+    const long long sys = (long long)pl.rows * (L.g.nh + 1);
+    k_plane_tri<T><<<nblk(sys), kBlock, 0, h->stream>>>(L.g, L.G, L.gk, parity, PB::lam(m), S,
+                                                        PB::C(h));
+    LAUNCH_CHECK();
+    k_plane_inv<T><<<pl.blocks, kBlock, 0, h->stream>>>(L.g, parity, tw, twN, S, x);
+    LAUNCH_CHECK();
+}
+
 // Gauss-Seidel sweeps over all colours (reverse order for post-smoothing).
 // from_zero: x is zero on entry; with two colours it is then not even read
 // (nor initialised) before the first pass writes it, otherwise it is filled.
+// With the plane smoother a sweep is the two zebra half-sweeps (parity 0
+// then 1, reversed for post-smoothing).
 // dot (two colours on marching levels): the last two passes, which leave
 // every cell final, write partial sums of b . x at dot[0 ..) and after
 // them; returns the number of partial sums written (0 without dot).
@@ -315,6 +368,12 @@ template <typename T>
 long long smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse,
                  bool from_zero = false, double* dot = nullptr)
 {
+    if (h->opts.smoother == 1) {
+        if (from_zero) fill<T>(h, x, h->lv[l].n, T(0));
+        for (int s = 0; s < sweeps; ++s)
+            for (int k = 0; k < 2; ++k) plane_half_sweep<T>(h, l, reverse ? 1 - k : k, b, x);
+        return 0;
+    }
     const bool skip = from_zero && h->ncol == 2;
     if (from_zero && !skip) fill<T>(h, x, h->lv[l].n, T(0));
     long long parts = 0;
@@ -630,6 +689,7 @@ void validate_opts(const cps_opts* o)
     if (o && (o->accel < 0 || o->accel > 2)) fail(CPS_E_INVALID, "bad accel");
     if (o && (o->tune < 0 || o->tune > 2)) fail(CPS_E_INVALID, "bad tune");
     if (o && (o->eager < 0 || o->eager > 1)) fail(CPS_E_INVALID, "bad eager");
+    if (o && (o->smoother < 0 || o->smoother > 1)) fail(CPS_E_INVALID, "bad smoother");
 }
 
 void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
@@ -772,6 +832,50 @@ int checked_plan(const cps_grid& g, int dims[kMaxLevels][3])
     return L;
 }
 
+// Tables and scratch of the plane smoother (7-point, phi-invariant
+// hierarchies whose smoothed levels have power-of-two rings of <= 2048).
+void setup_plane(cps_handle* h)
+{
+    if (!marching(h))
+        fail(CPS_E_INVALID,
+             "the plane smoother needs the 7-point operator with phi-invariant metrics");
+    const bool mixed = h->opts.precision == 1;
+    size_t spec = 0;
+    for (int l = 0; l + 1 < h->L; ++l) {
+        LevelMem& m = h->lv[l];
+        const int nh = m.np / 2;
+        if (nh < 2 || nh > kPlaneLds || (nh & (nh - 1)))
+            fail(CPS_E_INVALID, "the plane smoother needs n_phi a power of two in [4, %d] on "
+                 "every smoothed level (level %d has %d)", 2 * kPlaneLds, l, m.np);
+        std::vector<double> tw(nh), twN(2 * (nh + 1)), lam(nh + 1);
+        for (int q = 0; q < nh / 2; ++q) {
+            tw[2 * q] = std::cos(-2.0 * M_PI * q / nh);
+            tw[2 * q + 1] = std::sin(-2.0 * M_PI * q / nh);
+        }
+        for (int k = 0; k <= nh; ++k) {
+            twN[2 * k] = std::cos(-2.0 * M_PI * k / m.np);
+            twN[2 * k + 1] = std::sin(-2.0 * M_PI * k / m.np);
+            lam[k] = 2.0 * std::cos(2.0 * M_PI * k / m.np) - 2.0;
+        }
+        auto up64 = [&](Buf<double>& d, const std::vector<double>& v) {
+            d.alloc(v.size());
+            HIPC(hipMemcpy(d.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+        };
+        auto up32 = [&](Buf<float>& d, const std::vector<double>& v) {
+            std::vector<float> f(v.begin(), v.end());
+            d.alloc(f.size());
+            HIPC(hipMemcpy(d.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        };
+        up64(m.tw64, tw); up64(m.twN64, twN); up64(m.lam64, lam);
+        if (mixed) { up32(m.tw32, tw); up32(m.twN32, twN); up32(m.lam32, lam); }
+        spec = std::max(spec, (size_t)m.nr * ((m.nt + 1) / 2) * (nh + 1));
+    }
+    // FP64 scratch for the FP64 hierarchy (and its per-step entry points),
+    // FP32 scratch for the mixed form's cycles
+    if (!mixed) { h->ps64.alloc(2 * spec); h->pc64.alloc(spec); }
+    else { h->ps32.alloc(2 * spec); h->pc32.alloc(spec); }
+}
+
 void build(cps_handle* h)
 {
     int dims[kMaxLevels][3];
@@ -824,6 +928,7 @@ void build(cps_handle* h)
         h->r0.alloc(n0); h->v.alloc(n0); h->s.alloc(n0); h->t.alloc(n0);
         h->sh.alloc(n0);
     }
+    if (h->opts.smoother == 1) setup_plane(h);
     autotune(h, h->opts.tune);
     HIPC(hipStreamSynchronize(h->stream));
 }
@@ -1228,6 +1333,21 @@ cps_status cps_debug_gs_pass(cps_handle* h, int32_t level, int32_t colour, const
         const double* bp = split_copy(h, level, b, bs);
         double* xp = split_copy(h, level, x, xs);
         gs_pass<double>(h, level, colour, bp, xp);
+        natural_copy(h, level, xp, x);
+    });
+}
+
+cps_status cps_debug_plane_sweep(cps_handle* h, int32_t level, int32_t parity, const double* b,
+                                 double* x)
+{
+    return guarded([&] {
+        need_level(h, level, true);
+        if (parity < 0 || parity > 1) fail(CPS_E_INVALID, "bad parity");
+        if (h->opts.smoother != 1) fail(CPS_E_INVALID, "handle not set up with smoother = 1");
+        Buf<double> bs, xs;
+        const double* bp = split_copy(h, level, b, bs);
+        double* xp = split_copy(h, level, x, xs);
+        plane_half_sweep<double>(h, level, parity, bp, xp);
         natural_copy(h, level, xp, x);
     });
 }

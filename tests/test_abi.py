@@ -97,13 +97,13 @@ def test_service_report_layout_and_footprint(tmp_path):
     if not os.path.exists(cps.LIB_PATH):
         pytest.skip("libcps.so not built")
     from paper_2305_17875_amd.inputs import Shell, MAP_OBLATE
-    opts = cps.cps_opts(1, 200, 1, 0, 0, None)
+    opts = cps.cps_opts(1, 200, 1, 0, 0, 0, None)
     f = [cps.cps_service_footprint(cps.make_grid(Shell(*s)), opts)
          for s in [(16, 16, 16), (32, 32, 32), (64, 64, 128)]]
     assert f[0] < f[1] < f[2]
     n = 64 * 64 * 128
     assert f[2] > 8 * 5 * n  # at least the five FP64 vectors of the finest level
-    bicg = cps.cps_opts(1, 200, 2, 0, 0, None)
+    bicg = cps.cps_opts(1, 200, 2, 0, 0, 0, None)
     fo = cps.cps_service_footprint(cps.make_grid(Shell(64, 64, 128, map=MAP_OBLATE,
                                                         flattening=0.1)), bicg)
     assert fo > f[2]  # BiCGStab's extra vectors

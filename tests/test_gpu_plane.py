@@ -1,0 +1,113 @@
+"""The zebra (r, phi)-plane smoother on the GPU (Fourier transform along phi
++ Thomas along r) against the oracle's exact block Gauss-Seidel solves
+(sparse LU of every (r, phi) plane), its V-cycle against the oracle's plane
+V-cycle, and solves against the oracle's exact solution."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import direct, plane
+from paper_2305_17875_amd import cps, inputs
+from paper_2305_17875_amd.inputs import Shell, MAP_OBLATE, MAP_IDENTITY
+from gpu_util import needs_gpu, log, dev, host, rel, relmax, torch
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+CASES = [
+    ("sphere-stretch-8x8x64", Shell(8, 8, 64, radial_stretch=2.0)),
+    ("sphere-6x10x32", Shell(6, 10, 32)),           # 5 rows of each parity
+    ("sphere-8x6x128", Shell(8, 6, 128, radial_stretch=2.0)),
+    ("sphere-4x4x2048", Shell(4, 4, 2048)),         # the longest ring (1024 per parity)
+    ("identity-8x8x32", Shell(8, 8, 32, map=MAP_IDENTITY)),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    name, g = request.param
+    log("plane", name)
+    s = cps.Solver(g, precision=0, accel=0, smoother=1)
+    mg = O.Multigrid(g)
+    yield name, g, s, mg
+    s.close()
+
+
+def test_half_sweeps_match_block_gauss_seidel(case):
+    """Per entry to 1e-11 relative: the transform of a ring of up to 2048
+    cells adds ~log2(n) roundings, amplified by the plane systems' condition
+    (phi coupling ~1e3 x the theta coupling on the longest ring)."""
+    name, g, s, mg = case
+    rng = np.random.default_rng(11)
+    for l, shp in enumerate(s.levels[:-1]):
+        G = mg.metrics(l)
+        sm = plane.PlaneSmoother(G)
+        b = rng.standard_normal(shp)
+        x = rng.standard_normal(shp)
+        for parity in (0, 1):
+            want = sm.half_sweep(b, x, parity)
+            xd = dev(x).flatten()
+            cps.cps_debug_plane_sweep(s.h, l, parity, dev(b).flatten(), xd)
+            got = host(xd).reshape(shp)
+            assert relmax(got, want) < 1e-11, (l, parity, relmax(got, want))
+            x = want
+
+
+def test_plane_vcycle_matches_oracle(case):
+    name, g, s, mg = case
+    pm = plane.PlaneMultigrid(mg, nu=2)
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal(g.shape)
+    b -= b.mean()
+    x = rng.standard_normal(g.shape) * 0.1
+    want = pm.vcycle(b, x)
+    xd = dev(x).flatten()
+    cps.cps_debug_vcycle(s.h, dev(b).flatten(), xd)
+    got = host(xd).reshape(g.shape)
+    assert relmax(got, want) < 1e-11, relmax(got, want)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plane_solve_against_exact_and_fewer_cycles(precision):
+    g = Shell(32, 32, 64, radial_stretch=2.0)
+    b = inputs.smoothed_noise(g.shape, 21)
+    want = direct.solve_axisym(O.face_metrics(g), b)
+    out = {}
+    for sm in (0, 1):
+        s = cps.Solver(g, precision=precision, accel=1, smoother=sm, max_iters=400)
+        try:
+            r = s.solve(dev(b).flatten())
+            out[sm] = (host(r.p).reshape(g.shape), r)
+        finally:
+            s.close()
+    x, r = out[1]
+    assert r.status == cps.CPS_OK and r.rel_residual <= 1e-10
+    assert rel(x, want) <= 1e-9, rel(x, want)
+    log("plane cycles", precision, out[0][1].iterations, r.iterations)
+    assert r.iterations * 3 <= out[0][1].iterations
+
+
+def test_plane_smoother_rejects_what_it_cannot_do():
+    with pytest.raises(cps.CpsError, match="7-point"):
+        cps.Solver(Shell(16, 16, 32, map=MAP_OBLATE, flattening=0.1), smoother=1)
+    with pytest.raises(cps.CpsError, match="power of two"):
+        cps.Solver(Shell(16, 16, 48), smoother=1)
+    with pytest.raises(cps.CpsError, match="point smoother"):
+        cps.cps_batch_setup([cps.make_grid(Shell(16, 16, 16))], cps.cps_metrics(0),
+                            cps.cps_opts(1, 200, 1, 0, 0, 1, None))
+
+
+def test_plane_graph_replays_equal_eager():
+    g = Shell(16, 16, 64, radial_stretch=2.0)
+    side = torch.cuda.Stream()
+    sg = cps.Solver(g, precision=1, accel=1, smoother=1, stream=side)
+    se = cps.Solver(g, precision=1, accel=1, smoother=1, stream=side, eager=True)
+    try:
+        for k in range(3):
+            b = dev(inputs.smoothed_noise(g.shape, 400 + k)).flatten()
+            torch.cuda.synchronize()
+            xg = host(sg.solve(b).p)
+            xe = host(se.solve(b).p)
+            assert np.array_equal(xg, xe), k
+    finally:
+        sg.close()
+        se.close()
