@@ -152,6 +152,9 @@ struct LevelMem {
     // n_phi) (m <= nh) as (re, im) pairs, and the symbols 2 cos(2 pi m/n_phi) - 2
     Buf<double> tw64, twN64, lam64;
     Buf<float> tw32, twN32, lam32;
+    // inverse pivots of the r-line eliminations of both parities (plane.hpp)
+    Buf<double> pv64;
+    Buf<float> pv32;
 };
 
 } // namespace
@@ -173,9 +176,9 @@ struct cps_handle {
     double* hsc = nullptr; // pinned host mirror
     // level-0 FP64 work vectors
     Buf<double> x0, b0, r, z, pd, q, r0, v, s, t, ph, sh;
-    // plane smoother scratch: spectra and elimination factors of one parity
-    Buf<double> ps64, pc64;
-    Buf<float> ps32, pc32;
+    // plane smoother scratch: the spectra of one parity
+    Buf<double> ps64;
+    Buf<float> ps32;
     // captured outer-iteration bodies (G_* keys), replayed by run_body
     hipGraphExec_t gexec[4] = {};
     // optional HIP-event timing of the finest-level kernels, per class
@@ -322,16 +325,16 @@ struct PlaneBufs<double> {
     static const double* tw(const LevelMem& m) { return m.tw64.p; }
     static const double* twN(const LevelMem& m) { return m.twN64.p; }
     static const double* lam(const LevelMem& m) { return m.lam64.p; }
+    static const double* piv(const LevelMem& m) { return m.pv64.p; }
     static double* S(cps_handle* h) { return h->ps64.p; }
-    static double* C(cps_handle* h) { return h->pc64.p; }
 };
 template <>
 struct PlaneBufs<float> {
     static const float* tw(const LevelMem& m) { return m.tw32.p; }
     static const float* twN(const LevelMem& m) { return m.twN32.p; }
     static const float* lam(const LevelMem& m) { return m.lam32.p; }
+    static const float* piv(const LevelMem& m) { return m.pv32.p; }
     static float* S(cps_handle* h) { return h->ps32.p; }
-    static float* C(cps_handle* h) { return h->pc32.p; }
 };
 
 template <typename T>
@@ -340,19 +343,21 @@ void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
     using PB = PlaneBufs<T>;
     const Level<T> L = view<T>(h, l);
     const LevelMem& m = h->lv[l];
-    if (!PB::tw(m) || !PB::S(h)) fail(CPS_E_INVALID, "internal: plane smoother not set up");
+    if (!PB::tw(m) || !PB::S(h) || !PB::piv(m))
+        fail(CPS_E_INVALID, "internal: plane smoother not set up");
     const PlaneLaunch pl = plane_launch(L.g, parity);
     const auto* tw = reinterpret_cast<const Vec2<T>*>(PB::tw(m));
     const auto* twN = reinterpret_cast<const Vec2<T>*>(PB::twN(m));
     auto* S = reinterpret_cast<Vec2<T>*>(PB::S(h));
     ProfScope ps(h, CPS_KERNEL_GS, l);
-    k_plane_fwd<T><<<pl.blocks, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, b, x, parity, tw, twN, S);
+    k_plane_fwd<T><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, L.G, L.gk, b, x, parity, tw,
+                                                            twN, S);
     LAUNCH_CHECK();
-    const long long sys = (long long)pl.rows * (L.g.nh + 1);
-    k_plane_tri<T><<<nblk(sys), kBlock, 0, h->stream>>>(L.g, L.G, L.gk, parity, PB::lam(m), S,
-                                                        PB::C(h));
+    const long long lanes = 2LL * pl.rows * (L.g.nh + 1);
+    k_plane_tri<T><<<(unsigned)cdiv(lanes, kTriBlock), kTriBlock, 0, h->stream>>>(
+        L.g, L.G, parity, PB::piv(m) + plane_pivot_offset(L.g, parity), PB::S(h));
     LAUNCH_CHECK();
-    k_plane_inv<T><<<pl.blocks, kBlock, 0, h->stream>>>(L.g, parity, tw, twN, S, x);
+    k_plane_inv<T><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN, S, x);
     LAUNCH_CHECK();
 }
 
@@ -717,6 +722,28 @@ void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
 // operator.  Buffers are allocated on first use and reused when the
 // operator is recomputed for a new map of the same dims (remap); returns
 // the stencil class (MODE_*) found.
+// Inverse pivots of the plane smoother's r-line eliminations on every
+// smoothed level, in the precision the cycles run in.  They depend on the
+// metrics only: computed at set-up and again when the metrics change.
+void plane_factors(cps_handle* h)
+{
+    const bool mixed = h->opts.precision == 1;
+    for (int l = 0; l + 1 < h->L; ++l) {
+        const LevelMem& m = h->lv[l];
+        for (int k = 0; k < 2; ++k) {
+            const long long sys = (long long)((m.nt - k + 1) / 2) * (m.np / 2 + 1);
+            const long long off = plane_pivot_offset(m.geo, k);
+            if (mixed)
+                k_plane_factor<float><<<nblk(sys), kBlock, 0, h->stream>>>(
+                    m.geo, m.G32.p, m.gk, k, m.lam32.p, m.pv32.p + off);
+            else
+                k_plane_factor<double><<<nblk(sys), kBlock, 0, h->stream>>>(
+                    m.geo, m.G64.p, m.gk, k, m.lam64.p, m.pv64.p + off);
+            LAUNCH_CHECK();
+        }
+    }
+}
+
 int compute_operator(cps_handle* h)
 {
     const cps_grid& g = h->grid;
@@ -811,6 +838,7 @@ int compute_operator(cps_handle* h)
         A.release(); M0.release(); E.release(); Xp.release();
         used.release(); piv.release(); bad.release();
     }
+    if (h->lv[0].pv64.p || h->lv[0].pv32.p) plane_factors(h); // new metrics of a set-up hierarchy
     return mode;
 }
 
@@ -869,11 +897,15 @@ void setup_plane(cps_handle* h)
         up64(m.tw64, tw); up64(m.twN64, twN); up64(m.lam64, lam);
         if (mixed) { up32(m.tw32, tw); up32(m.twN32, twN); up32(m.lam32, lam); }
         spec = std::max(spec, (size_t)m.nr * ((m.nt + 1) / 2) * (nh + 1));
+        // pivots of both parities, in the precision of the cycles (FP64 for
+        // the FP64 hierarchy and its per-step entry points)
+        const size_t npiv = (size_t)m.nr * m.nt * (nh + 1);
+        if (mixed) m.pv32.alloc(npiv);
+        else m.pv64.alloc(npiv);
     }
-    // FP64 scratch for the FP64 hierarchy (and its per-step entry points),
-    // FP32 scratch for the mixed form's cycles
-    if (!mixed) { h->ps64.alloc(2 * spec); h->pc64.alloc(spec); }
-    else { h->ps32.alloc(2 * spec); h->pc32.alloc(spec); }
+    if (!mixed) h->ps64.alloc(2 * spec);
+    else h->ps32.alloc(2 * spec);
+    plane_factors(h);
 }
 
 void build(cps_handle* h)

@@ -16,13 +16,17 @@
 //  - k_plane_fwd: right-hand side of each (r, row) ring and its real Fourier
 //    transform.  A ring of n_phi reals is the complex sequence
 //    z_j = x_{2j} + i x_{2j+1}, exactly the two parity planes of the split
-//    layout; a Stockham radix-2 transform of length n_phi/2 in LDS and the
-//    usual even/odd recombination give the n_phi/2 + 1 modes;
-//  - k_plane_tri: one thread per (row, mode) runs the Thomas algorithm down
-//    and up the r-line, keeping the elimination factors in a scratch array;
+//    layout; a Stockham radix-4 transform of length n_phi/2 in LDS and the
+//    usual even/odd recombination give the n_phi/2 + 1 modes.  The lanes of
+//    a ring lie in one wavefront, so the stages need no block barrier;
+//  - k_plane_tri: forward elimination and back substitution down and up the
+//    r-line of every (row, mode), real and imaginary parts on two lanes.  The
+//    inverse pivots depend on the operator only and are computed once per
+//    set-up (k_plane_factor); a pass streams the spectra and the pivots with
+//    a batch of r-steps in flight per lane;
 //  - k_plane_inv: the inverse transform back into the rows.
-// Spectra are laid out [a][row][mode], so the r-line solves read and write
-// consecutive modes across a wavefront.
+// Spectra and pivots are laid out [a][row][mode], so the r-line solves read
+// and write consecutive modes across a wavefront.
 
 namespace cps {
 
@@ -43,48 +47,124 @@ __device__ __forceinline__ Vec2<T> conjv(Vec2<T> a)
 }
 
 constexpr int kPlaneLds = 1024; // complex values per LDS buffer (rings x length)
+constexpr int kTriBlock = 64;
+constexpr int kTriBatch = 8;   // r-steps whose loads a lane issues together
+constexpr int kLdBatch = 4;    // ring positions whose loads a lane issues together
 
-// Stockham radix-2 transform of length n (a power of 2) of the ring held at
-// A + ring * n, tpr threads per ring; the result is in the returned buffer.
-// tw[q] = exp(-2 pi i q / n) for q < n / 2; inverse: conjugate twiddles, no
-// scaling.  Every thread of the block must call it (it holds the barriers).
-template <typename T>
-__device__ Vec2<T>* lds_fft(Vec2<T>* A, Vec2<T>* B, int n, int ring, int tr, int tpr,
-                            const Vec2<T>* __restrict__ tw, bool inverse)
+// Orders the LDS accesses of the lanes of one wavefront (no block barrier).
+__device__ __forceinline__ void wave_sync()
 {
-    for (int Ls = 1; Ls < n; Ls <<= 1) {
-        const int stride = n / (2 * Ls);
-        for (int t = tr; t < n / 2; t += tpr) {
-            const int j = t & (Ls - 1), k = t / Ls;
-            Vec2<T> w = tw[j * stride];
-            if (inverse) w.y = -w.y;
-            const Vec2<T> a = A[ring * n + k * Ls + j];
-            const Vec2<T> wb = cmul(w, A[ring * n + k * Ls + j + n / 2]);
-            B[ring * n + 2 * k * Ls + j] = a + wb;
-            B[ring * n + 2 * k * Ls + j + Ls] = a - wb;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// In-place Stockham transform of length n (a power of 2, <= kPlaneLds) of
+// one ring held at A, tpr lanes of one wavefront per ring: a radix-2 stage
+// when log2 n is odd, then radix-4 stages.  A stage reads all of its inputs
+// into registers before any lane writes, so one buffer serves; the lanes of
+// a ring are one wavefront, so the stages need no block barrier.  tw[q] =
+// exp(-2 pi i q / n) for q < n / 2 (in LDS); inverse: conjugate twiddles and
+// rotations, no scaling.
+//
+// A radix-4 stage of span Ls merges the four length-Ls transforms at block
+// offsets q n / 4 (q = 0..3, the residues q of the index mod 4 Ls / Ls) into
+// one of length 4 Ls: y_{j + p Ls} = sum_q (-i)^{pq} W^{qj} X_q[j],
+// W = exp(-2 pi i / (4 Ls)); W^{qj} = tw[q j n / (4 Ls)], and for an index
+// past n / 2, tw[s] = -tw[s - n / 2].
+template <typename T>
+__device__ void wave_fft(Vec2<T>* A, int n, int tr, int tpr, const Vec2<T>* tw, bool inverse)
+{
+    constexpr int kB2 = kPlaneLds / 128, kB4 = kPlaneLds / 256; // butterflies per lane
+    int Ls = 1;
+    if (__builtin_ctz(n) & 1) {
+        Vec2<T> u[kB2], v[kB2];
+#pragma unroll
+        for (int i = 0; i < kB2; ++i) {
+            const int t = tr + i * tpr;
+            if (t < n / 2) {
+                u[i] = A[t];
+                v[i] = A[t + n / 2];
+            }
         }
-        __syncthreads();
-        Vec2<T>* s = A;
-        A = B;
-        B = s;
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < kB2; ++i) {
+            const int t = tr + i * tpr;
+            if (t < n / 2) {
+                A[2 * t] = u[i] + v[i];
+                A[2 * t + 1] = u[i] - v[i];
+            }
+        }
+        wave_sync();
+        Ls = 2;
     }
-    return A;
+    for (; Ls < n; Ls *= 4) {
+        const int stride = n / (4 * Ls);
+        Vec2<T> c[kB4][4];
+#pragma unroll
+        for (int i = 0; i < kB4; ++i) {
+            const int t = tr + i * tpr;
+            if (t < n / 4) {
+                const int j = t & (Ls - 1), k = t / Ls;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) c[i][q] = A[k * Ls + j + q * (n / 4)];
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < kB4; ++i) {
+            const int t = tr + i * tpr;
+            if (t < n / 4) {
+                const int j = t & (Ls - 1), k = t / Ls;
+                const int s1 = j * stride, s3 = 3 * j * stride;
+                Vec2<T> w1 = tw[s1], w2 = tw[2 * s1];
+                Vec2<T> w3 = s3 < n / 2 ? tw[s3] : -tw[s3 - n / 2];
+                if (inverse) {
+                    w1.y = -w1.y;
+                    w2.y = -w2.y;
+                    w3.y = -w3.y;
+                }
+                const Vec2<T> c0 = c[i][0], c1 = cmul(w1, c[i][1]), c2 = cmul(w2, c[i][2]),
+                              c3 = cmul(w3, c[i][3]);
+                const Vec2<T> s02 = c0 + c2, d02 = c0 - c2, s13 = c1 + c3, d13 = c1 - c3;
+                Vec2<T> rot; // -i d13 (forward), +i d13 (inverse)
+                rot.x = inverse ? -d13.y : d13.y;
+                rot.y = inverse ? d13.x : -d13.x;
+                Vec2<T>* o = A + 4 * k * Ls + j;
+                o[0] = s02 + s13;
+                o[Ls] = d02 + rot;
+                o[2 * Ls] = s02 - s13;
+                o[3 * Ls] = d02 - rot;
+            }
+        }
+        wave_sync();
+    }
 }
 
 struct PlaneLaunch {
-    int tpr, rb, rows, rings, blocks;
+    int tpr, rb, threads, rows, rings, blocks;
 };
 
-// rows of parity k; threads per ring and rings per 256-thread block
+// rows of parity k; lanes per ring (a power of two <= 64, so a ring never
+// straddles wavefronts), rings per block (<= 256 lanes, <= kPlaneLds values)
 __host__ __device__ inline PlaneLaunch plane_launch(const Geo& g, int parity)
 {
     PlaneLaunch p;
     p.rows = (g.nt - parity + 1) / 2;
-    p.tpr = g.nh / 2 < kBlock ? g.nh / 2 : kBlock;
+    p.tpr = g.nh / 2 < 64 ? g.nh / 2 : 64;
     p.rb = kBlock / p.tpr;
+    if (p.rb * g.nh > kPlaneLds) p.rb = kPlaneLds / g.nh;
+    p.threads = p.rb * p.tpr;
     p.rings = g.nr * p.rows;
     p.blocks = (p.rings + p.rb - 1) / p.rb;
     return p;
+}
+
+// offset of parity k's pivots in a level's table
+__host__ __device__ inline long long plane_pivot_offset(const Geo& g, int parity)
+{
+    return parity ? (long long)g.nr * ((g.nt + 1) / 2) * (g.nh + 1) : 0;
 }
 
 // Right-hand sides of the rings of parity k and their real transforms:
@@ -97,60 +177,95 @@ __global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict
                                                       const Vec2<T>* __restrict__ twN,
                                                       Vec2<T>* __restrict__ S)
 {
-    __shared__ Vec2<T> bufA[kPlaneLds], bufB[kPlaneLds];
+    __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
     const PlaneLaunch pl = plane_launch(g, parity);
     const int nh = g.nh;
+    for (int q = (int)threadIdx.x; q < nh / 2; q += pl.threads) twS[q] = tw[q];
     const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
     const int ring = (int)blockIdx.x * pl.rb + rl;
     const bool live = ring < pl.rings;
     const int a = live ? ring / pl.rows : 0, bi = live ? ring - a * pl.rows : 0;
     const int b = 2 * bi + parity;
+    Vec2<T>* A = buf + rl * nh;
     if (live) {
         const long long ci = (long long)a * g.nt + b;
         const T gtl = G[4 * gk + ci];
         const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
         const long long base = (long long)a * g.rowlen + (long long)b * nh;
-        for (int j = tr; j < nh; j += pl.tpr) {
-            Vec2<T> z;
-            z.x = bv[base + j];
-            z.y = bv[g.P + base + j];
-            if (b > 0) {
-                z.x -= gtl * x[base - nh + j];
-                z.y -= gtl * x[g.P + base - nh + j];
+        const bool lo = b > 0, hi = b < g.nt - 1;
+        for (int j0 = tr; j0 < nh; j0 += kLdBatch * pl.tpr) {
+            // the loads of a batch are all issued before any is used
+            T e[kLdBatch], o[kLdBatch], el[kLdBatch], ol[kLdBatch], eh[kLdBatch], oh[kLdBatch];
+#pragma unroll
+            for (int u = 0; u < kLdBatch; ++u) {
+                const int j = j0 + u * pl.tpr;
+                if (j < nh) {
+                    e[u] = ld_once(bv + base + j);
+                    o[u] = ld_once(bv + g.P + base + j);
+                    el[u] = lo ? x[base - nh + j] : T(0);
+                    ol[u] = lo ? x[g.P + base - nh + j] : T(0);
+                    eh[u] = hi ? x[base + nh + j] : T(0);
+                    oh[u] = hi ? x[g.P + base + nh + j] : T(0);
+                }
             }
-            if (b < g.nt - 1) {
-                z.x -= gth * x[base + nh + j];
-                z.y -= gth * x[g.P + base + nh + j];
+#pragma unroll
+            for (int u = 0; u < kLdBatch; ++u) {
+                const int j = j0 + u * pl.tpr;
+                if (j < nh) {
+                    Vec2<T> z;
+                    z.x = e[u];
+                    z.y = o[u];
+                    if (lo) {
+                        z.x -= gtl * el[u];
+                        z.y -= gtl * ol[u];
+                    }
+                    if (hi) {
+                        z.x -= gth * eh[u];
+                        z.y -= gth * oh[u];
+                    }
+                    A[j] = z;
+                }
             }
-            bufA[rl * nh + j] = z;
         }
-    } else {
-        for (int j = tr; j < nh; j += pl.tpr) bufA[rl * nh + j] = Vec2<T>{T(0), T(0)};
     }
-    __syncthreads();
-    const Vec2<T>* Z = lds_fft<T>(bufA, bufB, nh, rl, tr, pl.tpr, tw, false);
+    __syncthreads(); // twiddles of the block (the ring's values are wave-local)
     if (!live) return;
+    wave_fft<T>(A, nh, tr, pl.tpr, twS, false);
+    const Vec2<T>* Z = A;
     Vec2<T>* out = S + (long long)ring * (nh + 1);
-    for (int m = tr; m <= nh; m += pl.tpr) {
-        const Vec2<T> zm = Z[rl * nh + (m == nh ? 0 : m)];
-        const Vec2<T> zc = conjv(Z[rl * nh + (m == 0 ? 0 : nh - m)]);
-        // even part E = (zm + zc) / 2, odd part O = (zm - zc) / (2i)
-        Vec2<T> E, O;
-        E.x = T(0.5) * (zm.x + zc.x);
-        E.y = T(0.5) * (zm.y + zc.y);
-        O.x = T(0.5) * (zm.y - zc.y);
-        O.y = -T(0.5) * (zm.x - zc.x);
-        out[m] = E + cmul(twN[m], O);
+    for (int m0 = tr; m0 <= nh; m0 += kLdBatch * pl.tpr) {
+        Vec2<T> w[kLdBatch];
+#pragma unroll
+        for (int u = 0; u < kLdBatch; ++u) {
+            const int m = m0 + u * pl.tpr;
+            if (m <= nh) w[u] = twN[m];
+        }
+#pragma unroll
+        for (int u = 0; u < kLdBatch; ++u) {
+            const int m = m0 + u * pl.tpr;
+            if (m <= nh) {
+                const Vec2<T> zm = Z[m == nh ? 0 : m];
+                const Vec2<T> zc = conjv(Z[m == 0 ? 0 : nh - m]);
+                // even part E = (zm + zc) / 2, odd part O = (zm - zc) / (2i)
+                Vec2<T> E, O;
+                E.x = T(0.5) * (zm.x + zc.x);
+                E.y = T(0.5) * (zm.y + zc.y);
+                O.x = T(0.5) * (zm.y - zc.y);
+                O.y = -T(0.5) * (zm.x - zc.x);
+                out[m] = E + cmul(w[u], O);
+            }
+        }
     }
 }
 
-// Thomas algorithm along r for every (row, mode) of parity k, in place in S;
-// cp: scratch for the elimination factors (same indexing as S).
+// Inverse pivots of the Thomas elimination of every (row, mode) r-line of
+// parity k: P[(a rows + bi)(nh + 1) + m] = 1 / (diag - grl c_{a-1}),
+// c_a = grh_a P_a.  One thread per (row, mode); set-up only.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_plane_tri(Geo g, const T* __restrict__ G, long long gk,
-                                                      int parity, const T* __restrict__ lam,
-                                                      Vec2<T>* __restrict__ S,
-                                                      T* __restrict__ cp)
+__global__ void __launch_bounds__(kBlock) k_plane_factor(Geo g, const T* __restrict__ G,
+                                                         long long gk, int parity,
+                                                         const T* __restrict__ lam,
+                                                         T* __restrict__ P)
 {
     const int rows = (g.nt - parity + 1) / 2;
     const int nm = g.nh + 1;
@@ -159,9 +274,8 @@ __global__ void __launch_bounds__(kBlock) k_plane_tri(Geo g, const T* __restrict
     const int bi = (int)(t / nm), m = (int)(t - (long long)bi * nm);
     const int b = 2 * bi + parity;
     const T lm = lam[m];
-    const long long stride = (long long)rows * nm; // one r-plane of spectra
+    const long long stride = (long long)rows * nm;
     T c = T(0);
-    Vec2<T> d{T(0), T(0)};
     for (int a = 0; a < g.nr; ++a) {
         const long long ci = (long long)a * g.nt + b;
         const T grl = G[ci];
@@ -170,22 +284,71 @@ __global__ void __launch_bounds__(kBlock) k_plane_tri(Geo g, const T* __restrict
         const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
         const T diag = -(grl + grh + gtl + gth) + G[8 * gk + ci] * lm;
         const T inv = T(1) / (diag - grl * c);
-        const long long o = (long long)a * stride + t;
-        const Vec2<T> r = S[o];
-        d.x = (r.x - grl * d.x) * inv;
-        d.y = (r.y - grl * d.y) * inv;
+        P[a * stride + t] = inv;
         c = grh * inv;
-        S[o] = d;
-        cp[o] = c;
     }
-    Vec2<T> xn = d; // X at a = nr - 1
-    for (int a = g.nr - 2; a >= 0; --a) {
-        const long long o = (long long)a * stride + t;
-        const Vec2<T> da = S[o];
-        const T ca = cp[o];
-        xn.x = da.x - ca * xn.x;
-        xn.y = da.y - ca * xn.y;
-        S[o] = xn;
+}
+
+// Thomas algorithm along r for every (row, mode) of parity k, in place in
+// the spectra S (read as reals: lane 2u + q takes component q of system u),
+// with the inverse pivots P of k_plane_factor.
+template <typename T>
+__global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restrict__ G, int parity,
+                                                         const T* __restrict__ P,
+                                                         T* __restrict__ S)
+{
+    const int rows = (g.nt - parity + 1) / 2;
+    const int nm = g.nh + 1, nr = g.nr, nt = g.nt;
+    const long long sys = (long long)rows * nm; // one r-plane of spectra
+    const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= 2 * sys) return;
+    const long long t = u >> 1;
+    const int q = (int)(u & 1);
+    const int b = 2 * (int)(t / nm) + parity;
+    T d = T(0);
+    for (int a0 = 0; a0 < nr; a0 += kTriBatch) {
+        T r[kTriBatch], p[kTriBatch], gl[kTriBatch];
+#pragma unroll
+        for (int k = 0; k < kTriBatch; ++k) {
+            const int a = a0 + k;
+            if (a < nr) {
+                const long long o = a * sys + t;
+                r[k] = S[2 * o + q];
+                p[k] = P[o];
+                gl[k] = G[(long long)a * nt + b];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kTriBatch; ++k) {
+            const int a = a0 + k;
+            if (a < nr) {
+                d = (r[k] - gl[k] * d) * p[k];
+                S[2 * (a * sys + t) + q] = d;
+            }
+        }
+    }
+    T xn = d; // X at a = nr - 1
+    for (int a0 = nr - 2; a0 >= 0; a0 -= kTriBatch) {
+        T s[kTriBatch], p[kTriBatch], gh[kTriBatch];
+#pragma unroll
+        for (int k = 0; k < kTriBatch; ++k) {
+            const int a = a0 - k;
+            if (a >= 0) {
+                const long long o = a * sys + t;
+                s[k] = S[2 * o + q];
+                p[k] = P[o];
+                gh[k] = G[(long long)(a + 1) * nt + b];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kTriBatch; ++k) {
+            const int a = a0 - k;
+            if (a >= 0) {
+                const T c = gh[k] * p[k];
+                xn = s[k] - c * xn;
+                S[2 * (a * sys + t) + q] = xn;
+            }
+        }
     }
 }
 
@@ -197,41 +360,56 @@ __global__ void __launch_bounds__(kBlock) k_plane_inv(Geo g, int parity,
                                                       const Vec2<T>* __restrict__ S,
                                                       T* __restrict__ x)
 {
-    __shared__ Vec2<T> bufA[kPlaneLds], bufB[kPlaneLds];
+    __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
     const PlaneLaunch pl = plane_launch(g, parity);
     const int nh = g.nh;
+    for (int q = (int)threadIdx.x; q < nh / 2; q += pl.threads) twS[q] = tw[q];
     const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
     const int ring = (int)blockIdx.x * pl.rb + rl;
     const bool live = ring < pl.rings;
+    Vec2<T>* A = buf + rl * nh;
     if (live) {
         const Vec2<T>* X = S + (long long)ring * (nh + 1);
-        for (int m = tr; m < nh; m += pl.tpr) {
-            const Vec2<T> xm = X[m];
-            const Vec2<T> xc = conjv(X[nh - m]);
-            // E = (xm + xc) / 2, O = (xm - xc) conj(twN[m]) / 2, Z = E + i O
-            Vec2<T> E, D;
-            E.x = T(0.5) * (xm.x + xc.x);
-            E.y = T(0.5) * (xm.y + xc.y);
-            D.x = T(0.5) * (xm.x - xc.x);
-            D.y = T(0.5) * (xm.y - xc.y);
-            const Vec2<T> O = cmul(conjv(twN[m]), D);
-            Vec2<T> z;
-            z.x = E.x - O.y;
-            z.y = E.y + O.x;
-            bufA[rl * nh + m] = z;
+        for (int m0 = tr; m0 < nh; m0 += kLdBatch * pl.tpr) {
+            Vec2<T> xm[kLdBatch], xc[kLdBatch], w[kLdBatch];
+#pragma unroll
+            for (int u = 0; u < kLdBatch; ++u) {
+                const int m = m0 + u * pl.tpr;
+                if (m < nh) {
+                    xm[u] = X[m];
+                    xc[u] = conjv(X[nh - m]);
+                    w[u] = conjv(twN[m]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kLdBatch; ++u) {
+                const int m = m0 + u * pl.tpr;
+                if (m < nh) {
+                    // E = (xm + xc) / 2, O = (xm - xc) conj(twN[m]) / 2, Z = E + i O
+                    Vec2<T> E, D;
+                    E.x = T(0.5) * (xm[u].x + xc[u].x);
+                    E.y = T(0.5) * (xm[u].y + xc[u].y);
+                    D.x = T(0.5) * (xm[u].x - xc[u].x);
+                    D.y = T(0.5) * (xm[u].y - xc[u].y);
+                    const Vec2<T> O = cmul(w[u], D);
+                    Vec2<T> z;
+                    z.x = E.x - O.y;
+                    z.y = E.y + O.x;
+                    A[m] = z;
+                }
+            }
         }
-    } else {
-        for (int m = tr; m < nh; m += pl.tpr) bufA[rl * nh + m] = Vec2<T>{T(0), T(0)};
     }
-    __syncthreads();
-    const Vec2<T>* z = lds_fft<T>(bufA, bufB, nh, rl, tr, pl.tpr, tw, true);
+    __syncthreads(); // twiddles of the block (the ring's values are wave-local)
     if (!live) return;
+    wave_fft<T>(A, nh, tr, pl.tpr, twS, true);
+    const Vec2<T>* z = A;
     const int a = ring / pl.rows, bi = ring - a * pl.rows;
     const int b = 2 * bi + parity;
     const long long base = (long long)a * g.rowlen + (long long)b * nh;
     const T s = T(1) / T(nh);
     for (int j = tr; j < nh; j += pl.tpr) {
-        const Vec2<T> v = z[rl * nh + j];
+        const Vec2<T> v = z[j];
         x[base + j] = v.x * s;
         x[g.P + base + j] = v.y * s;
     }

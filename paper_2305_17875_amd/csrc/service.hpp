@@ -74,10 +74,11 @@ size_t handle_bytes(const cps_handle* h)
     add(h->Ainv); add(h->partial); add(h->sc);
     add(h->x0); add(h->b0); add(h->r); add(h->z); add(h->pd); add(h->q);
     add(h->r0); add(h->v); add(h->s); add(h->t); add(h->ph); add(h->sh);
-    add(h->ps64); add(h->pc64); add(h->ps32); add(h->pc32);
+    add(h->ps64); add(h->ps32);
     for (int l = 0; l < h->L; ++l) {
         const LevelMem& m = h->lv[l];
         add(m.tw64); add(m.twN64); add(m.lam64); add(m.tw32); add(m.twN32); add(m.lam32);
+        add(m.pv64); add(m.pv32);
     }
     return s;
 }
@@ -100,9 +101,13 @@ size_t estimate_bytes(const cps_grid& g, const cps_opts& o)
     const size_t n0 = (size_t)g.n_r * g.n_theta * g.n_phi;
     const size_t nc = (size_t)dims[L - 1][0] * dims[L - 1][1] * dims[L - 1][2];
     s += n0 * 8 * (3 + 2 + (o.accel >= 1 ? 4 : 0) + (o.accel == 2 ? 5 : 0));
-    if (o.smoother == 1) // spectra and elimination factors of one parity, tables
-        s += (size_t)dims[0][0] * ((dims[0][1] + 1) / 2) * (dims[0][2] / 2 + 1) * 3 * 8 +
+    if (o.smoother == 1) { // spectra of one parity, pivots of every smoothed level, tables
+        const size_t w = mixed ? 4 : 8;
+        s += (size_t)dims[0][0] * ((dims[0][1] + 1) / 2) * (dims[0][2] / 2 + 1) * 2 * w +
              (size_t)L * (2 * dims[0][2] + 8) * 8 * 2;
+        for (int l = 0; l + 1 < L; ++l)
+            s += (size_t)dims[l][0] * dims[l][1] * (dims[l][2] / 2 + 1) * w;
+    }
     s += (2 * std::max<size_t>(n0 / kBlock + 1, kMaxGrid) + 64) * 8 + nc * nc * 8 * 4 +
          nc * kGJ * 8 * 3;
     return s;
