@@ -7,7 +7,8 @@ removed), one MI355X.
 A step is one complete cps_solve (FP64 hierarchy, conjugate gradients
 preconditioned by one V(2,2) cycle) from the right-hand side resident in HBM
 to relative residual 1e-10.  The FP32-multigrid + FP64-refinement form is
-timed on the same input and reported beside it.  Prints one JSON line.
+timed on the same input and reported beside it, and so is the same solve
+with the zebra (r, phi)-plane smoother (`plane`).  Prints one JSON line.
 
 Roofline: the dominant kernel is the finest-level Gauss-Seidel colour pass.
 Its duration is measured live with HIP events recorded on the solve stream
@@ -33,6 +34,8 @@ HBM_PEAK_GBS = 8000.0
 TOL = 1e-10
 KERNEL_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_pass_config2_traffic.json")
+PLANE_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "plane.hpp")
+PLANE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plane_half_sweep_config2_traffic.json")
 KNAMES = ["gs_pass", "residual", "apply", "restrict", "prolong", "vcycle"]
 GS_KERNEL = "k_gs_march2<double, 0, 0>"
 
@@ -41,8 +44,21 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(path=KERNEL_SRC) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def plane_traffic(key):
+    """Counter bytes of one finest-level half-sweep (fetch + write, scaled
+    by the copy yardstick) while they were taken on the current plane
+    kernel source, else None."""
+    try:
+        d = json.load(open(PLANE_TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_hash(PLANE_SRC) or key not in d:
+        return None
+    return d[key]["bytes_per_half_sweep"]
 
 
 def gs_bytes_per_launch(shape, ncol, word, phi_invariant, nterms):
@@ -76,8 +92,22 @@ def vcycle_bytes(levels, word, phi_invariant=True):
     return total + nc * nc * 8 + 2 * nc * word
 
 
-def run_form(cps, torch, g, rhs, precision, steps, warmup):
-    s = cps.Solver(g, precision=precision, accel=1, max_iters=400)
+def plane_half_sweep_bytes(shape, word):
+    """Algorithmic HBM bytes of one zebra half-sweep of the plane smoother
+    (the theta rows of one parity), per kernel with no cross-kernel fusion:
+    the forward transform reads b of the relaxed rows and x of the other
+    parity and writes the spectra; the r-line elimination reads and writes
+    the spectra twice (down and up) and reads the inverse pivots twice; the
+    inverse transform reads the spectra and writes x of the relaxed rows."""
+    nr, nt, np_ = shape
+    half = nr * nt * np_ // 2
+    spec = nr * (nt // 2) * (np_ // 2 + 1) * 2  # words: (n_phi/2 + 1) complex per ring
+    piv = spec // 2
+    return (2 * half + spec + 4 * spec + 2 * piv + spec + half) * word
+
+
+def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
+    s = cps.Solver(g, precision=precision, accel=1, max_iters=400, smoother=smoother)
     p = torch.empty_like(rhs)
     for i in range(warmup):
         res = s.solve(rhs, TOL, out=p)
@@ -94,7 +124,7 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup):
     dt = (time.perf_counter() - t0) / steps
     prof = {k: cps.cps_profile_read(s.h, k) for k in range(len(KNAMES))}
     cps.cps_profile_enable(s.h, False)
-    log(f"precision={precision}: {dt * 1e3:.1f} ms/solve, iterations={iters}, "
+    log(f"precision={precision} smoother={smoother}: {dt * 1e3:.1f} ms/solve, iterations={iters}, "
         f"rel_residual={res.rel_residual:.3e}")
     return dict(solver=s, p=p, res=res, sec=dt, iters=iters, prof=prof)
 
@@ -135,6 +165,33 @@ def yardstick(cps, torch, n):
     dt = (time.perf_counter() - t0) / reps
     del a, b
     return 16.0 * n / dt / 1e9
+
+
+def plane_form(cps, torch, g, rhs, x64, steps, warmup):
+    """The same solve with the zebra (r, phi)-plane smoother in place of
+    point red-black Gauss-Seidel (cps_opts.smoother = 1): FP64 and FP32
+    cycles, each with its half-sweep rate against the byte model of
+    plane_half_sweep_bytes."""
+    out = {"smoother": "zebra (r,phi)-plane block Gauss-Seidel: FFT along phi, "
+                       "Thomas along r per mode; V(2,2), PCG"}
+    for precision, key, word in ((0, "fp64", 8), (1, "mixed", 4)):
+        f = run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=1)
+        hs_ms, hs_n = f["prof"][cps.KERNEL_GS]
+        hs_s = hs_ms / max(hs_n, 1) * 1e-3
+        hb = plane_half_sweep_bytes(g.shape, word)
+        err = float(torch.linalg.norm(f["p"] - x64) / torch.linalg.norm(x64))
+        out[key] = {"value": g.cells / f["sec"], "unit": "unknowns/s",
+                    "ms_per_step": f["sec"] * 1e3, "iterations": f["iters"][-1],
+                    "rel_residual": f["res"].rel_residual, "rel_diff_vs_fp64_point": err,
+                    "half_sweep": {"avg_us": hs_s * 1e6, "per_step": hs_n / steps,
+                                   "algorithmic_bytes": hb, "achieved_GBs": hb / hs_s / 1e9,
+                                   "frac_of_peak": hb / hs_s / 1e9 / HBM_PEAK_GBS,
+                                   "traffic": plane_traffic("fp64" if precision == 0 else "fp32")},
+                    "kernels": kernel_table(f["prof"], steps)}
+        f["solver"].close()
+        del f
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(g, rhs_np, gpu_iters):
@@ -373,6 +430,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-plane", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
@@ -444,7 +502,11 @@ def main():
                          "kernels": kernel_table(mx["prof"], a.steps),
                          "vcycle": vcycle_rate(mx["prof"], mx["solver"].levels, 4)}
         mx["solver"].close()
+        del mx
     s64.close()
+    if not a.no_plane:
+        torch.cuda.empty_cache()
+        line["plane"] = plane_form(cps, torch, g, rhs, x64, a.steps, a.warmup)
     gpu_iters = f64["iters"][-1]
     del x64, f64, rhs
     torch.cuda.empty_cache()

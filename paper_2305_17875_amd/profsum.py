@@ -1,7 +1,8 @@
 """Summarise rocprofv3 result databases of bench.py into short text.
 
     python -m paper_2305_17875_amd.profsum --kt KT.db --fetch F.db --write W.db \\
-        --cmd "<the rocprofv3 commands>" --md out.md --traffic out.json
+        --cmd "<the rocprofv3 commands>" --md out.md --traffic out.json \\
+        [--plane-md plane.md --plane-traffic plane.json]
 
 --kt     database of `rocprofv3 --kernel-trace --stats -- python3 bench.py ...`
 --fetch  database of `rocprofv3 --pmc FETCH_SIZE -- python3 bench.py ...`
@@ -11,7 +12,10 @@ Counter values (KiB per dispatch) are scaled by what the same counter reads
 on bench.py's plain copy kernel of 192*256*512 doubles (201,326,592 bytes
 read and written), which turns them into bytes.  The traffic JSON records
 the finest-level Gauss-Seidel kernel's bytes per launch together with a hash
-of the kernel source, so bench.py can tell whether it is still current.
+of the kernel source, so bench.py can tell whether it is still current.  The
+plane outputs do the same for the three kernels of one zebra half-sweep of
+the plane smoother on the finest level (largest grid of each), FP64 and
+FP32, with a hash of the plane kernels' source.
 """
 from __future__ import annotations
 
@@ -24,6 +28,8 @@ import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "kernels.hpp")
+PLANE_SRC = os.path.join(HERE, "csrc", "plane.hpp")
+PLANE_KERNELS = ("k_plane_fwd", "k_plane_tri", "k_plane_inv")
 COPY_BYTES = 192 * 256 * 512 * 8
 GS_FINEST = "k_gs_march2<double, 0, 0>"
 
@@ -64,6 +70,8 @@ def main():
     ap.add_argument("--md", required=True)
     ap.add_argument("--traffic", required=True)
     ap.add_argument("--top", type=int, default=16)
+    ap.add_argument("--plane-md")
+    ap.add_argument("--plane-traffic")
     a = ap.parse_args()
     kh = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
     dur = durations(a.kt)
@@ -109,6 +117,44 @@ def main():
                "bytes_per_launch": gs[0] + gs[1], "fetch_bytes": gs[0], "write_bytes": gs[1],
                "fetch_scale": sf, "write_scale": sw, "avg_us_trace": mean(gsd[0]) / 1e3},
               open(a.traffic, "w"), indent=1)
+    print("\n".join(lines))
+    if a.plane_md:
+        plane_summary(a, dur, fe, wr, sf, sw)
+
+
+def plane_summary(a, dur, fe, wr, sf, sw):
+    ph = hashlib.sha256(open(PLANE_SRC, "rb").read()).hexdigest()[:16]
+    lines = ["# rocprofv3 summary: plane-smoother half-sweep, spherical shell 192x256x512",
+             "", "Same runs as the Gauss-Seidel summary (bench.py's `plane` form, FP64 and "
+             "FP32 cycles); commands:", "", "```", a.cmd, "```", "",
+             f"plane kernel source sha256[:16] = `{ph}`", "",
+             "Finest level (largest grid of each kernel), per launch:", "",
+             "| kernel | grid (threads) | launches | avg us | fetch MB | write MB |",
+             "|---|---|---|---|---|---|"]
+    out = {"kernel_source_sha256_16": ph, "fetch_scale": sf, "write_scale": sw}
+    for prec in ("double", "float"):
+        tot_us = tot_b = 0.0
+        for k in PLANE_KERNELS:
+            name = f"{k}<{prec}>"
+            grids = [g for (n, g) in dur if n == name]
+            if not grids:
+                continue
+            g = max(grids)
+            d = dur[(name, g)]
+            f = mean(fe.get((name, g, "FETCH_SIZE"), [0.0])) * 1024 * sf
+            w = mean(wr.get((name, g, "WRITE_SIZE"), [0.0])) * 1024 * sw
+            lines.append(f"| `{name}` | {g} | {len(d)} | {mean(d) / 1e3:.1f} | "
+                         f"{f / 1e6:.1f} | {w / 1e6:.1f} |")
+            tot_us += mean(d) / 1e3
+            tot_b += f + w
+        if tot_us:
+            lines.append(f"| **half-sweep {prec}** | | | **{tot_us:.1f}** | "
+                         f"{tot_b / 1e6:.1f} (fetch + write) | |")
+            out["fp64" if prec == "double" else "fp32"] = {"avg_us_trace": tot_us,
+                                                            "bytes_per_half_sweep": tot_b}
+    lines.append("")
+    open(a.plane_md, "w").write("\n".join(lines))
+    json.dump(out, open(a.plane_traffic, "w"), indent=1)
     print("\n".join(lines))
 
 
