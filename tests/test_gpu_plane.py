@@ -111,3 +111,35 @@ def test_plane_graph_replays_equal_eager():
     finally:
         sg.close()
         se.close()
+
+
+def test_service_with_plane_smoother_recomputes_pivots_on_remap():
+    """The service with smoother = 1 and one slot: three sphere stretchings
+    of one shape share a pooled hierarchy, whose metrics, coarse inverse and
+    plane pivots are recomputed in place for each new map; every result
+    equals a fresh solve bit for bit, and the footprint estimate covers the
+    resident hierarchy."""
+    shape = (16, 16, 64)
+    gs = [Shell(*shape, radial_stretch=s) for s in (0.0, 2.0, 1.0)]
+    reqs = [(g, inputs.smoothed_noise(shape, 60 + i)) for i, g in enumerate(gs)]
+    log("plane service remap")
+    svc = cps.Service(1 << 30, max_slots=1, precision=1, smoother=1)
+    try:
+        fp = svc.footprint(gs[0])
+        out = [svc.wait(svc.submit(g, b)) for g, b in reqs]
+        st = svc.stats()
+    finally:
+        svc.close()
+    for i, ((g, b), (status, p, info)) in enumerate(zip(reqs, out)):
+        assert status == cps.CPS_OK, i
+        s = cps.Solver(g, precision=1, accel=1, smoother=1)
+        try:
+            r = s.solve(dev(b).flatten())
+            xa = host(r.p).reshape(shape)
+        finally:
+            s.close()
+        assert info.iterations == r.iterations, i
+        assert np.array_equal(p, xa), (i, np.abs(p - xa).max())
+    assert st["hierarchies_built"] == 1 and st["hierarchies_reused"] == 2, st
+    assert st["map_rebuilds"] == 2, st
+    assert 0 < st["hbm_in_use"] <= fp, (st["hbm_in_use"], fp)
