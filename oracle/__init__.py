@@ -7,6 +7,8 @@ no source with it.
 * ``cps_oracle.c`` -- map, face metrics (Sec. 3.2), the nine-term flux-form
   operator of eq. (PC_8)/(PC_term1-3), Gauss-Seidel colour passes, grid
   transfers, dense coarse LU and the multigrid solve of eq. (PC_6).
+  It also holds the two steps either side of the solve: the divergence
+  right-hand side of eq. (PC_6) and the velocity correction of eq. (PC_7).
 * ``direct.py`` -- exact solves (dense, DCT/FFT on the identity box, rFFT in
   phi with sparse LU per mode on axisymmetric maps) that pin the multigrid.
 
@@ -90,6 +92,13 @@ def _load():
             lib.orc_mg_coarse_solve.argtypes = [P, P, P]
             lib.orc_mg_solve.argtypes = [P, P, P, D, I, I, P, P, P, P]
             lib.orc_mg_solve.restype = I
+            L = ctypes.c_longlong
+            lib.orc_face_crow.argtypes = [P, I, I, I, I, I, I, I, I, P]
+            lib.orc_face_crow.restype = D
+            lib.orc_cell_jdet.argtypes = [P, I, I, I, I, I, I, I]
+            lib.orc_cell_jdet.restype = D
+            lib.orc_divergence.argtypes = [P, I, I, I, I, P, L, P, P]
+            lib.orc_correct.argtypes = [P, I, I, I, I, P, P, L, P, P]
             _lib = lib
     return _lib
 
@@ -274,3 +283,69 @@ class Multigrid:
                                     ctypes.byref(it), ctypes.byref(rel), _p(hist),
                                     ctypes.byref(mean))
         return x, st, it.value, rel.value, hist[:it.value].copy(), mean.value
+
+
+# ---------------------------------------------------------------------------
+# Projection step: the right-hand side of eq. (PC_6) and eq. (PC_7)
+# ---------------------------------------------------------------------------
+
+def face_crow(grid, d: int, a: int, b: int, c: int, method: int = METRICS_CENTRAL):
+    """(C_d., |J^-1|) at the LOW d-face of cell (a, b, c); a may be n_r and
+    b may be n_theta (the high walls)."""
+    g = as_grid(grid)
+    C = np.zeros(3)
+    det = _load().orc_face_crow(ctypes.byref(g.c_struct()), *g.shape, method, d, a, b, c, _p(C))
+    return C, det
+
+
+def cell_jdet(grid, a: int, b: int, c: int, method: int = METRICS_CENTRAL) -> float:
+    """|J^-1| at the cell centre: mean of its six face determinants."""
+    g = as_grid(grid)
+    return _load().orc_cell_jdet(ctypes.byref(g.c_struct()), *g.shape, method, a, b, c)
+
+
+def _cells(g, cells):
+    if cells is None:
+        return 0, None, int(np.prod(g.shape))
+    idx = np.ascontiguousarray(cells, dtype=np.int64).ravel()
+    return idx, _p(idx), idx.size
+
+
+def divergence(grid, u, cells=None, method: int = METRICS_CENTRAL) -> np.ndarray:
+    """d/ds_j [C_ji u_i] (u: [3, n_r, n_theta, n_phi]) at every cell
+    (shape of the grid) or at the listed flat cell indices (1-D)."""
+    g = as_grid(grid)
+    u = _f64(u).reshape((3,) + g.shape)
+    idx, ptr, n = _cells(g, cells)
+    out = np.zeros(n)
+    _load().orc_divergence(ctypes.byref(g.c_struct()), *g.shape, method, _p(u), n, ptr, _p(out))
+    return out.reshape(g.shape) if cells is None else out
+
+
+def correct(grid, phi, u, cells=None, method: int = METRICS_CENTRAL) -> np.ndarray:
+    """u - (1/|J^-1|) d/ds_j [C_ji phi]: [3, n_r, n_theta, n_phi] for every
+    cell, or [n, 3] at the listed flat cell indices."""
+    g = as_grid(grid)
+    u = _f64(u).reshape((3,) + g.shape)
+    phi = _f64(phi).reshape(g.shape)
+    idx, ptr, n = _cells(g, cells)
+    out = np.zeros((n, 3))
+    _load().orc_correct(ctypes.byref(g.c_struct()), *g.shape, method, _p(phi), _p(u), n, ptr,
+                        _p(out))
+    if cells is None:
+        return np.moveaxis(out.reshape(g.shape + (3,)), -1, 0).copy()
+    return out
+
+
+def project(grid, u, method: int = METRICS_CENTRAL):
+    """The projection step with an exact solve: rhs = d/ds_j [C_ji u_i],
+    A phi = rhs - mean(rhs) with mean(phi) = 0 (``direct.solve_axisym`` for
+    phi-invariant metrics, else ``direct.solve_sparse``), then eq. (PC_7).
+    Returns (u_new, phi, rhs)."""
+    from . import direct
+    g = as_grid(grid)
+    rhs = divergence(g, u, method=method)
+    G = face_metrics(g, method=method)
+    solve = direct.solve_axisym if direct.is_axisymmetric(G) else direct.solve_sparse
+    phi = solve(G, rhs)
+    return correct(g, phi, u, method=method), phi, rhs

@@ -151,6 +151,69 @@ double orc_metric_from_chords(const double t[9], double G[9])
  * differences of nearby points, so an orthogonal map shows rounding noise of
  * about 1e-12 relative at 512 cells per direction); wall faces are
  * zero.  Returns 0, or -1 if some interior face has det <= 0. */
+/* Chords t[3q .. 3q+2] = dX/ds_q across the LOW d-face of cell (a,b,c) of a
+ * level with dims (nr, nt, np), by `method` (see orc_face_metrics).  The
+ * face may lie on a wall, including the high walls a = nr and b = nt: the
+ * map is evaluated wherever the formula asks. */
+static void og_face_chords(const og_grid* g, int nr, int nt, int np, int method, int d, int a,
+                           int b, int c, double t[9])
+{
+    double lo[3] = {a, b, c}; /* vertex at the face's low corner */
+    if (method == 0) {
+        double f[3] = {a + 0.5, b + 0.5, c + 0.5};
+        f[d] -= 0.5;
+        for (int q = 0; q < 3; ++q) {
+            double p1[3] = {f[0], f[1], f[2]}, p0[3] = {f[0], f[1], f[2]};
+            p1[q] += 0.5; p0[q] -= 0.5;
+            double X1[3], X0[3];
+            og_point(g, nr, nt, np, p1[0], p1[1], p1[2], X1);
+            og_point(g, nr, nt, np, p0[0], p0[1], p0[2], X0);
+            for (int k = 0; k < 3; ++k) t[3 * q + k] = X1[k] - X0[k];
+        }
+        return;
+    }
+    int u = (d + 1) % 3, v = (d + 2) % 3; /* tangential directions */
+    /* normal: 1/8 sum over 4 face vertices of X(v+e_d) - X(v-e_d) */
+    for (int k = 0; k < 3; ++k) t[3 * d + k] = 0.0;
+    for (int iu = 0; iu < 2; ++iu)
+        for (int iv = 0; iv < 2; ++iv) {
+            double p[3] = {lo[0], lo[1], lo[2]};
+            p[u] += iu; p[v] += iv;
+            double p1[3] = {p[0], p[1], p[2]}, p0[3] = {p[0], p[1], p[2]};
+            p1[d] += 1.0; p0[d] -= 1.0;
+            double X1[3], X0[3];
+            og_point(g, nr, nt, np, p1[0], p1[1], p1[2], X1);
+            og_point(g, nr, nt, np, p0[0], p0[1], p0[2], X0);
+            for (int k = 0; k < 3; ++k) t[3 * d + k] += 0.125 * (X1[k] - X0[k]);
+        }
+    /* tangential q: 1/2 sum over the 2 edges along q */
+    for (int s = 0; s < 2; ++s) {
+        int q = s == 0 ? u : v, o = s == 0 ? v : u;
+        for (int k = 0; k < 3; ++k) t[3 * q + k] = 0.0;
+        for (int io = 0; io < 2; ++io) {
+            double p0[3] = {lo[0], lo[1], lo[2]};
+            p0[o] += io;
+            double p1[3] = {p0[0], p0[1], p0[2]};
+            p1[q] += 1.0;
+            double X1[3], X0[3];
+            og_point(g, nr, nt, np, p1[0], p1[1], p1[2], X1);
+            og_point(g, nr, nt, np, p0[0], p0[1], p0[2], X0);
+            for (int k = 0; k < 3; ++k) t[3 * q + k] += 0.5 * (X1[k] - X0[k]);
+        }
+    }
+}
+
+/* Metrics of every face of a level with dims (nr, nt, np).
+ * method 0 (default): chords t_q of the map across the face centre,
+ *   t_q = X(f + e_q/2) - X(f - e_q/2), central differences of the map.
+ * method 1 (the paper's item 1): the normal derivative is the average over
+ *   the face's four vertices of the central difference across vertex planes
+ *   (weight 1/8), each tangential derivative is the mean of the face's two
+ *   edges along that direction (weight 1/2).
+ * Cross entries below 1e-10 sqrt(G_dd G_qq) are set to zero (chords are
+ * differences of nearby points, so an orthogonal map shows rounding noise of
+ * about 1e-12 relative at 512 cells per direction); wall faces are
+ * zero.  Returns 0, or -1 if some interior face has det <= 0. */
 int orc_face_metrics(const og_grid* g, int nr, int nt, int np, int method, double* G)
 {
     const size_t N = (size_t)nr * nt * np;
@@ -165,49 +228,7 @@ int orc_face_metrics(const og_grid* g, int nr, int nt, int np, int method, doubl
                     int wall = (d == 0 && a == 0) || (d == 1 && b == 0);
                     if (!wall) {
                         double t[9];
-                        double lo[3] = {a, b, c}; /* vertex at the face's low corner */
-                        if (method == 0) {
-                            double f[3] = {a + 0.5, b + 0.5, c + 0.5};
-                            f[d] -= 0.5;
-                            for (int q = 0; q < 3; ++q) {
-                                double p1[3] = {f[0], f[1], f[2]}, p0[3] = {f[0], f[1], f[2]};
-                                p1[q] += 0.5; p0[q] -= 0.5;
-                                double X1[3], X0[3];
-                                og_point(g, nr, nt, np, p1[0], p1[1], p1[2], X1);
-                                og_point(g, nr, nt, np, p0[0], p0[1], p0[2], X0);
-                                for (int k = 0; k < 3; ++k) t[3 * q + k] = X1[k] - X0[k];
-                            }
-                        } else {
-                            int u = (d + 1) % 3, v = (d + 2) % 3; /* tangential directions */
-                            /* normal: 1/8 sum over 4 face vertices of X(v+e_d) - X(v-e_d) */
-                            for (int k = 0; k < 3; ++k) t[3 * d + k] = 0.0;
-                            for (int iu = 0; iu < 2; ++iu)
-                                for (int iv = 0; iv < 2; ++iv) {
-                                    double p[3] = {lo[0], lo[1], lo[2]};
-                                    p[u] += iu; p[v] += iv;
-                                    double p1[3] = {p[0], p[1], p[2]}, p0[3] = {p[0], p[1], p[2]};
-                                    p1[d] += 1.0; p0[d] -= 1.0;
-                                    double X1[3], X0[3];
-                                    og_point(g, nr, nt, np, p1[0], p1[1], p1[2], X1);
-                                    og_point(g, nr, nt, np, p0[0], p0[1], p0[2], X0);
-                                    for (int k = 0; k < 3; ++k) t[3 * d + k] += 0.125 * (X1[k] - X0[k]);
-                                }
-                            /* tangential q: 1/2 sum over the 2 edges along q */
-                            for (int s = 0; s < 2; ++s) {
-                                int q = s == 0 ? u : v, o = s == 0 ? v : u;
-                                for (int k = 0; k < 3; ++k) t[3 * q + k] = 0.0;
-                                for (int io = 0; io < 2; ++io) {
-                                    double p0[3] = {lo[0], lo[1], lo[2]};
-                                    p0[o] += io;
-                                    double p1[3] = {p0[0], p0[1], p0[2]};
-                                    p1[q] += 1.0;
-                                    double X1[3], X0[3];
-                                    og_point(g, nr, nt, np, p1[0], p1[1], p1[2], X1);
-                                    og_point(g, nr, nt, np, p0[0], p0[1], p0[2], X0);
-                                    for (int k = 0; k < 3; ++k) t[3 * q + k] += 0.5 * (X1[k] - X0[k]);
-                                }
-                            }
-                        }
+                        og_face_chords(g, nr, nt, np, method, d, a, b, c, t);
                         double det = orc_metric_from_chords(t, Gf);
                         if (!(det > 0.0)) bad = 1;
                         for (int p = 0; p < 3; ++p)
@@ -749,4 +770,113 @@ int orc_mg_solve(og_mg* m, const double* b_in, double* x, double tol, int max_it
     free(bb);
     free(r);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Projection step around the solve: the right-hand side of eq. (PC_6),     */
+/* d/ds_j [C_ji u_i], and the velocity correction of eq. (PC_7),            */
+/* u_i <- u_i - (1/|J^-1|) d/ds_j [C_ji phi], with phi the solution of      */
+/* eq. (PC_6) (phi = h dP).  Flux form on the collocated grid: face values  */
+/* are the mean of the two cells sharing the face, as in eq. (PC_term1).    */
+/* Velocities are [3][n_r][n_theta][n_phi], Cartesian components.           */
+/* ------------------------------------------------------------------------ */
+
+/* Row d of C at the LOW d-face of cell (a,b,c) (eq. (skewness), Sec. 3.2
+ * items 4-5): C_dq = |J^-1| ds_d/dx_q, and the rows of |J^-1| J are the
+ * cyclic cross products of the chords, n_d = t_{d+1} x t_{d+2}.  Returns
+ * |J^-1| at that face (item 2).  a may be n_r, b may be n_theta (the high
+ * walls); c wraps. */
+double orc_face_crow(const og_grid* g, int nr, int nt, int np, int method, int d, int a, int b,
+                     int c, double Crow[3])
+{
+    double t[9];
+    og_face_chords(g, nr, nt, np, method, d, a, b, c, t);
+    og_cross(&t[3 * ((d + 1) % 3)], &t[3 * ((d + 2) % 3)], Crow);
+    double n0[3];
+    og_cross(&t[3], &t[6], n0);
+    return og_dot(&t[0], n0);
+}
+
+/* |J^-1| at the centre of cell (a,b,c): the mean of the determinants of its
+ * six faces (Sec. 3.2 item 3). */
+double orc_cell_jdet(const og_grid* g, int nr, int nt, int np, int method, int a, int b, int c)
+{
+    double C[3], s = 0.0;
+    s += orc_face_crow(g, nr, nt, np, method, 0, a, b, c, C);
+    s += orc_face_crow(g, nr, nt, np, method, 0, a + 1, b, c, C);
+    s += orc_face_crow(g, nr, nt, np, method, 1, a, b, c, C);
+    s += orc_face_crow(g, nr, nt, np, method, 1, a, b + 1, c, C);
+    s += orc_face_crow(g, nr, nt, np, method, 2, a, b, c, C);
+    s += orc_face_crow(g, nr, nt, np, method, 2, a, b, c + 1, C);
+    return s / 6.0;
+}
+
+/* Contravariant flux U_d = C_dq u_q through the LOW d-face of (a,b,c); u at
+ * the face is the mean of the two cells sharing it.  Zero through the r-
+ * and theta-walls (no flow through the walls). */
+static double og_uflux(const og_grid* g, og_dims n, int method, const double* u, int d, int a,
+                       int b, int c)
+{
+    if (d == 0 && (a == 0 || a == n.nr)) return 0.0;
+    if (d == 1 && (b == 0 || b == n.nt)) return 0.0;
+    const size_t N = (size_t)n.nr * n.nt * n.np;
+    double C[3];
+    orc_face_crow(g, n.nr, n.nt, n.np, method, d, a, b, c, C);
+    int lo[3] = {a, b, c};
+    lo[d] -= 1;
+    double U = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        double uf = 0.5 * (og_x(n, u + q * N, a, b, c) + og_x(n, u + q * N, lo[0], lo[1], lo[2]));
+        U += C[q] * uf;
+    }
+    return U;
+}
+
+/* Right-hand side of eq. (PC_6) at `ncell` cells (flat indices `cells`, or
+ * every cell when cells is NULL): the sum over directions of the flux
+ * through the high face minus the flux through the low face. */
+void orc_divergence(const og_grid* g, int nr, int nt, int np, int method, const double* u,
+                    long long ncell, const long long* cells, double* out)
+{
+    og_dims n = {nr, nt, np};
+#pragma omp parallel for
+    for (long long i = 0; i < ncell; ++i) {
+        long long id = cells ? cells[i] : i;
+        int c = (int)(id % np), b = (int)((id / np) % nt), a = (int)(id / ((long long)np * nt));
+        double s = 0.0;
+        s += og_uflux(g, n, method, u, 0, a + 1, b, c) - og_uflux(g, n, method, u, 0, a, b, c);
+        s += og_uflux(g, n, method, u, 1, a, b + 1, c) - og_uflux(g, n, method, u, 1, a, b, c);
+        s += og_uflux(g, n, method, u, 2, a, b, c + 1) - og_uflux(g, n, method, u, 2, a, b, c);
+        out[i] = s;
+    }
+}
+
+/* eq. (PC_7) at `ncell` cells: out[3 i + q] = u_q - (1/|J^-1|_c) sum_d
+ * [C_dq phi]_{low face}^{high face}, phi at a face the mean of the two
+ * cells, mirrored (the cell's own value) on the r- and theta-walls, where
+ * the metric C is that of the wall face. */
+void orc_correct(const og_grid* g, int nr, int nt, int np, int method, const double* phi,
+                 const double* u, long long ncell, const long long* cells, double* out)
+{
+    og_dims n = {nr, nt, np};
+    const size_t N = (size_t)nr * nt * np;
+#pragma omp parallel for
+    for (long long i = 0; i < ncell; ++i) {
+        long long id = cells ? cells[i] : i;
+        int c = (int)(id % np), b = (int)((id / np) % nt), a = (int)(id / ((long long)np * nt));
+        double grad[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < 3; ++d)
+            for (int side = 0; side < 2; ++side) { /* 0: low face, 1: high face */
+                int f[3] = {a, b, c};
+                f[d] += side;
+                int o[3] = {a, b, c}; /* the other cell sharing the face */
+                o[d] += side ? 1 : -1;
+                double C[3];
+                orc_face_crow(g, nr, nt, np, method, d, f[0], f[1], f[2], C);
+                double pf = 0.5 * (og_x(n, phi, a, b, c) + og_x(n, phi, o[0], o[1], o[2]));
+                for (int q = 0; q < 3; ++q) grad[q] += (side ? 1.0 : -1.0) * C[q] * pf;
+            }
+        double J = orc_cell_jdet(g, nr, nt, np, method, a, b, c);
+        for (int q = 0; q < 3; ++q) out[3 * i + q] = u[q * N + id] - grad[q] / J;
+    }
 }
