@@ -155,6 +155,35 @@ const char* cps_last_error(void);
 cps_status cps_levels(const cps_handle* h, int32_t* n_levels, int32_t* dims_out,
                       int32_t* ncolours, int32_t* phi_invariant);
 
+/* ---- Projection step around the solve (finest grid) --------------------
+ * The pressure-correction section: the solve of eq. (PC_6) is one step of
+ * the projection that makes the intermediate velocity u*** divergence
+ * free.  Discretised in flux form on the collocated grid like eq.
+ * (PC_term1): a face value is the mean of the two cells sharing the face,
+ * C_ji = |J^-1| ds_j/dx_i (eq. (skewness)) is evaluated at the faces from the
+ * same chords of the map as the face metrics (Sec. 3.2 items 4-5), and
+ * |J^-1| of a cell is the mean of its six face determinants (item 3).
+ * No flow crosses the r- and theta-walls; phi is mirrored there.
+ * Velocities: device FP64 [3][n_r][n_theta][n_phi], Cartesian components
+ * with the polar axis along x1, natural order; scalar fields: device FP64
+ * [n_r][n_theta][n_phi].  The face tables are built on the first call
+ * (device memory owned by the handle: 12 words per (r, theta) position for
+ * maps symmetric about the polar axis, 12 per cell otherwise) and rebuilt
+ * after the metrics change.  Errors: CPS_E_INVALID for NULL arguments and
+ * for a scalar field that overlaps u. */
+
+/* rhs = d/ds_j [C_ji u_i], the right-hand side of eq. (PC_6); its sum over
+ * the cells is zero to rounding (the fluxes telescope). */
+cps_status cps_divergence(cps_handle* h, const double* u, double* rhs);
+/* eq. (PC_7): u_i <- u_i - (1/|J^-1|) d/ds_j [C_ji phi] in place, with phi
+ * the solution of eq. (PC_6) (phi = h dP). */
+cps_status cps_correct(cps_handle* h, const double* phi, double* u);
+/* One projection step: rhs = cps_divergence(u), cps_solve(rhs -> phi, tol),
+ * then cps_correct(phi, u) -- u is corrected in place only when the solve
+ * converged (the solve's status is returned; phi holds its last iterate).
+ * Uses a handle-owned right-hand-side buffer (allocated on first call). */
+cps_status cps_project(cps_handle* h, double* u, double* phi, double tol, cps_info* info);
+
 /* ---- Kernel-level entry points (FP64 hierarchy of the handle) ----------
  * For parity tests of each step against an independent implementation.
  * level l indexes the hierarchy (0 = finest); all arrays are device FP64
@@ -273,7 +302,9 @@ enum {
     CPS_KERNEL_PROLONG = 4,  /* trilinear correction from level 1 */
     CPS_KERNEL_VCYCLE = 5,   /* one preconditioning V-cycle, all levels (the span
                                 from its first to its last launch) */
-    CPS_KERNEL_CLASSES = 6
+    CPS_KERNEL_DIVERGENCE = 6, /* the projection step's right-hand side */
+    CPS_KERNEL_CORRECT = 7,    /* the projection step's velocity correction */
+    CPS_KERNEL_CLASSES = 8
 };
 /* enable != 0 starts recording (and clears earlier records). */
 cps_status cps_profile_enable(cps_handle* h, int32_t enable);

@@ -120,7 +120,10 @@ def lib():
         L.cps_profile_enable.argtypes = [P, I]
         L.cps_profile_read.argtypes = [P, I, P, P]
         L.cps_debug_copy.argtypes = [P, P, ctypes.c_int64, P]
-        for f in ("cps_profile_enable", "cps_profile_read", "cps_debug_copy",
+        L.cps_divergence.argtypes = [P, P, P]
+        L.cps_correct.argtypes = [P, P, P]
+        L.cps_project.argtypes = [P, P, P, D, P]
+        for f in ("cps_divergence", "cps_correct", "cps_project", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
                   "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
                   "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
                   "cps_debug_coarse_solve", "cps_debug_vcycle", "cps_debug_plane_sweep"):
@@ -173,6 +176,32 @@ def cps_solve(h, rhs, p, tol: float):
     _expect(rhs, n, "rhs"); _expect(p, n, "p")
     info = cps_info()
     st = lib().cps_solve(h, _ptr(rhs), _ptr(p), tol, ctypes.byref(info))
+    if st not in (CPS_OK, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED):
+        _check(st)
+    return st, info
+
+
+def cps_divergence(h, u, rhs):
+    """rhs = d/ds_j [C_ji u_i] (u: 3 x cells, rhs: cells; device FP64)."""
+    _, n = _dims(h, 0)
+    _expect(u, 3 * n, "u"); _expect(rhs, n, "rhs")
+    _check(lib().cps_divergence(h, _ptr(u), _ptr(rhs)))
+
+
+def cps_correct(h, phi, u):
+    """u_i -= (1/|J^-1|) d/ds_j [C_ji phi] in place."""
+    _, n = _dims(h, 0)
+    _expect(phi, n, "phi"); _expect(u, 3 * n, "u")
+    _check(lib().cps_correct(h, _ptr(phi), _ptr(u)))
+
+
+def cps_project(h, u, phi, tol: float):
+    """Divergence, solve, correction; returns (status, cps_info) like
+    cps_solve (u is corrected only when the solve converged)."""
+    _, n = _dims(h, 0)
+    _expect(u, 3 * n, "u"); _expect(phi, n, "phi")
+    info = cps_info()
+    st = lib().cps_project(h, _ptr(u), _ptr(phi), tol, ctypes.byref(info))
     if st not in (CPS_OK, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED):
         _check(st)
     return st, info
@@ -267,7 +296,8 @@ def cps_debug_vcycle(h, b, x):
     _check(lib().cps_debug_vcycle(h, _ptr(b), _ptr(x)))
 
 
-KERNEL_GS, KERNEL_RESIDUAL, KERNEL_APPLY, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE = range(6)
+KERNEL_GS, KERNEL_RESIDUAL, KERNEL_APPLY, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_VCYCLE, \
+    KERNEL_DIVERGENCE, KERNEL_CORRECT = range(8)
 
 
 def cps_profile_enable(h, enable: bool):
@@ -321,6 +351,28 @@ class Solver:
         p = out if out is not None else torch.empty_like(rhs)
         st, info = cps_solve(self.h, rhs, p, tol)
         return Result(p, st, info.iterations, info.rel_residual, info.rhs_mean_removed,
+                      info.seconds)
+
+    def divergence(self, u, out=None):
+        """Right-hand side of eq. (PC_6) for the velocity u (3 x cells)."""
+        import torch
+        rhs = out if out is not None else torch.empty(u.numel() // 3, dtype=u.dtype,
+                                                      device=u.device)
+        cps_divergence(self.h, u, rhs)
+        return rhs
+
+    def correct(self, phi, u):
+        """eq. (PC_7) in place on u."""
+        cps_correct(self.h, phi, u)
+        return u
+
+    def project(self, u, tol: float = 1e-10, phi=None) -> Result:
+        """One projection step on u in place; Result.p is phi."""
+        import torch
+        phi = phi if phi is not None else torch.empty(u.numel() // 3, dtype=u.dtype,
+                                                      device=u.device)
+        st, info = cps_project(self.h, u, phi, tol)
+        return Result(phi, st, info.iterations, info.rel_residual, info.rhs_mean_removed,
                       info.seconds)
 
     def close(self):

@@ -10,6 +10,7 @@
 #include "cps.h"
 #include "kernels.hpp"
 #include "plane.hpp"
+#include "project.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -179,6 +180,10 @@ struct cps_handle {
     // plane smoother scratch: the spectra of one parity
     Buf<double> ps64;
     Buf<float> ps32;
+    // projection step (finest grid, built on first use): C rows and
+    // determinants of the faces, cell |J^-1|, the divergence right-hand side
+    Buf<double> pC, pJf, pJc, prhs;
+    bool cm_valid = false;
     // captured outer-iteration bodies (G_* keys), replayed by run_body
     hipGraphExec_t gexec[4] = {};
     // optional HIP-event timing of the finest-level kernels, per class
@@ -839,6 +844,7 @@ int compute_operator(cps_handle* h)
         used.release(); piv.release(); bad.release();
     }
     if (h->lv[0].pv64.p || h->lv[0].pv32.p) plane_factors(h); // new metrics of a set-up hierarchy
+    h->cm_valid = false; // the projection step's face tables follow the map
     return mode;
 }
 
@@ -979,6 +985,7 @@ void destroy(cps_handle* h)
     h->x0.release(); h->b0.release(); h->r.release(); h->z.release(); h->pd.release(); h->q.release();
     h->r0.release(); h->v.release(); h->s.release(); h->t.release(); h->ph.release();
     h->sh.release();
+    h->pC.release(); h->pJf.release(); h->pJc.release(); h->prhs.release();
     for (hipGraphExec_t& g : h->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (h->hsc) (void)hipHostFree(h->hsc);
@@ -1243,6 +1250,85 @@ void need_level(const cps_handle* h, int l, bool fine)
 // C ABI
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// projection step (eq. (PC_6) right-hand side, eq. (PC_7))
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Face tables of the finest grid for the projection step, on first use and
+// after every recomputation of the metrics.
+int csym(const cps_handle* h)
+{
+    if (!h->axi) return kPerCell;
+    return h->grid.map == CPS_MAP_IDENTITY ? kInvariant : kRotational;
+}
+
+void ensure_cmetrics(cps_handle* h)
+{
+    if (h->cm_valid) return;
+    const LevelMem& m = h->lv[0];
+    const int nc = csym(h) == kPerCell ? m.np : 1;
+    const long long F = (long long)(m.nr + 1) * (m.nt + 1) * nc;
+    const long long nj = (long long)m.nr * m.nt * nc;
+    if (h->pC.n != (size_t)(9 * F)) h->pC.alloc(9 * F);
+    if (h->pJf.n != (size_t)(3 * F)) h->pJf.alloc(3 * F);
+    if (h->pJc.n != (size_t)nj) h->pJc.alloc(nj);
+    const cps_grid& g = h->grid;
+    MapParams mp{g.map, g.r_inner, g.r_outer, g.theta0, g.theta1, g.radial_stretch, g.flattening,
+                 g.skew};
+    k_crows<<<nblk(F), kBlock, 0, h->stream>>>(mp, m.nr, m.nt, m.np, nc, h->met.method, h->pC.p,
+                                               h->pJf.p);
+    LAUNCH_CHECK();
+    k_cell_jdet<<<nblk(nj), kBlock, 0, h->stream>>>(m.nr, m.nt, nc, h->pJf.p, h->pJc.p);
+    LAUNCH_CHECK();
+    h->cm_valid = true;
+}
+
+CRows crows(const cps_handle* h)
+{
+    const LevelMem& m = h->lv[0];
+    const int nc = csym(h) == kPerCell ? m.np : 1;
+    return CRows{h->pC.p, (long long)(m.nr + 1) * (m.nt + 1) * nc, m.nt + 1, nc};
+}
+
+// launch f.template operator()<SYM>() for the handle's symmetry
+template <typename F>
+void with_csym(const cps_handle* h, F&& f)
+{
+    switch (csym(h)) {
+    case kPerCell: f(std::integral_constant<int, kPerCell>{}); break;
+    case kInvariant: f(std::integral_constant<int, kInvariant>{}); break;
+    default: f(std::integral_constant<int, kRotational>{}); break;
+    }
+}
+
+void divergence(cps_handle* h, const double* u, double* rhs)
+{
+    ensure_cmetrics(h);
+    const LevelMem& m = h->lv[0];
+    ProfScope ps(h, CPS_KERNEL_DIVERGENCE, 0);
+    with_csym(h, [&](auto S) {
+        k_divergence<decltype(S)::value><<<nblk(m.n), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np,
+                                                                              crows(h), u, rhs);
+    });
+    LAUNCH_CHECK();
+}
+
+void correct(cps_handle* h, const double* phi, double* u)
+{
+    ensure_cmetrics(h);
+    const LevelMem& m = h->lv[0];
+    ProfScope ps(h, CPS_KERNEL_CORRECT, 0);
+    with_csym(h, [&](auto S) {
+        k_correct<decltype(S)::value><<<nblk(m.n), kBlock, 0, h->stream>>>(
+            m.nr, m.nt, m.np, crows(h), h->pJc.p, phi, u);
+    });
+    LAUNCH_CHECK();
+}
+
+} // namespace
+
 extern "C" {
 
 void cps_grid_default(cps_grid* g)
@@ -1461,6 +1547,42 @@ cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_m
         if (launches) *launches = (int64_t)(u / 2);
         h->ev_used[kernel_class] = 0;
     });
+}
+
+cps_status cps_divergence(cps_handle* h, const double* u, double* rhs)
+{
+    return guarded([&] {
+        if (!h || !u || !rhs) fail(CPS_E_INVALID, "NULL argument");
+        const long long n = h->lv[0].n;
+        if (rhs + n > u && rhs < u + 3 * n) fail(CPS_E_INVALID, "rhs and u must not overlap");
+        divergence(h, u, rhs);
+    });
+}
+
+cps_status cps_correct(cps_handle* h, const double* phi, double* u)
+{
+    return guarded([&] {
+        if (!h || !phi || !u) fail(CPS_E_INVALID, "NULL argument");
+        const long long n = h->lv[0].n;
+        if (phi + n > u && phi < u + 3 * n) fail(CPS_E_INVALID, "phi and u must not overlap");
+        correct(h, phi, u);
+    });
+}
+
+cps_status cps_project(cps_handle* h, double* u, double* phi, double tol, cps_info* info)
+{
+    cps_status st = CPS_OK;
+    cps_status g = guarded([&] {
+        if (!h || !u || !phi) fail(CPS_E_INVALID, "NULL argument");
+        if (!(tol > 0)) fail(CPS_E_INVALID, "tol must be positive");
+        const long long n = h->lv[0].n;
+        if (phi + n > u && phi < u + 3 * n) fail(CPS_E_INVALID, "phi and u must not overlap");
+        if (h->prhs.n != (size_t)h->lv[0].n) h->prhs.alloc(h->lv[0].n);
+        divergence(h, u, h->prhs.p);
+        st = solve(h, h->prhs.p, phi, tol, info);
+        if (st == CPS_OK) correct(h, phi, u);
+    });
+    return g != CPS_OK ? g : st;
 }
 
 cps_status cps_debug_copy(const double* src, double* dst, int64_t n, void* stream)

@@ -2152,11 +2152,67 @@ __device__ inline void map_point(const MapParams& m, double sr, double st, doubl
     X[2] = r * sth * sph;
 }
 
+// Chords t[q] = dX/ds_q across the LOW d-face of cell (a, b, c) of a level
+// with dims (nr, nt, np).  method 0: chords of the map across the face
+// centre; method 1: the paper's vertex averages (the normal derivative is
+// the mean over the face's four vertices of the difference across vertex
+// planes, weight 1/8; each tangential derivative the mean of the face's two
+// edges along it).  The face may lie on a wall, the high walls included.
+__device__ inline void face_chords(const MapParams& m, int nr, int nt, int np, int method, int d,
+                                   int a, int b, int c, double t[3][3])
+{
+    auto P = [&](double ia, double ib, double ic, double X[3]) {
+        map_point(m, ia / nr, ib / nt, ic / np, X);
+    };
+    const double lo[3] = {(double)a, (double)b, (double)c};
+    if (method == 0) {
+        double f[3] = {a + 0.5, b + 0.5, c + 0.5};
+        f[d] -= 0.5;
+        for (int q = 0; q < 3; ++q) {
+            double p1[3] = {f[0], f[1], f[2]}, p0[3] = {f[0], f[1], f[2]};
+            p1[q] += 0.5;
+            p0[q] -= 0.5;
+            double X1[3], X0[3];
+            P(p1[0], p1[1], p1[2], X1);
+            P(p0[0], p0[1], p0[2], X0);
+            for (int k = 0; k < 3; ++k) t[q][k] = X1[k] - X0[k];
+        }
+        return;
+    }
+    const int u = (d + 1) % 3, v = (d + 2) % 3;
+    for (int k = 0; k < 3; ++k) t[d][k] = t[u][k] = t[v][k] = 0.0;
+    for (int iu = 0; iu < 2; ++iu)
+        for (int iv = 0; iv < 2; ++iv) {
+            double p1[3] = {lo[0], lo[1], lo[2]};
+            p1[u] += iu;
+            p1[v] += iv;
+            double p0[3] = {p1[0], p1[1], p1[2]};
+            p1[d] += 1.0;
+            p0[d] -= 1.0;
+            double X1[3], X0[3];
+            P(p1[0], p1[1], p1[2], X1);
+            P(p0[0], p0[1], p0[2], X0);
+            for (int k = 0; k < 3; ++k) t[d][k] += 0.125 * (X1[k] - X0[k]);
+        }
+    for (int s = 0; s < 2; ++s) {
+        const int q = s == 0 ? u : v, o = s == 0 ? v : u;
+        for (int io = 0; io < 2; ++io) {
+            double p0[3] = {lo[0], lo[1], lo[2]};
+            p0[o] += io;
+            double p1[3] = {p0[0], p0[1], p0[2]};
+            p1[q] += 1.0;
+            double X1[3], X0[3];
+            P(p1[0], p1[1], p1[2], X1);
+            P(p0[0], p0[1], p0[2], X0);
+            for (int k = 0; k < 3; ++k) t[q][k] += 0.5 * (X1[k] - X0[k]);
+        }
+    }
+}
+
 // Face metrics of one level.  One thread per (a, b, c) (c = 0 only when the
-// metrics are phi-invariant), three faces each.  method 0: chords of the map
-// across the face centre; method 1: the paper's vertex averages.  flags[blk]
-// gets bit 0 for a face with det <= 0, bit 1 for a non-zero r-theta cross
-// metric, bit 2 for a non-zero cross metric involving phi.
+// metrics are phi-invariant), three faces each, chords by face_chords.
+// flags[blk] gets bit 0 for a face with det <= 0, bit 1 for a non-zero
+// r-theta cross metric, bit 2 for a non-zero cross metric involving phi.
 __global__ void __launch_bounds__(kBlock) k_metrics(MapParams m, int nr, int nt, int np, int nc,
                                                     int method, double* __restrict__ G,
                                                     int* __restrict__ flags)
@@ -2171,57 +2227,12 @@ __global__ void __launch_bounds__(kBlock) k_metrics(MapParams m, int nr, int nt,
         const int c = (int)(i % nc);
         const long long row = i / nc;
         const int b = (int)(row % nt), a = (int)(row / nt);
-        auto P = [&](double ia, double ib, double ic, double X[3]) {
-            map_point(m, ia / nr, ib / nt, ic / np, X);
-        };
         for (int d = 0; d < 3; ++d) {
             double Gd[3] = {0.0, 0.0, 0.0};
             const bool wall = (d == 0 && a == 0) || (d == 1 && b == 0);
             if (!wall) {
                 double t[3][3];
-                const double lo[3] = {(double)a, (double)b, (double)c};
-                if (method == 0) {
-                    double f[3] = {a + 0.5, b + 0.5, c + 0.5};
-                    f[d] -= 0.5;
-                    for (int q = 0; q < 3; ++q) {
-                        double p1[3] = {f[0], f[1], f[2]}, p0[3] = {f[0], f[1], f[2]};
-                        p1[q] += 0.5;
-                        p0[q] -= 0.5;
-                        double X1[3], X0[3];
-                        P(p1[0], p1[1], p1[2], X1);
-                        P(p0[0], p0[1], p0[2], X0);
-                        for (int k = 0; k < 3; ++k) t[q][k] = X1[k] - X0[k];
-                    }
-                } else {
-                    const int u = (d + 1) % 3, v = (d + 2) % 3;
-                    for (int k = 0; k < 3; ++k) t[d][k] = t[u][k] = t[v][k] = 0.0;
-                    for (int iu = 0; iu < 2; ++iu)
-                        for (int iv = 0; iv < 2; ++iv) {
-                            double p1[3] = {lo[0], lo[1], lo[2]};
-                            p1[u] += iu;
-                            p1[v] += iv;
-                            double p0[3] = {p1[0], p1[1], p1[2]};
-                            p1[d] += 1.0;
-                            p0[d] -= 1.0;
-                            double X1[3], X0[3];
-                            P(p1[0], p1[1], p1[2], X1);
-                            P(p0[0], p0[1], p0[2], X0);
-                            for (int k = 0; k < 3; ++k) t[d][k] += 0.125 * (X1[k] - X0[k]);
-                        }
-                    for (int s = 0; s < 2; ++s) {
-                        const int q = s == 0 ? u : v, o = s == 0 ? v : u;
-                        for (int io = 0; io < 2; ++io) {
-                            double p0[3] = {lo[0], lo[1], lo[2]};
-                            p0[o] += io;
-                            double p1[3] = {p0[0], p0[1], p0[2]};
-                            p1[q] += 1.0;
-                            double X1[3], X0[3];
-                            P(p1[0], p1[1], p1[2], X1);
-                            P(p0[0], p0[1], p0[2], X0);
-                            for (int k = 0; k < 3; ++k) t[q][k] += 0.5 * (X1[k] - X0[k]);
-                        }
-                    }
-                }
+                face_chords(m, nr, nt, np, method, d, a, b, c, t);
                 // rows of the Jacobian: cyclic cross products over det
                 double nv[3][3];
                 for (int e = 0; e < 3; ++e) {
@@ -2257,7 +2268,6 @@ __global__ void __launch_bounds__(kBlock) k_metrics(MapParams m, int nr, int nt,
     if (threadIdx.x == 0) flags[blockIdx.x] = sflag;
 }
 
-// Float copy of an FP64 array.
 // Float copy of an FP64 array.
 __global__ void __launch_bounds__(kBlock) k_to_f32(long long n, const double* __restrict__ a,
                                                    float* __restrict__ b)

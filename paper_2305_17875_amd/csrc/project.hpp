@@ -1,0 +1,190 @@
+// project.hpp -- the two steps either side of the pressure-correction solve,
+// on the finest grid of a handle.  Included by cps.hip after kernels.hpp.
+//
+// Right-hand side of eq. (PC_6): the divergence d/ds_j [C_ji u_i] of the
+// contravariant flux, with C_ji = |J^-1| ds_j/dx_i (eq. (skewness)) at the
+// cell faces (Sec. 3.2 items 4-5).  Velocity correction of eq. (PC_7):
+// u_i <- u_i - (1/|J^-1|) d/ds_j [C_ji phi], phi = h dP the solution of
+// eq. (PC_6), |J^-1| at a cell the mean of its six face determinants
+// (item 3).  Both in flux form on the collocated grid, like the terms of
+// eq. (PC_term1): a face value is the mean of the two cells sharing the
+// face; no flow through the r- and theta-walls; phi is mirrored there (the
+// wall face takes the cell's own value), with the wall face's C.
+//
+// Velocities are [3][n_r][n_theta][n_phi] (Cartesian components, polar axis
+// x1), phi and the right-hand side [n_r][n_theta][n_phi], natural order, one
+// thread per cell, phi fastest across a wavefront.
+//
+// C rows of the LOW d-face of every position (a, b, c), a <= n_r, b <=
+// n_theta (the high walls included): Cf[(3d + q) F + (a (n_theta + 1) + b)
+// nc + c], F = (n_r + 1)(n_theta + 1) nc, in one of three forms (CSym):
+//  - kRotational (sphere, oblate shell: symmetric under rotation about the
+//    polar axis): the faces of cell c are those of cell 0 turned by
+//    2 pi c / n_phi about x1, so nc = 1 and the kernels rotate the (x2, x3)
+//    components;
+//  - kInvariant (identity box: phi is a translation): nc = 1, no rotation;
+//  - kPerCell (triaxial): nc = n_phi.
+
+namespace cps {
+
+// chord rows of every face position: C row d and |J^-1| of the LOW d-face
+// (C_d = t_{d+1} x t_{d+2}, |J^-1| = t_0 . (t_1 x t_2))
+__global__ void __launch_bounds__(kBlock) k_crows(MapParams m, int nr, int nt, int np, int nc,
+                                                  int method, double* __restrict__ Cf,
+                                                  double* __restrict__ Jf)
+{
+    const long long F = (long long)(nr + 1) * (nt + 1) * nc;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F) return;
+    const int c = (int)(i % nc);
+    const long long row = i / nc;
+    const int b = (int)(row % (nt + 1)), a = (int)(row / (nt + 1));
+    auto cross = [](const double* u, const double* v, double* w) {
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    for (int d = 0; d < 3; ++d) {
+        double t[3][3], C[3], n0[3];
+        face_chords(m, nr, nt, np, method, d, a, b, c, t);
+        cross(t[(d + 1) % 3], t[(d + 2) % 3], C);
+        cross(t[1], t[2], n0);
+        for (int q = 0; q < 3; ++q) Cf[(3 * d + q) * F + i] = C[q];
+        Jf[d * F + i] = t[0][0] * n0[0] + t[0][1] * n0[1] + t[0][2] * n0[2];
+    }
+}
+
+// |J^-1| of every cell (c < nc): the mean of its six face determinants
+__global__ void __launch_bounds__(kBlock) k_cell_jdet(int nr, int nt, int nc,
+                                                      const double* __restrict__ Jf,
+                                                      double* __restrict__ Jc)
+{
+    const long long n = (long long)nr * nt * nc, F = (long long)(nr + 1) * (nt + 1) * nc;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % nc);
+    const long long row = i / nc;
+    const int b = (int)(row % nt), a = (int)(row / nt);
+    auto fi = [&](int fa, int fb, int fc) { return ((long long)fa * (nt + 1) + fb) * nc + fc; };
+    double s = 0.0;
+    s += Jf[fi(a, b, c)];
+    s += Jf[fi(a + 1, b, c)];
+    s += Jf[F + fi(a, b, c)];
+    s += Jf[F + fi(a, b + 1, c)];
+    s += Jf[2 * F + fi(a, b, c)];
+    s += Jf[2 * F + fi(a, b, (c + 1) % nc)];
+    Jc[i] = s / 6.0;
+}
+
+enum CSym { kPerCell = 0, kInvariant = 1, kRotational = 2 };
+
+struct CRows {
+    const double* C;
+    long long F;
+    int nt1, nc;
+};
+
+// C row d of the LOW d-face of position (a, b, c); kRotational: the entry
+// of (a, b, 0) turned about x1 by the angle with cosine cs and sine sn
+template <int SYM>
+__device__ __forceinline__ void crow(const CRows& R, int d, int a, int b, int c, double cs,
+                                     double sn, double out[3])
+{
+    const long long fi = ((long long)a * R.nt1 + b) * R.nc + (SYM == kPerCell ? c : 0);
+    const double c0 = R.C[(3 * d) * R.F + fi], c1 = R.C[(3 * d + 1) * R.F + fi],
+                 c2 = R.C[(3 * d + 2) * R.F + fi];
+    out[0] = c0;
+    if (SYM == kRotational) {
+        out[1] = c1 * cs - c2 * sn;
+        out[2] = c1 * sn + c2 * cs;
+    } else {
+        out[1] = c1;
+        out[2] = c2;
+    }
+}
+
+// rhs = d/ds_j [C_ji u_i]: per direction, flux through the high face minus
+// flux through the low face; a flux is C_d . (mean of the two cells' u)
+template <int SYM>
+__global__ void __launch_bounds__(kBlock) k_divergence(int nr, int nt, int np, CRows R,
+                                                       const double* __restrict__ u,
+                                                       double* __restrict__ rhs)
+{
+    const long long N = (long long)nr * nt * np, plane = (long long)nt * np;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int c = (int)(i % np);
+    const long long row = i / np;
+    const int b = (int)(row % nt), a = (int)(row / nt);
+    const int cm = c == 0 ? np - 1 : c - 1, cp = c == np - 1 ? 0 : c + 1;
+    double s0 = 0.0, c0 = 1.0, s1 = 0.0, c1 = 1.0;
+    if (SYM == kRotational) {
+        sincospi(2.0 * c / np, &s0, &c0);
+        sincospi(2.0 * (c + 1) / np, &s1, &c1);
+    }
+    const double* u0 = u;
+    const double* u1 = u + N;
+    const double* u2 = u + 2 * N;
+    auto flux = [&](int d, int fa, int fb, int fc, long long ihi, long long ilo, double cs,
+                    double sn) {
+        double C[3];
+        crow<SYM>(R, d, fa, fb, fc, cs, sn, C);
+        double U = 0.0;
+        U += C[0] * (0.5 * (u0[ihi] + u0[ilo]));
+        U += C[1] * (0.5 * (u1[ihi] + u1[ilo]));
+        U += C[2] * (0.5 * (u2[ihi] + u2[ilo]));
+        return U;
+    };
+    const double r_lo = a > 0 ? flux(0, a, b, c, i, i - plane, c0, s0) : 0.0;
+    const double r_hi = a < nr - 1 ? flux(0, a + 1, b, c, i + plane, i, c0, s0) : 0.0;
+    const double t_lo = b > 0 ? flux(1, a, b, c, i, i - np, c0, s0) : 0.0;
+    const double t_hi = b < nt - 1 ? flux(1, a, b + 1, c, i + np, i, c0, s0) : 0.0;
+    const double p_lo = flux(2, a, b, c, i, i - c + cm, c0, s0);
+    const double p_hi = flux(2, a, b, cp, i - c + cp, i, c1, s1);
+    double s = 0.0;
+    s += r_hi - r_lo;
+    s += t_hi - t_lo;
+    s += p_hi - p_lo;
+    rhs[i] = s;
+}
+
+// u_q <- u_q - (1/|J^-1|) sum over the six faces of +-C_dq (face mean of
+// phi); phi is mirrored on the r- and theta-walls
+template <int SYM>
+__global__ void __launch_bounds__(kBlock) k_correct(int nr, int nt, int np, CRows R,
+                                                    const double* __restrict__ Jc,
+                                                    const double* __restrict__ phi,
+                                                    double* __restrict__ u)
+{
+    const long long N = (long long)nr * nt * np, plane = (long long)nt * np;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int c = (int)(i % np);
+    const long long row = i / np;
+    const int b = (int)(row % nt), a = (int)(row / nt);
+    const int cm = c == 0 ? np - 1 : c - 1, cp = c == np - 1 ? 0 : c + 1;
+    double s0 = 0.0, c0 = 1.0, s1 = 0.0, c1 = 1.0;
+    if (SYM == kRotational) {
+        sincospi(2.0 * c / np, &s0, &c0);
+        sincospi(2.0 * (c + 1) / np, &s1, &c1);
+    }
+    const double pc = phi[i];
+    double g[3] = {0.0, 0.0, 0.0};
+    auto face = [&](int d, int fa, int fb, int fc, long long io, double sign, double cs,
+                    double sn) {
+        double C[3];
+        crow<SYM>(R, d, fa, fb, fc, cs, sn, C);
+        const double pf = 0.5 * (pc + phi[io]);
+        for (int q = 0; q < 3; ++q) g[q] += sign * C[q] * pf;
+    };
+    face(0, a, b, c, a > 0 ? i - plane : i, -1.0, c0, s0);
+    face(0, a + 1, b, c, a < nr - 1 ? i + plane : i, 1.0, c0, s0);
+    face(1, a, b, c, b > 0 ? i - np : i, -1.0, c0, s0);
+    face(1, a, b + 1, c, b < nt - 1 ? i + np : i, 1.0, c0, s0);
+    face(2, a, b, c, i - c + cm, -1.0, c0, s0);
+    face(2, a, b, cp, i - c + cp, 1.0, c1, s1);
+    const double J = Jc[SYM == kPerCell ? i : row];
+    for (int q = 0; q < 3; ++q) u[q * N + i] = u[q * N + i] - g[q] / J;
+}
+
+} // namespace cps

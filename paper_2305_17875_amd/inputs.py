@@ -83,6 +83,13 @@ def config1() -> Shell:
     return Shell(32, 32, 32)
 
 
+def velocity_field(shape, seed: int = 0) -> np.ndarray:
+    """Synthetic intermediate velocity u*** for the projection step:
+    [3][n_r][n_theta][n_phi] Cartesian components, each a smoothed N(0,1)
+    field (seeds seed, seed + 1, seed + 2)."""
+    return np.stack([smoothed_noise(shape, seed + q) for q in range(3)])
+
+
 def config2() -> Shell:
     """Paper-scale shell 192(r) x 256(theta) x 512(phi), tanh clustering
     with stretching factor 2.0."""

@@ -23,7 +23,8 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for want in ("cps_setup", "cps_solve", "cps_destroy", "cps_last_error", "cps_levels",
-                 "cps_debug_residual", "cps_debug_gs_pass", "cps_debug_vcycle"):
+                 "cps_debug_residual", "cps_debug_gs_pass", "cps_debug_vcycle",
+                 "cps_divergence", "cps_correct", "cps_project"):
         assert want in names
 
 
