@@ -8,7 +8,8 @@ A step is one complete cps_solve (FP64 hierarchy, conjugate gradients
 preconditioned by one V(2,2) cycle) from the right-hand side resident in HBM
 to relative residual 1e-10.  The FP32-multigrid + FP64-refinement form is
 timed on the same input and reported beside it, and so is the same solve
-with the zebra (r, phi)-plane smoother (`plane`).  Prints one JSON line.
+with the zebra (r, phi)-plane smoother (`plane`); the whole projection step
+around the solve is timed under `project`.  Prints one JSON line.
 
 Roofline: the dominant kernel is the finest-level Gauss-Seidel colour pass.
 Its duration is measured live with HIP events recorded on the solve stream
@@ -36,7 +37,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_pass_config2_traffic.json")
 PLANE_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "plane.hpp")
 PLANE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plane_half_sweep_config2_traffic.json")
-KNAMES = ["gs_pass", "residual", "apply", "restrict", "prolong", "vcycle"]
+KNAMES = ["gs_pass", "residual", "apply", "restrict", "prolong", "vcycle", "divergence",
+          "correct"]
 GS_KERNEL = "k_gs_march2<double, 0, 0>"
 
 
@@ -191,6 +193,58 @@ def plane_form(cps, torch, g, rhs, x64, steps, warmup):
         f["solver"].close()
         del f
         torch.cuda.empty_cache()
+    return out
+
+
+def project_form(cps, torch, inputs, g, steps, warmup):
+    """One projection step (cps_project: divergence right-hand side of eq.
+    (PC_6), the solve, the correction of eq. (PC_7)) on a synthetic
+    intermediate velocity, with the FP64 point-smoother solve of the headline
+    and with the plane smoother.  The velocity is restored before each step
+    outside the timed region.  Kernel rates against per-cell byte models:
+    divergence reads 3 velocity words and writes 1; the correction reads phi
+    and 3 velocity words and writes 3 (the face tables of a map symmetric
+    about the polar axis are one row per (r, theta))."""
+    u0 = torch.from_numpy(inputs.velocity_field(g.shape, 40)).cuda().flatten()
+    n = g.cells
+    out = {"workload": "u*** = three smoothed N(0,1) fields (seeds 40-42) as Cartesian "
+                       "components on the paper-scale shell; tol 1e-10"}
+    for key, smoother in (("fp64_point", 0), ("fp64_plane", 1)):
+        s = cps.Solver(g, precision=0, accel=1, max_iters=400, smoother=smoother)
+        u = torch.empty_like(u0)
+        phi = torch.empty(n, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            u.copy_(u0)
+            s.project(u, TOL, phi=phi)
+        torch.cuda.synchronize()
+        cps.cps_profile_enable(s.h, True)
+        total, its = 0.0, []
+        for _ in range(steps):
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = s.project(u, TOL, phi=phi)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+            its.append(r.iterations)
+        prof = {k: cps.cps_profile_read(s.h, k) for k in range(len(KNAMES))}
+        cps.cps_profile_enable(s.h, False)
+        dt = total / steps
+        rates = {}
+        for name, cls, words in (("divergence", cps.KERNEL_DIVERGENCE, 4),
+                                 ("correct", cps.KERNEL_CORRECT, 7)):
+            ms, cnt = prof[cls]
+            t = ms / max(cnt, 1) * 1e-3
+            b = words * 8 * n
+            rates[name] = {"avg_us": t * 1e6, "algorithmic_bytes": b,
+                           "achieved_GBs": b / t / 1e9, "frac_of_peak": b / t / 1e9 / HBM_PEAK_GBS}
+        out[key] = {"value": n / dt, "unit": "unknowns/s", "ms_per_step": dt * 1e3,
+                    "iterations": its[-1], "status": r.status, "kernels": rates}
+        log(f"project {key}: {dt * 1e3:.1f} ms/step, iterations {its}")
+        s.close()
+        del u, phi
+    del u0
+    torch.cuda.empty_cache()
     return out
 
 
@@ -432,6 +486,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-plane", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-project", action="store_true")
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
@@ -510,6 +565,8 @@ def main():
     gpu_iters = f64["iters"][-1]
     del x64, f64, rhs
     torch.cuda.empty_cache()
+    if not a.no_project:
+        line["project"] = project_form(cps, torch, inputs, g, a.steps, a.warmup)
     if not a.no_batch:
         line["batch"] = batch_form(cps, torch, inputs, a.batch_problems, a.steps, a.warmup)
         torch.cuda.empty_cache()

@@ -182,7 +182,7 @@ struct cps_handle {
     Buf<float> ps32;
     // projection step (finest grid, built on first use): C rows and
     // determinants of the faces, cell |J^-1|, the divergence right-hand side
-    Buf<double> pC, pJf, pJc, prhs;
+    Buf<double> pC, pJf, pJc, prhs, prot;
     bool cm_valid = false;
     // captured outer-iteration bodies (G_* keys), replayed by run_body
     hipGraphExec_t gexec[4] = {};
@@ -985,7 +985,7 @@ void destroy(cps_handle* h)
     h->x0.release(); h->b0.release(); h->r.release(); h->z.release(); h->pd.release(); h->q.release();
     h->r0.release(); h->v.release(); h->s.release(); h->t.release(); h->ph.release();
     h->sh.release();
-    h->pC.release(); h->pJf.release(); h->pJc.release(); h->prhs.release();
+    h->pC.release(); h->pJf.release(); h->pJc.release(); h->prhs.release(); h->prot.release();
     for (hipGraphExec_t& g : h->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (h->hsc) (void)hipHostFree(h->hsc);
@@ -1282,6 +1282,17 @@ void ensure_cmetrics(cps_handle* h)
     LAUNCH_CHECK();
     k_cell_jdet<<<nblk(nj), kBlock, 0, h->stream>>>(m.nr, m.nt, nc, h->pJf.p, h->pJc.p);
     LAUNCH_CHECK();
+    // cos, sin of the azimuth 2 pi c / n_phi for c = 0 .. n_phi (the turn of
+    // cell c's faces against cell 0's about the polar axis)
+    std::vector<double> rot(2 * (m.np + 1));
+    for (int c = 0; c <= m.np; ++c) {
+        rot[2 * c] = std::cos(2.0 * M_PI * c / m.np);
+        rot[2 * c + 1] = std::sin(2.0 * M_PI * c / m.np);
+    }
+    h->prot.alloc(rot.size());
+    HIPC(hipMemcpyAsync(h->prot.p, rot.data(), rot.size() * sizeof(double),
+                        hipMemcpyHostToDevice, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
     h->cm_valid = true;
 }
 
@@ -1289,7 +1300,7 @@ CRows crows(const cps_handle* h)
 {
     const LevelMem& m = h->lv[0];
     const int nc = csym(h) == kPerCell ? m.np : 1;
-    return CRows{h->pC.p, (long long)(m.nr + 1) * (m.nt + 1) * nc, m.nt + 1, nc};
+    return CRows{h->pC.p, (long long)(m.nr + 1) * (m.nt + 1) * nc, m.nt + 1, nc, h->prot.p};
 }
 
 // launch f.template operator()<SYM>() for the handle's symmetry
@@ -1309,7 +1320,8 @@ void divergence(cps_handle* h, const double* u, double* rhs)
     const LevelMem& m = h->lv[0];
     ProfScope ps(h, CPS_KERNEL_DIVERGENCE, 0);
     with_csym(h, [&](auto S) {
-        k_divergence<decltype(S)::value><<<nblk(m.n), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np,
+        k_divergence<decltype(S)::value>
+            <<<(unsigned)proj_grid(m.nr, m.nt, m.np), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np,
                                                                               crows(h), u, rhs);
     });
     LAUNCH_CHECK();
@@ -1321,8 +1333,9 @@ void correct(cps_handle* h, const double* phi, double* u)
     const LevelMem& m = h->lv[0];
     ProfScope ps(h, CPS_KERNEL_CORRECT, 0);
     with_csym(h, [&](auto S) {
-        k_correct<decltype(S)::value><<<nblk(m.n), kBlock, 0, h->stream>>>(
-            m.nr, m.nt, m.np, crows(h), h->pJc.p, phi, u);
+        k_correct<decltype(S)::value><<<(unsigned)proj_grid(m.nr, m.nt, m.np), kBlock, 0,
+                                        h->stream>>>(m.nr, m.nt, m.np, crows(h), h->pJc.p, phi,
+                                                     u);
     });
     LAUNCH_CHECK();
 }

@@ -82,7 +82,46 @@ struct CRows {
     const double* C;
     long long F;
     int nt1, nc;
+    const double* rot; // kRotational: cos, sin of 2 pi c / n_phi for c = 0 .. n_phi
 };
+
+// Launch shape of the per-cell kernels: a block is 4 theta rows x 64
+// consecutive phi cells of one r-plane; the linear block index is remapped
+// so that each of the 8 XCDs (which receive blocks round-robin) takes one
+// contiguous range of (plane, row group, phi segment), sharing the theta-
+// and r-neighbour rows in its own L2.
+constexpr int kProjRows = 4;
+
+struct ProjCell {
+    int a, b, c;
+    bool live;
+};
+
+__host__ __device__ inline long long proj_blocks(int nr, int nt, int np)
+{
+    return (long long)nr * ((nt + kProjRows - 1) / kProjRows) * ((np + 63) / 64);
+}
+
+__host__ __device__ inline long long proj_grid(int nr, int nt, int np)
+{
+    return (proj_blocks(nr, nt, np) + 7) / 8 * 8;
+}
+
+__device__ inline ProjCell proj_cell(int nr, int nt, int np)
+{
+    ProjCell p{0, 0, 0, false};
+    const long long nb = proj_blocks(nr, nt, np), per = (nb + 7) / 8;
+    const long long lb = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (lb >= nb) return p;
+    const int segs = (np + 63) / 64, groups = (nt + kProjRows - 1) / kProjRows;
+    const int cs = (int)(lb % segs);
+    const long long t = lb / segs;
+    p.a = (int)(t / groups);
+    p.b = (int)(t % groups) * kProjRows + (int)(threadIdx.x >> 6);
+    p.c = cs * 64 + (int)(threadIdx.x & 63);
+    p.live = p.b < nt && p.c < np;
+    return p;
+}
 
 // C row d of the LOW d-face of position (a, b, c); kRotational: the entry
 // of (a, b, 0) turned about x1 by the angle with cosine cs and sine sn
@@ -110,17 +149,18 @@ __global__ void __launch_bounds__(kBlock) k_divergence(int nr, int nt, int np, C
                                                        const double* __restrict__ u,
                                                        double* __restrict__ rhs)
 {
+    const ProjCell pc = proj_cell(nr, nt, np);
+    if (!pc.live) return;
+    const int a = pc.a, b = pc.b, c = pc.c;
     const long long N = (long long)nr * nt * np, plane = (long long)nt * np;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int c = (int)(i % np);
-    const long long row = i / np;
-    const int b = (int)(row % nt), a = (int)(row / nt);
+    const long long row = (long long)a * nt + b, i = row * np + c;
     const int cm = c == 0 ? np - 1 : c - 1, cp = c == np - 1 ? 0 : c + 1;
     double s0 = 0.0, c0 = 1.0, s1 = 0.0, c1 = 1.0;
     if (SYM == kRotational) {
-        sincospi(2.0 * c / np, &s0, &c0);
-        sincospi(2.0 * (c + 1) / np, &s1, &c1);
+        c0 = R.rot[2 * c];
+        s0 = R.rot[2 * c + 1];
+        c1 = R.rot[2 * c + 2];
+        s1 = R.rot[2 * c + 3];
     }
     const double* u0 = u;
     const double* u1 = u + N;
@@ -156,17 +196,18 @@ __global__ void __launch_bounds__(kBlock) k_correct(int nr, int nt, int np, CRow
                                                     const double* __restrict__ phi,
                                                     double* __restrict__ u)
 {
+    const ProjCell cell = proj_cell(nr, nt, np);
+    if (!cell.live) return;
+    const int a = cell.a, b = cell.b, c = cell.c;
     const long long N = (long long)nr * nt * np, plane = (long long)nt * np;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int c = (int)(i % np);
-    const long long row = i / np;
-    const int b = (int)(row % nt), a = (int)(row / nt);
+    const long long row = (long long)a * nt + b, i = row * np + c;
     const int cm = c == 0 ? np - 1 : c - 1, cp = c == np - 1 ? 0 : c + 1;
     double s0 = 0.0, c0 = 1.0, s1 = 0.0, c1 = 1.0;
     if (SYM == kRotational) {
-        sincospi(2.0 * c / np, &s0, &c0);
-        sincospi(2.0 * (c + 1) / np, &s1, &c1);
+        c0 = R.rot[2 * c];
+        s0 = R.rot[2 * c + 1];
+        c1 = R.rot[2 * c + 2];
+        s1 = R.rot[2 * c + 3];
     }
     const double pc = phi[i];
     double g[3] = {0.0, 0.0, 0.0};
