@@ -8,7 +8,8 @@ no source with it.
   operator of eq. (PC_8)/(PC_term1-3), Gauss-Seidel colour passes, grid
   transfers, dense coarse LU and the multigrid solve of eq. (PC_6).
   It also holds the two steps either side of the solve: the divergence
-  right-hand side of eq. (PC_6) and the velocity correction of eq. (PC_7).
+  right-hand side of eq. (PC_6) and the velocity correction of eq. (PC_7),
+  and the implicit line solves of the ADI steps, eq. (solve_2)-(solve_4).
 * ``direct.py`` -- exact solves (dense, DCT/FFT on the identity box, rFFT in
   phi with sparse LU per mode on axisymmetric maps) that pin the multigrid.
 
@@ -99,6 +100,9 @@ def _load():
             lib.orc_cell_jdet.restype = D
             lib.orc_divergence.argtypes = [P, I, I, I, I, P, L, P, P]
             lib.orc_correct.argtypes = [P, I, I, I, I, P, P, L, P, P]
+            lib.orc_line_apply.argtypes = [P, I, I, I, I, I, D, I, D, I, D, P, P]
+            lib.orc_line_solve.argtypes = [P, I, I, I, I, I, D, I, D, I, D, P, P]
+            lib.orc_line_solve.restype = I
             _lib = lib
     return _lib
 
@@ -349,3 +353,35 @@ def project(grid, u, method: int = METRICS_CENTRAL):
     solve = direct.solve_axisym if direct.is_axisymmetric(G) else direct.solve_sparse
     phi = solve(G, rhs)
     return correct(g, phi, u, method=method), phi, rhs
+
+
+# ---------------------------------------------------------------------------
+# Implicit line solves of the ADI steps, eq. (solve_2)-(solve_4)
+# ---------------------------------------------------------------------------
+
+def line_apply(grid, d: int, coef: float, psi, bc=(0, 0.0, 0, 0.0),
+               method: int = METRICS_CENTRAL) -> np.ndarray:
+    """|J^-1| psi - coef [G_dd (psi_hi - psi_lo)] along direction d, the wall
+    fluxes of bc = (type_lo, v_lo, type_hi, v_hi) (type 0 no flux, 1 value v
+    on the wall face; phi is periodic)."""
+    g = as_grid(grid)
+    psi = _f64(psi).reshape(g.shape)
+    out = np.zeros(g.shape)
+    _load().orc_line_apply(ctypes.byref(g.c_struct()), *g.shape, method, d, coef, bc[0], bc[1],
+                           bc[2], bc[3], _p(psi), _p(out))
+    return out
+
+
+def line_solve(grid, d: int, coef: float, rhs, bc=(0, 0.0, 0, 0.0),
+               method: int = METRICS_CENTRAL) -> np.ndarray:
+    """psi with line_apply(psi) = rhs on every line along d: the Thomas
+    algorithm, and for the periodic phi-lines the paper's split with a
+    closing row."""
+    g = as_grid(grid)
+    rhs = _f64(rhs).reshape(g.shape)
+    psi = np.zeros(g.shape)
+    rc = _load().orc_line_solve(ctypes.byref(g.c_struct()), *g.shape, method, d, coef, bc[0],
+                                bc[1], bc[2], bc[3], _p(rhs), _p(psi))
+    if rc != 0:
+        raise ValueError("periodic lines need at least 3 cells")
+    return psi

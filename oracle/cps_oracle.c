@@ -880,3 +880,173 @@ void orc_correct(const og_grid* g, int nr, int nt, int np, int method, const dou
         for (int q = 0; q < 3; ++q) out[3 * i + q] = u[q * N + id] - grad[q] / J;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Implicit line solves of the ADI steps, eq. (solve_2)-(solve_4)           */
+/* ------------------------------------------------------------------------ */
+/* Along direction d every line of cells solves
+ *     |J^-1|_i psi_i - coef [F_{i+1/2} - F_{i-1/2}] = g_i,
+ * F = G_dd (psi_hi - psi_lo) on an interior face (the diagonal term of
+ * eq. (PC_term1)), |J^-1|_i the cell value of Sec. 3.2 item 3 and G_dd of a
+ * face |C_d|^2 / |J^-1|_face from the face's chords.  On an r- or theta-wall
+ * face: bc 0, F = 0 (no flux); bc 1, the value v on the wall face:
+ * F = 2 G_dd (psi_0 - v) at the low wall, 2 G_dd (v - psi_{n-1}) at the high
+ * wall.  phi is periodic.  Lines: d = 0 indexed by (b, c), d = 1 by (a, c),
+ * d = 2 by (a, b). */
+
+typedef struct { int type_lo, type_hi; double v_lo, v_hi; } og_line_bc;
+
+static double og_face_gdd(const og_grid* g, og_dims n, int method, int d, int a, int b, int c)
+{
+    double C[3];
+    double det = orc_face_crow(g, n.nr, n.nt, n.np, method, d, a, b, c, C);
+    return og_dot(C, C) / det;
+}
+
+/* position of cell i of line `line` along direction d */
+static void og_line_cell(og_dims n, int d, long long line, int i, int p[3])
+{
+    if (d == 0) { p[0] = i; p[1] = (int)(line / n.np); p[2] = (int)(line % n.np); }
+    else if (d == 1) { p[0] = (int)(line / n.np); p[1] = i; p[2] = (int)(line % n.np); }
+    else { p[0] = (int)(line / n.nt); p[1] = (int)(line % n.nt); p[2] = i; }
+}
+
+static int og_line_len(og_dims n, int d) { return d == 0 ? n.nr : (d == 1 ? n.nt : n.np); }
+
+static long long og_line_count(og_dims n, int d)
+{
+    return d == 0 ? (long long)n.nt * n.np : (d == 1 ? (long long)n.nr * n.np
+                                                     : (long long)n.nr * n.nt);
+}
+
+/* Coefficients of one line: lo[i] psi_{i-1} + di[i] psi_i + hi[i] psi_{i+1}
+ * = g_i + ex[i]; for d = 2, lo[0] couples psi_{n-1} and hi[n-1] psi_0. */
+static void og_line_coefs(const og_grid* g, og_dims n, int method, int d, long long line,
+                          double coef, const og_line_bc* bc, double* lo, double* di, double* hi,
+                          double* ex)
+{
+    int len = og_line_len(n, d);
+    for (int i = 0; i < len; ++i) {
+        int p[3];
+        og_line_cell(n, d, line, i, p);
+        double J = orc_cell_jdet(g, n.nr, n.nt, n.np, method, p[0], p[1], p[2]);
+        int q[3] = {p[0], p[1], p[2]};
+        q[d] += 1; /* the high face is the low face of the next position */
+        double Gl = og_face_gdd(g, n, method, d, p[0], p[1], p[2]);
+        double Gh = og_face_gdd(g, n, method, d, q[0], q[1], q[2]);
+        lo[i] = -coef * Gl;
+        hi[i] = -coef * Gh;
+        di[i] = J + coef * (Gl + Gh);
+        ex[i] = 0.0;
+        if (d < 2 && i == 0) {
+            lo[i] = 0.0;
+            if (bc->type_lo == 1) { di[i] += coef * Gl; ex[i] += 2.0 * coef * Gl * bc->v_lo; }
+            else di[i] -= coef * Gl;
+        }
+        if (d < 2 && i == len - 1) {
+            hi[i] = 0.0;
+            if (bc->type_hi == 1) { di[i] += coef * Gh; ex[i] += 2.0 * coef * Gh * bc->v_hi; }
+            else di[i] -= coef * Gh;
+        }
+    }
+}
+
+/* out = |J^-1| psi - coef [F]_{low face}^{high face} along direction d, the
+ * plain definition with the wall fluxes above (values included). */
+void orc_line_apply(const og_grid* g, int nr, int nt, int np, int method, int d, double coef,
+                    int bc_lo, double v_lo, int bc_hi, double v_hi, const double* psi,
+                    double* out)
+{
+    og_dims n = {nr, nt, np};
+    int len = og_line_len(n, d);
+#pragma omp parallel for
+    for (long long line = 0; line < og_line_count(n, d); ++line) {
+        for (int i = 0; i < len; ++i) {
+            int p[3], lo_[3], hi_[3];
+            og_line_cell(n, d, line, i, p);
+            for (int k = 0; k < 3; ++k) { lo_[k] = p[k]; hi_[k] = p[k]; }
+            lo_[d] -= 1;
+            hi_[d] += 1;
+            double x = psi[og_idx(n, p[0], p[1], p[2])];
+            double Fl, Fh;
+            double Gl = og_face_gdd(g, n, method, d, p[0], p[1], p[2]);
+            double Gh = og_face_gdd(g, n, method, d, hi_[0], hi_[1], hi_[2]);
+            if (d < 2 && i == 0) Fl = bc_lo == 1 ? 2.0 * Gl * (x - v_lo) : 0.0;
+            else Fl = Gl * (x - og_x(n, psi, lo_[0], lo_[1], lo_[2]));
+            if (d < 2 && i == len - 1) Fh = bc_hi == 1 ? 2.0 * Gh * (v_hi - x) : 0.0;
+            else Fh = Gh * (og_x(n, psi, hi_[0], hi_[1], hi_[2]) - x);
+            double J = orc_cell_jdet(g, nr, nt, np, method, p[0], p[1], p[2]);
+            out[og_idx(n, p[0], p[1], p[2])] = J * x - coef * (Fh - Fl);
+        }
+    }
+}
+
+/* Thomas algorithm, eq. (FIBRE_TA1)-(FIBRE_TA2): forward elimination of the
+ * sub-diagonal (b'_i = b_i - a_i c_{i-1} / b'_{i-1}, g'_i likewise), then
+ * back substitution psi_i = (g'_i - c_i psi_{i+1}) / b'_i.  Uses bp, gp. */
+static void og_thomas(int n, const double* a, const double* b, const double* c, const double* r,
+                      double* x, double* bp, double* gp)
+{
+    bp[0] = b[0];
+    gp[0] = r[0];
+    for (int i = 1; i < n; ++i) {
+        double m = a[i] / bp[i - 1];
+        bp[i] = b[i] - m * c[i - 1];
+        gp[i] = r[i] - m * gp[i - 1];
+    }
+    x[n - 1] = gp[n - 1] / bp[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = (gp[i] - c[i] * x[i + 1]) / bp[i];
+}
+
+/* Solve every line along d (see above) for psi; rhs and psi are
+ * [n_r][n_theta][n_phi].  Periodic lines (d = 2, length n >= 3): the paper's
+ * split of eq. (FIBRE_TAP1)-(FIBRE_TAP8): the first n-1 unknowns solve the
+ * open system twice, for g and for the corner column (-a_0 at the first row,
+ * -c_{n-2} at the last), the last unknown follows from the closing row, and
+ * psi = psi1 + psi2 psi_{n-1}.  Returns -1 for a periodic line shorter than 3. */
+int orc_line_solve(const og_grid* g, int nr, int nt, int np, int method, int d, double coef,
+                   int bc_lo, double v_lo, int bc_hi, double v_hi, const double* rhs,
+                   double* psi)
+{
+    og_dims n = {nr, nt, np};
+    og_line_bc bc = {bc_lo, bc_hi, v_lo, v_hi};
+    int len = og_line_len(n, d);
+    if (d == 2 && len < 3) return -1;
+#pragma omp parallel
+    {
+        double* w = (double*)malloc(sizeof(double) * 10 * (size_t)len);
+        double *lo = w, *di = w + len, *hi = w + 2 * len, *ex = w + 3 * len, *r = w + 4 * len,
+               *x = w + 5 * len, *bp = w + 6 * len, *gp = w + 7 * len, *x2 = w + 8 * len,
+               *r2 = w + 9 * len;
+#pragma omp for
+        for (long long line = 0; line < og_line_count(n, d); ++line) {
+            og_line_coefs(g, n, method, d, line, coef, &bc, lo, di, hi, ex);
+            for (int i = 0; i < len; ++i) {
+                int p[3];
+                og_line_cell(n, d, line, i, p);
+                r[i] = rhs[og_idx(n, p[0], p[1], p[2])] + ex[i];
+            }
+            if (d < 2) {
+                og_thomas(len, lo, di, hi, r, x, bp, gp);
+            } else {
+                int m = len - 1; /* open system of the first m unknowns */
+                og_thomas(m, lo, di, hi, r, x, bp, gp);
+                for (int i = 0; i < m; ++i) r2[i] = 0.0;
+                r2[0] = -lo[0];
+                r2[m - 1] -= hi[m - 1];
+                og_thomas(m, lo, di, hi, r2, x2, bp, gp);
+                double xl = (r[m] - hi[m] * x[0] - lo[m] * x[m - 1]) /
+                            (di[m] + hi[m] * x2[0] + lo[m] * x2[m - 1]);
+                for (int i = 0; i < m; ++i) x[i] += x2[i] * xl;
+                x[m] = xl;
+            }
+            for (int i = 0; i < len; ++i) {
+                int p[3];
+                og_line_cell(n, d, line, i, p);
+                psi[og_idx(n, p[0], p[1], p[2])] = x[i];
+            }
+        }
+        free(w);
+    }
+    return 0;
+}
