@@ -184,6 +184,34 @@ cps_status cps_correct(cps_handle* h, const double* phi, double* u);
  * Uses a handle-owned right-hand-side buffer (allocated on first call). */
 cps_status cps_project(cps_handle* h, double* u, double* phi, double tol, cps_info* info);
 
+/* ---- Implicit line solves of the ADI steps (finest grid) ---------------
+ * eq. (solve_2)-(solve_4): each ADI step solves, along one direction dir
+ * (0 r, 1 theta, 2 phi), every line of cells for psi:
+ *     |J^-1|_i psi_i - coef [F_{i+1/2} - F_{i-1/2}] = rhs_i,
+ * F = G_dd (psi_hi - psi_lo) on an interior face (the diagonal viscous term,
+ * as in eq. (PC_term1)), G_dd = |C_d|^2 / |J^-1| at the face from the face's
+ * chords, |J^-1|_i the cell value of the projection step.  coef is the
+ * implicit weight (e.g. sqrt(Pr/Ra) h / 2).  r- and theta-lines use the
+ * Thomas algorithm (eq. (FIBRE_TA1)-(FIBRE_TA2)); phi-lines are periodic
+ * and use the split with a closing row of eq. (FIBRE_TAP1)-(FIBRE_TAP8). */
+typedef struct {
+    int32_t type_lo, type_hi; /* 0: no flux through the wall face; 1: value on it */
+    double value_lo, value_hi; /* the wall values for type 1 (F = 2 G_dd (psi_0 -
+                                  value_lo) at the low wall, 2 G_dd (value_hi -
+                                  psi_{n-1}) at the high wall) */
+} cps_line_bc;
+
+/* rhs, psi: device FP64 [n_r][n_theta][n_phi], the same array (in place) or
+ * not overlapping.  bc: host, nullable (no flux); ignored for dir 2.
+ * Needs phi-invariant metrics (box, sphere, oblate shell) and, for dir 2,
+ * n_phi >= 3.  Device memory owned by the handle, built on first use: the
+ * projection step's face tables, an elimination table of 3 words per
+ * (r, theta) position, and for dir 2 two scratch fields.
+ * Errors: CPS_E_INVALID (dir, coef < 0 or not finite, bc types, map,
+ * overlap). */
+cps_status cps_line_solve(cps_handle* h, int32_t dir, double coef, const cps_line_bc* bc,
+                          const double* rhs, double* psi);
+
 /* ---- Kernel-level entry points (FP64 hierarchy of the handle) ----------
  * For parity tests of each step against an independent implementation.
  * level l indexes the hierarchy (0 = finest); all arrays are device FP64

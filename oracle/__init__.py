@@ -101,7 +101,7 @@ def _load():
             lib.orc_divergence.argtypes = [P, I, I, I, I, P, L, P, P]
             lib.orc_correct.argtypes = [P, I, I, I, I, P, P, L, P, P]
             lib.orc_line_apply.argtypes = [P, I, I, I, I, I, D, I, D, I, D, P, P]
-            lib.orc_line_solve.argtypes = [P, I, I, I, I, I, D, I, D, I, D, P, P]
+            lib.orc_line_solve.argtypes = [P, I, I, I, I, I, D, I, D, I, D, P, P, L, P]
             lib.orc_line_solve.restype = I
             _lib = lib
     return _lib
@@ -373,15 +373,19 @@ def line_apply(grid, d: int, coef: float, psi, bc=(0, 0.0, 0, 0.0),
 
 
 def line_solve(grid, d: int, coef: float, rhs, bc=(0, 0.0, 0, 0.0),
-               method: int = METRICS_CENTRAL) -> np.ndarray:
+               method: int = METRICS_CENTRAL, lines=None) -> np.ndarray:
     """psi with line_apply(psi) = rhs on every line along d: the Thomas
     algorithm, and for the periodic phi-lines the paper's split with a
-    closing row."""
+    closing row.  lines: solve only these line indices (d = 0: b n_phi + c,
+    d = 1: a n_phi + c, d = 2: a n_theta + b); psi is zero elsewhere."""
     g = as_grid(grid)
     rhs = _f64(rhs).reshape(g.shape)
     psi = np.zeros(g.shape)
+    idx = None if lines is None else np.ascontiguousarray(lines, dtype=np.int64).ravel()
     rc = _load().orc_line_solve(ctypes.byref(g.c_struct()), *g.shape, method, d, coef, bc[0],
-                                bc[1], bc[2], bc[3], _p(rhs), _p(psi))
+                                bc[1], bc[2], bc[3], _p(rhs), _p(psi),
+                                0 if idx is None else idx.size,
+                                None if idx is None else _p(idx))
     if rc != 0:
         raise ValueError("periodic lines need at least 3 cells")
     return psi

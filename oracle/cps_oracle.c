@@ -1003,10 +1003,13 @@ static void og_thomas(int n, const double* a, const double* b, const double* c, 
  * split of eq. (FIBRE_TAP1)-(FIBRE_TAP8): the first n-1 unknowns solve the
  * open system twice, for g and for the corner column (-a_0 at the first row,
  * -c_{n-2} at the last), the last unknown follows from the closing row, and
- * psi = psi1 + psi2 psi_{n-1}.  Returns -1 for a periodic line shorter than 3. */
+ * psi = psi1 + psi2 psi_{n-1}.  `lines` (nullable): solve only the listed
+ * line indices (d = 0: b n_phi + c; d = 1: a n_phi + c; d = 2: a n_theta + b),
+ * `nline` of them; psi is written on those lines only.  Returns -1 for a
+ * periodic line shorter than 3. */
 int orc_line_solve(const og_grid* g, int nr, int nt, int np, int method, int d, double coef,
                    int bc_lo, double v_lo, int bc_hi, double v_hi, const double* rhs,
-                   double* psi)
+                   double* psi, long long nline, const long long* lines)
 {
     og_dims n = {nr, nt, np};
     og_line_bc bc = {bc_lo, bc_hi, v_lo, v_hi};
@@ -1018,8 +1021,10 @@ int orc_line_solve(const og_grid* g, int nr, int nt, int np, int method, int d, 
         double *lo = w, *di = w + len, *hi = w + 2 * len, *ex = w + 3 * len, *r = w + 4 * len,
                *x = w + 5 * len, *bp = w + 6 * len, *gp = w + 7 * len, *x2 = w + 8 * len,
                *r2 = w + 9 * len;
+        const long long count = lines ? nline : og_line_count(n, d);
 #pragma omp for
-        for (long long line = 0; line < og_line_count(n, d); ++line) {
+        for (long long li = 0; li < count; ++li) {
+            const long long line = lines ? lines[li] : li;
             og_line_coefs(g, n, method, d, line, coef, &bc, lo, di, hi, ex);
             for (int i = 0; i < len; ++i) {
                 int p[3];

@@ -123,7 +123,8 @@ def lib():
         L.cps_divergence.argtypes = [P, P, P]
         L.cps_correct.argtypes = [P, P, P]
         L.cps_project.argtypes = [P, P, P, D, P]
-        for f in ("cps_divergence", "cps_correct", "cps_project", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
+        L.cps_line_solve.argtypes = [P, I, D, P, P, P]
+        for f in ("cps_divergence", "cps_correct", "cps_project", "cps_line_solve", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
                   "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
                   "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
                   "cps_debug_coarse_solve", "cps_debug_vcycle", "cps_debug_plane_sweep"):
@@ -205,6 +206,20 @@ def cps_project(h, u, phi, tol: float):
     if st not in (CPS_OK, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED):
         _check(st)
     return st, info
+
+
+class cps_line_bc(ctypes.Structure):
+    _fields_ = [("type_lo", ctypes.c_int32), ("type_hi", ctypes.c_int32),
+                ("value_lo", ctypes.c_double), ("value_hi", ctypes.c_double)]
+
+
+def cps_line_solve(h, d: int, coef: float, rhs, psi, bc=(0, 0.0, 0, 0.0)):
+    """One ADI direction's implicit line solves (bc = (type_lo, value_lo,
+    type_hi, value_hi)); rhs and psi may be the same tensor."""
+    _, n = _dims(h, 0)
+    _expect(rhs, n, "rhs"); _expect(psi, n, "psi")
+    b = cps_line_bc(bc[0], bc[2], bc[1], bc[3])
+    _check(lib().cps_line_solve(h, d, coef, ctypes.byref(b), _ptr(rhs), _ptr(psi)))
 
 
 def cps_destroy(h):
@@ -374,6 +389,13 @@ class Solver:
         st, info = cps_project(self.h, u, phi, tol)
         return Result(phi, st, info.iterations, info.rel_residual, info.rhs_mean_removed,
                       info.seconds)
+
+    def line_solve(self, d: int, coef: float, rhs, bc=(0, 0.0, 0, 0.0), out=None):
+        """Implicit line solves along direction d (0 r, 1 theta, 2 phi)."""
+        import torch
+        psi = out if out is not None else torch.empty_like(rhs)
+        cps_line_solve(self.h, d, coef, rhs, psi, bc)
+        return psi
 
     def close(self):
         if getattr(self, "h", None):

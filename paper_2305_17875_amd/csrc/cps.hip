@@ -11,6 +11,7 @@
 #include "kernels.hpp"
 #include "plane.hpp"
 #include "project.hpp"
+#include "lines.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -183,6 +184,9 @@ struct cps_handle {
     // projection step (finest grid, built on first use): C rows and
     // determinants of the faces, cell |J^-1|, the divergence right-hand side
     Buf<double> pC, pJf, pJc, prhs, prot;
+    // ADI line solves: elimination tables of the distinct open lines, and
+    // the periodic lines' scratch (built on first use)
+    Buf<double> plf, pls;
     bool cm_valid = false;
     // captured outer-iteration bodies (G_* keys), replayed by run_body
     hipGraphExec_t gexec[4] = {};
@@ -986,6 +990,7 @@ void destroy(cps_handle* h)
     h->r0.release(); h->v.release(); h->s.release(); h->t.release(); h->ph.release();
     h->sh.release();
     h->pC.release(); h->pJf.release(); h->pJc.release(); h->prhs.release(); h->prot.release();
+    h->plf.release(); h->pls.release();
     for (hipGraphExec_t& g : h->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (h->hsc) (void)hipHostFree(h->hsc);
@@ -1342,6 +1347,47 @@ void correct(cps_handle* h, const double* phi, double* u)
 
 } // namespace
 
+// ---------------------------------------------------------------------------
+// ADI line solves (eq. (solve_2)-(solve_4))
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void line_solve(cps_handle* h, int dir, double coef, const LineBC& bc, const double* rhs,
+                double* psi)
+{
+    ensure_cmetrics(h);
+    const LevelMem& m = h->lv[0];
+    const CRows R = crows(h);
+    if (dir < 2) {
+        const int lines = dir == 0 ? m.nt : m.nr, n = dir == 0 ? m.nr : m.nt;
+        const size_t need = 3 * (size_t)lines * n + 2 * (size_t)lines;
+        if (h->plf.n < need) h->plf.alloc(need);
+        double* Fm = h->plf.p;
+        double* Fi = Fm + (size_t)lines * n;
+        double* Fh = Fi + (size_t)lines * n;
+        double* Fx = Fh + (size_t)lines * n;
+        k_line_factor<<<nblk(lines), kBlock, 0, h->stream>>>(m.nr, m.nt, dir, coef, bc, R,
+                                                             h->pJf.p, h->pJc.p, Fm, Fi, Fh, Fx);
+        LAUNCH_CHECK();
+        const long long threads = (long long)lines * m.np;
+        if (dir == 0)
+            k_line_open<0><<<nblk(threads), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, Fm, Fi, Fh,
+                                                                    Fx, rhs, psi);
+        else
+            k_line_open<1><<<nblk(threads), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, Fm, Fi, Fh,
+                                                                    Fx, rhs, psi);
+        LAUNCH_CHECK();
+        return;
+    }
+    if (h->pls.n < (size_t)(2 * m.n)) h->pls.alloc(2 * m.n);
+    k_line_periodic<<<nblk((long long)m.nr * m.nt), kBlock, 0, h->stream>>>(
+        m.nr, m.nt, m.np, coef, R, h->pJf.p, h->pJc.p, rhs, psi, h->pls.p, h->pls.p + m.n);
+    LAUNCH_CHECK();
+}
+
+} // namespace
+
 extern "C" {
 
 void cps_grid_default(cps_grid* g)
@@ -1596,6 +1642,29 @@ cps_status cps_project(cps_handle* h, double* u, double* phi, double tol, cps_in
         if (st == CPS_OK) correct(h, phi, u);
     });
     return g != CPS_OK ? g : st;
+}
+
+cps_status cps_line_solve(cps_handle* h, int32_t dir, double coef, const cps_line_bc* bc,
+                          const double* rhs, double* psi)
+{
+    return guarded([&] {
+        if (!h || !rhs || !psi) fail(CPS_E_INVALID, "NULL argument");
+        if (dir < 0 || dir > 2) fail(CPS_E_INVALID, "dir must be 0 (r), 1 (theta) or 2 (phi)");
+        if (!(coef >= 0.0) || !std::isfinite(coef)) fail(CPS_E_INVALID, "coef must be >= 0");
+        if (!h->axi)
+            fail(CPS_E_INVALID, "line solves need phi-invariant metrics (box, sphere, oblate)");
+        if (dir == 2 && h->lv[0].np < 3) fail(CPS_E_INVALID, "periodic lines need n_phi >= 3");
+        const long long n = h->lv[0].n;
+        if (rhs != psi && rhs + n > psi && rhs < psi + n)
+            fail(CPS_E_INVALID, "rhs and psi must be the same array or not overlap");
+        LineBC b{0, 0, 0.0, 0.0};
+        if (bc) {
+            if (bc->type_lo < 0 || bc->type_lo > 1 || bc->type_hi < 0 || bc->type_hi > 1)
+                fail(CPS_E_INVALID, "bc types must be 0 (no flux) or 1 (value)");
+            b = LineBC{bc->type_lo, bc->type_hi, bc->value_lo, bc->value_hi};
+        }
+        line_solve(h, dir, coef, b, rhs, psi);
+    });
 }
 
 cps_status cps_debug_copy(const double* src, double* dst, int64_t n, void* stream)

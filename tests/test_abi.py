@@ -24,7 +24,7 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for want in ("cps_setup", "cps_solve", "cps_destroy", "cps_last_error", "cps_levels",
                  "cps_debug_residual", "cps_debug_gs_pass", "cps_debug_vcycle",
-                 "cps_divergence", "cps_correct", "cps_project"):
+                 "cps_divergence", "cps_correct", "cps_project", "cps_line_solve"):
         assert want in names
 
 
@@ -48,6 +48,7 @@ def test_ctypes_layout_matches_c(tmp_path):
         'printf("%zu %zu %zu %zu\\n", sizeof(cps_grid), sizeof(cps_metrics), sizeof(cps_opts), sizeof(cps_info));\n'
         'printf("%zu %zu %zu\\n", offsetof(cps_grid, r_inner), offsetof(cps_grid, skew), offsetof(cps_grid, n_levels));\n'
         'printf("%zu %zu\\n", offsetof(cps_opts, stream), offsetof(cps_info, seconds));\n'
+        'printf("%zu %zu\\n", sizeof(cps_line_bc), offsetof(cps_line_bc, value_hi));\n'
         "return 0;}\n")
     exe = tmp_path / "probe"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe),
@@ -57,7 +58,8 @@ def test_ctypes_layout_matches_c(tmp_path):
                         ctypes.sizeof(cps.cps_opts), ctypes.sizeof(cps.cps_info)]
     assert vals[4:7] == [cps.cps_grid.r_inner.offset, cps.cps_grid.skew.offset,
                          cps.cps_grid.n_levels.offset]
-    assert vals[7:] == [cps.cps_opts.stream.offset, cps.cps_info.seconds.offset]
+    assert vals[7:9] == [cps.cps_opts.stream.offset, cps.cps_info.seconds.offset]
+    assert vals[9:] == [ctypes.sizeof(cps.cps_line_bc), cps.cps_line_bc.value_hi.offset]
 
 
 def test_grid_default_and_invalid_setup_without_gpu():
