@@ -9,7 +9,8 @@ preconditioned by one V(2,2) cycle) from the right-hand side resident in HBM
 to relative residual 1e-10.  The FP32-multigrid + FP64-refinement form is
 timed on the same input and reported beside it, and so is the same solve
 with the zebra (r, phi)-plane smoother (`plane`); the whole projection step
-around the solve is timed under `project`.  Prints one JSON line.
+around the solve is timed under `project`, and the implicit line solves of
+the ADI steps under `lines`.  Prints one JSON line.
 
 Roofline: the dominant kernel is the finest-level Gauss-Seidel colour pass.
 Its duration is measured live with HIP events recorded on the solve stream
@@ -244,6 +245,45 @@ def project_form(cps, torch, inputs, g, steps, warmup):
         s.close()
         del u, phi
     del u0
+    torch.cuda.empty_cache()
+    return out
+
+
+def lines_form(cps, torch, inputs, g, steps, warmup):
+    """The implicit line solves of the ADI steps (cps_line_solve) along each
+    direction on the paper-scale shell, coef 1e-4, value 0 on the low wall
+    and no flux on the high wall.  Timed with events on the solve stream;
+    rates against the design's bytes per cell: open r- and theta-lines read
+    the right-hand side and write psi on the way down, read and write psi on
+    the way up (4 words); periodic phi-lines with a power-of-two ring are
+    solved by one transform per ring in LDS (read once, written once: 2
+    words), other rings by the split with a closing row (12 words)."""
+    n = g.cells
+    rhs = torch.from_numpy(inputs.smoothed_noise(g.shape, 50)).cuda().flatten()
+    psi = torch.empty_like(rhs)
+    s = cps.Solver(g, precision=0)
+    out = {"workload": "paper-scale shell, smoothed N(0,1) rhs seed 50, coef 1e-4, "
+                       "bc: value 0 at the low wall, no flux at the high wall"}
+    bc = (1, 0.0, 0, 0.0)
+    nh = g.n_phi // 2
+    phi_words = 2 if nh >= 2 and nh & (nh - 1) == 0 and nh <= 1024 else 12
+    for d, name, words in ((0, "r", 4), (1, "theta", 4), (2, "phi_periodic", phi_words)):
+        for _ in range(warmup):
+            s.line_solve(d, 1e-4, rhs, bc, out=psi)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(steps):
+            s.line_solve(d, 1e-4, rhs, bc, out=psi)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / steps * 1e-3
+        b = words * 8 * n
+        out[name] = {"avg_us": t * 1e6, "unknowns_per_s": n / t, "algorithmic_bytes": b,
+                     "achieved_GBs": b / t / 1e9, "frac_of_peak": b / t / 1e9 / HBM_PEAK_GBS}
+        log(f"lines {name}: {t * 1e6:.1f} us")
+    s.close()
+    del rhs, psi
     torch.cuda.empty_cache()
     return out
 
@@ -487,6 +527,7 @@ def main():
     ap.add_argument("--no-plane", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-project", action="store_true")
+    ap.add_argument("--no-lines", action="store_true")
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
@@ -567,6 +608,8 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_project:
         line["project"] = project_form(cps, torch, inputs, g, a.steps, a.warmup)
+    if not a.no_lines:
+        line["lines"] = lines_form(cps, torch, inputs, g, a.steps, a.warmup)
     if not a.no_batch:
         line["batch"] = batch_form(cps, torch, inputs, a.batch_problems, a.steps, a.warmup)
         torch.cuda.empty_cache()

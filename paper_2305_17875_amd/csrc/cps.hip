@@ -184,9 +184,14 @@ struct cps_handle {
     // projection step (finest grid, built on first use): C rows and
     // determinants of the faces, cell |J^-1|, the divergence right-hand side
     Buf<double> pC, pJf, pJc, prhs, prot;
-    // ADI line solves: elimination tables of the distinct open lines, and
-    // the periodic lines' scratch (built on first use)
-    Buf<double> plf, pls;
+    // ADI line solves (built on first use): elimination tables of the
+    // distinct open r- and theta-lines with the (coef, walls) they were built
+    // for, the periodic lines' scratch, and the ring transform's tables
+    Buf<double> plf[2], pls, plam;
+    Buf<double> ptw, ptwN;
+    bool lf_valid[2] = {false, false};
+    double lf_coef[2] = {0.0, 0.0};
+    LineBC lf_bc[2] = {};
     bool cm_valid = false;
     // captured outer-iteration bodies (G_* keys), replayed by run_body
     hipGraphExec_t gexec[4] = {};
@@ -849,6 +854,7 @@ int compute_operator(cps_handle* h)
     }
     if (h->lv[0].pv64.p || h->lv[0].pv32.p) plane_factors(h); // new metrics of a set-up hierarchy
     h->cm_valid = false; // the projection step's face tables follow the map
+    h->lf_valid[0] = h->lf_valid[1] = false;
     return mode;
 }
 
@@ -990,7 +996,8 @@ void destroy(cps_handle* h)
     h->r0.release(); h->v.release(); h->s.release(); h->t.release(); h->ph.release();
     h->sh.release();
     h->pC.release(); h->pJf.release(); h->pJc.release(); h->prhs.release(); h->prot.release();
-    h->plf.release(); h->pls.release();
+    h->plf[0].release(); h->plf[1].release(); h->pls.release(); h->plam.release();
+    h->ptw.release(); h->ptwN.release();
     for (hipGraphExec_t& g : h->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (h->hsc) (void)hipHostFree(h->hsc);
@@ -1353,6 +1360,44 @@ void correct(cps_handle* h, const double* phi, double* u)
 
 namespace {
 
+bool same_bc(const LineBC& x, const LineBC& y)
+{
+    return x.type_lo == y.type_lo && x.type_hi == y.type_hi && x.v_lo == y.v_lo &&
+           x.v_hi == y.v_hi;
+}
+
+// ring transform applies: n_phi / 2 a power of two in [2, kPlaneLds], both
+// fields 16-byte aligned (they are read and written as pairs)
+bool fft_lines(const cps_handle* h, const double* rhs, const double* psi)
+{
+    const int nh = h->lv[0].np / 2;
+    return nh >= 2 && nh <= kPlaneLds && (nh & (nh - 1)) == 0 &&
+           ((uintptr_t)rhs % 16) == 0 && ((uintptr_t)psi % 16) == 0;
+}
+
+void ensure_ring_tables(cps_handle* h)
+{
+    if (h->plam.p) return;
+    const int np = h->lv[0].np, nh = np / 2;
+    std::vector<double> tw(nh), twN(2 * (nh + 1)), lam(nh + 1);
+    for (int q = 0; q < nh / 2; ++q) {
+        tw[2 * q] = std::cos(-2.0 * M_PI * q / nh);
+        tw[2 * q + 1] = std::sin(-2.0 * M_PI * q / nh);
+    }
+    for (int k = 0; k <= nh; ++k) {
+        twN[2 * k] = std::cos(-2.0 * M_PI * k / np);
+        twN[2 * k + 1] = std::sin(-2.0 * M_PI * k / np);
+        lam[k] = 2.0 * std::cos(2.0 * M_PI * k / np) - 2.0;
+    }
+    auto up = [&](Buf<double>& d, const std::vector<double>& v) {
+        d.alloc(v.size());
+        HIPC(hipMemcpy(d.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    };
+    up(h->ptw, tw);
+    up(h->ptwN, twN);
+    up(h->plam, lam);
+}
+
 void line_solve(cps_handle* h, int dir, double coef, const LineBC& bc, const double* rhs,
                 double* psi)
 {
@@ -1361,15 +1406,30 @@ void line_solve(cps_handle* h, int dir, double coef, const LineBC& bc, const dou
     const CRows R = crows(h);
     if (dir < 2) {
         const int lines = dir == 0 ? m.nt : m.nr, n = dir == 0 ? m.nr : m.nt;
+        Buf<double>& F = h->plf[dir];
         const size_t need = 3 * (size_t)lines * n + 2 * (size_t)lines;
-        if (h->plf.n < need) h->plf.alloc(need);
-        double* Fm = h->plf.p;
-        double* Fi = Fm + (size_t)lines * n;
-        double* Fh = Fi + (size_t)lines * n;
-        double* Fx = Fh + (size_t)lines * n;
-        k_line_factor<<<nblk(lines), kBlock, 0, h->stream>>>(m.nr, m.nt, dir, coef, bc, R,
-                                                             h->pJf.p, h->pJc.p, Fm, Fi, Fh, Fx);
-        LAUNCH_CHECK();
+        double* Fm;
+        double *Fi, *Fh, *Fx;
+        auto views = [&] {
+            Fm = F.p;
+            Fi = Fm + (size_t)lines * n;
+            Fh = Fi + (size_t)lines * n;
+            Fx = Fh + (size_t)lines * n;
+        };
+        // the elimination depends on (coef, walls) and the metrics only: an
+        // ADI step repeats it every time step, so it is kept
+        if (!h->lf_valid[dir] || h->lf_coef[dir] != coef || !same_bc(h->lf_bc[dir], bc)) {
+            if (F.n < need) F.alloc(need);
+            views();
+            k_line_factor<<<nblk(lines), kBlock, 0, h->stream>>>(m.nr, m.nt, dir, coef, bc, R,
+                                                                 h->pJf.p, h->pJc.p, Fm, Fi, Fh,
+                                                                 Fx);
+            LAUNCH_CHECK();
+            h->lf_valid[dir] = true;
+            h->lf_coef[dir] = coef;
+            h->lf_bc[dir] = bc;
+        }
+        views();
         const long long threads = (long long)lines * m.np;
         if (dir == 0)
             k_line_open<0><<<nblk(threads), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, Fm, Fi, Fh,
@@ -1377,6 +1437,16 @@ void line_solve(cps_handle* h, int dir, double coef, const LineBC& bc, const dou
         else
             k_line_open<1><<<nblk(threads), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, Fm, Fi, Fh,
                                                                     Fx, rhs, psi);
+        LAUNCH_CHECK();
+        return;
+    }
+    if (fft_lines(h, rhs, psi)) {
+        ensure_ring_tables(h);
+        const FftLineLaunch pl = fft_line_launch(m.nr, m.nt, m.np);
+        k_line_fft<<<pl.blocks, pl.threads, 0, h->stream>>>(
+            m.nr, m.nt, m.np, coef, R, h->pJf.p, h->pJc.p,
+            reinterpret_cast<const Vec2<double>*>(h->ptw.p),
+            reinterpret_cast<const Vec2<double>*>(h->ptwN.p), h->plam.p, rhs, psi);
         LAUNCH_CHECK();
         return;
     }

@@ -214,3 +214,115 @@ __global__ void __launch_bounds__(kBlock) k_line_periodic(int nr, int nt, int np
 }
 
 } // namespace cps
+
+namespace cps {
+
+// Periodic phi-lines with constant coefficients (phi-invariant metrics) are
+// circulant: a real Fourier transform along the ring diagonalises them, mode
+// m having the symbol |J^-1| - coef G_pp lam_m, lam_m = 2 cos(2 pi m / n_phi)
+// - 2.  One wavefront per ring (n_phi / 2 a power of two <= kPlaneLds): the
+// ring is read once as n_phi / 2 complex pairs (x_{2j}, x_{2j+1}), transformed
+// in LDS (wave_fft), divided mode by mode, transformed back and written once.
+struct FftLineLaunch {
+    int tpr, rb, threads, rings, blocks;
+};
+
+__host__ __device__ inline FftLineLaunch fft_line_launch(int nr, int nt, int np)
+{
+    FftLineLaunch p;
+    const int nh = np / 2;
+    p.tpr = nh / 2 < 64 ? nh / 2 : 64;
+    p.rb = kBlock / p.tpr;
+    if (p.rb * (nh + 1) > kPlaneLds) p.rb = kPlaneLds / (nh + 1);
+    p.threads = p.rb * p.tpr;
+    p.rings = nr * nt;
+    p.blocks = (p.rings + p.rb - 1) / p.rb;
+    return p;
+}
+
+__global__ void __launch_bounds__(kBlock) k_line_fft(int nr, int nt, int np, double coef, CRows R,
+                                                     const double* __restrict__ Jf,
+                                                     const double* __restrict__ Jc,
+                                                     const Vec2<double>* __restrict__ tw,
+                                                     const Vec2<double>* __restrict__ twN,
+                                                     const double* __restrict__ lam,
+                                                     const double* rhs, double* psi)
+{
+    __shared__ Vec2<double> buf[kPlaneLds], twS[kPlaneLds / 2];
+    const FftLineLaunch pl = fft_line_launch(nr, nt, np);
+    const int nh = np / 2;
+    for (int q = (int)threadIdx.x; q < nh / 2; q += pl.threads) twS[q] = tw[q];
+    // one ring = nh complex values (the pair of mode m = nh aliases slot 0)
+    const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
+    const int ring = (int)blockIdx.x * pl.rb + rl;
+    const bool live = ring < pl.rings;
+    Vec2<double>* A = buf + rl * (nh + 1);
+    const long long base = (long long)ring * np;
+    if (live)
+        for (int j0 = tr; j0 < nh; j0 += kLdBatch * pl.tpr) {
+            Vec2<double> z[kLdBatch];
+#pragma unroll
+            for (int u = 0; u < kLdBatch; ++u) {
+                const int j = j0 + u * pl.tpr;
+                if (j < nh) z[u] = *reinterpret_cast<const Vec2<double>*>(rhs + base + 2 * j);
+            }
+#pragma unroll
+            for (int u = 0; u < kLdBatch; ++u) {
+                const int j = j0 + u * pl.tpr;
+                if (j < nh) A[j] = z[u];
+            }
+        }
+    __syncthreads(); // twiddles of the block (the ring's values are wave-local)
+    if (!live) return;
+    const int a = ring / nt, b = ring - a * nt;
+    const double G = face_gdd(R, Jf, 2, a, b), J = Jc[ring];
+    wave_fft<double>(A, nh, tr, pl.tpr, twS, false);
+    // Mode pairs (m, nh - m), m <= nh / 2, one lane each: the two slots of
+    // the half-length transform give the real modes X_m and X_{nh-m} (X_m =
+    // E + twN[m] O, E and O the even and odd parts), each is divided by its
+    // symbol, and the inverse recombination writes the same two slots back;
+    // no other lane reads them.
+    const double dJ = J, cG = coef * G;
+    auto real_mode = [&](Vec2<double> zm, Vec2<double> zc, int k) {
+        // zm = Z_k, zc = conj(Z_{nh-k})
+        Vec2<double> E, O;
+        E.x = 0.5 * (zm.x + zc.x);
+        E.y = 0.5 * (zm.y + zc.y);
+        O.x = 0.5 * (zm.y - zc.y);
+        O.y = -0.5 * (zm.x - zc.x);
+        const double s = 1.0 / (dJ - cG * lam[k]);
+        return (E + cmul(twN[k], O)) * s;
+    };
+    auto half_seq = [&](Vec2<double> xm, Vec2<double> xc, int k) {
+        // xm = Y_k, xc = conj(Y_{nh-k}): the half-length value z_k
+        Vec2<double> E, D;
+        E.x = 0.5 * (xm.x + xc.x);
+        E.y = 0.5 * (xm.y + xc.y);
+        D.x = 0.5 * (xm.x - xc.x);
+        D.y = 0.5 * (xm.y - xc.y);
+        const Vec2<double> O = cmul(conjv(twN[k]), D);
+        Vec2<double> z;
+        z.x = E.x - O.y;
+        z.y = E.y + O.x;
+        return z;
+    };
+    for (int m = tr; m <= nh / 2; m += pl.tpr) {
+        const int k = nh - m;
+        const Vec2<double> Zm = A[m], Zk = A[k == nh ? 0 : k];
+        const Vec2<double> Ym = real_mode(Zm, conjv(Zk), m);
+        const Vec2<double> Yk = real_mode(Zk, conjv(Zm), k);
+        A[m] = half_seq(Ym, conjv(Yk), m);
+        if (k != m && k < nh) A[k] = half_seq(Yk, conjv(Ym), k);
+    }
+    wave_sync();
+    wave_fft<double>(A, nh, tr, pl.tpr, twS, true);
+    const double sc = 1.0 / nh;
+    for (int j = tr; j < nh; j += pl.tpr) {
+        Vec2<double> v = A[j];
+        v.x *= sc;
+        v.y *= sc;
+        *reinterpret_cast<Vec2<double>*>(psi + base + 2 * j) = v;
+    }
+}
+
+} // namespace cps
