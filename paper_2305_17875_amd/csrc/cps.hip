@@ -364,14 +364,23 @@ void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
     const auto* twN = reinterpret_cast<const Vec2<T>*>(PB::twN(m));
     auto* S = reinterpret_cast<Vec2<T>*>(PB::S(h));
     ProfScope ps(h, CPS_KERNEL_GS, l);
-    k_plane_fwd<T><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, L.G, L.gk, b, x, parity, tw,
-                                                            twN, S);
+    if (L.g.nh <= kSmallRing)
+        k_plane_fwd<T, kSmallRing><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, L.G, L.gk, b, x,
+                                                                            parity, tw, twN, S);
+    else
+        k_plane_fwd<T, kPlaneLds><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, L.G, L.gk, b, x,
+                                                                           parity, tw, twN, S);
     LAUNCH_CHECK();
     const long long lanes = 2LL * pl.rows * (L.g.nh + 1);
     k_plane_tri<T><<<(unsigned)cdiv(lanes, kTriBlock), kTriBlock, 0, h->stream>>>(
         L.g, L.G, parity, PB::piv(m) + plane_pivot_offset(L.g, parity), PB::S(h));
     LAUNCH_CHECK();
-    k_plane_inv<T><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN, S, x);
+    if (L.g.nh <= kSmallRing)
+        k_plane_inv<T, kSmallRing><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN,
+                                                                            S, x);
+    else
+        k_plane_inv<T, kPlaneLds><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN, S,
+                                                                           x);
     LAUNCH_CHECK();
 }
 
@@ -1443,10 +1452,14 @@ void line_solve(cps_handle* h, int dir, double coef, const LineBC& bc, const dou
     if (fft_lines(h, rhs, psi)) {
         ensure_ring_tables(h);
         const FftLineLaunch pl = fft_line_launch(m.nr, m.nt, m.np);
-        k_line_fft<<<pl.blocks, pl.threads, 0, h->stream>>>(
-            m.nr, m.nt, m.np, coef, R, h->pJf.p, h->pJc.p,
-            reinterpret_cast<const Vec2<double>*>(h->ptw.p),
-            reinterpret_cast<const Vec2<double>*>(h->ptwN.p), h->plam.p, rhs, psi);
+        const auto* tw = reinterpret_cast<const Vec2<double>*>(h->ptw.p);
+        const auto* twN = reinterpret_cast<const Vec2<double>*>(h->ptwN.p);
+        if (m.np / 2 <= kSmallRing)
+            k_line_fft<kSmallRing><<<pl.blocks, pl.threads, 0, h->stream>>>(
+                m.nr, m.nt, m.np, coef, R, h->pJf.p, h->pJc.p, tw, twN, h->plam.p, rhs, psi);
+        else
+            k_line_fft<kPlaneLds><<<pl.blocks, pl.threads, 0, h->stream>>>(
+                m.nr, m.nt, m.np, coef, R, h->pJf.p, h->pJc.p, tw, twN, h->plam.p, rhs, psi);
         LAUNCH_CHECK();
         return;
     }

@@ -240,6 +240,7 @@ __host__ __device__ inline FftLineLaunch fft_line_launch(int nr, int nt, int np)
     return p;
 }
 
+template <int NMAX>
 __global__ void __launch_bounds__(kBlock) k_line_fft(int nr, int nt, int np, double coef, CRows R,
                                                      const double* __restrict__ Jf,
                                                      const double* __restrict__ Jc,
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(kBlock) k_line_fft(int nr, int nt, int np, dou
     if (!live) return;
     const int a = ring / nt, b = ring - a * nt;
     const double G = face_gdd(R, Jf, 2, a, b), J = Jc[ring];
-    wave_fft<double>(A, nh, tr, pl.tpr, twS, false);
+    wave_fft<double, NMAX>(A, nh, tr, pl.tpr, twS, false);
     // Mode pairs (m, nh - m), m <= nh / 2, one lane each: the two slots of
     // the half-length transform give the real modes X_m and X_{nh-m} (X_m =
     // E + twN[m] O, E and O the even and odd parts), each is divided by its
@@ -315,7 +316,7 @@ __global__ void __launch_bounds__(kBlock) k_line_fft(int nr, int nt, int np, dou
         if (k != m && k < nh) A[k] = half_seq(Yk, conjv(Ym), k);
     }
     wave_sync();
-    wave_fft<double>(A, nh, tr, pl.tpr, twS, true);
+    wave_fft<double, NMAX>(A, nh, tr, pl.tpr, twS, true);
     const double sc = 1.0 / nh;
     for (int j = tr; j < nh; j += pl.tpr) {
         Vec2<double> v = A[j];

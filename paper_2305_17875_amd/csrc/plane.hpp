@@ -50,6 +50,7 @@ constexpr int kPlaneLds = 1024; // complex values per LDS buffer (rings x length
 constexpr int kTriBlock = 64;
 constexpr int kTriBatch = 8;   // r-steps whose loads a lane issues together
 constexpr int kLdBatch = 4;    // ring positions whose loads a lane issues together
+constexpr int kSmallRing = 256; // ring-size class of the paper-scale shell
 
 // Orders the LDS accesses of the lanes of one wavefront (no block barrier).
 __device__ __forceinline__ void wave_sync()
@@ -65,17 +66,20 @@ __device__ __forceinline__ void wave_sync()
 // into registers before any lane writes, so one buffer serves; the lanes of
 // a ring are one wavefront, so the stages need no block barrier.  tw[q] =
 // exp(-2 pi i q / n) for q < n / 2 (in LDS); inverse: conjugate twiddles and
-// rotations, no scaling.
+// rotations, no scaling.  NMAX bounds n (the register staging of a stage
+// is sized for it: kernels are built for rings up to 256 and up to
+// kPlaneLds).
 //
 // A radix-4 stage of span Ls merges the four length-Ls transforms at block
 // offsets q n / 4 (q = 0..3, the residues q of the index mod 4 Ls / Ls) into
 // one of length 4 Ls: y_{j + p Ls} = sum_q (-i)^{pq} W^{qj} X_q[j],
 // W = exp(-2 pi i / (4 Ls)); W^{qj} = tw[q j n / (4 Ls)], and for an index
 // past n / 2, tw[s] = -tw[s - n / 2].
-template <typename T>
+template <typename T, int NMAX>
 __device__ void wave_fft(Vec2<T>* A, int n, int tr, int tpr, const Vec2<T>* tw, bool inverse)
 {
-    constexpr int kB2 = kPlaneLds / 128, kB4 = kPlaneLds / 256; // butterflies per lane
+    // butterflies per lane of a radix-2 and a radix-4 stage
+    constexpr int kB2 = NMAX / 128 > 0 ? NMAX / 128 : 1, kB4 = NMAX / 256 > 0 ? NMAX / 256 : 1;
     int Ls = 1;
     if (__builtin_ctz(n) & 1) {
         Vec2<T> u[kB2], v[kB2];
@@ -169,7 +173,7 @@ __host__ __device__ inline long long plane_pivot_offset(const Geo& g, int parity
 
 // Right-hand sides of the rings of parity k and their real transforms:
 // S[(a rows + bi)(nh + 1) + m], m = 0..nh.
-template <typename T>
+template <typename T, int NMAX>
 __global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict__ G, long long gk,
                                                       const T* __restrict__ bv,
                                                       const T* __restrict__ x, int parity,
@@ -230,7 +234,7 @@ __global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict
     }
     __syncthreads(); // twiddles of the block (the ring's values are wave-local)
     if (!live) return;
-    wave_fft<T>(A, nh, tr, pl.tpr, twS, false);
+    wave_fft<T, NMAX>(A, nh, tr, pl.tpr, twS, false);
     const Vec2<T>* Z = A;
     Vec2<T>* out = S + (long long)ring * (nh + 1);
     for (int m0 = tr; m0 <= nh; m0 += kLdBatch * pl.tpr) {
@@ -353,7 +357,7 @@ __global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restr
 }
 
 // Inverse transforms of the solved spectra into the rows of parity k.
-template <typename T>
+template <typename T, int NMAX>
 __global__ void __launch_bounds__(kBlock) k_plane_inv(Geo g, int parity,
                                                       const Vec2<T>* __restrict__ tw,
                                                       const Vec2<T>* __restrict__ twN,
@@ -402,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_plane_inv(Geo g, int parity,
     }
     __syncthreads(); // twiddles of the block (the ring's values are wave-local)
     if (!live) return;
-    wave_fft<T>(A, nh, tr, pl.tpr, twS, true);
+    wave_fft<T, NMAX>(A, nh, tr, pl.tpr, twS, true);
     const Vec2<T>* z = A;
     const int a = ring / pl.rows, bi = ring - a * pl.rows;
     const int b = 2 * bi + parity;
