@@ -72,6 +72,7 @@ def main():
     ap.add_argument("--top", type=int, default=16)
     ap.add_argument("--plane-md")
     ap.add_argument("--plane-traffic")
+    ap.add_argument("--step-md", help="projection step and ADI line-solve kernels")
     a = ap.parse_args()
     kh = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
     dur = durations(a.kt)
@@ -120,6 +121,33 @@ def main():
     print("\n".join(lines))
     if a.plane_md:
         plane_summary(a, dur, fe, wr, sf, sw)
+    if a.step_md:
+        step_summary(a, dur, fe, wr, sf, sw)
+
+
+STEP_KERNELS = ("k_divergence", "k_correct", "k_line_factor", "k_line_open", "k_line_fft",
+                "k_line_periodic")
+
+
+def step_summary(a, dur, fe, wr, sf, sw):
+    lines = ["# rocprofv3 summary: projection step and ADI line solves, spherical shell "
+             "192x256x512", "", "Same runs as the Gauss-Seidel summary (bench.py's `project` and "
+             "`lines` forms); commands:", "", "```", a.cmd, "```", "",
+             "Largest grid of each kernel, per launch:", "",
+             "| kernel | grid (threads) | launches | avg us | fetch MB | write MB |",
+             "|---|---|---|---|---|---|"]
+    for k in STEP_KERNELS:
+        names = sorted({n for (n, g) in dur if n.startswith(k + "<") or n == k})
+        for name in names:
+            g = max(gg for (n, gg) in dur if n == name)
+            d = dur[(name, g)]
+            f = mean(fe.get((name, g, "FETCH_SIZE"), [0.0])) * 1024 * sf
+            w = mean(wr.get((name, g, "WRITE_SIZE"), [0.0])) * 1024 * sw
+            lines.append(f"| `{name}` | {g} | {len(d)} | {mean(d) / 1e3:.1f} | "
+                         f"{f / 1e6:.1f} | {w / 1e6:.1f} |")
+    lines.append("")
+    open(a.step_md, "w").write("\n".join(lines))
+    print("\n".join(lines))
 
 
 def plane_summary(a, dur, fe, wr, sf, sw):
@@ -135,11 +163,11 @@ def plane_summary(a, dur, fe, wr, sf, sw):
     for prec in ("double", "float"):
         tot_us = tot_b = 0.0
         for k in PLANE_KERNELS:
-            name = f"{k}<{prec}>"
-            grids = [g for (n, g) in dur if n == name]
-            if not grids:
+            # k<prec> or k<prec, ring-size class>: the finest level's launch
+            cands = [(g, n) for (n, g) in dur if n == f"{k}<{prec}>" or n.startswith(f"{k}<{prec},")]
+            if not cands:
                 continue
-            g = max(grids)
+            g, name = max(cands)
             d = dur[(name, g)]
             f = mean(fe.get((name, g, "FETCH_SIZE"), [0.0])) * 1024 * sf
             w = mean(wr.get((name, g, "WRITE_SIZE"), [0.0])) * 1024 * sw
