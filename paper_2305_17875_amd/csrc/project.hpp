@@ -86,20 +86,23 @@ struct CRows {
 };
 
 // Launch shape of the per-cell kernels: a block is 4 theta rows x 64
-// consecutive phi cells of one r-plane; the linear block index is remapped
-// so that each of the 8 XCDs (which receive blocks round-robin) takes one
-// contiguous range of (plane, row group, phi segment), sharing the theta-
-// and r-neighbour rows in its own L2.
+// consecutive phi cells marching over a chunk of kProjChunk r-planes (each
+// thread keeps its own column's r-neighbours in registers); the linear block
+// index is remapped so that each of the 8 XCDs (which receive blocks
+// round-robin) takes one contiguous range of (chunk, row group, phi
+// segment), sharing the theta-neighbour rows in its own L2.
 constexpr int kProjRows = 4;
+constexpr int kProjChunk = 8;
 
-struct ProjCell {
-    int a, b, c;
+struct ProjCol {
+    int a0, a1, b, c;
     bool live;
 };
 
 __host__ __device__ inline long long proj_blocks(int nr, int nt, int np)
 {
-    return (long long)nr * ((nt + kProjRows - 1) / kProjRows) * ((np + 63) / 64);
+    return (long long)((nr + kProjChunk - 1) / kProjChunk) * ((nt + kProjRows - 1) / kProjRows) *
+           ((np + 63) / 64);
 }
 
 __host__ __device__ inline long long proj_grid(int nr, int nt, int np)
@@ -107,17 +110,21 @@ __host__ __device__ inline long long proj_grid(int nr, int nt, int np)
     return (proj_blocks(nr, nt, np) + 7) / 8 * 8;
 }
 
-__device__ inline ProjCell proj_cell(int nr, int nt, int np)
+__device__ inline ProjCol proj_col(int nr, int nt, int np)
 {
-    ProjCell p{0, 0, 0, false};
+    ProjCol p{0, 0, 0, 0, false};
     const long long nb = proj_blocks(nr, nt, np), per = (nb + 7) / 8;
     const long long lb = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (lb >= nb) return p;
     const int segs = (np + 63) / 64, groups = (nt + kProjRows - 1) / kProjRows;
     const int cs = (int)(lb % segs);
     const long long t = lb / segs;
-    p.a = (int)(t / groups);
-    p.b = (int)(t % groups) * kProjRows + (int)(threadIdx.x >> 6);
+    const int ch = (int)(t / groups);
+    p.a0 = ch * kProjChunk;
+    p.a1 = p.a0 + kProjChunk < nr ? p.a0 + kProjChunk : nr;
+    // the theta row is one per wavefront: made uniform so that the face
+    // tables (one row per (r, theta)) are read with scalar loads
+    p.b = __builtin_amdgcn_readfirstlane((int)(t % groups) * kProjRows + (int)(threadIdx.x >> 6));
     p.c = cs * 64 + (int)(threadIdx.x & 63);
     p.live = p.b < nt && p.c < np;
     return p;
@@ -143,17 +150,18 @@ __device__ __forceinline__ void crow(const CRows& R, int d, int a, int b, int c,
 }
 
 // rhs = d/ds_j [C_ji u_i]: per direction, flux through the high face minus
-// flux through the low face; a flux is C_d . (mean of the two cells' u)
+// flux through the low face; a flux is C_d . (mean of the two cells' u).
+// A thread marches its (b, c) column over a chunk of planes with u at a - 1,
+// a and a + 1 in registers (the load of a + 2 issued before a is computed).
 template <int SYM>
 __global__ void __launch_bounds__(kBlock) k_divergence(int nr, int nt, int np, CRows R,
                                                        const double* __restrict__ u,
                                                        double* __restrict__ rhs)
 {
-    const ProjCell pc = proj_cell(nr, nt, np);
-    if (!pc.live) return;
-    const int a = pc.a, b = pc.b, c = pc.c;
+    const ProjCol col = proj_col(nr, nt, np);
+    if (!col.live) return;
+    const int b = col.b, c = col.c;
     const long long N = (long long)nr * nt * np, plane = (long long)nt * np;
-    const long long row = (long long)a * nt + b, i = row * np + c;
     const int cm = c == 0 ? np - 1 : c - 1, cp = c == np - 1 ? 0 : c + 1;
     double s0 = 0.0, c0 = 1.0, s1 = 0.0, c1 = 1.0;
     if (SYM == kRotational) {
@@ -165,42 +173,86 @@ __global__ void __launch_bounds__(kBlock) k_divergence(int nr, int nt, int np, C
     const double* u0 = u;
     const double* u1 = u + N;
     const double* u2 = u + 2 * N;
-    auto flux = [&](int d, int fa, int fb, int fc, long long ihi, long long ilo, double cs,
-                    double sn) {
+    const long long col0 = (long long)b * np + c;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool whole = np <= 64; // the ring is the wavefront's lanes 0 .. np-1
+    const int lane_lo = whole ? cm : lane - 1, lane_hi = whole ? cp : lane + 1;
+    const bool shfl_lo = whole || lane > 0, shfl_hi = whole || (lane < 63 && c + 1 < np);
+    auto load = [&](int a, double v[3]) {
+        const long long i = a * plane + col0;
+        v[0] = u0[i];
+        v[1] = u1[i];
+        v[2] = u2[i];
+    };
+    auto flux = [&](int d, int fa, int fb, int fc, const double hi[3], const double lo[3],
+                    double cs, double sn) {
         double C[3];
         crow<SYM>(R, d, fa, fb, fc, cs, sn, C);
         double U = 0.0;
-        U += C[0] * (0.5 * (u0[ihi] + u0[ilo]));
-        U += C[1] * (0.5 * (u1[ihi] + u1[ilo]));
-        U += C[2] * (0.5 * (u2[ihi] + u2[ilo]));
+        U += C[0] * (0.5 * (hi[0] + lo[0]));
+        U += C[1] * (0.5 * (hi[1] + lo[1]));
+        U += C[2] * (0.5 * (hi[2] + lo[2]));
         return U;
     };
-    const double r_lo = a > 0 ? flux(0, a, b, c, i, i - plane, c0, s0) : 0.0;
-    const double r_hi = a < nr - 1 ? flux(0, a + 1, b, c, i + plane, i, c0, s0) : 0.0;
-    const double t_lo = b > 0 ? flux(1, a, b, c, i, i - np, c0, s0) : 0.0;
-    const double t_hi = b < nt - 1 ? flux(1, a, b + 1, c, i + np, i, c0, s0) : 0.0;
-    const double p_lo = flux(2, a, b, c, i, i - c + cm, c0, s0);
-    const double p_hi = flux(2, a, b, cp, i - c + cp, i, c1, s1);
-    double s = 0.0;
-    s += r_hi - r_lo;
-    s += t_hi - t_lo;
-    s += p_hi - p_lo;
-    rhs[i] = s;
+    double um[3] = {0.0, 0.0, 0.0}, uc[3], up[3] = {0.0, 0.0, 0.0};
+    if (col.a0 > 0) load(col.a0 - 1, um);
+    load(col.a0, uc);
+    if (col.a0 + 1 < nr) load(col.a0 + 1, up);
+    for (int a = col.a0; a < col.a1; ++a) {
+        double un[3] = {0.0, 0.0, 0.0};
+        if (a + 2 < nr && a + 1 < col.a1) load(a + 2, un);
+        const long long i = a * plane + col0;
+        double nb[3], v[3];
+        const double r_lo = a > 0 ? flux(0, a, b, c, uc, um, c0, s0) : 0.0;
+        const double r_hi = a < nr - 1 ? flux(0, a + 1, b, c, up, uc, c0, s0) : 0.0;
+        double t_lo = 0.0, t_hi = 0.0;
+        if (b > 0) {
+            v[0] = u0[i - np]; v[1] = u1[i - np]; v[2] = u2[i - np];
+            t_lo = flux(1, a, b, c, uc, v, c0, s0);
+        }
+        if (b < nt - 1) {
+            v[0] = u0[i + np]; v[1] = u1[i + np]; v[2] = u2[i + np];
+            t_hi = flux(1, a, b + 1, c, v, uc, c0, s0);
+        }
+        // phi-neighbours: the adjacent lanes' own values where they hold
+        // them (the ring fits the wavefront, or the neighbour is in this
+        // 64-cell segment), else loaded
+        for (int q = 0; q < 3; ++q) nb[q] = __shfl(uc[q], lane_lo);
+        if (!shfl_lo) {
+            nb[0] = u0[i - c + cm]; nb[1] = u1[i - c + cm]; nb[2] = u2[i - c + cm];
+        }
+        const double p_lo = flux(2, a, b, c, uc, nb, c0, s0);
+        for (int q = 0; q < 3; ++q) nb[q] = __shfl(uc[q], lane_hi);
+        if (!shfl_hi) {
+            nb[0] = u0[i - c + cp]; nb[1] = u1[i - c + cp]; nb[2] = u2[i - c + cp];
+        }
+        const double p_hi = flux(2, a, b, cp, nb, uc, c1, s1);
+        double s = 0.0;
+        s += r_hi - r_lo;
+        s += t_hi - t_lo;
+        s += p_hi - p_lo;
+        rhs[i] = s;
+        for (int q = 0; q < 3; ++q) {
+            um[q] = uc[q];
+            uc[q] = up[q];
+            up[q] = un[q];
+        }
+    }
 }
 
 // u_q <- u_q - (1/|J^-1|) sum over the six faces of +-C_dq (face mean of
-// phi); phi is mirrored on the r- and theta-walls
+// phi); phi is mirrored on the r- and theta-walls.  Marches like
+// k_divergence with phi at a - 1, a and a + 1 in registers.
 template <int SYM>
 __global__ void __launch_bounds__(kBlock) k_correct(int nr, int nt, int np, CRows R,
                                                     const double* __restrict__ Jc,
                                                     const double* __restrict__ phi,
                                                     double* __restrict__ u)
 {
-    const ProjCell cell = proj_cell(nr, nt, np);
-    if (!cell.live) return;
-    const int a = cell.a, b = cell.b, c = cell.c;
+    const ProjCol col = proj_col(nr, nt, np);
+    if (!col.live) return;
+    const int b = col.b, c = col.c;
     const long long N = (long long)nr * nt * np, plane = (long long)nt * np;
-    const long long row = (long long)a * nt + b, i = row * np + c;
     const int cm = c == 0 ? np - 1 : c - 1, cp = c == np - 1 ? 0 : c + 1;
     double s0 = 0.0, c0 = 1.0, s1 = 0.0, c1 = 1.0;
     if (SYM == kRotational) {
@@ -209,23 +261,34 @@ __global__ void __launch_bounds__(kBlock) k_correct(int nr, int nt, int np, CRow
         c1 = R.rot[2 * c + 2];
         s1 = R.rot[2 * c + 3];
     }
-    const double pc = phi[i];
-    double g[3] = {0.0, 0.0, 0.0};
-    auto face = [&](int d, int fa, int fb, int fc, long long io, double sign, double cs,
-                    double sn) {
-        double C[3];
-        crow<SYM>(R, d, fa, fb, fc, cs, sn, C);
-        const double pf = 0.5 * (pc + phi[io]);
-        for (int q = 0; q < 3; ++q) g[q] += sign * C[q] * pf;
-    };
-    face(0, a, b, c, a > 0 ? i - plane : i, -1.0, c0, s0);
-    face(0, a + 1, b, c, a < nr - 1 ? i + plane : i, 1.0, c0, s0);
-    face(1, a, b, c, b > 0 ? i - np : i, -1.0, c0, s0);
-    face(1, a, b + 1, c, b < nt - 1 ? i + np : i, 1.0, c0, s0);
-    face(2, a, b, c, i - c + cm, -1.0, c0, s0);
-    face(2, a, b, cp, i - c + cp, 1.0, c1, s1);
-    const double J = Jc[SYM == kPerCell ? i : row];
-    for (int q = 0; q < 3; ++q) u[q * N + i] = u[q * N + i] - g[q] / J;
+    const long long col0 = (long long)b * np + c;
+    double pm = 0.0, pc = phi[col.a0 * plane + col0], pp = 0.0;
+    if (col.a0 > 0) pm = phi[(col.a0 - 1) * plane + col0];
+    if (col.a0 + 1 < nr) pp = phi[(col.a0 + 1) * plane + col0];
+    for (int a = col.a0; a < col.a1; ++a) {
+        double pn = 0.0;
+        if (a + 2 < nr && a + 1 < col.a1) pn = phi[(a + 2) * plane + col0];
+        const long long i = a * plane + col0;
+        double g[3] = {0.0, 0.0, 0.0};
+        auto face = [&](int d, int fa, int fb, int fc, double po, double sign, double cs,
+                        double sn) {
+            double C[3];
+            crow<SYM>(R, d, fa, fb, fc, cs, sn, C);
+            const double pf = 0.5 * (pc + po);
+            for (int q = 0; q < 3; ++q) g[q] += sign * C[q] * pf;
+        };
+        face(0, a, b, c, a > 0 ? pm : pc, -1.0, c0, s0);
+        face(0, a + 1, b, c, a < nr - 1 ? pp : pc, 1.0, c0, s0);
+        face(1, a, b, c, b > 0 ? phi[i - np] : pc, -1.0, c0, s0);
+        face(1, a, b + 1, c, b < nt - 1 ? phi[i + np] : pc, 1.0, c0, s0);
+        face(2, a, b, c, phi[i - c + cm], -1.0, c0, s0);
+        face(2, a, b, cp, phi[i - c + cp], 1.0, c1, s1);
+        const double iJ = 1.0 / Jc[SYM == kPerCell ? i : (long long)a * nt + b];
+        for (int q = 0; q < 3; ++q) u[q * N + i] = u[q * N + i] - g[q] * iJ;
+        pm = pc;
+        pc = pp;
+        pp = pn;
+    }
 }
 
 } // namespace cps
