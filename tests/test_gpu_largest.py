@@ -1,0 +1,43 @@
+"""The paper's largest grid: 256 (r) x 512 (theta) x 512 (phi) = 67.1 M
+cells with tanh clustering 2.0 (a 7-level hierarchy, ~7.4 GB in FP64).
+FP64 solves with the point and the plane smoother reach relative residual
+1e-10; the check is the oracle's own FP64 residual of the GPU answer and the
+zero mean, properties that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_17875_amd import cps, inputs
+from paper_2305_17875_amd.inputs import Shell
+from gpu_util import needs_gpu, log, dev, host, torch
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.fixture(scope="module")
+def largest():
+    g = Shell(256, 512, 512, radial_stretch=2.0)
+    log("largest grid oracle setup", g.shape)
+    b = inputs.smoothed_noise(g.shape, 7)
+    G = O.face_metrics(g)
+    return g, b, G
+
+
+@pytest.mark.parametrize("smoother", [0, 1], ids=["point", "plane"])
+def test_largest_grid_solve(largest, smoother):
+    g, b, G = largest
+    log("largest grid solve, smoother", smoother)
+    s = cps.Solver(g, precision=0, accel=1, max_iters=400, smoother=smoother)
+    try:
+        assert len(s.levels) == 7
+        res = s.solve(dev(b).flatten(), tol=1e-10)
+        x = host(res.p).reshape(g.shape)
+    finally:
+        s.close()
+        torch.cuda.empty_cache()
+    log("largest grid iterations", res.iterations, "rel", res.rel_residual)
+    assert res.status == cps.CPS_OK and res.rel_residual <= 1e-10
+    bb = b - b.mean()
+    r = O.residual(G, bb, x)
+    assert np.linalg.norm(r) <= 1.5e-10 * np.linalg.norm(bb)
+    assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
