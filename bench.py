@@ -14,7 +14,7 @@ the ADI steps under `lines`.  Prints one JSON line.
 
 Roofline: the dominant kernel is the finest-level Gauss-Seidel colour pass.
 Its duration is measured live with HIP events recorded on the solve stream
-around every finest-level launch in the timed region.  `traffic` comes from
+around each of its launches in the timed region.  `traffic` comes from
 profiles/gs_pass_config2_traffic.json (FETCH_SIZE / WRITE_SIZE counter runs,
 scaled by the same counters on a plain copy of known size) when that file
 was taken on the current kernel source, else null.
@@ -109,14 +109,27 @@ def plane_half_sweep_bytes(shape, word):
     return (2 * half + spec + 4 * spec + 2 * piv + spec + half) * word
 
 
+PROF_STEPS = 2
+
+
 def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
-    s = cps.Solver(g, precision=precision, accel=1, max_iters=400, smoother=smoother)
+    """The timed solves run on a stream of the solver's own, as a user would
+    set it up.  Inside the timed region HIP events are recorded on that
+    stream around every launch of the finest-level smoothing pass only (the
+    roofline's kernel; events around every class would add ~6% to the
+    solve); PROF_STEPS more solves with events around every finest-level
+    class give the kernel table and the V-cycle span."""
+    stream = torch.cuda.Stream()
+    s = cps.Solver(g, precision=precision, accel=1, max_iters=400, smoother=smoother,
+                   stream=stream)
     p = torch.empty_like(rhs)
+    torch.cuda.synchronize()
     for i in range(warmup):
         res = s.solve(rhs, TOL, out=p)
         log(f"warmup {i}: status={res.status} iterations={res.iterations} "
             f"{res.seconds * 1e3:.1f} ms")
     torch.cuda.synchronize()
+    cps.cps_profile_select(s.h, [cps.KERNEL_GS])
     cps.cps_profile_enable(s.h, True)
     t0 = time.perf_counter()
     iters = []
@@ -125,11 +138,19 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
         iters.append(res.iterations)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    timed_gs = cps.cps_profile_read(s.h, cps.KERNEL_GS)
+    cps.cps_profile_select(s.h, None)
+    for k in range(len(KNAMES)):
+        cps.cps_profile_read(s.h, k)
+    for i in range(PROF_STEPS):
+        s.solve(rhs, TOL, out=p)
     prof = {k: cps.cps_profile_read(s.h, k) for k in range(len(KNAMES))}
     cps.cps_profile_enable(s.h, False)
+    torch.cuda.synchronize()
     log(f"precision={precision} smoother={smoother}: {dt * 1e3:.1f} ms/solve, iterations={iters}, "
         f"rel_residual={res.rel_residual:.3e}")
-    return dict(solver=s, p=p, res=res, sec=dt, iters=iters, prof=prof)
+    return dict(solver=s, p=p, res=res, sec=dt, iters=iters, prof=prof, prof_steps=PROF_STEPS,
+                timed_gs=timed_gs)
 
 
 def kernel_table(prof, steps):
@@ -179,7 +200,7 @@ def plane_form(cps, torch, g, rhs, x64, steps, warmup):
                        "Thomas along r per mode; V(2,2), PCG"}
     for precision, key, word in ((0, "fp64", 8), (1, "mixed", 4)):
         f = run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=1)
-        hs_ms, hs_n = f["prof"][cps.KERNEL_GS]
+        hs_ms, hs_n = f["timed_gs"]  # HIP events over the timed region
         hs_s = hs_ms / max(hs_n, 1) * 1e-3
         hb = plane_half_sweep_bytes(g.shape, word)
         err = float(torch.linalg.norm(f["p"] - x64) / torch.linalg.norm(x64))
@@ -190,7 +211,7 @@ def plane_form(cps, torch, g, rhs, x64, steps, warmup):
                                    "algorithmic_bytes": hb, "achieved_GBs": hb / hs_s / 1e9,
                                    "frac_of_peak": hb / hs_s / 1e9 / HBM_PEAK_GBS,
                                    "traffic": plane_traffic("fp64" if precision == 0 else "fp32")},
-                    "kernels": kernel_table(f["prof"], steps)}
+                    "kernels": kernel_table(f["prof"], f["prof_steps"])}
         f["solver"].close()
         del f
         torch.cuda.empty_cache()
@@ -211,14 +232,15 @@ def project_form(cps, torch, inputs, g, steps, warmup):
     out = {"workload": "u*** = three smoothed N(0,1) fields (seeds 40-42) as Cartesian "
                        "components on the paper-scale shell; tol 1e-10"}
     for key, smoother in (("fp64_point", 0), ("fp64_plane", 1)):
-        s = cps.Solver(g, precision=0, accel=1, max_iters=400, smoother=smoother)
+        stream = torch.cuda.Stream()
+        s = cps.Solver(g, precision=0, accel=1, max_iters=400, smoother=smoother, stream=stream)
         u = torch.empty_like(u0)
         phi = torch.empty(n, dtype=torch.float64, device="cuda")
         for _ in range(warmup):
             u.copy_(u0)
+            torch.cuda.synchronize()
             s.project(u, TOL, phi=phi)
         torch.cuda.synchronize()
-        cps.cps_profile_enable(s.h, True)
         total, its = 0.0, []
         for _ in range(steps):
             u.copy_(u0)
@@ -228,6 +250,10 @@ def project_form(cps, torch, inputs, g, steps, warmup):
             torch.cuda.synchronize()
             total += time.perf_counter() - t0
             its.append(r.iterations)
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        cps.cps_profile_enable(s.h, True)
+        s.project(u, TOL, phi=phi)
         prof = {k: cps.cps_profile_read(s.h, k) for k in range(len(KNAMES))}
         cps.cps_profile_enable(s.h, False)
         dt = total / steps
@@ -554,7 +580,7 @@ def main():
 
     f64 = run_form(cps, torch, g, rhs, 0, a.steps, a.warmup)
     s64 = f64["solver"]
-    gs_ms, gs_n = f64["prof"][cps.KERNEL_GS]
+    gs_ms, gs_n = f64["timed_gs"]  # HIP events over the timed region
     avg_gs_s = gs_ms / max(gs_n, 1) * 1e-3
     nterms = {2: 3, 4: 5}[s64.ncolours] if s64.phi_invariant else 9
     gs_bytes = gs_bytes_per_launch(g.shape, s64.ncolours, 8, s64.phi_invariant, nterms)
@@ -585,7 +611,7 @@ def main():
                                "the zero-iterate first pass of a cycle is a kernel of its own)",
                      "avg_us": avg_gs_s * 1e6, "algorithmic_bytes": gs_bytes,
                      "kernel_source_sha256_16": kh, "copy_yardstick_GBs": copy_gbs},
-        "kernels_fp64": kernel_table(f64["prof"], a.steps),
+        "kernels_fp64": kernel_table(f64["prof"], f64["prof_steps"]),
         "vcycle_fp64": vcycle_rate(f64["prof"], s64.levels, 8),
     }
     x64 = f64["p"]
@@ -595,7 +621,7 @@ def main():
         line["mixed"] = {"value": n / mx["sec"], "ms_per_step": mx["sec"] * 1e3,
                          "iterations": mx["iters"][-1], "rel_residual": mx["res"].rel_residual,
                          "rel_diff_vs_fp64": err, "dtype": "f32 V-cycles, f64 outer",
-                         "kernels": kernel_table(mx["prof"], a.steps),
+                         "kernels": kernel_table(mx["prof"], mx["prof_steps"]),
                          "vcycle": vcycle_rate(mx["prof"], mx["solver"].levels, 4)}
         mx["solver"].close()
         del mx

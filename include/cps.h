@@ -320,8 +320,10 @@ void cps_service_destroy(cps_service* s);
 
 /* ---- Measurement -------------------------------------------------------
  * Kernel classes timed on the finest level with HIP events recorded on the
- * handle's stream around each launch (the colour class leaves out the
- * zero-iterate first pass of a cycle, which moves fewer bytes). */
+ * handle's stream around each launch; the point smoother's full colour
+ * passes of one smoothing call run back to back and are timed as one span
+ * over their launches (the colour class leaves out the zero-iterate first
+ * pass of a cycle, which moves fewer bytes). */
 enum {
     CPS_KERNEL_GS = 0,       /* one Gauss-Seidel colour pass */
     CPS_KERNEL_RESIDUAL = 1, /* r = b - A x (+ norm partials) */
@@ -336,6 +338,9 @@ enum {
 };
 /* enable != 0 starts recording (and clears earlier records). */
 cps_status cps_profile_enable(cps_handle* h, int32_t enable);
+/* Record only the classes whose bit (1 << class) is set in class_mask
+ * (default: all): fewer events around the launches of interest. */
+cps_status cps_profile_select(cps_handle* h, uint32_t class_mask);
 /* Synchronises the stream; *total_ms (host) = summed duration of the
  * recorded launches of the class, *launches = their count; then clears. */
 cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_ms,

@@ -118,13 +118,15 @@ def lib():
         L.cps_service_destroy.argtypes = [P]
         L.cps_service_destroy.restype = None
         L.cps_profile_enable.argtypes = [P, I]
+        L.cps_profile_select.argtypes = [P, ctypes.c_uint32]
         L.cps_profile_read.argtypes = [P, I, P, P]
         L.cps_debug_copy.argtypes = [P, P, ctypes.c_int64, P]
         L.cps_divergence.argtypes = [P, P, P]
         L.cps_correct.argtypes = [P, P, P]
         L.cps_project.argtypes = [P, P, P, D, P]
         L.cps_line_solve.argtypes = [P, I, D, P, P, P]
-        for f in ("cps_divergence", "cps_correct", "cps_project", "cps_line_solve", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
+        for f in ("cps_divergence", "cps_correct", "cps_project", "cps_line_solve",
+                  "cps_profile_select", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
                   "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
                   "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
                   "cps_debug_coarse_solve", "cps_debug_vcycle", "cps_debug_plane_sweep"):
@@ -317,6 +319,12 @@ KERNEL_GS, KERNEL_RESIDUAL, KERNEL_APPLY, KERNEL_RESTRICT, KERNEL_PROLONG, KERNE
 
 def cps_profile_enable(h, enable: bool):
     _check(lib().cps_profile_enable(h, 1 if enable else 0))
+
+
+def cps_profile_select(h, classes=None):
+    """Record only these kernel classes (None: all)."""
+    mask = 0xFFFFFFFF if classes is None else sum(1 << c for c in classes)
+    _check(lib().cps_profile_select(h, mask))
 
 
 def cps_profile_read(h, kernel_class: int):

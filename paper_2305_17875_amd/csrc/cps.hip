@@ -197,8 +197,10 @@ struct cps_handle {
     hipGraphExec_t gexec[4] = {};
     // optional HIP-event timing of the finest-level kernels, per class
     bool prof = false;
+    uint32_t prof_mask = ~0u; // kernel classes recorded while prof is on
     std::vector<hipEvent_t> ev[CPS_KERNEL_CLASSES];
     size_t ev_used[CPS_KERNEL_CLASSES] = {};
+    int64_t ev_launches[CPS_KERNEL_CLASSES] = {}; // launches the recorded spans cover
 };
 
 namespace {
@@ -241,13 +243,16 @@ float* rl<float>(cps_handle* h, int l) { return h->lv[l].r32.p; }
 
 // Brackets one finest-level launch of kernel class k with two events on the
 // handle's stream (no-op unless profiling is enabled).
+// One event pair around `count` consecutive launches of class k on the
+// finest level (k < 0: not recorded).
 struct ProfScope {
     cps_handle* h;
     int k;
     hipEvent_t stop = nullptr;
-    ProfScope(cps_handle* hh, int kk, int level) : h(hh), k(kk)
+    ProfScope(cps_handle* hh, int kk, int level, int count = 1) : h(hh), k(kk)
     {
-        if (!h->prof || level != 0 || k < 0) return;
+        if (!h->prof || level != 0 || k < 0 || count < 1 || !((h->prof_mask >> k) & 1u)) return;
+        h->ev_launches[k] += count;
         auto& v = h->ev[k];
         size_t& u = h->ev_used[k];
         while (v.size() < u + 2) {
@@ -285,14 +290,15 @@ inline bool marching(const cps_handle* h) { return h->mode == MODE_ORTHO && h->a
 // updated cells, written at dot[0 .. grid); returns the number written.
 template <typename T>
 long long gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero = false,
-                  double* dot = nullptr)
+                  double* dot = nullptr, bool grouped = false)
 {
     const Level<T> L = view<T>(h, l);
     const int rowlen = h->ncol == 2 ? L.g.rowlen : L.g.rowlen / 2;
     const int bpa = (int)nblk(rowlen);
     const int z = zero ? 1 : 0;
-    // the zero-iterate first pass moves fewer bytes: not in the GS class
-    ProfScope ps(h, zero ? -1 : CPS_KERNEL_GS, l);
+    // the zero-iterate first pass moves fewer bytes: not in the GS class;
+    // grouped: timed with its neighbours by the caller
+    ProfScope ps(h, zero || grouped ? -1 : CPS_KERNEL_GS, l);
     if (marching(h)) {
         const MarchShape ms = stencil_shape(L.g, h->lv[l].gs_ch);
         if (row_pairs(L.g)) {
@@ -406,13 +412,17 @@ long long smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool revers
     if (from_zero && !skip) fill<T>(h, x, h->lv[l].n, T(0));
     long long parts = 0;
     const int last = sweeps * h->ncol;
-    for (int s = 0; s < sweeps; ++s)
-        for (int k = 0; k < h->ncol; ++k) {
-            const int pass = s * h->ncol + k;
-            const bool with_dot = dot && h->ncol == 2 && pass >= last - 2;
-            parts += gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x, skip && pass == 0,
-                                with_dot ? dot + parts : nullptr);
-        }
+    auto pass_at = [&](int pass) {
+        const int k = pass % h->ncol;
+        const bool with_dot = dot && h->ncol == 2 && pass >= last - 2;
+        parts += gs_pass<T>(h, l, reverse ? h->ncol - 1 - k : k, b, x, skip && pass == 0,
+                            with_dot ? dot + parts : nullptr, !(skip && pass == 0));
+    };
+    const int first = skip ? 1 : 0;
+    if (skip) pass_at(0);
+    // the full passes run back to back: one event pair around all of them
+    ProfScope ps(h, CPS_KERNEL_GS, l, last - first);
+    for (int pass = first; pass < last; ++pass) pass_at(pass);
     return parts;
 }
 
@@ -1667,6 +1677,15 @@ cps_status cps_profile_enable(cps_handle* h, int32_t enable)
         if (!h) fail(CPS_E_INVALID, "handle is NULL");
         h->prof = enable != 0;
         for (auto& u : h->ev_used) u = 0;
+        for (auto& c : h->ev_launches) c = 0;
+    });
+}
+
+cps_status cps_profile_select(cps_handle* h, uint32_t class_mask)
+{
+    return guarded([&] {
+        if (!h) fail(CPS_E_INVALID, "handle is NULL");
+        h->prof_mask = class_mask;
     });
 }
 
@@ -1686,8 +1705,9 @@ cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_m
             tot += ms;
         }
         if (total_ms) *total_ms = tot;
-        if (launches) *launches = (int64_t)(u / 2);
+        if (launches) *launches = h->ev_launches[kernel_class];
         h->ev_used[kernel_class] = 0;
+        h->ev_launches[kernel_class] = 0;
     });
 }
 
