@@ -424,7 +424,7 @@ class OutPool:
             self.free.setdefault(a.shape, []).append(a)
 
 
-def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator):
+def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoother=2):
     """Poisson arrivals at `rate`/s for `duration` s submitted in real time
     to the solve service (FP32 V-cycles in FP64 refinement, hierarchies kept
     resident); then, if asked, the same stream served one request at a time
@@ -434,7 +434,8 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator):
     arr = inputs.arrival_stream(rate=rate, duration=duration)
     pool = rhs_pool(inputs, inputs.SIZE_SET, 4)
     demand = sum(a.problem.grid.cells for a in arr) / duration
-    svc = cps.Service(budget_gib * (1 << 30), max_slots=slots, precision=1, accel=1)
+    svc = cps.Service(budget_gib * (1 << 30), max_slots=slots, precision=1, accel=1,
+                      smoother=smoother)
     # warm the code paths once per (size, class) so that start-up compiles
     # and tuning are not in the measured stream
     outs = OutPool()
@@ -491,6 +492,9 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator):
            "map_rebuilds": st["map_rebuilds"] - base["map_rebuilds"],
            "evictions": st["evictions"] - base["evictions"],
            "dtype": "f32 V-cycles, f64 outer",
+           "smoother": {0: "point red-black", 1: "zebra plane",
+                        2: "automatic: zebra plane where the hierarchy allows it (spheres), "
+                           "point red-black otherwise (oblate shells)"}[smoother],
            "workload": f"Poisson arrivals {rate}/s for {duration} s (seed 5), sizes uniform over "
                        "16^3, 32^3, 64x64x128, 96x128x256, 128x128x256, sphere or oblate "
                        "f~U(0,0.15); rhs from 4 smoothed N(0,1) fields per size; tol 1e-10; "
@@ -559,6 +563,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-smoother", type=int, default=2,
+                    help="0 point, 1 plane, 2 automatic (plane where the hierarchy allows it)")
     ap.add_argument("--no-serve-comparator", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -641,7 +647,7 @@ def main():
         torch.cuda.empty_cache()
     if not a.no_serve:
         line["serve"] = serve_form(cps, inputs, a.serve_seconds, a.serve_rate, a.serve_slots,
-                                   64, not a.no_serve_comparator)
+                                   64, not a.no_serve_comparator, a.serve_smoother)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(g, rhs_np, gpu_iters)

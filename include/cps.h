@@ -108,7 +108,10 @@ typedef struct {
                           radial and cone-tip anisotropy.  Needs the 7-point
                           operator with phi-invariant metrics (identity box,
                           sphere) and n_phi a power of two in [4, 2048] on
-                          every smoothed level. */
+                          every smoothed level;
+                          2: automatic -- 1 where the hierarchy allows it,
+                          else 0 (decided at set-up; the batched form takes 0
+                          only). */
     void* stream;      /* hipStream_t the calls are ordered on; NULL = null stream */
 } cps_opts;
 

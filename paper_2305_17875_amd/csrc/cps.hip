@@ -727,7 +727,7 @@ void validate_opts(const cps_opts* o)
     if (o && (o->accel < 0 || o->accel > 2)) fail(CPS_E_INVALID, "bad accel");
     if (o && (o->tune < 0 || o->tune > 2)) fail(CPS_E_INVALID, "bad tune");
     if (o && (o->eager < 0 || o->eager > 1)) fail(CPS_E_INVALID, "bad eager");
-    if (o && (o->smoother < 0 || o->smoother > 1)) fail(CPS_E_INVALID, "bad smoother");
+    if (o && (o->smoother < 0 || o->smoother > 2)) fail(CPS_E_INVALID, "bad smoother");
 }
 
 void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
@@ -895,6 +895,19 @@ int checked_plan(const cps_grid& g, int dims[kMaxLevels][3])
     return L;
 }
 
+// The plane smoother applies: the 7-point operator with phi-invariant
+// metrics, and n_phi / 2 a power of two in [2, kPlaneLds] on every smoothed
+// level.
+bool plane_eligible(const cps_handle* h)
+{
+    if (!marching(h)) return false;
+    for (int l = 0; l + 1 < h->L; ++l) {
+        const int nh = h->lv[l].np / 2;
+        if (nh < 2 || nh > kPlaneLds || (nh & (nh - 1))) return false;
+    }
+    return true;
+}
+
 // Tables and scratch of the plane smoother (7-point, phi-invariant
 // hierarchies whose smoothed levels have power-of-two rings of <= 2048).
 void setup_plane(cps_handle* h)
@@ -995,6 +1008,7 @@ void build(cps_handle* h)
         h->r0.alloc(n0); h->v.alloc(n0); h->s.alloc(n0); h->t.alloc(n0);
         h->sh.alloc(n0);
     }
+    if (h->opts.smoother == 2) h->opts.smoother = plane_eligible(h) ? 1 : 0; // automatic
     if (h->opts.smoother == 1) setup_plane(h);
     autotune(h, h->opts.tune);
     HIPC(hipStreamSynchronize(h->stream));

@@ -101,7 +101,13 @@ size_t estimate_bytes(const cps_grid& g, const cps_opts& o)
     const size_t n0 = (size_t)g.n_r * g.n_theta * g.n_phi;
     const size_t nc = (size_t)dims[L - 1][0] * dims[L - 1][1] * dims[L - 1][2];
     s += n0 * 8 * (3 + 2 + (o.accel >= 1 ? 4 : 0) + (o.accel == 2 ? 5 : 0));
-    if (o.smoother == 1) { // spectra of one parity, pivots of every smoothed level, tables
+    bool plane_dims = L > 1;
+    for (int l = 0; l + 1 < L; ++l) {
+        const int nh = dims[l][2] / 2;
+        plane_dims = plane_dims && nh >= 2 && nh <= kPlaneLds && (nh & (nh - 1)) == 0;
+    }
+    if (o.smoother == 1 || (o.smoother == 2 && plane_dims)) {
+        // spectra of one parity, pivots of every smoothed level, tables
         const size_t w = mixed ? 4 : 8;
         s += (size_t)dims[0][0] * ((dims[0][1] + 1) / 2) * (dims[0][2] / 2 + 1) * 2 * w +
              (size_t)L * (2 * dims[0][2] + 8) * 8 * 2;

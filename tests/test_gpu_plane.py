@@ -143,3 +143,37 @@ def test_service_with_plane_smoother_recomputes_pivots_on_remap():
     assert st["hierarchies_built"] == 1 and st["hierarchies_reused"] == 2, st
     assert st["map_rebuilds"] == 2, st
     assert 0 < st["hbm_in_use"] <= fp, (st["hbm_in_use"], fp)
+
+
+def test_automatic_smoother_in_the_service():
+    """smoother = 2: a sphere's hierarchy takes the plane smoother, an oblate
+    shell's (cross terms) the point smoother; each result equals the same
+    problem solved alone with the same opts, bit for bit, and the sphere
+    needs fewer cycles than with the point smoother."""
+    reqs = [(Shell(16, 16, 32, radial_stretch=2.0), inputs.smoothed_noise((16, 16, 32), 70)),
+            (Shell(16, 16, 32, map=MAP_OBLATE, flattening=0.1),
+             inputs.smoothed_noise((16, 16, 32), 71)),
+            (Shell(32, 32, 64, radial_stretch=2.0), inputs.smoothed_noise((32, 32, 64), 72))]
+    log("automatic smoother service")
+    svc = cps.Service(1 << 30, max_slots=2, precision=1, smoother=2)
+    try:
+        out = [svc.wait(svc.submit(g, b)) for g, b in reqs]
+    finally:
+        svc.close()
+    for i, ((g, b), (status, p, info)) in enumerate(zip(reqs, out)):
+        assert status == cps.CPS_OK, i
+        its = {}
+        for sm in (2, 0):
+            s = cps.Solver(g, precision=1, accel=1, smoother=sm)
+            try:
+                r = s.solve(dev(b).flatten())
+                its[sm] = r.iterations
+                if sm == 2:
+                    assert np.array_equal(p, host(r.p).reshape(g.shape)), i
+                    assert info.iterations == r.iterations, i
+            finally:
+                s.close()
+        if g.map == MAP_OBLATE:
+            assert its[2] == its[0], its
+        else:
+            assert 3 * its[2] <= its[0], its
