@@ -167,3 +167,32 @@ def test_graph_replays_equal_eager_solves(name, g, accel, precision):
     finally:
         sg.close()
         se.close()
+
+
+def test_profile_classes_and_grouped_colour_passes():
+    """cps_profile_select/enable/read: with only the colour class selected,
+    every outer iteration's V(2,2) cycle contributes its 7 full finest-level
+    colour passes (the zero-iterate first pass is not in the class), timed as
+    spans over back-to-back passes; the other classes record nothing; the
+    profiled solve gives the same bits as an unprofiled one."""
+    g = Shell(16, 16, 32, radial_stretch=2.0)
+    b = dev(inputs.smoothed_noise(g.shape, 13)).flatten()
+    s = cps.Solver(g, precision=0, accel=1)
+    try:
+        x0 = host(s.solve(b).p)
+        cps.cps_profile_select(s.h, [cps.KERNEL_GS])
+        cps.cps_profile_enable(s.h, True)
+        r = s.solve(b)
+        ms, n = cps.cps_profile_read(s.h, cps.KERNEL_GS)
+        others = [cps.cps_profile_read(s.h, k)[1] for k in range(1, 8)]
+        cps.cps_profile_select(s.h, None)
+        r2 = s.solve(b)
+        vms, vn = cps.cps_profile_read(s.h, cps.KERNEL_VCYCLE)
+        cps.cps_profile_enable(s.h, False)
+        x1 = host(r.p)
+    finally:
+        s.close()
+    assert n == 7 * r.iterations and ms > 0, (n, r.iterations)
+    assert others == [0] * 7, others
+    assert vn == r2.iterations and vms > 0
+    assert np.array_equal(x0, x1)
