@@ -896,11 +896,13 @@ void orc_correct(const og_grid* g, int nr, int nt, int np, int method, const dou
 
 typedef struct { int type_lo, type_hi; double v_lo, v_hi; } og_line_bc;
 
+/* A face of zero area (the pole faces of a full sphere, theta0 = 0 or
+ * theta1 = pi) carries no flux: G_dd = 0 there. */
 static double og_face_gdd(const og_grid* g, og_dims n, int method, int d, int a, int b, int c)
 {
     double C[3];
     double det = orc_face_crow(g, n.nr, n.nt, n.np, method, d, a, b, c, C);
-    return og_dot(C, C) / det;
+    return det > 0.0 ? og_dot(C, C) / det : 0.0;
 }
 
 /* position of cell i of line `line` along direction d */
