@@ -60,7 +60,9 @@ typedef struct {
     int32_t n_r, n_theta, n_phi; /* cells; every level but the coarsest needs even dims */
     int32_t map;                 /* cps_map */
     double r_inner, r_outer;     /* the paper's shell: 1.5, 2.5 (gap 1, ratio 0.6) */
-    double theta0, theta1;       /* cone walls, e.g. 0.05 and pi - 0.05 */
+    double theta0, theta1;       /* cone walls in [0, pi], e.g. 0.05 and pi - 0.05;
+                                    0 and pi give the full sphere, whose
+                                    polar faces have zero area (no flux) */
     double radial_stretch;       /* rx2 of eq. (stretching); 0 = uniform */
     double flattening, skew;     /* oblate / triaxial shape parameters */
     int32_t n_levels;            /* 0 = halve while > 1024 cells, dims even and >= 4, and

@@ -741,8 +741,10 @@ void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
     if (!(g->r_outer > g->r_inner)) fail(CPS_E_INVALID, "r_outer must exceed r_inner");
     if (g->map != CPS_MAP_IDENTITY && !(g->r_inner > 0)) fail(CPS_E_INVALID, "r_inner must be > 0");
     if (!(g->theta1 > g->theta0)) fail(CPS_E_INVALID, "theta1 must exceed theta0");
-    if (g->map != CPS_MAP_IDENTITY && !(g->theta0 > 0 && g->theta1 < M_PI))
-        fail(CPS_E_INVALID, "cone walls must lie inside (0, pi)");
+    // theta0 = 0 / theta1 = pi: a full sphere, whose polar faces have zero
+    // area and carry no flux (no coupling across the pole is needed)
+    if (g->map != CPS_MAP_IDENTITY && !(g->theta0 >= 0 && g->theta1 <= M_PI))
+        fail(CPS_E_INVALID, "theta0 and theta1 must lie in [0, pi]");
     if (g->radial_stretch < 0) fail(CPS_E_INVALID, "radial_stretch must be >= 0");
     if (g->n_levels < 0 || g->n_levels > kMaxLevels) fail(CPS_E_INVALID, "bad n_levels");
     if (m && m->method != CPS_METRICS_MAP_CENTRAL && m->method != CPS_METRICS_PAPER_VERTEX)

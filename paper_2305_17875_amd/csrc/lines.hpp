@@ -32,14 +32,16 @@ struct LineBC {
 
 constexpr int kLineBatch = 8;
 
-// G_dd of the LOW d-face of position (a, b) of phi-invariant face tables
+// G_dd of the LOW d-face of position (a, b) of phi-invariant face tables; a
+// face of zero area (a pole of a full sphere) carries no flux: 0
 __device__ __forceinline__ double face_gdd(const CRows& R, const double* __restrict__ Jf, int d,
                                            int a, int b)
 {
     const long long fi = (long long)a * R.nt1 + b;
     const double c0 = R.C[(3 * d) * R.F + fi], c1 = R.C[(3 * d + 1) * R.F + fi],
                  c2 = R.C[(3 * d + 2) * R.F + fi];
-    return (c0 * c0 + c1 * c1 + c2 * c2) / Jf[d * R.F + fi];
+    const double J = Jf[d * R.F + fi];
+    return J > 0.0 ? (c0 * c0 + c1 * c1 + c2 * c2) / J : 0.0;
 }
 
 // Elimination of the distinct open lines along d (0 r: one per b; 1 theta:
