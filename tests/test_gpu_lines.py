@@ -105,3 +105,32 @@ def test_paper_scale_sampled_lines():
             sl = {0: (slice(None), line // np_, line % np_), 1: (line // np_, slice(None), line % np_),
                   2: (line // nt, line % nt, slice(None))}[d]
             assert np.abs(got[sl] - want[sl]).max() <= 1e-12 * np.abs(want[sl]).max(), (d, line)
+
+
+def test_degenerate_cases():
+    """coef = 0: psi = g / |J^-1| exactly along every direction; a ring of 2
+    phi cells (both neighbours are the same cell) and a zero field in the
+    projection step."""
+    g = Shell(8, 8, 16, radial_stretch=2.0)
+    b = np.random.default_rng(60).standard_normal(g.shape)
+    Jc = np.array([[O.cell_jdet(g, a, bb, 0) for bb in range(g.n_theta)] for a in range(g.n_r)])
+    s = cps.Solver(g, precision=0)
+    try:
+        for d in range(3):
+            got = host(s.line_solve(d, 0.0, dev(b).flatten())).reshape(g.shape)
+            assert np.abs(got - b / Jc[:, :, None]).max() <= 1e-14 * np.abs(got).max(), d
+        z = torch.zeros(3 * g.cells, dtype=torch.float64, device="cuda")
+        assert not host(s.divergence(z)).any()
+    finally:
+        s.close()
+    g2 = Shell(4, 4, 2)  # one level: phi ring of 2
+    u = np.random.default_rng(61).standard_normal((3,) + g2.shape)
+    s = cps.Solver(g2, precision=0)
+    try:
+        got = host(s.divergence(dev(u).flatten())).reshape(g2.shape)
+        with pytest.raises(cps.CpsError, match="n_phi"):
+            s.line_solve(2, 1.0, dev(u[0]).flatten())
+    finally:
+        s.close()
+    want = O.divergence(g2, u)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
