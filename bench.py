@@ -337,17 +337,19 @@ def cpu_baseline(g, rhs_np, gpu_iters):
                       f"same algorithm takes to reach 1e-10"}
 
 
-def batch_form(cps, torch, inputs, n_problems, steps, warmup):
+def batch_form(cps, torch, inputs, n_problems, steps, warmup, smoother=2):
     """64 uneven-size problems (half spherical, half oblate with flattening
     0.1) solved together by the batched form, against the same problems
-    solved one after another by cps_solve with the same options."""
+    solved one after another by cps_solve with the same options.  smoother 2
+    (automatic): the spheres run the plane smoother as a group of their own,
+    the oblate shells the point smoother."""
     probs = inputs.batch_problems(n_problems)
     grids = [p.grid for p in probs]
     log(f"batch: generating {n_problems} right-hand sides")
     rhs = [torch.from_numpy(p.rhs()).cuda().flatten() for p in probs]
     cells = sum(g.cells for g in grids)
     t0 = time.perf_counter()
-    B = cps.Batch(grids, tune=1)
+    B = cps.Batch(grids, tune=1, smoother=smoother)
     setup = time.perf_counter() - t0
     out = [torch.empty_like(r) for r in rhs]
     for _ in range(warmup):
@@ -363,7 +365,7 @@ def batch_form(cps, torch, inputs, n_problems, steps, warmup):
     worst = max(i.rel_residual for i in infos)
     log(f"batch: {dt * 1e3:.1f} ms per batch solve, status {st}, iterations {min(its)}..{max(its)}")
     # the same problems one at a time (hierarchies built beforehand)
-    solvers = [cps.Solver(g, precision=1, accel=1) for g in grids]
+    solvers = [cps.Solver(g, precision=1, accel=1, smoother=smoother) for g in grids]
     for s, r, o in zip(solvers, rhs, out):
         s.solve(r, TOL, out=o)
     torch.cuda.synchronize()
@@ -380,6 +382,8 @@ def batch_form(cps, torch, inputs, n_problems, steps, warmup):
             "iterations_min": min(its), "iterations_max": max(its), "worst_rel_residual": worst,
             "setup_s": setup, "sequential_ms": seq * 1e3, "speedup_vs_sequential": seq / dt,
             "dtype": "f32 V-cycles, f64 outer",
+            "smoother": {0: "point red-black", 2: "automatic: zebra plane for the spheres, "
+                                                  "point red-black for the oblate shells"}[smoother],
             "workload": f"{n_problems} shells, sizes by seed 4 from 16^3, 32^3, 64x64x128, "
                         "96x128x256, 128x128x256; even index sphere, odd oblate f=0.1; "
                         "smoothed N(0,1) rhs seeds 1000+i; rel residual 1e-10"}
@@ -559,6 +563,7 @@ def main():
     ap.add_argument("--no-project", action="store_true")
     ap.add_argument("--no-lines", action="store_true")
     ap.add_argument("--batch-problems", type=int, default=64)
+    ap.add_argument("--batch-smoother", type=int, default=2, choices=[0, 2])
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -643,7 +648,8 @@ def main():
     if not a.no_lines:
         line["lines"] = lines_form(cps, torch, inputs, g, a.steps, a.warmup)
     if not a.no_batch:
-        line["batch"] = batch_form(cps, torch, inputs, a.batch_problems, a.steps, a.warmup)
+        line["batch"] = batch_form(cps, torch, inputs, a.batch_problems, a.steps, a.warmup,
+                                   a.batch_smoother)
         torch.cuda.empty_cache()
     if not a.no_serve:
         line["serve"] = serve_form(cps, inputs, a.serve_seconds, a.serve_rate, a.serve_slots,

@@ -452,12 +452,12 @@ class Batch:
     """Many problems solved together (FP32 V-cycles inside FP64 refinement)."""
 
     def __init__(self, grids, max_iters: int = 200, metrics: int = METRICS_MAP_CENTRAL,
-                 stream=None, tune: int = 0):
+                 stream=None, tune: int = 0, smoother: int = 0):
         import torch
         self.grids = list(grids)
         self.sizes = [g.n_r * g.n_theta * g.n_phi for g in self.grids]
         s = stream if stream is not None else torch.cuda.current_stream()
-        opts = cps_opts(1, max_iters, 1, tune, 0, 0, ctypes.c_void_p(s.cuda_stream))
+        opts = cps_opts(1, max_iters, 1, tune, 0, smoother, ctypes.c_void_p(s.cuda_stream))
         self.h = cps_batch_setup([make_grid(g) for g in self.grids], cps_metrics(metrics), opts)
 
     def solve(self, rhs_list, tol: float = 1e-10, out=None):

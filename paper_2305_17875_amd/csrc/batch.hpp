@@ -15,6 +15,49 @@
 // only host round trip per iteration gathers the residual norms, retires
 // converged problems and uploads the active flags.
 
+namespace cps {
+
+// Plane-smoother half-sweep kernels of the batched form: the bodies of
+// k_plane_fwd / k_plane_tri / k_plane_inv with each block's problem and
+// logical index from the work table (rings of <= kSmallRing complex values,
+// whose launches take kBlock threads).
+__global__ void __launch_bounds__(kBlock) kb_plane_fwd(const BItem* __restrict__ items,
+                                                       const int* __restrict__ active,
+                                                       const PDesc<float>* __restrict__ pd,
+                                                       int level, int parity)
+{
+    CPS_BATCH_BLOCK
+    __shared__ Vec2<float> buf[kPlaneLds], twS[kPlaneLds / 2];
+    const LDesc<float>& d = pd[it.prob].lv[level];
+    d_plane_fwd<float, kSmallRing>(bk.L, buf, twS, d.g, d.G, d.gk, d.b, d.x, parity, d.ptw,
+                                   d.ptwN, d.pS);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_plane_tri(const BItem* __restrict__ items,
+                                                       const int* __restrict__ active,
+                                                       const PDesc<float>* __restrict__ pd,
+                                                       int level, int parity)
+{
+    CPS_BATCH_BLOCK
+    const LDesc<float>& d = pd[it.prob].lv[level];
+    d_plane_tri<float>((long long)bk.L * blockDim.x + threadIdx.x, d.g, d.G, parity,
+                       d.ppiv + plane_pivot_offset(d.g, parity),
+                       reinterpret_cast<float*>(d.pS));
+}
+
+__global__ void __launch_bounds__(kBlock) kb_plane_inv(const BItem* __restrict__ items,
+                                                       const int* __restrict__ active,
+                                                       const PDesc<float>* __restrict__ pd,
+                                                       int level, int parity)
+{
+    CPS_BATCH_BLOCK
+    __shared__ Vec2<float> buf[kPlaneLds], twS[kPlaneLds / 2];
+    const LDesc<float>& d = pd[it.prob].lv[level];
+    d_plane_inv<float, kSmallRing>(bk.L, buf, twS, d.g, parity, d.ptw, d.ptwN, d.pS, d.x);
+}
+
+} // namespace cps
+
 namespace {
 
 struct ItemTable {
@@ -24,11 +67,12 @@ struct ItemTable {
 
 struct BatchGroup {
     int mode = MODE_ORTHO;
-    bool axi = true, march = true, flexible_cg = true;
+    bool axi = true, march = true, flexible_cg = true, plane = false;
     int ncol = 2;
     std::vector<int> probs;
     int Lmax = 0;
     ItemTable gs[kMaxLevels], res[kMaxLevels], xfer[kMaxLevels], fill[kMaxLevels];
+    ItemTable pfwd[kMaxLevels][2], ptri[kMaxLevels][2]; // plane half-sweeps by parity
     ItemTable coarse, apply, vred, elem;
     hipGraphExec_t gA = nullptr, gB = nullptr;
     hipGraph_t graphA = nullptr, graphB = nullptr;
@@ -51,7 +95,7 @@ struct cps_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<cps_handle*> h;
-    BatchGroup grp[2];
+    BatchGroup grp[3]; // 7-point point smoother, the other stencil class, 7-point plane
     std::vector<PDesc<float>> hpd;
     Buf<PDesc<float>> pd;
     Buf<int> active;
@@ -92,6 +136,17 @@ void bdot(cps_batch* B, const ItemTable& vred, int u, int v, int slot)
 
 void b_smooth(cps_batch* B, BatchGroup& G, int l, bool reverse, bool from_zero)
 {
+    if (G.plane) { // as smooth() with the plane smoother: two sweeps of two half-sweeps
+        if (from_zero) blaunch(B, G.fill[l], kb_fill_level<float>, l);
+        for (int s = 0; s < 2; ++s)
+            for (int k = 0; k < 2; ++k) {
+                const int parity = reverse ? 1 - k : k;
+                blaunch(B, G.pfwd[l][parity], kb_plane_fwd, l, parity);
+                blaunch(B, G.ptri[l][parity], kb_plane_tri, l, parity);
+                blaunch(B, G.pfwd[l][parity], kb_plane_inv, l, parity);
+            }
+        return;
+    }
     const bool skip = from_zero && G.ncol == 2;
     if (from_zero && !skip) blaunch(B, G.fill[l], kb_fill_level<float>, l);
     for (int s = 0; s < 2; ++s)
@@ -238,6 +293,13 @@ PDesc<float> make_desc(cps_handle* h)
     for (int l = 0; l < h->L; ++l) {
         const LevelMem& m = h->lv[l];
         d.lv[l] = LDesc<float>{m.geo, m.G32.p, m.gk, m.x32.p, m.b32.p, m.r32.p, m.gs_ch};
+        if (h->opts.smoother == 1 && l + 1 < h->L) {
+            d.lv[l].ptw = reinterpret_cast<const Vec2<float>*>(m.tw32.p);
+            d.lv[l].ptwN = reinterpret_cast<const Vec2<float>*>(m.twN32.p);
+            d.lv[l].plam = m.lam32.p;
+            d.lv[l].ppiv = m.pv32.p;
+            d.lv[l].pS = reinterpret_cast<Vec2<float>*>(h->ps32.p);
+        }
     }
     return d;
 }
@@ -267,6 +329,20 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
         build_items(G.res[l], res);
         build_items(G.xfer[l], xf);
         build_items(G.fill[l], fl);
+        if (G.plane)
+            for (int k = 0; k < 2; ++k) {
+                PG pf, pt;
+                for (int p : G.probs) {
+                    cps_handle* h = B->h[p];
+                    if (l + 1 >= h->L) continue;
+                    const Geo& g = h->lv[l].geo;
+                    const PlaneLaunch pl = plane_launch(g, k);
+                    pf.push_back({p, pl.blocks});
+                    pt.push_back({p, cdiv(2LL * pl.rows * (g.nh + 1), kBlock)});
+                }
+                build_items(G.pfwd[l][k], pf);
+                build_items(G.ptri[l][k], pt);
+            }
     }
     PG co, ap, vr, el;
     for (int p : G.probs) {
@@ -335,12 +411,21 @@ void batch_build(cps_batch* B, int n, const cps_grid* grids, const cps_metrics* 
     // groups
     BatchGroup& g0 = B->grp[0];
     BatchGroup& g1 = B->grp[1];
+    BatchGroup& g2 = B->grp[2];
     g0.mode = MODE_ORTHO; g0.axi = true; g0.march = true; g0.ncol = 2; g0.flexible_cg = true;
+    g2.mode = MODE_ORTHO; g2.axi = true; g2.march = true; g2.ncol = 2; g2.flexible_cg = true;
+    g2.plane = true;
     int mode1 = -1;
     bool axi1 = true;
     for (int p = 0; p < n; ++p) {
         cps_handle* h = B->h[p];
-        if (marching(h)) {
+        if (h->opts.smoother == 1) {
+            for (int l = 0; l + 1 < h->L; ++l)
+                if (h->lv[l].np / 2 > kSmallRing)
+                    fail(CPS_E_INVALID, "the batched plane smoother takes n_phi <= %d "
+                         "(problem %d)", 2 * kSmallRing, p);
+            g2.probs.push_back(p);
+        } else if (marching(h)) {
             g0.probs.push_back(p);
         } else {
             if (mode1 >= 0 && (h->mode != mode1 || h->axi != axi1))
@@ -421,7 +506,7 @@ cps_status batch_solve(cps_batch* B, const double* const* rhs, double* const* ou
             st[p] = CPS_E_NOT_CONVERGED;
         }
     }
-    for (int gi = 0; gi < 2; ++gi) {
+    for (int gi = 0; gi < 3; ++gi) {
         BatchGroup& G = B->grp[gi];
         if (G.probs.empty()) continue;
         std::vector<int> act(n, 0);
@@ -512,8 +597,8 @@ cps_status cps_batch_setup(int32_t n, const cps_grid* grids, const cps_metrics* 
         if (opts && opts->precision != 1)
             fail(CPS_E_INVALID, "the batched form runs FP32 V-cycles inside FP64 refinement "
                                 "(precision = 1)");
-        if (opts && opts->smoother != 0)
-            fail(CPS_E_INVALID, "the batched form runs the point smoother (smoother = 0)");
+        if (opts && (opts->smoother < 0 || opts->smoother > 2))
+            fail(CPS_E_INVALID, "bad smoother");
         B = new cps_batch();
         batch_build(B, n, grids, metrics, opts);
     });

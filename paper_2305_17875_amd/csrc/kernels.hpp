@@ -1854,6 +1854,13 @@ struct LDesc {
     long long gk;
     T *x, *b, *r;
     int gs_ch; // marching chunk of the colour pass (autotuned)
+    // plane smoother (null without it): ring transform tables, the r-line
+    // inverse pivots of both parities, the spectra scratch of one parity
+    const Vec2<T>* ptw;
+    const Vec2<T>* ptwN;
+    const T* plam;
+    const T* ppiv;
+    Vec2<T>* pS;
 };
 
 template <typename T>

@@ -173,20 +173,21 @@ __host__ __device__ inline long long plane_pivot_offset(const Geo& g, int parity
 
 // Right-hand sides of the rings of parity k and their real transforms:
 // S[(a rows + bi)(nh + 1) + m], m = 0..nh.
+// Bodies take the logical block index (the batched form maps its blocks to
+// problems); buf and twS are the block's LDS.
 template <typename T, int NMAX>
-__global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict__ G, long long gk,
-                                                      const T* __restrict__ bv,
-                                                      const T* __restrict__ x, int parity,
-                                                      const Vec2<T>* __restrict__ tw,
-                                                      const Vec2<T>* __restrict__ twN,
-                                                      Vec2<T>* __restrict__ S)
+__device__ __forceinline__ void d_plane_fwd(unsigned blk, Vec2<T>* buf, Vec2<T>* twS, Geo g,
+                                            const T* __restrict__ G, long long gk,
+                                            const T* __restrict__ bv, const T* __restrict__ x,
+                                            int parity, const Vec2<T>* __restrict__ tw,
+                                            const Vec2<T>* __restrict__ twN,
+                                            Vec2<T>* __restrict__ S)
 {
-    __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
     const PlaneLaunch pl = plane_launch(g, parity);
     const int nh = g.nh;
     for (int q = (int)threadIdx.x; q < nh / 2; q += pl.threads) twS[q] = tw[q];
     const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
-    const int ring = (int)blockIdx.x * pl.rb + rl;
+    const int ring = (int)blk * pl.rb + rl;
     const bool live = ring < pl.rings;
     const int a = live ? ring / pl.rows : 0, bi = live ? ring - a * pl.rows : 0;
     const int b = 2 * bi + parity;
@@ -262,6 +263,18 @@ __global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict
     }
 }
 
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict__ G, long long gk,
+                                                      const T* __restrict__ bv,
+                                                      const T* __restrict__ x, int parity,
+                                                      const Vec2<T>* __restrict__ tw,
+                                                      const Vec2<T>* __restrict__ twN,
+                                                      Vec2<T>* __restrict__ S)
+{
+    __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
+    d_plane_fwd<T, NMAX>(blockIdx.x, buf, twS, g, G, gk, bv, x, parity, tw, twN, S);
+}
+
 // Inverse pivots of the Thomas elimination of every (row, mode) r-line of
 // parity k: P[(a rows + bi)(nh + 1) + m] = 1 / (diag - grl c_{a-1}),
 // c_a = grh_a P_a.  One thread per (row, mode); set-up only.
@@ -297,14 +310,13 @@ __global__ void __launch_bounds__(kBlock) k_plane_factor(Geo g, const T* __restr
 // the spectra S (read as reals: lane 2u + q takes component q of system u),
 // with the inverse pivots P of k_plane_factor.
 template <typename T>
-__global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restrict__ G, int parity,
-                                                         const T* __restrict__ P,
-                                                         T* __restrict__ S)
+__device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restrict__ G,
+                                            int parity, const T* __restrict__ P,
+                                            T* __restrict__ S)
 {
     const int rows = (g.nt - parity + 1) / 2;
     const int nm = g.nh + 1, nr = g.nr, nt = g.nt;
     const long long sys = (long long)rows * nm; // one r-plane of spectra
-    const long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= 2 * sys) return;
     const long long t = u >> 1;
     const int q = (int)(u & 1);
@@ -356,20 +368,26 @@ __global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restr
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restrict__ G, int parity,
+                                                         const T* __restrict__ P,
+                                                         T* __restrict__ S)
+{
+    d_plane_tri<T>((long long)blockIdx.x * blockDim.x + threadIdx.x, g, G, parity, P, S);
+}
+
 // Inverse transforms of the solved spectra into the rows of parity k.
 template <typename T, int NMAX>
-__global__ void __launch_bounds__(kBlock) k_plane_inv(Geo g, int parity,
-                                                      const Vec2<T>* __restrict__ tw,
-                                                      const Vec2<T>* __restrict__ twN,
-                                                      const Vec2<T>* __restrict__ S,
-                                                      T* __restrict__ x)
+__device__ __forceinline__ void d_plane_inv(unsigned blk, Vec2<T>* buf, Vec2<T>* twS, Geo g,
+                                            int parity, const Vec2<T>* __restrict__ tw,
+                                            const Vec2<T>* __restrict__ twN,
+                                            const Vec2<T>* __restrict__ S, T* __restrict__ x)
 {
-    __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
     const PlaneLaunch pl = plane_launch(g, parity);
     const int nh = g.nh;
     for (int q = (int)threadIdx.x; q < nh / 2; q += pl.threads) twS[q] = tw[q];
     const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
-    const int ring = (int)blockIdx.x * pl.rb + rl;
+    const int ring = (int)blk * pl.rb + rl;
     const bool live = ring < pl.rings;
     Vec2<T>* A = buf + rl * nh;
     if (live) {
@@ -417,6 +435,17 @@ __global__ void __launch_bounds__(kBlock) k_plane_inv(Geo g, int parity,
         x[base + j] = v.x * s;
         x[g.P + base + j] = v.y * s;
     }
+}
+
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(kBlock) k_plane_inv(Geo g, int parity,
+                                                      const Vec2<T>* __restrict__ tw,
+                                                      const Vec2<T>* __restrict__ twN,
+                                                      const Vec2<T>* __restrict__ S,
+                                                      T* __restrict__ x)
+{
+    __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
+    d_plane_inv<T, NMAX>(blockIdx.x, buf, twS, g, parity, tw, twN, S, x);
 }
 
 } // namespace cps

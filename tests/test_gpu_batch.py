@@ -32,8 +32,8 @@ def rhs_of(i, g):
     return inputs.smoothed_noise(g.shape, seed=100 + i)
 
 
-def alone(g, b):
-    s = cps.Solver(g, precision=1, accel=1)
+def alone(g, b, smoother=0):
+    s = cps.Solver(g, precision=1, accel=1, smoother=smoother)
     try:
         r = s.solve(dev(b).flatten())
         return host(r.p).reshape(g.shape), r
@@ -91,3 +91,31 @@ def test_batch_retires_diverged_and_capped_problems():
     assert st == cps.CPS_E_NOT_CONVERGED and infos[0].iterations == 1
     with pytest.raises(cps.CpsError):
         cps.Batch([Shell(34, 34, 34)])
+
+
+def test_batch_with_the_automatic_smoother():
+    """smoother = 2: the spheres with power-of-two rings run the plane
+    smoother as a group of their own, the sphere with a 48-cell ring the point
+    smoother, the oblate shells theirs; every result equals the same problem
+    solved alone with the same opts, bit for bit, and the oracle's exact
+    solution to 1e-9."""
+    grids = [Shell(16, 16, 32, radial_stretch=2.0), Shell(32, 32, 64, map=MAP_OBLATE,
+                                                          flattening=0.1),
+             Shell(32, 32, 64), Shell(16, 16, 48), Shell(8, 12, 256),
+             Shell(16, 16, 16, map=MAP_OBLATE, flattening=0.05)]
+    rhs = [rhs_of(20 + i, g) for i, g in enumerate(grids)]
+    log("batch automatic smoother", len(grids))
+    B = cps.Batch(grids, smoother=2)
+    try:
+        st, p, infos = B.solve([dev(b).flatten() for b in rhs])
+        xs = [host(t).reshape(g.shape) for t, g in zip(p, grids)]
+    finally:
+        B.close()
+    assert st == cps.CPS_OK
+    for i, (g, b, x, info) in enumerate(zip(grids, rhs, xs, infos)):
+        xa, ra = alone(g, b, smoother=2)
+        assert info.iterations == ra.iterations, i
+        assert np.array_equal(x, xa), (i, np.abs(x - xa).max())
+        want = direct.solve_axisym(O.face_metrics(g), b)
+        assert rel(x, want) <= 1e-9, (i, rel(x, want))
+    assert infos[0].iterations <= 8 and infos[3].iterations > 3 * infos[0].iterations
