@@ -107,13 +107,17 @@ typedef struct {
                           of one parity at a time, each (r, phi) plane solved
                           exactly by a Fourier transform along phi and the
                           Thomas algorithm along r; robust to the shell's
-                          radial and cone-tip anisotropy.  Needs the 7-point
-                          operator with phi-invariant metrics (identity box,
-                          sphere) and n_phi a power of two in [4, 2048] on
-                          every smoothed level;
+                          radial and cone-tip anisotropy.  Needs
+                          phi-invariant metrics without phi cross terms: the
+                          7-point operator (identity box, sphere) or the
+                          11-point one with r-theta cross terms (oblate
+                          shell; its r-lines are then tridiagonal but not
+                          symmetric), and n_phi a power of two in [4, 2048]
+                          on every smoothed level (<= 512 in the batched
+                          form);
                           2: automatic -- 1 where the hierarchy allows it,
-                          else 0 (decided at set-up; the batched form takes 0
-                          only). */
+                          else 0 (decided at set-up, per problem in the
+                          batched form). */
     void* stream;      /* hipStream_t the calls are ordered on; NULL = null stream */
 } cps_opts;
 

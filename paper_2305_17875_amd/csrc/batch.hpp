@@ -9,9 +9,11 @@
 // descriptors hold the problem's geometry and buffers.  Each problem thus
 // sees exactly the arithmetic and reduction order of its own solve: the
 // result of a problem is the same alone and in the batch, bit for bit.
-// Problems are grouped by stencil: 7-point with phi-invariant metrics
-// (marching kernels) and the rest (generic kernels); both run flexible CG.  The iteration
-// bodies of both groups are captured once in hipGraphs and replayed; the
+// Problems are grouped by stencil and smoother: with the point smoother,
+// 7-point with phi-invariant metrics (marching kernels) and the rest
+// (generic kernels); with the plane smoother, the 7-point and the 11-point
+// (r-theta cross terms) axisymmetric classes.  All run flexible CG.  The
+// iteration bodies of the groups are captured once in hipGraphs and replayed; the
 // only host round trip per iteration gathers the residual norms, retires
 // converged problems and uploads the active flags.
 
@@ -21,6 +23,7 @@ namespace cps {
 // k_plane_fwd / k_plane_tri / k_plane_inv with each block's problem and
 // logical index from the work table (rings of <= kSmallRing complex values,
 // whose launches take kBlock threads).
+template <bool CROSS>
 __global__ void __launch_bounds__(kBlock) kb_plane_fwd(const BItem* __restrict__ items,
                                                        const int* __restrict__ active,
                                                        const PDesc<float>* __restrict__ pd,
@@ -29,10 +32,11 @@ __global__ void __launch_bounds__(kBlock) kb_plane_fwd(const BItem* __restrict__
     CPS_BATCH_BLOCK
     __shared__ Vec2<float> buf[kPlaneLds], twS[kPlaneLds / 2];
     const LDesc<float>& d = pd[it.prob].lv[level];
-    d_plane_fwd<float, kSmallRing>(bk.L, buf, twS, d.g, d.G, d.gk, d.b, d.x, parity, d.ptw,
-                                   d.ptwN, d.pS);
+    d_plane_fwd<float, kSmallRing, CROSS>(bk.L, buf, twS, d.g, d.G, d.gk, d.b, d.x, parity,
+                                          d.ptw, d.ptwN, d.pS);
 }
 
+template <bool CROSS>
 __global__ void __launch_bounds__(kBlock) kb_plane_tri(const BItem* __restrict__ items,
                                                        const int* __restrict__ active,
                                                        const PDesc<float>* __restrict__ pd,
@@ -40,9 +44,9 @@ __global__ void __launch_bounds__(kBlock) kb_plane_tri(const BItem* __restrict__
 {
     CPS_BATCH_BLOCK
     const LDesc<float>& d = pd[it.prob].lv[level];
-    d_plane_tri<float>((long long)bk.L * blockDim.x + threadIdx.x, d.g, d.G, parity,
-                       d.ppiv + plane_pivot_offset(d.g, parity),
-                       reinterpret_cast<float*>(d.pS));
+    d_plane_tri<float, CROSS>((long long)bk.L * blockDim.x + threadIdx.x, d.g, d.G, d.gk,
+                              parity, d.ppiv + plane_pivot_offset(d.g, parity),
+                              reinterpret_cast<float*>(d.pS));
 }
 
 __global__ void __launch_bounds__(kBlock) kb_plane_inv(const BItem* __restrict__ items,
@@ -95,7 +99,7 @@ struct cps_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<cps_handle*> h;
-    BatchGroup grp[3]; // 7-point point smoother, the other stencil class, 7-point plane
+    BatchGroup grp[4]; // point smoother: 7-point, the other stencil class; plane: 7-, 11-point
     std::vector<PDesc<float>> hpd;
     Buf<PDesc<float>> pd;
     Buf<int> active;
@@ -138,11 +142,14 @@ void b_smooth(cps_batch* B, BatchGroup& G, int l, bool reverse, bool from_zero)
 {
     if (G.plane) { // as smooth() with the plane smoother: two sweeps of two half-sweeps
         if (from_zero) blaunch(B, G.fill[l], kb_fill_level<float>, l);
+        const bool cross = G.mode == MODE_RT;
         for (int s = 0; s < 2; ++s)
             for (int k = 0; k < 2; ++k) {
                 const int parity = reverse ? 1 - k : k;
-                blaunch(B, G.pfwd[l][parity], kb_plane_fwd, l, parity);
-                blaunch(B, G.ptri[l][parity], kb_plane_tri, l, parity);
+                blaunch(B, G.pfwd[l][parity], cross ? kb_plane_fwd<true> : kb_plane_fwd<false>, l,
+                        parity);
+                blaunch(B, G.ptri[l][parity], cross ? kb_plane_tri<true> : kb_plane_tri<false>, l,
+                        parity);
                 blaunch(B, G.pfwd[l][parity], kb_plane_inv, l, parity);
             }
         return;
@@ -412,9 +419,14 @@ void batch_build(cps_batch* B, int n, const cps_grid* grids, const cps_metrics* 
     BatchGroup& g0 = B->grp[0];
     BatchGroup& g1 = B->grp[1];
     BatchGroup& g2 = B->grp[2];
+    BatchGroup& g3 = B->grp[3];
     g0.mode = MODE_ORTHO; g0.axi = true; g0.march = true; g0.ncol = 2; g0.flexible_cg = true;
     g2.mode = MODE_ORTHO; g2.axi = true; g2.march = true; g2.ncol = 2; g2.flexible_cg = true;
     g2.plane = true;
+    // r-theta cross terms with the plane smoother: generic residual and
+    // transfer kernels of that class
+    g3.mode = MODE_RT; g3.axi = true; g3.march = false; g3.ncol = 4; g3.flexible_cg = true;
+    g3.plane = true;
     int mode1 = -1;
     bool axi1 = true;
     for (int p = 0; p < n; ++p) {
@@ -424,7 +436,7 @@ void batch_build(cps_batch* B, int n, const cps_grid* grids, const cps_metrics* 
                 if (h->lv[l].np / 2 > kSmallRing)
                     fail(CPS_E_INVALID, "the batched plane smoother takes n_phi <= %d "
                          "(problem %d)", 2 * kSmallRing, p);
-            g2.probs.push_back(p);
+            (h->mode == MODE_RT ? g3 : g2).probs.push_back(p);
         } else if (marching(h)) {
             g0.probs.push_back(p);
         } else {
@@ -506,7 +518,7 @@ cps_status batch_solve(cps_batch* B, const double* const* rhs, double* const* ou
             st[p] = CPS_E_NOT_CONVERGED;
         }
     }
-    for (int gi = 0; gi < 3; ++gi) {
+    for (int gi = 0; gi < 4; ++gi) {
         BatchGroup& G = B->grp[gi];
         if (G.probs.empty()) continue;
         std::vector<int> act(n, 0);

@@ -357,8 +357,15 @@ struct PlaneBufs<float> {
     static float* S(cps_handle* h) { return h->ps32.p; }
 };
 
-template <typename T>
-void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
+// The plane smoother's operator classes: phi-invariant metrics (an
+// axisymmetric map) with no cross terms, or with the r-theta ones only.
+bool plane_class_ok(const cps_handle* h)
+{
+    return h->axi && (h->mode == MODE_ORTHO || h->mode == MODE_RT);
+}
+
+template <typename T, bool CROSS>
+void plane_half_sweep_t(cps_handle* h, int l, int parity, const T* b, T* x)
 {
     using PB = PlaneBufs<T>;
     const Level<T> L = view<T>(h, l);
@@ -371,15 +378,15 @@ void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
     auto* S = reinterpret_cast<Vec2<T>*>(PB::S(h));
     ProfScope ps(h, CPS_KERNEL_GS, l);
     if (L.g.nh <= kSmallRing)
-        k_plane_fwd<T, kSmallRing><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, L.G, L.gk, b, x,
-                                                                            parity, tw, twN, S);
+        k_plane_fwd<T, kSmallRing, CROSS><<<pl.blocks, pl.threads, 0, h->stream>>>(
+            L.g, L.G, L.gk, b, x, parity, tw, twN, S);
     else
-        k_plane_fwd<T, kPlaneLds><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, L.G, L.gk, b, x,
-                                                                           parity, tw, twN, S);
+        k_plane_fwd<T, kPlaneLds, CROSS><<<pl.blocks, pl.threads, 0, h->stream>>>(
+            L.g, L.G, L.gk, b, x, parity, tw, twN, S);
     LAUNCH_CHECK();
     const long long lanes = 2LL * pl.rows * (L.g.nh + 1);
-    k_plane_tri<T><<<(unsigned)cdiv(lanes, kTriBlock), kTriBlock, 0, h->stream>>>(
-        L.g, L.G, parity, PB::piv(m) + plane_pivot_offset(L.g, parity), PB::S(h));
+    k_plane_tri<T, CROSS><<<(unsigned)cdiv(lanes, kTriBlock), kTriBlock, 0, h->stream>>>(
+        L.g, L.G, L.gk, parity, PB::piv(m) + plane_pivot_offset(L.g, parity), PB::S(h));
     LAUNCH_CHECK();
     if (L.g.nh <= kSmallRing)
         k_plane_inv<T, kSmallRing><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN,
@@ -388,6 +395,13 @@ void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
         k_plane_inv<T, kPlaneLds><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN, S,
                                                                            x);
     LAUNCH_CHECK();
+}
+
+template <typename T>
+void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
+{
+    if (h->mode == MODE_RT) plane_half_sweep_t<T, true>(h, l, parity, b, x);
+    else plane_half_sweep_t<T, false>(h, l, parity, b, x);
 }
 
 // Gauss-Seidel sweeps over all colours (reverse order for post-smoothing).
@@ -768,11 +782,18 @@ void plane_factors(cps_handle* h)
         for (int k = 0; k < 2; ++k) {
             const long long sys = (long long)((m.nt - k + 1) / 2) * (m.np / 2 + 1);
             const long long off = plane_pivot_offset(m.geo, k);
-            if (mixed)
-                k_plane_factor<float><<<nblk(sys), kBlock, 0, h->stream>>>(
+            const bool cross = h->mode == MODE_RT;
+            if (mixed && cross)
+                k_plane_factor<float, true><<<nblk(sys), kBlock, 0, h->stream>>>(
                     m.geo, m.G32.p, m.gk, k, m.lam32.p, m.pv32.p + off);
+            else if (mixed)
+                k_plane_factor<float, false><<<nblk(sys), kBlock, 0, h->stream>>>(
+                    m.geo, m.G32.p, m.gk, k, m.lam32.p, m.pv32.p + off);
+            else if (cross)
+                k_plane_factor<double, true><<<nblk(sys), kBlock, 0, h->stream>>>(
+                    m.geo, m.G64.p, m.gk, k, m.lam64.p, m.pv64.p + off);
             else
-                k_plane_factor<double><<<nblk(sys), kBlock, 0, h->stream>>>(
+                k_plane_factor<double, false><<<nblk(sys), kBlock, 0, h->stream>>>(
                     m.geo, m.G64.p, m.gk, k, m.lam64.p, m.pv64.p + off);
             LAUNCH_CHECK();
         }
@@ -897,12 +918,12 @@ int checked_plan(const cps_grid& g, int dims[kMaxLevels][3])
     return L;
 }
 
-// The plane smoother applies: the 7-point operator with phi-invariant
-// metrics, and n_phi / 2 a power of two in [2, kPlaneLds] on every smoothed
-// level.
+// The plane smoother applies: phi-invariant metrics with no cross terms or
+// the r-theta ones only, and n_phi / 2 a power of two in [2, kPlaneLds] on
+// every smoothed level.
 bool plane_eligible(const cps_handle* h)
 {
-    if (!marching(h)) return false;
+    if (!plane_class_ok(h)) return false;
     for (int l = 0; l + 1 < h->L; ++l) {
         const int nh = h->lv[l].np / 2;
         if (nh < 2 || nh > kPlaneLds || (nh & (nh - 1))) return false;
@@ -910,13 +931,14 @@ bool plane_eligible(const cps_handle* h)
     return true;
 }
 
-// Tables and scratch of the plane smoother (7-point, phi-invariant
-// hierarchies whose smoothed levels have power-of-two rings of <= 2048).
+// Tables and scratch of the plane smoother (phi-invariant hierarchies with
+// no cross terms or r-theta ones only, whose smoothed levels have
+// power-of-two rings of <= 2048).
 void setup_plane(cps_handle* h)
 {
-    if (!marching(h))
-        fail(CPS_E_INVALID,
-             "the plane smoother needs the 7-point operator with phi-invariant metrics");
+    if (!plane_class_ok(h))
+        fail(CPS_E_INVALID, "the plane smoother needs phi-invariant metrics without "
+                            "phi cross terms (a 7- or 11-point axisymmetric operator)");
     const bool mixed = h->opts.precision == 1;
     size_t spec = 0;
     for (int l = 0; l + 1 < h->L; ++l) {

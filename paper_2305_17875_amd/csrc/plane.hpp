@@ -27,6 +27,14 @@
 //  - k_plane_inv: the inverse transform back into the rows.
 // Spectra and pivots are laid out [a][row][mode], so the r-line solves read
 // and write consecutive modes across a wavefront.
+//
+// CROSS: the r-theta cross metrics of an axisymmetric map with cross terms
+// (the oblate shell; G_r.phi = G_theta.phi = 0, so phi still decouples).  The
+// theta-face cross terms couple a row's own r-neighbours, and where a theta
+// wall mirrors row b -/+ 1 onto row b the r-face cross terms do too: the
+// r-line stays tridiagonal (not symmetric) with phi-invariant coefficients
+// (plane_row).  The cross terms that reach rows b -/+ 1 go to the
+// right-hand side.
 
 namespace cps {
 
@@ -173,9 +181,48 @@ __host__ __device__ inline long long plane_pivot_offset(const Geo& g, int parity
 
 // Right-hand sides of the rings of parity k and their real transforms:
 // S[(a rows + bi)(nh + 1) + m], m = 0..nh.
+// The r-line of row b at a: sub x_{a-1} + (dia + G_pp lam_m) x_a + sup x_{a+1},
+// with walls (zero metrics on wall faces, mirrored reads) included.
+template <typename T, bool CROSS>
+__device__ __forceinline__ void plane_row(const Geo& g, const T* __restrict__ G, long long gk,
+                                          int a, int b, T& sub, T& dia, T& sup)
+{
+    const long long ci = (long long)a * g.nt + b;
+    const T grl = G[ci];
+    const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
+    const T gtl = G[4 * gk + ci];
+    const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
+    sub = grl;
+    sup = grh;
+    dia = -(grl + grh + gtl + gth);
+    if (CROSS) {
+        // r-face cross terms whose row b -/+ 1 the theta walls mirror onto b
+        const T qrl = T(0.25) * G[gk + ci];
+        const T qrh = a < g.nr - 1 ? T(0.25) * G[gk + ci + g.nt] : T(0);
+        if (b == g.nt - 1) {
+            sup += qrh;
+            dia += qrh - qrl;
+            sub -= qrl;
+        }
+        if (b == 0) {
+            sup -= qrh;
+            dia += qrl - qrh;
+            sub += qrl;
+        }
+        // theta-face cross terms on this row: (qth - qtl)(x_{a+1} - x_{a-1})
+        const T qtl = T(0.25) * G[3 * gk + ci];
+        const T qth = b < g.nt - 1 ? T(0.25) * G[3 * gk + ci + 1] : T(0);
+        const T s = qth - qtl;
+        if (a < g.nr - 1) sup += s;
+        else dia += s;
+        if (a > 0) sub -= s;
+        else dia -= s;
+    }
+}
+
 // Bodies take the logical block index (the batched form maps its blocks to
 // problems); buf and twS are the block's LDS.
-template <typename T, int NMAX>
+template <typename T, int NMAX, bool CROSS = false>
 __device__ __forceinline__ void d_plane_fwd(unsigned blk, Vec2<T>* buf, Vec2<T>* twS, Geo g,
                                             const T* __restrict__ G, long long gk,
                                             const T* __restrict__ bv, const T* __restrict__ x,
@@ -192,7 +239,36 @@ __device__ __forceinline__ void d_plane_fwd(unsigned blk, Vec2<T>* buf, Vec2<T>*
     const int a = live ? ring / pl.rows : 0, bi = live ? ring - a * pl.rows : 0;
     const int b = 2 * bi + parity;
     Vec2<T>* A = buf + rl * nh;
-    if (live) {
+    if (live && CROSS) {
+        // b + sum over rows b -/+ 1 at a - 1, a, a + 1 (mirrored in r) of
+        // coefficient x value: the theta-face metrics and both faces' cross
+        // terms (a mirrored position carries a zero metric or folds onto a)
+        const long long ci = (long long)a * g.nt + b;
+        const bool lo = b > 0, hi = b < g.nt - 1;
+        const T gtl = G[4 * gk + ci], gth = hi ? G[4 * gk + ci + 1] : T(0);
+        const T qrl = T(0.25) * G[gk + ci];
+        const T qrh = a < g.nr - 1 ? T(0.25) * G[gk + ci + g.nt] : T(0);
+        const T qtl = T(0.25) * G[3 * gk + ci], qth = hi ? T(0.25) * G[3 * gk + ci + 1] : T(0);
+        const T ch0 = -gth - qrh + qrl, chp = -qrh - qth, chm = qrl + qth;
+        const T cl0 = -gtl + qrh - qrl, clp = qrh + qtl, clm = -qrl - qtl;
+        const long long base = (long long)a * g.rowlen + (long long)b * nh;
+        const long long dp = a < g.nr - 1 ? g.rowlen : 0, dm = a > 0 ? g.rowlen : 0;
+        for (int j = tr; j < nh; j += pl.tpr) {
+            Vec2<T> z;
+            z.x = ld_once(bv + base + j);
+            z.y = ld_once(bv + g.P + base + j);
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool on = side ? hi : lo;
+                if (!on) continue;
+                const long long r0 = base + (side ? nh : -nh) + j;
+                const T c0 = side ? ch0 : cl0, cp = side ? chp : clp, cm = side ? chm : clm;
+                z.x += c0 * x[r0] + cp * x[r0 + dp] + cm * x[r0 - dm];
+                z.y += c0 * x[g.P + r0] + cp * x[g.P + r0 + dp] + cm * x[g.P + r0 - dm];
+            }
+            A[j] = z;
+        }
+    } else if (live) {
         const long long ci = (long long)a * g.nt + b;
         const T gtl = G[4 * gk + ci];
         const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
@@ -263,7 +339,7 @@ __device__ __forceinline__ void d_plane_fwd(unsigned blk, Vec2<T>* buf, Vec2<T>*
     }
 }
 
-template <typename T, int NMAX>
+template <typename T, int NMAX, bool CROSS>
 __global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict__ G, long long gk,
                                                       const T* __restrict__ bv,
                                                       const T* __restrict__ x, int parity,
@@ -272,13 +348,13 @@ __global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict
                                                       Vec2<T>* __restrict__ S)
 {
     __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
-    d_plane_fwd<T, NMAX>(blockIdx.x, buf, twS, g, G, gk, bv, x, parity, tw, twN, S);
+    d_plane_fwd<T, NMAX, CROSS>(blockIdx.x, buf, twS, g, G, gk, bv, x, parity, tw, twN, S);
 }
 
 // Inverse pivots of the Thomas elimination of every (row, mode) r-line of
 // parity k: P[(a rows + bi)(nh + 1) + m] = 1 / (diag - grl c_{a-1}),
 // c_a = grh_a P_a.  One thread per (row, mode); set-up only.
-template <typename T>
+template <typename T, bool CROSS>
 __global__ void __launch_bounds__(kBlock) k_plane_factor(Geo g, const T* __restrict__ G,
                                                          long long gk, int parity,
                                                          const T* __restrict__ lam,
@@ -295,23 +371,21 @@ __global__ void __launch_bounds__(kBlock) k_plane_factor(Geo g, const T* __restr
     T c = T(0);
     for (int a = 0; a < g.nr; ++a) {
         const long long ci = (long long)a * g.nt + b;
-        const T grl = G[ci];
-        const T grh = a < g.nr - 1 ? G[ci + g.nt] : T(0);
-        const T gtl = G[4 * gk + ci];
-        const T gth = b < g.nt - 1 ? G[4 * gk + ci + 1] : T(0);
-        const T diag = -(grl + grh + gtl + gth) + G[8 * gk + ci] * lm;
-        const T inv = T(1) / (diag - grl * c);
+        T sub, dia, sup;
+        plane_row<T, CROSS>(g, G, gk, a, b, sub, dia, sup);
+        const T diag = dia + G[8 * gk + ci] * lm;
+        const T inv = T(1) / (diag - sub * c);
         P[a * stride + t] = inv;
-        c = grh * inv;
+        c = sup * inv;
     }
 }
 
 // Thomas algorithm along r for every (row, mode) of parity k, in place in
 // the spectra S (read as reals: lane 2u + q takes component q of system u),
 // with the inverse pivots P of k_plane_factor.
-template <typename T>
+template <typename T, bool CROSS = false>
 __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restrict__ G,
-                                            int parity, const T* __restrict__ P,
+                                            long long gk, int parity, const T* __restrict__ P,
                                             T* __restrict__ S)
 {
     const int rows = (g.nt - parity + 1) / 2;
@@ -331,7 +405,12 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
                 const long long o = a * sys + t;
                 r[k] = S[2 * o + q];
                 p[k] = P[o];
-                gl[k] = G[(long long)a * nt + b];
+                if (CROSS) {
+                    T dia, sup;
+                    plane_row<T, true>(g, G, gk, a, b, gl[k], dia, sup);
+                } else {
+                    gl[k] = G[(long long)a * nt + b];
+                }
             }
         }
 #pragma unroll
@@ -353,7 +432,12 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
                 const long long o = a * sys + t;
                 s[k] = S[2 * o + q];
                 p[k] = P[o];
-                gh[k] = G[(long long)(a + 1) * nt + b];
+                if (CROSS) {
+                    T sub, dia;
+                    plane_row<T, true>(g, G, gk, a, b, sub, dia, gh[k]);
+                } else {
+                    gh[k] = G[(long long)(a + 1) * nt + b];
+                }
             }
         }
 #pragma unroll
@@ -368,12 +452,14 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restrict__ G, int parity,
+template <typename T, bool CROSS>
+__global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restrict__ G,
+                                                         long long gk, int parity,
                                                          const T* __restrict__ P,
                                                          T* __restrict__ S)
 {
-    d_plane_tri<T>((long long)blockIdx.x * blockDim.x + threadIdx.x, g, G, parity, P, S);
+    d_plane_tri<T, CROSS>((long long)blockIdx.x * blockDim.x + threadIdx.x, g, G, gk, parity, P,
+                          S);
 }
 
 // Inverse transforms of the solved spectra into the rows of parity k.

@@ -95,10 +95,10 @@ def test_batch_retires_diverged_and_capped_problems():
 
 def test_batch_with_the_automatic_smoother():
     """smoother = 2: the spheres with power-of-two rings run the plane
-    smoother as a group of their own, the sphere with a 48-cell ring the point
-    smoother, the oblate shells theirs; every result equals the same problem
-    solved alone with the same opts, bit for bit, and the oracle's exact
-    solution to 1e-9."""
+    smoother as a group of their own, the oblate shells the plane smoother
+    with r-theta cross terms as another, the sphere with a 48-cell ring the
+    point smoother; every result equals the same problem solved alone with
+    the same opts, bit for bit, and the oracle's exact solution to 1e-9."""
     grids = [Shell(16, 16, 32, radial_stretch=2.0), Shell(32, 32, 64, map=MAP_OBLATE,
                                                           flattening=0.1),
              Shell(32, 32, 64), Shell(16, 16, 48), Shell(8, 12, 256),
@@ -118,4 +118,6 @@ def test_batch_with_the_automatic_smoother():
         assert np.array_equal(x, xa), (i, np.abs(x - xa).max())
         want = direct.solve_axisym(O.face_metrics(g), b)
         assert rel(x, want) <= 1e-9, (i, rel(x, want))
+    log("batch automatic smoother iterations", [i.iterations for i in infos])
     assert infos[0].iterations <= 8 and infos[3].iterations > 3 * infos[0].iterations
+    assert infos[1].iterations <= 10 and infos[5].iterations <= 10
