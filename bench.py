@@ -342,7 +342,8 @@ def batch_form(cps, torch, inputs, n_problems, steps, warmup, smoother=2):
     0.1) solved together by the batched form, against the same problems
     solved one after another by cps_solve with the same options.  smoother 2
     (automatic): the spheres run the plane smoother as a group of their own,
-    the oblate shells the point smoother."""
+    the oblate shells the plane smoother with r-theta cross terms as
+    another."""
     probs = inputs.batch_problems(n_problems)
     grids = [p.grid for p in probs]
     log(f"batch: generating {n_problems} right-hand sides")
@@ -382,8 +383,9 @@ def batch_form(cps, torch, inputs, n_problems, steps, warmup, smoother=2):
             "iterations_min": min(its), "iterations_max": max(its), "worst_rel_residual": worst,
             "setup_s": setup, "sequential_ms": seq * 1e3, "speedup_vs_sequential": seq / dt,
             "dtype": "f32 V-cycles, f64 outer",
-            "smoother": {0: "point red-black", 2: "automatic: zebra plane for the spheres, "
-                                                  "point red-black for the oblate shells"}[smoother],
+            "smoother": {0: "point red-black", 2: "automatic: zebra plane for the spheres and "
+                                                  "(with r-theta cross terms) the oblate "
+                                                  "shells"}[smoother],
             "workload": f"{n_problems} shells, sizes by seed 4 from 16^3, 32^3, 64x64x128, "
                         "96x128x256, 128x128x256; even index sphere, odd oblate f=0.1; "
                         "smoothed N(0,1) rhs seeds 1000+i; rel residual 1e-10"}
@@ -497,8 +499,8 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoot
            "evictions": st["evictions"] - base["evictions"],
            "dtype": "f32 V-cycles, f64 outer",
            "smoother": {0: "point red-black", 1: "zebra plane",
-                        2: "automatic: zebra plane where the hierarchy allows it (spheres), "
-                           "point red-black otherwise (oblate shells)"}[smoother],
+                        2: "automatic: zebra plane where the hierarchy allows it (spheres, "
+                           "oblate shells), point red-black otherwise"}[smoother],
            "workload": f"Poisson arrivals {rate}/s for {duration} s (seed 5), sizes uniform over "
                        "16^3, 32^3, 64x64x128, 96x128x256, 128x128x256, sphere or oblate "
                        "f~U(0,0.15); rhs from 4 smoothed N(0,1) fields per size; tol 1e-10; "
