@@ -1188,11 +1188,13 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                     LAUNCH_CHECK();
                     if (fused) {
                         const MarchShape ms = stencil_shape(g0);
-                        ProfScope ps(h, CPS_KERNEL_APPLY, 0);
-                        k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
-                            g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
-                            h->sc.p + S_BETA, pnx, q, h->partial.p);
-                        LAUNCH_CHECK();
+                        {
+                            ProfScope ps(h, CPS_KERNEL_APPLY, 0); // the product only
+                            k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
+                                g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
+                                h->sc.p + S_BETA, pnx, q, h->partial.p);
+                            LAUNCH_CHECK();
+                        }
                         reduce(h, ms.grid, S_PQ);
                         step(pnx);
                     } else {

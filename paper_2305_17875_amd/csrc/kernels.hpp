@@ -966,9 +966,11 @@ struct Dir {
     __device__ __forceinline__ T operator()(long long i) const { return z[i] + beta * p[i]; }
 };
 
+// below / above: load the theta row below / above the pair (a caller that
+// has them from the adjacent wavefronts passes false).
 template <typename T, typename X>
 __device__ __forceinline__ void march2_load(const Geo& g, const X& x, const March2& p, int a,
-                                            Nb4<T>& n)
+                                            Nb4<T>& n, bool below = true, bool above = true)
 {
     const int nh = g.nh, j = p.j;
     const long long base = (long long)a * g.rowlen + p.r0;
@@ -977,12 +979,16 @@ __device__ __forceinline__ void march2_load(const Geo& g, const X& x, const Marc
     n.up.v0 = x(g.P + ab);
     n.up.u1 = x(ab + nh);
     n.up.v1 = x(g.P + ab + nh);
-    const long long tl = p.b0 > 0 ? base - nh : base;
-    const long long th = p.b0 + 1 < g.nt - 1 ? base + 2 * nh : base + nh;
-    n.utm0 = x(tl);
-    n.vtm0 = x(g.P + tl);
-    n.utp1 = x(th);
-    n.vtp1 = x(g.P + th);
+    if (below) {
+        const long long tl = p.b0 > 0 ? base - nh : base;
+        n.utm0 = x(tl);
+        n.vtm0 = x(g.P + tl);
+    }
+    if (above) {
+        const long long th = p.b0 + 1 < g.nt - 1 ? base + 2 * nh : base + nh;
+        n.utp1 = x(th);
+        n.vtp1 = x(g.P + th);
+    }
     if (!p.ring && p.lane == 0) {
         const long long jm = base - j + (j == 0 ? nh - 1 : j - 1);
         n.vjm0 = x(g.P + jm);
@@ -1185,6 +1191,12 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
 // p = z + beta p_old (beta: a device scalar) is formed wherever it is read,
 // written for the thread's own cells, and q = A p with partial sums of
 // p . q.  p must not alias p_old (other threads still read p_old).
+// The theta rows just outside a pair are the adjacent wavefronts' own rows:
+// each wavefront hands its plane-a values to its neighbours through LDS
+// (double-buffered by plane, one barrier per plane), so only the block's
+// outermost rows are formed from memory.  Reading both z and p_old at every
+// neighbour instead doubles the L2 traffic of the stencil rows, and half of
+// it then misses.
 template <typename T, int LTAG>
 __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __restrict__ G,
                                                              long long gk, int bpa, int ch,
@@ -1195,16 +1207,38 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
                                                              T* __restrict__ q,
                                                              double* __restrict__ partial)
 {
+    __shared__ T sh[2][kPairs][4][64];
     March2 p;
     double acc = 0.0;
-    if (march2_pos(bk, g, bpa, ch, p)) {
+    const bool live = march2_pos(bk, g, bpa, ch, p);
+    // the chunk of planes is the block's: wavefronts past the last pair stay
+    // in the loop for its barriers (a neighbour's row is read only where the
+    // pair exists, i.e. its wavefront is live)
+    if (p.a0 < g.nr) {
         const Dir<T> X{z, pold, (T)*beta};
-        Col4<T> cm, c;
-        march2_start<T>(g, X, p, cm, c);
+        const int w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
         const long long o[4] = {0, g.P, g.nh, g.P + g.nh};
-        for (int a = p.a0; a < p.a1; ++a) {
+        Col4<T> cm, c;
+        if (live) march2_start<T>(g, X, p, cm, c);
+        for (int a = p.a0, buf = 0; a < p.a1; ++a, buf ^= 1) {
             Nb4<T> nb;
-            march2_load<T>(g, X, p, a, nb);
+            if (live) {
+                sh[buf][w][0][lane] = c.u0;
+                sh[buf][w][1][lane] = c.v0;
+                sh[buf][w][2][lane] = c.u1;
+                sh[buf][w][3][lane] = c.v1;
+                march2_load<T>(g, X, p, a, nb, w == 0, w == kPairs - 1);
+            }
+            __syncthreads();
+            if (!live) continue;
+            if (w > 0) {
+                nb.utm0 = sh[buf][w - 1][2][lane];
+                nb.vtm0 = sh[buf][w - 1][3][lane];
+            }
+            if (w < kPairs - 1) {
+                nb.utp1 = sh[buf][w + 1][0][lane];
+                nb.vtp1 = sh[buf][w + 1][1][lane];
+            }
             T yk[4];
             march2_apply<T>(g, G, gk, p, a, cm, c, nb, yk);
             const long long base = (long long)a * g.rowlen + p.r0;
