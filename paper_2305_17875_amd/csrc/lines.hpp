@@ -234,8 +234,10 @@ __host__ __device__ inline FftLineLaunch fft_line_launch(int nr, int nt, int np)
     FftLineLaunch p;
     const int nh = np / 2;
     p.tpr = nh / 2 < 64 ? nh / 2 : 64;
+    // a ring takes nh complex slots of the block's LDS (mode nh aliases slot
+    // 0), so a ring of kPlaneLds values still fits a block on its own
     p.rb = kBlock / p.tpr;
-    if (p.rb * (nh + 1) > kPlaneLds) p.rb = kPlaneLds / (nh + 1);
+    if (p.rb * nh > kPlaneLds) p.rb = kPlaneLds / nh;
     p.threads = p.rb * p.tpr;
     p.rings = nr * nt;
     p.blocks = (p.rings + p.rb - 1) / p.rb;
@@ -259,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_line_fft(int nr, int nt, int np, dou
     const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
     const int ring = (int)blockIdx.x * pl.rb + rl;
     const bool live = ring < pl.rings;
-    Vec2<double>* A = buf + rl * (nh + 1);
+    Vec2<double>* A = buf + rl * nh;
     const long long base = (long long)ring * np;
     if (live)
         for (int j0 = tr; j0 < nh; j0 += kLdBatch * pl.tpr) {
