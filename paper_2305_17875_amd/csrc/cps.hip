@@ -598,8 +598,12 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
 // sc[rz_slot] = in . out; zq: also sc[S_ZQ] = out . zq.  Both are taken
 // from passes that already touch the vectors where possible (the last
 // level-0 smoothing passes in FP64, the cast back in the mixed form).
+// Mixed form only: rhs_cast -- the FP32 right-hand side (in / scale) is
+// already in place (the conjugate-gradient step wrote it); out == nullptr --
+// the correction stays in FP32 (the next kernel forms it where it reads it)
+// and only the dot products are taken.
 void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1,
-                  const double* zq = nullptr)
+                  const double* zq = nullptr, bool rhs_cast = false)
 {
     const long long n = h->lv[0].n;
     if (h->opts.precision == 0) {
@@ -616,8 +620,11 @@ void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1
     } else {
         float* b = h->lv[0].b32.p;
         float* x = h->lv[0].x32.p;
-        k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, in, b, h->sc.p, S_SCALE, 1);
-        LAUNCH_CHECK();
+        if (!rhs_cast) {
+            k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, in, b, h->sc.p, S_SCALE,
+                                                                     1);
+            LAUNCH_CHECK();
+        }
         {
             ProfScope ps(h, CPS_KERNEL_VCYCLE, 0);
             vcycle<float>(h, b, x, true);
@@ -1160,11 +1167,17 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, z, p);
             LAUNCH_CHECK();
             reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
+            // the mixed form on the fused path: the step also casts the new
+            // residual into the FP32 right-hand side, and the direction is
+            // formed from the FP32 correction (no FP64 cast pass, z not stored)
+            const bool cast_fused = fused && mixed;
+            float* r32 = cast_fused ? h->lv[0].b32.p : nullptr;
             // x += alpha p, r -= alpha q and ||r||^2 (the first iteration's
             // step, and the tail of every later body)
             auto step = [&](double* pk) {
                 SCALAR_KERNEL(h, k_cg_alpha);
-                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, pk, q, h->partial.p);
+                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, pk, q, h->partial.p,
+                                                              r32);
                 LAUNCH_CHECK();
                 reduce(h, vgrid(n), S_RR);
                 copy_norm(h, S_RR);
@@ -1183,16 +1196,23 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                 run_body(h, G_CG0 + parity, [&] {
                     k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
                     LAUNCH_CHECK();
-                    precondition(h, r, z, S_RZ, flexible ? q : nullptr);
+                    precondition(h, r, cast_fused ? nullptr : z, S_RZ, flexible ? q : nullptr,
+                                 cast_fused);
                     k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
                     LAUNCH_CHECK();
                     if (fused) {
                         const MarchShape ms = stencil_shape(g0);
                         {
                             ProfScope ps(h, CPS_KERNEL_APPLY, 0); // the product only
-                            k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
-                                g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
-                                h->sc.p + S_BETA, pnx, q, h->partial.p);
+                            if (cast_fused)
+                                k_apply_dircast_march2<<<ms.grid, kBlock, 0, h->stream>>>(
+                                    g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch,
+                                    h->lv[0].x32.p, h->sc.p, S_SCALE, S_BETA, pc, pnx, q,
+                                    h->partial.p);
+                            else
+                                k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
+                                    g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
+                                    h->sc.p + S_BETA, pnx, q, h->partial.p);
                             LAUNCH_CHECK();
                         }
                         reduce(h, ms.grid, S_PQ);

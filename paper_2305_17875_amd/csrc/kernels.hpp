@@ -958,12 +958,37 @@ struct Plain {
     const T* __restrict__ x;
     __device__ __forceinline__ T operator()(long long i) const { return x[i]; }
 };
+// A product rounded on its own (never contracted into a later add), where
+// two paths must form bit-identical values.
+__device__ __forceinline__ double mul_rn(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+// The search direction p = z + beta p_old is one fma wherever it is formed
+// (here, in d_cg_dir and in the batched form), so all paths round alike.
 template <typename T>
 struct Dir {
     const T* __restrict__ z;
     const T* __restrict__ p;
     T beta;
-    __device__ __forceinline__ T operator()(long long i) const { return z[i] + beta * p[i]; }
+    __device__ __forceinline__ T operator()(long long i) const
+    {
+        return __builtin_fma(beta, p[i], z[i]);
+    }
+};
+// The same with z the FP32 correction of the mixed form, cast as k_cast_dots
+// casts it (z = (double) e * s, rounded before the direction is formed).
+struct DirCast {
+    const float* __restrict__ e;
+    double s;
+    const double* __restrict__ p;
+    double beta;
+    __device__ __forceinline__ double operator()(long long i) const
+    {
+        return __builtin_fma(beta, p[i], mul_rn((double)e[i], s));
+    }
 };
 
 // below / above: load the theta row below / above the pair (a caller that
@@ -1197,13 +1222,11 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
 // outermost rows are formed from memory.  Reading both z and p_old at every
 // neighbour instead doubles the L2 traffic of the stencil rows, and half of
 // it then misses.
-template <typename T, int LTAG>
+// X: the field p is formed from (Dir, or DirCast in the mixed form).
+template <typename T, int LTAG, typename X_>
 __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __restrict__ G,
                                                              long long gk, int bpa, int ch,
-                                                             const T* __restrict__ z,
-                                                             const T* __restrict__ pold,
-                                                             const double* __restrict__ beta,
-                                                             T* __restrict__ pnew,
+                                                             const X_ X, T* __restrict__ pnew,
                                                              T* __restrict__ q,
                                                              double* __restrict__ partial)
 {
@@ -1215,7 +1238,6 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
     // in the loop for its barriers (a neighbour's row is read only where the
     // pair exists, i.e. its wavefront is live)
     if (p.a0 < g.nr) {
-        const Dir<T> X{z, pold, (T)*beta};
         const int w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
         const long long o[4] = {0, g.P, g.nh, g.P + g.nh};
         Col4<T> cm, c;
@@ -1267,7 +1289,26 @@ __global__ void __launch_bounds__(kBlock) k_apply_dir_march2(Geo g, const T* __r
                                                              T* __restrict__ q,
                                                              double* __restrict__ partial)
 {
-    d_apply_dir_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, z, pold, beta, pnew, q, partial);
+    d_apply_dir_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, Dir<T>{z, pold, (T)*beta}, pnew,
+                                q, partial);
+}
+
+// The same in the mixed form: z = (double) e * sc[S_SCALE] from the FP32
+// correction e of the V-cycle, formed where it is read (z is not stored).
+__global__ void __launch_bounds__(kBlock) k_apply_dircast_march2(Geo g,
+                                                                 const double* __restrict__ G,
+                                                                 long long gk, int bpa, int ch,
+                                                                 const float* __restrict__ e,
+                                                                 const double* __restrict__ sc,
+                                                                 int scale_slot, int beta_slot,
+                                                                 const double* __restrict__ pold,
+                                                                 double* __restrict__ pnew,
+                                                                 double* __restrict__ q,
+                                                                 double* __restrict__ partial)
+{
+    d_apply_dir_march2<double, 0>(self_blk(), g, G, gk, bpa, ch,
+                                  DirCast{e, sc[scale_slot], pold, sc[beta_slot]}, pnew, q,
+                                  partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -1594,7 +1635,8 @@ __global__ void __launch_bounds__(kBlock) k_cast(long long n, const T* __restric
 }
 
 // z = (double) x * sc[slot] (the cast of k_cast) with per-block partial
-// sums of r . z and, when q is given, of q . z, in one grid-stride pass.
+// sums of r . z and, when q is given, of q . z, in one grid-stride pass;
+// z == nullptr: the sums only (z is formed again where it is read).
 __global__ void __launch_bounds__(kBlock) k_cast_dots(long long n, const float* __restrict__ x,
                                                       double* __restrict__ z,
                                                       const double* __restrict__ sc, int slot,
@@ -1608,8 +1650,8 @@ __global__ void __launch_bounds__(kBlock) k_cast_dots(long long n, const float* 
     double arz = 0.0, azq = 0.0;
     const long long stride = (long long)bk.G * blockDim.x;
     for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double v = (double)x[i] * s;
-        z[i] = v;
+        const double v = mul_rn((double)x[i], s);
+        if (z) z[i] = v;
         arz += r[i] * v;
         if (q) azq += q[i] * v;
     }
@@ -1701,15 +1743,20 @@ __device__ __forceinline__ void d_cg_step(Blk bk, long long n, const double* __r
                                                     double* __restrict__ r,
                                                     const double* __restrict__ p,
                                                     const double* __restrict__ q,
-                                                    double* __restrict__ partial)
+                                                    double* __restrict__ partial,
+                                                    float* __restrict__ r32 = nullptr)
 {
     const double al = sc[S_ALPHA];
+    // r32: also the FP32 right-hand side of the next mixed-form V-cycle,
+    // (float)(r / scale) as k_cast forms it
+    const double inv = r32 ? 1.0 / sc[S_SCALE] : 0.0;
     double acc = 0.0;
     const long long stride = (long long)bk.G * blockDim.x;
     for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride) {
         x[i] += al * p[i];
         const double v = r[i] - al * q[i];
         r[i] = v;
+        if (r32) r32[i] = (float)(v * inv);
         acc += v * v;
     }
     acc = block_sum(acc);
@@ -1721,9 +1768,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* _
                                                     double* __restrict__ r,
                                                     const double* __restrict__ p,
                                                     const double* __restrict__ q,
-                                                    double* __restrict__ partial)
+                                                    double* __restrict__ partial,
+                                                    float* __restrict__ r32)
 {
-    d_cg_step(self_blk(), n, sc, x, r, p, q, partial);
+    d_cg_step(self_blk(), n, sc, x, r, p, q, partial, r32);
 }
 
 // p = z + beta p
@@ -1732,7 +1780,7 @@ __device__ __forceinline__ void d_cg_dir(Blk bk, long long n, const double* __re
                                                    double* __restrict__ p)
 {
     const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = z[i] + sc[S_BETA] * p[i];
+    if (i < n) p[i] = __builtin_fma(sc[S_BETA], p[i], z[i]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_cg_dir(long long n, const double* __restrict__ sc,
