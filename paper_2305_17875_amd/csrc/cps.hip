@@ -1173,11 +1173,14 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             const bool cast_fused = fused && mixed;
             float* r32 = cast_fused ? h->lv[0].b32.p : nullptr;
             // x += alpha p, r -= alpha q and ||r||^2 (the first iteration's
-            // step, and the tail of every later body)
+            // step, and the tail of every later body).  On the fused path the
+            // next direction kernel applies x += alpha p instead (it streams
+            // p anyway), and the last update runs after the loop.
+            double* plast = p; // direction of the last step
             auto step = [&](double* pk) {
                 SCALAR_KERNEL(h, k_cg_alpha);
-                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, x, r, pk, q, h->partial.p,
-                                                              r32);
+                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, fused ? nullptr : x, r, pk,
+                                                              q, h->partial.p, r32);
                 LAUNCH_CHECK();
                 reduce(h, vgrid(n), S_RR);
                 copy_norm(h, S_RR);
@@ -1208,11 +1211,12 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                                 k_apply_dircast_march2<<<ms.grid, kBlock, 0, h->stream>>>(
                                     g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch,
                                     h->lv[0].x32.p, h->sc.p, S_SCALE, S_BETA, pc, pnx, q,
-                                    h->partial.p);
+                                    h->partial.p, x);
                             else
                                 k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
                                     g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
-                                    h->sc.p + S_BETA, pnx, q, h->partial.p);
+                                    h->sc.p + S_BETA, pnx, q, h->partial.p, x,
+                                    h->sc.p + S_ALPHA);
                             LAUNCH_CHECK();
                         }
                         reduce(h, ms.grid, S_PQ);
@@ -1224,7 +1228,12 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                         step(p);
                     }
                 });
+                if (fused) plast = pnx;
                 st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
+            }
+            if (fused) { // the update the last step left pending
+                k_cg_x<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, plast, x);
+                LAUNCH_CHECK();
             }
         } else {
             // BiCGStab (accel = 2), right-preconditioned by the V-cycle

@@ -30,6 +30,12 @@ namespace cps {
 
 enum { MODE_ORTHO = 0, MODE_RT = 1, MODE_FULL = 2 };
 
+// device scalar slots of the Krylov solvers (sc[])
+enum {
+    S_BB = 0, S_RR, S_RZ, S_RZ_OLD, S_PQ, S_ZQ, S_ALPHA, S_BETA, S_OMEGA, S_RHO, S_RHO_OLD,
+    S_TS, S_TT, S_R0V, S_SUM, S_SCALE, S_COUNT
+};
+
 constexpr int kBlock = 256;
 
 // geometry of one level in the parity-split layout
@@ -958,9 +964,17 @@ struct Plain {
     const T* __restrict__ x;
     __device__ __forceinline__ T operator()(long long i) const { return x[i]; }
 };
-// A product rounded on its own (never contracted into a later add), where
-// two paths must form bit-identical values.
-__device__ __forceinline__ double mul_rn(double a, double b)
+// Where two paths must form bit-identical values (a single solve and the
+// batched form), the products that feed a sum are written as explicit fmas
+// and a product that must round on its own goes through mul_t: whether the
+// compiler contracts a * b + c otherwise depends on the surrounding code.
+__device__ __forceinline__ double fma_t(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <typename T>
+__device__ __forceinline__ T mul_t(T a, T b)
 {
 #pragma clang fp contract(off)
     return a * b;
@@ -987,7 +1001,7 @@ struct DirCast {
     double beta;
     __device__ __forceinline__ double operator()(long long i) const
     {
-        return __builtin_fma(beta, p[i], mul_rn((double)e[i], s));
+        return __builtin_fma(beta, p[i], mul_t((double)e[i], s));
     }
 };
 
@@ -1042,10 +1056,20 @@ __device__ __forceinline__ void row_apply(const T* __restrict__ G, long long gk,
     const T gtl = G[4 * gk + ci];
     const T gth = th ? G[4 * gk + ci + 1] : T(0);
     const T gpp = G[8 * gk + ci];
-    y0 = grh * (up - u) - grl * (u - um) + gth * (utp - u) - gtl * (u - utm) + gpp * (v - u) -
-         gpp * (u - vjm);
-    y1 = grh * (vp - v) - grl * (v - vm) + gth * (vtp - v) - gtl * (v - vtm) + gpp * (ujp - v) -
-         gpp * (v - u);
+    // the sums as explicit fma chains (the row-pair product must round alike
+    // in every kernel that inlines it)
+    T s0 = mul_t(grh, up - u);
+    s0 = fma_t(-grl, u - um, s0);
+    s0 = fma_t(gth, utp - u, s0);
+    s0 = fma_t(-gtl, u - utm, s0);
+    s0 = fma_t(gpp, v - u, s0);
+    y0 = fma_t(-gpp, u - vjm, s0);
+    T s1 = mul_t(grh, vp - v);
+    s1 = fma_t(-grl, v - vm, s1);
+    s1 = fma_t(gth, vtp - v, s1);
+    s1 = fma_t(-gtl, v - vtm, s1);
+    s1 = fma_t(gpp, ujp - v, s1);
+    y1 = fma_t(-gpp, v - u, s1);
 }
 
 // (A x) of the four cells of a row-pair thread at plane a.
@@ -1188,7 +1212,7 @@ __device__ __forceinline__ void d_apply_march2(Blk bk, Geo g, const T* __restric
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         st_once(y + base + o[k], yk[k]);
-                        if (dotv) acc += (double)yk[k] * (double)dv[u][k];
+                        if (dotv) acc = __builtin_fma((double)yk[k], (double)dv[u][k], acc);
                     }
                     cm = c;
                     c = nb[u].up;
@@ -1223,12 +1247,18 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
 // neighbour instead doubles the L2 traffic of the stencil rows, and half of
 // it then misses.
 // X: the field p is formed from (Dir, or DirCast in the mixed form).
+// xs != nullptr: also the previous step's pending update of the iterate,
+// xs += alpha p_old on the thread's own cells (one fma, as in d_cg_step),
+// so the step itself need not stream x and p.
 template <typename T, int LTAG, typename X_>
 __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __restrict__ G,
                                                              long long gk, int bpa, int ch,
                                                              const X_ X, T* __restrict__ pnew,
                                                              T* __restrict__ q,
-                                                             double* __restrict__ partial)
+                                                             double* __restrict__ partial,
+                                                             T* __restrict__ xs = nullptr,
+                                                             const T* __restrict__ pold = nullptr,
+                                                             T alpha = T(0))
 {
     __shared__ T sh[2][kPairs][4][64];
     March2 p;
@@ -1244,12 +1274,21 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
         if (live) march2_start<T>(g, X, p, cm, c);
         for (int a = p.a0, buf = 0; a < p.a1; ++a, buf ^= 1) {
             Nb4<T> nb;
+            const long long base = (long long)a * g.rowlen + p.r0;
+            T xo[4], po[4];
             if (live) {
                 sh[buf][w][0][lane] = c.u0;
                 sh[buf][w][1][lane] = c.v0;
                 sh[buf][w][2][lane] = c.u1;
                 sh[buf][w][3][lane] = c.v1;
                 march2_load<T>(g, X, p, a, nb, w == 0, w == kPairs - 1);
+                if (xs) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        xo[k] = ld_once(xs + base + o[k]);
+                        po[k] = pold[base + o[k]];
+                    }
+                }
             }
             __syncthreads();
             if (!live) continue;
@@ -1263,13 +1302,13 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
             }
             T yk[4];
             march2_apply<T>(g, G, gk, p, a, cm, c, nb, yk);
-            const long long base = (long long)a * g.rowlen + p.r0;
             const T own[4] = {c.u0, c.v0, c.u1, c.v1};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 st_once(pnew + base + o[k], own[k]);
                 st_once(q + base + o[k], yk[k]);
-                acc += (double)yk[k] * (double)own[k];
+                acc = __builtin_fma((double)yk[k], (double)own[k], acc);
+                if (xs) st_once(xs + base + o[k], __builtin_fma(alpha, po[k], xo[k]));
             }
             cm = c;
             c = nb.up;
@@ -1287,10 +1326,12 @@ __global__ void __launch_bounds__(kBlock) k_apply_dir_march2(Geo g, const T* __r
                                                              const double* __restrict__ beta,
                                                              T* __restrict__ pnew,
                                                              T* __restrict__ q,
-                                                             double* __restrict__ partial)
+                                                             double* __restrict__ partial,
+                                                             T* __restrict__ xs,
+                                                             const double* __restrict__ alpha)
 {
     d_apply_dir_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, Dir<T>{z, pold, (T)*beta}, pnew,
-                                q, partial);
+                                q, partial, xs, pold, xs ? (T)*alpha : T(0));
 }
 
 // The same in the mixed form: z = (double) e * sc[S_SCALE] from the FP32
@@ -1304,11 +1345,12 @@ __global__ void __launch_bounds__(kBlock) k_apply_dircast_march2(Geo g,
                                                                  const double* __restrict__ pold,
                                                                  double* __restrict__ pnew,
                                                                  double* __restrict__ q,
-                                                                 double* __restrict__ partial)
+                                                                 double* __restrict__ partial,
+                                                                 double* __restrict__ xs)
 {
     d_apply_dir_march2<double, 0>(self_blk(), g, G, gk, bpa, ch,
                                   DirCast{e, sc[scale_slot], pold, sc[beta_slot]}, pnew, q,
-                                  partial);
+                                  partial, xs, pold, xs ? sc[S_ALPHA] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,7 +1635,7 @@ __device__ __forceinline__ void d_dot(Blk bk, long long n, const T* __restrict__
     double acc = 0.0;
     const long long stride = (long long)bk.G * blockDim.x;
     for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride)
-        acc += v ? (double)u[i] * (double)v[i] : (double)u[i];
+        acc = v ? __builtin_fma((double)u[i], (double)v[i], acc) : acc + (double)u[i];
     acc = block_sum(acc);
     if (threadIdx.x == 0) partial[bk.L] = acc;
 }
@@ -1650,10 +1692,10 @@ __global__ void __launch_bounds__(kBlock) k_cast_dots(long long n, const float* 
     double arz = 0.0, azq = 0.0;
     const long long stride = (long long)bk.G * blockDim.x;
     for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double v = mul_rn((double)x[i], s);
+        const double v = mul_t((double)x[i], s);
         if (z) z[i] = v;
-        arz += r[i] * v;
-        if (q) azq += q[i] * v;
+        arz = __builtin_fma(r[i], v, arz);
+        if (q) azq = __builtin_fma(q[i], v, azq);
     }
     arz = block_sum(arz);
     if (threadIdx.x == 0) prz[bk.L] = arz;
@@ -1712,12 +1754,9 @@ __global__ void __launch_bounds__(kBlock) k_ir_update(long long n, double* __res
     d_ir_update<U>(self_blk(), n, x, e, s);
 }
 
-// Scalar recurrences of the Krylov solvers, evaluated by one thread on
-// device scalars (sc[] slots) so that no host round trip is needed.
-enum {
-    S_BB = 0, S_RR, S_RZ, S_RZ_OLD, S_PQ, S_ZQ, S_ALPHA, S_BETA, S_OMEGA, S_RHO, S_RHO_OLD,
-    S_TS, S_TT, S_R0V, S_SUM, S_SCALE, S_COUNT
-};
+// Scalar recurrences of the Krylov solvers are evaluated by one thread on
+// device scalars (the sc[] slots declared at the top) so that no host round trip is
+// needed.
 
 // CG / flexible CG: alpha = rz / pq
 __global__ void k_cg_alpha(double* sc) { sc[S_ALPHA] = sc[S_RZ] / sc[S_PQ]; }
@@ -1753,11 +1792,11 @@ __device__ __forceinline__ void d_cg_step(Blk bk, long long n, const double* __r
     double acc = 0.0;
     const long long stride = (long long)bk.G * blockDim.x;
     for (long long i = (long long)bk.L * blockDim.x + threadIdx.x; i < n; i += stride) {
-        x[i] += al * p[i];
-        const double v = r[i] - al * q[i];
+        if (x) x[i] = __builtin_fma(al, p[i], x[i]);
+        const double v = __builtin_fma(-al, q[i], r[i]);
         r[i] = v;
         if (r32) r32[i] = (float)(v * inv);
-        acc += v * v;
+        acc = __builtin_fma(v, v, acc);
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) partial[bk.L] = acc;
@@ -1772,6 +1811,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* _
                                                     float* __restrict__ r32)
 {
     d_cg_step(self_blk(), n, sc, x, r, p, q, partial, r32);
+}
+
+// x += alpha p: the update the last step of a solve leaves pending when the
+// direction kernel carries the iterate's updates
+__global__ void __launch_bounds__(kBlock) k_cg_x(long long n, const double* __restrict__ sc,
+                                                 const double* __restrict__ p,
+                                                 double* __restrict__ x)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = __builtin_fma(sc[S_ALPHA], p[i], x[i]);
 }
 
 // p = z + beta p
