@@ -410,24 +410,32 @@ def rhs_pool(inputs, shapes, per_shape):
 
 
 class OutPool:
-    """Reusable pinned output arrays per shape (taken at submission,
-    returned once the request has been waited for)."""
+    """Pinned output arrays per shape, all allocated up front (taken at
+    submission, returned once the request has been waited for).  No host
+    memory is pinned while the stream runs: pinning memory on the submitting
+    thread while a service worker captures a hipGraph has invalidated that
+    capture.  take() waits for a returned array when none is free."""
 
-    def __init__(self):
+    def __init__(self, shapes, per_shape):
         import threading
-        self.free = {}
-        self.lock = threading.Lock()
+        self.free = {s: [pinned(s) for _ in range(per_shape)] for s in shapes}
+        self.cv = threading.Condition()
 
-    def take(self, shape):
-        with self.lock:
-            lst = self.free.setdefault(shape, [])
-            if lst:
-                return lst.pop()
-        return pinned(shape)
+    def take(self, shape, timeout=60.0):
+        with self.cv:
+            if not self.cv.wait_for(lambda: self.free[shape], timeout=timeout):
+                raise RuntimeError(f"no free output array of shape {shape} in {timeout} s")
+            return self.free[shape].pop()
 
     def give(self, a):
-        with self.lock:
-            self.free.setdefault(a.shape, []).append(a)
+        with self.cv:
+            self.free[a.shape].append(a)
+            self.cv.notify_all()
+
+
+# output arrays per request size: more than the requests of one size ever in
+# flight at once (they complete in tens of ms at 200 arrivals/s)
+OUT_PER_SHAPE = 24
 
 
 def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoother=2):
@@ -444,7 +452,7 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoot
                       smoother=smoother)
     # warm the code paths once per (size, class) so that start-up compiles
     # and tuning are not in the measured stream
-    outs = OutPool()
+    outs = OutPool(inputs.SIZE_SET, OUT_PER_SHAPE)
     for s in inputs.SIZE_SET:
         for g in (inputs.Shell(*s), inputs.Shell(*s, map=inputs.MAP_OBLATE, flattening=0.1)):
             o = outs.take(s)

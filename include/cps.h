@@ -285,7 +285,13 @@ void cps_batch_destroy(cps_batch* b);
  * first when a new one does not fit.  Every request runs exactly the code of
  * cps_solve with the service's opts, so its p equals the same problem solved
  * alone with cps_setup/cps_solve, bit for bit.  All functions are
- * thread-safe; latency is measured from submission to completion. */
+ * thread-safe; latency is measured from submission to completion.
+ * A worker captures each hierarchy's iteration bodies into hipGraphs on its
+ * own non-blocking stream.  The library never frees, allocates or uploads
+ * while any of its captures is open; code elsewhere in the process that
+ * synchronises the whole device meanwhile (hipDeviceSynchronize, hipFree,
+ * hipHostMalloc) can invalidate a capture, and that request then fails
+ * with CPS_E_HIP. */
 typedef struct cps_service cps_service;
 
 typedef struct {

@@ -89,7 +89,7 @@ void build_items(ItemTable& t, const std::vector<std::pair<int, int>>& pg)
         for (int L = 0; L < q.second; ++L) v.push_back(BItem{q.first, (unsigned)L, (unsigned)q.second});
     t.count = (int)v.size();
     t.d.alloc(v.size());
-    if (!v.empty()) HIPC(hipMemcpy(t.d.p, v.data(), v.size() * sizeof(BItem), hipMemcpyHostToDevice));
+    if (!v.empty()) upload(t.d.p, v.data(), v.size() * sizeof(BItem));
 }
 
 } // namespace
@@ -246,11 +246,12 @@ void bicg_body(cps_batch* B, BatchGroup& G)
 template <typename F>
 void capture(cps_batch* B, hipGraph_t& graph, hipGraphExec_t& exec, F&& f)
 {
+    std::shared_lock<std::shared_mutex> cap(g_capture_mu); // no free or sync meanwhile
     HIPC(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
     try {
         f();
     } catch (...) {
-        hipGraph_t g2;
+        hipGraph_t g2 = nullptr;
         (void)hipStreamEndCapture(B->stream, &g2);
         if (g2) (void)hipGraphDestroy(g2);
         throw;
@@ -370,14 +371,18 @@ void batch_destroy(cps_batch* B)
     if (!B) return;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
     for (auto& G : B->grp) {
+        MemLock lk(g_capture_mu); // graph teardown
         if (G.gA) (void)hipGraphExecDestroy(G.gA);
         if (G.gB) (void)hipGraphExecDestroy(G.gB);
         if (G.graphA) (void)hipGraphDestroy(G.graphA);
         if (G.graphB) (void)hipGraphDestroy(G.graphB);
     }
     for (cps_handle* h : B->h) destroy(h);
-    if (B->hactive) (void)hipHostFree(B->hactive);
-    if (B->hgath) (void)hipHostFree(B->hgath);
+    {
+        MemLock lk(g_capture_mu);
+        if (B->hactive) (void)hipHostFree(B->hactive);
+        if (B->hgath) (void)hipHostFree(B->hgath);
+    }
     hipStream_t s = B->own_stream ? B->stream : nullptr;
     delete B;
     if (s) (void)hipStreamDestroy(s);
@@ -390,7 +395,8 @@ void batch_build(cps_batch* B, int n, const cps_grid* grids, const cps_metrics* 
     if (opts && opts->stream) {
         B->stream = (hipStream_t)opts->stream;
     } else {
-        HIPC(hipStreamCreate(&B->stream)); // default priority
+        // default priority; non-blocking (see the service workers' streams)
+        HIPC(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking));
         B->own_stream = true;
     }
     cps_opts o = opts ? *opts : cps_opts{};
@@ -413,8 +419,11 @@ void batch_build(cps_batch* B, int n, const cps_grid* grids, const cps_metrics* 
     B->pd.alloc(n);
     B->active.alloc(n);
     B->gath.alloc(n);
-    HIPC(hipHostMalloc(&B->hactive, n * sizeof(int), hipHostMallocDefault));
-    HIPC(hipHostMalloc(&B->hgath, n * sizeof(double), hipHostMallocDefault));
+    {
+        MemLock lk(g_capture_mu);
+        HIPC(hipHostMalloc(&B->hactive, n * sizeof(int), hipHostMallocDefault));
+        HIPC(hipHostMalloc(&B->hgath, n * sizeof(double), hipHostMallocDefault));
+    }
     // groups
     BatchGroup& g0 = B->grp[0];
     BatchGroup& g1 = B->grp[1];

@@ -27,6 +27,7 @@
 #include <vector>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <condition_variable>
 #include <deque>
 #include <memory>
@@ -117,6 +118,25 @@ void dispatch(int mode, bool axi, F&& f)
     }
 }
 
+// Graph capture and memory management exclude each other, process-wide.
+// Freeing device memory synchronises the device, and a device-wide (or
+// null-stream) synchronisation while another thread's stream is being
+// captured invalidates that capture: with several service workers (or a
+// service beside other handles), one worker building or dropping a
+// hierarchy would break another's capture of its iteration bodies.
+// Captures take the lock shared (they may overlap each other: each is on
+// its own non-blocking stream); device and pinned host allocations, frees
+// and synchronous null-stream uploads take it exclusively.
+std::shared_mutex g_capture_mu;
+using MemLock = std::unique_lock<std::shared_mutex>;
+
+// A synchronous upload of set-up tables (pageable host memory).
+void upload(void* dst, const void* src, size_t bytes)
+{
+    MemLock lk(g_capture_mu);
+    HIPC(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+}
+
 // Owning device buffer (freed on destruction; not copyable).
 template <typename T>
 struct Buf {
@@ -128,6 +148,7 @@ struct Buf {
     ~Buf() { release(); }
     void alloc(size_t count)
     {
+        MemLock lk(g_capture_mu);
         if (p) HIPC(hipFree(p));
         p = nullptr;
         n = count;
@@ -135,7 +156,9 @@ struct Buf {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (!p) return;
+        MemLock lk(g_capture_mu);
+        (void)hipFree(p);
         p = nullptr;
         n = 0;
     }
@@ -166,6 +189,11 @@ struct cps_handle {
     cps_metrics met{};
     cps_opts opts{};
     hipStream_t stream = nullptr;
+    // coarsest-inverse scratch (augmented matrix, dense operator, panel
+    // buffers, pivots); kept between set-ups when keep_gj
+    Buf<double> gjA, gjM, gjE, gjXp;
+    Buf<int> gjUsed, gjPiv, gjBad;
+    bool keep_gj = false;
     int L = 0;
     LevelMem lv[kMaxLevels];
     int mode = MODE_ORTHO;
@@ -659,6 +687,7 @@ void run_body(cps_handle* h, int key, F&& body)
     }
     hipGraphExec_t& ex = h->gexec[key];
     if (!ex) {
+        std::shared_lock<std::shared_mutex> cap(g_capture_mu); // no free or sync meanwhile
         hipGraph_t g = nullptr;
         HIPC(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
         try {
@@ -847,15 +876,26 @@ int compute_operator(cps_handle* h)
     // coarsest dense inverse of A_c + alpha 1 1^T
     const int n = h->nc;
     {
-        Buf<double> A, M0, E, Xp;
-        Buf<int> used, piv, bad;
-        A.alloc((size_t)n * n);
-        M0.alloc((size_t)n * 2 * n);
-        E.alloc((size_t)n * kGJ);
-        Xp.alloc((size_t)kGJ * 2 * n);
-        used.alloc(n);
-        piv.alloc(n);
-        bad.alloc(1);
+        // scratch of the inversion: kept by hierarchies whose map is
+        // recomputed in place (a pooled service entry), so that a remap
+        // allocates and frees nothing (a free synchronises the device)
+        Buf<double>& A = h->gjA;
+        Buf<double>& M0 = h->gjM;
+        Buf<double>& E = h->gjE;
+        Buf<double>& Xp = h->gjXp;
+        Buf<int>& used = h->gjUsed;
+        Buf<int>& piv = h->gjPiv;
+        Buf<int>& bad = h->gjBad;
+        auto need = [](auto& b, size_t count) {
+            if (b.n != count || !b.p) b.alloc(count);
+        };
+        need(A, (size_t)n * n);
+        need(M0, (size_t)n * 2 * n);
+        need(E, (size_t)n * kGJ);
+        need(Xp, (size_t)kGJ * 2 * n);
+        need(used, n);
+        need(piv, n);
+        need(bad, 1);
         if (!h->Ainv.p) h->Ainv.alloc((size_t)n * n);
         HIPC(hipMemsetAsync(A.p, 0, (size_t)n * n * sizeof(double), h->stream));
         const Level<double> Lc = view<double>(h, h->L - 1);
@@ -897,9 +937,11 @@ int compute_operator(cps_handle* h)
         int hbad = 0;
         HIPC(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIPC(hipStreamSynchronize(h->stream));
+        if (!h->keep_gj) {
+            A.release(); M0.release(); E.release(); Xp.release();
+            used.release(); piv.release(); bad.release();
+        }
         if (hbad) fail(CPS_E_INVALID, "coarsest operator is singular");
-        A.release(); M0.release(); E.release(); Xp.release();
-        used.release(); piv.release(); bad.release();
     }
     if (h->lv[0].pv64.p || h->lv[0].pv32.p) plane_factors(h); // new metrics of a set-up hierarchy
     h->cm_valid = false; // the projection step's face tables follow the map
@@ -966,12 +1008,12 @@ void setup_plane(cps_handle* h)
         }
         auto up64 = [&](Buf<double>& d, const std::vector<double>& v) {
             d.alloc(v.size());
-            HIPC(hipMemcpy(d.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+            upload(d.p, v.data(), v.size() * sizeof(double));
         };
         auto up32 = [&](Buf<float>& d, const std::vector<double>& v) {
             std::vector<float> f(v.begin(), v.end());
             d.alloc(f.size());
-            HIPC(hipMemcpy(d.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+            upload(d.p, f.data(), f.size() * sizeof(float));
         };
         up64(m.tw64, tw); up64(m.twN64, twN); up64(m.lam64, lam);
         if (mixed) { up32(m.tw32, tw); up32(m.twN32, twN); up32(m.lam32, lam); }
@@ -1025,7 +1067,10 @@ void build(cps_handle* h)
     // two passes' (or two reductions') partial sums side by side
     h->partial.alloc(2 * std::max<long long>(nblk(n0), kMaxGrid) + 64);
     h->sc.alloc(S_COUNT);
-    HIPC(hipHostMalloc(&h->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
+    {
+        MemLock lk(g_capture_mu);
+        HIPC(hipHostMalloc(&h->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
+    }
     h->x0.alloc(n0);
     h->b0.alloc(n0);
     h->r.alloc(n0);
@@ -1062,9 +1107,12 @@ void destroy(cps_handle* h)
     h->pC.release(); h->pJf.release(); h->pJc.release(); h->prhs.release(); h->prot.release();
     h->plf[0].release(); h->plf[1].release(); h->pls.release(); h->plam.release();
     h->ptw.release(); h->ptwN.release();
-    for (hipGraphExec_t& g : h->gexec)
-        if (g) (void)hipGraphExecDestroy(g);
-    if (h->hsc) (void)hipHostFree(h->hsc);
+    {
+        MemLock lk(g_capture_mu); // graph teardown and the pinned free
+        for (hipGraphExec_t& g : h->gexec)
+            if (g) (void)hipGraphExecDestroy(g);
+        if (h->hsc) (void)hipHostFree(h->hsc);
+    }
     for (auto& v : h->ev)
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
     delete h;
@@ -1479,7 +1527,7 @@ void ensure_ring_tables(cps_handle* h)
     }
     auto up = [&](Buf<double>& d, const std::vector<double>& v) {
         d.alloc(v.size());
-        HIPC(hipMemcpy(d.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+        upload(d.p, v.data(), v.size() * sizeof(double));
     };
     up(h->ptw, tw);
     up(h->ptwN, twN);

@@ -75,6 +75,8 @@ size_t handle_bytes(const cps_handle* h)
     add(h->x0); add(h->b0); add(h->r); add(h->z); add(h->pd); add(h->q);
     add(h->r0); add(h->v); add(h->s); add(h->t); add(h->ph); add(h->sh);
     add(h->ps64); add(h->ps32);
+    add(h->gjA); add(h->gjM); add(h->gjE); add(h->gjXp);
+    add(h->gjUsed); add(h->gjPiv); add(h->gjBad);
     for (int l = 0; l < h->L; ++l) {
         const LevelMem& m = h->lv[l];
         add(m.tw64); add(m.twN64); add(m.lam64); add(m.tw32); add(m.twN32); add(m.lam32);
@@ -83,8 +85,9 @@ size_t handle_bytes(const cps_handle* h)
     return s;
 }
 
-// device bytes a hierarchy of this grid will take, including the transient
-// Gauss-Jordan buffers of its set-up
+// device bytes a hierarchy of this grid will take, including the
+// Gauss-Jordan buffers of the coarsest inverse (which a service hierarchy
+// keeps for its remaps)
 size_t estimate_bytes(const cps_grid& g, const cps_opts& o)
 {
     int dims[kMaxLevels][3];
@@ -114,8 +117,8 @@ size_t estimate_bytes(const cps_grid& g, const cps_opts& o)
         for (int l = 0; l + 1 < L; ++l)
             s += (size_t)dims[l][0] * dims[l][1] * (dims[l][2] / 2 + 1) * w;
     }
-    s += (2 * std::max<size_t>(n0 / kBlock + 1, kMaxGrid) + 64) * 8 + nc * nc * 8 * 4 +
-         nc * kGJ * 8 * 3;
+    s += (2 * std::max<size_t>(n0 / kBlock + 1, kMaxGrid) + 64 + S_COUNT) * 8 +
+         nc * nc * 8 * 4 + nc * kGJ * 8 * 3 + (2 * nc + 1) * 4;
     return s;
 }
 
@@ -169,6 +172,7 @@ cps_handle* new_hierarchy(const cps_service* S, const SvcReq* R, hipStream_t str
     h->met = R->met;
     h->opts = S->opts;
     h->stream = stream;
+    h->keep_gj = true; // remaps recompute the coarsest inverse in place
     try {
         build(h);
     } catch (...) {
@@ -245,7 +249,10 @@ void svc_worker(cps_service* S)
 {
     (void)hipSetDevice(S->device);
     hipStream_t stream = nullptr;
-    if (hipStreamCreate(&stream) != hipSuccess) return; // default priority
+    // default priority; non-blocking: null-stream work elsewhere in the
+    // process must not synchronise with (and so invalidate) this stream's
+    // graph captures
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return;
     for (;;) {
         SvcReq* R = nullptr;
         PoolEnt* pe = nullptr;

@@ -110,7 +110,9 @@ def test_service_budget_queues_evicts_and_rejects():
     finally:
         probe.close()
     budget = max(fa, fb) + min(fa, fb) // 5
-    assert 0 < resident_a < fa and resident_a + fb > budget and fh > budget
+    # the footprint covers the resident hierarchy (a service hierarchy keeps
+    # the scratch of its coarsest inverse for remaps, so the two can be equal)
+    assert 0 < resident_a <= fa and resident_a + fb > budget and fh > budget
     reqs = [(g, inputs.smoothed_noise(g.shape, 40 + i))
             for i, g in enumerate([ga, gb, ga, gb])]
     log("service budget", budget)
