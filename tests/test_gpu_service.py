@@ -177,3 +177,41 @@ def test_autotuned_solve_gives_the_same_bits(tmp_path, monkeypatch):
     import json
     keys = json.loads(cache.read_text())
     assert "gs_march/f64/32x32x64" in keys and "gs_march/f32/32x32x64" in keys
+
+
+def test_service_concurrent_builds_captures_and_remaps():
+    """Eight workers, all requests submitted at once: fresh hierarchies of
+    several shapes (each first solve captures its iteration bodies into
+    graphs) interleave with in-place remaps (every oblate request has its
+    own flattening, so its coarsest inverse is recomputed) on the other
+    workers.  Every request succeeds (no capture is invalidated by another
+    worker's allocation, free or upload), and sampled results equal the
+    same problems solved alone, bit for bit."""
+    rng = np.random.default_rng(77)
+    shapes = [(16, 16, 16), (16, 16, 32), (32, 16, 32), (16, 32, 64), (32, 32, 32), (32, 32, 64)]
+    reqs = []
+    for k in range(72):
+        s = shapes[k % len(shapes)]
+        if k % 2:
+            g = Shell(*s, map=MAP_OBLATE, flattening=float(rng.uniform(0.02, 0.15)))
+        else:
+            g = Shell(*s, radial_stretch=float(rng.uniform(0.0, 2.0)))
+        reqs.append((g, inputs.smoothed_noise(s, 500 + k)))
+    log("service concurrency", len(reqs))
+    for smoother in (0, 2):
+        svc = cps.Service(4 * GiB, max_slots=8, precision=1, smoother=smoother)
+        try:
+            out = run(svc, reqs)
+            st = svc.stats()
+        finally:
+            svc.close()
+        assert all(o[0] == cps.CPS_OK for o in out), [o[0] for o in out]
+        assert st["map_rebuilds"] > 0 and st["hierarchies_built"] >= len(shapes), st
+        for i in (0, 7, 31, 70):
+            g, b = reqs[i]
+            s = cps.Solver(g, precision=1, accel=1, smoother=smoother)
+            try:
+                xa = host(s.solve(dev(b).flatten()).p).reshape(g.shape)
+            finally:
+                s.close()
+            assert np.array_equal(out[i][1], xa), (smoother, i)
