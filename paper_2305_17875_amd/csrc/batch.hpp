@@ -324,7 +324,7 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
             if (l + 1 >= h->L) continue;
             const Geo& g = h->lv[l].geo;
             if (G.march) {
-                gs.push_back({p, stencil_shape(g, h->lv[l].gs_ch).grid});
+                gs.push_back({p, gs_shape<float>(g, h->lv[l].gs_ch).grid});
                 res.push_back({p, stencil_shape(g).grid});
             } else {
                 gs.push_back({p, (int)grid_of(g.nr, gs_bpa(g, h->ncol))});

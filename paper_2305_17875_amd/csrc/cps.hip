@@ -328,7 +328,7 @@ long long gs_pass(cps_handle* h, int l, int colour, const T* b, T* x, bool zero 
     // grouped: timed with its neighbours by the caller
     ProfScope ps(h, zero || grouped ? -1 : CPS_KERNEL_GS, l);
     if (marching(h)) {
-        const MarchShape ms = stencil_shape(L.g, h->lv[l].gs_ch);
+        const MarchShape ms = gs_shape<T>(L.g, h->lv[l].gs_ch);
         if (row_pairs(L.g)) {
             auto launch = [&](auto T_, auto Z) {
                 k_gs_march2<T, decltype(T_)::value, decltype(Z)::value>

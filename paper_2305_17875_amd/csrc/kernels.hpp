@@ -784,6 +784,9 @@ __device__ __forceinline__ bool march2_pos(Blk bk, const Geo& g, int bpa, int ch
     const int bp = pg * kPairs + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     p.a0 = chunk * ch;
     p.a1 = min(g.nr, p.a0 + ch);
+    p.b0 = p.j = p.lane = 0; // defined for the wavefronts that drop out too
+    p.r0 = 0;
+    p.ring = false;
     // pairs past the last one: whole wavefronts drop out
     if (bp >= (g.nt >> 1) || p.a0 >= g.nr) return false;
     p.b0 = 2 * bp;
@@ -802,10 +805,21 @@ __device__ __forceinline__ bool march2_pos(Blk bk, const Geo& g, int bpa, int ch
 // iterate, x = b / D.
 template <typename T, int AHEAD>
 __device__ __forceinline__ void gs_march2_body(const Geo& g, const T* __restrict__ G, long long gk,
-                                               const March2& p, const T* __restrict__ bv,
-                                               T* __restrict__ x, int colour, int zero,
-                                               double& acc)
+                                               const March2& p, bool live,
+                                               const T* __restrict__ bv, T* __restrict__ x,
+                                               int colour, int zero, double& acc)
 {
+    // full FP64 passes: the other-colour values of the rows next to a pair
+    // (its theta neighbours) are the adjacent wavefronts' own column values;
+    // they come through LDS (double-buffered, one barrier per AHEAD planes)
+    // and only the block's outermost rows are read from memory.  Every
+    // wavefront of a block with planes stays in the loop for the barriers.
+    // FP32 passes read those rows themselves: with half the bytes per plane
+    // the barrier costs more than the loads it saves (38.5 against 37.1 us).
+    constexpr bool kLds = sizeof(T) == 8;
+    __shared__ T sh[kLds ? 2 : 1][AHEAD][kPairs][2][64];
+    if (p.a0 >= g.nr || (zero && !live)) return; // block-uniform / no barriers
+    const int w = (int)threadIdx.x >> 6;
     const long long sr = g.rowlen, r0 = p.r0, r1 = p.r0 + g.nh;
     const int b0 = p.b0, b1 = b0 + 1, nh = g.nh, j = p.j, lane = p.lane;
     const bool tlo = b0 > 0, thi = b1 < g.nt - 1;
@@ -859,24 +873,52 @@ __device__ __forceinline__ void gs_march2_body(const Geo& g, const T* __restrict
     // a row whose updated cells are in plane s needs the other colour at
     // j - 1 (s = 0) or j + 1 (s = 1): loaded at the wavefront's ends
     auto edge = [&](int s) { return !p.ring && (s == 0 ? lane == 0 : lane == 63); };
-    T m0 = col(p.a0 - 1, b0, r0), c0 = col(p.a0, b0, r0);
-    T m1 = col(p.a0 - 1, b1, r1), c1 = col(p.a0, b1, r1);
-    for (int a = p.a0; a < p.a1; a += AHEAD) {
+    T m0 = T(0), c0 = T(0), m1 = T(0), c1 = T(0);
+    if (live) {
+        m0 = col(p.a0 - 1, b0, r0);
+        c0 = col(p.a0, b0, r0);
+        m1 = col(p.a0 - 1, b1, r1);
+        c1 = col(p.a0, b1, r1);
+    }
+    for (int a = p.a0, buf = 0; a < p.a1; a += AHEAD, buf ^= 1) {
         T p0[AHEAD], p1[AHEAD], q0[AHEAD], q1[AHEAD], tm0[AHEAD], tp1[AHEAD], e0[AHEAD], e1[AHEAD];
+        if (live) {
 #pragma unroll
-        for (int u = 0; u < AHEAD; ++u) {
-            const int aa = a + u;
-            if (aa < p.a1) {
-                const int s0 = (colour + aa + b0) & 1, s1 = 1 - s0;
-                const long long base = (long long)aa * sr;
-                p0[u] = col(aa + 1, b0, r0);
-                p1[u] = col(aa + 1, b1, r1);
-                q0[u] = ld_once(bv + s0 * g.P + base + r0);
-                q1[u] = ld_once(bv + s1 * g.P + base + r1);
-                tm0[u] = tlo ? x[s0 * g.P + base + r0 - nh] : T(0);
-                tp1[u] = thi ? x[s1 * g.P + base + r1 + nh] : T(0);
-                e0[u] = edge(s0) ? x[s1 * g.P + base + r0 - j + (s0 == 0 ? jlo : jhi)] : T(0);
-                e1[u] = edge(s1) ? x[s0 * g.P + base + r1 - j + (s1 == 0 ? jlo : jhi)] : T(0);
+            for (int u = 0; u < AHEAD; ++u) {
+                const int aa = a + u;
+                if (aa < p.a1) {
+                    const int s0 = (colour + aa + b0) & 1, s1 = 1 - s0;
+                    const long long base = (long long)aa * sr;
+                    p0[u] = col(aa + 1, b0, r0);
+                    p1[u] = col(aa + 1, b1, r1);
+                    q0[u] = ld_once(bv + s0 * g.P + base + r0);
+                    q1[u] = ld_once(bv + s1 * g.P + base + r1);
+                    tm0[u] = ((!kLds || w == 0) && tlo) ? x[s0 * g.P + base + r0 - nh] : T(0);
+                    tp1[u] = ((!kLds || w == kPairs - 1) && thi) ? x[s1 * g.P + base + r1 + nh]
+                                                                   : T(0);
+                    e0[u] = edge(s0) ? x[s1 * g.P + base + r0 - j + (s0 == 0 ? jlo : jhi)] : T(0);
+                    e1[u] = edge(s1) ? x[s0 * g.P + base + r1 - j + (s1 == 0 ? jlo : jhi)] : T(0);
+                }
+            }
+            // this pair's other-colour values at planes a .. a + AHEAD - 1:
+            // row b0's is the theta neighbour of the pair below's row b1,
+            // row b1's that of the pair above's row b0
+            if constexpr (kLds) {
+#pragma unroll
+                for (int u = 0; u < AHEAD; ++u) {
+                    sh[buf][u][w][0][lane] = u == 0 ? c0 : p0[u - 1];
+                    sh[buf][u][w][1][lane] = u == 0 ? c1 : p1[u - 1];
+                }
+            }
+        }
+        if constexpr (kLds) __syncthreads();
+        if (!live) continue;
+        // a neighbour row exists only where its pair (and wavefront) does
+        if constexpr (kLds) {
+#pragma unroll
+            for (int u = 0; u < AHEAD; ++u) {
+                if (w > 0 && tlo) tm0[u] = sh[buf][u][w - 1][1][lane];
+                if (w < kPairs - 1 && thi) tp1[u] = sh[buf][u][w + 1][0][lane];
             }
         }
 #pragma unroll
@@ -920,7 +962,8 @@ __device__ __forceinline__ void d_gs_march2(Blk bk, Geo g, const T* __restrict__
 {
     March2 p;
     double acc = 0.0;
-    if (march2_pos(bk, g, bpa, ch, p)) gs_march2_body<T, AHEAD>(g, G, gk, p, bv, x, colour, zero, acc);
+    const bool live = march2_pos(bk, g, bpa, ch, p);
+    gs_march2_body<T, AHEAD>(g, G, gk, p, live, bv, x, colour, zero, acc);
     if (dot) {
         acc = block_sum(acc);
         if (threadIdx.x == 0) dot[bk.L] = acc;
@@ -1925,10 +1968,10 @@ struct MarchShape {
 // Marching launch over the planes of g: bpa blocks per plane, chunks of ch
 // planes; ch <= 0 picks chunks that give about 2048 blocks (one resident
 // wave of 8 blocks per CU).
-__host__ __device__ inline MarchShape chunked(const Geo& g, int bpa, int ch)
+__host__ __device__ inline MarchShape chunked(const Geo& g, int bpa, int ch, int target = 2048)
 {
     if (ch <= 0) {
-        int nchunks = cdiv(2048, bpa);
+        int nchunks = cdiv(target, bpa);
         nchunks = nchunks < 1 ? 1 : (nchunks > g.nr ? g.nr : nchunks);
         ch = cdiv(g.nr, nchunks);
     }
@@ -1941,13 +1984,23 @@ __host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
 }
 // Row-pair kernels: bpa blocks over the (n_theta / 2) * (n_phi / 2)
 // positions of a plane.  stencil_shape: the marching launch a level uses.
-__host__ __device__ inline MarchShape march2_shape(const Geo& g, int ch = 0)
+__host__ __device__ inline MarchShape march2_shape(const Geo& g, int ch = 0, int target = 2048)
 {
-    return chunked(g, cdiv(g.nt / 2, kPairs) * (g.nh / 64), ch);
+    return chunked(g, cdiv(g.nt / 2, kPairs) * (g.nh / 64), ch, target);
 }
 __host__ __device__ inline MarchShape stencil_shape(const Geo& g, int ch = 0)
 {
     return row_pairs(g) ? march2_shape(g, ch) : march_shape(g, ch);
+}
+// The colour pass's launch: on row-pair levels of FP64 the automatic chunk
+// aims at about 1024 blocks (twice the planes per block of the other
+// kernels, which halves the r-halo planes a block reads again; measured
+// 59.9 against 63.3 us on the paper-scale shell, while FP32 passes run best
+// at the usual 2048), else as stencil_shape.
+template <typename T>
+__host__ __device__ inline MarchShape gs_shape(const Geo& g, int ch)
+{
+    return row_pairs(g) ? march2_shape(g, ch, sizeof(T) == 8 ? 1024 : 2048) : march_shape(g, ch);
 }
 
 // blocks per plane of the generic colour pass and of generic stencil kernels
@@ -2020,7 +2073,7 @@ __global__ void __launch_bounds__(kBlock) kb_gs_march(const BItem* __restrict__ 
 {
     CPS_BATCH_BLOCK
     const LDesc<T>& d = pd[it.prob].lv[level];
-    const MarchShape ms = stencil_shape(d.g, d.gs_ch);
+    const MarchShape ms = gs_shape<T>(d.g, d.gs_ch);
     if (row_pairs(d.g))
         d_gs_march2<T, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, colour, zero);
     else if (d.g.nh % 64 == 0)
