@@ -516,7 +516,9 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoot
     out["p50_p99_note"] = ("latency = submission to completion, p50/p99 over this stream "
                            "(the latency percentiles include queueing: at this rate the stream "
                            "asks for more unknowns/s than one GPU serves)"
-                           if demand > out["unknowns_per_s"] else
+                           # work left queued when the arrivals stop, beyond the
+                           # last requests' own latency
+                           if wall - duration > max(0.05 * duration, 2e-3 * st["p99_ms"]) else
                            "latency = submission to completion, p50/p99 over this stream")
     log(f"serve: {len(arr)} requests, p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, "
         f"{cells / wall / 1e6:.1f} M unknowns/s (demand {demand / 1e6:.1f} M)")
