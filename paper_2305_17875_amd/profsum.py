@@ -9,8 +9,9 @@
 --write  database of `rocprofv3 --pmc WRITE_SIZE -- python3 bench.py ...`
 
 Counter values (KiB per dispatch) are scaled by what the same counter reads
-on bench.py's plain copy kernel of 192*256*512 doubles (201,326,592 bytes
-read and written), which turns them into bytes.  The traffic JSON records
+on the library's plain copy kernel (k_copy) over 192*256*512 doubles
+(201,326,592 bytes read and written; every solve copies its right-hand side
+with it), which turns them into bytes.  The traffic JSON records
 the finest-level Gauss-Seidel kernel's bytes per launch together with a hash
 of the kernel source, so bench.py can tell whether it is still current.  The
 plane outputs do the same for the three kernels of one zebra half-sweep of
