@@ -30,7 +30,7 @@ struct LineBC {
     double v_lo, v_hi;
 };
 
-constexpr int kLineBatch = 8;
+constexpr int kLineBatch = 16;
 
 // G_dd of the LOW d-face of position (a, b) of phi-invariant face tables; a
 // face of zero area (a pole of a full sphere) carries no flux: 0
