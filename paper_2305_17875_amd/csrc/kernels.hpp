@@ -2563,6 +2563,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
     __shared__ double sv[2][kGJThreads / 64];
     __shared__ int si[2][kGJThreads / 64];
     __shared__ double prow[2][KB], erow[2][KB];
+    __shared__ int spiv[KB]; // the panel's pivot rows, for the copy at the end
     const long long w = 2LL * n;
     const int kb = min(KB, n - c0);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -2578,16 +2579,24 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
             ev[r][q] = 0.0;
         }
     }
+    // entry t of a row's panel values, by selects over compile-time indices:
+    // the steps run as a loop (a quarter of the unrolled code), and a
+    // register array indexed at run time would live in scratch memory
+    auto at = [](const double (&a)[KB], int t) {
+        double v = 0.0;
 #pragma unroll
-    for (int t = 0; t < KB; ++t) {
-        if (t >= kb) continue; // uniform; keeps the loop unrollable
+        for (int q = 0; q < KB; ++q) v = q == t ? a[q] : v;
+        return v;
+    };
+#pragma unroll 1
+    for (int t = 0; t < kb; ++t) {
         const int c = c0 + t;
         double best = -1.0;
         int bi = -1;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = threadIdx.x + r * kGJThreads;
-            const double v = fabs(pv[r][t]);
+            const double v = fabs(at(pv[r], t));
             if (used[r] >= c && v > best) { best = v; bi = i; }
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -2610,6 +2619,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
             if (threadIdx.x == 0) *fail = 1;
             return; // uniform: every thread reached the same decision
         }
+        if (threadIdx.x == 0) spiv[t] = p;
         // the owner of the pivot row broadcasts it, scaled
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -2617,8 +2627,10 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
                 used[r] = c;
                 used_at[p] = c;
                 piv[c] = p;
-                ev[r][t] = 1.0;
-                const double inv = 1.0 / pv[r][t];
+#pragma unroll
+                for (int q = 0; q < KB; ++q)
+                    if (q == t) ev[r][q] = 1.0;
+                const double inv = 1.0 / at(pv[r], t);
 #pragma unroll
                 for (int q = 0; q < KB; ++q) {
                     prow[h][q] = q >= t ? pv[r][q] * inv : 0.0;
@@ -2636,7 +2648,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
                     ev[r][q] = erow[h][q];
                 }
             } else {
-                const double m = pv[r][t];
+                const double m = at(pv[r], t);
 #pragma unroll
                 for (int q = 0; q < KB; ++q) {
                     if (q >= t) pv[r][q] -= m * prow[h][q];
@@ -2655,11 +2667,15 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
             E[(long long)i * kGJ + q] = ev[r][q];
         }
     }
-    // the panel's pivot rows, before the update of the other columns
-    for (long long q = threadIdx.x; q < (long long)kb * w; q += blockDim.x) {
+    // the panel's pivot rows, before the update of the other columns (only
+    // the columns past the panel are read from the copy); the rows from LDS
+    // (spiv was set before the last step's barriers)
+    const long long tot = (long long)kb * w;
+#pragma unroll 8
+    for (long long q = threadIdx.x; q < tot; q += blockDim.x) {
         const int u = (int)(q / w);
         const long long col = q - (long long)u * w;
-        Xp[q] = M[(long long)piv[c0 + u] * w + col];
+        Xp[q] = M[(long long)spiv[u] * w + col];
     }
 }
 
