@@ -917,15 +917,17 @@ int compute_operator(cps_handle* h)
         const int KB = R == 1 ? 16 : (R == 2 ? 8 : 4);
         for (int c0 = 0; c0 < n; c0 += KB) {
             if (R == 1)
-                k_gj_panel<1, 16><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, Xp.p, used.p,
+                k_gj_panel<1, 16><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, used.p,
                                                                    piv.p, bad.p);
             else if (R == 2)
-                k_gj_panel<2, 8><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, Xp.p, used.p,
+                k_gj_panel<2, 8><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, used.p,
                                                                   piv.p, bad.p);
             else
-                k_gj_panel<4, 4><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, Xp.p, used.p,
+                k_gj_panel<4, 4><<<1, kGJThreads, 0, h->stream>>>(n, c0, M0.p, E.p, used.p,
                                                                   piv.p, bad.p);
             const int kb = std::min(KB, n - c0);
+            k_gj_pivrows<<<nblk((long long)kb * 2 * n), kBlock, 0, h->stream>>>(n, c0, kb, M0.p,
+                                                                               piv.p, Xp.p);
             const long long rest = 2LL * n - c0 - kb;
             const long long blocks = cdiv(rest, 64) * (long long)cdiv(n, kBlock / 64);
             k_gj_update<<<(unsigned)blocks, kBlock, 0, h->stream>>>(n, c0, kb, M0.p, E.p, Xp.p,

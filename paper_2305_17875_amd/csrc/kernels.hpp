@@ -2544,7 +2544,7 @@ __global__ void __launch_bounds__(kBlock) k_augment(int n, const double* __restr
 //    unit vector of the pivot row of step u (untouched by the steps before
 //    it, so it is set when that step starts).  Afterwards any column x of the
 //    rest transforms as x' = (x off the panel's pivot rows) + E x[pivots].
-//    The panel's pivot rows are copied aside (Xp) before the update.
+//  - k_gj_pivrows copies the panel's pivot rows aside (Xp) before the update.
 //  - k_gj_update applies that rank-KB update to the columns past the panel.
 // KB = 16 / R keeps a thread's registers to 2 R KB values (n <= 1024 R).
 constexpr int kGJ = 16;          // row stride of E
@@ -2553,7 +2553,6 @@ constexpr int kGJThreads = 1024;
 template <int R, int KB>
 __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* __restrict__ M,
                                                          double* __restrict__ E,
-                                                         double* __restrict__ Xp,
                                                          int* __restrict__ used_at,
                                                          int* __restrict__ piv,
                                                          int* __restrict__ fail)
@@ -2563,7 +2562,6 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
     __shared__ double sv[2][kGJThreads / 64];
     __shared__ int si[2][kGJThreads / 64];
     __shared__ double prow[2][KB], erow[2][KB];
-    __shared__ int spiv[KB]; // the panel's pivot rows, for the copy at the end
     const long long w = 2LL * n;
     const int kb = min(KB, n - c0);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -2607,9 +2605,11 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
         const int h = t & 1;
         if (lane == 0) { sv[h][wid] = best; si[h][wid] = bi; }
         __syncthreads();
-        // every thread combines the wavefronts' candidates itself
+        // every thread combines the wavefronts' candidates itself (unrolled:
+        // the LDS reads issue together instead of one latency per wavefront)
         double bb = sv[h][0];
         int p = si[h][0];
+#pragma unroll
         for (int q = 1; q < kGJThreads / 64; ++q) {
             const double v2 = sv[h][q];
             const int i2 = si[h][q];
@@ -2619,7 +2619,6 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
             if (threadIdx.x == 0) *fail = 1;
             return; // uniform: every thread reached the same decision
         }
-        if (threadIdx.x == 0) spiv[t] = p;
         // the owner of the pivot row broadcasts it, scaled
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -2667,16 +2666,23 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_panel(int n, int c0, double* 
             E[(long long)i * kGJ + q] = ev[r][q];
         }
     }
-    // the panel's pivot rows, before the update of the other columns (only
-    // the columns past the panel are read from the copy); the rows from LDS
-    // (spiv was set before the last step's barriers)
-    const long long tot = (long long)kb * w;
-#pragma unroll 8
-    for (long long q = threadIdx.x; q < tot; q += blockDim.x) {
-        const int u = (int)(q / w);
-        const long long col = q - (long long)u * w;
-        Xp[q] = M[(long long)spiv[u] * w + col];
-    }
+}
+
+// The panel's pivot rows, copied aside before the update of the other
+// columns (which overwrites them); only the columns past the panel are read
+// from the copy.  Many blocks: in the one-block panel kernel this copy took
+// a fifth of its time.
+__global__ void __launch_bounds__(kBlock) k_gj_pivrows(int n, int c0, int kb,
+                                                       const double* __restrict__ M,
+                                                       const int* __restrict__ piv,
+                                                       double* __restrict__ Xp)
+{
+    const long long w = 2LL * n;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)kb * w) return;
+    const int u = (int)(q / w);
+    const long long col = q - (long long)u * w;
+    Xp[q] = M[(long long)piv[c0 + u] * w + col];
 }
 
 // x' = (x off the pivot rows) + E x[pivots] for the columns past the panel.
