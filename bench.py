@@ -591,8 +591,8 @@ def main():
     ap.add_argument("--no-serve-comparator", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU (asked for --gpus {a.gpus}): one grid's solve is not "
-              "sharded across devices in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {a.gpus}): a grid's solve runs on "
+              "a single device; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
