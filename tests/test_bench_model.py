@@ -1,0 +1,78 @@
+"""The byte models behind bench.py's roofline figures, pinned to brute-force
+counts on small grids and to the paper-scale values the measurement quotes;
+and the one-GPU contract of bench.py's command line.  CPU only."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PAPER_SCALE = (192, 256, 512)
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_model", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def colour_of(shape, ncol):
+    """Red-black (a + b + c) mod 2, or the four colours ((a + c) mod 2,
+    (b + c) mod 2) of the 19-point class."""
+    a, b, c = np.meshgrid(*[np.arange(k) for k in shape], indexing="ij")
+    if ncol == 2:
+        return (a + b + c) % 2
+    return ((a + c) % 2) * 2 + (b + c) % 2
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (6, 4, 10)])
+@pytest.mark.parametrize("ncol,nterms", [(2, 3), (4, 5)])
+def test_colour_pass_bytes_count_every_access_once(bench, shape, ncol, nterms):
+    """One pass of colour k: every cell of colour k reads b and writes x,
+    every other cell is read once as a neighbour, the metric arrays once
+    (per (r, theta)); counted cell by cell."""
+    col = colour_of(shape, ncol)
+    w = 8
+    for k in range(ncol):
+        upd = int((col == k).sum())
+        other = col.size - upd
+        want = upd * 2 * w + other * w + nterms * shape[0] * shape[1] * w
+        got = bench.gs_bytes_per_launch(shape, ncol, w, True, nterms)
+        # the model takes n / ncol cells per colour; the colour classes of
+        # these grids have exactly that size
+        assert upd == col.size // ncol
+        assert got == want, (k, got, want)
+
+
+def test_paper_scale_figures(bench):
+    """The algorithmic bytes the roofline and the half-sweep rate use on the
+    paper-scale shell (FP64)."""
+    assert bench.gs_bytes_per_launch(PAPER_SCALE, 2, 8, True, 3) == 303_169_536
+    assert bench.plane_half_sweep_bytes(PAPER_SCALE, 8) == 1_009_385_472
+    levels = [(192, 256, 512), (96, 128, 256), (48, 64, 128), (24, 32, 64), (12, 16, 32),
+              (6, 8, 16)]
+    assert bench.vcycle_bytes(levels, 8) == 4_102_801_920
+
+
+def test_plane_half_sweep_counts_its_terms(bench):
+    """Half-sweep = b and x in (n/2 each), spectra out, the elimination's two
+    passes over the spectra (4 x) and pivots (2 x half of them), spectra in,
+    x out; spectra are n_phi/2 + 1 complex values per relaxed ring."""
+    nr, nt, np_ = 4, 6, 16
+    rings = nr * (nt // 2)
+    spec = rings * (np_ // 2 + 1) * 2
+    half = nr * nt * np_ // 2
+    words = 2 * half + spec + 4 * spec + spec + spec + half
+    assert bench.plane_half_sweep_bytes((nr, nt, np_), 4) == words * 4
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and "--gpus 1" in r.stderr
