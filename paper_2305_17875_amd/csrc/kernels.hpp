@@ -1992,15 +1992,14 @@ __host__ __device__ inline MarchShape stencil_shape(const Geo& g, int ch = 0)
 {
     return row_pairs(g) ? march2_shape(g, ch) : march_shape(g, ch);
 }
-// The colour pass's launch: on row-pair levels of FP64 the automatic chunk
-// aims at about 1024 blocks (twice the planes per block of the other
-// kernels, which halves the r-halo planes a block reads again; measured
-// 59.9 against 63.3 us on the paper-scale shell, while FP32 passes run best
-// at the usual 2048), else as stencil_shape.
+// The colour pass's launch: on row-pair levels the automatic chunk aims at
+// about 1024 blocks (twice the planes per block of the other kernels, which
+// halves the r-halo planes a block reads again; the autotuner's choice on
+// the paper-scale shell in both precisions), else as stencil_shape.
 template <typename T>
 __host__ __device__ inline MarchShape gs_shape(const Geo& g, int ch)
 {
-    return row_pairs(g) ? march2_shape(g, ch, sizeof(T) == 8 ? 1024 : 2048) : march_shape(g, ch);
+    return row_pairs(g) ? march2_shape(g, ch, 1024) : march_shape(g, ch);
 }
 
 // blocks per plane of the generic colour pass and of generic stencil kernels
