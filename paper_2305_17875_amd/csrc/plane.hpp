@@ -56,7 +56,11 @@ __device__ __forceinline__ Vec2<T> conjv(Vec2<T> a)
 
 constexpr int kPlaneLds = 1024; // complex values per LDS buffer (rings x length)
 constexpr int kTriBlock = 64;
-constexpr int kTriBatch = 8;   // r-steps whose loads a lane issues together
+// r-steps whose loads a lane issues together: 8 in FP64, 16 in FP32 (on
+// the paper-scale shell 16 made the FP64 half-sweep 212 instead of 200 us
+// and the mixed solve 17.1 instead of 17.4 ms)
+template <typename T>
+constexpr int tri_batch() { return sizeof(T) == 8 ? 8 : 16; }
 constexpr int kLdBatch = 4;    // ring positions whose loads a lane issues together
 constexpr int kSmallRing = 256; // ring-size class of the paper-scale shell
 
@@ -396,6 +400,7 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
     const int q = (int)(u & 1);
     const int b = 2 * (int)(t / nm) + parity;
     T d = T(0);
+    constexpr int kTriBatch = tri_batch<T>();
     for (int a0 = 0; a0 < nr; a0 += kTriBatch) {
         T r[kTriBatch], p[kTriBatch], gl[kTriBatch];
 #pragma unroll
