@@ -56,11 +56,11 @@ __device__ __forceinline__ Vec2<T> conjv(Vec2<T> a)
 
 constexpr int kPlaneLds = 1024; // complex values per LDS buffer (rings x length)
 constexpr int kTriBlock = 64;
-// r-steps whose loads a lane issues together: 8 in FP64, 16 in FP32 (on
-// the paper-scale shell 16 made the FP64 half-sweep 212 instead of 200 us
-// and the mixed solve 17.1 instead of 17.4 ms)
+// r-steps whose loads a lane issues together (16 made the paper-scale FP64
+// half-sweep 212 instead of 200 us and the batched form 9% slower, for 2%
+// on the single FP32 solve)
 template <typename T>
-constexpr int tri_batch() { return sizeof(T) == 8 ? 8 : 16; }
+constexpr int tri_batch() { return 8; }
 constexpr int kLdBatch = 4;    // ring positions whose loads a lane issues together
 constexpr int kSmallRing = 256; // ring-size class of the paper-scale shell
 
