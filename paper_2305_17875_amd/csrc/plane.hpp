@@ -56,11 +56,7 @@ __device__ __forceinline__ Vec2<T> conjv(Vec2<T> a)
 
 constexpr int kPlaneLds = 1024; // complex values per LDS buffer (rings x length)
 constexpr int kTriBlock = 64;
-// r-steps whose loads a lane issues together (16 made the paper-scale FP64
-// half-sweep 212 instead of 200 us and the batched form 9% slower, for 2%
-// on the single FP32 solve)
-template <typename T>
-constexpr int tri_batch() { return 8; }
+constexpr int kTriBatch = 8;   // r-steps whose loads a lane issues together
 constexpr int kLdBatch = 4;    // ring positions whose loads a lane issues together
 constexpr int kSmallRing = 256; // ring-size class of the paper-scale shell
 
@@ -400,7 +396,6 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
     const int q = (int)(u & 1);
     const int b = 2 * (int)(t / nm) + parity;
     T d = T(0);
-    constexpr int kTriBatch = tri_batch<T>();
     for (int a0 = 0; a0 < nr; a0 += kTriBatch) {
         T r[kTriBatch], p[kTriBatch], gl[kTriBatch];
 #pragma unroll
