@@ -121,3 +121,29 @@ def test_batch_with_the_automatic_smoother():
     log("batch automatic smoother iterations", [i.iterations for i in infos])
     assert infos[0].iterations <= 8 and infos[3].iterations > 3 * infos[0].iterations
     assert infos[1].iterations <= 10 and infos[5].iterations <= 10
+
+
+def test_batch_plane_smoother_on_long_oblate_rings():
+    """smoother = 1 for every problem: oblate shells (r-theta cross terms,
+    the batched plane group with cross terms) up to the batched form's
+    longest ring (n_phi = 512) beside spheres; every result equals the same
+    problem solved alone, bit for bit, and the oracle's exact solution to
+    1e-9."""
+    grids = [Shell(8, 8, 512, map=MAP_OBLATE, flattening=0.1),
+             Shell(16, 16, 64, map=MAP_OBLATE, flattening=0.15, radial_stretch=1.5),
+             Shell(8, 8, 512, radial_stretch=1.0)]
+    rhs = [rhs_of(60 + i, g) for i, g in enumerate(grids)]
+    log("batch plane long rings", len(grids))
+    B = cps.Batch(grids, smoother=1)
+    try:
+        st, p, infos = B.solve([dev(b).flatten() for b in rhs])
+        xs = [host(t).reshape(g.shape) for t, g in zip(p, grids)]
+    finally:
+        B.close()
+    assert st == cps.CPS_OK
+    for i, (g, b, x, info) in enumerate(zip(grids, rhs, xs, infos)):
+        xa, ra = alone(g, b, smoother=1)
+        assert info.iterations == ra.iterations, i
+        assert np.array_equal(x, xa), (i, np.abs(x - xa).max())
+        want = direct.solve_axisym(O.face_metrics(g), b)
+        assert rel(x, want) <= 1e-9, (i, rel(x, want))
