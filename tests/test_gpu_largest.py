@@ -1,4 +1,4 @@
-"""The paper's largest grid: 256 (r) x 512 (theta) x 512 (phi) = 67.1 M
+"""The paper's largest grid (tests/golden/paper_grids.txt): 256 (r) x 512 (theta) x 512 (phi) = 67.1 M
 cells with tanh clustering 2.0 (a 7-level hierarchy, ~7.4 GB in FP64).
 FP64 solves with the point and the plane smoother reach relative residual
 1e-10; the check is the oracle's own FP64 residual of the GPU answer and the
@@ -10,13 +10,16 @@ import oracle as O
 from paper_2305_17875_amd import cps, inputs
 from paper_2305_17875_amd.inputs import Shell
 from gpu_util import needs_gpu, log, dev, host, torch
+from test_paper_grids import paper_grids
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
 
 @pytest.fixture(scope="module")
 def largest():
-    g = Shell(256, 512, 512, radial_stretch=2.0)
+    shape = max((s for _, s in paper_grids()), key=lambda s: s[0] * s[1] * s[2])
+    assert shape == (256, 512, 512)
+    g = Shell(*shape, radial_stretch=2.0)
     log("largest grid oracle setup", g.shape)
     b = inputs.smoothed_noise(g.shape, 7)
     G = O.face_metrics(g)
