@@ -1453,6 +1453,12 @@ __device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch
     const long long cm = f.P + (p.jc == 0 ? f.nh - 1 : cv - 1);
     const long long cp = p.jc == c.nh - 1 ? 0 : cv + 2;
     const T wq[4] = {w0, w1, w1, w0};
+    // the outer phi values 4jc-1 and 4jc+4 are the adjacent threads' pairs
+    // (jc-1's last odd value, jc+1's first even one): taken from the
+    // adjacent lanes where those hold the same row, else loaded
+    const int lane = (int)(threadIdx.x & 63);
+    const bool lo_lane = lane > 0 && p.jc > 0;
+    const bool hi_lane = lane < 63 && p.jc < c.nh - 1;
     // theta-phi restriction of fine plane a for K = 2jc (s0) and 2jc+1 (s1)
     auto plane = [&](int a, T& s0, T& s1) {
         const T* ra = r + (long long)clampi(a, f.nr - 1) * f.rowlen;
@@ -1463,8 +1469,13 @@ __device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch
             const T* rr = ra + rowo[q];
             e[q] = *reinterpret_cast<const Vec2<T>*>(rr + cv);
             o[q] = *reinterpret_cast<const Vec2<T>*>(rr + f.P + cv);
-            v0[q] = rr[cm];
-            v5[q] = rr[cp];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v0[q] = __shfl(o[q].y, lane - 1);
+            v5[q] = __shfl(e[q].x, lane + 1);
+            if (!lo_lane) v0[q] = ra[rowo[q] + cm];
+            if (!hi_lane) v5[q] = ra[rowo[q] + cp];
         }
         s0 = T(0);
         s1 = T(0);
