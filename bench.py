@@ -24,6 +24,7 @@ import hashlib
 import json
 import os
 import sys
+import statistics
 import time
 
 import numpy as np
@@ -139,9 +140,13 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
     cps.cps_profile_select(s.h, [cps.KERNEL_GS])
     cps.cps_profile_enable(s.h, True)
     t0 = time.perf_counter()
-    iters = []
+    iters, solve_s = [], []
     for i in range(steps):
+        # a solve returns after its result is written: the host clock
+        # around it is the solve's own time
+        t1 = time.perf_counter()
         res = s.solve(rhs, TOL, out=p)
+        solve_s.append(time.perf_counter() - t1)
         iters.append(res.iterations)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
@@ -165,7 +170,8 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
     log(f"precision={precision} smoother={smoother}: {dt * 1e3:.1f} ms/solve, iterations={iters}, "
         f"rel_residual={res.rel_residual:.3e}")
     return dict(solver=s, p=p, res=res, sec=dt, iters=iters, prof=prof, prof_steps=PROF_STEPS,
-                setup_s=setup_s,
+                setup_s=setup_s, solve_ms_median=statistics.median(solve_s) * 1e3,
+                solve_ms_min=min(solve_s) * 1e3,
                 timed_gs=timed_gs)
 
 
@@ -641,6 +647,8 @@ def main():
         "warmup": a.warmup,
         "ms_per_step": f64["sec"] * 1e3,
         "setup_ms": f64["setup_s"] * 1e3,  # once per hierarchy; not in ms_per_step
+        "solve_ms_median": f64["solve_ms_median"],
+        "solve_ms_min": f64["solve_ms_min"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -657,7 +665,8 @@ def main():
                      "kernel": GS_KERNEL + " (finest-level red-black colour pass, row pairs; "
                                "the zero-iterate first pass of a cycle is a kernel of its own)",
                      "avg_us": avg_gs_s * 1e6, "algorithmic_bytes": gs_bytes,
-                     "kernel_source_sha256_16": kh, "copy_yardstick_GBs": copy_gbs},
+                     "kernel_source_sha256_16": kh, "copy_yardstick_GBs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs if copy_gbs else None},
         "kernels_fp64": kernel_table(f64["prof"], f64["prof_steps"]),
         "vcycle_fp64": vcycle_rate(f64["prof"], s64.levels, 8, f64["prof_steps"]),
     }
@@ -667,6 +676,8 @@ def main():
         err = float(torch.linalg.norm(mx["p"] - x64) / torch.linalg.norm(x64))
         line["mixed"] = {"value": n / mx["sec"], "ms_per_step": mx["sec"] * 1e3,
                          "setup_ms": mx["setup_s"] * 1e3,
+                         "solve_ms_median": mx["solve_ms_median"],
+                         "solve_ms_min": mx["solve_ms_min"],
                          "iterations": mx["iters"][-1], "rel_residual": mx["res"].rel_residual,
                          "rel_diff_vs_fp64": err, "dtype": "f32 V-cycles, f64 outer",
                          "kernels": kernel_table(mx["prof"], mx["prof_steps"]),
