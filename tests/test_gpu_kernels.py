@@ -33,6 +33,9 @@ CASES = [
     # group overhanging n_theta, and rows of 2 segments (phi halo loads)
     ("sphere-tile-8x6x128", Shell(8, 6, 128, radial_stretch=2.0), 0),
     ("sphere-tile-6x10x256", Shell(6, 10, 256), 0),
+    # coarse rings of 128 phi pairs: two wavefronts per coarse row, so the
+    # restriction's outer phi values cross a wavefront boundary inside a ring
+    ("sphere-wide-8x8x512", Shell(8, 8, 512), 0),
 ]
 
 
