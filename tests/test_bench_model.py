@@ -76,3 +76,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and "--gpus 1" in r.stderr
+
+
+def test_vcycle_rate_reports_cycles_per_solve(bench):
+    """The V-cycle figure divides the byte model by the mean event span of a
+    cycle, and counts cycles per profiled solve, not in total."""
+    levels = [PAPER_SCALE, (96, 128, 256), (48, 64, 128), (24, 32, 64), (12, 16, 32), (6, 8, 16)]
+    vc = bench.KNAMES.index("vcycle")
+    prof = {k: (0.0, 0) for k in range(len(bench.KNAMES))}
+    prof[vc] = (150 * 0.93, 150)  # 150 cycles of 930 us in 2 solves
+    out = bench.vcycle_rate(prof, levels, 8, 2)
+    assert out["cycles_per_step"] == 75
+    assert out["bytes_per_cycle"] == bench.vcycle_bytes(levels, 8)
+    assert out["avg_us"] == pytest.approx(930.0)
+    assert out["frac_of_peak"] == pytest.approx(out["bytes_per_cycle"] / 930e-6 / 1e9 / 8000.0)
+    prof[vc] = (0.0, 0)
+    assert bench.vcycle_rate(prof, levels, 8, 2) is None
