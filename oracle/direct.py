@@ -124,34 +124,69 @@ def is_axisymmetric(G: np.ndarray, rtol: float = 1e-12) -> bool:
     return not (G[2].any() or G[5].any() or G[6].any() or G[7].any())
 
 
-def solve_axisym(G: np.ndarray, b: np.ndarray) -> np.ndarray:
+def _mode_solve(A2, gpp, rhs: np.ndarray, m: int, np_: int) -> np.ndarray:
+    """Azimuthal mode m of the solution: (A_2d - 4 sin^2(pi m / n_phi)
+    diag(G_pp)) x_m = b_m by sparse LU; mode 0 bordered with sum(x_0) = 0.
+    rhs: the complex mode of b, flattened over (r, theta)."""
+    n2 = A2.shape[0]
+    if m == 0:
+        one = sp.csr_matrix(np.ones((n2, 1)))
+        K = sp.bmat([[A2, one], [one.T, None]], format="csc")
+        lu = spla.splu(K)
+        xr = lu.solve(np.concatenate([rhs.real, [0.0]]))[:n2]
+        xi = lu.solve(np.concatenate([rhs.imag, [0.0]]))[:n2]
+    else:
+        shift = -4.0 * np.sin(np.pi * m / np_) ** 2 * gpp
+        lu = spla.splu((A2 + sp.diags(shift)).tocsc())
+        xr = lu.solve(np.ascontiguousarray(rhs.real))
+        xi = lu.solve(np.ascontiguousarray(rhs.imag))
+    return xr + 1j * xi
+
+
+_pool_state = {}
+
+
+def _pool_init(A2, gpp, np_):
+    _pool_state.update(A2=A2, gpp=gpp, np_=np_)
+
+
+def _pool_mode(task):
+    m, rhs = task
+    s = _pool_state
+    return m, _mode_solve(s["A2"], s["gpp"], rhs, m, s["np_"])
+
+
+def solve_axisym(G: np.ndarray, b: np.ndarray, workers: int = 1, progress=None) -> np.ndarray:
     """Exact solve for phi-invariant metrics with G_{r phi} = G_{theta phi} = 0.
 
     On each azimuthal mode m the phi-flux difference G_pp (x_{c+1} - 2 x_c +
     x_{c-1}) becomes -4 sin^2(pi m / n_phi) G_pp x_m, so A splits into
     (A_2d - 4 sin^2(pi m/n_phi) diag(G_pp)) x_m = b_m.  Mode 0 is singular and
-    is solved bordered with sum(x_0) = 0."""
+    is solved bordered with sum(x_0) = 0.  The modes are independent systems:
+    workers > 1 solves them in that many spawned processes (the same
+    arithmetic per mode).  progress(done, total) is called as modes finish."""
     if not is_axisymmetric(G):
         raise ValueError("metrics are not axisymmetric")
     nr, nt, np_ = b.shape
     A2, gpp = _axisym_2d(G)
     bh = np.fft.rfft(b - b.mean(), axis=2)
     xh = np.zeros_like(bh)
-    n2 = nr * nt
-    for m in range(bh.shape[2]):
-        shift = -4.0 * np.sin(np.pi * m / np_) ** 2 * gpp
-        rhs = bh[:, :, m].ravel()
-        if m == 0:
-            one = sp.csr_matrix(np.ones((n2, 1)))
-            K = sp.bmat([[A2, one], [one.T, None]], format="csc")
-            lu = spla.splu(K)
-            xr = lu.solve(np.concatenate([rhs.real, [0.0]]))[:n2]
-            xi = lu.solve(np.concatenate([rhs.imag, [0.0]]))[:n2]
-        else:
-            lu = spla.splu((A2 + sp.diags(shift)).tocsc())
-            xr = lu.solve(np.ascontiguousarray(rhs.real))
-            xi = lu.solve(np.ascontiguousarray(rhs.imag))
-        xh[:, :, m] = (xr + 1j * xi).reshape(nr, nt)
+    nm = bh.shape[2]
+    if workers <= 1:
+        for m in range(nm):
+            xh[:, :, m] = _mode_solve(A2, gpp, bh[:, :, m].ravel(), m, np_).reshape(nr, nt)
+            if progress:
+                progress(m + 1, nm)
+    else:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        tasks = [(m, np.ascontiguousarray(bh[:, :, m].ravel())) for m in range(nm)]
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
+                                    initializer=_pool_init, initargs=(A2, gpp, np_)) as ex:
+            for k, (m, xm) in enumerate(ex.map(_pool_mode, tasks, chunksize=4)):
+                xh[:, :, m] = xm.reshape(nr, nt)
+                if progress:
+                    progress(k + 1, nm)
     x = np.fft.irfft(xh, n=np_, axis=2)
     return x - x.mean()
 
