@@ -123,7 +123,10 @@ typedef struct {
 
 typedef struct {
     int32_t iterations;      /* outer iterations done */
-    double rel_residual;     /* ||b - A p|| / ||b|| with b = rhs - mean(rhs) */
+    double rel_residual;     /* ||b - A p|| / ||b|| with b = rhs - mean(rhs), of the p
+                                returned: the Krylov forms update the residual by
+                                recurrence, and before they stop they form b - A p
+                                itself and restart from it if it misses tol */
     double rhs_mean_removed; /* mean(rhs) */
     double seconds;          /* wall time of the call */
 } cps_info;

@@ -369,10 +369,31 @@ class Solver:
         self.h = cps_setup(make_grid(grid, n_levels), cps_metrics(metrics), opts)
         self.levels, self.ncolours, self.phi_invariant = cps_levels(self.h)
 
+    def _enter(self, *tensors):
+        """The library runs on self.stream: order it after the work the
+        caller's current stream has queued (which may still be writing the
+        inputs), and tell torch's caching allocator that the tensors are in
+        use on self.stream, so their memory is not handed out again before
+        the library is done with it."""
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+            for t in tensors:
+                t.record_stream(self.stream)
+        return cur
+
+    def _leave(self, cur):
+        """Later work on the caller's stream sees the library's results."""
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def solve(self, rhs, tol: float = 1e-10, out=None) -> Result:
         import torch
         p = out if out is not None else torch.empty_like(rhs)
+        cur = self._enter(rhs, p)
         st, info = cps_solve(self.h, rhs, p, tol)
+        self._leave(cur)
         return Result(p, st, info.iterations, info.rel_residual, info.rhs_mean_removed,
                       info.seconds)
 
@@ -381,12 +402,16 @@ class Solver:
         import torch
         rhs = out if out is not None else torch.empty(u.numel() // 3, dtype=u.dtype,
                                                       device=u.device)
+        cur = self._enter(u, rhs)
         cps_divergence(self.h, u, rhs)
+        self._leave(cur)
         return rhs
 
     def correct(self, phi, u):
         """eq. (PC_7) in place on u."""
+        cur = self._enter(phi, u)
         cps_correct(self.h, phi, u)
+        self._leave(cur)
         return u
 
     def project(self, u, tol: float = 1e-10, phi=None) -> Result:
@@ -394,7 +419,9 @@ class Solver:
         import torch
         phi = phi if phi is not None else torch.empty(u.numel() // 3, dtype=u.dtype,
                                                       device=u.device)
+        cur = self._enter(u, phi)
         st, info = cps_project(self.h, u, phi, tol)
+        self._leave(cur)
         return Result(phi, st, info.iterations, info.rel_residual, info.rhs_mean_removed,
                       info.seconds)
 
@@ -402,7 +429,9 @@ class Solver:
         """Implicit line solves along direction d (0 r, 1 theta, 2 phi)."""
         import torch
         psi = out if out is not None else torch.empty_like(rhs)
+        cur = self._enter(rhs, psi)
         cps_line_solve(self.h, d, coef, rhs, psi, bc)
+        self._leave(cur)
         return psi
 
     def close(self):

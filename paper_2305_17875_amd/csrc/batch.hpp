@@ -490,6 +490,36 @@ void set_active(cps_batch* B, const std::vector<int>& on)
     upload_active(B);
 }
 
+// The problems marked in `check` met the tolerance by the conjugate-gradient
+// recurrence: as solve() does, form r = b0 - A x (y = A x into q) and decide
+// on its norm.  A problem that misses the tolerance restarts from that
+// residual: its direction is zeroed, so the next part B takes p = z.  Leaves
+// the active flags at `check` (the caller sets its own next).
+void true_residuals(cps_batch* B, BatchGroup& G, const std::vector<int>& check,
+                    const std::vector<double>& bb, double tol, std::vector<double>& rel,
+                    std::vector<cps_status>& st)
+{
+    set_active(B, check);
+    dispatch(G.mode, G.axi, [&](auto M, auto A) {
+        blaunch(B, G.apply, kb_apply64<float, decltype(M)::value, decltype(A)::value>, (int)V_X,
+                (int)V_Q, -1);
+    });
+    blaunch(B, G.elem, kb_elem<float>, (int)EOP_SUB, (int)V_B0, (int)V_Q, (int)V_R);
+    bdot(B, G.vred, V_R, V_R, S_RR);
+    gather(B, S_RR); // synchronises: the flags below may be rewritten
+    std::vector<int> again(B->n, 0);
+    bool any = false;
+    for (int p = 0; p < B->n; ++p) {
+        if (!check[p]) continue;
+        st[p] = check_norm(B->hgath[p], bb[p], tol, &rel[p]);
+        if (st[p] == CPS_E_NOT_CONVERGED) again[p] = 1, any = true;
+    }
+    if (!any) return;
+    set_active(B, again);
+    blaunch(B, G.elem, kb_elem<float>, (int)EOP_FILL, (int)V_P, 0, 0);
+    HIPC(hipStreamSynchronize(B->stream)); // before the flags are rewritten
+}
+
 cps_status batch_solve(cps_batch* B, const double* const* rhs, double* const* out, double tol,
                        cps_info* infos)
 {
@@ -561,13 +591,21 @@ cps_status batch_solve(cps_batch* B, const double* const* rhs, double* const* ou
             HIPC(hipGraphLaunch(G.gA, B->stream));
             gather(B, S_RR);
             bool left = false;
+            std::vector<int> check(n, 0); // the recurrence met the tolerance
+            bool any_check = false;
             for (int p : G.probs) {
                 if (!act[p]) continue;
                 iters[p] = it;
-                const int m = B->h[p]->opts.max_iters > 0 ? B->h[p]->opts.max_iters : 200;
                 const cps_status s = check_norm(B->hgath[p], bb[p], tol, &rel[p]);
                 st[p] = s;
-                if (s != CPS_E_NOT_CONVERGED || it >= m) act[p] = 0;
+                if (s == CPS_OK) check[p] = 1, any_check = true;
+            }
+            if (any_check) // as solve(): the residual of the iterate decides
+                true_residuals(B, G, check, bb, tol, rel, st);
+            for (int p : G.probs) {
+                if (!act[p]) continue;
+                const int m = B->h[p]->opts.max_iters > 0 ? B->h[p]->opts.max_iters : 200;
+                if (st[p] != CPS_E_NOT_CONVERGED || it >= m) act[p] = 0;
                 left = left || act[p];
             }
             if (!left) break;

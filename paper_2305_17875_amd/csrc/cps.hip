@@ -1131,6 +1131,21 @@ cps_status check_norm(double rr, double bb, double tol, double* rel)
     return *rel <= tol ? CPS_OK : CPS_E_NOT_CONVERGED;
 }
 
+// The Krylov recurrences update r without forming b - A x, and rounding
+// lets the two drift apart; a solve that the recurrence calls converged is
+// checked on the residual of the iterate itself: y = A x into q, r = b0 - y
+// (r then holds it), *rel = ||r|| / ||b0||.  The batched form takes the same
+// steps with the same kernel bodies, so both see the same bits.
+cps_status true_residual(cps_handle* h, double bb, double tol, double* rel)
+{
+    const long long n = h->lv[0].n;
+    apply<double>(h, 0, h->x0.p, h->q.p, nullptr);
+    k_sub<<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, h->q.p, h->r.p);
+    LAUNCH_CHECK();
+    dot<double, double>(h, n, h->r.p, h->r.p, S_RR);
+    return check_norm(read_scalar(h, S_RR), bb, tol, rel);
+}
+
 cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cps_info* info)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1241,63 +1256,82 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             // later iterations: new direction from the preconditioned
             // residual, then the step; with the fused product the direction
             // alternates between two buffers, so two bodies by parity
-            while (st == CPS_E_NOT_CONVERGED && it < maxit) {
-                ++it;
-                const int parity = fused ? (it & 1) : 0;
-                double* pc = parity ? pn : p; // direction of the previous iteration
-                double* pnx = parity ? p : pn;
-                run_body(h, G_CG0 + parity, [&] {
-                    k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
-                    LAUNCH_CHECK();
-                    precondition(h, r, cast_fused ? nullptr : z, S_RZ, flexible ? q : nullptr,
-                                 cast_fused);
-                    k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
-                    LAUNCH_CHECK();
-                    if (fused) {
-                        const MarchShape ms = stencil_shape(g0);
-                        {
-                            ProfScope ps(h, CPS_KERNEL_APPLY, 0); // the product only
-                            if (cast_fused)
-                                k_apply_dircast_march2<<<ms.grid, kBlock, 0, h->stream>>>(
-                                    g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch,
-                                    h->lv[0].x32.p, h->sc.p, S_SCALE, S_BETA, pc, pnx, q,
-                                    h->partial.p, x);
-                            else
-                                k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
-                                    g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
-                                    h->sc.p + S_BETA, pnx, q, h->partial.p, x,
-                                    h->sc.p + S_ALPHA);
-                            LAUNCH_CHECK();
-                        }
-                        reduce(h, ms.grid, S_PQ);
-                        step(pnx);
-                    } else {
-                        k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
+            for (;;) {
+                while (st == CPS_E_NOT_CONVERGED && it < maxit) {
+                    ++it;
+                    const int parity = fused ? (it & 1) : 0;
+                    double* pc = parity ? pn : p; // direction of the previous iteration
+                    double* pnx = parity ? p : pn;
+                    run_body(h, G_CG0 + parity, [&] {
+                        k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
                         LAUNCH_CHECK();
-                        reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
-                        step(p);
-                    }
-                });
-                if (fused) plast = pnx;
-                st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
-            }
-            if (fused) { // the update the last step left pending
-                k_cg_x<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, plast, x);
-                LAUNCH_CHECK();
+                        precondition(h, r, cast_fused ? nullptr : z, S_RZ, flexible ? q : nullptr,
+                                     cast_fused);
+                        k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
+                        LAUNCH_CHECK();
+                        if (fused) {
+                            const MarchShape ms = stencil_shape(g0);
+                            {
+                                ProfScope ps(h, CPS_KERNEL_APPLY, 0); // the product only
+                                if (cast_fused)
+                                    k_apply_dircast_march2<<<ms.grid, kBlock, 0, h->stream>>>(
+                                        g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch,
+                                        h->lv[0].x32.p, h->sc.p, S_SCALE, S_BETA, pc, pnx, q,
+                                        h->partial.p, x);
+                                else
+                                    k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
+                                        g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
+                                        h->sc.p + S_BETA, pnx, q, h->partial.p, x,
+                                        h->sc.p + S_ALPHA);
+                                LAUNCH_CHECK();
+                            }
+                            reduce(h, ms.grid, S_PQ);
+                            step(pnx);
+                        } else {
+                            k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
+                            LAUNCH_CHECK();
+                            reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
+                            step(p);
+                        }
+                    });
+                    if (fused) plast = pnx;
+                    st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
+                }
+                if (fused) { // the update the last step left pending
+                    k_cg_x<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, plast, x);
+                    LAUNCH_CHECK();
+                }
+                if (st != CPS_OK) break;
+                st = true_residual(h, bb, tol, &rel);
+                if (st != CPS_E_NOT_CONVERGED || it >= maxit) break;
+                // restart from the residual of the iterate: the next direction
+                // is the preconditioned residual alone (its previous direction
+                // is zero, and so is the pending update that the fused product
+                // applies with it)
+                fill<double>(h, plast, n, 0.0);
+                if (cast_fused) {
+                    k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, r, r32, h->sc.p,
+                                                                             S_SCALE, 1);
+                    LAUNCH_CHECK();
+                }
             }
         } else {
             // BiCGStab (accel = 2), right-preconditioned by the V-cycle
             double* r = h->r.p;
             double* p = h->pd.p;
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, r);
-            k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, h->b0.p, h->r0.p);
             LAUNCH_CHECK();
-            fill<double>(h, p, n, 0.0);
-            fill<double>(h, h->v.p, n, 0.0);
-            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO, 1.0); // becomes rho_old
-            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_ALPHA, 1.0);
-            k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_OMEGA, 1.0);
-            LAUNCH_CHECK();
+            auto start = [&] { // (re)start from the residual in r
+                k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, r, h->r0.p);
+                LAUNCH_CHECK();
+                fill<double>(h, p, n, 0.0);
+                fill<double>(h, h->v.p, n, 0.0);
+                k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO, 1.0); // becomes rho_old
+                k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_ALPHA, 1.0);
+                k_set_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_OMEGA, 1.0);
+                LAUNCH_CHECK();
+            };
+            start();
             for (it = 1; it <= maxit; ++it) {
                 run_body(h, G_BICG, [&] {
                     k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RHO_OLD, S_RHO);
@@ -1323,6 +1357,10 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                     copy_norm(h, S_RR);
                 });
                 st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
+                if (st == CPS_OK) { // the recurrence says so: check b - A x
+                    st = true_residual(h, bb, tol, &rel);
+                    if (st == CPS_E_NOT_CONVERGED && it < maxit) start();
+                }
                 if (st != CPS_E_NOT_CONVERGED) break;
             }
         }

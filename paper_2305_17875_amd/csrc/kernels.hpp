@@ -1877,6 +1877,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_x(long long n, const double* __re
     if (i < n) x[i] = __builtin_fma(sc[S_ALPHA], p[i], x[i]);
 }
 
+// r = b - y with y = A x: the residual of the iterate itself (the Krylov
+// recurrences update r without forming it)
+__device__ __forceinline__ void d_sub(Blk bk, long long n, const double* __restrict__ b,
+                                      const double* __restrict__ y, double* __restrict__ r)
+{
+    const long long i = (long long)bk.L * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = b[i] - y[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub(long long n, const double* __restrict__ b,
+                                                const double* __restrict__ y,
+                                                double* __restrict__ r)
+{
+    d_sub(self_blk(), n, b, y, r);
+}
+
 // p = z + beta p
 __device__ __forceinline__ void d_cg_dir(Blk bk, long long n, const double* __restrict__ sc,
                                                    const double* __restrict__ z,
@@ -2276,7 +2292,8 @@ __global__ void kb_gather(const PDesc<T>* __restrict__ pd, int nprob, int slot, 
 }
 
 // element-wise finest-level operations
-enum { EOP_FILL = 0, EOP_COPY, EOP_CG_DIR, EOP_BICG_DIR, EOP_BICG_S, EOP_TO_SPLIT, EOP_FROM_SPLIT };
+enum { EOP_FILL = 0, EOP_COPY, EOP_CG_DIR, EOP_BICG_DIR, EOP_BICG_S, EOP_TO_SPLIT, EOP_FROM_SPLIT,
+       EOP_SUB };
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) kb_elem(const BItem* __restrict__ items,
@@ -2295,6 +2312,7 @@ __global__ void __launch_bounds__(kBlock) kb_elem(const BItem* __restrict__ item
     case EOP_BICG_DIR: d_bicg_dir(bk, n, P.sc, P.vec[a], P.vec[b], P.vec[c]); break;
     case EOP_BICG_S: d_bicg_s(bk, n, P.sc, P.vec[a], P.vec[b], P.vec[c]); break;
     case EOP_TO_SPLIT: d_to_split<double, double>(bk, g, P.vec[a], P.vec[b], c >= 0 ? P.sc + c : nullptr); break;
+    case EOP_SUB: d_sub(bk, n, P.vec[a], P.vec[b], P.vec[c]); break;
     default: d_from_split<double, double>(bk, g, P.vec[a], P.vec[b], c >= 0 ? P.sc + c : nullptr); break;
     }
 }

@@ -147,3 +147,30 @@ def test_batch_plane_smoother_on_long_oblate_rings():
         assert np.array_equal(x, xa), (i, np.abs(x - xa).max())
         want = direct.solve_axisym(O.face_metrics(g), b)
         assert rel(x, want) <= 1e-9, (i, rel(x, want))
+
+
+def test_batch_equals_alone_near_fp64_reach():
+    """At a tolerance near what FP64 can reach, the conjugate-gradient
+    recurrence and the residual of the iterate part, and both forms check
+    (and restart from) the latter in the same way: still the same bits."""
+    grids = [GRIDS[0], GRIDS[1], GRIDS[7]]
+    rhs = [rhs_of(i, g) for i, g in enumerate(grids)]
+    tol = 1e-13
+    log("batch near fp64 reach")
+    B = cps.Batch(grids, max_iters=60)
+    try:
+        st, p, infos = B.solve([dev(b).flatten() for b in rhs], tol)
+        xs = [host(t).reshape(g.shape) for t, g in zip(p, grids)]
+    finally:
+        B.close()
+    for i, (g, b, x, info) in enumerate(zip(grids, rhs, xs, infos)):
+        s = cps.Solver(g, precision=1, accel=1, max_iters=60)
+        try:
+            r = s.solve(dev(b).flatten(), tol)
+            xa = host(r.p).reshape(g.shape)
+        finally:
+            s.close()
+        log(i, "iterations", info.iterations, r.iterations, "rel", info.rel_residual,
+            r.rel_residual)
+        assert info.iterations == r.iterations and info.rel_residual == r.rel_residual, i
+        assert np.array_equal(x, xa), (i, np.abs(x - xa).max())

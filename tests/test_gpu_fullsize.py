@@ -1,15 +1,23 @@
 """Parity at the paper-scale shell (192 r x 256 theta x 512 phi, tanh
 clustering 2.0, smoothed N(0,1) right-hand side, seed 0) in the launch
-configuration bench.py times, FP64 and FP32-multigrid + FP64 refinement.
+configuration bench.py times: FP64 and FP32-multigrid + FP64 refinement, each
+with the point red-black and the zebra plane smoother, conjugate gradients.
 
-The full exact solution is too costly for a test, so the oracle checks
-properties that hold at any size and outputs it can compute one at a time:
-  * the oracle's own FP64 residual of the GPU answer, ||b - A p|| / ||b||;
-  * sampled azimuthal Fourier modes of p: the metrics are phi-invariant and
-    do not couple phi with r or theta, so every mode of the exact solution
-    is one sparse 2-D solve (oracle.direct); each sampled mode must match to
-    1e-9 of ||p||.
+The reference is the exact discrete solution, element by element: the
+metrics are phi-invariant and do not couple phi with r or theta, so an rFFT
+in phi splits A into one sparse (r, theta) system per azimuthal mode
+(oracle.direct.solve_axisym, 257 sparse LU solves of 49,152 unknowns, in a
+process pool).  Each GPU answer must be within 1e-9 of it in relative L2
+norm; the largest element error is logged.  The oracle's own FP64 residual of
+each answer must meet the tolerance and agree with the residual the library
+reports (the library checks b - A p itself before it stops).
+
+The batched form is checked the same way at the two largest sizes of its
+size set: a 128 x 128 x 256 sphere and a 96 x 128 x 256 oblate shell
+(flattening 0.1, r-theta cross terms).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -20,55 +28,76 @@ from gpu_util import needs_gpu, log, dev, host, torch
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
-MODES = [0, 1, 2, 17, 128, 256]
+TOL = 1e-10
+WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def exact(G, b, what):
+    def progress(done, total):
+        if done % 64 == 0 or done == total:
+            log(f"{what}: exact modes {done}/{total}")
+    return direct.solve_axisym(G, b, workers=WORKERS, progress=progress)
 
 
 @pytest.fixture(scope="module")
-def problem():
+def config2():
     g = inputs.config2()
     log("fullsize oracle setup", g.shape)
     b = inputs.smoothed_noise(g.shape, seed=0)
     G = O.face_metrics(g)
     assert direct.is_axisymmetric(G)
-    A2, gpp = direct._axisym_2d(G)
-    return g, b, G, A2, gpp
+    x = exact(G, b, "config 2")
+    return g, b, G, x
 
 
-def exact_mode(A2, gpp, bhat_m, m, n_phi):
-    import scipy.sparse as sp
-    import scipy.sparse.linalg as spla
-    n2 = A2.shape[0]
-    if m == 0:
-        one = sp.csr_matrix(np.ones((n2, 1)))
-        K = sp.bmat([[A2, one], [one.T, None]], format="csc")
-        lu = spla.splu(K)
-        f = lambda v: lu.solve(np.concatenate([v, [0.0]]))[:n2]
-    else:
-        lu = spla.splu((A2 + sp.diags(-4.0 * np.sin(np.pi * m / n_phi) ** 2 * gpp)).tocsc())
-        f = lambda v: lu.solve(np.ascontiguousarray(v))
-    return f(bhat_m.real.ravel()) + 1j * f(bhat_m.imag.ravel())
+def check_answer(G, b, x, want, reported_rel, what):
+    bb = b - b.mean()
+    assert abs(x.mean()) <= 1e-13 * np.abs(x).max()
+    rel_o = np.linalg.norm(O.residual(G, bb, x)) / np.linalg.norm(bb)
+    err = np.linalg.norm(x - want) / np.linalg.norm(want)
+    emax = np.abs(x - want).max() / np.abs(want).max()
+    log(f"{what}: rel L2 error {err:.3e}, max error {emax:.3e} (of max |x|), oracle residual "
+        f"{rel_o:.3e}, reported {reported_rel:.3e}")
+    # the library stops on ||b - A p|| computed in FP64 on the device; the
+    # oracle forms the same norm in another order
+    assert rel_o <= TOL * (1 + 1e-3), rel_o
+    assert abs(rel_o - reported_rel) <= 1e-3 * reported_rel, (rel_o, reported_rel)
+    assert err <= 1e-9, err
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_config2_solution(problem, precision):
-    g, b, G, A2, gpp = problem
-    log("fullsize solve precision", precision)
-    s = cps.Solver(g, precision=precision, accel=1, max_iters=400)
+@pytest.mark.parametrize("precision,smoother", [(0, 0), (1, 0), (0, 1), (1, 1)],
+                         ids=["fp64-point", "mixed-point", "fp64-plane", "mixed-plane"])
+def test_config2_solution(config2, precision, smoother):
+    g, b, G, want = config2
+    log("fullsize solve precision", precision, "smoother", smoother)
+    s = cps.Solver(g, precision=precision, accel=1, max_iters=400, smoother=smoother)
     try:
-        res = s.solve(dev(b).flatten(), tol=1e-10)
+        res = s.solve(dev(b).flatten(), tol=TOL)
         x = host(res.p).reshape(g.shape)
     finally:
         s.close()
-    assert res.status == cps.CPS_OK and res.rel_residual <= 1e-10
-    assert abs(x.mean()) <= 1e-13 * np.abs(x).max()
-    bb = b - b.mean()
-    r = O.residual(G, bb, x)
-    rel = np.linalg.norm(r) / np.linalg.norm(bb)
-    assert rel <= 1.2e-10, rel
-    xh = np.fft.rfft(x, axis=2)
-    bh = np.fft.rfft(bb, axis=2)
-    xn = np.linalg.norm(x) * np.sqrt(g.n_phi)  # Parseval scale of the rfft coefficients
-    for m in MODES:
-        want = exact_mode(A2, gpp, bh[:, :, m], m, g.n_phi)
-        err = np.linalg.norm(xh[:, :, m].ravel() - want) / xn
-        assert err <= 1e-9, (m, err)
+    log("iterations", res.iterations, "rel", res.rel_residual)
+    assert res.status == cps.CPS_OK and res.rel_residual <= TOL
+    check_answer(G, b, x, want, res.rel_residual, f"precision {precision} smoother {smoother}")
+
+
+@pytest.mark.parametrize("smoother", [0, 2], ids=["point", "auto"])
+def test_batch_largest_sizes(smoother):
+    grids = [inputs.Shell(128, 128, 256),
+             inputs.Shell(96, 128, 256, map=inputs.MAP_OBLATE, flattening=0.1)]
+    rhs = [inputs.smoothed_noise(g.shape, 1000 + i) for i, g in enumerate(grids)]
+    log("batch of the largest sizes, smoother", smoother)
+    B = cps.Batch(grids, smoother=smoother)
+    try:
+        st, ps, infos = B.solve([dev(r).flatten() for r in rhs], TOL)
+        xs = [host(p).reshape(g.shape) for p, g in zip(ps, grids)]
+    finally:
+        B.close()
+    assert st == cps.CPS_OK
+    for g, r, x, info in zip(grids, rhs, xs, infos):
+        G = O.face_metrics(g)
+        assert direct.is_axisymmetric(G)
+        want = exact(G, r, f"batch {g.shape} map {g.map}")
+        assert info.rel_residual <= TOL
+        check_answer(G, r, x, want, info.rel_residual,
+                     f"batch {g.shape} map {g.map} iterations {info.iterations}")

@@ -1,6 +1,8 @@
 """The full sphere (theta0 = 0, theta1 = pi) on the GPU: the polar faces have
 zero area and carry no flux, so the same kernels apply.  Solves with both
-smoothers and precisions against the oracle's exact solution; the
+smoothers and precisions, on the sphere and on the oblate shell (whose
+polar rows carry r-theta cross metrics), against the oracle's exact
+solution; the
 projection step's divergence and correction and the ADI line solves (theta
 lines ending on both poles) against the oracle entry by entry."""
 import numpy as np
@@ -21,13 +23,15 @@ def _sphere(nr, nt, np_, **kw):
     return Shell(nr, nt, np_, theta0=0.0, theta1=PI, **kw)
 
 
+@pytest.mark.parametrize("flattening", [0.0, 0.1], ids=["sphere", "oblate"])
 @pytest.mark.parametrize("smoother", [0, 1], ids=["point", "plane"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_full_sphere_solve_against_exact(smoother, precision):
-    g = _sphere(16, 16, 64, radial_stretch=2.0)
+def test_full_sphere_solve_against_exact(smoother, precision, flattening):
+    kw = dict(map=inputs.MAP_OBLATE, flattening=flattening) if flattening else {}
+    g = _sphere(16, 16, 64, radial_stretch=2.0, **kw)
     b = inputs.smoothed_noise(g.shape, 80)
     want = direct.solve_axisym(O.face_metrics(g), b)
-    log("full sphere solve", smoother, precision)
+    log("full sphere solve", smoother, precision, flattening)
     s = cps.Solver(g, precision=precision, accel=1, smoother=smoother, max_iters=400)
     try:
         r = s.solve(dev(b).flatten())

@@ -36,6 +36,11 @@ CASES = [
     # coarse rings of 128 phi pairs: two wavefronts per coarse row, so the
     # restriction's outer phi values cross a wavefront boundary inside a ring
     ("sphere-wide-8x8x512", Shell(8, 8, 512), 0),
+    # full spheres (theta from 0 to pi): the polar rows' r-faces carry an
+    # r-theta cross metric on the oblate shell and with vertex metrics
+    ("oblate-fullsphere-16x12x20",
+     Shell(16, 12, 20, map=MAP_OBLATE, flattening=0.1, theta0=0.0, theta1=np.pi), 0),
+    ("sphere-vertex-fullsphere-12x8x16", Shell(12, 8, 16, theta0=0.0, theta1=np.pi), 1),
 ]
 
 

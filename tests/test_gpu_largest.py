@@ -1,8 +1,11 @@
 """The paper's largest grid (tests/golden/paper_grids.txt): 256 (r) x 512 (theta) x 512 (phi) = 67.1 M
 cells with tanh clustering 2.0 (a 7-level hierarchy, ~7.4 GB in FP64).
 FP64 solves with the point and the plane smoother reach relative residual
-1e-10; the check is the oracle's own FP64 residual of the GPU answer and the
-zero mean, properties that hold at any size."""
+1e-10; the check is the oracle's own FP64 residual of the GPU answer (it
+must meet the tolerance and agree with the residual the library reports) and
+the zero mean, properties that hold at any size.  Element-wise comparison
+with the exact solution is done at the paper-scale shell
+(test_gpu_fullsize.py)."""
 import numpy as np
 import pytest
 
@@ -41,6 +44,10 @@ def test_largest_grid_solve(largest, smoother):
     log("largest grid iterations", res.iterations, "rel", res.rel_residual)
     assert res.status == cps.CPS_OK and res.rel_residual <= 1e-10
     bb = b - b.mean()
-    r = O.residual(G, bb, x)
-    assert np.linalg.norm(r) <= 1.5e-10 * np.linalg.norm(bb)
+    rel_o = np.linalg.norm(O.residual(G, bb, x)) / np.linalg.norm(bb)
+    log("largest grid oracle residual", rel_o)
+    # the library stops on ||b - A p|| itself (formed in FP64 on the device);
+    # the oracle forms the same norm in another order
+    assert rel_o <= 1e-10 * (1 + 1e-3), rel_o
+    assert abs(rel_o - res.rel_residual) <= 1e-3 * res.rel_residual, (rel_o, res.rel_residual)
     assert abs(x.mean()) <= 1e-12 * np.abs(x).max()

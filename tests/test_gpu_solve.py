@@ -196,3 +196,31 @@ def test_profile_classes_and_grouped_colour_passes():
     assert others == [0] * 7, others
     assert vn == r2.iterations and vms > 0
     assert np.array_equal(x0, x1)
+
+
+@pytest.mark.parametrize("tol", [1e-10, 1e-13], ids=["tol1e-10", "tol1e-13"])
+@pytest.mark.parametrize("precision,accel", [(0, 0), (0, 1), (1, 1), (0, 2)])
+def test_reported_residual_is_that_of_the_answer(precision, accel, tol):
+    """info.rel_residual is ||b - A p|| / ||b|| of the p returned (the Krylov
+    recurrences are checked against it before the solve stops), also at a
+    tolerance near FP64's reach, where recurrence and true residual part:
+    a solve then restarts from the true residual or stops at the cap."""
+    if accel == 2:
+        g = Shell(16, 16, 64, map=MAP_OBLATE, flattening=0.1, radial_stretch=2.0)
+    elif accel == 1:
+        g = Shell(16, 16, 128, radial_stretch=2.0)
+    else:  # the stationary iteration: a shell it contracts on in tens of cycles
+        g = Shell(16, 16, 32)
+    b = inputs.smoothed_noise(g.shape, seed=77)
+    log("reported residual", precision, accel, tol)
+    x, res = solve(g, b, precision, accel, tol=tol, max_iters=400 if accel == 0 else 80)
+    assert res.status in (cps.CPS_OK, cps.CPS_E_NOT_CONVERGED)
+    bb = b - b.mean()
+    rel_o = np.linalg.norm(O.residual(O.face_metrics(g), bb, x)) / np.linalg.norm(bb)
+    log("iterations", res.iterations, "reported", res.rel_residual, "oracle", rel_o)
+    assert abs(rel_o - res.rel_residual) <= 1e-3 * res.rel_residual + 2e-14, (rel_o,
+                                                                              res.rel_residual)
+    if res.status == cps.CPS_OK:
+        assert res.rel_residual <= tol
+    if tol == 1e-10:
+        assert res.status == cps.CPS_OK
