@@ -224,6 +224,34 @@ typedef struct {
 cps_status cps_line_solve(cps_handle* h, int32_t dir, double coef, const cps_line_bc* bc,
                           const double* rhs, double* psi);
 
+/* ---- Line solves without allocation -----------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight time-step or serving loops, harnesses that forbid
+ * hipMalloc.  cps_line_solve with the same arguments and the same result,
+ * bit for bit, but every table that cps_line_solve builds on first use and
+ * keeps in the handle (the face tables, the elimination of the open lines,
+ * the ring transform's tables) is formed anew on each call in one fixed
+ * device array of CPS_LINE_SCRATCH_BYTES per GPU, which the library holds
+ * from its load until the process ends.  The call only launches kernels on
+ * the handle's stream: no allocation, free, copy, memset or
+ * synchronisation, so it can be captured into a graph (the handle itself
+ * is set up beforehand with cps_setup).
+ * Limits: phi-invariant metrics (box, sphere, oblate shell); the tables
+ * take 12 (n_r + 1)(n_theta + 1) + n_r n_theta words plus, for dir 0 / 1,
+ * 3 n + 2 words per distinct line (n_theta lines of n_r cells / n_r lines of
+ * n_theta cells) and, for dir 2, 2 n_phi + 3 words, each part rounded up to
+ * an even count, at most CPS_LINE_SCRATCH_BYTES / 8 words in all (the
+ * paper-scale 192 x 256 shell needs 5 MB); dir 2 needs n_phi / 2 a power of
+ * two in [2, 2048] and rhs, psi aligned to 16 bytes (the ring transform).
+ * Anything else: CPS_E_INVALID, and nothing is launched.
+ * The array is shared by every call on one GPU and keeps the last call's
+ * tables: calls that overlap in time on one GPU (other streams or threads)
+ * race with each other and give wrong results; the caller serialises them.
+ * Arguments and errors otherwise as cps_line_solve. */
+#define CPS_LINE_SCRATCH_BYTES (32u << 20)
+cps_status cps_line_solve_noalloc(cps_handle* h, int32_t dir, double coef, const cps_line_bc* bc,
+                                  const double* rhs, double* psi);
+
 /* ---- Kernel-level entry points (FP64 hierarchy of the handle) ----------
  * For parity tests of each step against an independent implementation.
  * level l indexes the hierarchy (0 = finest); all arrays are device FP64

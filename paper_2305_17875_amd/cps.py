@@ -125,7 +125,9 @@ def lib():
         L.cps_correct.argtypes = [P, P, P]
         L.cps_project.argtypes = [P, P, P, D, P]
         L.cps_line_solve.argtypes = [P, I, D, P, P, P]
+        L.cps_line_solve_noalloc.argtypes = [P, I, D, P, P, P]
         for f in ("cps_divergence", "cps_correct", "cps_project", "cps_line_solve",
+                  "cps_line_solve_noalloc",
                   "cps_profile_select", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
                   "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
                   "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
@@ -222,6 +224,15 @@ def cps_line_solve(h, d: int, coef: float, rhs, psi, bc=(0, 0.0, 0, 0.0)):
     _expect(rhs, n, "rhs"); _expect(psi, n, "psi")
     b = cps_line_bc(bc[0], bc[2], bc[1], bc[3])
     _check(lib().cps_line_solve(h, d, coef, ctypes.byref(b), _ptr(rhs), _ptr(psi)))
+
+
+def cps_line_solve_noalloc(h, d: int, coef: float, rhs, psi, bc=(0, 0.0, 0, 0.0)):
+    """cps_line_solve without allocation: its tables are formed on every
+    call in the library's fixed device array (kernel launches only)."""
+    _, n = _dims(h, 0)
+    _expect(rhs, n, "rhs"); _expect(psi, n, "psi")
+    b = cps_line_bc(bc[0], bc[2], bc[1], bc[3])
+    _check(lib().cps_line_solve_noalloc(h, d, coef, ctypes.byref(b), _ptr(rhs), _ptr(psi)))
 
 
 def cps_destroy(h):

@@ -1551,27 +1551,113 @@ bool fft_lines(const cps_handle* h, const double* rhs, const double* psi)
            ((uintptr_t)rhs % 16) == 0 && ((uintptr_t)psi % 16) == 0;
 }
 
+void ring_tables(cps_handle* h, double* tw, double* twN, double* lam)
+{
+    const int np = h->lv[0].np;
+    k_ring_tables<<<nblk(np / 2 + 1), kBlock, 0, h->stream>>>(np, tw, twN, lam);
+    LAUNCH_CHECK();
+}
+
 void ensure_ring_tables(cps_handle* h)
 {
     if (h->plam.p) return;
-    const int np = h->lv[0].np, nh = np / 2;
-    std::vector<double> tw(nh), twN(2 * (nh + 1)), lam(nh + 1);
-    for (int q = 0; q < nh / 2; ++q) {
-        tw[2 * q] = std::cos(-2.0 * M_PI * q / nh);
-        tw[2 * q + 1] = std::sin(-2.0 * M_PI * q / nh);
+    const int nh = h->lv[0].np / 2;
+    h->ptw.alloc(nh);
+    h->ptwN.alloc(2 * (nh + 1));
+    h->plam.alloc(nh + 1);
+    ring_tables(h, h->ptw.p, h->ptwN.p, h->plam.p);
+}
+
+// The fixed device array of the allocation-free line solve.  In host code
+// `line_scratch` names a host-side stand-in, not device memory: kernels get
+// the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kLineScratchWords = CPS_LINE_SCRATCH_BYTES / sizeof(double);
+__device__ __align__(256) double line_scratch[kLineScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of line_scratch on the current device, resolved once per
+// device (at set-up, so that a later call under graph capture finds it).
+double* line_scratch_ptr()
+{
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(CPS_E_INVALID, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(line_scratch)));
+        g_scratch_dev[dev] = static_cast<double*>(p);
     }
-    for (int k = 0; k <= nh; ++k) {
-        twN[2 * k] = std::cos(-2.0 * M_PI * k / np);
-        twN[2 * k + 1] = std::sin(-2.0 * M_PI * k / np);
-        lam[k] = 2.0 * std::cos(2.0 * M_PI * k / np) - 2.0;
+    return g_scratch_dev[dev];
+}
+
+// cps_line_solve with its tables formed in line_scratch on every call:
+// the same kernels in the same order, launches only.
+void line_solve_noalloc(cps_handle* h, int dir, double coef, const LineBC& bc,
+                        const double* rhs, double* psi)
+{
+    const LevelMem& m = h->lv[0];
+    if (csym(h) == kPerCell)
+        fail(CPS_E_INVALID, "line solves need phi-invariant metrics (box, sphere, oblate)");
+    auto even = [](long long w) { return (w + 1) & ~1LL; }; // 16-byte aligned parts
+    const long long F = (long long)(m.nr + 1) * (m.nt + 1), nj = (long long)m.nr * m.nt;
+    const int lines = dir == 0 ? m.nt : m.nr, n = dir == 0 ? m.nr : m.nt, nh = m.np / 2;
+    const long long tables = dir < 2 ? even(3LL * lines * n + 2LL * lines)
+                                     : even(nh) + even(2LL * (nh + 1)) + even(nh + 1);
+    const long long words = even(9 * F) + even(3 * F) + even(nj) + tables;
+    if (words > (long long)kLineScratchWords)
+        fail(CPS_E_INVALID, "the line solve's tables need %lld bytes, more than the %zu of the "
+             "allocation-free array", 8 * words, (size_t)CPS_LINE_SCRATCH_BYTES);
+    if (dir == 2 && !fft_lines(h, rhs, psi))
+        fail(CPS_E_INVALID, "the allocation-free phi-line solve needs n_phi / 2 a power of two "
+             "in [2, %d] and 16-byte aligned fields", kPlaneLds);
+    double* C = line_scratch_ptr();
+    double* Jf = C + even(9 * F);
+    double* Jc = Jf + even(3 * F);
+    double* T = Jc + even(nj);
+    const cps_grid& g = h->grid;
+    const MapParams mp{g.map, g.r_inner, g.r_outer, g.theta0, g.theta1, g.radial_stretch,
+                       g.flattening, g.skew};
+    k_crows<<<nblk(F), kBlock, 0, h->stream>>>(mp, m.nr, m.nt, m.np, 1, h->met.method, C, Jf);
+    LAUNCH_CHECK();
+    k_cell_jdet<<<nblk(nj), kBlock, 0, h->stream>>>(m.nr, m.nt, 1, Jf, Jc);
+    LAUNCH_CHECK();
+    const CRows R{C, F, m.nt + 1, 1, nullptr};
+    if (dir < 2) {
+        double* Fm = T;
+        double* Fi = Fm + (size_t)lines * n;
+        double* Fh = Fi + (size_t)lines * n;
+        double* Fx = Fh + (size_t)lines * n;
+        k_line_factor<<<nblk(lines), kBlock, 0, h->stream>>>(m.nr, m.nt, dir, coef, bc, R, Jf, Jc,
+                                                             Fm, Fi, Fh, Fx);
+        LAUNCH_CHECK();
+        const long long threads = (long long)lines * m.np;
+        if (dir == 0)
+            k_line_open<0><<<nblk(threads), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, Fm, Fi, Fh,
+                                                                    Fx, rhs, psi);
+        else
+            k_line_open<1><<<nblk(threads), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, Fm, Fi, Fh,
+                                                                    Fx, rhs, psi);
+        LAUNCH_CHECK();
+        return;
     }
-    auto up = [&](Buf<double>& d, const std::vector<double>& v) {
-        d.alloc(v.size());
-        upload(d.p, v.data(), v.size() * sizeof(double));
-    };
-    up(h->ptw, tw);
-    up(h->ptwN, twN);
-    up(h->plam, lam);
+    double* tw = T;
+    double* twN = tw + even(nh);
+    double* lam = twN + even(2LL * (nh + 1));
+    ring_tables(h, tw, twN, lam);
+    const FftLineLaunch pl = fft_line_launch(m.nr, m.nt, m.np);
+    const auto* tw2 = reinterpret_cast<const Vec2<double>*>(tw);
+    const auto* twN2 = reinterpret_cast<const Vec2<double>*>(twN);
+    if (nh <= kSmallRing)
+        k_line_fft<kSmallRing><<<pl.blocks, pl.threads, 0, h->stream>>>(
+            m.nr, m.nt, m.np, coef, R, Jf, Jc, tw2, twN2, lam, rhs, psi);
+    else
+        k_line_fft<kPlaneLds><<<pl.blocks, pl.threads, 0, h->stream>>>(
+            m.nr, m.nt, m.np, coef, R, Jf, Jc, tw2, twN2, lam, rhs, psi);
+    LAUNCH_CHECK();
 }
 
 void line_solve(cps_handle* h, int dir, double coef, const LineBC& bc, const double* rhs,
@@ -1671,6 +1757,7 @@ cps_status cps_setup(const cps_grid* grid, const cps_metrics* metrics, const cps
         if (opts) h->opts = *opts;
         h->stream = (hipStream_t)h->opts.stream;
         build(h);
+        line_scratch_ptr(); // the allocation-free line solve's array on this device
     });
     if (st != CPS_OK) {
         destroy(h);
@@ -1904,26 +1991,51 @@ cps_status cps_project(cps_handle* h, double* u, double* phi, double tol, cps_in
     return g != CPS_OK ? g : st;
 }
 
+} // extern "C"
+
+namespace {
+
+// Argument checks shared by both line-solve entry points.
+LineBC line_args(const cps_handle* h, int32_t dir, double coef, const cps_line_bc* bc,
+                 const double* rhs, const double* psi)
+{
+    if (!h || !rhs || !psi) fail(CPS_E_INVALID, "NULL argument");
+    if (dir < 0 || dir > 2) fail(CPS_E_INVALID, "dir must be 0 (r), 1 (theta) or 2 (phi)");
+    if (!(coef >= 0.0) || !std::isfinite(coef)) fail(CPS_E_INVALID, "coef must be >= 0");
+    if (!h->axi)
+        fail(CPS_E_INVALID, "line solves need phi-invariant metrics (box, sphere, oblate)");
+    if (dir == 2 && h->lv[0].np < 3) fail(CPS_E_INVALID, "periodic lines need n_phi >= 3");
+    const long long n = h->lv[0].n;
+    if (rhs != psi && rhs + n > psi && rhs < psi + n)
+        fail(CPS_E_INVALID, "rhs and psi must be the same array or not overlap");
+    LineBC b{0, 0, 0.0, 0.0};
+    if (bc) {
+        if (bc->type_lo < 0 || bc->type_lo > 1 || bc->type_hi < 0 || bc->type_hi > 1)
+            fail(CPS_E_INVALID, "bc types must be 0 (no flux) or 1 (value)");
+        b = LineBC{bc->type_lo, bc->type_hi, bc->value_lo, bc->value_hi};
+    }
+    return b;
+}
+
+} // namespace
+
+extern "C" {
+
 cps_status cps_line_solve(cps_handle* h, int32_t dir, double coef, const cps_line_bc* bc,
                           const double* rhs, double* psi)
 {
     return guarded([&] {
-        if (!h || !rhs || !psi) fail(CPS_E_INVALID, "NULL argument");
-        if (dir < 0 || dir > 2) fail(CPS_E_INVALID, "dir must be 0 (r), 1 (theta) or 2 (phi)");
-        if (!(coef >= 0.0) || !std::isfinite(coef)) fail(CPS_E_INVALID, "coef must be >= 0");
-        if (!h->axi)
-            fail(CPS_E_INVALID, "line solves need phi-invariant metrics (box, sphere, oblate)");
-        if (dir == 2 && h->lv[0].np < 3) fail(CPS_E_INVALID, "periodic lines need n_phi >= 3");
-        const long long n = h->lv[0].n;
-        if (rhs != psi && rhs + n > psi && rhs < psi + n)
-            fail(CPS_E_INVALID, "rhs and psi must be the same array or not overlap");
-        LineBC b{0, 0, 0.0, 0.0};
-        if (bc) {
-            if (bc->type_lo < 0 || bc->type_lo > 1 || bc->type_hi < 0 || bc->type_hi > 1)
-                fail(CPS_E_INVALID, "bc types must be 0 (no flux) or 1 (value)");
-            b = LineBC{bc->type_lo, bc->type_hi, bc->value_lo, bc->value_hi};
-        }
+        const LineBC b = line_args(h, dir, coef, bc, rhs, psi);
         line_solve(h, dir, coef, b, rhs, psi);
+    });
+}
+
+cps_status cps_line_solve_noalloc(cps_handle* h, int32_t dir, double coef, const cps_line_bc* bc,
+                                  const double* rhs, double* psi)
+{
+    return guarded([&] {
+        const LineBC b = line_args(h, dir, coef, bc, rhs, psi);
+        line_solve_noalloc(h, dir, coef, b, rhs, psi);
     });
 }
 

@@ -104,6 +104,32 @@ __global__ void __launch_bounds__(kBlock) k_line_factor(int nr, int nt, int d, d
     Fx[2 * p + 1] = exl;
 }
 
+// Tables of the ring transform for rings of n_phi = np cells (nh = np / 2
+// complex values): tw[q] = exp(-2 pi i q / nh) for q < nh / 2, twN[k] =
+// exp(-2 pi i k / n_phi) and lam[k] = 2 cos(2 pi k / n_phi) - 2 for k <= nh
+// (as (re, im) pairs for tw and twN).  Formed on the device, so that a call
+// that may not copy from the host can build them too.
+__global__ void __launch_bounds__(kBlock) k_ring_tables(int np, double* __restrict__ tw,
+                                                        double* __restrict__ twN,
+                                                        double* __restrict__ lam)
+{
+    const int nh = np / 2;
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k < nh / 2) {
+        double sn, cs;
+        sincos(-2.0 * M_PI * k / nh, &sn, &cs);
+        tw[2 * k] = cs;
+        tw[2 * k + 1] = sn;
+    }
+    if (k <= nh) {
+        double sn, cs;
+        sincos(-2.0 * M_PI * k / np, &sn, &cs);
+        twN[2 * k] = cs;
+        twN[2 * k + 1] = sn;
+        lam[k] = 2.0 * cos(2.0 * M_PI * k / np) - 2.0;
+    }
+}
+
 // Open lines along d (0 r, 1 theta): one thread per (other index, c).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_line_open(int nr, int nt, int np,
