@@ -10,7 +10,13 @@ to relative residual 1e-10.  The FP32-multigrid + FP64-refinement form is
 timed on the same input and reported beside it, and so is the same solve
 with the zebra (r, phi)-plane smoother (`plane`); the whole projection step
 around the solve is timed under `project`, and the implicit line solves of
-the ADI steps under `lines`.  Prints one JSON line.
+the ADI steps under `lines`; the 64-problem batched form under `batch`, the
+cache-resident 32^3 shell under `config1`, and a 60 s stream of Poisson
+arrivals at 200/s through the solve service under `serve`.  The CPU leg
+then times the oracle on the host (`cpu_baseline`) and computes the exact
+discrete solution of the paper-scale shell and of every batch problem, and
+each form's answer is compared with it (`error_vs_oracle`).  Prints one JSON
+line.
 
 Roofline: the dominant kernel is the finest-level Gauss-Seidel colour pass.
 Its duration is measured live with HIP events recorded on the solve stream
@@ -169,7 +175,8 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
     torch.cuda.synchronize()
     log(f"precision={precision} smoother={smoother}: {dt * 1e3:.1f} ms/solve, iterations={iters}, "
         f"rel_residual={res.rel_residual:.3e}")
-    return dict(solver=s, p=p, res=res, sec=dt, iters=iters, prof=prof, prof_steps=PROF_STEPS,
+    return dict(solver=s, p=p, host_p=p.cpu().numpy().reshape(g.shape), res=res, sec=dt,
+                iters=iters, prof=prof, prof_steps=PROF_STEPS,
                 setup_s=setup_s, solve_ms_median=statistics.median(solve_s) * 1e3,
                 solve_ms_min=min(solve_s) * 1e3,
                 timed_gs=timed_gs)
@@ -219,7 +226,7 @@ def yardstick(cps, torch, n):
     return 16.0 * n / dt / 1e9
 
 
-def plane_form(cps, torch, g, rhs, x64, steps, warmup):
+def plane_form(cps, torch, g, rhs, x64, steps, warmup, answers):
     """The same solve with the zebra (r, phi)-plane smoother in place of
     point red-black Gauss-Seidel (cps_opts.smoother = 1): FP64 and FP32
     cycles, each with its half-sweep rate against the byte model of
@@ -228,6 +235,7 @@ def plane_form(cps, torch, g, rhs, x64, steps, warmup):
                        "Thomas along r per mode; V(2,2), PCG"}
     for precision, key, word in ((0, "fp64", 8), (1, "mixed", 4)):
         f = run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=1)
+        answers[("plane", key)] = f["host_p"]
         hs_ms, hs_n = f["timed_gs"]  # HIP events over the timed region
         hs_s = hs_ms / max(hs_n, 1) * 1e-3
         hb = plane_half_sweep_bytes(g.shape, word)
@@ -343,30 +351,148 @@ def lines_form(cps, torch, inputs, g, steps, warmup):
     return out
 
 
-def cpu_baseline(g, rhs_np, gpu_iters):
-    """The oracle's multigrid (same levels, smoother, transfers, coarse
-    solve and conjugate-gradient outer iteration) on the full grid, timed for
-    two outer iterations on the host cores and scaled to the iteration count
-    the same algorithm needs to reach 1e-10."""
+def config1_form(cps, torch, inputs, steps, warmup):
+    """The cache-resident 32^3 shell (uniform radius, cone walls): a plain
+    FP64 V(2,2) red-black iteration (`vcycle`, accel 0) and the same cycle
+    under conjugate gradients (`pcg`), to relative residual 1e-10.  The
+    right-hand side is A p_s for the manufactured p_s = cos(pi xi) sin(2 phi)
+    sin(theta), formed by the library's own operator (cps_debug_apply), so
+    the exact answer is p_s - mean(p_s).  The working set (a few MB) stays in
+    the caches: the figures are time per solve, per iteration and per
+    V-cycle, which show the launch overhead, not an HBM fraction."""
+    g = inputs.config1()
+    ps = inputs.manufactured_p(g)
+    want = ps - ps.mean()
+    out = {"workload": "sphere shell 32^3, r 1.5..2.5 uniform, theta 0.05..pi-0.05, "
+                       "rhs = A p_s (p_s = cos(pi xi) sin(2 phi) sin(theta)), rel residual 1e-10"}
+    stream = torch.cuda.Stream()
+    for accel, key in ((0, "vcycle"), (1, "pcg")):
+        s = cps.Solver(g, precision=0, accel=accel, max_iters=500, stream=stream)
+        pd = torch.from_numpy(ps).cuda().flatten()
+        b = torch.empty_like(pd)
+        cps.cps_debug_apply(s.h, 0, pd, b)
+        p = torch.empty_like(b)
+        for _ in range(warmup):
+            s.solve(b, TOL, out=p)
+        times, its = [], []
+        for _ in range(max(steps, 5)):
+            t0 = time.perf_counter()
+            res = s.solve(b, TOL, out=p)  # returns once p is written
+            times.append(time.perf_counter() - t0)
+            its.append(res.iterations)
+        x = p.cpu().numpy().reshape(g.shape)
+        err = float(np.linalg.norm(x - want) / np.linalg.norm(want))
+        t = statistics.median(times)
+        entry = {"solve_ms_median": t * 1e3, "solve_ms_min": min(times) * 1e3,
+                 "iterations": its[-1], "ms_per_iteration": t * 1e3 / its[-1],
+                 "rel_residual": res.rel_residual, "status": res.status,
+                 "rel_error_vs_exact": err, "unknowns_per_s": g.cells / t}
+        if accel == 1:
+            # the preconditioning V-cycle alone, HIP events around each cycle
+            # (profiling launches every kernel directly: no graph replay)
+            vc = KNAMES.index("vcycle")
+            cps.cps_profile_select(s.h, [vc])
+            cps.cps_profile_enable(s.h, True)
+            s.solve(b, TOL, out=p)
+            ms, cnt = cps.cps_profile_read(s.h, vc)
+            cps.cps_profile_enable(s.h, False)
+            entry["vcycle_us_direct_launches"] = ms / max(cnt, 1) * 1e3
+            # per smoothed level: 4 pre-passes, residual, restriction,
+            # prolongation, 4 post-passes; then the coarsest solve
+            entry["launches_per_vcycle"] = 11 * (len(s.levels) - 1) + 1
+        out[key] = entry
+        log(f"config1 {key}: {t * 1e3:.2f} ms/solve, {its[-1]} iterations, error {err:.2e}")
+        s.close()
+    return out
+
+
+def cpu_model():
+    """CPU model name and the logical CPUs this process may run on."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(g, rhs_np, answers, batch_ref):
+    """The CPU leg: the oracle timed on this host, and the oracle's exact
+    answers that every GPU result is compared with.
+
+    Timing: the oracle's own multigrid (same level plan, V(2,2) red-black
+    cycle, transfers, coarse solve and conjugate-gradient outer iteration as
+    the FP64 form) built with gcc -O3 -march=native on this host, one full
+    solve of the paper-scale shell to 1e-10 on every CPU this process may use
+    (set-up timed apart), and one outer iteration on a single thread.
+    Errors: the exact discrete solution of the paper-scale shell (rFFT in phi
+    and sparse LU per azimuthal mode, oracle.direct) against the answer of
+    each GPU form, and the same for every problem of the batched form."""
     import oracle as O
+    from oracle import direct
+    O.use_native_build()
+    model, cpus = cpu_model()
+    O.set_threads(cpus)
+    threads = O.max_threads()
     og = O.Grid(g.n_r, g.n_theta, g.n_phi, map=g.map, r_inner=g.r_inner, r_outer=g.r_outer,
                 theta0=g.theta0, theta1=g.theta1, radial_stretch=g.radial_stretch)
-    mg = O.Multigrid(og)
-    k = 2
     t0 = time.perf_counter()
-    mg.solve(rhs_np, tol=1e-300, max_iters=k, accel=1)
-    per_iter = (time.perf_counter() - t0) / k
-    n = g.n_r * g.n_theta * g.n_phi
-    threads = O.max_threads()
-    return {"value": n / (per_iter * gpu_iters), "unit": "unknowns/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{k} conjugate-gradient iterations of the oracle's V(2,2) multigrid on "
-                      f"the full {g.n_r}x{g.n_theta}x{g.n_phi} grid ({per_iter:.2f} s each on "
-                      f"{threads} OpenMP threads), scaled to the {gpu_iters} iterations the "
-                      f"same algorithm takes to reach 1e-10"}
+    mg = O.Multigrid(og)
+    setup = time.perf_counter() - t0
+    log(f"cpu baseline: oracle set-up {setup:.1f} s on {threads} threads ({model})")
+    t0 = time.perf_counter()
+    x, st, it, rel, _, _ = mg.solve(rhs_np, tol=TOL, max_iters=400, accel=1)
+    solve_s = time.perf_counter() - t0
+    log(f"cpu baseline: full solve {solve_s:.1f} s, {it} iterations, rel {rel:.2e}")
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    mg.solve(rhs_np, tol=1e-300, max_iters=1, accel=1)
+    one = time.perf_counter() - t0
+    O.set_threads(threads)
+    del mg
+    log(f"cpu baseline: one iteration on one thread {one:.1f} s")
+    n = g.cells
+    out = {"value": n / solve_s, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
+           "sample": f"one full solve of the paper-scale shell {g.n_r}x{g.n_theta}x{g.n_phi} to "
+                     f"rel residual 1e-10 by the oracle's V(2,2) multigrid with conjugate "
+                     f"gradients ({it} iterations, {solve_s:.1f} s; set-up {setup:.1f} s "
+                     f"apart) on {threads} OpenMP threads",
+           "status": st, "iterations": it, "rel_residual": rel, "seconds": solve_s,
+           "setup_s": setup, "single_thread_s_per_iteration": one,
+           "single_thread_unknowns_per_s_est": n / (one * it),
+           "cpu_model": model, "logical_cpus": cpus, "build": "gcc -O3 -march=native -fopenmp"}
+    # exact answers
+    errors = {}
+    workers = max(1, min(16, cpus))
+    t0 = time.perf_counter()
+    G = O.face_metrics(og)
+    with direct.mode_pool(workers) as pool:
+        xe = direct.solve_axisym(G, rhs_np, pool=pool)
+        del G
+        for key, xg in answers.items():
+            errors[key] = error_stats(xg, xe)
+        out["oracle_cpu_rel_error_vs_exact"] = error_stats(x, xe)["rel_l2"]
+        worst = None
+        for (grid, b, xg) in batch_ref:
+            e = error_stats(xg, direct.solve_axisym(O.face_metrics(grid), b, pool=pool))
+            if worst is None or e["rel_l2"] > worst["rel_l2"]:
+                worst = dict(e, shape=list(grid.shape), map=grid.map)
+        if worst is not None:
+            errors["batch_worst"] = worst
+    log(f"cpu baseline: exact answers in {time.perf_counter() - t0:.1f} s")
+    return out, errors
 
 
-def batch_form(cps, torch, inputs, n_problems, steps, warmup, smoother=2):
+def error_stats(x, want):
+    """Relative L2 error, and the largest element error over max |want|."""
+    return {"rel_l2": float(np.linalg.norm(x - want) / np.linalg.norm(want)),
+            "max": float(np.abs(x - want).max() / np.abs(want).max())}
+
+
+def batch_form(cps, torch, inputs, n_problems, steps, warmup, smoother, batch_ref):
     """64 uneven-size problems (half spherical, half oblate with flattening
     0.1) solved together by the batched form, against the same problems
     solved one after another by cps_solve with the same options.  smoother 2
@@ -391,6 +517,8 @@ def batch_form(cps, torch, inputs, n_problems, steps, warmup, smoother=2):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     B.close()
+    for p, o in zip(probs, out):
+        batch_ref.append((p.grid, p.rhs(), o.cpu().numpy().reshape(p.grid.shape)))
     its = [i.iterations for i in infos]
     worst = max(i.rel_residual for i in infos)
     log(f"batch: {dt * 1e3:.1f} ms per batch solve, status {st}, iterations {min(its)}..{max(its)}")
@@ -467,11 +595,14 @@ class OutPool:
 OUT_PER_SHAPE = 24
 
 
-def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoother=2):
+def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator_s, smoother=2):
     """Poisson arrivals at `rate`/s for `duration` s submitted in real time
     to the solve service (FP32 V-cycles in FP64 refinement, hierarchies kept
-    resident); then, if asked, the same stream served one request at a time
-    by a plain FP64 cps_setup + cps_solve per request."""
+    resident); then the requests that arrive in the first `comparator_s`
+    seconds of the same stream served one at a time by a plain FP64
+    cps_setup + cps_solve per request (a fixed sample: one at a time the
+    plain solve serves a fifth of the stream's demand, so the whole stream
+    would take minutes)."""
     import threading
     import numpy as np
     arr = inputs.arrival_stream(rate=rate, duration=duration)
@@ -551,11 +682,13 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoot
                            "latency = submission to completion, p50/p99 over this stream")
     log(f"serve: {len(arr)} requests, p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms, "
         f"{cells / wall / 1e6:.1f} M unknowns/s (demand {demand / 1e6:.1f} M)")
-    if comparator:
+    if comparator_s > 0:
         import torch
         lat = []
+        sample = [a for a in arr if a.t < comparator_s]
+        cells = sum(a.problem.grid.cells for a in sample)
         t0 = time.perf_counter()
-        for a in arr:
+        for a in sample:
             d = t0 + a.t - time.perf_counter()
             if d > 0:
                 time.sleep(d)
@@ -573,8 +706,10 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator, smoot
         out["comparator_fp64_per_request"] = {
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "unknowns_per_s": cells / wall_c,
-            "what": "same stream, one request at a time: FP64 cps_setup + cps_solve + "
-                    "cps_destroy per request, host rhs in, host p out"}
+            "requests": len(sample), "sample_s": comparator_s,
+            "what": f"the requests arriving in the first {comparator_s:g} s of the same stream, "
+                    "one at a time: FP64 cps_setup + cps_solve + cps_destroy per request, host "
+                    "rhs in, host p out"}
         log(f"serve comparator: p50 {np.percentile(lat, 50):.1f} ms p99 "
             f"{np.percentile(lat, 99):.1f} ms, {cells / wall_c / 1e6:.1f} M unknowns/s")
     return out
@@ -606,12 +741,15 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=64)
     ap.add_argument("--batch-smoother", type=int, default=2, choices=[0, 2])
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-smoother", type=int, default=2,
                     help="0 point, 1 plane, 2 automatic (plane where the hierarchy allows it)")
-    ap.add_argument("--no-serve-comparator", action="store_true")
+    ap.add_argument("--serve-comparator-seconds", type=float, default=5.0,
+                    help="serve the requests of the first this many seconds of the stream one "
+                         "at a time with plain FP64 solves (0: skip)")
+    ap.add_argument("--no-config1", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {a.gpus}): a grid's solve runs on "
@@ -671,6 +809,7 @@ def main():
         "vcycle_fp64": vcycle_rate(f64["prof"], s64.levels, 8, f64["prof_steps"]),
     }
     x64 = f64["p"]
+    answers = {("fp64",): f64["host_p"]}  # GPU answers, compared with the oracle's exact one
     if not a.no_mixed:
         mx = run_form(cps, torch, g, rhs, 1, a.steps, a.warmup)
         err = float(torch.linalg.norm(mx["p"] - x64) / torch.linalg.norm(x64))
@@ -682,29 +821,41 @@ def main():
                          "rel_diff_vs_fp64": err, "dtype": "f32 V-cycles, f64 outer",
                          "kernels": kernel_table(mx["prof"], mx["prof_steps"]),
                          "vcycle": vcycle_rate(mx["prof"], mx["solver"].levels, 4, mx["prof_steps"])}
+        answers[("mixed",)] = mx["host_p"]
         mx["solver"].close()
         del mx
     s64.close()
     if not a.no_plane:
         torch.cuda.empty_cache()
-        line["plane"] = plane_form(cps, torch, g, rhs, x64, a.steps, a.warmup)
-    gpu_iters = f64["iters"][-1]
+        line["plane"] = plane_form(cps, torch, g, rhs, x64, a.steps, a.warmup, answers)
     del x64, f64, rhs
     torch.cuda.empty_cache()
     if not a.no_project:
         line["project"] = project_form(cps, torch, inputs, g, a.steps, a.warmup)
     if not a.no_lines:
         line["lines"] = lines_form(cps, torch, inputs, g, a.steps, a.warmup)
+    batch_ref = []
     if not a.no_batch:
         line["batch"] = batch_form(cps, torch, inputs, a.batch_problems, a.steps, a.warmup,
-                                   a.batch_smoother)
+                                   a.batch_smoother, batch_ref)
         torch.cuda.empty_cache()
+    if not a.no_config1:
+        line["config1"] = config1_form(cps, torch, inputs, a.steps, a.warmup)
     if not a.no_serve:
         line["serve"] = serve_form(cps, inputs, a.serve_seconds, a.serve_rate, a.serve_slots,
-                                   64, not a.no_serve_comparator, a.serve_smoother)
+                                   64, a.serve_comparator_seconds, a.serve_smoother)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(g, rhs_np, gpu_iters)
+        line["cpu_baseline"], errors = cpu_baseline(g, rhs_np, answers, batch_ref)
+        # each form's error against the oracle's exact solution
+        line["error_vs_oracle"] = errors.pop(("fp64",))
+        if ("mixed",) in errors:
+            line["mixed"]["error_vs_oracle"] = errors.pop(("mixed",))
+        for key in ("fp64", "mixed"):
+            if ("plane", key) in errors:
+                line["plane"][key]["error_vs_oracle"] = errors.pop(("plane", key))
+        if "batch_worst" in errors:
+            line["batch"]["worst_error_vs_oracle"] = errors.pop("batch_worst")
     print(json.dumps(line), flush=True)
 
 

@@ -27,7 +27,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cps_oracle.c")
-_LIB = os.path.join(_HERE, "libcps_oracle.so")
+_LIB_DEFAULT = os.path.join(_HERE, "libcps_oracle.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -35,15 +35,41 @@ MAP_IDENTITY, MAP_SPHERE, MAP_OBLATE, MAP_TRIAXIAL = 0, 1, 2, 3
 METRICS_CENTRAL, METRICS_VERTEX = 0, 1
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+_LIB_NATIVE = os.path.join(_HERE, "libcps_oracle_native.so")
+
+
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path.
+    native: a second build with -O3 -march=native (the same source, tuned
+    for the host it is built on), for timing the oracle as a CPU baseline;
+    it is built where it runs, never shipped."""
+    lib, opt = (_LIB_NATIVE, ["-O3", "-march=native"]) if native else (_LIB_DEFAULT, ["-O2"])
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+            ["gcc", *opt, "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         )
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
+
+
+_native = False
+
+
+def use_native_build() -> None:
+    """Load the -O3 -march=native build (compiled now, on this host) in place
+    of the default one.  Must run before the first oracle call."""
+    global _native
+    with _lock:
+        if _lib is not None:
+            raise RuntimeError("the oracle library is already loaded")
+        build(force=True, native=True)
+        _native = True
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    _load().orc_set_threads(int(n))
 
 
 class _Grid(ctypes.Structure):
@@ -61,12 +87,13 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build(force=False)
-            lib = ctypes.CDLL(_LIB)
+            lib = ctypes.CDLL(build(force=False, native=_native))
             P = ctypes.c_void_p
             I = ctypes.c_int
             D = ctypes.c_double
             lib.orc_max_threads.restype = I
+            lib.orc_set_threads.argtypes = [I]
+            lib.orc_set_threads.restype = None
             lib.orc_map.argtypes = [P, D, D, D, P]
             lib.orc_metric_from_chords.argtypes = [P, P]
             lib.orc_metric_from_chords.restype = D

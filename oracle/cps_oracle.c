@@ -47,6 +47,16 @@ int orc_max_threads(void)
 #endif
 }
 
+/* set the threads of the parallel loops (n >= 1); for timing at one thread */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid and map (Sec. 2, 3.1; the tanh clustering is eq. (stretching))      */
 /* ------------------------------------------------------------------------ */

@@ -143,28 +143,31 @@ def _mode_solve(A2, gpp, rhs: np.ndarray, m: int, np_: int) -> np.ndarray:
     return xr + 1j * xi
 
 
-_pool_state = {}
+def _mode_chunk(task):
+    """Worker body: the modes of one chunk, as (m, x_m) pairs."""
+    A2, gpp, np_, chunk = task
+    return [(m, _mode_solve(A2, gpp, rhs, m, np_)) for m, rhs in chunk]
 
 
-def _pool_init(A2, gpp, np_):
-    _pool_state.update(A2=A2, gpp=gpp, np_=np_)
+def mode_pool(workers: int):
+    """A process pool for solve_axisym (spawned workers: they import numpy and
+    scipy only); the caller closes it (use as a context manager)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    return cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
 
 
-def _pool_mode(task):
-    m, rhs = task
-    s = _pool_state
-    return m, _mode_solve(s["A2"], s["gpp"], rhs, m, s["np_"])
-
-
-def solve_axisym(G: np.ndarray, b: np.ndarray, workers: int = 1, progress=None) -> np.ndarray:
+def solve_axisym(G: np.ndarray, b: np.ndarray, workers: int = 1, progress=None,
+                 pool=None) -> np.ndarray:
     """Exact solve for phi-invariant metrics with G_{r phi} = G_{theta phi} = 0.
 
     On each azimuthal mode m the phi-flux difference G_pp (x_{c+1} - 2 x_c +
     x_{c-1}) becomes -4 sin^2(pi m / n_phi) G_pp x_m, so A splits into
     (A_2d - 4 sin^2(pi m/n_phi) diag(G_pp)) x_m = b_m.  Mode 0 is singular and
     is solved bordered with sum(x_0) = 0.  The modes are independent systems:
-    workers > 1 solves them in that many spawned processes (the same
-    arithmetic per mode).  progress(done, total) is called as modes finish."""
+    with workers > 1 (or a pool from mode_pool) they are solved in chunks in
+    worker processes, the same arithmetic per mode.  progress(done, total)
+    is called as modes finish."""
     if not is_axisymmetric(G):
         raise ValueError("metrics are not axisymmetric")
     nr, nt, np_ = b.shape
@@ -172,21 +175,27 @@ def solve_axisym(G: np.ndarray, b: np.ndarray, workers: int = 1, progress=None) 
     bh = np.fft.rfft(b - b.mean(), axis=2)
     xh = np.zeros_like(bh)
     nm = bh.shape[2]
-    if workers <= 1:
+    if workers <= 1 and pool is None:
         for m in range(nm):
             xh[:, :, m] = _mode_solve(A2, gpp, bh[:, :, m].ravel(), m, np_).reshape(nr, nt)
             if progress:
                 progress(m + 1, nm)
     else:
-        import concurrent.futures as cf
-        import multiprocessing as mp
-        tasks = [(m, np.ascontiguousarray(bh[:, :, m].ravel())) for m in range(nm)]
-        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"),
-                                    initializer=_pool_init, initargs=(A2, gpp, np_)) as ex:
-            for k, (m, xm) in enumerate(ex.map(_pool_mode, tasks, chunksize=4)):
-                xh[:, :, m] = xm.reshape(nr, nt)
+        ex = pool if pool is not None else mode_pool(workers)
+        try:
+            nchunk = 4 * (workers if pool is None else ex._max_workers)
+            modes = [(m, np.ascontiguousarray(bh[:, :, m].ravel())) for m in range(nm)]
+            tasks = [(A2, gpp, np_, modes[k::nchunk]) for k in range(min(nchunk, nm))]
+            done = 0
+            for res in ex.map(_mode_chunk, tasks):
+                for m, xm in res:
+                    xh[:, :, m] = xm.reshape(nr, nt)
+                done += len(res)
                 if progress:
-                    progress(k + 1, nm)
+                    progress(done, nm)
+        finally:
+            if pool is None:
+                ex.shutdown()
     x = np.fft.irfft(xh, n=np_, axis=2)
     return x - x.mean()
 
