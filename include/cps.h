@@ -74,11 +74,38 @@ typedef struct {
  *   MAP_CENTRAL   the inverse Jacobian's columns are chords of the map
  *                 across the face centre (second-order central differences);
  *   PAPER_VERTEX  the paper's item 1: the normal derivative averaged over the
- *                 face's four vertices, tangential ones over its two edges. */
-typedef enum { CPS_METRICS_MAP_CENTRAL = 0, CPS_METRICS_PAPER_VERTEX = 1 } cps_metrics_method;
+ *                 face's four vertices, tangential ones over its two edges;
+ *   USER_FACE     the caller's own face metrics of the finest level (from a
+ *                 grid of its own, formed as in Sec. 3.2 items 1-5, which the
+ *                 paper hands to its pressure solver as the stencil of eq.
+ *                 (PC_term1)-(PC_term3)): face_G, a HOST array
+ *                 [9][n_r][n_theta][n_phi] in C order, entry 3d+q of cell
+ *                 (a, b, c) = G_dq on the cell's low d-face (d, q: 0 r,
+ *                 1 theta, 2 phi); read during cps_setup only.  The low r-
+ *                 and theta-wall faces carry no flux: their entries are
+ *                 ignored (taken as 0); the high walls are implicit.  Every
+ *                 other entry must be finite and every diagonal entry G_dd
+ *                 >= 0, else CPS_E_INVALID.  A coarser level's face is made
+ *                 of four faces of the level below: its metrics are half their
+ *                 sum, entry by entry (four times the area over twice the
+ *                 normal length).  The storage and stencil class follow the
+ *                 data: one value per (r, theta) when every entry agrees with
+ *                 the c = 0 one of its row to 1e-12 of the face's diagonal
+ *                 entry (the c = 0 values then serve the whole ring: a map
+ *                 symmetric about the polar axis, up to the rounding of the
+ *                 caller's trigonometry), 7-point when every cross entry is 0.
+ *                 Such a handle has no map: the projection step and the line
+ *                 solves, which need the map's chords, return CPS_E_INVALID,
+ *                 and the batched form and the service do not take it. */
+typedef enum {
+    CPS_METRICS_MAP_CENTRAL = 0,
+    CPS_METRICS_PAPER_VERTEX = 1,
+    CPS_METRICS_USER_FACE = 2
+} cps_metrics_method;
 
 typedef struct {
-    int32_t method; /* cps_metrics_method */
+    int32_t method;       /* cps_metrics_method */
+    const double* face_G; /* USER_FACE only (see above); NULL otherwise */
 } cps_metrics;
 
 typedef struct {
@@ -138,9 +165,10 @@ typedef struct cps_handle cps_handle;
 void cps_grid_default(cps_grid* g);
 
 /* Build the hierarchy on the current device: level plan, face metrics of
- * every level (computed on the GPU from the map), classification of the
- * operator (7-point when every cross metric vanishes, else 19-point), and
- * the dense inverse of the coarsest operator plus alpha 1 1^T.
+ * every level (computed on the GPU from the map, or coarsened from the
+ * caller's, see cps_metrics), classification of the operator (7-point when
+ * every cross metric vanishes, else 19-point), and the dense inverse of the
+ * coarsest operator plus alpha 1 1^T.
  * grid, metrics, opts: host pointers, read during the call only.
  * *out receives a handle owning all device memory of the hierarchy.
  * Errors: CPS_E_INVALID (dims, non-positive det), CPS_E_OOM, CPS_E_HIP. */

@@ -111,6 +111,9 @@ def _load():
             lib.orc_level_plan.restype = I
             lib.orc_mg_create.argtypes = [P, I, I, I]
             lib.orc_mg_create.restype = P
+            lib.orc_mg_create_user.argtypes = [P, I, I, I, I, I]
+            lib.orc_mg_create_user.restype = P
+            lib.orc_coarsen_metrics.argtypes = [I, I, I, P, P]
             lib.orc_mg_destroy.argtypes = [P]
             lib.orc_mg_levels.argtypes = [P, P, P]
             lib.orc_mg_levels.restype = I
@@ -245,6 +248,16 @@ def restrict(r) -> np.ndarray:
     return bc
 
 
+def coarsen_metrics(G) -> np.ndarray:
+    """Face metrics of the next coarser level from a level's [9][n_r][n_t][n_p]
+    metrics: each coarse face is half the sum of its four child faces."""
+    G = _f64(G)
+    nr, nt, np_ = G.shape[1:]
+    Gc = np.zeros((9, nr // 2, nt // 2, np_ // 2))
+    _load().orc_coarsen_metrics(nr, nt, np_, _p(G), _p(Gc))
+    return Gc
+
+
 def dense_matrix(G) -> np.ndarray:
     G = _f64(G)
     nr, nt, np_ = G.shape[1:]
@@ -265,11 +278,22 @@ def level_plan(nr: int, nt: int, np_: int, n_levels: int = 0):
 class Multigrid:
     """Oracle multigrid hierarchy for one grid (metrics from the map)."""
 
-    def __init__(self, grid, method: int = METRICS_CENTRAL, n_levels: int = 0, ncol: int = 0):
+    def __init__(self, grid, method: int = METRICS_CENTRAL, n_levels: int = 0, ncol: int = 0,
+                 face_G=None):
+        """face_G: caller-given level-0 face metrics [9][n_r][n_t][n_p] (the
+        low-wall faces taken as zero; coarse levels by coarsen_metrics) in
+        place of metrics from the map."""
         self._lib = _load()
         self.grid = as_grid(grid)
         self._g = self.grid.c_struct()
-        self._h = self._lib.orc_mg_create(ctypes.byref(self._g), method, n_levels, ncol)
+        if face_G is None:
+            self._h = self._lib.orc_mg_create(ctypes.byref(self._g), method, n_levels, ncol)
+        else:
+            self._G0 = _f64(face_G)
+            if self._G0.shape != (9,) + self.grid.shape:
+                raise ValueError("face_G must be [9][n_r][n_theta][n_phi]")
+            self._h = self._lib.orc_mg_create_user(_p(self._G0), *self.grid.shape, n_levels,
+                                                   ncol)
         if not self._h:
             raise ValueError("oracle multigrid setup failed")
         dims = np.zeros(48, dtype=np.int32)

@@ -560,9 +560,44 @@ void orc_mg_destroy(og_mg* m)
     free(m);
 }
 
-/* metrics_l0: optional caller-given level-0 metrics (NULL = from the map).
- * Coarse levels always come from the map at their own index spacing. */
-og_mg* orc_mg_create(const og_grid* g, int method, int n_levels, int force_ncol)
+/* Face metrics of a coarse level from those of the fine level below it.
+ * The low d-face of coarse cell (A, B, C) is made of the four fine low
+ * d-faces at index 2A (d = r), 2B (d = theta) or 2C (d = phi) along d and
+ * the two fine indices of each other direction.  A face metric is an area
+ * over a normal length (G_dd = |J^-1| |grad s_d|^2 = area^2 / volume per
+ * unit index spacing): the coarse face has four times the area and twice
+ * the normal length, so G_H = 2 G_h = (1/2) of the sum over the four
+ * children, entry by entry (the cross entries scale the same way).  Exact
+ * for a uniform box; second order otherwise.  Wall faces stay zero. */
+void orc_coarsen_metrics(int nr, int nt, int np, const double* Gf, double* Gc)
+{
+    og_dims f = {nr, nt, np}, c = {nr / 2, nt / 2, np / 2};
+    size_t nf = og_n(f), ncell = og_n(c);
+#pragma omp parallel for
+    for (long long i = 0; i < (long long)ncell; ++i) {
+        int C = (int)(i % c.np), B = (int)((i / c.np) % c.nt), A = (int)(i / ((size_t)c.np * c.nt));
+        for (int d = 0; d < 3; ++d)
+            for (int q = 0; q < 3; ++q) {
+                const double* g = Gf + (size_t)(3 * d + q) * nf;
+                double s = 0.0;
+                for (int u = 0; u < 2; ++u)
+                    for (int v = 0; v < 2; ++v) {
+                        int a = 2 * A, b = 2 * B, cc = 2 * C;
+                        if (d == 0) { b += u; cc += v; }
+                        else if (d == 1) { a += u; cc += v; }
+                        else { a += u; b += v; }
+                        s += g[og_idx(f, a, b, cc)];
+                    }
+                Gc[(size_t)(3 * d + q) * ncell + i] = 0.5 * s;
+            }
+    }
+}
+
+/* Shared part of the set-ups: level plan and buffers, every level's metrics
+ * through `fill`, the colouring and the coarsest operator's LU.  fill
+ * returns nonzero on failure. */
+static og_mg* og_mg_build(const og_grid* g, int n_levels, int force_ncol,
+                          int (*fill)(og_mg* m, int l, const void* ctx), const void* ctx)
 {
     int dims[3 * OG_MAXL];
     int L = orc_level_plan(g->n_r, g->n_theta, g->n_phi, n_levels, dims);
@@ -581,7 +616,7 @@ og_mg* orc_mg_create(const og_grid* g, int method, int n_levels, int force_ncol)
         m->x[l] = calloc(n, sizeof(double));
         m->b[l] = calloc(n, sizeof(double));
         m->r[l] = calloc(n, sizeof(double));
-        if (orc_face_metrics(g, d.nr, d.nt, d.np, method, m->G[l]) != 0) {
+        if (fill(m, l, ctx) != 0) {
             orc_mg_destroy(m);
             return NULL;
         }
@@ -608,6 +643,54 @@ og_mg* orc_mg_create(const og_grid* g, int method, int n_levels, int force_ncol)
         return NULL;
     }
     return m;
+}
+
+typedef struct { int method; } og_map_ctx;
+
+static int og_fill_map(og_mg* m, int l, const void* ctx)
+{
+    const og_map_ctx* c = ctx;
+    return orc_face_metrics(&m->g, m->d[l].nr, m->d[l].nt, m->d[l].np, c->method, m->G[l]);
+}
+
+/* Every level's metrics from the map at its own index spacing. */
+og_mg* orc_mg_create(const og_grid* g, int method, int n_levels, int force_ncol)
+{
+    og_map_ctx c = {method};
+    return og_mg_build(g, n_levels, force_ncol, og_fill_map, &c);
+}
+
+/* Level 0 from caller-given face metrics G0 [9][nr][nt][np] (the low r- and
+ * theta-wall faces carry no flux: their entries are taken as zero), coarse
+ * levels by orc_coarsen_metrics.  orc_mg_create_user returns NULL when an
+ * entry is not finite or a diagonal entry is negative. */
+static int og_fill_user(og_mg* m, int l, const void* ctx)
+{
+    og_dims d = m->d[l];
+    size_t n = og_n(d);
+    if (l > 0) {
+        og_dims f = m->d[l - 1];
+        orc_coarsen_metrics(f.nr, f.nt, f.np, m->G[l - 1], m->G[l]);
+        return 0;
+    }
+    const double* G0 = ctx;
+    for (int k = 0; k < 9; ++k)
+        for (size_t i = 0; i < n; ++i) {
+            double v = G0[(size_t)k * n + i];
+            int b = (int)((i / d.np) % d.nt), a = (int)(i / ((size_t)d.np * d.nt));
+            if ((k < 3 && a == 0) || (k >= 3 && k < 6 && b == 0)) v = 0.0; /* wall face */
+            if (!isfinite(v) || ((k == 0 || k == 4 || k == 8) && v < 0.0)) return 1;
+            m->G[0][(size_t)k * n + i] = v;
+        }
+    return 0;
+}
+
+og_mg* orc_mg_create_user(const double* G0, int nr, int nt, int np, int n_levels, int force_ncol)
+{
+    og_grid g;
+    memset(&g, 0, sizeof g);
+    g.n_r = nr; g.n_theta = nt; g.n_phi = np;
+    return og_mg_build(&g, n_levels, force_ncol, og_fill_user, G0);
 }
 
 int orc_mg_levels(const og_mg* m, int* dims_out, int* ncol)

@@ -20,7 +20,7 @@ CPS_OK, CPS_E_INVALID, CPS_E_OOM, CPS_E_HIP, CPS_E_NOT_CONVERGED, CPS_E_DIVERGED
 STATUS_NAMES = {0: "CPS_OK", -1: "CPS_E_INVALID", -2: "CPS_E_OOM", -3: "CPS_E_HIP",
                 -4: "CPS_E_NOT_CONVERGED", -5: "CPS_E_DIVERGED"}
 MAP_IDENTITY, MAP_SPHERE, MAP_OBLATE, MAP_TRIAXIAL = 0, 1, 2, 3
-METRICS_MAP_CENTRAL, METRICS_PAPER_VERTEX = 0, 1
+METRICS_MAP_CENTRAL, METRICS_PAPER_VERTEX, METRICS_USER_FACE = 0, 1, 2
 
 
 class cps_grid(ctypes.Structure):
@@ -35,7 +35,7 @@ class cps_grid(ctypes.Structure):
 
 
 class cps_metrics(ctypes.Structure):
-    _fields_ = [("method", ctypes.c_int32)]
+    _fields_ = [("method", ctypes.c_int32), ("face_G", ctypes.c_void_p)]
 
 
 class cps_opts(ctypes.Structure):
@@ -370,14 +370,24 @@ class Solver:
 
     def __init__(self, grid, precision: int = 0, accel: int = 1, max_iters: int = 200,
                  metrics: int = METRICS_MAP_CENTRAL, n_levels: int = 0, stream=None,
-                 tune: int = 0, eager: bool = False, smoother: int = 0):
+                 tune: int = 0, eager: bool = False, smoother: int = 0, face_G=None):
+        """face_G: the caller's own finest-level face metrics, a host float64
+        array of shape (9, n_r, n_theta, n_phi) (metrics = METRICS_USER_FACE);
+        read during set-up only."""
+        import numpy as np
         import torch
         self.shape = (grid.n_r, grid.n_theta, grid.n_phi)
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
         opts = cps_opts(precision, max_iters, accel, tune, 1 if eager else 0, smoother,
                         ctypes.c_void_p(s.cuda_stream))
-        self.h = cps_setup(make_grid(grid, n_levels), cps_metrics(metrics), opts)
+        met = cps_metrics(metrics)
+        if face_G is not None:
+            fg = np.ascontiguousarray(face_G, dtype=np.float64)
+            if fg.shape != (9,) + self.shape:
+                raise ValueError(f"face_G must have shape {(9,) + self.shape}")
+            met = cps_metrics(METRICS_USER_FACE, fg.ctypes.data_as(ctypes.c_void_p))
+        self.h = cps_setup(make_grid(grid, n_levels), met, opts)
         self.levels, self.ncolours, self.phi_invariant = cps_levels(self.h)
 
     def _enter(self, *tensors):

@@ -658,6 +658,8 @@ cps_status cps_batch_setup(int32_t n, const cps_grid* grids, const cps_metrics* 
                                 "(precision = 1)");
         if (opts && (opts->smoother < 0 || opts->smoother > 2))
             fail(CPS_E_INVALID, "bad smoother");
+        if (metrics && metrics->method == CPS_METRICS_USER_FACE)
+            fail(CPS_E_INVALID, "the batched form forms its metrics from each problem's map");
         B = new cps_batch();
         batch_build(B, n, grids, metrics, opts);
     });

@@ -797,8 +797,11 @@ void validate(const cps_grid* g, const cps_metrics* m, const cps_opts* o)
         fail(CPS_E_INVALID, "theta0 and theta1 must lie in [0, pi]");
     if (g->radial_stretch < 0) fail(CPS_E_INVALID, "radial_stretch must be >= 0");
     if (g->n_levels < 0 || g->n_levels > kMaxLevels) fail(CPS_E_INVALID, "bad n_levels");
-    if (m && m->method != CPS_METRICS_MAP_CENTRAL && m->method != CPS_METRICS_PAPER_VERTEX)
+    if (m && m->method != CPS_METRICS_MAP_CENTRAL && m->method != CPS_METRICS_PAPER_VERTEX &&
+        m->method != CPS_METRICS_USER_FACE)
         fail(CPS_E_INVALID, "bad metrics method");
+    if (m && m->method == CPS_METRICS_USER_FACE && !m->face_G)
+        fail(CPS_E_INVALID, "caller-supplied metrics need face_G");
     validate_opts(o);
 }
 
@@ -836,30 +839,91 @@ void plane_factors(cps_handle* h)
     }
 }
 
-int compute_operator(cps_handle* h)
+// OR of the per-block flags a metrics kernel left in `dflags`.
+int gather_flags(cps_handle* h, const Buf<int>& dflags, long long blocks)
+{
+    std::vector<int> hflags(blocks);
+    HIPC(hipMemcpyAsync(hflags.data(), dflags.p, hflags.size() * sizeof(int),
+                        hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    int all = 0;
+    for (int f : hflags) all |= f;
+    return all;
+}
+
+// Caller-supplied metrics (CPS_METRICS_USER_FACE): the finest level's array
+// goes to the device in natural layout, where its wall faces are zeroed and
+// it is checked and classified (k_user_metrics flags).  The natural array
+// stays in `unat` for compute_operator.  Sets h->axi; returns the flags.
+int upload_user_metrics(cps_handle* h, Buf<double>& unat)
+{
+    const long long n = (long long)h->grid.n_r * h->grid.n_theta * h->grid.n_phi;
+    unat.alloc(9 * n);
+    upload(unat.p, h->met.face_G, 9 * n * sizeof(double));
+    Buf<int> dflags;
+    dflags.alloc(nblk(n) + 1);
+    k_user_metrics<<<nblk(n), kBlock, 0, h->stream>>>(h->grid.n_r, h->grid.n_theta,
+                                                      h->grid.n_phi, unat.p, dflags.p);
+    LAUNCH_CHECK();
+    const int flags = gather_flags(h, dflags, nblk(n));
+    if (flags & 1)
+        fail(CPS_E_INVALID, "face_G holds a non-finite entry or a negative diagonal entry");
+    h->axi = !(flags & 8);
+    return flags;
+}
+
+// Every level's storage from the natural finest-level array: level 0 as
+// given, each coarser one by k_coarsen_metrics from the level below.
+void store_user_metrics(cps_handle* h, Buf<double>& unat)
+{
+    Buf<double> fine, coarse;
+    for (int l = 0; l < h->L; ++l) {
+        LevelMem& m = h->lv[l];
+        if (!m.G64.p) m.G64.alloc(9 * m.gk);
+        const double* U = unat.p;
+        if (l > 0) {
+            const LevelMem& f = h->lv[l - 1];
+            coarse.alloc(9 * m.n);
+            k_coarsen_metrics<<<nblk(m.n), kBlock, 0, h->stream>>>(f.nr, f.nt, f.np,
+                                                                   l == 1 ? unat.p : fine.p,
+                                                                   coarse.p);
+            LAUNCH_CHECK();
+            HIPC(hipStreamSynchronize(h->stream)); // before `fine` is freed below
+            std::swap(fine.p, coarse.p);
+            std::swap(fine.n, coarse.n);
+            coarse.release();
+            U = fine.p;
+        }
+        k_store_metrics<<<nblk(m.gk), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np, m.nc, U,
+                                                              m.G64.p);
+        LAUNCH_CHECK();
+    }
+    HIPC(hipStreamSynchronize(h->stream));
+}
+
+int compute_operator(cps_handle* h, Buf<double>* unat = nullptr, int user_flags = 0)
 {
     const cps_grid& g = h->grid;
     MapParams mp{g.map, g.r_inner, g.r_outer, g.theta0, g.theta1, g.radial_stretch, g.flattening,
                  g.skew};
     int flags_all = 0;
-    std::vector<int> hflags;
-    Buf<int> dflags;
-    long long maxn = 0;
-    for (int l = 0; l < h->L; ++l) maxn = std::max(maxn, h->lv[l].gk);
-    dflags.alloc(nblk(maxn) + 1);
-    for (int l = 0; l < h->L; ++l) {
-        LevelMem& m = h->lv[l];
-        if (!m.G64.p) m.G64.alloc(9 * m.gk);
-        k_metrics<<<nblk(m.gk), kBlock, 0, h->stream>>>(mp, m.nr, m.nt, m.np, m.nc,
-                                                         h->met.method, m.G64.p, dflags.p);
-        LAUNCH_CHECK();
-        hflags.resize(nblk(m.gk));
-        HIPC(hipMemcpyAsync(hflags.data(), dflags.p, hflags.size() * sizeof(int),
-                            hipMemcpyDeviceToHost, h->stream));
-        HIPC(hipStreamSynchronize(h->stream));
-        for (int f : hflags) flags_all |= f;
+    if (unat) {
+        store_user_metrics(h, *unat);
+        flags_all = user_flags & 6;
+    } else {
+        Buf<int> dflags;
+        long long maxn = 0;
+        for (int l = 0; l < h->L; ++l) maxn = std::max(maxn, h->lv[l].gk);
+        dflags.alloc(nblk(maxn) + 1);
+        for (int l = 0; l < h->L; ++l) {
+            LevelMem& m = h->lv[l];
+            if (!m.G64.p) m.G64.alloc(9 * m.gk);
+            k_metrics<<<nblk(m.gk), kBlock, 0, h->stream>>>(mp, m.nr, m.nt, m.np, m.nc,
+                                                             h->met.method, m.G64.p, dflags.p);
+            LAUNCH_CHECK();
+            flags_all |= gather_flags(h, dflags, nblk(m.gk));
+        }
     }
-    dflags.release();
     if (flags_all & 1) fail(CPS_E_INVALID, "a face of the map has det <= 0");
     const int mode = (flags_all & 4) ? MODE_FULL : ((flags_all & 2) ? MODE_RT : MODE_ORTHO);
     if (h->Ainv.p && mode != h->mode)
@@ -1035,7 +1099,14 @@ void build(cps_handle* h)
 {
     int dims[kMaxLevels][3];
     h->L = checked_plan(h->grid, dims);
-    h->axi = h->grid.map != CPS_MAP_TRIAXIAL;
+    Buf<double> unat; // caller-supplied metrics, natural layout (set-up only)
+    int uflags = 0;
+    if (h->met.method == CPS_METRICS_USER_FACE) {
+        uflags = upload_user_metrics(h, unat);
+        h->met.face_G = nullptr; // the caller's array is not retained
+    } else {
+        h->axi = h->grid.map != CPS_MAP_TRIAXIAL;
+    }
     for (int l = 0; l < h->L; ++l) {
         LevelMem& m = h->lv[l];
         m.nr = dims[l][0];
@@ -1047,7 +1118,8 @@ void build(cps_handle* h)
         m.geo = make_geo(m.nr, m.nt, m.np);
     }
     h->nc = (int)h->lv[h->L - 1].n;
-    compute_operator(h);
+    compute_operator(h, unat.p ? &unat : nullptr, uflags);
+    unat.release();
     // per-level vectors
     const bool mixed = h->opts.precision == 1;
     for (int l = 0; l < h->L; ++l) {
@@ -1452,8 +1524,17 @@ int csym(const cps_handle* h)
     return h->grid.map == CPS_MAP_IDENTITY ? kInvariant : kRotational;
 }
 
+// The projection step and the line solves form C rows from the map's chords.
+void need_map(const cps_handle* h)
+{
+    if (h->met.method == CPS_METRICS_USER_FACE)
+        fail(CPS_E_INVALID, "the projection step and the line solves need the map's chords; this "
+                            "handle was set up with caller-supplied face metrics");
+}
+
 void ensure_cmetrics(cps_handle* h)
 {
+    need_map(h);
     if (h->cm_valid) return;
     const LevelMem& m = h->lv[0];
     const int nc = csym(h) == kPerCell ? m.np : 1;
@@ -1600,6 +1681,7 @@ void line_solve_noalloc(cps_handle* h, int dir, double coef, const LineBC& bc,
                         const double* rhs, double* psi)
 {
     const LevelMem& m = h->lv[0];
+    need_map(h);
     if (csym(h) == kPerCell)
         fail(CPS_E_INVALID, "line solves need phi-invariant metrics (box, sphere, oblate)");
     auto even = [](long long w) { return (w + 1) & ~1LL; }; // 16-byte aligned parts

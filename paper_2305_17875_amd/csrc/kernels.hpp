@@ -2487,6 +2487,97 @@ __global__ void __launch_bounds__(kBlock) k_metrics(MapParams m, int nr, int nt,
     if (threadIdx.x == 0) flags[blockIdx.x] = sflag;
 }
 
+// Caller-supplied face metrics of the finest level, natural layout
+// [9][nr][nt][np] (entry 3d+q: G_dq on the cell's low d-face), checked and
+// classified in place: the low r- and theta-wall faces carry no flux (their
+// entries are set to 0); flags bit 1: an entry is not finite or a diagonal
+// entry is negative; 2: r-theta cross entries; 4: cross entries with phi;
+// 8: some entry differs from the one at c = 0 of its (r, theta) row by more
+// than 1e-12 of the face's diagonal entry (the metrics are not
+// phi-invariant; within that, the c = 0 values serve the whole ring, as
+// rounding in the caller's own trigonometry leaves ~1e-14 differences on a
+// map symmetric about the polar axis).  Per-block flags as k_metrics.
+__global__ void __launch_bounds__(kBlock) k_user_metrics(int nr, int nt, int np,
+                                                         double* __restrict__ U,
+                                                         int* __restrict__ flags)
+{
+    __shared__ int sflag;
+    if (threadIdx.x == 0) sflag = 0;
+    __syncthreads();
+    const long long n = (long long)nr * nt * np;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int fl = 0;
+    if (i < n) {
+        const int c = (int)(i % np);
+        const long long row = i / np;
+        const int b = (int)(row % nt), a = (int)(row / nt);
+        for (int k = 0; k < 9; ++k) {
+            const int d = k / 3, q = k % 3;
+            if ((d == 0 && a == 0) || (d == 1 && b == 0)) { // wall face: no flux
+                U[k * n + i] = 0.0;
+                continue;
+            }
+            const double v = U[k * n + i];
+            if (!isfinite(v) || (d == q && v < 0.0)) fl |= 1;
+            if (d != q && v != 0.0) fl |= (d == 2 || q == 2) ? 4 : 2;
+            if (c > 0) {
+                const long long dd = (long long)(4 * d) * n;
+                const double tol = 1e-12 * fmax(fabs(U[dd + i]), fabs(U[dd + row * np]));
+                if (!(fabs(v - U[k * n + row * np]) <= tol)) fl |= 8;
+            }
+        }
+    }
+    if (fl) atomicOr(&sflag, fl);
+    __syncthreads();
+    if (threadIdx.x == 0) flags[blockIdx.x] = sflag;
+}
+
+// Natural-layout metrics [9][nr][nt][np] into a level's storage: one entry
+// per (r, theta) when phi-invariant (nc == 1: the c = 0 entry), else the
+// parity-split layout of the level's fields (as k_metrics writes them).
+__global__ void __launch_bounds__(kBlock) k_store_metrics(int nr, int nt, int np, int nc,
+                                                          const double* __restrict__ U,
+                                                          double* __restrict__ G)
+{
+    const long long n = (long long)nr * nt * np, gk = (long long)nr * nt * nc;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= gk) return;
+    const int c = (int)(i % nc);
+    const long long row = i / nc;
+    const long long oi = nc == 1 ? i : (long long)(c & 1) * (gk / 2) + row * (np / 2) + (c >> 1);
+    for (int k = 0; k < 9; ++k) G[k * gk + oi] = U[k * n + row * np + c];
+}
+
+// Face metrics of the next coarser level, natural layout: the low d-face of
+// coarse cell (A, B, C) is made of the four fine low d-faces at index 2A,
+// 2B or 2C along d and the two fine indices of each other direction; a
+// face metric is an area over a normal length, so the coarse face (four
+// times the area, twice the length) takes half the sum of the four.
+__global__ void __launch_bounds__(kBlock) k_coarsen_metrics(int nr, int nt, int np,
+                                                            const double* __restrict__ Uf,
+                                                            double* __restrict__ Uc)
+{
+    const int cr = nr / 2, ct = nt / 2, cp = np / 2;
+    const long long nf = (long long)nr * nt * np, ncl = (long long)cr * ct * cp;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncl) return;
+    const int C = (int)(i % cp);
+    const long long row = i / cp;
+    const int B = (int)(row % ct), A = (int)(row / ct);
+    for (int k = 0; k < 9; ++k) {
+        const int d = k / 3;
+        double s = 0.0;
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) {
+                const int a = 2 * A + (d == 0 ? 0 : u);
+                const int b = 2 * B + (d == 1 ? 0 : (d == 0 ? u : v));
+                const int c = 2 * C + (d == 2 ? 0 : v);
+                s += Uf[k * nf + ((long long)a * nt + b) * np + c];
+            }
+        Uc[k * ncl + i] = 0.5 * s;
+    }
+}
+
 // Float copy of an FP64 array.
 __global__ void __launch_bounds__(kBlock) k_to_f32(long long n, const double* __restrict__ a,
                                                    float* __restrict__ b)

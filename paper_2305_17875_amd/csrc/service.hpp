@@ -425,6 +425,9 @@ cps_status cps_service_submit(cps_service* S, const cps_grid* grid, const cps_me
         if (!S || !grid || !rhs_host || !p_host || !ticket) fail(CPS_E_INVALID, "NULL argument");
         if (!(tol > 0)) fail(CPS_E_INVALID, "tol must be positive");
         validate(grid, metrics, &S->opts);
+        if (metrics && metrics->method == CPS_METRICS_USER_FACE)
+            fail(CPS_E_INVALID, "the service forms each request's metrics from its map (pooled "
+                                "hierarchies are matched by the map)");
         int dims[kMaxLevels][3];
         (void)checked_plan(*grid, dims);
         auto R = std::make_unique<SvcReq>();

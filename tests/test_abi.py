@@ -49,6 +49,7 @@ def test_ctypes_layout_matches_c(tmp_path):
         'printf("%zu %zu %zu\\n", offsetof(cps_grid, r_inner), offsetof(cps_grid, skew), offsetof(cps_grid, n_levels));\n'
         'printf("%zu %zu\\n", offsetof(cps_opts, stream), offsetof(cps_info, seconds));\n'
         'printf("%zu %zu\\n", sizeof(cps_line_bc), offsetof(cps_line_bc, value_hi));\n'
+        'printf("%zu\\n", offsetof(cps_metrics, face_G));\n'
         "return 0;}\n")
     exe = tmp_path / "probe"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe),
@@ -59,7 +60,8 @@ def test_ctypes_layout_matches_c(tmp_path):
     assert vals[4:7] == [cps.cps_grid.r_inner.offset, cps.cps_grid.skew.offset,
                          cps.cps_grid.n_levels.offset]
     assert vals[7:9] == [cps.cps_opts.stream.offset, cps.cps_info.seconds.offset]
-    assert vals[9:] == [ctypes.sizeof(cps.cps_line_bc), cps.cps_line_bc.value_hi.offset]
+    assert vals[9:11] == [ctypes.sizeof(cps.cps_line_bc), cps.cps_line_bc.value_hi.offset]
+    assert vals[11:] == [cps.cps_metrics.face_G.offset]
 
 
 def test_grid_default_and_invalid_setup_without_gpu():
