@@ -1500,12 +1500,132 @@ __device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch
     }
 }
 
+// The restriction with the theta rows shared through LDS, for coarse levels
+// whose rows are whole wavefronts (n_phi / 2 of the coarse level a multiple
+// of 64) and whose theta count is a multiple of 4.  A block is 4 coarse rows
+// x one 64-wide phi segment (the 256 positions of a block of d_restrict,
+// regrouped): wavefront w owns coarse row J = 4G + w and loads only its own
+// fine rows 2J and 2J + 1.  Each forms the phi restriction of those rows
+// (weights 1, 3, 3, 1 over fine phi 4jc - 1 .. 4jc + 4, the outer two from
+// the adjacent lanes) and hands it to the neighbouring wavefronts through
+// LDS: row 2J - 1 is wavefront w - 1's second row, 2J + 2 wavefront w + 1's
+// first; the block's first and last wavefronts form their outer row
+// themselves (mirrored at the theta walls).  Half the loads of d_restrict,
+// the same sums in the same order.  LDS double-buffered by fine plane: one
+// barrier per plane.
+template <typename T>
+struct RestrictLds {
+    Vec2<T> v[2][4][2][64];
+};
+
+__host__ __device__ inline bool restrict_rows(const Geo& c)
+{
+    return c.nh % 64 == 0 && c.nt % 4 == 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void d_restrict2(Blk bk, Geo f, Geo c, int bpa, int ch,
+                                            const T* __restrict__ r, T* __restrict__ bc,
+                                            RestrictLds<T>& sh)
+{
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const int segs = c.nh >> 6;
+    const int L = (int)bk.L;
+    const int chunk = L / bpa, lb = L - chunk * bpa;
+    const int G = lb / segs, seg = lb - G * segs;
+    const int J = 4 * G + w, jc = seg * 64 + lane;
+    const int I0 = chunk * ch, I1 = min(c.nr, I0 + ch);
+    if (I0 >= c.nr) return; // whole block: no barrier is skipped by part of it
+    const T w0 = T(0.25), w1 = T(0.75);
+    const T wq[4] = {w0, w1, w1, w0};
+    const long long cv = 2 * jc;
+    const long long cm = f.P + (jc == 0 ? f.nh - 1 : cv - 1);
+    const long long cp = jc == c.nh - 1 ? 0 : cv + 2;
+    const bool lo_lane = lane > 0 && jc > 0;
+    const bool hi_lane = lane < 63 && jc < c.nh - 1;
+    // phi restriction of fine row `row` of the plane at ra, for K = 2jc (q0)
+    // and 2jc + 1 (q1)
+    auto phi = [&](const T* ra, int row, T& q0, T& q1) {
+        const T* rr = ra + (long long)row * f.nh;
+        const Vec2<T> e = *reinterpret_cast<const Vec2<T>*>(rr + cv);
+        const Vec2<T> o = *reinterpret_cast<const Vec2<T>*>(rr + f.P + cv);
+        T v0 = __shfl(o.y, lane - 1);
+        T v5 = __shfl(e.x, lane + 1);
+        if (!lo_lane) v0 = rr[cm];
+        if (!hi_lane) v5 = rr[cp];
+        const T v1 = e.x, v2 = o.x, v3 = e.y, v4 = o.y;
+        q0 = w0 * v0 + w1 * v1 + w1 * v2 + w0 * v3;
+        q1 = w0 * v2 + w1 * v3 + w1 * v4 + w0 * v5;
+    };
+    int buf = 0;
+    // theta-phi restriction of fine plane a
+    auto plane = [&](int a, T& s0, T& s1) {
+        const T* ra = r + (long long)clampi(a, f.nr - 1) * f.rowlen;
+        T p0[4], p1[4]; // fine rows 2J - 1 .. 2J + 2
+        phi(ra, 2 * J, p0[1], p1[1]);
+        phi(ra, 2 * J + 1, p0[2], p1[2]);
+        if (w == 0) phi(ra, clampi(2 * J - 1, f.nt - 1), p0[0], p1[0]);
+        if (w == 3) phi(ra, clampi(2 * J + 2, f.nt - 1), p0[3], p1[3]);
+        Vec2<T> own0, own1;
+        own0.x = p0[1];
+        own0.y = p1[1];
+        own1.x = p0[2];
+        own1.y = p1[2];
+        sh.v[buf][w][0][lane] = own0;
+        sh.v[buf][w][1][lane] = own1;
+        __syncthreads();
+        if (w > 0) {
+            const Vec2<T> v = sh.v[buf][w - 1][1][lane];
+            p0[0] = v.x;
+            p1[0] = v.y;
+        }
+        if (w < 3) {
+            const Vec2<T> v = sh.v[buf][w + 1][0][lane];
+            p0[3] = v.x;
+            p1[3] = v.y;
+        }
+        buf ^= 1;
+        s0 = T(0);
+        s1 = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            s0 += wq[q] * p0[q];
+            s1 += wq[q] * p1[q];
+        }
+    };
+    T pa0, pa1, pb0, pb1;
+    plane(2 * I0 - 1, pa0, pa1);
+    plane(2 * I0, pb0, pb1);
+    const int m = J * c.nh + jc;
+    for (int I = I0; I < I1; ++I) {
+        T qa0, qa1, qb0, qb1;
+        plane(2 * I + 1, qa0, qa1);
+        plane(2 * I + 2, qb0, qb1);
+        const long long o = (long long)I * c.rowlen + m;
+        bc[o] = w0 * pa0 + w1 * pb0 + w1 * qa0 + w0 * qb0;
+        bc[c.P + o] = w0 * pa1 + w1 * pb1 + w1 * qa1 + w0 * qb1;
+        pa0 = qa0; pa1 = qa1; pb0 = qb0; pb1 = qb1;
+    }
+}
+
+// Either restriction, chosen by the coarse level's shape (the same choice in
+// the single and the batched form; both take march_shape(c)'s blocks).
+template <typename T>
+__device__ __forceinline__ void d_restrict_any(Blk bk, Geo f, Geo c, int bpa, int ch,
+                                               const T* __restrict__ r, T* __restrict__ bc,
+                                               RestrictLds<T>& sh)
+{
+    if (restrict_rows(c)) d_restrict2<T>(bk, f, c, bpa, ch, r, bc, sh);
+    else d_restrict<T>(bk, f, c, bpa, ch, r, bc);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa, int ch,
                                                      const T* __restrict__ r,
                                                      T* __restrict__ bc)
 {
-    d_restrict<T>(self_blk(), f, c, bpa, ch, r, bc);
+    __shared__ RestrictLds<T> sh;
+    d_restrict_any<T>(self_blk(), f, c, bpa, ch, r, bc, sh);
 }
 
 // x += P e (trilinear); the thread writes fine rows 2J, 2J+1 and fine phi
@@ -2151,10 +2271,11 @@ __global__ void __launch_bounds__(kBlock) kb_restrict(const BItem* __restrict__ 
                                                       const PDesc<T>* __restrict__ pd, int level)
 {
     CPS_BATCH_BLOCK
+    __shared__ RestrictLds<T> sh;
     const PDesc<T>& P = pd[it.prob];
     const MarchShape ms = march_shape(P.lv[level + 1].g);
-    d_restrict<T>(bk, P.lv[level].g, P.lv[level + 1].g, ms.bpa, ms.ch, P.lv[level].r,
-                  P.lv[level + 1].b);
+    d_restrict_any<T>(bk, P.lv[level].g, P.lv[level + 1].g, ms.bpa, ms.ch, P.lv[level].r,
+                      P.lv[level + 1].b, sh);
 }
 
 template <typename T>

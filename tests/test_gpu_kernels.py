@@ -36,6 +36,10 @@ CASES = [
     # coarse rings of 128 phi pairs: two wavefronts per coarse row, so the
     # restriction's outer phi values cross a wavefront boundary inside a ring
     ("sphere-wide-8x8x512", Shell(8, 8, 512), 0),
+    # coarse rows of 64 phi pairs in groups of four: the restriction shares
+    # its theta rows between the wavefronts of a block through LDS (two row
+    # groups, mirrored rows at both theta walls)
+    ("sphere-rows-6x16x256", Shell(6, 16, 256, radial_stretch=2.0), 0),
     # full spheres (theta from 0 to pi): the polar rows' r-faces carry an
     # r-theta cross metric on the oblate shell and with vertex metrics
     ("oblate-fullsphere-16x12x20",
