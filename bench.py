@@ -756,6 +756,11 @@ def main():
               "a single device; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # the autotuner's choices (the batched form tunes its shapes) land here
+    import tempfile
+    tune_cache = os.path.join(tempfile.mkdtemp(prefix="cps_tune_"), "tune.json")
+    os.environ["CPS_TUNE_CACHE"] = tune_cache
+
     import torch
     from paper_2305_17875_amd import cps, inputs
 
@@ -838,6 +843,11 @@ def main():
     if not a.no_batch:
         line["batch"] = batch_form(cps, torch, inputs, a.batch_problems, a.steps, a.warmup,
                                    a.batch_smoother, batch_ref)
+        try:  # "plane/f32/<stencil>/<dims>": 100 x rings per block + r-steps in flight
+            line["batch"]["tuned_shapes"] = {k: v for k, v in json.load(open(tune_cache)).items()
+                                             if k.startswith("plane/f32/")}
+        except (OSError, ValueError):
+            line["batch"]["tuned_shapes"] = None
         torch.cuda.empty_cache()
     if not a.no_config1:
         line["config1"] = config1_form(cps, torch, inputs, a.steps, a.warmup)

@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(kBlock) kb_plane_fwd(const BItem* __restrict__
     __shared__ Vec2<float> buf[kPlaneLds], twS[kPlaneLds / 2];
     const LDesc<float>& d = pd[it.prob].lv[level];
     d_plane_fwd<float, kSmallRing, CROSS>(bk.L, buf, twS, d.g, d.G, d.gk, d.b, d.x, parity,
-                                          d.ptw, d.ptwN, d.pS);
+                                          d.ptw, d.ptwN, d.pS, d.prb);
 }
 
 template <bool CROSS>
@@ -44,6 +44,9 @@ __global__ void __launch_bounds__(kBlock) kb_plane_tri(const BItem* __restrict__
 {
     CPS_BATCH_BLOCK
     const LDesc<float>& d = pd[it.prob].lv[level];
+    // the default r-steps in flight: one depth per launch keeps the
+    // kernel's registers those of that depth (the depth schedules the same
+    // arithmetic, so the bits equal the single solve's with its tuned one)
     d_plane_tri<float, CROSS>((long long)bk.L * blockDim.x + threadIdx.x, d.g, d.G, d.gk,
                               parity, d.ppiv + plane_pivot_offset(d.g, parity),
                               reinterpret_cast<float*>(d.pS));
@@ -57,7 +60,8 @@ __global__ void __launch_bounds__(kBlock) kb_plane_inv(const BItem* __restrict__
     CPS_BATCH_BLOCK
     __shared__ Vec2<float> buf[kPlaneLds], twS[kPlaneLds / 2];
     const LDesc<float>& d = pd[it.prob].lv[level];
-    d_plane_inv<float, kSmallRing>(bk.L, buf, twS, d.g, parity, d.ptw, d.ptwN, d.pS, d.x);
+    d_plane_inv<float, kSmallRing>(bk.L, buf, twS, d.g, parity, d.ptw, d.ptwN, d.pS, d.x,
+                                   d.prb);
 }
 
 } // namespace cps
@@ -307,6 +311,7 @@ PDesc<float> make_desc(cps_handle* h)
             d.lv[l].plam = m.lam32.p;
             d.lv[l].ppiv = m.pv32.p;
             d.lv[l].pS = reinterpret_cast<Vec2<float>*>(h->ps32.p);
+            d.lv[l].prb = m.plane_rb;
         }
     }
     return d;
@@ -344,7 +349,7 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
                     cps_handle* h = B->h[p];
                     if (l + 1 >= h->L) continue;
                     const Geo& g = h->lv[l].geo;
-                    const PlaneLaunch pl = plane_launch(g, k);
+                    const PlaneLaunch pl = plane_launch(g, k, h->lv[l].plane_rb);
                     pf.push_back({p, pl.blocks});
                     pt.push_back({p, cdiv(2LL * pl.rows * (g.nh + 1), kBlock)});
                 }

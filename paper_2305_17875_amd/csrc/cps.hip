@@ -173,6 +173,9 @@ struct LevelMem {
     Buf<double> x64, b64, r64;
     Buf<float> x32, b32, r32;
     int gs_ch = 0; // marching chunk of the colour pass (0 = default; autotuned)
+    // plane smoother's launch shapes (0 = default; autotuned): rings per
+    // block of the transforms, r-steps in flight per lane of the elimination
+    int plane_rb = 0, plane_tb = 0;
     // plane smoother: twiddles exp(-2 pi i q / nh) (q < nh/2), exp(-2 pi i m /
     // n_phi) (m <= nh) as (re, im) pairs, and the symbols 2 cos(2 pi m/n_phi) - 2
     Buf<double> tw64, twN64, lam64;
@@ -400,28 +403,38 @@ void plane_half_sweep_t(cps_handle* h, int l, int parity, const T* b, T* x)
     const LevelMem& m = h->lv[l];
     if (!PB::tw(m) || !PB::S(h) || !PB::piv(m))
         fail(CPS_E_INVALID, "internal: plane smoother not set up");
-    const PlaneLaunch pl = plane_launch(L.g, parity);
+    const int rb = m.plane_rb;
+    const PlaneLaunch pl = plane_launch(L.g, parity, rb);
     const auto* tw = reinterpret_cast<const Vec2<T>*>(PB::tw(m));
     const auto* twN = reinterpret_cast<const Vec2<T>*>(PB::twN(m));
     auto* S = reinterpret_cast<Vec2<T>*>(PB::S(h));
     ProfScope ps(h, CPS_KERNEL_GS, l);
     if (L.g.nh <= kSmallRing)
         k_plane_fwd<T, kSmallRing, CROSS><<<pl.blocks, pl.threads, 0, h->stream>>>(
-            L.g, L.G, L.gk, b, x, parity, tw, twN, S);
+            L.g, L.G, L.gk, b, x, parity, tw, twN, S, rb);
     else
         k_plane_fwd<T, kPlaneLds, CROSS><<<pl.blocks, pl.threads, 0, h->stream>>>(
-            L.g, L.G, L.gk, b, x, parity, tw, twN, S);
+            L.g, L.G, L.gk, b, x, parity, tw, twN, S, rb);
     LAUNCH_CHECK();
     const long long lanes = 2LL * pl.rows * (L.g.nh + 1);
-    k_plane_tri<T, CROSS><<<(unsigned)cdiv(lanes, kTriBlock), kTriBlock, 0, h->stream>>>(
-        L.g, L.G, L.gk, parity, PB::piv(m) + plane_pivot_offset(L.g, parity), PB::S(h));
+    const unsigned tblocks = (unsigned)cdiv(lanes, kTriBlock);
+    const T* piv = PB::piv(m) + plane_pivot_offset(L.g, parity);
+    auto tri = [&](auto TB) {
+        k_plane_tri<T, CROSS, decltype(TB)::value><<<tblocks, kTriBlock, 0, h->stream>>>(
+            L.g, L.G, L.gk, parity, piv, PB::S(h));
+    };
+    switch (tri_batch_of(m.plane_tb)) {
+    case 4: tri(IM<4>{}); break;
+    case 16: tri(IM<16>{}); break;
+    default: tri(IM<kTriBatch>{}); break;
+    }
     LAUNCH_CHECK();
     if (L.g.nh <= kSmallRing)
         k_plane_inv<T, kSmallRing><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN,
-                                                                            S, x);
+                                                                            S, x, rb);
     else
         k_plane_inv<T, kPlaneLds><<<pl.blocks, pl.threads, 0, h->stream>>>(L.g, parity, tw, twN, S,
-                                                                           x);
+                                                                           x, rb);
     LAUNCH_CHECK();
 }
 

@@ -2191,6 +2191,7 @@ struct LDesc {
     const T* plam;
     const T* ppiv;
     Vec2<T>* pS;
+    int prb; // rings per block of the transforms (autotuned)
 };
 
 template <typename T>

@@ -159,14 +159,16 @@ struct PlaneLaunch {
 };
 
 // rows of parity k; lanes per ring (a power of two <= 64, so a ring never
-// straddles wavefronts), rings per block (<= 256 lanes, <= kPlaneLds values)
-__host__ __device__ inline PlaneLaunch plane_launch(const Geo& g, int parity)
+// straddles wavefronts), rings per block (<= 256 lanes, <= kPlaneLds values;
+// rb > 0 asks for at most that many: the autotuner's choice)
+__host__ __device__ inline PlaneLaunch plane_launch(const Geo& g, int parity, int rb = 0)
 {
     PlaneLaunch p;
     p.rows = (g.nt - parity + 1) / 2;
     p.tpr = g.nh / 2 < 64 ? g.nh / 2 : 64;
     p.rb = kBlock / p.tpr;
     if (p.rb * g.nh > kPlaneLds) p.rb = kPlaneLds / g.nh;
+    if (rb > 0 && rb < p.rb) p.rb = rb;
     p.threads = p.rb * p.tpr;
     p.rings = g.nr * p.rows;
     p.blocks = (p.rings + p.rb - 1) / p.rb;
@@ -228,14 +230,16 @@ __device__ __forceinline__ void d_plane_fwd(unsigned blk, Vec2<T>* buf, Vec2<T>*
                                             const T* __restrict__ bv, const T* __restrict__ x,
                                             int parity, const Vec2<T>* __restrict__ tw,
                                             const Vec2<T>* __restrict__ twN,
-                                            Vec2<T>* __restrict__ S)
+                                            Vec2<T>* __restrict__ S, int rb = 0)
 {
-    const PlaneLaunch pl = plane_launch(g, parity);
+    const PlaneLaunch pl = plane_launch(g, parity, rb);
     const int nh = g.nh;
     for (int q = (int)threadIdx.x; q < nh / 2; q += pl.threads) twS[q] = tw[q];
     const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
     const int ring = (int)blk * pl.rb + rl;
-    const bool live = ring < pl.rings;
+    // threads past the block's rings (a batched launch of a fixed block
+    // size) only take part in the barrier
+    const bool live = rl < pl.rb && ring < pl.rings;
     const int a = live ? ring / pl.rows : 0, bi = live ? ring - a * pl.rows : 0;
     const int b = 2 * bi + parity;
     Vec2<T>* A = buf + rl * nh;
@@ -345,10 +349,10 @@ __global__ void __launch_bounds__(kBlock) k_plane_fwd(Geo g, const T* __restrict
                                                       const T* __restrict__ x, int parity,
                                                       const Vec2<T>* __restrict__ tw,
                                                       const Vec2<T>* __restrict__ twN,
-                                                      Vec2<T>* __restrict__ S)
+                                                      Vec2<T>* __restrict__ S, int rb)
 {
     __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
-    d_plane_fwd<T, NMAX, CROSS>(blockIdx.x, buf, twS, g, G, gk, bv, x, parity, tw, twN, S);
+    d_plane_fwd<T, NMAX, CROSS>(blockIdx.x, buf, twS, g, G, gk, bv, x, parity, tw, twN, S, rb);
 }
 
 // Inverse pivots of the Thomas elimination of every (row, mode) r-line of
@@ -382,8 +386,9 @@ __global__ void __launch_bounds__(kBlock) k_plane_factor(Geo g, const T* __restr
 
 // Thomas algorithm along r for every (row, mode) of parity k, in place in
 // the spectra S (read as reals: lane 2u + q takes component q of system u),
-// with the inverse pivots P of k_plane_factor.
-template <typename T, bool CROSS = false>
+// with the inverse pivots P of k_plane_factor; TB r-steps of loads in
+// flight per lane.
+template <typename T, bool CROSS = false, int TB = kTriBatch>
 __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restrict__ G,
                                             long long gk, int parity, const T* __restrict__ P,
                                             T* __restrict__ S)
@@ -396,10 +401,10 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
     const int q = (int)(u & 1);
     const int b = 2 * (int)(t / nm) + parity;
     T d = T(0);
-    for (int a0 = 0; a0 < nr; a0 += kTriBatch) {
-        T r[kTriBatch], p[kTriBatch], gl[kTriBatch];
+    for (int a0 = 0; a0 < nr; a0 += TB) {
+        T r[TB], p[TB], gl[TB];
 #pragma unroll
-        for (int k = 0; k < kTriBatch; ++k) {
+        for (int k = 0; k < TB; ++k) {
             const int a = a0 + k;
             if (a < nr) {
                 const long long o = a * sys + t;
@@ -414,7 +419,7 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
             }
         }
 #pragma unroll
-        for (int k = 0; k < kTriBatch; ++k) {
+        for (int k = 0; k < TB; ++k) {
             const int a = a0 + k;
             if (a < nr) {
                 d = (r[k] - gl[k] * d) * p[k];
@@ -423,10 +428,10 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
         }
     }
     T xn = d; // X at a = nr - 1
-    for (int a0 = nr - 2; a0 >= 0; a0 -= kTriBatch) {
-        T s[kTriBatch], p[kTriBatch], gh[kTriBatch];
+    for (int a0 = nr - 2; a0 >= 0; a0 -= TB) {
+        T s[TB], p[TB], gh[TB];
 #pragma unroll
-        for (int k = 0; k < kTriBatch; ++k) {
+        for (int k = 0; k < TB; ++k) {
             const int a = a0 - k;
             if (a >= 0) {
                 const long long o = a * sys + t;
@@ -441,7 +446,7 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
             }
         }
 #pragma unroll
-        for (int k = 0; k < kTriBatch; ++k) {
+        for (int k = 0; k < TB; ++k) {
             const int a = a0 - k;
             if (a >= 0) {
                 const T c = gh[k] * p[k];
@@ -452,29 +457,35 @@ __device__ __forceinline__ void d_plane_tri(long long u, Geo g, const T* __restr
     }
 }
 
-template <typename T, bool CROSS>
+template <typename T, bool CROSS, int TB>
 __global__ void __launch_bounds__(kTriBlock) k_plane_tri(Geo g, const T* __restrict__ G,
                                                          long long gk, int parity,
                                                          const T* __restrict__ P,
                                                          T* __restrict__ S)
 {
-    d_plane_tri<T, CROSS>((long long)blockIdx.x * blockDim.x + threadIdx.x, g, G, gk, parity, P,
-                          S);
+    d_plane_tri<T, CROSS, TB>((long long)blockIdx.x * blockDim.x + threadIdx.x, g, G, gk, parity,
+                              P, S);
 }
+
+// r-steps in flight per lane of the elimination: the candidates the
+// autotuner times (the same arithmetic in the same order for each)
+__host__ __device__ inline int tri_batch_of(int tb) { return tb == 4 || tb == 16 ? tb : kTriBatch; }
+
 
 // Inverse transforms of the solved spectra into the rows of parity k.
 template <typename T, int NMAX>
 __device__ __forceinline__ void d_plane_inv(unsigned blk, Vec2<T>* buf, Vec2<T>* twS, Geo g,
                                             int parity, const Vec2<T>* __restrict__ tw,
                                             const Vec2<T>* __restrict__ twN,
-                                            const Vec2<T>* __restrict__ S, T* __restrict__ x)
+                                            const Vec2<T>* __restrict__ S, T* __restrict__ x,
+                                            int rb = 0)
 {
-    const PlaneLaunch pl = plane_launch(g, parity);
+    const PlaneLaunch pl = plane_launch(g, parity, rb);
     const int nh = g.nh;
     for (int q = (int)threadIdx.x; q < nh / 2; q += pl.threads) twS[q] = tw[q];
     const int rl = (int)threadIdx.x / pl.tpr, tr = (int)threadIdx.x - rl * pl.tpr;
     const int ring = (int)blk * pl.rb + rl;
-    const bool live = ring < pl.rings;
+    const bool live = rl < pl.rb && ring < pl.rings;
     Vec2<T>* A = buf + rl * nh;
     if (live) {
         const Vec2<T>* X = S + (long long)ring * (nh + 1);
@@ -528,10 +539,10 @@ __global__ void __launch_bounds__(kBlock) k_plane_inv(Geo g, int parity,
                                                       const Vec2<T>* __restrict__ tw,
                                                       const Vec2<T>* __restrict__ twN,
                                                       const Vec2<T>* __restrict__ S,
-                                                      T* __restrict__ x)
+                                                      T* __restrict__ x, int rb)
 {
     __shared__ Vec2<T> buf[kPlaneLds], twS[kPlaneLds / 2];
-    d_plane_inv<T, NMAX>(blockIdx.x, buf, twS, g, parity, tw, twN, S, x);
+    d_plane_inv<T, NMAX>(blockIdx.x, buf, twS, g, parity, tw, twN, S, x, rb);
 }
 
 } // namespace cps

@@ -179,6 +179,35 @@ def test_autotuned_solve_gives_the_same_bits(tmp_path, monkeypatch):
     assert "gs_march/f64/32x32x64" in keys and "gs_march/f32/32x32x64" in keys
 
 
+@pytest.mark.parametrize("map_,f", [(inputs.MAP_SPHERE, 0.0), (inputs.MAP_OBLATE, 0.1)],
+                         ids=["sphere", "oblate"])
+def test_plane_launch_shapes_give_the_same_bits(tmp_path, monkeypatch, map_, f):
+    """The plane smoother's launch shapes (rings per block of the transforms,
+    r-steps in flight of the elimination) only schedule the same arithmetic:
+    a solve with the shapes the autotuner picks (tune=2) equals one with the
+    default shapes (tune=0 on a shape no earlier call has tuned), bit for
+    bit, and the choices land in the cache file."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("CPS_TUNE_CACHE", str(cache))
+    g = Shell(24, 20, 64, map=map_, flattening=f, radial_stretch=1.5)
+    b = dev(inputs.smoothed_noise(g.shape, 92)).flatten()
+    for precision in (0, 1):
+        out = []
+        for tune in (0, 2):
+            s = cps.Solver(g, precision=precision, accel=1, smoother=1, tune=tune)
+            try:
+                r = s.solve(b)
+                out.append((host(r.p), r.iterations))
+            finally:
+                s.close()
+        log("plane shapes", map_, precision, out[0][1], out[1][1])
+        assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    import json
+    keys = json.loads(cache.read_text())
+    cls = "rt" if map_ == inputs.MAP_OBLATE else "ortho"
+    assert f"plane/f64/{cls}/24x20x64" in keys and f"plane/f32/{cls}/12x10x32" in keys
+
+
 def test_service_concurrent_builds_captures_and_remaps():
     """Eight workers, all requests submitted at once: fresh hierarchies of
     several shapes (each first solve captures its iteration bodies into
