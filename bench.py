@@ -86,20 +86,28 @@ def gs_bytes_per_launch(shape, ncol, word, phi_invariant, nterms):
 
 def vcycle_bytes(levels, word, phi_invariant=True):
     """Algorithmic HBM bytes of one V(2,2) cycle from a zero iterate on the
-    7-point hierarchy: per smoothed level of n cells, the zero-iterate pass
-    (b and x of one colour: n words), seven full colour passes (b and x of
-    the updated colour, x of the other: 1.5 n words each), the residual (x,
-    b in, r out: 3 n), restriction (n in, n/8 out) and prolongation (n/8 in,
-    x in and out: 2 n + n/8) -- 17.75 n words -- plus the three metric
-    arrays per (r, theta) read by each of the 8 passes and the residual;
-    the coarsest level reads its FP64 dense inverse once."""
+    7-point hierarchy with point red-black smoothing: per smoothed level of n
+    cells, the zero-iterate pass (b and x of one colour: n words), seven full
+    colour passes (b and x of the updated colour, x of the other: 1.5 n
+    words each), the residual, the restriction and the prolongation (n/8 in,
+    x in and out: 2 n + n/8), plus the three metric arrays per (r, theta)
+    read by each of the 8 passes and the residual; the coarsest level reads
+    its FP64 dense inverse once.
+
+    The pre-smoothing ends on the black pass, which leaves the black
+    residual zero.  On row-pair levels (n_phi / 2 a multiple of 64, n_theta
+    even) only the red residual is formed and restricted: residual x in,
+    red b in, red r out (2 n), restriction red r in, n/8 out -- 16.25 n
+    words a level.  Elsewhere the full residual (x, b in, r out: 3 n) and
+    restriction (n in, n/8 out) -- 17.75 n."""
     total = 0
     for nr, nt, np_ in levels[:-1]:
         n = nr * nt * np_
         coef = 3 * nr * nt * (1 if phi_invariant else np_)
-        total += (17.75 * n + 9 * coef) * word
+        red = (np_ // 2) % 64 == 0 and nt % 2 == 0
+        total += ((16.25 if red else 17.75) * n + 9 * coef) * word
     nc = levels[-1][0] * levels[-1][1] * levels[-1][2]
-    return total + nc * nc * 8 + 2 * nc * word
+    return int(round(total)) + nc * nc * 8 + 2 * nc * word
 
 
 def plane_half_sweep_bytes(shape, word):

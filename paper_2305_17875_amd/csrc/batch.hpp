@@ -183,10 +183,13 @@ void b_vcycle(cps_batch* B, BatchGroup& G)
     for (int l = 0; l + 1 < G.Lmax; ++l) {
         if (!G.gs[l].count) continue;
         b_smooth(B, G, l, false, true);
+        // as vcycle(): after point red-black smoothing, the red residual on
+        // row-pair levels (the kernels check the level's shape)
+        const int red = !G.plane && G.mode == MODE_ORTHO && G.axi ? 1 : 0;
         dispatch(G.mode, G.axi, [&](auto M, auto A) {
-            blaunch(B, G.res[l], kb_residual<float, decltype(M)::value, decltype(A)::value>, l);
+            blaunch(B, G.res[l], kb_residual<float, decltype(M)::value, decltype(A)::value>, l, red);
         });
-        blaunch(B, G.xfer[l], kb_restrict<float>, l);
+        blaunch(B, G.xfer[l], kb_restrict<float>, l, red);
     }
     blaunch(B, G.coarse, kb_coarse<float>);
     for (int l = G.Lmax - 2; l >= 0; --l) {

@@ -482,9 +482,13 @@ long long smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool revers
 }
 
 // r = b - A x; partial sums of r^2 into h->partial when want_norm.
-// Returns the number of partial sums written.
+// red: x has just been smoothed red-black with the black pass last, and on a
+// row-pair level only r's red cells are formed (the black ones are zero, and
+// are left stale: only restrict_to(red) reads this r).  Returns the number
+// of partial sums written.
 template <typename T>
-long long residual(cps_handle* h, int l, const T* b, const T* x, T* r, bool want_norm)
+long long residual(cps_handle* h, int l, const T* b, const T* x, T* r, bool want_norm,
+                   bool red = false)
 {
     const Level<T> L = view<T>(h, l);
     const int bpa = (int)nblk(L.g.rowlen);
@@ -494,11 +498,11 @@ long long residual(cps_handle* h, int l, const T* b, const T* x, T* r, bool want
         const MarchShape ms = stencil_shape(L.g);
         if (row_pairs(L.g)) {
             if (l == 0)
-                k_residual_march2<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa,
-                                                                          ms.ch, b, x, r, part);
+                k_residual_march2<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(
+                    L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, r, part, red ? 1 : 0);
             else
-                k_residual_march2<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(L.g, L.G, L.gk, ms.bpa,
-                                                                          ms.ch, b, x, r, part);
+                k_residual_march2<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(
+                    L.g, L.G, L.gk, ms.bpa, ms.ch, b, x, r, part, red ? 1 : 0);
             LAUNCH_CHECK();
             return ms.grid;
         }
@@ -573,14 +577,20 @@ void dot(cps_handle* h, long long n, const T* u, const U* v, int slot)
     reduce(h, vgrid(n), slot);
 }
 
+// red: r is residual(red)'s output, of which only the red cells are read.
 template <typename T>
-void restrict_to(cps_handle* h, int l, const T* r, T* bc)
+void restrict_to(cps_handle* h, int l, const T* r, T* bc, bool red = false)
 {
     const Geo& f = h->lv[l].geo;
     const Geo& c = h->lv[l + 1].geo;
-    const MarchShape ms = march_shape(c);
+    const MarchShape ms = restrict_shape(c);
     ProfScope ps(h, CPS_KERNEL_RESTRICT, l);
-    k_restrict<T><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, r, bc);
+    if (!restrict_rows(c))
+        k_restrict<T><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, r, bc, red ? 1 : 0);
+    else if (red)
+        k_restrict_rows<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, r, bc);
+    else
+        k_restrict_rows<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, r, bc);
     LAUNCH_CHECK();
 }
 
@@ -619,8 +629,11 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
         T* x = l == 0 ? x0 : xl<T>(h, l);
         // coarse corrections start from zero
         smooth<T>(h, l, b, x, 2, false, l > 0 || x0_zero);
-        residual<T>(h, l, b, x, rl<T>(h, l), false);
-        restrict_to<T>(h, l, rl<T>(h, l), bl<T>(h, l + 1));
+        // point red-black smoothing ends on the black pass: on row-pair
+        // levels only the red residual is formed and restricted
+        const bool red = h->opts.smoother == 0 && marching(h) && row_pairs(h->lv[l].geo);
+        residual<T>(h, l, b, x, rl<T>(h, l), false, red);
+        restrict_to<T>(h, l, rl<T>(h, l), bl<T>(h, l + 1), red);
     }
     coarse_solve<T>(h, bl<T>(h, L - 1), xl<T>(h, L - 1));
     long long parts = 0;

@@ -1159,13 +1159,21 @@ __device__ __forceinline__ void march2_start(const Geo& g, const X& x, const Mar
 }
 
 // r = b - A x (and partial sums of r^2) over row pairs.
+// red != 0: the residual after a red-black smoothing whose last pass was
+// the black one (colour 1).  Each black cell's update made its own equation
+// hold with its red neighbours as they stand, and none has changed since, so
+// its residual is zero (in exact arithmetic; rounding leaves ~1e-16 of b).
+// Only the red cells (colour 0: plane (a + b) mod 2 of row b at plane a) are
+// formed: b is read and r written there only, and r's black entries are
+// left as they are -- the restriction (red != 0) never reads them.  No norm.
 template <typename T, int LTAG, int AHEAD = 1>
 __device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __restrict__ G,
                                                             long long gk, int bpa, int ch,
                                                             const T* __restrict__ bv,
                                                             const T* __restrict__ x,
                                                             T* __restrict__ r,
-                                                            double* __restrict__ partial)
+                                                            double* __restrict__ partial,
+                                                            int red = 0)
 {
     March2 p;
     double acc = 0.0;
@@ -1176,13 +1184,17 @@ __device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __rest
         for (int a = p.a0; a < p.a1; a += AHEAD) {
             Nb4<T> nb[AHEAD];
             T bb[AHEAD][4];
+            // the red cells of the pair at plane a: (u0, v1) for even a,
+            // (v0, u1) for odd a (row b0 is even)
+            auto is_red = [&](int k, int aa) { return (((k == 1 || k == 2) ? 1 : 0) ^ (aa & 1)) == 0; };
 #pragma unroll
             for (int u = 0; u < AHEAD; ++u)
                 if (a + u < p.a1) {
                     march2_load<T>(g, Plain<T>{x}, p, a + u, nb[u]);
                     const long long base = (long long)(a + u) * g.rowlen + p.r0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) bb[u][k] = ld_once(bv + base + o[k]);
+                    for (int k = 0; k < 4; ++k)
+                        if (!red || is_red(k, a + u)) bb[u][k] = ld_once(bv + base + o[k]);
                 }
 #pragma unroll
             for (int u = 0; u < AHEAD; ++u)
@@ -1192,6 +1204,7 @@ __device__ __forceinline__ void d_residual_march2(Blk bk, Geo g, const T* __rest
                     const long long base = (long long)(a + u) * g.rowlen + p.r0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
+                        if (red && !is_red(k, a + u)) continue;
                         const T rk = bb[u][k] - y[k];
                         st_once(r + base + o[k], rk);
                         acc += (double)rk * (double)rk;
@@ -1213,9 +1226,10 @@ __global__ void __launch_bounds__(kBlock) k_residual_march2(Geo g, const T* __re
                                                             const T* __restrict__ bv,
                                                             const T* __restrict__ x,
                                                             T* __restrict__ r,
-                                                            double* __restrict__ partial)
+                                                            double* __restrict__ partial,
+                                                            int red)
 {
-    d_residual_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, r, partial);
+    d_residual_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, bv, x, r, partial, red);
 }
 
 // y = A x (and partial sums of y . dotv) over row pairs.
@@ -1435,11 +1449,14 @@ __device__ __forceinline__ bool coarse_col(Blk bk, const Geo& c, int bpa, int ch
     return true;
 }
 
-// bc = R r (full weighting; interior rows sum to 8).
+// bc = R r (full weighting; interior rows sum to 8).  red != 0: r is the
+// red-only residual of d_residual_march2 (zero on the black cells, whose
+// entries hold stale values): of each fine row only its red parity plane,
+// (plane + row) mod 2, is read, the other taken as zero.
 template <typename T>
 __device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch,
                                                      const T* __restrict__ r,
-                                                     T* __restrict__ bc)
+                                                     T* __restrict__ bc, int red = 0)
 {
     CoarseCol p;
     if (!coarse_col(bk, c, bpa, ch, p)) return;
@@ -1461,21 +1478,26 @@ __device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch
     const bool hi_lane = lane < 63 && p.jc < c.nh - 1;
     // theta-phi restriction of fine plane a for K = 2jc (s0) and 2jc+1 (s1)
     auto plane = [&](int a, T& s0, T& s1) {
-        const T* ra = r + (long long)clampi(a, f.nr - 1) * f.rowlen;
+        const int ac = clampi(a, f.nr - 1);
+        const T* ra = r + (long long)ac * f.rowlen;
         Vec2<T> e[4], o[4];
         T v0[4], v5[4];
+        const Vec2<T> zero2{T(0), T(0)};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const T* rr = ra + rowo[q];
-            e[q] = *reinterpret_cast<const Vec2<T>*>(rr + cv);
-            o[q] = *reinterpret_cast<const Vec2<T>*>(rr + f.P + cv);
+            // red: the row's red cells are in plane (ac + row) mod 2
+            const int sp = (ac + (int)(rowo[q] / f.nh)) & 1;
+            e[q] = !red || sp == 0 ? *reinterpret_cast<const Vec2<T>*>(rr + cv) : zero2;
+            o[q] = !red || sp == 1 ? *reinterpret_cast<const Vec2<T>*>(rr + f.P + cv) : zero2;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+            const int sp = (ac + (int)(rowo[q] / f.nh)) & 1;
             v0[q] = __shfl(o[q].y, lane - 1);
             v5[q] = __shfl(e[q].x, lane + 1);
-            if (!lo_lane) v0[q] = ra[rowo[q] + cm];
-            if (!hi_lane) v5[q] = ra[rowo[q] + cp];
+            if (!lo_lane) v0[q] = !red || sp == 1 ? ra[rowo[q] + cm] : T(0);
+            if (!hi_lane) v5[q] = !red || sp == 0 ? ra[rowo[q] + cp] : T(0);
         }
         s0 = T(0);
         s1 = T(0);
@@ -1510,9 +1532,17 @@ __device__ __forceinline__ void d_restrict(Blk bk, Geo f, Geo c, int bpa, int ch
 // the adjacent lanes) and hands it to the neighbouring wavefronts through
 // LDS: row 2J - 1 is wavefront w - 1's second row, 2J + 2 wavefront w + 1's
 // first; the block's first and last wavefronts form their outer row
-// themselves (mirrored at the theta walls).  Half the loads of d_restrict,
-// the same sums in the same order.  LDS double-buffered by fine plane: one
-// barrier per plane.
+// themselves (mirrored at the theta walls).  Half the loads of d_restrict.
+// LDS double-buffered by fine plane: one barrier per plane.
+//
+// The marching over fine planes is latency-bound unless loads run ahead of
+// the barriers: the raw values of two planes are held in registers, and the
+// loads of a plane are issued as soon as its buffer is consumed, two planes
+// before it is restricted.
+//
+// RED (d_residual_march2's red residual): of each fine row only its red
+// parity plane, (plane + row) mod 2, is read -- one 2-vector and one outer
+// phi value per row -- and the black values enter as zeros.
 template <typename T>
 struct RestrictLds {
     Vec2<T> v[2][4][2][64];
@@ -1523,7 +1553,23 @@ __host__ __device__ inline bool restrict_rows(const Geo& c)
     return c.nh % 64 == 0 && c.nt % 4 == 0;
 }
 
+// raw values of one fine row at one plane: the 2-vectors of both parity
+// planes at the thread's phi pair and the outer phi values (m: plane 1 at
+// 4jc - 1, p: plane 0 at 4jc + 4; loaded only by the lanes without a
+// neighbour holding them)
+template <typename T, int RED>
+struct RestrictRaw {
+    Vec2<T> e, o;
+    T m, p;
+};
+// red only: the red parity plane's 2-vector and its one outer value
 template <typename T>
+struct RestrictRaw<T, 1> {
+    Vec2<T> v;
+    T edge;
+};
+
+template <typename T, int RED>
 __device__ __forceinline__ void d_restrict2(Blk bk, Geo f, Geo c, int bpa, int ch,
                                             const T* __restrict__ r, T* __restrict__ bc,
                                             RestrictLds<T>& sh)
@@ -1543,29 +1589,65 @@ __device__ __forceinline__ void d_restrict2(Blk bk, Geo f, Geo c, int bpa, int c
     const long long cp = jc == c.nh - 1 ? 0 : cv + 2;
     const bool lo_lane = lane > 0 && jc > 0;
     const bool hi_lane = lane < 63 && jc < c.nh - 1;
-    // phi restriction of fine row `row` of the plane at ra, for K = 2jc (q0)
-    // and 2jc + 1 (q1)
-    auto phi = [&](const T* ra, int row, T& q0, T& q1) {
-        const T* rr = ra + (long long)row * f.nh;
-        const Vec2<T> e = *reinterpret_cast<const Vec2<T>*>(rr + cv);
-        const Vec2<T> o = *reinterpret_cast<const Vec2<T>*>(rr + f.P + cv);
-        T v0 = __shfl(o.y, lane - 1);
-        T v5 = __shfl(e.x, lane + 1);
-        if (!lo_lane) v0 = rr[cm];
-        if (!hi_lane) v5 = rr[cp];
-        const T v1 = e.x, v2 = o.x, v3 = e.y, v4 = o.y;
-        q0 = w0 * v0 + w1 * v1 + w1 * v2 + w0 * v3;
-        q1 = w0 * v2 + w1 * v3 + w1 * v4 + w0 * v5;
+    // the wavefront's rows: 2J, 2J + 1 and (first and last wavefront) the
+    // outer row, mirrored at the theta walls
+    const bool outer = w == 0 || w == 3;
+    const int rows[3] = {2 * J, 2 * J + 1,
+                         clampi(w == 0 ? 2 * J - 1 : 2 * J + 2, f.nt - 1)};
+    using Raw = RestrictRaw<T, RED>;
+    auto load = [&](int a, Raw (&q)[3]) {
+        const int ac = clampi(a, f.nr - 1);
+        const T* ra = r + (long long)ac * f.rowlen;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k == 2 && !outer) continue;
+            const T* rr = ra + (long long)rows[k] * f.nh;
+            if constexpr (RED) {
+                const int sp = (ac + rows[k]) & 1;
+                q[k].v = *reinterpret_cast<const Vec2<T>*>(rr + (sp ? f.P : 0) + cv);
+                q[k].edge = (sp ? !lo_lane : !hi_lane) ? rr[sp ? cm : cp] : T(0);
+            } else {
+                q[k].e = *reinterpret_cast<const Vec2<T>*>(rr + cv);
+                q[k].o = *reinterpret_cast<const Vec2<T>*>(rr + f.P + cv);
+                q[k].m = !lo_lane ? rr[cm] : T(0);
+                q[k].p = !hi_lane ? rr[cp] : T(0);
+            }
+        }
+    };
+    // phi restriction of one row's raw values, for K = 2jc (q0) and 2jc + 1
+    // (q1); fine phi 4jc - 1 .. 4jc + 4 are v0 .. v5
+    auto phi = [&](int ac, int row, const Raw& q, T& q0, T& q1) {
+        if constexpr (RED) {
+            if (((ac + row) & 1) == 0) { // red in plane 0: v1, v3, v5
+                T v5 = __shfl(q.v.x, lane + 1);
+                if (!hi_lane) v5 = q.edge;
+                q0 = w1 * q.v.x + w0 * q.v.y;
+                q1 = w1 * q.v.y + w0 * v5;
+            } else { // red in plane 1: v0, v2, v4
+                T v0 = __shfl(q.v.y, lane - 1);
+                if (!lo_lane) v0 = q.edge;
+                q0 = w0 * v0 + w1 * q.v.x;
+                q1 = w0 * q.v.x + w1 * q.v.y;
+            }
+        } else {
+            T v0 = __shfl(q.o.y, lane - 1);
+            T v5 = __shfl(q.e.x, lane + 1);
+            if (!lo_lane) v0 = q.m;
+            if (!hi_lane) v5 = q.p;
+            const T v1 = q.e.x, v2 = q.o.x, v3 = q.e.y, v4 = q.o.y;
+            q0 = w0 * v0 + w1 * v1 + w1 * v2 + w0 * v3;
+            q1 = w0 * v2 + w1 * v3 + w1 * v4 + w0 * v5;
+        }
     };
     int buf = 0;
-    // theta-phi restriction of fine plane a
-    auto plane = [&](int a, T& s0, T& s1) {
-        const T* ra = r + (long long)clampi(a, f.nr - 1) * f.rowlen;
+    // theta-phi restriction of fine plane a from its raw values
+    auto plane = [&](int a, const Raw (&q)[3], T& s0, T& s1) {
+        const int ac = clampi(a, f.nr - 1);
         T p0[4], p1[4]; // fine rows 2J - 1 .. 2J + 2
-        phi(ra, 2 * J, p0[1], p1[1]);
-        phi(ra, 2 * J + 1, p0[2], p1[2]);
-        if (w == 0) phi(ra, clampi(2 * J - 1, f.nt - 1), p0[0], p1[0]);
-        if (w == 3) phi(ra, clampi(2 * J + 2, f.nt - 1), p0[3], p1[3]);
+        phi(ac, rows[0], q[0], p0[1], p1[1]);
+        phi(ac, rows[1], q[1], p0[2], p1[2]);
+        if (w == 0) phi(ac, rows[2], q[2], p0[0], p1[0]);
+        if (w == 3) phi(ac, rows[2], q[2], p0[3], p1[3]);
         Vec2<T> own0, own1;
         own0.x = p0[1];
         own0.y = p1[1];
@@ -1593,14 +1675,23 @@ __device__ __forceinline__ void d_restrict2(Blk bk, Geo f, Geo c, int bpa, int c
             s1 += wq[q] * p1[q];
         }
     };
+    // coarse plane I takes fine planes 2I - 1 .. 2I + 2 (weights 1, 3, 3, 1);
+    // A holds the odd fine planes, B the even ones
+    Raw A[3], B[3];
+    load(2 * I0 - 1, A);
+    load(2 * I0, B);
     T pa0, pa1, pb0, pb1;
-    plane(2 * I0 - 1, pa0, pa1);
-    plane(2 * I0, pb0, pb1);
+    plane(2 * I0 - 1, A, pa0, pa1);
+    load(2 * I0 + 1, A);
+    plane(2 * I0, B, pb0, pb1);
+    load(2 * I0 + 2, B);
     const int m = J * c.nh + jc;
     for (int I = I0; I < I1; ++I) {
         T qa0, qa1, qb0, qb1;
-        plane(2 * I + 1, qa0, qa1);
-        plane(2 * I + 2, qb0, qb1);
+        plane(2 * I + 1, A, qa0, qa1);
+        if (I + 1 < I1) load(2 * I + 3, A);
+        plane(2 * I + 2, B, qb0, qb1);
+        if (I + 1 < I1) load(2 * I + 4, B);
         const long long o = (long long)I * c.rowlen + m;
         bc[o] = w0 * pa0 + w1 * pb0 + w1 * qa0 + w0 * qb0;
         bc[c.P + o] = w0 * pa1 + w1 * pb1 + w1 * qa1 + w0 * qb1;
@@ -1609,23 +1700,34 @@ __device__ __forceinline__ void d_restrict2(Blk bk, Geo f, Geo c, int bpa, int c
 }
 
 // Either restriction, chosen by the coarse level's shape (the same choice in
-// the single and the batched form; both take march_shape(c)'s blocks).
+// the single and the batched form; any chunk gives the same bits).
 template <typename T>
 __device__ __forceinline__ void d_restrict_any(Blk bk, Geo f, Geo c, int bpa, int ch,
                                                const T* __restrict__ r, T* __restrict__ bc,
-                                               RestrictLds<T>& sh)
+                                               RestrictLds<T>& sh, int red)
 {
-    if (restrict_rows(c)) d_restrict2<T>(bk, f, c, bpa, ch, r, bc, sh);
-    else d_restrict<T>(bk, f, c, bpa, ch, r, bc);
+    if (!restrict_rows(c)) d_restrict<T>(bk, f, c, bpa, ch, r, bc, red);
+    else if (red) d_restrict2<T, 1>(bk, f, c, bpa, ch, r, bc, sh);
+    else d_restrict2<T, 0>(bk, f, c, bpa, ch, r, bc, sh);
 }
 
+// the single solve launches each body as a kernel of its own (its registers
+// are then its own)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict(Geo f, Geo c, int bpa, int ch,
                                                      const T* __restrict__ r,
-                                                     T* __restrict__ bc)
+                                                     T* __restrict__ bc, int red)
+{
+    d_restrict<T>(self_blk(), f, c, bpa, ch, r, bc, red);
+}
+
+template <typename T, int RED>
+__global__ void __launch_bounds__(kBlock) k_restrict_rows(Geo f, Geo c, int bpa, int ch,
+                                                          const T* __restrict__ r,
+                                                          T* __restrict__ bc)
 {
     __shared__ RestrictLds<T> sh;
-    d_restrict_any<T>(self_blk(), f, c, bpa, ch, r, bc, sh);
+    d_restrict2<T, RED>(self_blk(), f, c, bpa, ch, r, bc, sh);
 }
 
 // x += P e (trilinear); the thread writes fine rows 2J, 2J+1 and fine phi
@@ -2129,6 +2231,14 @@ __host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
 {
     return chunked(g, cdiv(g.rowlen, kBlock), ch);
 }
+// The restriction's launch: on whole-wavefront coarse levels about 1024
+// blocks (6 coarse planes a block on the paper-scale shell's finest
+// restriction: a probe over 2 .. 12 put it fastest), else march_shape.
+__host__ __device__ inline MarchShape restrict_shape(const Geo& c)
+{
+    return restrict_rows(c) ? chunked(c, cdiv(c.rowlen, kBlock), 0, 1024) : march_shape(c);
+}
+
 // Row-pair kernels: bpa blocks over the (n_theta / 2) * (n_phi / 2)
 // positions of a plane.  stencil_shape: the marching launch a level uses.
 __host__ __device__ inline MarchShape march2_shape(const Geo& g, int ch = 0, int target = 2048)
@@ -2246,17 +2356,20 @@ __global__ void __launch_bounds__(kBlock) kb_gs(const BItem* __restrict__ items,
 }
 
 // r = b - A x on a level (no norm), marching (7-point, phi-invariant) or generic
+// red: the group smooths red-black (not by planes): on row-pair levels the
+// red-only residual, as the single solve forms it
 template <typename T, int MODE, bool AXI>
 __global__ void __launch_bounds__(kBlock) kb_residual(const BItem* __restrict__ items,
                                                       const int* __restrict__ active,
-                                                      const PDesc<T>* __restrict__ pd, int level)
+                                                      const PDesc<T>* __restrict__ pd, int level,
+                                                      int red)
 {
     CPS_BATCH_BLOCK
     const LDesc<T>& d = pd[it.prob].lv[level];
     const bool u = d.g.nh % 64 == 0;
     if constexpr (MODE == MODE_ORTHO && AXI) {
         const MarchShape ms = stencil_shape(d.g);
-        if (row_pairs(d.g)) d_residual_march2<T, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
+        if (row_pairs(d.g)) d_residual_march2<T, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr, red);
         else if (u) d_residual_march<T, true, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
         else d_residual_march<T, false, 1>(bk, d.g, d.G, d.gk, ms.bpa, ms.ch, d.b, d.x, d.r, nullptr);
     } else {
@@ -2269,14 +2382,15 @@ __global__ void __launch_bounds__(kBlock) kb_residual(const BItem* __restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) kb_restrict(const BItem* __restrict__ items,
                                                       const int* __restrict__ active,
-                                                      const PDesc<T>* __restrict__ pd, int level)
+                                                      const PDesc<T>* __restrict__ pd, int level,
+                                                      int red)
 {
     CPS_BATCH_BLOCK
     __shared__ RestrictLds<T> sh;
     const PDesc<T>& P = pd[it.prob];
     const MarchShape ms = march_shape(P.lv[level + 1].g);
     d_restrict_any<T>(bk, P.lv[level].g, P.lv[level + 1].g, ms.bpa, ms.ch, P.lv[level].r,
-                      P.lv[level + 1].b, sh);
+                      P.lv[level + 1].b, sh, red && row_pairs(P.lv[level].g));
 }
 
 template <typename T>

@@ -56,7 +56,21 @@ def test_paper_scale_figures(bench):
     assert bench.plane_half_sweep_bytes(PAPER_SCALE, 8) == 1_009_385_472
     levels = [(192, 256, 512), (96, 128, 256), (48, 64, 128), (24, 32, 64), (12, 16, 32),
               (6, 8, 16)]
-    assert bench.vcycle_bytes(levels, 8) == 4_102_801_920
+    assert bench.vcycle_bytes(levels, 8) == 3_758_344_704
+
+
+def test_vcycle_bytes_red_residual_levels(bench):
+    """Row-pair levels (n_phi / 2 a multiple of 64, n_theta even) form and
+    restrict only the red residual: 16.25 n words a level against 17.75 n
+    on the others; the coarsest level's dense inverse is the same."""
+    coarse = (2, 2, 4)
+    nc = 16
+    tail = nc * nc * 8 + 2 * nc * 8
+    for shape, words in (((4, 8, 128), 16.25), ((4, 8, 64), 17.75), ((4, 7, 128), 17.75)):
+        nr, nt, np_ = shape
+        n = nr * nt * np_
+        want = int(round((words * n + 9 * 3 * nr * nt) * 8)) + tail
+        assert bench.vcycle_bytes([shape, coarse], 8) == want, shape
 
 
 def test_plane_half_sweep_counts_its_terms(bench):

@@ -119,6 +119,34 @@ def test_colour_pass_is_sequential_gauss_seidel(kw, ncol):
         np.testing.assert_allclose(got.ravel(), want, rtol=1e-12, atol=1e-12)
 
 
+def test_black_residual_vanishes_after_a_black_pass():
+    """After a red-black sweep that ends on the black pass (colour 1), every
+    black cell's own equation holds with its red neighbours as they stand:
+    its residual is zero up to rounding, the red residual is not.  So the
+    restriction of the red residual alone (black entries zeroed) equals the
+    restriction of the whole residual up to rounding -- the fact that lets
+    the V-cycle form and restrict only the red residual after
+    pre-smoothing."""
+    g = O.Grid(6, 8, 16, radial_stretch=2.0)
+    G = O.face_metrics(g)
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(g.shape)
+    x = rng.standard_normal(g.shape)
+    for _ in range(2):
+        for col in (0, 1):
+            x = O.gs_pass(G, b, x, 2, col)
+    r = O.residual(G, b, x)
+    scale = np.abs(b).max() + np.abs(O.apply(G, x)).max()
+    black = np.zeros(g.shape, dtype=bool)
+    for a, bb, c in itertools.product(*map(range, g.shape)):
+        black[a, bb, c] = O.colour(2, a, bb, c) == 1
+    assert np.abs(r[black]).max() <= 1e-14 * scale
+    assert np.abs(r[~black]).max() >= 1e-3 * scale
+    red_only = np.where(black, 0.0, r)
+    full, red = O.restrict(r), O.restrict(red_only)
+    assert np.abs(full - red).max() <= 1e-13 * np.abs(full).max()
+
+
 def test_coarse_solve_is_exact_on_zero_mean_data():
     g = O.Grid(8, 8, 16)
     mg = O.Multigrid(g)
