@@ -1615,9 +1615,14 @@ void divergence(cps_handle* h, const double* u, double* rhs)
     const LevelMem& m = h->lv[0];
     ProfScope ps(h, CPS_KERNEL_DIVERGENCE, 0);
     with_csym(h, [&](auto S) {
-        k_divergence<decltype(S)::value>
-            <<<(unsigned)proj_grid(m.nr, m.nt, m.np), kBlock, 0, h->stream>>>(m.nr, m.nt, m.np,
-                                                                              crows(h), u, rhs);
+        if (m.nt % 2 == 0)
+            k_divergence2<decltype(S)::value>
+                <<<(unsigned)proj2_grid(m.nr, m.nt, m.np), kBlock, 0, h->stream>>>(
+                    m.nr, m.nt, m.np, crows(h), u, rhs);
+        else
+            k_divergence<decltype(S)::value>
+                <<<(unsigned)proj_grid(m.nr, m.nt, m.np), kBlock, 0, h->stream>>>(
+                    m.nr, m.nt, m.np, crows(h), u, rhs);
     });
     LAUNCH_CHECK();
 }

@@ -240,6 +240,152 @@ __global__ void __launch_bounds__(kBlock) k_divergence(int nr, int nt, int np, C
     }
 }
 
+// The divergence over theta-row pairs (n_theta even): wavefront w of a
+// block owns rows b0 = 2 (4 G + w) and b0 + 1 over one 64-cell phi segment
+// and marches both columns over a chunk of kProjChunk2 planes.  The theta
+// face between its rows is formed once from the two columns in registers,
+// so only the rows just outside the pair are loaded: 4 row loads per 2
+// cells and plane, against 3 per cell.  Block order as proj_col (each XCD a
+// contiguous range).  Every flux is the same expression, on the same values,
+// as in k_divergence, and each cell sums its faces in the same order.
+constexpr int kProjChunk2 = 8;
+
+struct ProjPair {
+    int a0, a1, b0, c;
+    bool live;
+};
+
+__host__ __device__ inline long long proj2_blocks(int nr, int nt, int np)
+{
+    return (long long)((nr + kProjChunk2 - 1) / kProjChunk2) *
+           ((nt / 2 + kProjRows - 1) / kProjRows) * ((np + 63) / 64);
+}
+
+__host__ __device__ inline long long proj2_grid(int nr, int nt, int np)
+{
+    return (proj2_blocks(nr, nt, np) + 7) / 8 * 8;
+}
+
+__device__ inline ProjPair proj_pair(int nr, int nt, int np)
+{
+    ProjPair p{0, 0, 0, 0, false};
+    const long long nb = proj2_blocks(nr, nt, np), per = (nb + 7) / 8;
+    const long long lb = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (lb >= nb) return p;
+    const int segs = (np + 63) / 64, groups = (nt / 2 + kProjRows - 1) / kProjRows;
+    const int cs = (int)(lb % segs);
+    const long long t = lb / segs;
+    const int ch = (int)(t / groups);
+    p.a0 = ch * kProjChunk2;
+    p.a1 = p.a0 + kProjChunk2 < nr ? p.a0 + kProjChunk2 : nr;
+    p.b0 = 2 * __builtin_amdgcn_readfirstlane((int)(t % groups) * kProjRows +
+                                              (int)(threadIdx.x >> 6));
+    p.c = cs * 64 + (int)(threadIdx.x & 63);
+    p.live = p.b0 < nt && p.c < np;
+    return p;
+}
+
+template <int SYM>
+__global__ void __launch_bounds__(kBlock) k_divergence2(int nr, int nt, int np, CRows R,
+                                                        const double* __restrict__ u,
+                                                        double* __restrict__ rhs)
+{
+    const ProjPair col = proj_pair(nr, nt, np);
+    if (!col.live) return;
+    const int b0 = col.b0, b1 = b0 + 1, c = col.c;
+    const long long N = (long long)nr * nt * np, plane = (long long)nt * np;
+    const int cm = c == 0 ? np - 1 : c - 1, cp = c == np - 1 ? 0 : c + 1;
+    double s0 = 0.0, c0 = 1.0, s1 = 0.0, c1 = 1.0;
+    if (SYM == kRotational) {
+        c0 = R.rot[2 * c];
+        s0 = R.rot[2 * c + 1];
+        c1 = R.rot[2 * c + 2];
+        s1 = R.rot[2 * c + 3];
+    }
+    const double* u0 = u;
+    const double* u1 = u + N;
+    const double* u2 = u + 2 * N;
+    const long long col0 = (long long)b0 * np + c;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool whole = np <= 64;
+    const int lane_lo = whole ? cm : lane - 1, lane_hi = whole ? cp : lane + 1;
+    const bool shfl_lo = whole || lane > 0, shfl_hi = whole || (lane < 63 && c + 1 < np);
+    // both rows' columns at plane a: v[0..2] row b0, v[3..5] row b1
+    auto load = [&](int a, double v[6]) {
+        const long long i = a * plane + col0;
+        v[0] = u0[i];
+        v[1] = u1[i];
+        v[2] = u2[i];
+        v[3] = u0[i + np];
+        v[4] = u1[i + np];
+        v[5] = u2[i + np];
+    };
+    auto flux = [&](int d, int fa, int fb, int fc, const double hi[3], const double lo[3],
+                    double cs, double sn) {
+        double C[3];
+        crow<SYM>(R, d, fa, fb, fc, cs, sn, C);
+        double U = 0.0;
+        U += C[0] * (0.5 * (hi[0] + lo[0]));
+        U += C[1] * (0.5 * (hi[1] + lo[1]));
+        U += C[2] * (0.5 * (hi[2] + lo[2]));
+        return U;
+    };
+    // the phi faces and the sum of one cell, given its theta fluxes
+    auto cell = [&](int a, int b, long long i, const double uc[3], double r_lo, double r_hi,
+                    double t_lo, double t_hi) {
+        double nb[3];
+        for (int q = 0; q < 3; ++q) nb[q] = __shfl(uc[q], lane_lo);
+        if (!shfl_lo) {
+            nb[0] = u0[i - c + cm]; nb[1] = u1[i - c + cm]; nb[2] = u2[i - c + cm];
+        }
+        const double p_lo = flux(2, a, b, c, uc, nb, c0, s0);
+        for (int q = 0; q < 3; ++q) nb[q] = __shfl(uc[q], lane_hi);
+        if (!shfl_hi) {
+            nb[0] = u0[i - c + cp]; nb[1] = u1[i - c + cp]; nb[2] = u2[i - c + cp];
+        }
+        const double p_hi = flux(2, a, b, cp, nb, uc, c1, s1);
+        double s = 0.0;
+        s += r_hi - r_lo;
+        s += t_hi - t_lo;
+        s += p_hi - p_lo;
+        rhs[i] = s;
+    };
+    double um[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, uc[6], up[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (col.a0 > 0) load(col.a0 - 1, um);
+    load(col.a0, uc);
+    if (col.a0 + 1 < nr) load(col.a0 + 1, up);
+    for (int a = col.a0; a < col.a1; ++a) {
+        double un[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (a + 2 < nr && a + 1 < col.a1) load(a + 2, un);
+        const long long i = a * plane + col0;
+        double v[3];
+        // rows outside the pair (loading them a plane ahead costs registers:
+        // 137 VGPRs, 3 waves per SIMD, 283 against 272 us)
+        double t_lo0 = 0.0, t_hi1 = 0.0;
+        if (b0 > 0) {
+            v[0] = u0[i - np]; v[1] = u1[i - np]; v[2] = u2[i - np];
+            t_lo0 = flux(1, a, b0, c, uc, v, c0, s0);
+        }
+        if (b1 < nt - 1) {
+            v[0] = u0[i + 2 * np]; v[1] = u1[i + 2 * np]; v[2] = u2[i + 2 * np];
+            t_hi1 = flux(1, a, b1 + 1, c, v, uc + 3, c0, s0);
+        }
+        // the face between the rows, once for both
+        const double t_mid = flux(1, a, b1, c, uc + 3, uc, c0, s0);
+        const double r_lo0 = a > 0 ? flux(0, a, b0, c, uc, um, c0, s0) : 0.0;
+        const double r_hi0 = a < nr - 1 ? flux(0, a + 1, b0, c, up, uc, c0, s0) : 0.0;
+        const double r_lo1 = a > 0 ? flux(0, a, b1, c, uc + 3, um + 3, c0, s0) : 0.0;
+        const double r_hi1 = a < nr - 1 ? flux(0, a + 1, b1, c, up + 3, uc + 3, c0, s0) : 0.0;
+        cell(a, b0, i, uc, r_lo0, r_hi0, t_lo0, t_mid);
+        cell(a, b1, i + np, uc + 3, r_lo1, r_hi1, t_mid, t_hi1);
+        for (int q = 0; q < 6; ++q) {
+            um[q] = uc[q];
+            uc[q] = up[q];
+            up[q] = un[q];
+        }
+    }
+}
+
 // u_q <- u_q - (1/|J^-1|) sum over the six faces of +-C_dq (face mean of
 // phi); phi is mirrored on the r- and theta-walls.  Marches like
 // k_divergence with phi at a - 1, a and a + 1 in registers.

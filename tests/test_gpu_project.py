@@ -17,6 +17,10 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 CASES = [
     ("sphere-stretch-8x8x16", Shell(8, 8, 16, radial_stretch=2.0), 0),
     ("sphere-6x10x36", Shell(6, 10, 36), 0),  # 2160 cells: a ragged last block
+    # odd n_theta: the divergence takes one row per thread, not row pairs
+    ("sphere-4x7x128", Shell(4, 7, 128, radial_stretch=2.0), 0),
+    # 12 row pairs (a ragged pair group), two 64-cell phi segments
+    ("oblate-8x24x256", Shell(8, 24, 256, map=MAP_OBLATE, flattening=0.1), 0),
     ("oblate-8x8x16", Shell(8, 8, 16, map=MAP_OBLATE, flattening=0.1), 0),
     ("triaxial-6x8x16", Shell(6, 8, 16, map=MAP_TRIAXIAL, flattening=0.1, skew=0.1), 0),
     ("identity-8x8x16", Shell(8, 8, 16, map=MAP_IDENTITY), 0),
