@@ -419,6 +419,17 @@ cps_status cps_profile_select(cps_handle* h, uint32_t class_mask);
  * recorded launches of the class, *launches = their count; then clears. */
 cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_ms,
                             int64_t* launches);
+/* The preconditioning V-cycle as the solve runs it (Sec. on the multigrid
+ * solver: V(2,2) with the handle's smoother, precision and tuned launch
+ * shapes, from a zero iterate): `cycles` V-cycles are captured into one
+ * hipGraph, launched once untimed and then `reps` times between two HIP
+ * events on the handle's stream; *us_per_cycle (host) = elapsed time /
+ * (reps * cycles).  The input is the handle's finest-level residual vector,
+ * filled with ones; it and the finest-level iterate are overwritten (the
+ * next solve sets both).  Synchronous.  CPS_E_INVALID: a NULL argument,
+ * cycles or reps < 1, the handle on the null stream (it cannot be
+ * captured), or profiling on (cps_profile_enable). */
+cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* us_per_cycle);
 /* dst[i] = src[i] for i < n (device FP64, ordered on `stream`, synchronous):
  * a plain copy of known size, the yardstick for the HBM byte counters. */
 cps_status cps_debug_copy(const double* src, double* dst, int64_t n, void* stream);

@@ -121,6 +121,7 @@ def lib():
         L.cps_profile_select.argtypes = [P, ctypes.c_uint32]
         L.cps_profile_read.argtypes = [P, I, P, P]
         L.cps_debug_copy.argtypes = [P, P, ctypes.c_int64, P]
+        L.cps_time_vcycle.argtypes = [P, I, I, P]
         L.cps_divergence.argtypes = [P, P, P]
         L.cps_correct.argtypes = [P, P, P]
         L.cps_project.argtypes = [P, P, P, D, P]
@@ -129,6 +130,7 @@ def lib():
         for f in ("cps_divergence", "cps_correct", "cps_project", "cps_line_solve",
                   "cps_line_solve_noalloc",
                   "cps_profile_select", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
+                  "cps_time_vcycle",
                   "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
                   "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
                   "cps_debug_coarse_solve", "cps_debug_vcycle", "cps_debug_plane_sweep"):
@@ -346,6 +348,14 @@ def cps_profile_read(h, kernel_class: int):
     return ms.value, n.value
 
 
+def cps_time_vcycle(h, cycles: int, reps: int) -> float:
+    """Microseconds per preconditioning V-cycle, replayed from a hipGraph
+    of `cycles` cycles, `reps` launches timed with events."""
+    us = ctypes.c_double()
+    _check(lib().cps_time_vcycle(h, int(cycles), int(reps), ctypes.byref(us)))
+    return us.value
+
+
 def cps_debug_copy(src, dst, stream=None):
     if src.numel() != dst.numel():
         raise ValueError("size mismatch")
@@ -408,6 +418,14 @@ class Solver:
         """Later work on the caller's stream sees the library's results."""
         if cur != self.stream:
             cur.wait_stream(self.stream)
+
+    def time_vcycle(self, cycles: int = 10, reps: int = 5) -> float:
+        """Microseconds per V-cycle as the solve replays it (cps_time_vcycle)."""
+        cur = self._enter()
+        try:
+            return cps_time_vcycle(self.h, cycles, reps)
+        finally:
+            self._leave(cur)
 
     def solve(self, rhs, tol: float = 1e-10, out=None) -> Result:
         import torch

@@ -2068,6 +2068,60 @@ cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_m
     });
 }
 
+cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* us_per_cycle)
+{
+    return guarded([&] {
+        if (!h || !us_per_cycle) fail(CPS_E_INVALID, "NULL argument");
+        if (cycles < 1 || reps < 1) fail(CPS_E_INVALID, "cycles and reps must be >= 1");
+        if (!h->stream) fail(CPS_E_INVALID, "the null stream cannot be captured: set a stream");
+        if (h->prof) fail(CPS_E_INVALID, "profiling is on (its events cannot be captured)");
+        const long long n = h->lv[0].n;
+        const bool mixed = h->opts.precision == 1;
+        if (mixed) fill<float>(h, h->lv[0].b32.p, n, 1.0f);
+        else fill<double>(h, h->r.p, n, 1.0);
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        {
+            std::shared_lock<std::shared_mutex> cap(g_capture_mu); // no free or sync meanwhile
+            HIPC(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int c = 0; c < cycles; ++c) {
+                    if (mixed) vcycle<float>(h, h->lv[0].b32.p, h->lv[0].x32.p, true);
+                    else vcycle<double>(h, h->r.p, h->x0.p, true);
+                }
+            } catch (...) {
+                hipGraph_t g2 = nullptr;
+                (void)hipStreamEndCapture(h->stream, &g2);
+                if (g2) (void)hipGraphDestroy(g2);
+                throw;
+            }
+            HIPC(hipStreamEndCapture(h->stream, &g));
+        }
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPC(e);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float ms = 0.f;
+        hipError_t err = hipEventCreate(&e0);
+        if (err == hipSuccess) err = hipEventCreate(&e1);
+        if (err == hipSuccess) err = hipGraphLaunch(ex, h->stream);
+        if (err == hipSuccess) err = hipEventRecord(e0, h->stream);
+        for (int i = 0; i < reps && err == hipSuccess; ++i) err = hipGraphLaunch(ex, h->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, h->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipStreamSynchronize(h->stream);
+        {
+            MemLock lk(g_capture_mu); // graph teardown
+            (void)hipGraphExecDestroy(ex);
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        HIPC(err);
+        *us_per_cycle = (double)ms * 1e3 / ((double)reps * cycles);
+    });
+}
+
 cps_status cps_divergence(cps_handle* h, const double* u, double* rhs)
 {
     return guarded([&] {

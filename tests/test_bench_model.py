@@ -104,5 +104,11 @@ def test_vcycle_rate_reports_cycles_per_solve(bench):
     assert out["bytes_per_cycle"] == bench.vcycle_bytes(levels, 8)
     assert out["avg_us"] == pytest.approx(930.0)
     assert out["frac_of_peak"] == pytest.approx(out["bytes_per_cycle"] / 930e-6 / 1e9 / 8000.0)
+    # with the graph-replayed time: the rate is on it, the eager span beside it
+    g = bench.vcycle_rate(prof, levels, 8, 2, graph_us=800.0)
+    assert g["avg_us"] == pytest.approx(800.0)
+    assert g["frac_of_peak"] == pytest.approx(g["bytes_per_cycle"] / 800e-6 / 1e9 / 8000.0)
+    assert g["eager_avg_us"] == pytest.approx(930.0)
+    assert g["eager_frac_of_peak"] == pytest.approx(out["frac_of_peak"])
     prof[vc] = (0.0, 0)
     assert bench.vcycle_rate(prof, levels, 8, 2) is None

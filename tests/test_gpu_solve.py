@@ -198,6 +198,39 @@ def test_profile_classes_and_grouped_colour_passes():
     assert np.array_equal(x0, x1)
 
 
+@pytest.mark.parametrize("precision,smoother", [(0, 0), (1, 0), (0, 1)])
+def test_time_vcycle(precision, smoother):
+    """cps_time_vcycle replays captured V-cycles: a positive time per cycle,
+    a solve after it gives the same bits as before it, and the argument
+    checks (null stream, cycles or reps < 1, profiling on) fail cleanly."""
+    g = Shell(16, 16, 64, radial_stretch=2.0)
+    b = dev(inputs.smoothed_noise(g.shape, 17)).flatten()
+    stream = torch.cuda.Stream()
+    s = cps.Solver(g, precision=precision, accel=1, smoother=smoother, stream=stream)
+    try:
+        x0 = host(s.solve(b).p)
+        us = s.time_vcycle(cycles=4, reps=3)
+        x1 = host(s.solve(b).p)
+        for cycles, reps in ((0, 1), (1, 0)):
+            with pytest.raises(cps.CpsError):
+                cps.cps_time_vcycle(s.h, cycles, reps)
+        cps.cps_profile_enable(s.h, True)
+        with pytest.raises(cps.CpsError):
+            cps.cps_time_vcycle(s.h, 1, 1)
+        cps.cps_profile_enable(s.h, False)
+    finally:
+        s.close()
+    log("time_vcycle", precision, smoother, f"{us:.1f} us")
+    assert 0 < us < 1e5
+    assert np.array_equal(x0, x1)
+    s = cps.Solver(g, precision=0, accel=1)  # the null stream
+    try:
+        with pytest.raises(cps.CpsError):
+            cps.cps_time_vcycle(s.h, 1, 1)
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("tol", [1e-10, 1e-13], ids=["tol1e-10", "tol1e-13"])
 @pytest.mark.parametrize("precision,accel", [(0, 0), (0, 1), (1, 1), (0, 2)])
 def test_reported_residual_is_that_of_the_answer(precision, accel, tol):
