@@ -80,6 +80,7 @@ struct BatchGroup {
     std::vector<int> probs;
     int Lmax = 0;
     ItemTable gs[kMaxLevels], res[kMaxLevels], xfer[kMaxLevels], fill[kMaxLevels];
+    ItemTable tile[kMaxLevels]; // problems whose level takes the tile path: its tiles
     ItemTable pfwd[kMaxLevels][2], ptri[kMaxLevels][2]; // plane half-sweeps by parity
     ItemTable coarse, apply, vred, elem;
     hipGraphExec_t gA = nullptr, gB = nullptr;
@@ -120,6 +121,15 @@ void blaunch(cps_batch* B, const ItemTable& t, K kernel, A... args)
 {
     if (!t.count) return;
     kernel<<<t.count, kBlock, 0, B->stream>>>(t.d.p, B->active.p, B->pd.p, args...);
+    LAUNCH_CHECK();
+}
+
+// the same for the tile kernels' larger blocks
+template <typename K, typename... A>
+void blaunch_tile(cps_batch* B, const ItemTable& t, K kernel, A... args)
+{
+    if (!t.count) return;
+    kernel<<<t.count, kTileThreads, 0, B->stream>>>(t.d.p, B->active.p, B->pd.p, args...);
     LAUNCH_CHECK();
 }
 
@@ -181,6 +191,8 @@ void b_smooth(cps_batch* B, BatchGroup& G, int l, bool reverse, bool from_zero)
 void b_vcycle(cps_batch* B, BatchGroup& G)
 {
     for (int l = 0; l + 1 < G.Lmax; ++l) {
+        // problems whose level l takes the tile path (as vcycle() does)
+        blaunch_tile(B, G.tile[l], kb_vpre_tile<float>, l);
         if (!G.gs[l].count) continue;
         b_smooth(B, G, l, false, true);
         // as vcycle(): after point red-black smoothing, the red residual on
@@ -193,6 +205,7 @@ void b_vcycle(cps_batch* B, BatchGroup& G)
     }
     blaunch(B, G.coarse, kb_coarse<float>);
     for (int l = G.Lmax - 2; l >= 0; --l) {
+        blaunch_tile(B, G.tile[l], kb_vpost_tile<float>, l);
         if (!G.gs[l].count) continue;
         blaunch(B, G.xfer[l], kb_prolong<float>, l);
         b_smooth(B, G, l, true, false);
@@ -308,6 +321,8 @@ PDesc<float> make_desc(cps_handle* h)
     for (int l = 0; l < h->L; ++l) {
         const LevelMem& m = h->lv[l];
         d.lv[l] = LDesc<float>{m.geo, m.G32.p, m.gk, m.x32.p, m.b32.p, m.r32.p, m.gs_ch};
+        d.lv[l].tile = m.tile ? 1 : 0;
+        d.lv[l].xt = m.xt32.p;
         if (h->opts.smoother == 1 && l + 1 < h->L) {
             d.lv[l].ptw = reinterpret_cast<const Vec2<float>*>(m.tw32.p);
             d.lv[l].ptwN = reinterpret_cast<const Vec2<float>*>(m.twN32.p);
@@ -326,11 +341,15 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
     G.Lmax = 0;
     for (int p : G.probs) G.Lmax = std::max(G.Lmax, B->h[p]->L);
     for (int l = 0; l + 1 < G.Lmax; ++l) {
-        PG gs, res, xf, fl;
+        PG gs, res, xf, fl, tl;
         for (int p : G.probs) {
             cps_handle* h = B->h[p];
             if (l + 1 >= h->L) continue;
             const Geo& g = h->lv[l].geo;
+            if (h->lv[l].tile) {
+                tl.push_back({p, tile_count(g)});
+                continue;
+            }
             if (G.march) {
                 gs.push_back({p, gs_shape<float>(g, h->lv[l].gs_ch).grid});
                 res.push_back({p, stencil_shape(g).grid});
@@ -345,6 +364,7 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
         build_items(G.res[l], res);
         build_items(G.xfer[l], xf);
         build_items(G.fill[l], fl);
+        build_items(G.tile[l], tl);
         if (G.plane)
             for (int k = 0; k < 2; ++k) {
                 PG pf, pt;

@@ -12,6 +12,7 @@
 #include "plane.hpp"
 #include "project.hpp"
 #include "lines.hpp"
+#include "tile.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -172,6 +173,11 @@ struct LevelMem {
     Buf<float> G32;
     Buf<double> x64, b64, r64;
     Buf<float> x32, b32, r32;
+    // small levels of the point smoother (tile.hpp): the V-cycle's work on
+    // the level is two launches; the post-smoothed iterate goes to xt
+    bool tile = false;
+    Buf<double> xt64;
+    Buf<float> xt32;
     int gs_ch = 0; // marching chunk of the colour pass (0 = default; autotuned)
     // plane smoother's launch shapes (0 = default; autotuned): rings per
     // block of the transforms, r-steps in flight per lane of the elimination
@@ -271,6 +277,18 @@ template <>
 double* rl<double>(cps_handle* h, int l) { return h->lv[l].r64.p; }
 template <>
 float* rl<float>(cps_handle* h, int l) { return h->lv[l].r32.p; }
+template <typename T>
+T* xtl(cps_handle* h, int l);
+template <>
+double* xtl<double>(cps_handle* h, int l) { return h->lv[l].xt64.p; }
+template <>
+float* xtl<float>(cps_handle* h, int l) { return h->lv[l].xt32.p; }
+// where level l's iterate is after its post-smoothing (l > 0)
+template <typename T>
+T* xfin(cps_handle* h, int l)
+{
+    return h->lv[l].tile ? xtl<T>(h, l) : xl<T>(h, l);
+}
 
 // Brackets one finest-level launch of kernel class k with two events on the
 // handle's stream (no-op unless profiling is enabled).
@@ -613,6 +631,27 @@ void coarse_solve(cps_handle* h, const T* b, T* e)
     LAUNCH_CHECK();
 }
 
+// The tile path of a small level (tile.hpp): pre-smoothing from zero,
+// residual and restriction into bc; prolongation of e and post-smoothing
+// from xi into xo.
+template <typename T>
+void vpre_tile(cps_handle* h, int l, const T* b, T* x, T* bc)
+{
+    const Level<T> L = view<T>(h, l);
+    k_vpre_tile<T><<<tile_count(L.g), kTileThreads, 0, h->stream>>>(L.g, L.G, L.gk, b, x,
+                                                                     h->lv[l + 1].geo, bc);
+    LAUNCH_CHECK();
+}
+
+template <typename T>
+void vpost_tile(cps_handle* h, int l, const T* b, const T* xi, T* xo, const T* e)
+{
+    const Level<T> L = view<T>(h, l);
+    k_vpost_tile<T><<<tile_count(L.g), kTileThreads, 0, h->stream>>>(L.g, L.G, L.gk, b, xi, xo,
+                                                                      h->lv[l + 1].geo, e);
+    LAUNCH_CHECK();
+}
+
 // One V(2,2) cycle with level-0 right-hand side b0 and iterate x0 (in place).
 // dot: the last level-0 passes leave partial sums of b0 . x0 in h->partial;
 // returns their number (0 when the cycle cannot provide them).
@@ -627,6 +666,10 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
     for (int l = 0; l < L - 1; ++l) {
         const T* b = l == 0 ? b0 : bl<T>(h, l);
         T* x = l == 0 ? x0 : xl<T>(h, l);
+        if (h->lv[l].tile) { // smoothing, residual and restriction in one launch
+            vpre_tile<T>(h, l, b, x, bl<T>(h, l + 1));
+            continue;
+        }
         // coarse corrections start from zero
         smooth<T>(h, l, b, x, 2, false, l > 0 || x0_zero);
         // point red-black smoothing ends on the black pass: on row-pair
@@ -640,7 +683,12 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
     for (int l = L - 2; l >= 0; --l) {
         const T* b = l == 0 ? b0 : bl<T>(h, l);
         T* x = l == 0 ? x0 : xl<T>(h, l);
-        prolong_add<T>(h, l, xl<T>(h, l + 1), x);
+        const T* e = l + 1 == L - 1 ? xl<T>(h, l + 1) : xfin<T>(h, l + 1);
+        if (h->lv[l].tile) { // prolongation and smoothing in one launch, into xt
+            vpost_tile<T>(h, l, b, x, xtl<T>(h, l), e);
+            continue;
+        }
+        prolong_add<T>(h, l, e, x);
         const bool d = dot && l == 0 && marching(h);
         parts = smooth<T>(h, l, b, x, 2, true, false, d ? h->partial.p : nullptr);
     }
@@ -1186,6 +1234,16 @@ void build(cps_handle* h)
     }
     if (h->opts.smoother == 2) h->opts.smoother = plane_eligible(h) ? 1 : 0; // automatic
     if (h->opts.smoother == 1) setup_plane(h);
+    // small levels of the point smoother run the tile path (not the finest:
+    // its passes also give the Krylov dot products; not the coarsest: it is
+    // solved directly)
+    for (int l = 1; l + 1 < h->L; ++l) {
+        LevelMem& m = h->lv[l];
+        m.tile = marching(h) && h->ncol == 2 && h->opts.smoother == 0 && tile_fits(m.geo);
+        if (!m.tile) continue;
+        if (mixed) m.xt32.alloc(m.n);
+        else m.xt64.alloc(m.n);
+    }
     autotune(h, h->opts.tune);
     HIPC(hipStreamSynchronize(h->stream));
 }
@@ -1198,6 +1256,7 @@ void destroy(cps_handle* h)
         LevelMem& m = h->lv[l];
         m.G64.release(); m.G32.release();
         m.x64.release(); m.b64.release(); m.r64.release();
+        m.xt64.release(); m.xt32.release();
         m.x32.release(); m.b32.release(); m.r32.release();
     }
     h->Ainv.release(); h->partial.release(); h->sc.release();

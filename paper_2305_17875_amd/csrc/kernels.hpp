@@ -1881,8 +1881,18 @@ __device__ __forceinline__ void d_coarse_gemv(Blk bk, int n, const double* __res
     const int row = bk.L * (kBlock / 64) + (threadIdx.x >> 6);
     if (row >= n) return;
     const double* Ar = Ainv + (long long)row * n;
-    double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc += Ar[j] * ((double)bv[j] - mu);
+    // four accumulators: each lane's loads of a row go out together instead
+    // of one after another on a single dependent sum
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = lane;
+    for (; j + 192 < n; j += 256) {
+        a0 += Ar[j] * ((double)bv[j] - mu);
+        a1 += Ar[j + 64] * ((double)bv[j + 64] - mu);
+        a2 += Ar[j + 128] * ((double)bv[j + 128] - mu);
+        a3 += Ar[j + 192] * ((double)bv[j + 192] - mu);
+    }
+    for (; j < n; j += 64) a0 += Ar[j] * ((double)bv[j] - mu);
+    double acc = (a0 + a1) + (a2 + a3);
     acc = wave_sum(acc);
     if (lane == 0) e[row] = (T)acc;
 }
@@ -2302,6 +2312,10 @@ struct LDesc {
     const T* ppiv;
     Vec2<T>* pS;
     int prb; // rings per block of the transforms (autotuned)
+    // small levels of the point smoother (tile.hpp): the post-smoothed
+    // iterate goes to xt
+    int tile;
+    T* xt;
 };
 
 template <typename T>
@@ -2401,8 +2415,8 @@ __global__ void __launch_bounds__(kBlock) kb_prolong(const BItem* __restrict__ i
     CPS_BATCH_BLOCK
     const PDesc<T>& P = pd[it.prob];
     const MarchShape ms = march_shape(P.lv[level + 1].g);
-    d_prolong<T>(bk, P.lv[level].g, P.lv[level + 1].g, ms.bpa, ms.ch, P.lv[level + 1].x,
-                 P.lv[level].x);
+    const LDesc<T>& c = P.lv[level + 1];
+    d_prolong<T>(bk, P.lv[level].g, c.g, ms.bpa, ms.ch, c.tile ? c.xt : c.x, P.lv[level].x);
 }
 
 template <typename T>

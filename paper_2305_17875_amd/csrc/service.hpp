@@ -69,7 +69,7 @@ size_t handle_bytes(const cps_handle* h)
     for (int l = 0; l < h->L; ++l) {
         const LevelMem& m = h->lv[l];
         add(m.G64); add(m.G32); add(m.x64); add(m.b64); add(m.r64);
-        add(m.x32); add(m.b32); add(m.r32);
+        add(m.x32); add(m.b32); add(m.r32); add(m.xt64); add(m.xt32);
     }
     add(h->Ainv); add(h->partial); add(h->sc);
     add(h->x0); add(h->b0); add(h->r); add(h->z); add(h->pd); add(h->q);
@@ -100,6 +100,8 @@ size_t estimate_bytes(const cps_grid& g, const cps_opts& o)
         s += 9 * gk * 8;
         if (mixed) s += 9 * gk * 4 + n * 4 * (l + 1 < L ? 3 : 2);
         else s += n * 8 * ((l > 0 ? 2 : 0) + (l + 1 < L ? 1 : 0));
+        // the tile path's second iterate (small levels, point smoother)
+        if (l > 0 && l + 1 < L && n <= (size_t)kTileMaxCells) s += n * (mixed ? 4 : 8);
     }
     const size_t n0 = (size_t)g.n_r * g.n_theta * g.n_phi;
     const size_t nc = (size_t)dims[L - 1][0] * dims[L - 1][1] * dims[L - 1][2];
