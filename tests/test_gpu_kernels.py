@@ -36,6 +36,12 @@ CASES = [
     # coarse rings of 128 phi pairs: two wavefronts per coarse row, so the
     # restriction's outer phi values cross a wavefront boundary inside a ring
     ("sphere-wide-8x8x512", Shell(8, 8, 512), 0),
+    # the V-cycle's tile path: level 1 (12 x 10 x 32) in ragged 8^3 tiles
+    # (r and theta) and four tiles around phi; then two tile levels in a row
+    # (24 x 16 x 32 and 12 x 8 x 16), the second's post-smoothed iterate
+    # being the first's coarse correction, and a ring of two tiles
+    ("sphere-tiles-24x20x64", Shell(24, 20, 64, radial_stretch=2.0), 0),
+    ("sphere-tiles-48x32x64", Shell(48, 32, 64), 0),
     # coarse rows of 64 phi pairs in groups of four: the restriction shares
     # its theta rows between the wavefronts of a block through LDS (two row
     # groups, mirrored rows at both theta walls)
