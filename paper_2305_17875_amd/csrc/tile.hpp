@@ -159,13 +159,26 @@ __device__ __forceinline__ void d_vpre_tile(Blk bk, Geo f, const T* __restrict__
     tile_origin(f, (int)bk.L, A0, B0, C0);
     const int ra = A0 - H, rb = B0 - H, rc = C0 - H;
     const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
-    for (int i = tid; i < R * R * R; i += nt) {
+    // every load of a thread goes out before any is stored (a loop that
+    // stores each value before the next load waits on every one in turn)
+    constexpr int NL = (R * R * R + kTileThreads - 1) / kTileThreads;
+    T v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = tid + k * kTileThreads;
         const int cc = i % R, bb = (i / R) % R, aa = i / (R * R);
         const int a = ra + aa, b = rb + bb;
-        T v = T(0);
-        if (a >= 0 && a < f.nr && b >= 0 && b < f.nt) v = bv[tile_at(f, a, b, wrapi(rc + cc, f.np))];
-        sh.b[i] = v;
-        sh.x[i] = T(0);
+        v[k] = T(0);
+        if (i < R * R * R && a >= 0 && a < f.nr && b >= 0 && b < f.nt)
+            v[k] = bv[tile_at(f, a, b, wrapi(rc + cc, f.np))];
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = tid + k * kTileThreads;
+        if (i < R * R * R) {
+            sh.b[i] = v[k];
+            sh.x[i] = T(0);
+        }
     }
     for (int i = tid; i < R * R; i += nt) {
         const int a = ra + i / R, b = rb + i % R;
@@ -261,10 +274,35 @@ __device__ __forceinline__ void d_vpost_tile(Blk bk, Geo f, const T* __restrict_
     // coarse box: I = A0/2 - 3 .. A0/2 + 6 (rows and planes clamped, phi wrapped)
     const int ea = A0 / 2 - 3, eb = B0 / 2 - 3, ec = C0 / 2 - 3;
     const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
-    for (int i = tid; i < E * E * E; i += nt) {
+    // loads before stores, as in pre
+    constexpr int NE = (E * E * E + kTileThreads - 1) / kTileThreads;
+    constexpr int NX = (R * R * R + kTileThreads - 1) / kTileThreads;
+    T ev[NE], xv[NX], bw[NX];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int i = tid + k * kTileThreads;
         const int kc = i % E, kb = (i / E) % E, ka = i / (E * E);
-        sh.e[i] = e[tile_at(c, clampi(ea + ka, c.nr - 1), clampi(eb + kb, c.nt - 1),
-                            wrapi(ec + kc, c.np))];
+        ev[k] = i < E * E * E ? e[tile_at(c, clampi(ea + ka, c.nr - 1), clampi(eb + kb, c.nt - 1),
+                                           wrapi(ec + kc, c.np))]
+                              : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+        const int i = tid + k * kTileThreads;
+        const int cc = i % R, bb = (i / R) % R, aa = i / (R * R);
+        const int a = ra + aa, b = rb + bb;
+        xv[k] = T(0);
+        bw[k] = T(0);
+        if (i < R * R * R && a >= 0 && a < f.nr && b >= 0 && b < f.nt) {
+            const long long o = tile_at(f, a, b, wrapi(rc + cc, f.np));
+            xv[k] = xi[o];
+            bw[k] = bv[o];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int i = tid + k * kTileThreads;
+        if (i < E * E * E) sh.e[i] = ev[k];
     }
     for (int i = tid; i < R * R; i += nt) {
         const int a = ra + i / R, b = rb + i % R;
@@ -274,13 +312,14 @@ __device__ __forceinline__ void d_vpost_tile(Blk bk, Geo f, const T* __restrict_
     }
     __syncthreads();
     const T w0 = T(0.75), w1 = T(0.25);
-    for (int i = tid; i < R * R * R; i += nt) {
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+        const int i = tid + k * kTileThreads;
+        if (i >= R * R * R) continue;
         const int cc = i % R, bb = (i / R) % R, aa = i / (R * R);
         const int a = ra + aa, b = rb + bb, cg = rc + cc;
-        T xv = T(0), bvv = T(0);
+        T xn = T(0);
         if (a >= 0 && a < f.nr && b >= 0 && b < f.nt) {
-            const long long o = tile_at(f, a, b, wrapi(cg, f.np));
-            bvv = bv[o];
             // fine 2I takes 3/4 of coarse I and 1/4 of I - 1, fine 2I + 1 of
             // I and I + 1, in each direction: theta, then phi, then r
             const int I = a >> 1, J = b >> 1, K = cg >> 1; // cg may be negative: floor
@@ -297,10 +336,10 @@ __device__ __forceinline__ void d_vpost_tile(Blk bk, Geo f, const T* __restrict_
                 }
                 tr[pa] = w0 * tp[0] + w1 * tp[1];
             }
-            xv = xi[o] + (w0 * tr[0] + w1 * tr[1]);
+            xn = xv[k] + (w0 * tr[0] + w1 * tr[1]);
         }
-        sh.x[i] = xv;
-        sh.b[i] = bvv;
+        sh.x[i] = xn;
+        sh.b[i] = bw[k];
     }
     __syncthreads();
     // colours 1, 0, 1, 0, each on a region one cell smaller
