@@ -127,7 +127,7 @@ def plane_half_sweep_bytes(shape, word):
 PROF_STEPS = 2
 
 
-def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
+def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0, graph_vcycle=True):
     """The timed solves run on a stream of the solver's own, as a user would
     set it up.  Inside the timed region HIP events are recorded on that
     stream around every launch of the finest-level smoothing pass only (the
@@ -164,12 +164,14 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
         iters.append(res.iterations)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    log(f"precision={precision} smoother={smoother}: timed solves done")
     timed_gs = cps.cps_profile_read(s.h, cps.KERNEL_GS)
     cps.cps_profile_select(s.h, None)
     for k in range(len(KNAMES)):
         cps.cps_profile_read(s.h, k)
     for i in range(PROF_STEPS):
         s.solve(rhs, TOL, out=p)
+        log(f"profiled solve {i + 1}/{PROF_STEPS} (every finest-level class) done")
     prof = {k: cps.cps_profile_read(s.h, k) for k in range(len(KNAMES))}
     # the V-cycle span from solves with events around the cycles only: the
     # events around the finest-level kernels inside a cycle add ~4% to it
@@ -177,13 +179,18 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0):
     cps.cps_profile_select(s.h, [vc])
     for i in range(PROF_STEPS):
         s.solve(rhs, TOL, out=p)
+        log(f"profiled solve {i + 1}/{PROF_STEPS} (V-cycle spans) done")
     prof[vc] = cps.cps_profile_read(s.h, vc)
     cps.cps_profile_select(s.h, None)
     cps.cps_profile_enable(s.h, False)
     # the V-cycle as the solve runs it: replayed from a hipGraph (the spans
-    # above launch every kernel from the host, as profiling requires)
-    vcycle_graph_us = s.time_vcycle(cycles=10, reps=5)
-    torch.cuda.synchronize()
+    # above launch every kernel from the host, as profiling requires); only
+    # where the line reports the cycle's rate
+    vcycle_graph_us = None
+    if graph_vcycle:
+        vcycle_graph_us = s.time_vcycle(cycles=10, reps=5)
+        torch.cuda.synchronize()
+        log(f"graph-replayed V-cycle: {vcycle_graph_us:.1f} us")
     log(f"precision={precision} smoother={smoother}: {dt * 1e3:.1f} ms/solve, iterations={iters}, "
         f"rel_residual={res.rel_residual:.3e}")
     return dict(solver=s, p=p, host_p=p.cpu().numpy().reshape(g.shape), res=res, sec=dt,
@@ -257,7 +264,8 @@ def plane_form(cps, torch, g, rhs, x64, steps, warmup, answers):
     out = {"smoother": "zebra (r,phi)-plane block Gauss-Seidel: FFT along phi, "
                        "Thomas along r per mode; V(2,2), PCG"}
     for precision, key, word in ((0, "fp64", 8), (1, "mixed", 4)):
-        f = run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=1)
+        f = run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=1,
+                     graph_vcycle=False)
         answers[("plane", key)] = f["host_p"]
         hs_ms, hs_n = f["timed_gs"]  # HIP events over the timed region
         hs_s = hs_ms / max(hs_n, 1) * 1e-3
@@ -310,10 +318,12 @@ def project_form(cps, torch, inputs, g, steps, warmup):
             torch.cuda.synchronize()
             total += time.perf_counter() - t0
             its.append(r.iterations)
+        log(f"project {key}: timed steps done")
         u.copy_(u0)
         torch.cuda.synchronize()
         cps.cps_profile_enable(s.h, True)
         s.project(u, TOL, phi=phi)
+        log(f"project {key}: profiled step done")
         prof = {k: cps.cps_profile_read(s.h, k) for k in range(len(KNAMES))}
         cps.cps_profile_enable(s.h, False)
         dt = total / steps

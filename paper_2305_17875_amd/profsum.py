@@ -5,8 +5,9 @@
         [--plane-md plane.md --plane-traffic plane.json]
 
 --kt     database of `rocprofv3 --kernel-trace --stats -- python3 bench.py ...`
---fetch  database of `rocprofv3 --pmc FETCH_SIZE -- python3 bench.py ...`
---write  database of `rocprofv3 --pmc WRITE_SIZE -- python3 bench.py ...`
+--fetch  database(s) of `rocprofv3 --pmc FETCH_SIZE -- python3 bench.py ...`
+--write  database(s) of `rocprofv3 --pmc WRITE_SIZE -- python3 bench.py ...`
+         (several runs, e.g. one per bench form, are merged kernel by kernel)
 
 Counter values (KiB per dispatch) are scaled by what the same counter reads
 on the library's plain copy kernel (k_copy) over 192*256*512 doubles
@@ -48,13 +49,14 @@ def durations(db):
     return agg
 
 
-def counters(db):
-    c = sqlite3.connect(db)
-    rows = c.execute("select kernel_name, grid_size, counter_name, value "
-                     "from counters_collection").fetchall()
+def counters(dbs):
     agg = collections.defaultdict(list)
-    for n, g, cn, v in rows:
-        agg[(short(n), g, cn)].append(v)
+    for db in dbs:
+        c = sqlite3.connect(db)
+        rows = c.execute("select kernel_name, grid_size, counter_name, value "
+                         "from counters_collection").fetchall()
+        for n, g, cn, v in rows:
+            agg[(short(n), g, cn)].append(v)
     return agg
 
 
@@ -65,8 +67,8 @@ def mean(v):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--kt", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch", required=True, nargs="+")
+    ap.add_argument("--write", required=True, nargs="+")
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--md", required=True)
     ap.add_argument("--traffic", required=True)
@@ -126,8 +128,8 @@ def main():
         step_summary(a, dur, fe, wr, sf, sw)
 
 
-STEP_KERNELS = ("k_divergence", "k_correct", "k_line_factor", "k_line_open", "k_line_fft",
-                "k_line_periodic")
+STEP_KERNELS = ("k_divergence", "k_divergence2", "k_correct", "k_line_factor", "k_line_open",
+                "k_line_fft", "k_line_periodic")
 
 
 def step_summary(a, dur, fe, wr, sf, sw):
