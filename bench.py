@@ -45,6 +45,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_pass_config2_traffic.json")
 PLANE_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "plane.hpp")
 PLANE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plane_half_sweep_config2_traffic.json")
+VCYCLE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vcycle_config2_fp64_traffic.json")
+TILE_SRC = os.path.join(ROOT, "paper_2305_17875_amd", "csrc", "tile.hpp")
 KNAMES = ["gs_pass", "residual", "apply", "restrict", "prolong", "vcycle", "divergence",
           "correct"]
 GS_KERNEL = "k_gs_march2<double, 0, 0>"
@@ -209,7 +211,7 @@ def kernel_table(prof, steps):
     return out
 
 
-def vcycle_rate(prof, levels, word, steps, graph_us=None):
+def vcycle_rate(prof, levels, word, steps, graph_us=None, traffic=None):
     """HBM rate of the preconditioning V-cycle: the byte model of
     vcycle_bytes over the time of one cycle.  graph_us: the cycle replayed
     from a hipGraph as the solve runs it (cps_time_vcycle), the rate's
@@ -230,6 +232,12 @@ def vcycle_rate(prof, levels, word, steps, graph_us=None):
     if graph_us:
         out["eager_avg_us"] = eager * 1e6
         out["eager_frac_of_peak"] = b / eager / 1e9 / HBM_PEAK_GBS
+    # the bytes the counters saw in one cycle (halo re-reads included) over
+    # the same time: the sustained HBM rate
+    out["traffic"] = None if traffic is None else {
+        "bytes_per_cycle": traffic, "achieved_GBs": traffic / t / 1e9,
+        "frac_of_peak": traffic / t / 1e9 / HBM_PEAK_GBS,
+        "source": os.path.relpath(VCYCLE_TRAFFIC_FILE, ROOT)}
     return out
 
 
@@ -750,6 +758,21 @@ def serve_form(cps, inputs, duration, rate, slots, budget_gib, comparator_s, smo
     return out
 
 
+def vcycle_traffic():
+    """Counter bytes of one FP64 V-cycle (profiles/), if they were taken on
+    the current kernel sources (kernels.hpp and tile.hpp)."""
+    try:
+        d = json.load(open(VCYCLE_TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, TILE_SRC):
+        h.update(open(path, "rb").read())
+    if d.get("source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return d.get("bytes_per_cycle")
+
+
 def traffic_for(kh):
     """Per-launch HBM bytes of the finest-level colour pass from the counter
     summary, if it was taken on this kernel source."""
@@ -847,7 +870,7 @@ def main():
                      "frac_of_copy": achieved / copy_gbs if copy_gbs else None},
         "kernels_fp64": kernel_table(f64["prof"], f64["prof_steps"]),
         "vcycle_fp64": vcycle_rate(f64["prof"], s64.levels, 8, f64["prof_steps"],
-                                   f64["vcycle_graph_us"]),
+                                   f64["vcycle_graph_us"], vcycle_traffic()),
     }
     x64 = f64["p"]
     answers = {("fp64",): f64["host_p"]}  # GPU answers, compared with the oracle's exact one

@@ -30,6 +30,7 @@ import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(HERE, "csrc", "kernels.hpp")
+TILE_SRC = os.path.join(HERE, "csrc", "tile.hpp")
 PLANE_SRC = os.path.join(HERE, "csrc", "plane.hpp")
 PLANE_KERNELS = ("k_plane_fwd", "k_plane_tri", "k_plane_inv")
 COPY_BYTES = 192 * 256 * 512 * 8
@@ -76,6 +77,7 @@ def main():
     ap.add_argument("--plane-md")
     ap.add_argument("--plane-traffic")
     ap.add_argument("--step-md", help="projection step and ADI line-solve kernels")
+    ap.add_argument("--vcycle-traffic", help="counter bytes of one FP64 V-cycle (JSON)")
     a = ap.parse_args()
     kh = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
     dur = durations(a.kt)
@@ -126,6 +128,54 @@ def main():
         plane_summary(a, dur, fe, wr, sf, sw)
     if a.step_md:
         step_summary(a, dur, fe, wr, sf, sw)
+    if a.vcycle_traffic:
+        vcycle_traffic(a, fe, wr, sf, sw)
+
+
+def vcycle_sources_hash() -> str:
+    h = hashlib.sha256()
+    for path in (KERNEL_SRC, TILE_SRC):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def vcycle_traffic(a, fe, wr, sf, sw):
+    """HBM bytes of one FP64 preconditioning V-cycle by the counters: the
+    kernels of one cycle as the kernel trace shows it (from a zero-iterate
+    finest-level pass to the next, with no outer-iteration kernel between:
+    a cycle of the graph replays that time it), each at its mean FETCH_SIZE
+    and WRITE_SIZE per dispatch."""
+    c = sqlite3.connect(a.kt)
+    rows = [(short(n), s, g) for n, s, g in
+            c.execute("select name, start, grid_x from kernels order by start")]
+    starts = [i for i, r in enumerate(rows) if r[0] == "k_gs_march2<double, 0, 1>"]
+    outer = ("k_apply", "k_cg", "k_reduce", "k_cast", "k_dot", "k_copy")
+    best = None
+    for i0, i1 in zip(starts, starts[1:]):
+        cyc = rows[i0:i1]
+        if any(n.startswith(outer) for n, _, _ in cyc):
+            continue
+        span = (rows[i1][1] - rows[i0][1]) / 1e3
+        if best is None or span < best[0]:
+            best = (span, cyc)
+    if best is None:
+        raise SystemExit("no bare V-cycle in the kernel trace")
+    span, cyc = best
+    total = 0.0
+    for n, _, g in cyc:
+        f = fe.get((n, g, "FETCH_SIZE"))
+        w = wr.get((n, g, "WRITE_SIZE"))
+        if not f or not w:
+            raise SystemExit(f"no counters for {n} grid {g}")
+        total += mean(f) * 1024 * sf + mean(w) * 1024 * sw
+    out = {"what": "HBM bytes of one FP64 V-cycle of the paper-scale shell by FETCH_SIZE "
+                   "and WRITE_SIZE (scaled by the copy kernel), over the kernels of one "
+                   "graph-replayed cycle",
+           "bytes_per_cycle": total, "kernels_per_cycle": len(cyc),
+           "trace_span_us": span, "fetch_scale": sf, "write_scale": sw,
+           "source_sha256_16": vcycle_sources_hash()}
+    json.dump(out, open(a.vcycle_traffic, "w"), indent=1)
+    print(json.dumps(out, indent=1))
 
 
 STEP_KERNELS = ("k_divergence", "k_divergence2", "k_correct", "k_line_factor", "k_line_open",

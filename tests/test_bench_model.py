@@ -110,5 +110,24 @@ def test_vcycle_rate_reports_cycles_per_solve(bench):
     assert g["frac_of_peak"] == pytest.approx(g["bytes_per_cycle"] / 800e-6 / 1e9 / 8000.0)
     assert g["eager_avg_us"] == pytest.approx(930.0)
     assert g["eager_frac_of_peak"] == pytest.approx(out["frac_of_peak"])
+    assert g["traffic"] is None
+    # with the counters' bytes of one cycle: their rate over the same time
+    t = bench.vcycle_rate(prof, levels, 8, 2, graph_us=800.0, traffic=3.9e9)
+    assert t["traffic"]["achieved_GBs"] == pytest.approx(3.9e9 / 800e-6 / 1e9)
+    assert t["traffic"]["frac_of_peak"] == pytest.approx(3.9e9 / 800e-6 / 1e9 / 8000.0)
     prof[vc] = (0.0, 0)
     assert bench.vcycle_rate(prof, levels, 8, 2) is None
+
+
+def test_vcycle_traffic_follows_the_kernel_sources(bench, tmp_path, monkeypatch):
+    """The committed counter bytes of a V-cycle are used only while the hash
+    of the kernel sources they were taken on matches."""
+    got = bench.vcycle_traffic()
+    import json
+    d = json.load(open(bench.VCYCLE_TRAFFIC_FILE))
+    assert got == d["bytes_per_cycle"] and 3e9 < got < 5e9
+    bad = dict(d, source_sha256_16="0" * 16)
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps(bad))
+    monkeypatch.setattr(bench, "VCYCLE_TRAFFIC_FILE", str(f))
+    assert bench.vcycle_traffic() is None
