@@ -120,14 +120,18 @@ def test_vcycle_rate_reports_cycles_per_solve(bench):
 
 
 def test_vcycle_traffic_follows_the_kernel_sources(bench, tmp_path, monkeypatch):
-    """The committed counter bytes of a V-cycle are used only while the hash
-    of the kernel sources they were taken on matches."""
-    got = bench.vcycle_traffic()
+    """Counter bytes of a V-cycle are used only while the hash of the kernel
+    sources they were taken on (kernels.hpp, then tile.hpp) matches."""
+    import hashlib
     import json
-    d = json.load(open(bench.VCYCLE_TRAFFIC_FILE))
-    assert got == d["bytes_per_cycle"] and 3e9 < got < 5e9
-    bad = dict(d, source_sha256_16="0" * 16)
+    h = hashlib.sha256()
+    for path in (bench.KERNEL_SRC, bench.TILE_SRC):
+        h.update(open(path, "rb").read())
     f = tmp_path / "t.json"
-    f.write_text(json.dumps(bad))
     monkeypatch.setattr(bench, "VCYCLE_TRAFFIC_FILE", str(f))
+    f.write_text(json.dumps({"bytes_per_cycle": 3.9e9, "source_sha256_16": h.hexdigest()[:16]}))
+    assert bench.vcycle_traffic() == 3.9e9
+    f.write_text(json.dumps({"bytes_per_cycle": 3.9e9, "source_sha256_16": "0" * 16}))
+    assert bench.vcycle_traffic() is None
+    f.unlink()
     assert bench.vcycle_traffic() is None
