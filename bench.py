@@ -190,7 +190,7 @@ def run_form(cps, torch, g, rhs, precision, steps, warmup, smoother=0, graph_vcy
     # where the line reports the cycle's rate
     vcycle_graph_us = None
     if graph_vcycle:
-        vcycle_graph_us = s.time_vcycle(cycles=10, reps=5)
+        vcycle_graph_us, _ = s.time_vcycle(cycles=10, reps=5)
         torch.cuda.synchronize()
         log(f"graph-replayed V-cycle: {vcycle_graph_us:.1f} us")
     log(f"precision={precision} smoother={smoother}: {dt * 1e3:.1f} ms/solve, iterations={iters}, "
@@ -438,11 +438,9 @@ def config1_form(cps, torch, inputs, steps, warmup):
             ms, cnt = cps.cps_profile_read(s.h, vc)
             cps.cps_profile_enable(s.h, False)
             entry["vcycle_us_direct_launches"] = ms / max(cnt, 1) * 1e3
-            # the same cycle replayed from a hipGraph, as the solve runs it
-            entry["vcycle_us_graph"] = s.time_vcycle(cycles=10, reps=5)
-            # per smoothed level: 4 pre-passes, residual, restriction,
-            # prolongation, 4 post-passes; then the coarsest solve
-            entry["launches_per_vcycle"] = 11 * (len(s.levels) - 1) + 1
+            # the same cycle replayed from a hipGraph, as the solve runs it,
+            # and the kernel nodes one cycle's graph holds
+            entry["vcycle_us_graph"], entry["launches_per_vcycle"] = s.time_vcycle(cycles=10, reps=5)
         out[key] = entry
         log(f"config1 {key}: {t * 1e3:.2f} ms/solve, {its[-1]} iterations, error {err:.2e}")
         s.close()

@@ -424,12 +424,15 @@ cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_m
  * shapes, from a zero iterate): `cycles` V-cycles are captured into one
  * hipGraph, launched once untimed and then `reps` times between two HIP
  * events on the handle's stream; *us_per_cycle (host) = elapsed time /
- * (reps * cycles).  The input is the handle's finest-level residual vector,
+ * (reps * cycles); *launches_per_cycle (host, may be NULL) = the kernel
+ * nodes of the captured graph / cycles.  The input is the handle's
+ * finest-level residual vector,
  * filled with ones; it and the finest-level iterate are overwritten (the
  * next solve sets both).  Synchronous.  CPS_E_INVALID: a NULL argument,
  * cycles or reps < 1, the handle on the null stream (it cannot be
  * captured), or profiling on (cps_profile_enable). */
-cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* us_per_cycle);
+cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* us_per_cycle,
+                           int64_t* launches_per_cycle);
 /* dst[i] = src[i] for i < n (device FP64, ordered on `stream`, synchronous):
  * a plain copy of known size, the yardstick for the HBM byte counters. */
 cps_status cps_debug_copy(const double* src, double* dst, int64_t n, void* stream);

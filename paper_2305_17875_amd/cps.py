@@ -121,7 +121,7 @@ def lib():
         L.cps_profile_select.argtypes = [P, ctypes.c_uint32]
         L.cps_profile_read.argtypes = [P, I, P, P]
         L.cps_debug_copy.argtypes = [P, P, ctypes.c_int64, P]
-        L.cps_time_vcycle.argtypes = [P, I, I, P]
+        L.cps_time_vcycle.argtypes = [P, I, I, P, P]
         L.cps_divergence.argtypes = [P, P, P]
         L.cps_correct.argtypes = [P, P, P]
         L.cps_project.argtypes = [P, P, P, D, P]
@@ -348,12 +348,13 @@ def cps_profile_read(h, kernel_class: int):
     return ms.value, n.value
 
 
-def cps_time_vcycle(h, cycles: int, reps: int) -> float:
-    """Microseconds per preconditioning V-cycle, replayed from a hipGraph
-    of `cycles` cycles, `reps` launches timed with events."""
+def cps_time_vcycle(h, cycles: int, reps: int):
+    """(microseconds, kernel launches) per preconditioning V-cycle, replayed
+    from a hipGraph of `cycles` cycles, `reps` launches timed with events."""
     us = ctypes.c_double()
-    _check(lib().cps_time_vcycle(h, int(cycles), int(reps), ctypes.byref(us)))
-    return us.value
+    n = ctypes.c_int64()
+    _check(lib().cps_time_vcycle(h, int(cycles), int(reps), ctypes.byref(us), ctypes.byref(n)))
+    return us.value, n.value
 
 
 def cps_debug_copy(src, dst, stream=None):
@@ -419,8 +420,9 @@ class Solver:
         if cur != self.stream:
             cur.wait_stream(self.stream)
 
-    def time_vcycle(self, cycles: int = 10, reps: int = 5) -> float:
-        """Microseconds per V-cycle as the solve replays it (cps_time_vcycle)."""
+    def time_vcycle(self, cycles: int = 10, reps: int = 5):
+        """(microseconds, kernel launches) per V-cycle as the solve replays
+        it (cps_time_vcycle)."""
         cur = self._enter()
         try:
             return cps_time_vcycle(self.h, cycles, reps)

@@ -663,11 +663,15 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
         coarse_solve<T>(h, b0, x0);
         return 0;
     }
+    // the finest level takes the tile path only from a zero iterate (its
+    // pre-smoothing starts from zero): pre writes the scratch iterate xt and
+    // post reads it and writes x0, so no block reads what another overwrote
+    const bool tile0 = h->lv[0].tile && x0_zero;
     for (int l = 0; l < L - 1; ++l) {
         const T* b = l == 0 ? b0 : bl<T>(h, l);
         T* x = l == 0 ? x0 : xl<T>(h, l);
-        if (h->lv[l].tile) { // smoothing, residual and restriction in one launch
-            vpre_tile<T>(h, l, b, x, bl<T>(h, l + 1));
+        if (l == 0 ? tile0 : h->lv[l].tile) { // smoothing, residual, restriction
+            vpre_tile<T>(h, l, b, l == 0 ? xtl<T>(h, 0) : x, bl<T>(h, l + 1));
             continue;
         }
         // coarse corrections start from zero
@@ -684,7 +688,11 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
         const T* b = l == 0 ? b0 : bl<T>(h, l);
         T* x = l == 0 ? x0 : xl<T>(h, l);
         const T* e = l + 1 == L - 1 ? xl<T>(h, l + 1) : xfin<T>(h, l + 1);
-        if (h->lv[l].tile) { // prolongation and smoothing in one launch, into xt
+        if (l == 0 && tile0) { // prolongation and smoothing, xt -> x0 (no dot sums)
+            vpost_tile<T>(h, 0, b, xtl<T>(h, 0), x, e);
+            continue;
+        }
+        if (l > 0 && h->lv[l].tile) { // prolongation and smoothing, into xt
             vpost_tile<T>(h, l, b, x, xtl<T>(h, l), e);
             continue;
         }
@@ -1234,10 +1242,10 @@ void build(cps_handle* h)
     }
     if (h->opts.smoother == 2) h->opts.smoother = plane_eligible(h) ? 1 : 0; // automatic
     if (h->opts.smoother == 1) setup_plane(h);
-    // small levels of the point smoother run the tile path (not the finest:
-    // its passes also give the Krylov dot products; not the coarsest: it is
-    // solved directly)
-    for (int l = 1; l + 1 < h->L; ++l) {
+    // small levels of the point smoother run the tile path (not the
+    // coarsest: it is solved directly; the finest only when the cycle starts
+    // from zero, and then its dot products come from a separate reduction)
+    for (int l = 0; l + 1 < h->L; ++l) {
         LevelMem& m = h->lv[l];
         m.tile = marching(h) && h->ncol == 2 && h->opts.smoother == 0 && tile_fits(m.geo);
         if (!m.tile) continue;
@@ -2127,7 +2135,8 @@ cps_status cps_profile_read(cps_handle* h, int32_t kernel_class, double* total_m
     });
 }
 
-cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* us_per_cycle)
+cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* us_per_cycle,
+                           int64_t* launches_per_cycle)
 {
     return guarded([&] {
         if (!h || !us_per_cycle) fail(CPS_E_INVALID, "NULL argument");
@@ -2156,7 +2165,19 @@ cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* 
             }
             HIPC(hipStreamEndCapture(h->stream, &g));
         }
-        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        int64_t kernels = 0;
+        size_t nodes = 0;
+        hipError_t e = hipGraphGetNodes(g, nullptr, &nodes);
+        if (e == hipSuccess && nodes > 0) {
+            std::vector<hipGraphNode_t> list(nodes);
+            e = hipGraphGetNodes(g, list.data(), &nodes);
+            for (size_t i = 0; i < nodes && e == hipSuccess; ++i) {
+                hipGraphNodeType t;
+                e = hipGraphNodeGetType(list[i], &t);
+                if (e == hipSuccess && t == hipGraphNodeTypeKernel) ++kernels;
+            }
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIPC(e);
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2178,6 +2199,7 @@ cps_status cps_time_vcycle(cps_handle* h, int32_t cycles, int32_t reps, double* 
         if (e1) (void)hipEventDestroy(e1);
         HIPC(err);
         *us_per_cycle = (double)ms * 1e3 / ((double)reps * cycles);
+        if (launches_per_cycle) *launches_per_cycle = kernels / cycles;
     });
 }
 

@@ -43,8 +43,9 @@ constexpr int kResR = kTile + 2;              // residual box: the tile +- 1
 constexpr int kCoarseR = kTile / 2 + 6;       // coarse correction box of post
 
 // A level takes the tile path when it is small enough that its launches
-// dominate, its rings split into whole tiles and it is not the finest (the
-// finest level's passes also form the Krylov dot products).  A tile block
+// dominate and its rings split into whole tiles (the finest level only in
+// cycles from a zero iterate; its Krylov dot products then come from a
+// separate reduction).  A tile block
 // takes 8-12 us (its phases are LDS-latency bound); on the paper-scale
 // shell the 24 x 32 x 64 and 12 x 16 x 32 levels gain (pre + post 21 and
 // 17 us against 46 and 38 us of per-kernel launches), the 48 x 64 x 128
@@ -388,7 +389,8 @@ __global__ void __launch_bounds__(kTileThreads) kb_vpre_tile(const BItem* __rest
     __shared__ TilePreLds<T> sh;
     const LDesc<T>& d = pd[it.prob].lv[level];
     const LDesc<T>& c = pd[it.prob].lv[level + 1];
-    d_vpre_tile<T>(bk, d.g, d.G, d.gk, d.b, d.x, c.g, c.b, sh);
+    // as vcycle(): the finest level's pre-smoothed iterate goes to xt
+    d_vpre_tile<T>(bk, d.g, d.G, d.gk, d.b, level == 0 ? d.xt : d.x, c.g, c.b, sh);
 }
 
 template <typename T>
@@ -401,7 +403,9 @@ __global__ void __launch_bounds__(kTileThreads) kb_vpost_tile(const BItem* __res
     __shared__ TilePostLds<T> sh;
     const LDesc<T>& d = pd[it.prob].lv[level];
     const LDesc<T>& c = pd[it.prob].lv[level + 1];
-    d_vpost_tile<T>(bk, d.g, d.G, d.gk, d.b, d.x, d.xt, c.g, c.tile ? c.xt : c.x, sh);
+    // the finest level reads xt and writes x; the others read x, write xt
+    d_vpost_tile<T>(bk, d.g, d.G, d.gk, d.b, level == 0 ? d.xt : d.x, level == 0 ? d.x : d.xt,
+                    c.g, c.tile ? c.xt : c.x, sh);
 }
 
 } // namespace cps

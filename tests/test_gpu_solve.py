@@ -174,8 +174,10 @@ def test_profile_classes_and_grouped_colour_passes():
     every outer iteration's V(2,2) cycle contributes its 7 full finest-level
     colour passes (the zero-iterate first pass is not in the class), timed as
     spans over back-to-back passes; the other classes record nothing; the
-    profiled solve gives the same bits as an unprofiled one."""
-    g = Shell(16, 16, 32, radial_stretch=2.0)
+    profiled solve gives the same bits as an unprofiled one. The grid is
+    above the 8^3-tile path's size limit, so its finest level runs the
+    marching colour passes the class times."""
+    g = Shell(16, 32, 160, radial_stretch=2.0)
     b = dev(inputs.smoothed_noise(g.shape, 13)).flatten()
     s = cps.Solver(g, precision=0, accel=1)
     try:
@@ -201,15 +203,21 @@ def test_profile_classes_and_grouped_colour_passes():
 @pytest.mark.parametrize("precision,smoother", [(0, 0), (1, 0), (0, 1)])
 def test_time_vcycle(precision, smoother):
     """cps_time_vcycle replays captured V-cycles: a positive time per cycle,
-    a solve after it gives the same bits as before it, and the argument
-    checks (null stream, cycles or reps < 1, profiling on) fail cleanly."""
+    a kernel count per cycle between two launches per smoothed level (each
+    level on the 8^3-tile path) plus the coarsest solve and, per level, a
+    dozen (point smoothing: 8 colour passes, residual, restriction,
+    prolongation) or 28 (plane smoothing: 8 half-sweeps of 3 kernels), a
+    solve after it gives the same bits as before it, and the
+    argument checks (null stream, cycles or reps < 1, profiling on) fail
+    cleanly."""
     g = Shell(16, 16, 64, radial_stretch=2.0)
     b = dev(inputs.smoothed_noise(g.shape, 17)).flatten()
     stream = torch.cuda.Stream()
     s = cps.Solver(g, precision=precision, accel=1, smoother=smoother, stream=stream)
     try:
         x0 = host(s.solve(b).p)
-        us = s.time_vcycle(cycles=4, reps=3)
+        us, launches = s.time_vcycle(cycles=4, reps=3)
+        nl = len(s.levels)
         x1 = host(s.solve(b).p)
         for cycles, reps in ((0, 1), (1, 0)):
             with pytest.raises(cps.CpsError):
@@ -220,8 +228,9 @@ def test_time_vcycle(precision, smoother):
         cps.cps_profile_enable(s.h, False)
     finally:
         s.close()
-    log("time_vcycle", precision, smoother, f"{us:.1f} us")
+    log("time_vcycle", precision, smoother, f"{us:.1f} us, {launches} launches, {nl} levels")
     assert 0 < us < 1e5
+    assert 2 * (nl - 1) + 1 <= launches <= (12 if smoother == 0 else 28) * nl, (launches, nl)
     assert np.array_equal(x0, x1)
     s = cps.Solver(g, precision=0, accel=1)  # the null stream
     try:
