@@ -1247,7 +1247,7 @@ void build(cps_handle* h)
     // from zero, and then its dot products come from a separate reduction)
     for (int l = 0; l + 1 < h->L; ++l) {
         LevelMem& m = h->lv[l];
-        m.tile = marching(h) && h->ncol == 2 && h->opts.smoother == 0 && tile_fits(m.geo);
+        m.tile = marching(h) && h->ncol == 2 && h->opts.smoother == 0 && tile_fits(m.geo, mixed);
         if (!m.tile) continue;
         if (mixed) m.xt32.alloc(m.n);
         else m.xt64.alloc(m.n);

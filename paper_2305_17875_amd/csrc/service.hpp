@@ -101,7 +101,7 @@ size_t estimate_bytes(const cps_grid& g, const cps_opts& o)
         if (mixed) s += 9 * gk * 4 + n * 4 * (l + 1 < L ? 3 : 2);
         else s += n * 8 * ((l > 0 ? 2 : 0) + (l + 1 < L ? 1 : 0));
         // the tile path's second iterate (small levels, point smoother)
-        if (l + 1 < L && n <= (size_t)kTileMaxCells) s += n * (mixed ? 4 : 8);
+        if (l + 1 < L && n <= (size_t)tile_max_cells(mixed)) s += n * (mixed ? 4 : 8);
     }
     const size_t n0 = (size_t)g.n_r * g.n_theta * g.n_phi;
     const size_t nc = (size_t)dims[L - 1][0] * dims[L - 1][1] * dims[L - 1][2];

@@ -50,12 +50,20 @@ constexpr int kCoarseR = kTile / 2 + 6;       // coarse correction box of post
 // shell the 24 x 32 x 64 and 12 x 16 x 32 levels gain (pre + post 21 and
 // 17 us against 46 and 38 us of per-kernel launches), the 48 x 64 x 128
 // level does not (768 tiles at one 117 KB block per CU: 61 against 52 us).
+// FP32 tiles take half the LDS (58 KB pre, 43 KB post), two blocks share a
+// CU, and the 48 x 64 x 128 level runs in two rounds instead of three.
 constexpr long long kTileMaxCells = 1LL << 16;
+constexpr long long kTileMaxCells32 = 1LL << 19;
 
-__host__ __device__ inline bool tile_fits(const Geo& g)
+__host__ __device__ inline long long tile_max_cells(bool fp32)
+{
+    return fp32 ? kTileMaxCells32 : kTileMaxCells;
+}
+
+__host__ __device__ inline bool tile_fits(const Geo& g, bool fp32 = false)
 {
     return g.np % kTile == 0 && g.nr % 2 == 0 && g.nt % 2 == 0 &&
-           (long long)g.nr * g.nt * g.np <= kTileMaxCells;
+           (long long)g.nr * g.nt * g.np <= tile_max_cells(fp32);
 }
 
 __host__ __device__ inline int tile_count(const Geo& g)
