@@ -86,7 +86,22 @@ def gs_bytes_per_launch(shape, ncol, word, phi_invariant, nterms):
     return field + coef
 
 
-def vcycle_bytes(levels, word, phi_invariant=True):
+def fused_transfer(f, c):
+    """Whether the FP64 cycle forms the red residual of level f inside its
+    restriction to c (one pass, r never stored): a row-pair level halved in
+    every direction whose coarse ring is one or two segments of 64 phi pairs
+    and whose coarse theta count splits into the kernel's row groups (4 rows
+    for one segment, 2 for two)."""
+    (nr, nt, np_), (cr, ct, cp) = f, c
+    if (np_ // 2) % 64 or nt % 2 or nr != 2 * cr or nt != 2 * ct or np_ != 2 * cp:
+        return False
+    if (cp // 2) % 64:
+        return False
+    segs = cp // 2 // 64
+    return segs in (1, 2) and ct % (4 if segs == 1 else 2) == 0
+
+
+def vcycle_bytes(levels, word, phi_invariant=True, fused=False):
     """Algorithmic HBM bytes of one V(2,2) cycle from a zero iterate on the
     7-point hierarchy with point red-black smoothing: per smoothed level of n
     cells, the zero-iterate pass (b and x of one colour: n words), seven full
@@ -101,13 +116,20 @@ def vcycle_bytes(levels, word, phi_invariant=True):
     even) only the red residual is formed and restricted: residual x in,
     red b in, red r out (2 n), restriction red r in, n/8 out -- 16.25 n
     words a level.  Elsewhere the full residual (x, b in, r out: 3 n) and
-    restriction (n in, n/8 out) -- 17.75 n."""
+    restriction (n in, n/8 out) -- 17.75 n.
+
+    fused (the FP64 cycle): where fused_transfer holds, the red residual is
+    formed inside the restriction: x in, red b in, n/8 out, and r is neither
+    written nor read back -- 15.25 n words."""
     total = 0
-    for nr, nt, np_ in levels[:-1]:
+    for k, (nr, nt, np_) in enumerate(levels[:-1]):
         n = nr * nt * np_
         coef = 3 * nr * nt * (1 if phi_invariant else np_)
         red = (np_ // 2) % 64 == 0 and nt % 2 == 0
-        total += ((16.25 if red else 17.75) * n + 9 * coef) * word
+        words = 16.25 if red else 17.75
+        if fused and fused_transfer(levels[k], levels[k + 1]):
+            words = 15.25
+        total += (words * n + 9 * coef) * word
     nc = levels[-1][0] * levels[-1][1] * levels[-1][2]
     return int(round(total)) + nc * nc * 8 + 2 * nc * word
 
@@ -223,7 +245,8 @@ def vcycle_rate(prof, levels, word, steps, graph_us=None, traffic=None):
         return None
     eager = ms / cnt * 1e-3
     t = graph_us * 1e-6 if graph_us else eager
-    b = vcycle_bytes(levels, word)
+    # FP64 cycles fuse the red residual into the restriction; FP32 ones do not
+    b = vcycle_bytes(levels, word, fused=word == 8)
     out = {"bytes_per_cycle": b, "avg_us": t * 1e6, "achieved_GBs": b / t / 1e9,
            "frac_of_peak": b / t / 1e9 / HBM_PEAK_GBS, "cycles_per_step": cnt / steps,
            "timing": ("hipGraph replay of 10 cycles, 5 launches between events "

@@ -298,6 +298,16 @@ cps_status cps_debug_gs_pass(cps_handle* h, int32_t level, int32_t colour, const
                              double* x);
 /* bc (level l+1) = P^T r (level l): full weighting, 64-point. */
 cps_status cps_debug_restrict(cps_handle* h, int32_t level, const double* r, double* bc);
+/* The V-cycle's transfer after red-black pre-smoothing (Sec. on the
+ * multigrid solver): bc (level l+1) = P^T r with r = b - A x on level l's
+ * red cells (colour 0) and 0 on its black cells, whose residual the black
+ * pass has just made zero.  Runs what the FP64 cycle runs: one fused pass
+ * where the level's shape allows it, else the red residual and the
+ * restriction.  CPS_E_INVALID: a level that forms its whole residual (not
+ * point red-black smoothing of the 7-point operator on n_phi / 2 a multiple
+ * of 64 and even n_theta), the coarsest level, or a mixed handle. */
+cps_status cps_debug_residual_restrict(cps_handle* h, int32_t level, const double* b,
+                                       const double* x, double* bc);
 /* x (level l) += P e (level l+1): cell-centred trilinear. */
 cps_status cps_debug_prolong(cps_handle* h, int32_t level, const double* e, double* x);
 /* e = (A_c + alpha 1 1^T)^-1 (b - mean b) on the coarsest level. */

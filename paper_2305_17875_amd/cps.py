@@ -95,6 +95,7 @@ def lib():
         L.cps_debug_residual.argtypes = [P, I, P, P, P, P]
         L.cps_debug_gs_pass.argtypes = [P, I, I, P, P]
         L.cps_debug_restrict.argtypes = [P, I, P, P]
+        L.cps_debug_residual_restrict.argtypes = [P, I, P, P, P]
         L.cps_debug_prolong.argtypes = [P, I, P, P]
         L.cps_debug_coarse_solve.argtypes = [P, P, P]
         L.cps_debug_vcycle.argtypes = [P, P, P]
@@ -132,7 +133,8 @@ def lib():
                   "cps_profile_select", "cps_profile_enable", "cps_profile_read", "cps_debug_copy",
                   "cps_time_vcycle",
                   "cps_debug_metrics", "cps_debug_apply", "cps_debug_residual",
-                  "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_prolong",
+                  "cps_debug_gs_pass", "cps_debug_restrict", "cps_debug_residual_restrict",
+                  "cps_debug_prolong",
                   "cps_debug_coarse_solve", "cps_debug_vcycle", "cps_debug_plane_sweep"):
             getattr(L, f).restype = I
         _lib = L
@@ -297,6 +299,17 @@ def cps_debug_restrict(h, level, r, bc):
         raise ValueError("no coarser level")
     _expect(r, n, "r"); _expect(bc, n // 8, "bc")
     _check(lib().cps_debug_restrict(h, level, _ptr(r), _ptr(bc)))
+
+
+def cps_debug_residual_restrict(h, level, b, x, bc):
+    """bc = P^T r, r = b - A x on the red cells of level `level` and 0 on
+    its black cells: the FP64 V-cycle's transfer after red-black smoothing."""
+    levels, n = _dims(h, level)
+    if level + 1 >= len(levels):
+        raise ValueError("no coarser level")
+    nc = math.prod(levels[level + 1])
+    _expect(b, n, "b"); _expect(x, n, "x"); _expect(bc, nc, "bc")
+    _check(lib().cps_debug_residual_restrict(h, level, _ptr(b), _ptr(x), _ptr(bc)))
 
 
 def cps_debug_prolong(h, level, e, x):

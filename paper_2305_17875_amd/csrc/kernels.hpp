@@ -1083,6 +1083,36 @@ __device__ __forceinline__ void march2_load(const Geo& g, const X& x, const Marc
     }
 }
 
+// Flux-form (A x) of one plane-0 cell (phi index 2j) of a row: its column
+// values at a-1 (um), a (u), a+1 (up), its theta neighbours below (utm) and
+// above (utp), and its phi neighbours v (plane 1, j) and vjm (plane 1, j-1);
+// metrics r low/high (grl, grh), theta low/high (gtl, gth), phi (gpp).  The
+// sum is an explicit fma chain, so every kernel that forms it rounds alike.
+template <typename T>
+__device__ __forceinline__ T cell_apply_e(T grl, T grh, T gtl, T gth, T gpp, T um, T u, T up,
+                                          T utm, T utp, T v, T vjm)
+{
+    T s = mul_t(grh, up - u);
+    s = fma_t(-grl, u - um, s);
+    s = fma_t(gth, utp - u, s);
+    s = fma_t(-gtl, u - utm, s);
+    s = fma_t(gpp, v - u, s);
+    return fma_t(-gpp, u - vjm, s);
+}
+// The same for a plane-1 cell (phi index 2j + 1): its phi neighbours are
+// ujp (plane 0, j + 1) and u (plane 0, j).
+template <typename T>
+__device__ __forceinline__ T cell_apply_o(T grl, T grh, T gtl, T gth, T gpp, T vm, T v, T vp,
+                                          T vtm, T vtp, T ujp, T u)
+{
+    T s = mul_t(grh, vp - v);
+    s = fma_t(-grl, v - vm, s);
+    s = fma_t(gth, vtp - v, s);
+    s = fma_t(-gtl, v - vtm, s);
+    s = fma_t(gpp, ujp - v, s);
+    return fma_t(-gpp, v - u, s);
+}
+
 // Flux-form (A x) of one row's two cells (plane 0 cell 2j, plane 1 cell
 // 2j+1) from the row's column values at a-1 (um, vm), a (u, v), a+1 (up,
 // vp), its theta neighbours below (utm, vtm) and above (utp, vtp), and the
@@ -1099,20 +1129,8 @@ __device__ __forceinline__ void row_apply(const T* __restrict__ G, long long gk,
     const T gtl = G[4 * gk + ci];
     const T gth = th ? G[4 * gk + ci + 1] : T(0);
     const T gpp = G[8 * gk + ci];
-    // the sums as explicit fma chains (the row-pair product must round alike
-    // in every kernel that inlines it)
-    T s0 = mul_t(grh, up - u);
-    s0 = fma_t(-grl, u - um, s0);
-    s0 = fma_t(gth, utp - u, s0);
-    s0 = fma_t(-gtl, u - utm, s0);
-    s0 = fma_t(gpp, v - u, s0);
-    y0 = fma_t(-gpp, u - vjm, s0);
-    T s1 = mul_t(grh, vp - v);
-    s1 = fma_t(-grl, v - vm, s1);
-    s1 = fma_t(gth, vtp - v, s1);
-    s1 = fma_t(-gtl, v - vtm, s1);
-    s1 = fma_t(gpp, ujp - v, s1);
-    y1 = fma_t(-gpp, v - u, s1);
+    y0 = cell_apply_e(grl, grh, gtl, gth, gpp, um, u, up, utm, utp, v, vjm);
+    y1 = cell_apply_o(grl, grh, gtl, gth, gpp, vm, v, vp, vtm, vtp, ujp, u);
 }
 
 // (A x) of the four cells of a row-pair thread at plane a.
@@ -1730,6 +1748,217 @@ __global__ void __launch_bounds__(kBlock) k_restrict_rows(Geo f, Geo c, int bpa,
     d_restrict2<T, RED>(self_blk(), f, c, bpa, ch, r, bc, sh);
 }
 
+// ---------------------------------------------------------------------------
+// Red residual and restriction in one pass: the FP64 V-cycle's transfer on a
+// row-pair level after point red-black pre-smoothing (whose last pass was the
+// black one, so only the red residual is formed, as d_residual_march2 does
+// with red != 0).  bc = P^T r with r = b - A x on the red cells and 0 on the
+// black ones; r never goes through memory, which saves writing it and
+// reading it back (two fields of half a level's cells).
+//
+// A block is rr_rows(SEGS) coarse theta rows x the whole phi ring
+// (SEGS = coarse n_phi / 128 segments of 64 coarse phi pairs) x a chunk of
+// ch coarse planes.  Each wavefront owns one fine row of one segment: the
+// 2 * rows fine rows of the block's coarse rows and the two outer rows the
+// theta restriction also reads (first - 1 and last + 1, clamped at the
+// theta walls as d_restrict2 clamps them), i.e. 2 * rows + 2 wavefronts a
+// segment; lane j holds fine phi pairs cv = 2 jc, 2 jc + 1 (jc = 64 s + j)
+// of each parity plane.  At each fine plane a a wavefront forms the red
+// residual of its row with the sums of cell_apply_e / cell_apply_o (theta
+// neighbours loaded, phi neighbours from the adjacent lanes and past the
+// wavefront's ends loaded) and stores it in LDS; after one barrier the
+// first `rows` wavefronts of each segment restrict fine rows 2J - 1 ..
+// 2J + 2 of their coarse row J in phi (the value past a segment's end from
+// the adjacent segment) and theta, with the weights and sums of
+// d_restrict2<T, 1>, and coarse plane I combines fine planes 2I - 1 ..
+// 2I + 2 (clamped at the r walls) as there.  A wavefront's loads of the next
+// planes are issued once its residual is formed, before the barrier.
+__host__ __device__ constexpr int rr_rows(int segs) { return segs == 1 ? 4 : 2; }
+__host__ __device__ constexpr int rr_waves(int segs) { return (2 * rr_rows(segs) + 2) * segs; }
+
+// The ring segments of the fused transfer from level f to c, or 0 where it
+// does not apply (then the residual and the restriction run apart).
+__host__ __device__ inline int resrestrict_segs(const Geo& f, const Geo& c)
+{
+    if (!row_pairs(f) || f.nr != 2 * c.nr || f.nt != 2 * c.nt || f.nh != 2 * c.nh) return 0;
+    const int segs = c.nh / 64;
+    if (c.nh % 64 != 0 || (segs != 1 && segs != 2)) return 0;
+    return c.nt % rr_rows(segs) == 0 ? segs : 0;
+}
+
+template <typename T, int SEGS>
+struct ResRestrictLds {
+    Vec2<T> v[2][SEGS][2 * rr_rows(SEGS) + 2][64]; // [buffer][segment][fine row slot][lane]
+};
+
+template <typename T, int SEGS>
+__device__ __forceinline__ void d_resrestrict(Blk bk, Geo f, const T* __restrict__ G, long long gk,
+                                              Geo c, int bpa, int ch, const T* __restrict__ bv,
+                                              const T* __restrict__ x, T* __restrict__ bc,
+                                              ResRestrictLds<T, SEGS>& sh)
+{
+    constexpr int ROWS = rr_rows(SEGS), W = 2 * ROWS + 2;
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+    const int s = wv / W, wr = wv - s * W;
+    const int L = (int)bk.L;
+    const int chunk = L / bpa, Gi = L - chunk * bpa;
+    const int I0 = chunk * ch, I1 = min(c.nr, I0 + ch);
+    if (I0 >= c.nr) return; // whole block: no barrier is skipped by part of it
+    const int jc = s * 64 + lane, cv = 2 * jc;
+    const int nh = f.nh, nt = f.nt;
+    const long long sr = f.rowlen, P = f.P;
+    // this wavefront's fine row (slot wr of the block's rows) and its theta
+    // neighbours (the row itself past a wall)
+    const int b = clampi(2 * ROWS * Gi - 1 + wr, nt - 1);
+    const int bl = b > 0 ? b - 1 : b, bh = b < nt - 1 ? b + 1 : b;
+    const int cm = jc == 0 ? nh - 1 : cv - 1;   // plane 1, the phi pair below
+    const int cp = jc == c.nh - 1 ? 0 : cv + 2; // plane 0, the phi pair above
+    struct RX {
+        Vec2<T> e, o;
+    };
+    struct RB {
+        Vec2<T> bb, tl, th;
+        T edge;
+    };
+    // every address: a wavefront-uniform row pointer + the lane's phi index
+    auto ld2 = [&](const T* row, int i) { return *reinterpret_cast<const Vec2<T>*>(row + i); };
+    auto load_x = [&](int a) {
+        const T* p = x + (long long)clampi(a, f.nr - 1) * sr + (long long)b * nh;
+        RX v;
+        v.e = ld2(p, cv);
+        v.o = ld2(p + P, cv);
+        return v;
+    };
+    // b on the red cells, the theta neighbours at the red parity, and the
+    // phi value past the wavefront's end (lane 0: plane 1 below; lane 63:
+    // plane 0 above)
+    auto load_b = [&](int a) {
+        a = clampi(a, f.nr - 1);
+        const int sp = (a + b) & 1;
+        const long long pl = (long long)a * sr + sp * P;
+        RB v;
+        v.bb = ld2(bv + pl + (long long)b * nh, cv);
+        v.tl = ld2(x + pl + (long long)bl * nh, cv);
+        v.th = ld2(x + pl + (long long)bh * nh, cv);
+        const T* row = x + (long long)a * sr + (long long)b * nh;
+        v.edge = T(0);
+        if (sp == 0 && lane == 0) v.edge = (row + P)[cm];
+        if (sp == 1 && lane == 63) v.edge = row[cp];
+        return v;
+    };
+    const int a_first = max(2 * I0 - 1, 0), a_last = min(2 * I1, f.nr - 1);
+    const bool dup_lo = 2 * I0 - 1 < 0, dup_hi = 2 * I1 > f.nr - 1;
+    Vec2<T> Xm; // plane a - 1 at the red parity of plane a
+    RX Xc, Xn;
+    RB Bc;
+    {
+        const RX m = load_x(a_first - 1);
+        Xm = ((a_first + b) & 1) ? m.o : m.e;
+        Xc = load_x(a_first);
+        Xn = load_x(a_first + 1);
+        Bc = load_b(a_first);
+    }
+    const T w0 = T(0.25), w1 = T(0.75);
+    const T wq[4] = {w0, w1, w1, w0};
+    // restricting wavefronts: the last three fine planes' sums (nominal
+    // planes, the clamped wall planes counted twice); coarse plane I is
+    // written when fine plane 2I + 2 arrives
+    const bool emit = wr < ROWS;
+    const int J = ROWS * Gi + wr;
+    T win0[3] = {T(0), T(0), T(0)}, win1[3] = {T(0), T(0), T(0)};
+    int knom = 0;
+    auto consume = [&](T s0, T s1) {
+        if (knom >= 3 && (knom & 1)) {
+            const int I = I0 + (knom - 3) / 2;
+            T* o = bc + (long long)I * c.rowlen + (long long)J * c.nh;
+            o[jc] = w0 * win0[0] + w1 * win0[1] + w1 * win0[2] + w0 * s0;
+            (o + c.P)[jc] = w0 * win1[0] + w1 * win1[1] + w1 * win1[2] + w0 * s1;
+        }
+        win0[0] = win0[1];
+        win0[1] = win0[2];
+        win0[2] = s0;
+        win1[0] = win1[1];
+        win1[1] = win1[2];
+        win1[2] = s1;
+        ++knom;
+    };
+    for (int a = a_first, buf = 0; a <= a_last; ++a, buf ^= 1) {
+        // red residual of the row at plane a
+        {
+            const int sp = (a + b) & 1;
+            const Vec2<T> xs = sp ? Xc.o : Xc.e; // the red cells
+            const Vec2<T> xb = sp ? Xc.e : Xc.o; // the row's black cells
+            const Vec2<T> xp = sp ? Xn.o : Xn.e;
+            const Vec2<T> tl = b > 0 ? Bc.tl : xs, th = b < nt - 1 ? Bc.th : xs;
+            const long long ci = (long long)a * nt + b;
+            const T grl = G[ci];
+            const T grh = a < f.nr - 1 ? G[ci + nt] : T(0);
+            const T gtl = G[4 * gk + ci];
+            const T gth = b < nt - 1 ? G[4 * gk + ci + 1] : T(0);
+            const T gpp = G[8 * gk + ci];
+            Vec2<T> y;
+            if (sp == 0) { // red in plane 0: phi neighbours in plane 1 at j - 1, j
+                const T sv = __shfl(xb.y, lane - 1);
+                const T vjm = lane > 0 ? sv : Bc.edge;
+                y.x = cell_apply_e(grl, grh, gtl, gth, gpp, Xm.x, xs.x, xp.x, tl.x, th.x, xb.x, vjm);
+                y.y = cell_apply_e(grl, grh, gtl, gth, gpp, Xm.y, xs.y, xp.y, tl.y, th.y, xb.y, xb.x);
+            } else { // red in plane 1: phi neighbours in plane 0 at j, j + 1
+                const T su = __shfl(xb.x, lane + 1);
+                const T ujp = lane < 63 ? su : Bc.edge;
+                y.x = cell_apply_o(grl, grh, gtl, gth, gpp, Xm.x, xs.x, xp.x, tl.x, th.x, xb.y, xb.x);
+                y.y = cell_apply_o(grl, grh, gtl, gth, gpp, Xm.y, xs.y, xp.y, tl.y, th.y, ujp, xb.y);
+            }
+            Vec2<T> r;
+            r.x = Bc.bb.x - y.x;
+            r.y = Bc.bb.y - y.y;
+            sh.v[buf][s][wr][lane] = r;
+        }
+        // the next planes' loads fly over the barrier and the restriction
+        Xm = ((a + 1 + b) & 1) ? Xc.o : Xc.e;
+        Xc = Xn;
+        Xn = load_x(a + 2);
+        Bc = load_b(a + 1);
+        __syncthreads();
+        if (emit) { // phi and theta restriction of fine rows 2J - 1 .. 2J + 2
+            T p0[4], p1[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int sl = 2 * wr + q;
+                const int fr = clampi(2 * ROWS * Gi - 1 + sl, nt - 1);
+                const Vec2<T> v = sh.v[buf][s][sl][lane];
+                if (((a + fr) & 1) == 0) { // red in plane 0: v1, v3, v5
+                    const T v5 = lane < 63 ? sh.v[buf][s][sl][lane + 1].x
+                                           : sh.v[buf][(s + 1) % SEGS][sl][0].x;
+                    p0[q] = w1 * v.x + w0 * v.y;
+                    p1[q] = w1 * v.y + w0 * v5;
+                } else { // red in plane 1: v0, v2, v4
+                    const T v0 = lane > 0 ? sh.v[buf][s][sl][lane - 1].y
+                                          : sh.v[buf][(s + SEGS - 1) % SEGS][sl][63].y;
+                    p0[q] = w0 * v0 + w1 * v.x;
+                    p1[q] = w0 * v.x + w1 * v.y;
+                }
+            }
+            T s0 = T(0), s1 = T(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s0 += wq[q] * p0[q];
+                s1 += wq[q] * p1[q];
+            }
+            consume(s0, s1);
+            if ((a == 0 && dup_lo) || (a == f.nr - 1 && dup_hi)) consume(s0, s1);
+        }
+    }
+}
+
+template <typename T, int SEGS>
+__global__ void __launch_bounds__(64 * rr_waves(SEGS))
+    k_resrestrict(Geo f, const T* __restrict__ G, long long gk, Geo c, int bpa, int ch,
+                  const T* __restrict__ bv, const T* __restrict__ x, T* __restrict__ bc)
+{
+    __shared__ ResRestrictLds<T, SEGS> sh;
+    d_resrestrict<T, SEGS>(self_blk(), f, G, gk, c, bpa, ch, bv, x, bc, sh);
+}
+
 // x += P e (trilinear); the thread writes fine rows 2J, 2J+1 and fine phi
 // 4jc .. 4jc+3 on the two fine planes of every coarse plane of its chunk.
 template <typename T>
@@ -2247,6 +2476,17 @@ __host__ __device__ inline MarchShape march_shape(const Geo& g, int ch = 0)
 __host__ __device__ inline MarchShape restrict_shape(const Geo& c)
 {
     return restrict_rows(c) ? chunked(c, cdiv(c.rowlen, kBlock), 0, 1024) : march_shape(c);
+}
+// The fused red residual and restriction: c.nt / rr_rows blocks per chunk
+// of coarse planes, chunks for about one block per CU (a block of 10 or 12
+// wavefronts at ~108 VGPRs has a CU to itself), at least two coarse planes a
+// chunk (a block re-reads two fine planes of x at each chunk end).
+__host__ __device__ inline MarchShape resrestrict_shape(const Geo& c, int segs, int ch = 0)
+{
+    const int bpa = c.nt / rr_rows(segs);
+    MarchShape ms = chunked(c, bpa, ch, 256);
+    if (ch <= 0 && ms.ch < 2 && c.nr >= 2) ms = chunked(c, bpa, 2);
+    return ms;
 }
 
 // Row-pair kernels: bpa blocks over the (n_theta / 2) * (n_phi / 2)

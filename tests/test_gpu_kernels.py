@@ -147,3 +147,51 @@ def test_coarse_solve_and_vcycle(case):
         cps.cps_debug_vcycle(s.h, dev(b).flatten(), xd)
         x = mg.vcycle(b, x)
         assert rel(host(xd).reshape(x.shape), x) < 1e-11, k
+
+
+# Red-residual transfer of the FP64 V-cycle (one fused pass where the level
+# allows it): rings of one and two 64-pair coarse segments, several chunks of
+# coarse planes, both theta walls, and levels that take the two-kernel form.
+RED_CASES = [
+    ("sphere-wide-16x16x512", Shell(16, 16, 512, radial_stretch=2.0)),
+    ("sphere-rows-12x32x256", Shell(12, 32, 256)),
+    ("sphere-rows-40x16x256", Shell(40, 16, 256, radial_stretch=1.5)),
+    ("sphere-tile-6x10x256", Shell(6, 10, 256)),
+]
+
+
+@pytest.mark.parametrize("name,g", RED_CASES, ids=[c[0] for c in RED_CASES])
+def test_red_residual_transfer(name, g):
+    """cps_debug_residual_restrict against the oracle: the residual b - A x
+    with its black cells set to 0, then the restriction, at 1e-13 of the
+    largest coarse value, on every level that forms a red residual."""
+    log("red transfer", name)
+    s = cps.Solver(g, precision=0, accel=1)
+    mg = O.Multigrid(g)
+    rng = np.random.default_rng(5)
+    done = 0
+    try:
+        for l in range(len(s.levels) - 1):
+            shp, cshp = s.levels[l], s.levels[l + 1]
+            if shp[2] % 128 != 0 or shp[1] % 2 != 0:
+                with pytest.raises(cps.CpsError):
+                    cps.cps_debug_residual_restrict(
+                        s.h, l, dev(np.zeros(shp)).flatten(), dev(np.zeros(shp)).flatten(),
+                        torch.empty(int(np.prod(cshp)), dtype=torch.float64, device="cuda"))
+                continue
+            b = rng.standard_normal(shp)
+            x = rng.standard_normal(shp)
+            bc = torch.empty(int(np.prod(cshp)), dtype=torch.float64, device="cuda")
+            cps.cps_debug_residual_restrict(s.h, l, dev(b).flatten(), dev(x).flatten(), bc)
+            r = O.residual(mg.metrics(l), b, x)
+            a, t, p = np.indices(shp)
+            r[(a + t + p) % 2 == 1] = 0.0
+            want = O.restrict(r)
+            got = host(bc).reshape(cshp)
+            err = np.abs(got - want).max() / np.abs(want).max()
+            log("red transfer", name, l, shp, f"{err:.1e}")
+            assert err < 1e-13, (l, err)
+            done += 1
+    finally:
+        s.close()
+    assert done >= 1
