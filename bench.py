@@ -87,7 +87,7 @@ def gs_bytes_per_launch(shape, ncol, word, phi_invariant, nterms):
 
 
 def fused_transfer(f, c):
-    """Whether the FP64 cycle forms the red residual of level f inside its
+    """Whether the V-cycle forms the red residual of level f inside its
     restriction to c (one pass, r never stored): a row-pair level halved in
     every direction whose coarse ring is one or two segments of 64 phi pairs
     and whose coarse theta count splits into the kernel's row groups (4 rows
@@ -118,7 +118,7 @@ def vcycle_bytes(levels, word, phi_invariant=True, fused=False):
     words a level.  Elsewhere the full residual (x, b in, r out: 3 n) and
     restriction (n in, n/8 out) -- 17.75 n.
 
-    fused (the FP64 cycle): where fused_transfer holds, the red residual is
+    fused (the library's cycles): where fused_transfer holds, the red residual is
     formed inside the restriction: x in, red b in, n/8 out, and r is neither
     written nor read back -- 15.25 n words."""
     total = 0
@@ -245,8 +245,7 @@ def vcycle_rate(prof, levels, word, steps, graph_us=None, traffic=None):
         return None
     eager = ms / cnt * 1e-3
     t = graph_us * 1e-6 if graph_us else eager
-    # FP64 cycles fuse the red residual into the restriction; FP32 ones do not
-    b = vcycle_bytes(levels, word, fused=word == 8)
+    b = vcycle_bytes(levels, word, fused=True)
     out = {"bytes_per_cycle": b, "avg_us": t * 1e6, "achieved_GBs": b / t / 1e9,
            "frac_of_peak": b / t / 1e9 / HBM_PEAK_GBS, "cycles_per_step": cnt / steps,
            "timing": ("hipGraph replay of 10 cycles, 5 launches between events "

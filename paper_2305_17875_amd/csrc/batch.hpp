@@ -80,6 +80,10 @@ struct BatchGroup {
     std::vector<int> probs;
     int Lmax = 0;
     ItemTable gs[kMaxLevels], res[kMaxLevels], xfer[kMaxLevels], fill[kMaxLevels];
+    // restriction of the problems that form their residual apart (xfer:
+    // every problem's prolongation); rr: the fused red residual and
+    // restriction, by ring segments (1, 2)
+    ItemTable rst[kMaxLevels], rr[kMaxLevels][2];
     ItemTable tile[kMaxLevels]; // problems whose level takes the tile path: its tiles
     ItemTable pfwd[kMaxLevels][2], ptri[kMaxLevels][2]; // plane half-sweeps by parity
     ItemTable coarse, apply, vred, elem;
@@ -124,13 +128,18 @@ void blaunch(cps_batch* B, const ItemTable& t, K kernel, A... args)
     LAUNCH_CHECK();
 }
 
-// the same for the tile kernels' larger blocks
+// the same for kernels of other block sizes (tiles, the fused transfer)
+template <typename K, typename... A>
+void blaunch_n(cps_batch* B, const ItemTable& t, int threads, K kernel, A... args)
+{
+    if (!t.count) return;
+    kernel<<<t.count, threads, 0, B->stream>>>(t.d.p, B->active.p, B->pd.p, args...);
+    LAUNCH_CHECK();
+}
 template <typename K, typename... A>
 void blaunch_tile(cps_batch* B, const ItemTable& t, K kernel, A... args)
 {
-    if (!t.count) return;
-    kernel<<<t.count, kTileThreads, 0, B->stream>>>(t.d.p, B->active.p, B->pd.p, args...);
-    LAUNCH_CHECK();
+    blaunch_n(B, t, kTileThreads, kernel, args...);
 }
 
 void bscalar(cps_batch* B, int op, int dst = 0, int src = 0, double value = 0.0)
@@ -201,7 +210,10 @@ void b_vcycle(cps_batch* B, BatchGroup& G)
         dispatch(G.mode, G.axi, [&](auto M, auto A) {
             blaunch(B, G.res[l], kb_residual<float, decltype(M)::value, decltype(A)::value>, l, red);
         });
-        blaunch(B, G.xfer[l], kb_restrict<float>, l, red);
+        blaunch(B, G.rst[l], kb_restrict<float>, l, red);
+        // where the shape allows it, the red residual inside the restriction
+        blaunch_n(B, G.rr[l][0], 64 * rr_waves(1), kb_resrestrict<float, 1>, l);
+        blaunch_n(B, G.rr[l][1], 64 * rr_waves(2), kb_resrestrict<float, 2>, l);
     }
     blaunch(B, G.coarse, kb_coarse<float>);
     for (int l = G.Lmax - 2; l >= 0; --l) {
@@ -340,8 +352,9 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
     using PG = std::vector<std::pair<int, int>>;
     G.Lmax = 0;
     for (int p : G.probs) G.Lmax = std::max(G.Lmax, B->h[p]->L);
+    const bool red = !G.plane && G.mode == MODE_ORTHO && G.axi;
     for (int l = 0; l + 1 < G.Lmax; ++l) {
-        PG gs, res, xf, fl, tl;
+        PG gs, res, xf, fl, tl, rs, rr1, rr2;
         for (int p : G.probs) {
             cps_handle* h = B->h[p];
             if (l + 1 >= h->L) continue;
@@ -350,18 +363,25 @@ void build_group_tables(cps_batch* B, BatchGroup& G)
                 tl.push_back({p, tile_count(g)});
                 continue;
             }
-            if (G.march) {
-                gs.push_back({p, gs_shape<float>(g, h->lv[l].gs_ch).grid});
-                res.push_back({p, stencil_shape(g).grid});
+            const Geo& c = h->lv[l + 1].geo;
+            const int segs = red && G.march ? resrestrict_segs(g, c) : 0;
+            if (G.march) gs.push_back({p, gs_shape<float>(g, h->lv[l].gs_ch).grid});
+            else gs.push_back({p, (int)grid_of(g.nr, gs_bpa(g, h->ncol))});
+            if (segs) {
+                (segs == 1 ? rr1 : rr2).push_back({p, resrestrict_shape<float>(c, segs).grid});
             } else {
-                gs.push_back({p, (int)grid_of(g.nr, gs_bpa(g, h->ncol))});
-                res.push_back({p, (int)grid_of(g.nr, cdiv(g.rowlen, kBlock))});
+                if (G.march) res.push_back({p, stencil_shape(g).grid});
+                else res.push_back({p, (int)grid_of(g.nr, cdiv(g.rowlen, kBlock))});
+                rs.push_back({p, march_shape(c).grid});
             }
-            xf.push_back({p, march_shape(h->lv[l + 1].geo).grid});
+            xf.push_back({p, march_shape(c).grid});
             fl.push_back({p, (int)nblk(h->lv[l].n)});
         }
         build_items(G.gs[l], gs);
         build_items(G.res[l], res);
+        build_items(G.rst[l], rs);
+        build_items(G.rr[l][0], rr1);
+        build_items(G.rr[l][1], rr2);
         build_items(G.xfer[l], xf);
         build_items(G.fill[l], fl);
         build_items(G.tile[l], tl);

@@ -613,21 +613,22 @@ void restrict_to(cps_handle* h, int l, const T* r, T* bc, bool red = false)
 }
 
 // bc = P^T r with r = b - A x on level l's red cells (0 on the black ones)
-// in one pass: the FP64 V-cycle's transfer where resrestrict_segs allows it
+// in one pass: the V-cycle's transfer where resrestrict_segs allows it
 // (timed in the restriction's class).
-void resrestrict(cps_handle* h, int l, const double* b, const double* x, double* bc)
+template <typename T>
+void resrestrict(cps_handle* h, int l, const T* b, const T* x, T* bc)
 {
-    const Level<double> F = view<double>(h, l);
+    const Level<T> F = view<T>(h, l);
     const Geo& c = h->lv[l + 1].geo;
     const int segs = resrestrict_segs(F.g, c);
     if (segs == 0) fail(CPS_E_INVALID, "internal: no fused transfer from level %d", l);
-    const MarchShape ms = resrestrict_shape(c, segs);
+    const MarchShape ms = resrestrict_shape<T>(c, segs);
     ProfScope ps(h, CPS_KERNEL_RESTRICT, l);
     if (segs == 2)
-        k_resrestrict<double, 2><<<ms.grid, 64 * rr_waves(2), 0, h->stream>>>(
+        k_resrestrict<T, 2><<<ms.grid, 64 * rr_waves(2), 0, h->stream>>>(
             F.g, F.G, F.gk, c, ms.bpa, ms.ch, b, x, bc);
     else
-        k_resrestrict<double, 1><<<ms.grid, 64 * rr_waves(1), 0, h->stream>>>(
+        k_resrestrict<T, 1><<<ms.grid, 64 * rr_waves(1), 0, h->stream>>>(
             F.g, F.G, F.gk, c, ms.bpa, ms.ch, b, x, bc);
     LAUNCH_CHECK();
 }
@@ -704,14 +705,12 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
         // coarse corrections start from zero
         smooth<T>(h, l, b, x, 2, false, l > 0 || x0_zero);
         // point red-black smoothing ends on the black pass: on row-pair
-        // levels only the red residual is formed and restricted (in FP64 in
-        // one pass where the level's shape allows it)
+        // levels only the red residual is formed and restricted (in one pass
+        // where the level's shape allows it)
         const bool red = red_residual(h, l);
-        if constexpr (std::is_same<T, double>::value) {
-            if (red && resrestrict_segs(h->lv[l].geo, h->lv[l + 1].geo) > 0) {
-                resrestrict(h, l, b, x, bl<double>(h, l + 1));
-                continue;
-            }
+        if (red && resrestrict_segs(h->lv[l].geo, h->lv[l + 1].geo) > 0) {
+            resrestrict<T>(h, l, b, x, bl<T>(h, l + 1));
+            continue;
         }
         residual<T>(h, l, b, x, rl<T>(h, l), false, red);
         restrict_to<T>(h, l, rl<T>(h, l), bl<T>(h, l + 1), red);
@@ -2105,7 +2104,7 @@ cps_status cps_debug_residual_restrict(cps_handle* h, int32_t level, const doubl
         const double* xp = split_copy(h, level, x, xs);
         cs.alloc(h->lv[level + 1].n);
         if (resrestrict_segs(h->lv[level].geo, h->lv[level + 1].geo) > 0) {
-            resrestrict(h, level, bp, xp, cs.p);
+            resrestrict<double>(h, level, bp, xp, cs.p);
         } else {
             residual<double>(h, level, bp, xp, rl<double>(h, level), false, true);
             restrict_to<double>(h, level, rl<double>(h, level), cs.p, true);

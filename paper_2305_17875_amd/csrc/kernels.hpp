@@ -1749,7 +1749,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict_rows(Geo f, Geo c, int bpa,
 }
 
 // ---------------------------------------------------------------------------
-// Red residual and restriction in one pass: the FP64 V-cycle's transfer on a
+// Red residual and restriction in one pass: the V-cycle's transfer on a
 // row-pair level after point red-black pre-smoothing (whose last pass was the
 // black one, so only the red residual is formed, as d_residual_march2 does
 // with red != 0).  bc = P^T r with r = b - A x on the red cells and 0 on the
@@ -2478,13 +2478,15 @@ __host__ __device__ inline MarchShape restrict_shape(const Geo& c)
     return restrict_rows(c) ? chunked(c, cdiv(c.rowlen, kBlock), 0, 1024) : march_shape(c);
 }
 // The fused red residual and restriction: c.nt / rr_rows blocks per chunk
-// of coarse planes, chunks for about one block per CU (a block of 10 or 12
-// wavefronts at ~108 VGPRs has a CU to itself), at least two coarse planes a
-// chunk (a block re-reads two fine planes of x at each chunk end).
+// of coarse planes, chunks for about one block per CU in FP64 (a block of 10
+// or 12 wavefronts at ~108 VGPRs has a CU to itself) and two in FP32 (~72
+// VGPRs), at least two coarse planes a chunk (a block re-reads two fine
+// planes of x at each chunk end).
+template <typename T>
 __host__ __device__ inline MarchShape resrestrict_shape(const Geo& c, int segs, int ch = 0)
 {
     const int bpa = c.nt / rr_rows(segs);
-    MarchShape ms = chunked(c, bpa, ch, 256);
+    MarchShape ms = chunked(c, bpa, ch, sizeof(T) == 8 ? 256 : 512);
     if (ch <= 0 && ms.ch < 2 && c.nr >= 2) ms = chunked(c, bpa, 2);
     return ms;
 }
@@ -2645,6 +2647,22 @@ __global__ void __launch_bounds__(kBlock) kb_restrict(const BItem* __restrict__ 
     const MarchShape ms = march_shape(P.lv[level + 1].g);
     d_restrict_any<T>(bk, P.lv[level].g, P.lv[level + 1].g, ms.bpa, ms.ch, P.lv[level].r,
                       P.lv[level + 1].b, sh, red && row_pairs(P.lv[level].g));
+}
+
+// the fused red residual and restriction of one problem's level (SEGS as
+// resrestrict_segs gives it; the block size is 64 * rr_waves(SEGS))
+template <typename T, int SEGS>
+__global__ void __launch_bounds__(64 * rr_waves(SEGS))
+    kb_resrestrict(const BItem* __restrict__ items, const int* __restrict__ active,
+                   const PDesc<T>* __restrict__ pd, int level)
+{
+    CPS_BATCH_BLOCK
+    __shared__ ResRestrictLds<T, SEGS> sh;
+    const PDesc<T>& P = pd[it.prob];
+    const LDesc<T>& d = P.lv[level];
+    const Geo c = P.lv[level + 1].g;
+    const MarchShape ms = resrestrict_shape<T>(c, SEGS);
+    d_resrestrict<T, SEGS>(bk, d.g, d.G, d.gk, c, ms.bpa, ms.ch, d.b, d.x, P.lv[level + 1].b, sh);
 }
 
 template <typename T>

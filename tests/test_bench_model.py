@@ -57,7 +57,7 @@ def test_paper_scale_figures(bench):
     levels = [(192, 256, 512), (96, 128, 256), (48, 64, 128), (24, 32, 64), (12, 16, 32),
               (6, 8, 16)]
     assert bench.vcycle_bytes(levels, 8) == 3_758_344_704
-    # the FP64 cycle's fused transfers on the two finest levels: one word a
+    # the cycle's fused transfers on the two finest levels: one word a
     # cell less there (25,165,824 + 3,145,728 cells)
     assert bench.vcycle_bytes(levels, 8, fused=True) == 3_758_344_704 - 8 * 28_311_552
 
@@ -74,7 +74,7 @@ def test_vcycle_bytes_red_residual_levels(bench):
         n = nr * nt * np_
         want = int(round((words * n + 9 * 3 * nr * nt) * 8)) + tail
         assert bench.vcycle_bytes([shape, coarse], 8) == want, shape
-    # the fused FP64 transfer: 15.25 n words where the coarse ring is one or
+    # the fused transfer: 15.25 n words where the coarse ring is one or
     # two 64-pair segments and its theta count splits into row groups
     for shape, c, words in (((8, 8, 256), (4, 4, 128), 15.25), ((8, 8, 512), (4, 4, 256), 15.25),
                             ((8, 4, 256), (4, 2, 128), 16.25), ((8, 8, 1024), (4, 4, 512), 16.25),
@@ -116,7 +116,7 @@ def test_vcycle_rate_reports_cycles_per_solve(bench):
     assert out["cycles_per_step"] == 75
     assert out["bytes_per_cycle"] == bench.vcycle_bytes(levels, 8, fused=True)
     assert bench.vcycle_rate(prof, levels, 4, 2)["bytes_per_cycle"] == \
-        bench.vcycle_bytes(levels, 4)
+        bench.vcycle_bytes(levels, 4, fused=True)
     assert out["avg_us"] == pytest.approx(930.0)
     assert out["frac_of_peak"] == pytest.approx(out["bytes_per_cycle"] / 930e-6 / 1e9 / 8000.0)
     # with the graph-replayed time: the rate is on it, the eager span beside it
