@@ -151,12 +151,17 @@ def test_coarse_solve_and_vcycle(case):
 
 # Red-residual transfer of the FP64 V-cycle (one fused pass where the level
 # allows it): rings of one and two 64-pair coarse segments, several chunks of
-# coarse planes, both theta walls, and levels that take the two-kernel form.
+# coarse planes, both theta walls, and levels that take the two-kernel form;
+# odd coarse plane counts (the last chunk one coarse plane, the top wall's
+# fine plane counted twice) with one and two segments; three row groups.
 RED_CASES = [
     ("sphere-wide-16x16x512", Shell(16, 16, 512, radial_stretch=2.0)),
     ("sphere-rows-12x32x256", Shell(12, 32, 256)),
     ("sphere-rows-40x16x256", Shell(40, 16, 256, radial_stretch=1.5)),
     ("sphere-tile-6x10x256", Shell(6, 10, 256)),
+    ("sphere-odd-6x16x256", Shell(6, 16, 256, radial_stretch=2.0)),
+    ("sphere-odd-6x8x512", Shell(6, 8, 512)),
+    ("sphere-rows-12x24x256", Shell(12, 24, 256, radial_stretch=1.5)),
 ]
 
 
