@@ -581,18 +581,23 @@ long long apply(cps_handle* h, int l, const T* x, T* y, const T* dotv)
     return grid_of(L.g.nr, bpa);
 }
 
-void reduce(cps_handle* h, long long nparts, int slot, long long first = 0)
+// ops: the conjugate-gradient scalar updates done in the same launch
+// (RED_* of k_reduce_cg)
+void reduce(cps_handle* h, long long nparts, int slot, long long first = 0, int ops = 0)
 {
-    k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p + first, nparts, h->sc.p + slot);
+    if (ops)
+        k_reduce_cg<<<1, kBlock, 0, h->stream>>>(h->partial.p + first, nparts, h->sc.p, slot, ops);
+    else
+        k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p + first, nparts, h->sc.p + slot);
     LAUNCH_CHECK();
 }
 
 template <typename T, typename U>
-void dot(cps_handle* h, long long n, const T* u, const U* v, int slot)
+void dot(cps_handle* h, long long n, const T* u, const U* v, int slot, int ops = 0)
 {
     k_dot<T, U><<<vgrid(n), kBlock, 0, h->stream>>>(n, u, v, h->partial.p);
     LAUNCH_CHECK();
-    reduce(h, vgrid(n), slot);
+    reduce(h, vgrid(n), slot, 0, ops);
 }
 
 // red: r is residual(red)'s output, of which only the red cells are read.
@@ -744,9 +749,11 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
 // Mixed form only: rhs_cast -- the FP32 right-hand side (in / scale) is
 // already in place (the conjugate-gradient step wrote it); out == nullptr --
 // the correction stays in FP32 (the next kernel forms it where it reads it)
-// and only the dot products are taken.
+// and only the dot products are taken.  rz_ops / zq_ops: scalar updates done
+// by the launch that stores r.z / z.q (RED_* of k_reduce_cg).
 void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1,
-                  const double* zq = nullptr, bool rhs_cast = false)
+                  const double* zq = nullptr, bool rhs_cast = false, int rz_ops = 0,
+                  int zq_ops = 0)
 {
     const long long n = h->lv[0].n;
     if (h->opts.precision == 0) {
@@ -756,10 +763,10 @@ void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1
             parts = vcycle<double>(h, in, out, true, rz_slot >= 0);
         }
         if (rz_slot >= 0) {
-            if (parts) reduce(h, parts, rz_slot);
-            else dot<double, double>(h, n, in, out, rz_slot);
+            if (parts) reduce(h, parts, rz_slot, 0, rz_ops);
+            else dot<double, double>(h, n, in, out, rz_slot, rz_ops);
         }
-        if (zq) dot<double, double>(h, n, out, zq, S_ZQ);
+        if (zq) dot<double, double>(h, n, out, zq, S_ZQ, zq_ops);
     } else {
         float* b = h->lv[0].b32.p;
         float* x = h->lv[0].x32.p;
@@ -781,8 +788,8 @@ void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1
         k_cast_dots<<<vg, kBlock, 0, h->stream>>>(n, x, out, h->sc.p, S_SCALE, in, zq,
                                                   h->partial.p, h->partial.p + vg);
         LAUNCH_CHECK();
-        if (rz_slot >= 0) reduce(h, vg, rz_slot);
-        if (zq) reduce(h, vg, S_ZQ, vg);
+        if (rz_slot >= 0) reduce(h, vg, rz_slot, 0, rz_ops);
+        if (zq) reduce(h, vg, S_ZQ, vg, zq_ops);
     }
 }
 
@@ -1429,19 +1436,19 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             precondition(h, r, z, S_RZ);
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, z, p);
             LAUNCH_CHECK();
-            reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
+            reduce(h, apply<double>(h, 0, p, q, p), S_PQ, 0, RED_ALPHA);
             // the mixed form on the fused path: the step also casts the new
             // residual into the FP32 right-hand side, and the direction is
             // formed from the FP32 correction (no FP64 cast pass, z not stored)
             const bool cast_fused = fused && mixed;
             float* r32 = cast_fused ? h->lv[0].b32.p : nullptr;
             // x += alpha p, r -= alpha q and ||r||^2 (the first iteration's
-            // step, and the tail of every later body).  On the fused path the
-            // next direction kernel applies x += alpha p instead (it streams
-            // p anyway), and the last update runs after the loop.
+            // step, and the tail of every later body; alpha comes from the
+            // launch that stored p.q).  On the fused path the next direction
+            // kernel applies x += alpha p instead (it streams p anyway), and
+            // the last update runs after the loop.
             double* plast = p; // direction of the last step
             auto step = [&](double* pk) {
-                SCALAR_KERNEL(h, k_cg_alpha);
                 k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, fused ? nullptr : x, r, pk,
                                                               q, h->partial.p, r32);
                 LAUNCH_CHECK();
@@ -1461,12 +1468,11 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                     double* pc = parity ? pn : p; // direction of the previous iteration
                     double* pnx = parity ? p : pn;
                     run_body(h, G_CG0 + parity, [&] {
-                        k_copy_scalar<<<1, 1, 0, h->stream>>>(h->sc.p, S_RZ_OLD, S_RZ);
-                        LAUNCH_CHECK();
+                        // the launch that stores the new r.z keeps the old one
+                        // and forms beta (flexible: the one that stores z.q)
                         precondition(h, r, cast_fused ? nullptr : z, S_RZ, flexible ? q : nullptr,
-                                     cast_fused);
-                        k_cg_beta<<<1, 1, 0, h->stream>>>(h->sc.p, flexible);
-                        LAUNCH_CHECK();
+                                     cast_fused, flexible ? RED_SHIFT_RZ : RED_SHIFT_RZ | RED_BETA,
+                                     flexible ? RED_FBETA : 0);
                         if (fused) {
                             const MarchShape ms = stencil_shape(g0);
                             {
@@ -1483,12 +1489,12 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                                         h->sc.p + S_ALPHA);
                                 LAUNCH_CHECK();
                             }
-                            reduce(h, ms.grid, S_PQ);
+                            reduce(h, ms.grid, S_PQ, 0, RED_ALPHA);
                             step(pnx);
                         } else {
                             k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
                             LAUNCH_CHECK();
-                            reduce(h, apply<double>(h, 0, p, q, p), S_PQ);
+                            reduce(h, apply<double>(h, 0, p, q, p), S_PQ, 0, RED_ALPHA);
                             step(p);
                         }
                     });

@@ -236,10 +236,9 @@ __device__ __forceinline__ double block_sum(double v)
     return t;
 }
 
-// *out = sum of partial[0..n) in a fixed order (one block; four
-// independent accumulators per thread keep several loads in flight).
-__device__ __forceinline__ void d_reduce(Blk bk, const double* __restrict__ partial, long long n,
-                                                   double* __restrict__ out)
+// The sum of partial[0..n) in a fixed order, valid in thread 0 (one block;
+// four independent accumulators per thread keep several loads in flight).
+__device__ __forceinline__ double d_reduce_sum(const double* __restrict__ partial, long long n)
 {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     long long i = threadIdx.x;
@@ -250,7 +249,14 @@ __device__ __forceinline__ void d_reduce(Blk bk, const double* __restrict__ part
         s3 += partial[i + 3 * kBlock];
     }
     for (; i < n; i += kBlock) s0 += partial[i];
-    const double s = block_sum((s0 + s1) + (s2 + s3));
+    return block_sum((s0 + s1) + (s2 + s3));
+}
+
+// *out = sum of partial[0..n)
+__device__ __forceinline__ void d_reduce(Blk bk, const double* __restrict__ partial, long long n,
+                                                   double* __restrict__ out)
+{
+    const double s = d_reduce_sum(partial, n);
     if (threadIdx.x == 0) *out = s;
 }
 
@@ -2273,12 +2279,23 @@ __global__ void __launch_bounds__(kBlock) k_ir_update(long long n, double* __res
 // device scalars (the sc[] slots declared at the top) so that no host round trip is
 // needed.
 
-// CG / flexible CG: alpha = rz / pq
-__global__ void k_cg_alpha(double* sc) { sc[S_ALPHA] = sc[S_RZ] / sc[S_PQ]; }
-// beta = rz_new / rz_old (CG) or -alpha zq / rz_old (flexible, Polak-Ribiere)
-__global__ void k_cg_beta(double* sc, int flexible)
+// CG / flexible CG, in the launch of the reduction they follow:
+// sc[slot] = sum of partial[0..n), and thread 0 does the scalar updates:
+// RED_SHIFT_RZ keeps the old r.z in S_RZ_OLD before the store, then
+// RED_BETA (beta = rz_new / rz_old), RED_FBETA (flexible, Polak-Ribiere:
+// beta = -alpha zq / rz_old) or RED_ALPHA (alpha = rz / pq).
+enum { RED_SHIFT_RZ = 1, RED_BETA = 2, RED_FBETA = 4, RED_ALPHA = 8 };
+__global__ void __launch_bounds__(kBlock) k_reduce_cg(const double* __restrict__ partial,
+                                                      long long n, double* __restrict__ sc,
+                                                      int slot, int ops)
 {
-    sc[S_BETA] = flexible ? -sc[S_ALPHA] * sc[S_ZQ] / sc[S_RZ_OLD] : sc[S_RZ] / sc[S_RZ_OLD];
+    const double s = d_reduce_sum(partial, n);
+    if (threadIdx.x != 0) return;
+    if (ops & RED_SHIFT_RZ) sc[S_RZ_OLD] = sc[S_RZ];
+    sc[slot] = s;
+    if (ops & RED_BETA) sc[S_BETA] = sc[S_RZ] / sc[S_RZ_OLD];
+    if (ops & RED_FBETA) sc[S_BETA] = -sc[S_ALPHA] * sc[S_ZQ] / sc[S_RZ_OLD];
+    if (ops & RED_ALPHA) sc[S_ALPHA] = sc[S_RZ] / sc[S_PQ];
 }
 __global__ void k_bicg_beta(double* sc)
 {
@@ -2770,7 +2787,8 @@ __global__ void __launch_bounds__(kBlock) kb_reduce(const int* __restrict__ acti
 enum { SOP_CG_ALPHA = 0, SOP_CG_BETA, SOP_FCG_BETA, SOP_BICG_BETA, SOP_BICG_ALPHA, SOP_BICG_OMEGA,
        SOP_COPY, SOP_SQRT, SOP_SET };
 
-// scalar recurrences, one thread per problem (same formulas as k_cg_* etc.)
+// scalar recurrences, one thread per problem (the formulas of k_reduce_cg's
+// updates and of k_bicg_*)
 template <typename T>
 __global__ void kb_scalar(const int* __restrict__ active, const PDesc<T>* __restrict__ pd, int nprob,
                           int op, int dst, int src, double value)
