@@ -471,9 +471,11 @@ void plane_half_sweep(cps_handle* h, int l, int parity, const T* b, T* x)
 // dot (two colours on marching levels): the last two passes, which leave
 // every cell final, write partial sums of b . x at dot[0 ..) and after
 // them; returns the number of partial sums written (0 without dot).
+// first_done (from zero, two colours): the caller has already made the
+// zero-iterate first pass (x = b / D on colour 0).
 template <typename T>
 long long smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool reverse,
-                 bool from_zero = false, double* dot = nullptr)
+                 bool from_zero = false, double* dot = nullptr, bool first_done = false)
 {
     if (h->opts.smoother == 1) {
         if (from_zero) fill<T>(h, x, h->lv[l].n, T(0));
@@ -492,7 +494,7 @@ long long smooth(cps_handle* h, int l, const T* b, T* x, int sweeps, bool revers
                             with_dot ? dot + parts : nullptr, !(skip && pass == 0));
     };
     const int first = skip ? 1 : 0;
-    if (skip) pass_at(0);
+    if (skip && !first_done) pass_at(0);
     // the full passes run back to back: one event pair around all of them
     ProfScope ps(h, CPS_KERNEL_GS, l, last - first);
     for (int pass = first; pass < last; ++pass) pass_at(pass);
@@ -688,8 +690,11 @@ void vpost_tile(cps_handle* h, int l, const T* b, const T* xi, T* xo, const T* e
 // One V(2,2) cycle with level-0 right-hand side b0 and iterate x0 (in place).
 // dot: the last level-0 passes leave partial sums of b0 . x0 in h->partial;
 // returns their number (0 when the cycle cannot provide them).
+// zero_done (from zero, the per-kernel finest level): x0 already holds the
+// zero-iterate first pass (the conjugate-gradient step made it).
 template <typename T>
-long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool dot = false)
+long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool dot = false,
+                 bool zero_done = false)
 {
     const int L = h->L;
     if (L == 1) {
@@ -708,7 +713,7 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
             continue;
         }
         // coarse corrections start from zero
-        smooth<T>(h, l, b, x, 2, false, l > 0 || x0_zero);
+        smooth<T>(h, l, b, x, 2, false, l > 0 || x0_zero, nullptr, l == 0 && zero_done);
         // point red-black smoothing ends on the black pass: on row-pair
         // levels only the red residual is formed and restricted (in one pass
         // where the level's shape allows it)
@@ -750,17 +755,18 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
 // already in place (the conjugate-gradient step wrote it); out == nullptr --
 // the correction stays in FP32 (the next kernel forms it where it reads it)
 // and only the dot products are taken.  rz_ops / zq_ops: scalar updates done
-// by the launch that stores r.z / z.q (RED_* of k_reduce_cg).
+// by the launch that stores r.z / z.q (RED_* of k_reduce_cg).  zero_done
+// (FP64): out already holds the cycle's zero-iterate first pass of in.
 void precondition(cps_handle* h, const double* in, double* out, int rz_slot = -1,
                   const double* zq = nullptr, bool rhs_cast = false, int rz_ops = 0,
-                  int zq_ops = 0)
+                  int zq_ops = 0, bool zero_done = false)
 {
     const long long n = h->lv[0].n;
     if (h->opts.precision == 0) {
         long long parts;
         {
             ProfScope ps(h, CPS_KERNEL_VCYCLE, 0);
-            parts = vcycle<double>(h, in, out, true, rz_slot >= 0);
+            parts = vcycle<double>(h, in, out, true, rz_slot >= 0, zero_done);
         }
         if (rz_slot >= 0) {
             if (parts) reduce(h, parts, rz_slot, 0, rz_ops);
@@ -1442,6 +1448,11 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             // formed from the FP32 correction (no FP64 cast pass, z not stored)
             const bool cast_fused = fused && mixed;
             float* r32 = cast_fused ? h->lv[0].b32.p : nullptr;
+            // FP64 point smoothing with the per-kernel finest level: the step
+            // also makes the next cycle's zero-iterate first pass, z = r / D
+            // on the red cells (k_cg_step_z)
+            const bool zfused = fused && !mixed && h->opts.smoother == 0 && h->ncol == 2 &&
+                                !h->lv[0].tile;
             // x += alpha p, r -= alpha q and ||r||^2 (the first iteration's
             // step, and the tail of every later body; alpha comes from the
             // launch that stored p.q).  On the fused path the next direction
@@ -1449,8 +1460,12 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             // the last update runs after the loop.
             double* plast = p; // direction of the last step
             auto step = [&](double* pk) {
-                k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, fused ? nullptr : x, r, pk,
-                                                              q, h->partial.p, r32);
+                if (zfused)
+                    k_cg_step_z<<<vgrid(n), kBlock, 0, h->stream>>>(g0, h->lv[0].G64.p, h->lv[0].gk,
+                                                                    h->sc.p, r, q, z, h->partial.p);
+                else
+                    k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, fused ? nullptr : x,
+                                                                  r, pk, q, h->partial.p, r32);
                 LAUNCH_CHECK();
                 reduce(h, vgrid(n), S_RR);
                 copy_norm(h, S_RR);
@@ -1472,7 +1487,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                         // and forms beta (flexible: the one that stores z.q)
                         precondition(h, r, cast_fused ? nullptr : z, S_RZ, flexible ? q : nullptr,
                                      cast_fused, flexible ? RED_SHIFT_RZ : RED_SHIFT_RZ | RED_BETA,
-                                     flexible ? RED_FBETA : 0);
+                                     flexible ? RED_FBETA : 0, zfused);
                         if (fused) {
                             const MarchShape ms = stencil_shape(g0);
                             {
@@ -1513,6 +1528,8 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                 // is zero, and so is the pending update that the fused product
                 // applies with it)
                 fill<double>(h, plast, n, 0.0);
+                // the next body expects the zero-iterate pass of the new r
+                if (zfused) gs_pass<double>(h, 0, 0, r, z, true);
                 if (cast_fused) {
                     k_cast<double, float><<<nblk(n), kBlock, 0, h->stream>>>(n, r, r32, h->sc.p,
                                                                              S_SCALE, 1);

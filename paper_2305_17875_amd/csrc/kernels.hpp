@@ -2345,6 +2345,53 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* _
     d_cg_step(self_blk(), n, sc, x, r, p, q, partial, r32);
 }
 
+// The CG step (r -= alpha q, partial sums of r^2; the iterate's update is
+// carried by the direction kernel) on a level whose rows are whole
+// wavefronts (n_phi / 2 a multiple of 64), which also makes the next
+// V-cycle's first pass: z = r / D on the red cells (colour 0), with D and
+// the division of the zero-iterate colour pass (the same values).  Every
+// cell of a row of one parity plane has one colour, (a + b + s) mod 2, so a
+// wavefront takes 64 cells of one row and forms D once.
+__global__ void __launch_bounds__(kBlock) k_cg_step_z(Geo g, const double* __restrict__ G,
+                                                      long long gk,
+                                                      const double* __restrict__ sc,
+                                                      double* __restrict__ r,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ z,
+                                                      double* __restrict__ partial)
+{
+    const Blk bk = self_blk();
+    const double al = sc[S_ALPHA];
+    // the segment arithmetic is wavefront-uniform and 32-bit (a level's
+    // cells are fewer than 2^31): one scalar division chain a segment
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = (int)threadIdx.x & 63;
+    const unsigned spr = (unsigned)g.nh / 64;              // wavefront segments a row
+    const unsigned rows = (unsigned)g.nr * (unsigned)g.nt; // rows of a parity plane
+    const unsigned nseg = 2 * rows * spr;
+    const unsigned stride = bk.G * (kBlock / 64);
+    double acc = 0.0;
+    for (unsigned S = bk.L * (kBlock / 64) + (unsigned)w; S < nseg; S += stride) {
+        const unsigned R = S / spr; // row of [2][n_r][n_theta]
+        const unsigned sp = R / rows;
+        const unsigned ab = R - sp * rows;
+        const unsigned a = ab / (unsigned)g.nt, b = ab - a * (unsigned)g.nt;
+        const long long i = (long long)R * g.nh + (long long)(S - R * spr) * 64 + lane;
+        const double v = __builtin_fma(-al, q[i], r[i]);
+        r[i] = v;
+        acc = __builtin_fma(v, v, acc);
+        if (((a + b + sp) & 1) == 0) {
+            const long long ci = ab;
+            const double D = -(G[ci] + ((int)a < g.nr - 1 ? G[ci + g.nt] : 0.0) + G[4 * gk + ci] +
+                               ((int)b < g.nt - 1 ? G[4 * gk + ci + 1] : 0.0) +
+                               2.0 * G[8 * gk + ci]);
+            z[i] = v / D;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[bk.L] = acc;
+}
+
 // x += alpha p: the update the last step of a solve leaves pending when the
 // direction kernel carries the iterate's updates
 __global__ void __launch_bounds__(kBlock) k_cg_x(long long n, const double* __restrict__ sc,
