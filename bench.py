@@ -101,7 +101,7 @@ def fused_transfer(f, c):
     return segs in (1, 2) and ct % (4 if segs == 1 else 2) == 0
 
 
-def vcycle_bytes(levels, word, phi_invariant=True, fused=False):
+def vcycle_bytes(levels, word, phi_invariant=True, fused=False, red_prolong=False):
     """Algorithmic HBM bytes of one V(2,2) cycle from a zero iterate on the
     7-point hierarchy with point red-black smoothing: per smoothed level of n
     cells, the zero-iterate pass (b and x of one colour: n words), seven full
@@ -120,7 +120,11 @@ def vcycle_bytes(levels, word, phi_invariant=True, fused=False):
 
     fused (the library's cycles): where fused_transfer holds, the red residual is
     formed inside the restriction: x in, red b in, n/8 out, and r is neither
-    written nor read back -- 15.25 n words."""
+    written nor read back -- 15.25 n words.
+
+    red_prolong (the library's cycles): the prolongation corrects only the
+    red cells (the black pass that follows overwrites the black ones): red x
+    in and out, n/8 in -- n words a level less."""
     total = 0
     for k, (nr, nt, np_) in enumerate(levels[:-1]):
         n = nr * nt * np_
@@ -129,6 +133,8 @@ def vcycle_bytes(levels, word, phi_invariant=True, fused=False):
         words = 16.25 if red else 17.75
         if fused and fused_transfer(levels[k], levels[k + 1]):
             words = 15.25
+        if red_prolong:
+            words -= 1.0
         total += (words * n + 9 * coef) * word
     nc = levels[-1][0] * levels[-1][1] * levels[-1][2]
     return int(round(total)) + nc * nc * 8 + 2 * nc * word
@@ -245,7 +251,7 @@ def vcycle_rate(prof, levels, word, steps, graph_us=None, traffic=None):
         return None
     eager = ms / cnt * 1e-3
     t = graph_us * 1e-6 if graph_us else eager
-    b = vcycle_bytes(levels, word, fused=True)
+    b = vcycle_bytes(levels, word, fused=True, red_prolong=True)
     out = {"bytes_per_cycle": b, "avg_us": t * 1e6, "achieved_GBs": b / t / 1e9,
            "frac_of_peak": b / t / 1e9 / HBM_PEAK_GBS, "cycles_per_step": cnt / steps,
            "timing": ("hipGraph replay of 10 cycles, 5 launches between events "

@@ -647,14 +647,17 @@ bool red_residual(const cps_handle* h, int l)
     return h->opts.smoother == 0 && marching(h) && h->ncol == 2 && row_pairs(h->lv[l].geo);
 }
 
+// red: only level l's red cells are corrected (a red-black post-smoothing
+// follows, whose first pass overwrites every black cell unread)
 template <typename T>
-void prolong_add(cps_handle* h, int l, const T* e, T* x)
+void prolong_add(cps_handle* h, int l, const T* e, T* x, bool red = false)
 {
     const Geo& f = h->lv[l].geo;
     const Geo& c = h->lv[l + 1].geo;
     const MarchShape ms = march_shape(c);
     ProfScope ps(h, CPS_KERNEL_PROLONG, l);
-    k_prolong<T><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, e, x);
+    if (red) k_prolong<T, 1><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, e, x);
+    else k_prolong<T, 0><<<ms.grid, kBlock, 0, h->stream>>>(f, c, ms.bpa, ms.ch, e, x);
     LAUNCH_CHECK();
 }
 
@@ -739,7 +742,9 @@ long long vcycle(cps_handle* h, const T* b0, T* x0, bool x0_zero = false, bool d
             vpost_tile<T>(h, l, b, x, xtl<T>(h, l), e);
             continue;
         }
-        prolong_add<T>(h, l, e, x);
+        // point red-black post-smoothing starts with the black pass: only
+        // the red cells need the correction
+        prolong_add<T>(h, l, e, x, h->opts.smoother == 0 && h->ncol == 2);
         const bool d = dot && l == 0 && marching(h);
         parts = smooth<T>(h, l, b, x, 2, true, false, d ? h->partial.p : nullptr);
     }

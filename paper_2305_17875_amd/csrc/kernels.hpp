@@ -1967,7 +1967,11 @@ __global__ void __launch_bounds__(64 * rr_waves(SEGS))
 
 // x += P e (trilinear); the thread writes fine rows 2J, 2J+1 and fine phi
 // 4jc .. 4jc+3 on the two fine planes of every coarse plane of its chunk.
-template <typename T>
+// RED: only the red cells (colour 0) are corrected -- read and written.  A
+// red-black post-smoothing starts with the black pass, which reads only red
+// values and overwrites every black cell, so the black cells' correction is
+// never read; it is not made (half the fine level's bytes).
+template <typename T, int RED = 0>
 __device__ __forceinline__ void d_prolong(Blk bk, Geo f, Geo c, int bpa, int ch,
                                                     const T* __restrict__ e,
                                                     T* __restrict__ x)
@@ -2012,6 +2016,8 @@ __device__ __forceinline__ void d_prolong(Blk bk, Geo f, Geo c, int bpa, int ch,
     for (int rr = 0; rr < 2; ++rr)
         for (int sp = 0; sp < 2; ++sp)
             fo[rr][sp] = (long long)sp * f.P + (long long)(2 * p.J + rr) * f.nh + 2 * p.jc;
+    // the red cells of fine row 2J + rr sit in plane (a + rr) mod 2 at fine
+    // plane a: sp == rr on the even plane 2I, sp != rr on the odd one
     for (int I = p.I0; I < p.I1; ++I) {
         plane(I + 1, tp);
         T* x0 = x + (long long)(2 * I) * f.rowlen;
@@ -2021,19 +2027,23 @@ __device__ __forceinline__ void d_prolong(Blk bk, Geo f, Geo c, int bpa, int ch,
         for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp) {
-                y0[rr][sp] = *reinterpret_cast<const Vec2<T>*>(x0 + fo[rr][sp]);
-                y1[rr][sp] = *reinterpret_cast<const Vec2<T>*>(x1 + fo[rr][sp]);
+                if (!RED || sp == rr) y0[rr][sp] = *reinterpret_cast<const Vec2<T>*>(x0 + fo[rr][sp]);
+                if (!RED || sp != rr) y1[rr][sp] = *reinterpret_cast<const Vec2<T>*>(x1 + fo[rr][sp]);
             }
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
             for (int sp = 0; sp < 2; ++sp) {
-                y0[rr][sp].x += w0 * t0[rr][sp] + w1 * tm[rr][sp];
-                y0[rr][sp].y += w0 * t0[rr][sp + 2] + w1 * tm[rr][sp + 2];
-                y1[rr][sp].x += w0 * t0[rr][sp] + w1 * tp[rr][sp];
-                y1[rr][sp].y += w0 * t0[rr][sp + 2] + w1 * tp[rr][sp + 2];
-                *reinterpret_cast<Vec2<T>*>(x0 + fo[rr][sp]) = y0[rr][sp];
-                *reinterpret_cast<Vec2<T>*>(x1 + fo[rr][sp]) = y1[rr][sp];
+                if (!RED || sp == rr) {
+                    y0[rr][sp].x += w0 * t0[rr][sp] + w1 * tm[rr][sp];
+                    y0[rr][sp].y += w0 * t0[rr][sp + 2] + w1 * tm[rr][sp + 2];
+                    *reinterpret_cast<Vec2<T>*>(x0 + fo[rr][sp]) = y0[rr][sp];
+                }
+                if (!RED || sp != rr) {
+                    y1[rr][sp].x += w0 * t0[rr][sp] + w1 * tp[rr][sp];
+                    y1[rr][sp].y += w0 * t0[rr][sp + 2] + w1 * tp[rr][sp + 2];
+                    *reinterpret_cast<Vec2<T>*>(x1 + fo[rr][sp]) = y1[rr][sp];
+                }
             }
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr)
@@ -2045,12 +2055,12 @@ __device__ __forceinline__ void d_prolong(Blk bk, Geo f, Geo c, int bpa, int ch,
     }
 }
 
-template <typename T>
+template <typename T, int RED>
 __global__ void __launch_bounds__(kBlock) k_prolong(Geo f, Geo c, int bpa, int ch,
                                                     const T* __restrict__ e,
                                                     T* __restrict__ x)
 {
-    d_prolong<T>(self_blk(), f, c, bpa, ch, e, x);
+    d_prolong<T, RED>(self_blk(), f, c, bpa, ch, e, x);
 }
 
 // Natural [r][theta][phi] <-> parity-split order.  y_split = x_nat - *mean

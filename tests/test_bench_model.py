@@ -60,6 +60,10 @@ def test_paper_scale_figures(bench):
     # the cycle's fused transfers on the two finest levels: one word a
     # cell less there (25,165,824 + 3,145,728 cells)
     assert bench.vcycle_bytes(levels, 8, fused=True) == 3_758_344_704 - 8 * 28_311_552
+    # and the red-only prolongation: one word a cell less on every smoothed
+    # level (28,760,064 cells)
+    assert bench.vcycle_bytes(levels, 8, fused=True, red_prolong=True) == \
+        3_758_344_704 - 8 * 28_311_552 - 8 * 28_760_064
 
 
 def test_vcycle_bytes_red_residual_levels(bench):
@@ -114,9 +118,9 @@ def test_vcycle_rate_reports_cycles_per_solve(bench):
     prof[vc] = (150 * 0.93, 150)  # 150 cycles of 930 us in 2 solves
     out = bench.vcycle_rate(prof, levels, 8, 2)
     assert out["cycles_per_step"] == 75
-    assert out["bytes_per_cycle"] == bench.vcycle_bytes(levels, 8, fused=True)
+    assert out["bytes_per_cycle"] == bench.vcycle_bytes(levels, 8, fused=True, red_prolong=True)
     assert bench.vcycle_rate(prof, levels, 4, 2)["bytes_per_cycle"] == \
-        bench.vcycle_bytes(levels, 4, fused=True)
+        bench.vcycle_bytes(levels, 4, fused=True, red_prolong=True)
     assert out["avg_us"] == pytest.approx(930.0)
     assert out["frac_of_peak"] == pytest.approx(out["bytes_per_cycle"] / 930e-6 / 1e9 / 8000.0)
     # with the graph-replayed time: the rate is on it, the eager span beside it
