@@ -219,7 +219,10 @@ void b_vcycle(cps_batch* B, BatchGroup& G)
     for (int l = G.Lmax - 2; l >= 0; --l) {
         blaunch_tile(B, G.tile[l], kb_vpost_tile<float>, l);
         if (!G.gs[l].count) continue;
-        blaunch(B, G.xfer[l], kb_prolong<float>, l);
+        // point red-black post-smoothing starts with the black pass: only
+        // the red cells need the correction (as vcycle())
+        if (!G.plane && G.ncol == 2) blaunch(B, G.xfer[l], kb_prolong<float, 1>, l);
+        else blaunch(B, G.xfer[l], kb_prolong<float, 0>, l);
         b_smooth(B, G, l, true, false);
     }
 }

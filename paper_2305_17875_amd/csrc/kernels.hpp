@@ -2739,7 +2739,8 @@ __global__ void __launch_bounds__(64 * rr_waves(SEGS))
     d_resrestrict<T, SEGS>(bk, d.g, d.G, d.gk, c, ms.bpa, ms.ch, d.b, d.x, P.lv[level + 1].b, sh);
 }
 
-template <typename T>
+// red: only the red cells are corrected (a red-black post-smoothing follows)
+template <typename T, int RED>
 __global__ void __launch_bounds__(kBlock) kb_prolong(const BItem* __restrict__ items,
                                                      const int* __restrict__ active,
                                                      const PDesc<T>* __restrict__ pd, int level)
@@ -2748,7 +2749,7 @@ __global__ void __launch_bounds__(kBlock) kb_prolong(const BItem* __restrict__ i
     const PDesc<T>& P = pd[it.prob];
     const MarchShape ms = march_shape(P.lv[level + 1].g);
     const LDesc<T>& c = P.lv[level + 1];
-    d_prolong<T>(bk, P.lv[level].g, c.g, ms.bpa, ms.ch, c.tile ? c.xt : c.x, P.lv[level].x);
+    d_prolong<T, RED>(bk, P.lv[level].g, c.g, ms.bpa, ms.ch, c.tile ? c.xt : c.x, P.lv[level].x);
 }
 
 template <typename T>
