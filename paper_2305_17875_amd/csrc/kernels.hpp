@@ -1040,6 +1040,11 @@ struct Dir {
     {
         return __builtin_fma(beta, p[i], z[i]);
     }
+    // the same from p_old[i] already in a register
+    __device__ __forceinline__ T from(T pold, long long i) const
+    {
+        return __builtin_fma(beta, pold, z[i]);
+    }
 };
 // The same with z the FP32 correction of the mixed form, cast as k_cast_dots
 // casts it (z = (double) e * s, rounded before the direction is formed).
@@ -1052,21 +1057,29 @@ struct DirCast {
     {
         return __builtin_fma(beta, p[i], mul_t((double)e[i], s));
     }
+    __device__ __forceinline__ double from(double pold, long long i) const
+    {
+        return __builtin_fma(beta, pold, mul_t((double)e[i], s));
+    }
 };
 
 // below / above: load the theta row below / above the pair (a caller that
-// has them from the adjacent wavefronts passes false).
+// has them from the adjacent wavefronts passes false); up == false: the
+// column at a + 1 is the caller's.
 template <typename T, typename X>
 __device__ __forceinline__ void march2_load(const Geo& g, const X& x, const March2& p, int a,
-                                            Nb4<T>& n, bool below = true, bool above = true)
+                                            Nb4<T>& n, bool below = true, bool above = true,
+                                            bool up = true)
 {
     const int nh = g.nh, j = p.j;
     const long long base = (long long)a * g.rowlen + p.r0;
     const long long ab = a < g.nr - 1 ? base + g.rowlen : base;
-    n.up.u0 = x(ab);
-    n.up.v0 = x(g.P + ab);
-    n.up.u1 = x(ab + nh);
-    n.up.v1 = x(g.P + ab + nh);
+    if (up) {
+        n.up.u0 = x(ab);
+        n.up.v0 = x(g.P + ab);
+        n.up.u1 = x(ab + nh);
+        n.up.v1 = x(g.P + ab + nh);
+    }
     if (below) {
         const long long tl = p.b0 > 0 ? base - nh : base;
         n.utm0 = x(tl);
@@ -1330,7 +1343,9 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
 // X: the field p is formed from (Dir, or DirCast in the mixed form).
 // xs != nullptr: also the previous step's pending update of the iterate,
 // xs += alpha p_old on the thread's own cells (one fma, as in d_cg_step),
-// so the step itself need not stream x and p.
+// so the step itself need not stream x and p.  p_old of plane a + 1 is
+// loaded once, forms the direction there (X.from) and makes that plane's
+// update.
 template <typename T, int LTAG, typename X_>
 __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __restrict__ G,
                                                              long long gk, int bpa, int ch,
@@ -1353,21 +1368,36 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
         const long long o[4] = {0, g.P, g.nh, g.P + g.nh};
         Col4<T> cm, c;
         if (live) march2_start<T>(g, X, p, cm, c);
+        // the pending update of the chunk's first plane; each later plane's
+        // comes with the loads that form its direction (p_old read once)
+        if (live && xs) {
+            const long long b0 = (long long)p.a0 * g.rowlen + p.r0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                st_once(xs + b0 + o[k], __builtin_fma(alpha, pold[b0 + o[k]], ld_once(xs + b0 + o[k])));
+        }
         for (int a = p.a0, buf = 0; a < p.a1; ++a, buf ^= 1) {
             Nb4<T> nb;
             const long long base = (long long)a * g.rowlen + p.r0;
+            const long long ab = a < g.nr - 1 ? base + g.rowlen : base;
+            const bool upd = xs && a + 1 < p.a1; // plane a + 1 is the chunk's
             T xo[4], po[4];
             if (live) {
                 sh[buf][w][0][lane] = c.u0;
                 sh[buf][w][1][lane] = c.v0;
                 sh[buf][w][2][lane] = c.u1;
                 sh[buf][w][3][lane] = c.v1;
-                march2_load<T>(g, X, p, a, nb, w == 0, w == kPairs - 1);
-                if (xs) {
+                march2_load<T>(g, X, p, a, nb, w == 0, w == kPairs - 1, !xs);
+                if (xs) { // the direction at a + 1 from p_old held for the update
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        xo[k] = ld_once(xs + base + o[k]);
-                        po[k] = pold[base + o[k]];
+                    for (int k = 0; k < 4; ++k) po[k] = pold[ab + o[k]];
+                    nb.up.u0 = X.from(po[0], ab + o[0]);
+                    nb.up.v0 = X.from(po[1], ab + o[1]);
+                    nb.up.u1 = X.from(po[2], ab + o[2]);
+                    nb.up.v1 = X.from(po[3], ab + o[3]);
+                    if (upd) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) xo[k] = ld_once(xs + ab + o[k]);
                     }
                 }
             }
@@ -1389,7 +1419,7 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
                 st_once(pnew + base + o[k], own[k]);
                 st_once(q + base + o[k], yk[k]);
                 acc = __builtin_fma((double)yk[k], (double)own[k], acc);
-                if (xs) st_once(xs + base + o[k], __builtin_fma(alpha, po[k], xo[k]));
+                if (upd) st_once(xs + ab + o[k], __builtin_fma(alpha, po[k], xo[k]));
             }
             cm = c;
             c = nb.up;
