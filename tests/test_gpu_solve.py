@@ -274,3 +274,42 @@ def test_reported_residual_is_that_of_the_answer(precision, accel, wide, tol):
         assert res.rel_residual <= tol
     if tol == 1e-10:
         assert res.status == cps.CPS_OK
+
+
+def _launches_model(levels, fp32):
+    """Kernel launches of one point red-black V(2,2) cycle from zero on a
+    sphere's hierarchy: a level on the 8^3-tile path (at most 64 K cells in
+    FP64, 512 K in FP32, n_phi a multiple of 8, even n_r and n_theta) takes
+    2; any other smoothed level 4 pre-passes, the transfer (1 where
+    bench.fused_transfer holds, else residual and restriction), the
+    prolongation and 4 post-passes; the coarsest level 1."""
+    import bench
+    total = 1
+    for k, (nr, nt, np_) in enumerate(levels[:-1]):
+        n = nr * nt * np_
+        tile = np_ % 8 == 0 and nr % 2 == 0 and nt % 2 == 0 and n <= (1 << (19 if fp32 else 16))
+        if tile:
+            total += 2
+        else:
+            total += 4 + (1 if bench.fused_transfer(levels[k], levels[k + 1]) else 2) + 1 + 4
+    return total
+
+
+@pytest.mark.parametrize("shape", [(32, 64, 512), (24, 48, 256), (16, 32, 256)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_launches_follow_the_level_rules(shape, precision):
+    """The kernel nodes of a captured V-cycle (cps_time_vcycle) are those the
+    level rules give: the tile path's size limits and bench.py's rule for
+    the fused red residual and restriction, which its byte model counts."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    g = Shell(*shape, radial_stretch=2.0)
+    stream = torch.cuda.Stream()
+    s = cps.Solver(g, precision=precision, accel=1, stream=stream)
+    try:
+        _, launches = s.time_vcycle(cycles=2, reps=1)
+        want = _launches_model([tuple(l) for l in s.levels], precision == 1)
+    finally:
+        s.close()
+    log("vcycle launches", shape, precision, launches, want)
+    assert launches == want, (launches, want)
