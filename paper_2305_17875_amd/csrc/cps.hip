@@ -1447,7 +1447,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             precondition(h, r, z, S_RZ);
             k_copy<double><<<nblk(n), kBlock, 0, h->stream>>>(n, z, p);
             LAUNCH_CHECK();
-            reduce(h, apply<double>(h, 0, p, q, p), S_PQ, 0, RED_ALPHA);
+            reduce(h, apply<double>(h, 0, p, q, p), S_PQ, 0, RED_ALPHA | RED_SHIFT_ALPHA);
             // the mixed form on the fused path: the step also casts the new
             // residual into the FP32 right-hand side, and the direction is
             // formed from the FP32 correction (no FP64 cast pass, z not stored)
@@ -1480,7 +1480,11 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
             // later iterations: new direction from the preconditioned
             // residual, then the step; with the fused product the direction
-            // alternates between two buffers, so two bodies by parity
+            // alternates between two buffers, so two bodies by parity.  The
+            // iterate's pending updates are applied every other iteration:
+            // the even body leaves alpha p_old pending, the odd one applies
+            // both (the older direction is still in the buffer it overwrites)
+            double* pprev = nullptr; // the direction an even body left pending
             for (;;) {
                 while (st == CPS_E_NOT_CONVERGED && it < maxit) {
                     ++it;
@@ -1497,19 +1501,20 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                             const MarchShape ms = stencil_shape(g0);
                             {
                                 ProfScope ps(h, CPS_KERNEL_APPLY, 0); // the product only
+                                double* xu = parity ? x : nullptr;
                                 if (cast_fused)
                                     k_apply_dircast_march2<<<ms.grid, kBlock, 0, h->stream>>>(
                                         g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch,
                                         h->lv[0].x32.p, h->sc.p, S_SCALE, S_BETA, pc, pnx, q,
-                                        h->partial.p, x);
+                                        h->partial.p, xu, parity);
                                 else
                                     k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
                                         g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
-                                        h->sc.p + S_BETA, pnx, q, h->partial.p, x,
-                                        h->sc.p + S_ALPHA);
+                                        h->sc.p + S_BETA, pnx, q, h->partial.p, xu,
+                                        h->sc.p + S_ALPHA, parity ? h->sc.p + S_ALPHA_OLD : nullptr);
                                 LAUNCH_CHECK();
                             }
-                            reduce(h, ms.grid, S_PQ, 0, RED_ALPHA);
+                            reduce(h, ms.grid, S_PQ, 0, RED_ALPHA | RED_SHIFT_ALPHA);
                             step(pnx);
                         } else {
                             k_cg_dir<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, z, p);
@@ -1518,21 +1523,31 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                             step(p);
                         }
                     });
-                    if (fused) plast = pnx;
+                    if (fused) {
+                        plast = pnx;
+                        pprev = parity ? nullptr : pc;
+                    }
                     st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
                 }
-                if (fused) { // the update the last step left pending
-                    k_cg_x<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, plast, x);
+                if (fused) { // the updates the last steps left pending, in order
+                    if (pprev) {
+                        k_cg_x<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, pprev, x,
+                                                                   S_ALPHA_OLD);
+                        LAUNCH_CHECK();
+                    }
+                    k_cg_x<<<nblk(n), kBlock, 0, h->stream>>>(n, h->sc.p, plast, x, S_ALPHA);
                     LAUNCH_CHECK();
+                    pprev = nullptr;
                 }
                 if (st != CPS_OK) break;
                 st = true_residual(h, bb, tol, &rel);
                 if (st != CPS_E_NOT_CONVERGED || it >= maxit) break;
                 // restart from the residual of the iterate: the next direction
                 // is the preconditioned residual alone (its previous direction
-                // is zero, and so is the pending update that the fused product
-                // applies with it)
-                fill<double>(h, plast, n, 0.0);
+                // is zero, and so are the pending updates that the fused
+                // product applies with it and the direction before it)
+                fill<double>(h, p, n, 0.0);
+                fill<double>(h, pn, n, 0.0);
                 // the next body expects the zero-iterate pass of the new r
                 if (zfused) gs_pass<double>(h, 0, 0, r, z, true);
                 if (cast_fused) {

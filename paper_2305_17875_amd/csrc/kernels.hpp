@@ -33,7 +33,7 @@ enum { MODE_ORTHO = 0, MODE_RT = 1, MODE_FULL = 2 };
 // device scalar slots of the Krylov solvers (sc[])
 enum {
     S_BB = 0, S_RR, S_RZ, S_RZ_OLD, S_PQ, S_ZQ, S_ALPHA, S_BETA, S_OMEGA, S_RHO, S_RHO_OLD,
-    S_TS, S_TT, S_R0V, S_SUM, S_SCALE, S_COUNT
+    S_TS, S_TT, S_R0V, S_SUM, S_SCALE, S_ALPHA_OLD, S_COUNT
 };
 
 constexpr int kBlock = 256;
@@ -1345,7 +1345,10 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
 // xs += alpha p_old on the thread's own cells (one fma, as in d_cg_step),
 // so the step itself need not stream x and p.  p_old of plane a + 1 is
 // loaded once, forms the direction there (X.from) and makes that plane's
-// update.
+// update.  two: the iterate also owes the update of the step before,
+// xs += alpha2 p_{k-2} first, with p_{k-2} read from pnew's buffer before
+// this kernel overwrites it (the same two roundings as two passes), so the
+// iterate is streamed every other iteration only.
 template <typename T, int LTAG, typename X_>
 __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __restrict__ G,
                                                              long long gk, int bpa, int ch,
@@ -1354,7 +1357,8 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
                                                              double* __restrict__ partial,
                                                              T* __restrict__ xs = nullptr,
                                                              const T* __restrict__ pold = nullptr,
-                                                             T alpha = T(0))
+                                                             T alpha = T(0), bool two = false,
+                                                             T alpha2 = T(0))
 {
     __shared__ T sh[2][kPairs][4][64];
     March2 p;
@@ -1373,15 +1377,18 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
         if (live && xs) {
             const long long b0 = (long long)p.a0 * g.rowlen + p.r0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                st_once(xs + b0 + o[k], __builtin_fma(alpha, pold[b0 + o[k]], ld_once(xs + b0 + o[k])));
+            for (int k = 0; k < 4; ++k) {
+                T xv = ld_once(xs + b0 + o[k]);
+                if (two) xv = __builtin_fma(alpha2, pnew[b0 + o[k]], xv);
+                st_once(xs + b0 + o[k], __builtin_fma(alpha, pold[b0 + o[k]], xv));
+            }
         }
         for (int a = p.a0, buf = 0; a < p.a1; ++a, buf ^= 1) {
             Nb4<T> nb;
             const long long base = (long long)a * g.rowlen + p.r0;
             const long long ab = a < g.nr - 1 ? base + g.rowlen : base;
             const bool upd = xs && a + 1 < p.a1; // plane a + 1 is the chunk's
-            T xo[4], po[4];
+            T xo[4], po[4], p2[4];
             if (live) {
                 sh[buf][w][0][lane] = c.u0;
                 sh[buf][w][1][lane] = c.v0;
@@ -1397,7 +1404,10 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
                     nb.up.v1 = X.from(po[3], ab + o[3]);
                     if (upd) {
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) xo[k] = ld_once(xs + ab + o[k]);
+                        for (int k = 0; k < 4; ++k) {
+                            xo[k] = ld_once(xs + ab + o[k]);
+                            if (two) p2[k] = pnew[ab + o[k]]; // before it is overwritten
+                        }
                     }
                 }
             }
@@ -1419,7 +1429,10 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
                 st_once(pnew + base + o[k], own[k]);
                 st_once(q + base + o[k], yk[k]);
                 acc = __builtin_fma((double)yk[k], (double)own[k], acc);
-                if (upd) st_once(xs + ab + o[k], __builtin_fma(alpha, po[k], xo[k]));
+                if (upd) {
+                    const T xv = two ? __builtin_fma(alpha2, p2[k], xo[k]) : xo[k];
+                    st_once(xs + ab + o[k], __builtin_fma(alpha, po[k], xv));
+                }
             }
             cm = c;
             c = nb.up;
@@ -1439,10 +1452,12 @@ __global__ void __launch_bounds__(kBlock) k_apply_dir_march2(Geo g, const T* __r
                                                              T* __restrict__ q,
                                                              double* __restrict__ partial,
                                                              T* __restrict__ xs,
-                                                             const double* __restrict__ alpha)
+                                                             const double* __restrict__ alpha,
+                                                             const double* __restrict__ alpha2)
 {
     d_apply_dir_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, Dir<T>{z, pold, (T)*beta}, pnew,
-                                q, partial, xs, pold, xs ? (T)*alpha : T(0));
+                                q, partial, xs, pold, xs ? (T)*alpha : T(0), alpha2 != nullptr,
+                                alpha2 ? (T)*alpha2 : T(0));
 }
 
 // The same in the mixed form: z = (double) e * sc[S_SCALE] from the FP32
@@ -1457,11 +1472,13 @@ __global__ void __launch_bounds__(kBlock) k_apply_dircast_march2(Geo g,
                                                                  double* __restrict__ pnew,
                                                                  double* __restrict__ q,
                                                                  double* __restrict__ partial,
-                                                                 double* __restrict__ xs)
+                                                                 double* __restrict__ xs,
+                                                                 int two)
 {
     d_apply_dir_march2<double, 0>(self_blk(), g, G, gk, bpa, ch,
                                   DirCast{e, sc[scale_slot], pold, sc[beta_slot]}, pnew, q,
-                                  partial, xs, pold, xs ? sc[S_ALPHA] : 0.0);
+                                  partial, xs, pold, xs ? sc[S_ALPHA] : 0.0, two != 0,
+                                  two ? sc[S_ALPHA_OLD] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -2323,8 +2340,9 @@ __global__ void __launch_bounds__(kBlock) k_ir_update(long long n, double* __res
 // sc[slot] = sum of partial[0..n), and thread 0 does the scalar updates:
 // RED_SHIFT_RZ keeps the old r.z in S_RZ_OLD before the store, then
 // RED_BETA (beta = rz_new / rz_old), RED_FBETA (flexible, Polak-Ribiere:
-// beta = -alpha zq / rz_old) or RED_ALPHA (alpha = rz / pq).
-enum { RED_SHIFT_RZ = 1, RED_BETA = 2, RED_FBETA = 4, RED_ALPHA = 8 };
+// beta = -alpha zq / rz_old) or RED_ALPHA (alpha = rz / pq; with
+// RED_SHIFT_ALPHA the old alpha is kept in S_ALPHA_OLD first).
+enum { RED_SHIFT_RZ = 1, RED_BETA = 2, RED_FBETA = 4, RED_ALPHA = 8, RED_SHIFT_ALPHA = 16 };
 __global__ void __launch_bounds__(kBlock) k_reduce_cg(const double* __restrict__ partial,
                                                       long long n, double* __restrict__ sc,
                                                       int slot, int ops)
@@ -2335,6 +2353,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_cg(const double* __restrict__
     sc[slot] = s;
     if (ops & RED_BETA) sc[S_BETA] = sc[S_RZ] / sc[S_RZ_OLD];
     if (ops & RED_FBETA) sc[S_BETA] = -sc[S_ALPHA] * sc[S_ZQ] / sc[S_RZ_OLD];
+    if (ops & RED_SHIFT_ALPHA) sc[S_ALPHA_OLD] = sc[S_ALPHA];
     if (ops & RED_ALPHA) sc[S_ALPHA] = sc[S_RZ] / sc[S_PQ];
 }
 __global__ void k_bicg_beta(double* sc)
@@ -2436,10 +2455,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_step_z(Geo g, const double* __res
 // direction kernel carries the iterate's updates
 __global__ void __launch_bounds__(kBlock) k_cg_x(long long n, const double* __restrict__ sc,
                                                  const double* __restrict__ p,
-                                                 double* __restrict__ x)
+                                                 double* __restrict__ x, int slot)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = __builtin_fma(sc[S_ALPHA], p[i], x[i]);
+    if (i < n) x[i] = __builtin_fma(sc[slot], p[i], x[i]);
 }
 
 // r = b - y with y = A x: the residual of the iterate itself (the Krylov
