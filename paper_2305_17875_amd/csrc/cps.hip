@@ -1455,7 +1455,8 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             float* r32 = cast_fused ? h->lv[0].b32.p : nullptr;
             // FP64 point smoothing with the per-kernel finest level: the step
             // also makes the next cycle's zero-iterate first pass, z = r / D
-            // on the red cells (k_cg_step_z)
+            // on the red cells, and forms q = A p again from p, so the
+            // direction kernel does not store q (k_cg_step_z)
             const bool zfused = fused && !mixed && h->opts.smoother == 0 && h->ncol == 2 &&
                                 !h->lv[0].tile;
             // x += alpha p, r -= alpha q and ||r||^2 (the first iteration's
@@ -1465,14 +1466,20 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
             // the last update runs after the loop.
             double* plast = p; // direction of the last step
             auto step = [&](double* pk) {
-                if (zfused)
-                    k_cg_step_z<<<vgrid(n), kBlock, 0, h->stream>>>(g0, h->lv[0].G64.p, h->lv[0].gk,
-                                                                    h->sc.p, r, q, z, h->partial.p);
-                else
+                if (zfused) { // q = A p formed again from p (the direction kernel keeps no q)
+                    const MarchShape ms = stencil_shape(g0);
+                    k_cg_step_z<<<ms.grid, kBlock, 0, h->stream>>>(g0, h->lv[0].G64.p,
+                                                                   h->lv[0].gk, ms.bpa, ms.ch,
+                                                                   h->sc.p, pk, r, z,
+                                                                   h->partial.p);
+                    LAUNCH_CHECK();
+                    reduce(h, ms.grid, S_RR);
+                } else {
                     k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, fused ? nullptr : x,
                                                                   r, pk, q, h->partial.p, r32);
-                LAUNCH_CHECK();
-                reduce(h, vgrid(n), S_RR);
+                    LAUNCH_CHECK();
+                    reduce(h, vgrid(n), S_RR);
+                }
                 copy_norm(h, S_RR);
             };
             step(p);
@@ -1510,7 +1517,8 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                                 else
                                     k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
                                         g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
-                                        h->sc.p + S_BETA, pnx, q, h->partial.p, xu,
+                                        h->sc.p + S_BETA, pnx, zfused ? nullptr : q,
+                                        h->partial.p, xu,
                                         h->sc.p + S_ALPHA, parity ? h->sc.p + S_ALPHA_OLD : nullptr);
                                 LAUNCH_CHECK();
                             }

@@ -1333,7 +1333,8 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
 // Conjugate-gradient direction and product in one pass over row pairs:
 // p = z + beta p_old (beta: a device scalar) is formed wherever it is read,
 // written for the thread's own cells, and q = A p with partial sums of
-// p . q.  p must not alias p_old (other threads still read p_old).
+// p . q (q is stored unless null: a step that forms q again from p needs
+// none).  p must not alias p_old (other threads still read p_old).
 // The theta rows just outside a pair are the adjacent wavefronts' own rows:
 // each wavefront hands its plane-a values to its neighbours through LDS
 // (double-buffered by plane, one barrier per plane), so only the block's
@@ -1427,7 +1428,7 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 st_once(pnew + base + o[k], own[k]);
-                st_once(q + base + o[k], yk[k]);
+                if (q) st_once(q + base + o[k], yk[k]);
                 acc = __builtin_fma((double)yk[k], (double)own[k], acc);
                 if (upd) {
                     const T xv = two ? __builtin_fma(alpha2, p2[k], xo[k]) : xo[k];
@@ -2404,47 +2405,80 @@ __global__ void __launch_bounds__(kBlock) k_cg_step(long long n, const double* _
     d_cg_step(self_blk(), n, sc, x, r, p, q, partial, r32);
 }
 
-// The CG step (r -= alpha q, partial sums of r^2; the iterate's update is
-// carried by the direction kernel) on a level whose rows are whole
-// wavefronts (n_phi / 2 a multiple of 64), which also makes the next
-// V-cycle's first pass: z = r / D on the red cells (colour 0), with D and
-// the division of the zero-iterate colour pass (the same values).  Every
-// cell of a row of one parity plane has one colour, (a + b + s) mod 2, so a
-// wavefront takes 64 cells of one row and forms D once.
+// The FP64 CG step on a row-pair level (the iterate's update is carried by
+// the direction kernel), which also makes the next V-cycle's first pass.
+// q is not read from memory: q = A p is formed again from the stored
+// direction p (march2_apply on the same values with the same sums as the
+// direction kernel's product, so q has the same bits), and the direction
+// kernel need not store it.  r -= alpha q with partial sums of r^2, and
+// z = r / D on the red cells (colour 0: plane (a + b) mod 2 of row b at
+// plane a) with D and the division of the zero-iterate colour pass (the
+// same values).  The theta rows just outside a pair come from the adjacent
+// wavefronts through LDS, as in the direction kernel.
 __global__ void __launch_bounds__(kBlock) k_cg_step_z(Geo g, const double* __restrict__ G,
-                                                      long long gk,
-                                                      const double* __restrict__ sc,
-                                                      double* __restrict__ r,
-                                                      const double* __restrict__ q,
-                                                      double* __restrict__ z,
-                                                      double* __restrict__ partial)
+                                                       long long gk, int bpa, int ch,
+                                                       const double* __restrict__ sc,
+                                                       const double* __restrict__ pd,
+                                                       double* __restrict__ r,
+                                                       double* __restrict__ z,
+                                                       double* __restrict__ partial)
 {
+    __shared__ double sh[2][kPairs][4][64];
     const Blk bk = self_blk();
-    const double al = sc[S_ALPHA];
-    // the segment arithmetic is wavefront-uniform and 32-bit (a level's
-    // cells are fewer than 2^31): one scalar division chain a segment
-    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    const int lane = (int)threadIdx.x & 63;
-    const unsigned spr = (unsigned)g.nh / 64;              // wavefront segments a row
-    const unsigned rows = (unsigned)g.nr * (unsigned)g.nt; // rows of a parity plane
-    const unsigned nseg = 2 * rows * spr;
-    const unsigned stride = bk.G * (kBlock / 64);
+    March2 p;
     double acc = 0.0;
-    for (unsigned S = bk.L * (kBlock / 64) + (unsigned)w; S < nseg; S += stride) {
-        const unsigned R = S / spr; // row of [2][n_r][n_theta]
-        const unsigned sp = R / rows;
-        const unsigned ab = R - sp * rows;
-        const unsigned a = ab / (unsigned)g.nt, b = ab - a * (unsigned)g.nt;
-        const long long i = (long long)R * g.nh + (long long)(S - R * spr) * 64 + lane;
-        const double v = __builtin_fma(-al, q[i], r[i]);
-        r[i] = v;
-        acc = __builtin_fma(v, v, acc);
-        if (((a + b + sp) & 1) == 0) {
-            const long long ci = ab;
-            const double D = -(G[ci] + ((int)a < g.nr - 1 ? G[ci + g.nt] : 0.0) + G[4 * gk + ci] +
-                               ((int)b < g.nt - 1 ? G[4 * gk + ci + 1] : 0.0) +
-                               2.0 * G[8 * gk + ci]);
-            z[i] = v / D;
+    const bool live = march2_pos(bk, g, bpa, ch, p);
+    if (p.a0 < g.nr) { // every wavefront of the block stays for the barriers
+        const double al = sc[S_ALPHA];
+        const int w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+        const long long o[4] = {0, g.P, g.nh, g.P + g.nh}; // u0, v0, u1, v1
+        const Plain<double> X{pd};
+        Col4<double> cm, c;
+        if (live) march2_start<double>(g, X, p, cm, c);
+        for (int a = p.a0, buf = 0; a < p.a1; ++a, buf ^= 1) {
+            Nb4<double> nb;
+            const long long base = (long long)a * g.rowlen + p.r0;
+            double rv[4];
+            if (live) {
+                sh[buf][w][0][lane] = c.u0;
+                sh[buf][w][1][lane] = c.v0;
+                sh[buf][w][2][lane] = c.u1;
+                sh[buf][w][3][lane] = c.v1;
+                march2_load<double>(g, X, p, a, nb, w == 0, w == kPairs - 1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) rv[k] = ld_once(r + base + o[k]);
+            }
+            __syncthreads();
+            if (!live) continue;
+            if (w > 0) {
+                nb.utm0 = sh[buf][w - 1][2][lane];
+                nb.vtm0 = sh[buf][w - 1][3][lane];
+            }
+            if (w < kPairs - 1) {
+                nb.utp1 = sh[buf][w + 1][0][lane];
+                nb.vtp1 = sh[buf][w + 1][1][lane];
+            }
+            double y[4];
+            march2_apply<double>(g, G, gk, p, a, cm, c, nb, y);
+            // D of rows b0 and b1 at plane a, as the zero-iterate pass forms it
+            const long long ci = (long long)a * g.nt + p.b0;
+            const bool rh = a < g.nr - 1, thi = p.b0 + 1 < g.nt - 1;
+            const double D0 = -(G[ci] + (rh ? G[ci + g.nt] : 0.0) + G[4 * gk + ci] +
+                                G[4 * gk + ci + 1] + 2.0 * G[8 * gk + ci]);
+            const double D1 = -(G[ci + 1] + (rh ? G[ci + 1 + g.nt] : 0.0) + G[4 * gk + ci + 1] +
+                                (thi ? G[4 * gk + ci + 2] : 0.0) + 2.0 * G[8 * gk + ci + 1]);
+            // red: u0 and v1 at even a, v0 and u1 at odd a (b0 is even)
+            const bool even = (a & 1) == 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double v = __builtin_fma(-al, y[k], rv[k]);
+                st_once(r + base + o[k], v);
+                acc = __builtin_fma(v, v, acc);
+                const bool red = (k == 0 || k == 3) == even;
+                if (red) st_once(z + base + o[k], v / (k < 2 ? D0 : D1));
+            }
+            cm = c;
+            c = nb.up;
         }
     }
     acc = block_sum(acc);
