@@ -1508,18 +1508,22 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                             const MarchShape ms = stencil_shape(g0);
                             {
                                 ProfScope ps(h, CPS_KERNEL_APPLY, 0); // the product only
-                                double* xu = parity ? x : nullptr;
+                                // the odd body applies both pending updates of
+                                // the iterate, the even body none
+                                auto kd = parity ? k_apply_dir_march2<double, 0, 2>
+                                                 : k_apply_dir_march2<double, 0, 0>;
+                                auto kc = parity ? k_apply_dircast_march2<2>
+                                                 : k_apply_dircast_march2<0>;
                                 if (cast_fused)
-                                    k_apply_dircast_march2<<<ms.grid, kBlock, 0, h->stream>>>(
+                                    kc<<<ms.grid, kBlock, 0, h->stream>>>(
                                         g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch,
                                         h->lv[0].x32.p, h->sc.p, S_SCALE, S_BETA, pc, pnx, q,
-                                        h->partial.p, xu, parity);
+                                        h->partial.p, x);
                                 else
-                                    k_apply_dir_march2<double, 0><<<ms.grid, kBlock, 0, h->stream>>>(
+                                    kd<<<ms.grid, kBlock, 0, h->stream>>>(
                                         g0, h->lv[0].G64.p, h->lv[0].gk, ms.bpa, ms.ch, z, pc,
                                         h->sc.p + S_BETA, pnx, zfused ? nullptr : q,
-                                        h->partial.p, xu,
-                                        h->sc.p + S_ALPHA, parity ? h->sc.p + S_ALPHA_OLD : nullptr);
+                                        h->partial.p, x, h->sc.p);
                                 LAUNCH_CHECK();
                             }
                             reduce(h, ms.grid, S_PQ, 0, RED_ALPHA | RED_SHIFT_ALPHA);

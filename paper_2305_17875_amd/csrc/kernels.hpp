@@ -1342,15 +1342,17 @@ __global__ void __launch_bounds__(kBlock) k_apply_march2(Geo g, const T* __restr
 // neighbour instead doubles the L2 traffic of the stencil rows, and half of
 // it then misses.
 // X: the field p is formed from (Dir, or DirCast in the mixed form).
-// xs != nullptr: also the previous step's pending update of the iterate,
-// xs += alpha p_old on the thread's own cells (one fma, as in d_cg_step),
-// so the step itself need not stream x and p.  p_old of plane a + 1 is
-// loaded once, forms the direction there (X.from) and makes that plane's
-// update.  two: the iterate also owes the update of the step before,
-// xs += alpha2 p_{k-2} first, with p_{k-2} read from pnew's buffer before
-// this kernel overwrites it (the same two roundings as two passes), so the
-// iterate is streamed every other iteration only.
-template <typename T, int LTAG, typename X_>
+// XU (compile-time, so a launch without updates carries none of their
+// registers): 0, the iterate is not touched; 1, also the previous step's
+// pending update of the iterate, xs += alpha p_old on the thread's own
+// cells (one fma, as in d_cg_step), so the step itself need not stream x
+// and p -- p_old of plane a + 1 is loaded once, forms the direction there
+// (X.from) and makes that plane's update; 2, the iterate also owes the
+// update of the step before, xs += alpha2 p_{k-2} first, with p_{k-2} read
+// from pnew's buffer before this kernel overwrites it (the same two
+// roundings as two passes), so the iterate is streamed every other
+// iteration only.
+template <typename T, int LTAG, int XU, typename X_>
 __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __restrict__ G,
                                                              long long gk, int bpa, int ch,
                                                              const X_ X, T* __restrict__ pnew,
@@ -1358,9 +1360,9 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
                                                              double* __restrict__ partial,
                                                              T* __restrict__ xs = nullptr,
                                                              const T* __restrict__ pold = nullptr,
-                                                             T alpha = T(0), bool two = false,
-                                                             T alpha2 = T(0))
+                                                             T alpha = T(0), T alpha2 = T(0))
 {
+    constexpr bool kX = XU > 0, two = XU == 2;
     __shared__ T sh[2][kPairs][4][64];
     March2 p;
     double acc = 0.0;
@@ -1375,12 +1377,12 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
         if (live) march2_start<T>(g, X, p, cm, c);
         // the pending update of the chunk's first plane; each later plane's
         // comes with the loads that form its direction (p_old read once)
-        if (live && xs) {
+        if (kX && live) {
             const long long b0 = (long long)p.a0 * g.rowlen + p.r0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 T xv = ld_once(xs + b0 + o[k]);
-                if (two) xv = __builtin_fma(alpha2, pnew[b0 + o[k]], xv);
+                if constexpr (two) xv = __builtin_fma(alpha2, pnew[b0 + o[k]], xv);
                 st_once(xs + b0 + o[k], __builtin_fma(alpha, pold[b0 + o[k]], xv));
             }
         }
@@ -1388,15 +1390,15 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
             Nb4<T> nb;
             const long long base = (long long)a * g.rowlen + p.r0;
             const long long ab = a < g.nr - 1 ? base + g.rowlen : base;
-            const bool upd = xs && a + 1 < p.a1; // plane a + 1 is the chunk's
+            const bool upd = kX && a + 1 < p.a1; // plane a + 1 is the chunk's
             T xo[4], po[4], p2[4];
             if (live) {
                 sh[buf][w][0][lane] = c.u0;
                 sh[buf][w][1][lane] = c.v0;
                 sh[buf][w][2][lane] = c.u1;
                 sh[buf][w][3][lane] = c.v1;
-                march2_load<T>(g, X, p, a, nb, w == 0, w == kPairs - 1, !xs);
-                if (xs) { // the direction at a + 1 from p_old held for the update
+                march2_load<T>(g, X, p, a, nb, w == 0, w == kPairs - 1, !kX);
+                if constexpr (kX) { // the direction at a + 1 from p_old held for the update
 #pragma unroll
                     for (int k = 0; k < 4; ++k) po[k] = pold[ab + o[k]];
                     nb.up.u0 = X.from(po[0], ab + o[0]);
@@ -1407,7 +1409,7 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             xo[k] = ld_once(xs + ab + o[k]);
-                            if (two) p2[k] = pnew[ab + o[k]]; // before it is overwritten
+                            if constexpr (two) p2[k] = pnew[ab + o[k]]; // before it is overwritten
                         }
                     }
                 }
@@ -1431,7 +1433,8 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
                 if (q) st_once(q + base + o[k], yk[k]);
                 acc = __builtin_fma((double)yk[k], (double)own[k], acc);
                 if (upd) {
-                    const T xv = two ? __builtin_fma(alpha2, p2[k], xo[k]) : xo[k];
+                    T xv = xo[k];
+                    if constexpr (two) xv = __builtin_fma(alpha2, p2[k], xv);
                     st_once(xs + ab + o[k], __builtin_fma(alpha, po[k], xv));
                 }
             }
@@ -1443,7 +1446,7 @@ __device__ __forceinline__ void d_apply_dir_march2(Blk bk, Geo g, const T* __res
     if (threadIdx.x == 0) partial[bk.L] = acc;
 }
 
-template <typename T, int LTAG>
+template <typename T, int LTAG, int XU>
 __global__ void __launch_bounds__(kBlock) k_apply_dir_march2(Geo g, const T* __restrict__ G,
                                                              long long gk, int bpa, int ch,
                                                              const T* __restrict__ z,
@@ -1453,16 +1456,17 @@ __global__ void __launch_bounds__(kBlock) k_apply_dir_march2(Geo g, const T* __r
                                                              T* __restrict__ q,
                                                              double* __restrict__ partial,
                                                              T* __restrict__ xs,
-                                                             const double* __restrict__ alpha,
-                                                             const double* __restrict__ alpha2)
+                                                             const double* __restrict__ sc)
 {
-    d_apply_dir_march2<T, LTAG>(self_blk(), g, G, gk, bpa, ch, Dir<T>{z, pold, (T)*beta}, pnew,
-                                q, partial, xs, pold, xs ? (T)*alpha : T(0), alpha2 != nullptr,
-                                alpha2 ? (T)*alpha2 : T(0));
+    d_apply_dir_march2<T, LTAG, XU>(self_blk(), g, G, gk, bpa, ch, Dir<T>{z, pold, (T)*beta},
+                                    pnew, q, partial, xs, pold,
+                                    XU > 0 ? (T)sc[S_ALPHA] : T(0),
+                                    XU == 2 ? (T)sc[S_ALPHA_OLD] : T(0));
 }
 
 // The same in the mixed form: z = (double) e * sc[S_SCALE] from the FP32
 // correction e of the V-cycle, formed where it is read (z is not stored).
+template <int XU>
 __global__ void __launch_bounds__(kBlock) k_apply_dircast_march2(Geo g,
                                                                  const double* __restrict__ G,
                                                                  long long gk, int bpa, int ch,
@@ -1473,13 +1477,12 @@ __global__ void __launch_bounds__(kBlock) k_apply_dircast_march2(Geo g,
                                                                  double* __restrict__ pnew,
                                                                  double* __restrict__ q,
                                                                  double* __restrict__ partial,
-                                                                 double* __restrict__ xs,
-                                                                 int two)
+                                                                 double* __restrict__ xs)
 {
-    d_apply_dir_march2<double, 0>(self_blk(), g, G, gk, bpa, ch,
-                                  DirCast{e, sc[scale_slot], pold, sc[beta_slot]}, pnew, q,
-                                  partial, xs, pold, xs ? sc[S_ALPHA] : 0.0, two != 0,
-                                  two ? sc[S_ALPHA_OLD] : 0.0);
+    d_apply_dir_march2<double, 0, XU>(self_blk(), g, G, gk, bpa, ch,
+                                      DirCast{e, sc[scale_slot], pold, sc[beta_slot]}, pnew, q,
+                                      partial, xs, pold, XU > 0 ? sc[S_ALPHA] : 0.0,
+                                      XU == 2 ? sc[S_ALPHA_OLD] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
