@@ -2663,12 +2663,19 @@ __host__ __device__ inline MarchShape stencil_shape(const Geo& g, int ch = 0)
 }
 // The colour pass's launch: on row-pair levels the automatic chunk aims at
 // about 1024 blocks (twice the planes per block of the other kernels, which
-// halves the r-halo planes a block reads again; the autotuner's choice on
-// the paper-scale shell in both precisions), else as stencil_shape.
+// halves the r-halo planes a block reads again); FP32 passes whose chunk
+// would be 8 planes or more take 4-plane chunks instead (more, shorter
+// blocks: the FP32 pass's registers leave room for 7 blocks a CU; the
+// autotuner's choice on the paper-scale shell).  The chunk does not change
+// a pass's values, but it does change the order of the partial sums of the
+// FP64 passes that also form b . x.  Elsewhere as stencil_shape.
 template <typename T>
 __host__ __device__ inline MarchShape gs_shape(const Geo& g, int ch)
 {
-    return row_pairs(g) ? march2_shape(g, ch, 1024) : march_shape(g, ch);
+    if (!row_pairs(g)) return march_shape(g, ch);
+    const MarchShape ms = march2_shape(g, ch, 1024);
+    if (ch <= 0 && sizeof(T) == 4 && ms.ch >= 8) return march2_shape(g, 4, 1024);
+    return ms;
 }
 
 // blocks per plane of the generic colour pass and of generic stencil kernels
