@@ -590,7 +590,17 @@ void reduce(cps_handle* h, long long nparts, int slot, long long first = 0, int 
     if (ops)
         k_reduce_cg<<<1, kBlock, 0, h->stream>>>(h->partial.p + first, nparts, h->sc.p, slot, ops);
     else
-        k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p + first, nparts, h->sc.p + slot);
+        k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p + first, nparts, h->sc.p + slot,
+                                              nullptr);
+    LAUNCH_CHECK();
+}
+
+// The same for the norm an outer iteration ends with: the sum also goes to
+// the host mirror (coherent pinned memory), which body_norm reads after the
+// stream is synchronised, so no copy follows the launch.
+void reduce_norm(cps_handle* h, long long nparts, int slot)
+{
+    k_reduce<<<1, kBlock, 0, h->stream>>>(h->partial.p, nparts, h->sc.p + slot, h->hsc + slot);
     LAUNCH_CHECK();
 }
 
@@ -845,12 +855,6 @@ double body_norm(cps_handle* h, int slot)
 {
     HIPC(hipStreamSynchronize(h->stream));
     return h->hsc[slot];
-}
-
-void copy_norm(cps_handle* h, int slot)
-{
-    HIPC(hipMemcpyAsync(h->hsc + slot, h->sc.p + slot, sizeof(double), hipMemcpyDeviceToHost,
-                        h->stream));
 }
 
 double read_scalar(cps_handle* h, int slot)
@@ -1276,7 +1280,8 @@ void build(cps_handle* h)
     h->sc.alloc(S_COUNT);
     {
         MemLock lk(g_capture_mu);
-        HIPC(hipHostMalloc(&h->hsc, S_COUNT * sizeof(double), hipHostMallocDefault));
+        // coherent: reduce_norm's kernel stores the norms here directly
+        HIPC(hipHostMalloc(&h->hsc, S_COUNT * sizeof(double), hipHostMallocCoherent));
     }
     h->x0.alloc(n0);
     h->b0.alloc(n0);
@@ -1398,8 +1403,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                 for (it = 1; it <= maxit; ++it) {
                     run_body(h, G_RICH, [&] {
                         vcycle<double>(h, h->b0.p, x);
-                        reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
-                        copy_norm(h, S_RR);
+                        reduce_norm(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
                     });
                     st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
                     if (st != CPS_E_NOT_CONVERGED) break;
@@ -1420,8 +1424,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                         vcycle<float>(h, b32, x32, true);
                         k_ir_update<float><<<nblk(n), kBlock, 0, h->stream>>>(n, x, x32, h->sc.p + S_SCALE);
                         LAUNCH_CHECK();
-                        reduce(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
-                        copy_norm(h, S_RR);
+                        reduce_norm(h, residual<double>(h, 0, h->b0.p, x, h->r.p, true), S_RR);
                     });
                     st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
                     if (st != CPS_E_NOT_CONVERGED) break;
@@ -1473,14 +1476,13 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                                                                    h->sc.p, pk, r, z,
                                                                    h->partial.p);
                     LAUNCH_CHECK();
-                    reduce(h, ms.grid, S_RR);
+                    reduce_norm(h, ms.grid, S_RR);
                 } else {
                     k_cg_step<<<vgrid(n), kBlock, 0, h->stream>>>(n, h->sc.p, fused ? nullptr : x,
                                                                   r, pk, q, h->partial.p, r32);
                     LAUNCH_CHECK();
-                    reduce(h, vgrid(n), S_RR);
+                    reduce_norm(h, vgrid(n), S_RR);
                 }
-                copy_norm(h, S_RR);
             };
             step(p);
             it = 1;
@@ -1606,8 +1608,7 @@ cps_status solve(cps_handle* h, const double* rhs, double* p_out, double tol, cp
                                                                    h->sh.p, h->s.p, h->t.p,
                                                                    h->partial.p);
                     LAUNCH_CHECK();
-                    reduce(h, vgrid(n), S_RR);
-                    copy_norm(h, S_RR);
+                    reduce_norm(h, vgrid(n), S_RR);
                 });
                 st = check_norm(body_norm(h, S_RR), bb, tol, &rel);
                 if (st == CPS_OK) { // the recurrence says so: check b - A x

@@ -260,10 +260,18 @@ __device__ __forceinline__ void d_reduce(Blk bk, const double* __restrict__ part
     if (threadIdx.x == 0) *out = s;
 }
 
+// host != nullptr: the sum is also stored there (coherent pinned host
+// memory, read by the host once the stream is synchronised), in place of a
+// copy after the launch
 __global__ void __launch_bounds__(kBlock) k_reduce(const double* __restrict__ partial, long long n,
-                                                   double* __restrict__ out)
+                                                   double* __restrict__ out,
+                                                   double* __restrict__ host)
 {
-    d_reduce(self_blk(), partial, n, out);
+    const double s = d_reduce_sum(partial, n);
+    if (threadIdx.x == 0) {
+        *out = s;
+        if (host) *host = s;
+    }
 }
 
 // Blocks of the stencil kernels walk a contiguous range of "units" (256
